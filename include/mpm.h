@@ -1,0 +1,155 @@
+/*
+ * libmpm - implicit-Euler finite-volume reaction-diffusion on a tumour bounding box,
+ * solved by restarted GMRES on one AMD MI355X (gfx950).
+ *
+ * What is computed (paper: Sec. 2.2 eqs. 1-4, Sec. 2.3, Sec. 2.4).  Each species obeys
+ * dc/dt = div(D grad c) - k c + s on the domain voxels (mask = 1) inside a box around
+ * the tumour cells.  One step of cell-centred finite volumes with first-order implicit
+ * Euler gives, for every domain voxel P with faces f toward neighbours Q,
+ *     A_PP = 1 + dt k_P + dt sum_f G_f,   A_PQ = -dt G_f,
+ *     b_P  = c^n_P + dt s_P + dt sum_{box faces f} G_f c_b,
+ * with G_f = D_f / h^2, D_f = 2 D_P D_Q / (D_P + D_Q) (0 if both are 0) between two
+ * domain voxels, G_f = 0 toward a voxel outside the mask, and G_f = 2 D_P / h^2 on a
+ * box face, where the Dirichlet value c_b sits half a voxel away.  c^{n+1} = A^{-1} b
+ * is written back onto the domain voxels of the box; every other lattice voxel keeps
+ * its value.  The solve is restarted GMRES (Sec. 2.4) with Jacobi scaling, classical
+ * Gram-Schmidt with one reorthogonalisation, and an FP64 stopping test on the true
+ * residual ||b - A x||_2 / ||b||_2 per (problem, species).
+ *
+ * Conventions for every call:
+ *  - Lattice arrays are C-ordered [z][y][x] (x fastest); multi-species lattice arrays
+ *    are [S][z][y][x].  Sizes, corners and coordinates are (x, y, z) triples.
+ *  - Boxes are half-open [lo, hi) per axis and lie inside the lattice.
+ *  - "device" pointers are HIP device memory on the current device (for example the
+ *    data_ptr() of a torch tensor); "host" pointers are ordinary CPU memory.
+ *  - The caller owns every array it passes; the library keeps no pointer past the
+ *    call, except the network attached with mpm_attach_net.  The library owns its
+ *    own workspace and frees it in mpm_destroy / mpm_net_destroy.
+ *  - 'stream' is a hipStream_t passed as void* (0 = the null stream).  All work of a
+ *    context is ordered after the work already queued on that stream and before
+ *    work queued on it after the call returns.
+ *  - Every call returns an mpm status (int32).  Negative values are errors, the
+ *    outputs are then unspecified; mpm_last_error() gives a message for the calling
+ *    thread.  MPM_NOT_CONVERGED is a warning: outputs hold the best iterate.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef MPM_H
+#define MPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MPM_OK 0
+#define MPM_NOT_CONVERGED 1 /* warning: fields hold the best iterate, stats are filled */
+#define MPM_EINVAL (-1)     /* bad argument: sizes, box, coefficients, tolerance, pointers */
+#define MPM_ENOMEM (-2)     /* device allocation failed */
+#define MPM_EHIP (-3)       /* a HIP runtime call failed */
+#define MPM_EEMPTY (-4)     /* no tumour voxel, or a box without any domain voxel */
+#define MPM_ESTATE (-5)     /* call out of order (e.g. a step before mpm_fv_setup) */
+
+/* precision of the Krylov inner solve */
+#define MPM_FP64 0    /* FP64 everywhere (plain GMRES) */
+#define MPM_FP32_IR 1 /* FP32 Krylov basis and stencil inside FP64 iterative refinement */
+
+/* initial guess of each step */
+#define MPM_WS_NONE 0   /* start from c^n */
+#define MPM_WS_NET 1    /* learned warm start from the attached network, fallback c^n */
+#define MPM_WS_EXTRAP 2 /* linear extrapolation 2 c^n - c^{n-1}, fallback c^n */
+
+#define MPM_MAX_SPECIES 4
+#define MPM_MAX_RESTART 30
+
+typedef struct mpm_ctx_s* mpm_ctx;
+
+typedef struct {
+    int32_t restart;     /* GMRES restart length m, 1..MPM_MAX_RESTART (default 30) */
+    int32_t max_cycles;  /* restart cycles allowed per step (default 50) */
+    int32_t precision;   /* MPM_FP64 or MPM_FP32_IR (default MPM_FP32_IR) */
+    int32_t batched;     /* 1: every (problem, species) system in each launch (default);
+                            0: one system after another */
+    int32_t use_graph;   /* 1: replay each GMRES cycle from a captured hipGraph */
+    int32_t warm_start;  /* MPM_WS_NONE, MPM_WS_NET or MPM_WS_EXTRAP */
+    int32_t tile_override; /* 0: autotuned work split; >0: unknowns per block (multiple of 1024) */
+    int32_t reserved;
+    double inner_rtol;   /* smallest residual reduction asked of one FP32 cycle (default 1e-6) */
+} mpm_options;
+
+typedef struct {
+    int32_t iterations;      /* Arnoldi steps in the last mpm_implicit_step */
+    int32_t cycles;          /* restart cycles (= refinement sweeps in MPM_FP32_IR) */
+    int32_t refinements;     /* FP64 residual evaluations after the first */
+    int32_t converged;       /* 1 if ||b - A x|| <= tol ||b|| */
+    int32_t warm_start_used; /* 1 if the warm start was accepted */
+    int32_t fallback;        /* 1 if a warm start was tried and rejected */
+    double rel_res_initial;  /* ||b - A c^n|| / ||b|| */
+    double rel_res_warm;     /* ||b - A x0|| / ||b|| of the warm start (0 if none) */
+    double rel_res_final;    /* true FP64 relative residual of the returned fields */
+    float ms_total;          /* wall time of the last mpm_implicit_step call */
+    int32_t reserved;
+} mpm_stats;
+
+/* Bounding box of all tumour cells plus a margin (Sec. 2.3).
+ * cell_id: device int32 [z][y][x]; a voxel belongs to a cell when its value is > 0.
+ * dims: host (nx, ny, nz).  On return lo/hi (host, 3 each) hold the half-open box
+ * lo_d = max(min_d - margin, 0), hi_d = min(max_d + margin + 1, n_d).
+ * Synchronises 'stream'.  MPM_EEMPTY if no voxel is positive; MPM_EINVAL for
+ * non-positive dims, negative margin or a null pointer. */
+int32_t mpm_bbox_from_cells(const int32_t* cell_id, const int32_t* dims, int32_t margin,
+                            int32_t* lo, int32_t* hi, void* stream);
+
+/* Fill *opt with the defaults listed in mpm_options. */
+int32_t mpm_default_options(mpm_options* opt);
+
+/* Create a solver context for 'nproblems' independent lattices, each carrying
+ * 'nspecies' (1..MPM_MAX_SPECIES) uncoupled species.  opt may be NULL (defaults).
+ * The context runs its work on 'stream'. */
+int32_t mpm_create(mpm_ctx* ctx, int32_t nspecies, int32_t nproblems, const mpm_options* opt,
+                   void* stream);
+
+/* Discretise problem 'problem' on 'box' (Sec. 2.3-2.4).  Re-call whenever the box or
+ * the coefficients change; fields live on the lattice, so a new box needs no remap.
+ * dims: host (nx, ny, nz) of the lattice; lo/hi: host box corners.
+ * mask: device uint8 [z][y][x] (1 = domain voxel).  D, k, src: device FP64
+ * [S][z][y][x], lattice-sized (diffusivity >= 0, rate >= 0, production).
+ * c_dirichlet: host FP64 [S], the value on the box faces.  dt > 0, h > 0.
+ * The input arrays are read before the call returns (the stream is synchronised).
+ * MPM_EINVAL for bad sizes, a box outside the lattice, negative D or k, dt <= 0 or
+ * h <= 0; MPM_EEMPTY if the box holds no domain voxel. */
+int32_t mpm_fv_setup(mpm_ctx ctx, int32_t problem, const int32_t* dims, const int32_t* lo,
+                     const int32_t* hi, const uint8_t* mask, const double* D, const double* k,
+                     const double* src, const double* c_dirichlet, double dt, double h);
+
+/* One implicit-Euler step of every problem and species (Sec. 2.4).
+ * fields: host array [nproblems] of device FP64 [S][z][y][x] lattice fields; read as
+ * c^n and overwritten with c^{n+1} on the domain voxels of each box.
+ * tol > 0: relative FP64 residual to reach per (problem, species).
+ * Synchronises the context stream.  Returns MPM_NOT_CONVERGED if some system did
+ * not reach tol within max_cycles (the best iterate is written). */
+int32_t mpm_implicit_step(mpm_ctx ctx, double* const* fields, double tol);
+
+/* Statistics of the last step for one (problem, species) system (host output). */
+int32_t mpm_gmres_stats(mpm_ctx ctx, int32_t problem, int32_t species, mpm_stats* out);
+
+/* Free the context and all its device memory. */
+int32_t mpm_destroy(mpm_ctx ctx);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* mpm_last_error(void);
+
+/* Test hook: apply the discrete operator of 'problem' to a lattice field.
+ * x_lattice, y_lattice: device FP64 [S][z][y][x]; only domain voxels of the box are
+ * read / written.  mode 0: y = A x (FP64, unscaled); mode 1: y = S A S x with
+ * S = diag(A)^(-1/2), in FP32 (the inner operator of MPM_FP32_IR); mode 2: the same
+ * scaled operator in FP64.  Synchronises the stream. */
+int32_t mpm_debug_apply(mpm_ctx ctx, int32_t problem, const double* x_lattice, double* y_lattice,
+                        int32_t mode);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPM_H */

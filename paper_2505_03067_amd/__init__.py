@@ -1,0 +1,14 @@
+"""MI355X-native implicit-Euler finite-volume reaction-diffusion on a tumour bounding box.
+
+The compute path is ``libmpm.so`` (hand-written HIP for gfx950, C ABI in
+``include/mpm.h``); ``mpm`` is its thin ctypes binding.  PyTorch only supplies
+device memory and streams.
+"""
+
+from .mpm import (  # noqa: F401
+    MPM_EEMPTY, MPM_EHIP, MPM_EINVAL, MPM_ENOMEM, MPM_ESTATE, MPM_FP32_IR, MPM_FP64,
+    MPM_NOT_CONVERGED, MPM_OK, MPM_WS_EXTRAP, MPM_WS_NET, MPM_WS_NONE, MpmError, Solver,
+    header_symbols, lib, mpm_bbox_from_cells, mpm_create, mpm_debug_apply,
+    mpm_default_options, mpm_destroy, mpm_fv_setup, mpm_gmres_stats, mpm_implicit_step,
+    mpm_last_error,
+)

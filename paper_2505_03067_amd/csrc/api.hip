@@ -1,0 +1,238 @@
+// C ABI of libmpm: argument checks, context lifetime and stream ordering.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "context.h"
+
+namespace mpm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return MPM_EHIP;
+}
+
+static void destroy_ctx(Ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& ph : c->probs) free_problem(ph);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    (void)hipFree(c->d_probs);
+    (void)hipFree(c->d_sk);
+    (void)hipFree(c->d_part);
+    (void)hipFree(c->d_cnt);
+    (void)hipFree(c->d_prm);
+    (void)hipFree(c->d_blocks);
+    (void)hipFree(c->d_blocks_sys);
+    (void)hipFree(c->d_fields);
+    (void)hipFree(c->V);
+    (void)hipFree(c->W);
+    (void)hipFree(c->x);
+    (void)hipFree(c->b);
+    if (c->h_fields) (void)hipHostFree(c->h_fields);
+    if (c->h_prm) (void)hipHostFree(c->h_prm);
+    if (c->h_sk) (void)hipHostFree(c->h_sk);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+// Order the context's private stream after the caller's stream (entry) and the
+// caller's stream after the private one (exit).
+static int enter(Ctx* c) {
+    MPM_HIP(hipEventRecord(c->ev_in, c->user_stream));
+    MPM_HIP(hipStreamWaitEvent(c->stream, c->ev_in, 0));
+    return MPM_OK;
+}
+static int leave(Ctx* c) {
+    MPM_HIP(hipEventRecord(c->ev_out, c->stream));
+    MPM_HIP(hipStreamWaitEvent(c->user_stream, c->ev_out, 0));
+    return MPM_OK;
+}
+
+}  // namespace mpm
+
+using namespace mpm;
+
+extern "C" const char* mpm_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t mpm_default_options(mpm_options* opt) {
+    if (!opt) {
+        set_error("mpm_default_options: null pointer");
+        return MPM_EINVAL;
+    }
+    std::memset(opt, 0, sizeof(*opt));
+    opt->restart = 30;
+    opt->max_cycles = 50;
+    opt->precision = MPM_FP32_IR;
+    opt->batched = 1;
+    opt->use_graph = 1;
+    opt->warm_start = MPM_WS_NONE;
+    opt->tile_override = 0;
+    opt->inner_rtol = 1e-6;
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_create(mpm_ctx* out, int32_t nspecies, int32_t nproblems, const mpm_options* opt,
+                              void* stream) {
+    if (!out) {
+        set_error("mpm_create: null ctx pointer");
+        return MPM_EINVAL;
+    }
+    *out = nullptr;
+    if (nspecies < 1 || nspecies > MPM_MAX_SPECIES || nproblems < 1 || nspecies * nproblems > kMaxSys) {
+        set_error("mpm_create: need 1 <= nspecies <= 4, nproblems >= 1 and nspecies * nproblems <= 64");
+        return MPM_EINVAL;
+    }
+    mpm_options o;
+    if (opt) o = *opt;
+    else mpm_default_options(&o);
+    if (o.restart < 1 || o.restart > MPM_MAX_RESTART || o.max_cycles < 1 ||
+        (o.precision != MPM_FP64 && o.precision != MPM_FP32_IR) || !(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0) ||
+        o.warm_start < MPM_WS_NONE || o.warm_start > MPM_WS_EXTRAP || o.tile_override < 0 ||
+        (o.tile_override % kAlign) != 0) {
+        set_error("mpm_create: invalid options");
+        return MPM_EINVAL;
+    }
+    Ctx* c = new Ctx();
+    c->S = nspecies;
+    c->P = nproblems;
+    c->opt = o;
+    c->user_stream = (hipStream_t)stream;
+    c->probs.resize(nproblems);
+    c->stats.assign((size_t)nspecies * nproblems, mpm_stats{});
+    const int nsys = nspecies * nproblems;
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&c->d_probs, nproblems * sizeof(ProbDev));
+    if (e == hipSuccess) e = hipMalloc(&c->d_sk, nsys * sizeof(SysK));
+    if (e == hipSuccess) e = hipMalloc(&c->d_cnt, kMaxSys * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&c->d_prm, sizeof(Params));
+    if (e == hipSuccess) e = hipMalloc(&c->d_fields, nproblems * sizeof(double*));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_fields, nproblems * sizeof(double*), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_prm, sizeof(Params), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sk, nsys * sizeof(SysK), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemset(c->d_sk, 0, nsys * sizeof(SysK));
+    if (e == hipSuccess) e = hipMemset(c->d_cnt, 0, kMaxSys * sizeof(int));
+    if (e != hipSuccess) {
+        int r = hip_fail(e, "mpm_create");
+        destroy_ctx(c);
+        return r == MPM_EHIP && e == hipErrorOutOfMemory ? MPM_ENOMEM : r;
+    }
+    *out = (mpm_ctx)c;
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_destroy(mpm_ctx ctx) {
+    destroy_ctx((Ctx*)ctx);
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_fv_setup(mpm_ctx ctx, int32_t problem, const int32_t* dims, const int32_t* lo,
+                                const int32_t* hi, const uint8_t* mask, const double* D, const double* k,
+                                const double* src, const double* c_dirichlet, double dt, double h) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !dims || !lo || !hi || !mask || !D || !k || !src || !c_dirichlet) {
+        set_error("mpm_fv_setup: null pointer");
+        return MPM_EINVAL;
+    }
+    if (problem < 0 || problem >= c->P) {
+        set_error("mpm_fv_setup: problem index out of range");
+        return MPM_EINVAL;
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (dims[d] <= 0 || lo[d] < 0 || hi[d] > dims[d] || lo[d] >= hi[d]) {
+            set_error("mpm_fv_setup: the box must be non-empty and inside the lattice");
+            return MPM_EINVAL;
+        }
+    }
+    if ((long long)dims[0] * dims[1] * dims[2] >= 0x7fffffffLL) {
+        set_error("mpm_fv_setup: lattice too large for 32-bit voxel indices");
+        return MPM_EINVAL;
+    }
+    if (!(dt > 0.0) || !(h > 0.0) || !std::isfinite(dt) || !std::isfinite(h)) {
+        set_error("mpm_fv_setup: dt and h must be positive and finite");
+        return MPM_EINVAL;
+    }
+    for (int s = 0; s < c->S; ++s) {
+        if (!std::isfinite(c_dirichlet[s])) {
+            set_error("mpm_fv_setup: non-finite Dirichlet value");
+            return MPM_EINVAL;
+        }
+    }
+    if (((uintptr_t)D | (uintptr_t)k | (uintptr_t)src) % 8 != 0) {
+        set_error("mpm_fv_setup: coefficient arrays must be 8-byte aligned");
+        return MPM_EINVAL;
+    }
+    int rc = enter(c);
+    if (rc != MPM_OK) return rc;
+    rc = setup_problem(c, problem, dims, lo, hi, mask, D, k, src, c_dirichlet, dt, h);
+    if (rc == MPM_OK) rc = leave(c);
+    return rc;
+}
+
+extern "C" int32_t mpm_implicit_step(mpm_ctx ctx, double* const* fields, double tol) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !fields) {
+        set_error("mpm_implicit_step: null pointer");
+        return MPM_EINVAL;
+    }
+    if (!(tol > 0.0) || !std::isfinite(tol)) {
+        set_error("mpm_implicit_step: tol must be positive");
+        return MPM_EINVAL;
+    }
+    for (int p = 0; p < c->P; ++p) {
+        if (!fields[p] || ((uintptr_t)fields[p] % 8) != 0) {
+            set_error("mpm_implicit_step: null or misaligned field pointer");
+            return MPM_EINVAL;
+        }
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = enter(c);
+    if (rc != MPM_OK) return rc;
+    const int st = run_step(c, fields, tol);
+    if (st < 0) return st;
+    rc = leave(c);
+    if (rc != MPM_OK) return rc;
+    const float ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (auto& s : c->stats) s.ms_total = ms;
+    c->stepped = true;
+    if (st == MPM_NOT_CONVERGED) set_error("mpm_implicit_step: some system did not reach the tolerance");
+    return st;
+}
+
+extern "C" int32_t mpm_gmres_stats(mpm_ctx ctx, int32_t problem, int32_t species, mpm_stats* out) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !out || problem < 0 || problem >= c->P || species < 0 || species >= c->S) {
+        set_error("mpm_gmres_stats: bad arguments");
+        return MPM_EINVAL;
+    }
+    if (!c->stepped) {
+        set_error("mpm_gmres_stats: no step has run yet");
+        return MPM_ESTATE;
+    }
+    MPM_HIP(hipStreamSynchronize(c->stream));
+    *out = c->stats[(size_t)problem * c->S + species];
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_debug_apply(mpm_ctx ctx, int32_t problem, const double* x_lattice, double* y_lattice,
+                                   int32_t mode) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !x_lattice || !y_lattice || problem < 0 || problem >= c->P || mode < 0 || mode > 2) {
+        set_error("mpm_debug_apply: bad arguments");
+        return MPM_EINVAL;
+    }
+    int rc = enter(c);
+    if (rc != MPM_OK) return rc;
+    rc = debug_apply(c, problem, x_lattice, y_lattice, mode);
+    if (rc == MPM_OK) rc = leave(c);
+    return rc;
+}

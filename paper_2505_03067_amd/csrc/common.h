@@ -1,0 +1,111 @@
+// Internal declarations shared by the libmpm translation units (device + host).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "mpm.h"
+
+namespace mpm {
+
+// ---------------------------------------------------------------- launch shape
+constexpr int kThreads = 256;            // 4 wave64 per block
+constexpr int kWaves = kThreads / 64;
+constexpr int kAlign = 1024;             // unknown counts are padded to this
+constexpr long long kLead = 1024;        // zero elements before the first unknown
+constexpr int kMaxM = MPM_MAX_RESTART;   // longest restart
+constexpr int kMaxSys = 64;              // (problem, species) systems per context
+constexpr int kPartRows = kMaxM + 2;     // partial-sum rows per block slot
+
+// ---------------------------------------------------------------- device views
+// Per-problem data, addressed with the problem-local unknown index
+// loc = species * Npad + l, where l is the compact index of a domain voxel
+// (C order over the box).  Entries with l >= N are zero padding; l == N is the
+// "no neighbour" target, always zero.
+struct ProbDev {
+    const int* vox;        // [Npad] lattice linear index of voxel l (-1 for padding)
+    const int4* nbr;       // [Npad] local index of the -y, +y, -z, +z neighbour (N if none)
+    const double* d64;     // [S*Npad] A_PP
+    const double* q64;     // [S*Npad] dt s + Dirichlet terms (b = c^n + q)
+    const double* a64;     // [3][S*Npad] A_PQ toward +x, +y, +z (0 if no coupling)
+    const double* sc64;    // [S*Npad] diag(A)^(-1/2) (0 on padding)
+    const float* c32;      // [3][S*Npad] scaled S A S couplings toward +x, +y, +z, FP32
+    const double* c64;     // [3][S*Npad] the same in FP64
+    long long off;         // global index of (species 0, l = 0)
+    long long nvox;        // lattice voxel count (species stride of lattice fields)
+    int N;                 // domain voxels in the box
+    int Npad;              // padded length per species (multiple of kAlign, >= N + 1)
+};
+
+// One block of work: a contiguous range of one system's unknowns (global indices).
+struct Block {
+    int sys;     // system id = problem * S + species, -1 for an idle block
+    int start;   // global unknown index, multiple of kAlign (relative to kLead)
+    int end;
+    int slot;    // partial-sum slot of this block
+};
+
+// Per-system Krylov state, written by the last block of each reduction.
+struct SysK {
+    double h1[kMaxM + 2];    // first Gram-Schmidt coefficients v_k . w
+    double c1[kMaxM + 2];    // the same scaled for the stored (unnormalised) vectors
+    double h2[kMaxM + 2];    // reorthogonalisation coefficients
+    double c2[kMaxM + 2];
+    double vs[kMaxM + 2];    // v_k = vs[k] * V_k
+    double g[kMaxM + 2];     // rotated right-hand side of the least-squares problem
+    double cs[kMaxM + 2];    // Givens cosines
+    double sn[kMaxM + 2];    // Givens sines
+    double y[kMaxM + 2];     // update coefficients of the stored vectors
+    double R[(kMaxM + 1) * (kMaxM + 1)];   // column j at R[j * (kMaxM + 1) + i]
+    double bnorm, rnorm, srnorm, eta;
+    double rel_init, rel_final, rel_warm, kappa_s;
+    unsigned long long dmin_bits, dmax_bits;   // extremes of A_PP (positive doubles)
+    int active;        // Arnoldi running in the current cycle
+    int converged;     // true residual met the tolerance this step
+    int need_update;   // a cycle finished and x must be corrected
+    int mcount;        // basis vectors used by the finished cycle
+    int iters, cycles, refinements, breakdown;
+    int ws_used, fallback, nblocks, slot0;
+};
+
+struct Params {          // per-step scalars read by the kernels
+    double tol;
+    double inner_rtol;   // floor of the per-cycle reduction (FP32 inner solve)
+    int restart;
+    int S;
+    int first;           // residual kernel: 1 on the first evaluation of a step
+    int pad;
+};
+
+// Kernel argument bundle of the Krylov kernels.
+template <typename T>
+struct KArgs {
+    const Block* blocks;
+    const ProbDev* probs;
+    SysK* sk;
+    double* part;          // [kPartRows][nslots]
+    int* cnt;              // [kMaxSys] arrival counters
+    const Params* prm;
+    T* V;                  // basis, vector k at V + k * ldv
+    T* W;                  // work vector
+    double* x;             // FP64 iterate
+    double* b;             // FP64 right-hand side
+    double* const* fields; // [P] lattice fields (device pointers)
+    long long ldv;
+    int nslots;
+    int S;
+};
+
+// ---------------------------------------------------------------- host helpers
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define MPM_HIP(call)                                          \
+    do {                                                       \
+        hipError_t _e = (call);                                \
+        if (_e != hipSuccess) return ::mpm::hip_fail(_e, #call); \
+    } while (0)
+
+}  // namespace mpm

@@ -1,0 +1,95 @@
+// Host-side solver context (not visible through the C ABI).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace mpm {
+
+// One lattice problem: its box discretisation lives in buffers owned here and is
+// addressed with problem-local indices (species * Npad + l).
+struct ProbHost {
+    bool ready = false;
+    int dims[3] = {0, 0, 0};
+    int lo[3] = {0, 0, 0};
+    int hi[3] = {0, 0, 0};
+    int N = 0;
+    int Npad = 0;
+    long long nvox = 0;
+    double dt = 0.0, h = 0.0;
+    double cb[MPM_MAX_SPECIES] = {0, 0, 0, 0};
+    int* vox = nullptr;
+    int4* nbr = nullptr;
+    double* d64 = nullptr;
+    double* q64 = nullptr;
+    double* a64 = nullptr;
+    double* sc64 = nullptr;
+    float* c32 = nullptr;
+    double* c64 = nullptr;
+    size_t cap_pad = 0;        // Npad the buffers were sized for
+};
+
+struct Ctx {
+    int S = 0, P = 0;
+    mpm_options opt{};
+    hipStream_t user_stream = nullptr;
+    hipStream_t stream = nullptr;      // private stream (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<ProbHost> probs;
+
+    // global layout of the work vectors: problem p occupies
+    // [off_p, off_p + S * Npad_p) starting at kLead.
+    bool layout_dirty = true;
+    long long U = 0;                   // unknowns over all problems (padded)
+    std::vector<long long> off;
+    std::vector<Block> blocks;         // batched launch table (XCD-swizzled)
+    std::vector<int> sys_first, sys_count;   // per-system slice of blocks_sys
+    std::vector<Block> blocks_sys;     // per-system tables, concatenated
+    std::vector<int> sys_tab_first;    // start of each system's table in blocks_sys
+    int nslots = 0;
+    int block_unknowns = 0;            // unknowns per block (autotuned or fixed)
+
+    // device buffers
+    ProbDev* d_probs = nullptr;
+    SysK* d_sk = nullptr;
+    double* d_part = nullptr;
+    int* d_cnt = nullptr;
+    Params* d_prm = nullptr;
+    Block* d_blocks = nullptr;
+    Block* d_blocks_sys = nullptr;
+    double** d_fields = nullptr;
+    size_t cap_blocks = 0, cap_slots = 0;
+    void* V = nullptr;                 // (restart + 1) vectors of the Krylov type
+    void* W = nullptr;
+    double* x = nullptr;
+    double* b = nullptr;
+    long long ldv = 0;
+    size_t cap_U = 0;
+
+    // pinned host mirrors
+    double** h_fields = nullptr;
+    Params* h_prm = nullptr;
+    SysK* h_sk = nullptr;
+
+    // graph of one GMRES cycle
+    hipGraphExec_t graph = nullptr;
+    bool graph_valid = false;
+
+    std::vector<mpm_stats> stats;
+    bool stepped = false;
+};
+
+// setup.hip
+int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi,
+                  const uint8_t* mask, const double* D, const double* k, const double* src,
+                  const double* cb, double dt, double h);
+void free_problem(ProbHost& ph);
+int launch_diag_extremes(Ctx* c, int p);
+
+// krylov.hip
+int run_step(Ctx* c, double* const* fields, double tol);
+int debug_apply(Ctx* c, int p, const double* x, double* y, int mode);
+int ensure_layout(Ctx* c);
+
+}  // namespace mpm

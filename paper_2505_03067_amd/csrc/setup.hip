@@ -1,0 +1,392 @@
+// Finite-volume discretisation of one problem on its box (paper Sec. 2.3-2.4).
+//
+// 1. Count the domain voxels of every box row, scan the counts, and compact the
+//    domain voxels in C order (z, y, x) with wave ballots: voxel l of the box
+//    gets its lattice index vox[l].
+// 2. Neighbour table: the compact index of the -y, +y, -z, +z neighbour of every
+//    domain voxel (N = "none", a zero padding slot).  The x neighbours of voxel l
+//    are l - 1 and l + 1 whenever they are coupled at all, so they need no table.
+// 3. Coefficients per (species, voxel), in FP64:
+//      G_f = harmonic-mean D / h^2 toward a domain voxel in the box,
+//      G_f = 0 toward a voxel outside the mask,
+//      G_f = 2 D_P / h^2 on a box face (Dirichlet value half a voxel away),
+//      A_PP = 1 + dt k + dt sum G_f,  A_PQ = -dt G_f (stored for the +x, +y, +z faces;
+//      the -d face of P is the +d face of its neighbour),
+//      q = dt s + dt sum_{box faces} G_f c_b,
+//    and the Jacobi scaling S = diag(A)^(-1/2) with the scaled couplings
+//    S_P A_PQ S_Q in FP64 and FP32.
+#include <algorithm>
+
+#include "context.h"
+
+namespace mpm {
+
+__device__ inline int wsum_int(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+struct BoxGeo {
+    int nx, ny, nz;      // lattice
+    int x0, y0, z0;      // box origin
+    int bx, by, bz;      // box size
+};
+
+__global__ __launch_bounds__(256) void k_row_count(const uint8_t* __restrict__ mask, BoxGeo g,
+                                                   int* __restrict__ rowcnt) {
+    const int r = blockIdx.x * kWaves + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    const int rows = g.by * g.bz;
+    if (r >= rows) return;
+    const int ry = r % g.by, rz = r / g.by;
+    const uint8_t* row = mask + ((long long)(g.z0 + rz) * g.ny + (g.y0 + ry)) * g.nx + g.x0;
+    int c = 0;
+    for (int x = lane; x < g.bx; x += 64) c += row[x] != 0;
+    c = wsum_int(c);
+    if (lane == 0) rowcnt[r] = c;
+}
+
+// Exclusive scan of 'n' counts by one block of 1024 threads; total written to *total.
+__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int* __restrict__ start,
+                                               int n, int* total) {
+    __shared__ int sh[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int a = min(n, t * per), e = min(n, a + per);
+    int s = 0;
+    for (int i = a; i < e; ++i) s += cnt[i];
+    sh[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {     // Hillis-Steele inclusive scan
+        int v = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    int run = sh[t] - s;
+    for (int i = a; i < e; ++i) {
+        start[i] = run;
+        run += cnt[i];
+    }
+    if (t == 1023) *total = sh[1023];
+}
+
+__global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ mask, BoxGeo g,
+                                                 const int* __restrict__ rowstart, int* __restrict__ vox,
+                                                 int* __restrict__ boxmap) {
+    const int r = blockIdx.x * kWaves + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    const int rows = g.by * g.bz;
+    if (r >= rows) return;
+    const int ry = r % g.by, rz = r / g.by;
+    const long long lrow = ((long long)(g.z0 + rz) * g.ny + (g.y0 + ry)) * g.nx + g.x0;
+    const long long brow = (long long)r * g.bx;
+    int run = rowstart[r];
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int x0 = 0; x0 < g.bx; x0 += 64) {
+        const int x = x0 + lane;
+        const bool in = x < g.bx;
+        const bool a = in && mask[lrow + x] != 0;
+        const unsigned long long bal = __ballot(a);
+        if (a) {
+            const int l = run + __popcll(bal & below);
+            vox[l] = (int)(lrow + x);
+            boxmap[brow + x] = l;
+        } else if (in) {
+            boxmap[brow + x] = -1;
+        }
+        run += __popcll(bal);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_neighbors(const int* __restrict__ vox, const int* __restrict__ boxmap,
+                                                   BoxGeo g, int N, int Npad, int4* __restrict__ nbr,
+                                                   int* __restrict__ voxpad) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= Npad) return;
+    if (l >= N) {
+        nbr[l] = make_int4(N, N, N, N);
+        voxpad[l] = -1;
+        return;
+    }
+    const int v = vox[l];
+    const int plane = g.nx * g.ny;
+    const int z = v / plane;
+    const int rem = v - z * plane;
+    const int y = rem / g.nx;
+    const int x = rem - y * g.nx;
+    const int bxr = x - g.x0, byr = y - g.y0, bzr = z - g.z0;
+    const long long bidx = ((long long)bzr * g.by + byr) * g.bx + bxr;
+    int4 n;
+    int m;
+    m = byr > 0 ? boxmap[bidx - g.bx] : -1;
+    n.x = m >= 0 ? m : N;
+    m = byr + 1 < g.by ? boxmap[bidx + g.bx] : -1;
+    n.y = m >= 0 ? m : N;
+    m = bzr > 0 ? boxmap[bidx - (long long)g.bx * g.by] : -1;
+    n.z = m >= 0 ? m : N;
+    m = bzr + 1 < g.bz ? boxmap[bidx + (long long)g.bx * g.by] : -1;
+    n.w = m >= 0 ? m : N;
+    nbr[l] = n;
+}
+
+struct CoefArgs {
+    const uint8_t* mask;
+    const double* D;
+    const double* k;
+    const double* src;
+    const int* vox;
+    double* d64;
+    double* q64;
+    double* a64;      // [3][S*Npad]
+    double* sc64;
+    BoxGeo g;
+    long long nvox;
+    double dt, inv_h2;
+    double cb[MPM_MAX_SPECIES];
+    int N, Npad, S;
+};
+
+__device__ inline double harm(double a, double b) {
+    const double s = a + b;
+    return s != 0.0 ? 2.0 * a * b / s : 0.0;
+}
+
+// One thread per (species, l).  Padding gets A_PP = 1, q = 0, couplings 0, scale 0.
+__global__ __launch_bounds__(256) void k_coefs(CoefArgs a) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)a.S * a.Npad;
+    if (i >= tot) return;
+    const int s = (int)(i / a.Npad);
+    const int l = (int)(i - (long long)s * a.Npad);
+    const long long stride3 = tot;
+    if (l >= a.N) {
+        a.d64[i] = 1.0;
+        a.q64[i] = 0.0;
+        a.a64[i] = 0.0;
+        a.a64[i + stride3] = 0.0;
+        a.a64[i + 2 * stride3] = 0.0;
+        a.sc64[i] = 0.0;
+        return;
+    }
+    const BoxGeo& g = a.g;
+    const int v = a.vox[l];
+    const int plane = g.nx * g.ny;
+    const int z = v / plane;
+    const int rem = v - z * plane;
+    const int y = rem / g.nx;
+    const int x = rem - y * g.nx;
+    const int cr[3] = {x - g.x0, y - g.y0, z - g.z0};
+    const int bs[3] = {g.bx, g.by, g.bz};
+    const long long ls[3] = {1, g.nx, (long long)plane};
+    const double* Ds = a.D + (long long)s * a.nvox;
+    const double DP = Ds[v];
+    double sumG = 0.0, dir = 0.0;
+    double up[3];
+    for (int d = 0; d < 3; ++d) {
+        for (int side = -1; side <= 1; side += 2) {
+            const int c = cr[d] + side;
+            double G = 0.0;
+            if (c < 0 || c >= bs[d]) {            // box face: Dirichlet at half a voxel
+                G = 2.0 * DP * a.inv_h2;
+                dir += G;
+            } else {
+                const long long q = v + side * ls[d];
+                if (a.mask[q]) G = harm(DP, Ds[q]) * a.inv_h2;
+            }
+            sumG += G;
+            if (side > 0) up[d] = (c < bs[d]) ? G : 0.0;
+        }
+    }
+    const double ks = a.k[(long long)s * a.nvox + v];
+    const double ss = a.src[(long long)s * a.nvox + v];
+    const double diag = 1.0 + a.dt * ks + a.dt * sumG;
+    a.d64[i] = diag;
+    a.q64[i] = a.dt * ss + a.dt * dir * a.cb[s];
+    a.a64[i] = -a.dt * up[0];
+    a.a64[i + stride3] = -a.dt * up[1];
+    a.a64[i + 2 * stride3] = -a.dt * up[2];
+    a.sc64[i] = 1.0 / sqrt(diag);
+}
+
+// Scaled couplings S_P A_PQ S_Q toward +x, +y, +z.
+__global__ __launch_bounds__(256) void k_scaled(const double* __restrict__ a64, const double* __restrict__ sc,
+                                                const int4* __restrict__ nbr, int N, int Npad, int S,
+                                                double* __restrict__ c64, float* __restrict__ c32) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)S * Npad;
+    if (i >= tot) return;
+    const int s = (int)(i / Npad);
+    const int l = (int)(i - (long long)s * Npad);
+    const long long base = (long long)s * Npad;
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    if (l < N) {
+        const int4 n = nbr[l];
+        const double sp = sc[i];
+        const double ax = a64[i], ay = a64[i + tot], az = a64[i + 2 * tot];
+        if (ax != 0.0) cx = ax * sp * sc[i + 1];
+        if (ay != 0.0) cy = ay * sp * sc[base + n.y];
+        if (az != 0.0) cz = az * sp * sc[base + n.w];
+    }
+    c64[i] = cx;
+    c64[i + tot] = cy;
+    c64[i + 2 * tot] = cz;
+    c32[i] = (float)cx;
+    c32[i + tot] = (float)cy;
+    c32[i + 2 * tot] = (float)cz;
+}
+
+// Coefficient arrays carry kAlign zero elements before and after their data so
+// that the "left neighbour" read of voxel 0 and the right read of the last
+// element stay inside the allocation and see zero couplings.
+template <typename T>
+static hipError_t alloc_padded(T** p, size_t n) {
+    T* raw = nullptr;
+    hipError_t e = hipMalloc(&raw, (n + 2 * kAlign) * sizeof(T));
+    if (e != hipSuccess) return e;
+    e = hipMemset(raw, 0, (n + 2 * kAlign) * sizeof(T));
+    *p = raw + kAlign;
+    return e;
+}
+template <typename T>
+static void free_padded(T*& p) {
+    if (p) (void)hipFree(p - kAlign);
+    p = nullptr;
+}
+
+void free_problem(ProbHost& ph) {
+    free_padded(ph.vox);
+    free_padded(ph.nbr);
+    free_padded(ph.d64);
+    free_padded(ph.q64);
+    free_padded(ph.a64);
+    free_padded(ph.sc64);
+    free_padded(ph.c32);
+    free_padded(ph.c64);
+    ph.cap_pad = 0;
+}
+
+static int alloc_problem(ProbHost& ph, int S, int Npad) {
+    if ((size_t)Npad <= ph.cap_pad) return MPM_OK;
+    free_problem(ph);
+    const size_t n = (size_t)Npad, u = (size_t)S * Npad;
+    if (alloc_padded(&ph.vox, n) != hipSuccess || alloc_padded(&ph.nbr, n) != hipSuccess ||
+        alloc_padded(&ph.d64, u) != hipSuccess || alloc_padded(&ph.q64, u) != hipSuccess ||
+        alloc_padded(&ph.a64, 3 * u) != hipSuccess || alloc_padded(&ph.sc64, u) != hipSuccess ||
+        alloc_padded(&ph.c32, 3 * u) != hipSuccess || alloc_padded(&ph.c64, 3 * u) != hipSuccess) {
+        free_problem(ph);
+        (void)hipGetLastError();
+        set_error("mpm_fv_setup: device allocation failed");
+        return MPM_ENOMEM;
+    }
+    ph.cap_pad = Npad;
+    return MPM_OK;
+}
+
+int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, const uint8_t* mask,
+                  const double* D, const double* k, const double* src, const double* cb, double dt,
+                  double h) {
+    ProbHost& ph = c->probs[p];
+    hipStream_t st = c->stream;
+    BoxGeo g;
+    g.nx = dims[0]; g.ny = dims[1]; g.nz = dims[2];
+    g.x0 = lo[0]; g.y0 = lo[1]; g.z0 = lo[2];
+    g.bx = hi[0] - lo[0]; g.by = hi[1] - lo[1]; g.bz = hi[2] - lo[2];
+    const int rows = g.by * g.bz;
+    const long long boxvox = (long long)rows * g.bx;
+
+    int* rowcnt = nullptr;
+    int* rowstart = nullptr;
+    int* boxmap = nullptr;
+    int* vox_tmp = nullptr;
+    int* total_d = nullptr;
+    int total_h = 0;
+    int rc = MPM_OK;
+    auto cleanup = [&]() {
+        (void)hipFree(rowcnt);
+        (void)hipFree(rowstart);
+        (void)hipFree(boxmap);
+        (void)hipFree(vox_tmp);
+        (void)hipFree(total_d);
+    };
+    if (hipMalloc(&rowcnt, rows * sizeof(int)) != hipSuccess ||
+        hipMalloc(&rowstart, rows * sizeof(int)) != hipSuccess ||
+        hipMalloc(&boxmap, boxvox * sizeof(int)) != hipSuccess || hipMalloc(&total_d, sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        set_error("mpm_fv_setup: device allocation failed");
+        return MPM_ENOMEM;
+    }
+    const int gr = (rows + kWaves - 1) / kWaves;
+    k_row_count<<<gr, kThreads, 0, st>>>(mask, g, rowcnt);
+    k_scan<<<1, 1024, 0, st>>>(rowcnt, rowstart, rows, total_d);
+    hipError_t e = hipMemcpyAsync(&total_h, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "mpm_fv_setup (count)");
+    }
+    if (total_h == 0) {
+        cleanup();
+        set_error("mpm_fv_setup: the box holds no domain voxel");
+        return MPM_EEMPTY;
+    }
+    const int N = total_h;
+    const int Npad = (int)(((long long)N + 1 + kAlign - 1) / kAlign * kAlign);
+    rc = alloc_problem(ph, c->S, Npad);
+    if (rc != MPM_OK) {
+        cleanup();
+        return rc;
+    }
+    if (hipMalloc(&vox_tmp, (size_t)Npad * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        set_error("mpm_fv_setup: device allocation failed");
+        return MPM_ENOMEM;
+    }
+    k_compact<<<gr, kThreads, 0, st>>>(mask, g, rowstart, vox_tmp, boxmap);
+    k_neighbors<<<(Npad + 255) / 256, 256, 0, st>>>(vox_tmp, boxmap, g, N, Npad, ph.nbr, ph.vox);
+    // ph.vox receives -1 on padding from k_neighbors; copy the domain part
+    e = hipMemcpyAsync(ph.vox, vox_tmp, (size_t)N * sizeof(int), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "mpm_fv_setup (vox)");
+    }
+    CoefArgs ca;
+    ca.mask = mask; ca.D = D; ca.k = k; ca.src = src; ca.vox = vox_tmp;
+    ca.d64 = ph.d64; ca.q64 = ph.q64; ca.a64 = ph.a64; ca.sc64 = ph.sc64;
+    ca.g = g;
+    ca.nvox = (long long)dims[0] * dims[1] * dims[2];
+    ca.dt = dt;
+    ca.inv_h2 = 1.0 / (h * h);
+    for (int s = 0; s < MPM_MAX_SPECIES; ++s) ca.cb[s] = s < c->S ? cb[s] : 0.0;
+    ca.N = N; ca.Npad = Npad; ca.S = c->S;
+    const long long tot = (long long)c->S * Npad;
+    k_coefs<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ca);
+    k_scaled<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ph.a64, ph.sc64, ph.nbr, N, Npad, c->S, ph.c64,
+                                                          ph.c32);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (coefficients)");
+
+    const bool grew = Npad != ph.Npad;
+    ph.N = N;
+    ph.Npad = Npad;
+    for (int d = 0; d < 3; ++d) {
+        ph.dims[d] = dims[d];
+        ph.lo[d] = lo[d];
+        ph.hi[d] = hi[d];
+    }
+    ph.nvox = ca.nvox;
+    ph.dt = dt;
+    ph.h = h;
+    for (int s = 0; s < c->S; ++s) ph.cb[s] = cb[s];
+    ph.ready = true;
+    // descriptors (pointers may have moved) and the layout are rebuilt lazily
+    c->layout_dirty = true;
+    (void)grew;
+    return MPM_OK;
+}
+
+}  // namespace mpm

@@ -1,0 +1,254 @@
+"""ctypes binding of libmpm (argument marshalling only).
+
+Every function has the name of the C entry point it wraps (see ``include/mpm.h``).
+Tensors are PyTorch tensors on the GPU; the binding checks dtype, device and
+contiguity, passes ``data_ptr()`` and the current HIP stream, and turns negative
+status codes into ``MpmError``.  No computation happens here: if ``libmpm.so`` is
+missing the import fails loudly, there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmpm.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "mpm.h")
+
+MPM_OK = 0
+MPM_NOT_CONVERGED = 1
+MPM_EINVAL = -1
+MPM_ENOMEM = -2
+MPM_EHIP = -3
+MPM_EEMPTY = -4
+MPM_ESTATE = -5
+MPM_FP64 = 0
+MPM_FP32_IR = 1
+MPM_WS_NONE = 0
+MPM_WS_NET = 1
+MPM_WS_EXTRAP = 2
+
+_NAMES = {MPM_EINVAL: "MPM_EINVAL", MPM_ENOMEM: "MPM_ENOMEM", MPM_EHIP: "MPM_EHIP",
+          MPM_EEMPTY: "MPM_EEMPTY", MPM_ESTATE: "MPM_ESTATE"}
+
+
+class MpmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class mpm_options(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("batched", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("tile_override", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("inner_rtol", ctypes.c_double)]
+
+
+class mpm_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("refinements", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("warm_start_used", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("rel_res_initial", ctypes.c_double), ("rel_res_warm", ctypes.c_double),
+                ("rel_res_final", ctypes.c_double), ("ms_total", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmpm.so from the package directory (built by ``build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "'python -m paper_2505_03067_amd.build'")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "mpm_bbox_from_cells": [_vp, _i32p, ctypes.c_int32, _i32p, _i32p, _vp],
+            "mpm_default_options": [ctypes.POINTER(mpm_options)],
+            "mpm_create": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32,
+                           ctypes.POINTER(mpm_options), _vp],
+            "mpm_fv_setup": [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _vp, _vp, _vp, _vp,
+                             ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double],
+            "mpm_implicit_step": [_vp, ctypes.POINTER(_vp), ctypes.c_double],
+            "mpm_gmres_stats": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mpm_stats)],
+            "mpm_destroy": [_vp],
+            "mpm_debug_apply": [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int32
+        L.mpm_last_error.argtypes = []
+        L.mpm_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list:
+    """Names of every function declared in include/mpm.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(mpm_[a-z_0-9]+)\s*\(", text)))
+
+
+def mpm_last_error() -> str:
+    return lib().mpm_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise MpmError(rc, mpm_last_error())
+    return rc
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _triple(v):
+    return (ctypes.c_int32 * 3)(*[int(a) for a in v])
+
+
+def mpm_default_options(**overrides) -> mpm_options:
+    o = mpm_options()
+    _check(lib().mpm_default_options(ctypes.byref(o)))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def mpm_bbox_from_cells(cell_id, margin: int, stream=None):
+    """Box ``(lo, hi)`` ((x, y, z) triples) of the positive voxels of ``cell_id`` [z][y][x]."""
+    import torch
+    ptr = _dev_ptr(cell_id, torch.int32, "cell_id")
+    if cell_id.dim() != 3:
+        raise ValueError("cell_id must be [z][y][x]")
+    nz, ny, nx = cell_id.shape
+    lo = (ctypes.c_int32 * 3)()
+    hi = (ctypes.c_int32 * 3)()
+    _check(lib().mpm_bbox_from_cells(ptr, _triple((nx, ny, nz)), int(margin), lo, hi,
+                                     _stream(stream)))
+    return tuple(lo), tuple(hi)
+
+
+def mpm_create(nspecies: int, nproblems: int = 1, options: Optional[mpm_options] = None,
+               stream=None) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(lib().mpm_create(ctypes.byref(ctx), int(nspecies), int(nproblems), opt,
+                            _stream(stream)))
+    return ctx
+
+
+def mpm_fv_setup(ctx, problem: int, box, mask, D, k, src, c_dirichlet: Sequence[float],
+                 dt: float, h: float):
+    """Discretise ``problem`` on ``box = (lo, hi)``; lattice arrays are torch tensors."""
+    import torch
+    if mask.dim() != 3:
+        raise ValueError("mask must be [z][y][x]")
+    nz, ny, nx = mask.shape
+    for name, a in (("D", D), ("k", k), ("src", src)):
+        if a.dim() != 4 or tuple(a.shape[1:]) != (nz, ny, nx):
+            raise ValueError(f"{name} must be [S][z][y][x] matching the mask")
+    lo, hi = box
+    cb = (ctypes.c_double * len(c_dirichlet))(*[float(v) for v in c_dirichlet])
+    return _check(lib().mpm_fv_setup(ctx, int(problem), _triple((nx, ny, nz)), _triple(lo),
+                                     _triple(hi), _dev_ptr(mask, torch.uint8, "mask"),
+                                     _dev_ptr(D, torch.float64, "D"),
+                                     _dev_ptr(k, torch.float64, "k"),
+                                     _dev_ptr(src, torch.float64, "src"), cb, float(dt),
+                                     float(h)))
+
+
+def mpm_implicit_step(ctx, fields, tol: float) -> int:
+    """One step for every problem; ``fields`` is a list of FP64 [S][z][y][x] tensors."""
+    import torch
+    arr = (ctypes.c_void_p * len(fields))(
+        *[_dev_ptr(f, torch.float64, f"fields[{i}]").value for i, f in enumerate(fields)])
+    return _check(lib().mpm_implicit_step(ctx, arr, float(tol)))
+
+
+def mpm_gmres_stats(ctx, problem: int = 0, species: int = 0) -> dict:
+    st = mpm_stats()
+    _check(lib().mpm_gmres_stats(ctx, int(problem), int(species), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def mpm_destroy(ctx) -> None:
+    if ctx is not None and ctx.value:
+        lib().mpm_destroy(ctx)
+
+
+def mpm_debug_apply(ctx, problem: int, x, y, mode: int) -> None:
+    import torch
+    _check(lib().mpm_debug_apply(ctx, int(problem), _dev_ptr(x, torch.float64, "x"),
+                                 _dev_ptr(y, torch.float64, "y"), int(mode)))
+
+
+class Solver:
+    """Owns one context; a convenience wrapper over the functions above."""
+
+    def __init__(self, nspecies: int, nproblems: int = 1, stream=None, **options):
+        self.options = mpm_default_options(**options)
+        self.ctx = mpm_create(nspecies, nproblems, self.options, stream)
+        self.nspecies = nspecies
+        self.nproblems = nproblems
+
+    def setup(self, problem, box, mask, D, k, src, c_dirichlet, dt, h):
+        return mpm_fv_setup(self.ctx, problem, box, mask, D, k, src, c_dirichlet, dt, h)
+
+    def step(self, fields, tol):
+        return mpm_implicit_step(self.ctx, list(fields), tol)
+
+    def stats(self, problem=0, species=0):
+        return mpm_gmres_stats(self.ctx, problem, species)
+
+    def apply(self, problem, x, y, mode):
+        return mpm_debug_apply(self.ctx, problem, x, y, mode)
+
+    def close(self):
+        mpm_destroy(self.ctx)
+        self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None) is not None:
+                self.close()
+        except Exception:
+            pass

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path against the CPU FP64 oracle on the same seeded inputs.
+
+Bar: every field within 1e-8 relative (per species, over the domain voxels of the
+box) of the oracle, solved to 1e-12 on the GPU and 1e-13 in the oracle (error <=
+kappa * tol per step, kappa <= 1 + dt (k_max + 12 D_max / h^2)); lattice voxels
+outside the box or the mask must come back bit-identical; bounding boxes bit-exact.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_run, rel_err_per_species, require_gpu, to_dev
+from oracle.bbox import bbox_from_cells
+from oracle.fv import assemble, box_slice
+from oracle.step import problem_box, run
+from synth import config1, random_problem
+
+pytestmark = pytest.mark.gpu
+
+PARITY = 1e-8
+
+
+def _check_parity(prob, steps, box=None, tol=1e-12, **opts):
+    box = box if box is not None else problem_box(prob)
+    got, stats = gpu_run(prob, steps, tol, box=box, **opts)
+    want, _ = run(prob, steps=steps, solver="pcg", tol=1e-13, box=box)
+    mb = prob.mask[box_slice(box)].astype(bool)
+    errs = rel_err_per_species(got, want, mb, box)
+    print(f"{prob.name} box={box} steps={steps} opts={opts} rel_err={errs}", flush=True)
+    assert max(errs) <= PARITY, errs
+    # voxels outside the box/mask are never written
+    touched = np.zeros(prob.mask.shape, bool)
+    touched[box_slice(box)] = mb
+    assert np.array_equal(got[:, ~touched], prob.c0[:, ~touched])
+    for st in stats[-1]:
+        assert st["converged"] == 1 and st["rel_res_final"] <= tol
+    return got, stats
+
+
+# ----------------------------------------------------------------- bounding box
+@pytest.mark.parametrize("dims,frac,margin", [((40, 24, 12), 0.01, 4), ((37, 29, 23), 0.003, 2),
+                                              ((64, 64, 64), 0.0005, 0), ((5, 3, 2), 0.2, 9)])
+def test_bbox_bit_exact(dims, frac, margin):
+    torch = require_gpu()
+    from paper_2505_03067_amd import mpm_bbox_from_cells
+    rng = np.random.default_rng(sum(dims))
+    nx, ny, nz = dims
+    cell = np.where(rng.random((nz, ny, nx)) < frac, rng.integers(1, 1000, (nz, ny, nx)), 0)
+    cell = cell.astype(np.int32)
+    cell[nz // 2, ny // 3, nx - 1] = 7
+    got = mpm_bbox_from_cells(torch.from_numpy(cell).cuda(), margin)
+    assert got == bbox_from_cells(cell, margin)
+
+
+def test_bbox_empty_and_single():
+    torch = require_gpu()
+    from paper_2505_03067_amd import MPM_EEMPTY, MpmError, mpm_bbox_from_cells
+    cell = np.zeros((6, 7, 8), np.int32)
+    with pytest.raises(MpmError) as e:
+        mpm_bbox_from_cells(torch.from_numpy(cell).cuda(), 2)
+    assert e.value.code == MPM_EEMPTY
+    cell[0, 0, 0] = -3                           # negative ids are not cells
+    with pytest.raises(MpmError):
+        mpm_bbox_from_cells(torch.from_numpy(cell).cuda(), 2)
+    cell[5, 6, 7] = 1
+    assert mpm_bbox_from_cells(torch.from_numpy(cell).cuda(), 2) == ((5, 4, 3), (8, 7, 6))
+
+
+# ----------------------------------------------------------------- stencil
+@pytest.mark.parametrize("seed,dims,box", [
+    (1, (19, 17, 13), None),
+    (2, (37, 29, 23), ((3, 2, 1), (35, 27, 22))),
+    (3, (64, 33, 9), ((0, 5, 0), (64, 33, 9))),
+])
+def test_stencil_matches_oracle_matrix(seed, dims, box):
+    torch = require_gpu()
+    from paper_2505_03067_amd import Solver
+    p = random_problem(seed, dims, S=3, fill=0.55, box=box)
+    box = p.box
+    sl = box_slice(box)
+    mb = p.mask[sl].astype(bool)
+    d = to_dev(p)
+    x = np.random.default_rng(seed).uniform(-1, 1, p.c0.shape)
+    xd = torch.from_numpy(x).cuda()
+    for prec, modes in ((0, (0, 2)), (1, (0, 1))):
+        with Solver(3, 1, precision=prec) as s:
+            s.setup(0, box, d["mask"], d["D"], d["k"], d["src"], p.c_b, 0.7, 1.3)
+            for mode in modes:
+                y = torch.full_like(xd, 123.0)
+                s.apply(0, xd, y, mode)
+                yh = y.cpu().numpy()
+                for sp in range(3):
+                    A, _ = assemble(mb, p.D[sp][sl], p.k[sp][sl], p.src[sp][sl], p.c_b[sp], 0.7, 1.3)
+                    xs = x[sp][sl][mb]
+                    if mode == 0:
+                        ref = A @ xs
+                    else:
+                        sc = 1.0 / np.sqrt(A.diagonal())
+                        ref = sc * (A @ (sc * xs))
+                    scale = abs(A) @ abs(xs) if mode == 0 else np.abs(ref) + 1.0
+                    err = np.max(np.abs(yh[sp][sl][mb] - ref) / scale)
+                    tolm = 1e-6 if mode == 1 else 1e-14
+                    assert err <= tolm, (prec, mode, sp, err)
+                    # voxels outside the domain of the box untouched
+                    outside = np.ones(p.mask.shape, bool)
+                    outside[sl] = ~mb
+                    assert np.all(yh[sp][outside] == 123.0)
+
+
+# ----------------------------------------------------------------- whole steps
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config1_ten_steps(precision):
+    require_gpu()
+    p = config1()
+    _, stats = _check_parity(p, 10, precision=precision)
+    its = [s[0]["iterations"] for s in stats]
+    print("iterations per step", its)
+    assert all(5 <= i <= 120 for i in its)
+
+
+@pytest.mark.parametrize("seed,dims,fill,S", [(11, (37, 29, 23), 0.5, 3), (12, (50, 21, 17), 0.8, 2),
+                                              (13, (23, 41, 30), 0.3, 4), (14, (9, 8, 7), 0.9, 1)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_random_masked_boxes(seed, dims, fill, S, precision):
+    require_gpu()
+    p = random_problem(seed, dims, S=S, fill=fill,
+                       box=((1, 2, 0), (dims[0] - 1, dims[1], dims[2] - 2)), dt=1.5, h=0.9)
+    _check_parity(p, 3, precision=precision)
+
+
+def test_cell_bounding_box_workload_small():
+    """Box from cells with a margin on a ragged lattice, three species."""
+    torch = require_gpu()
+    from paper_2505_03067_amd import mpm_bbox_from_cells
+    p = random_problem(21, (45, 38, 27), S=3, fill=0.7)
+    p.cell_id[:] = 0
+    p.cell_id[10:18, 6:30, 12:40] = 5
+    box = mpm_bbox_from_cells(torch.from_numpy(p.cell_id).cuda(), 4)
+    assert box == bbox_from_cells(p.cell_id, 4)
+    _check_parity(p, 2, box=box)
+
+
+@pytest.mark.parametrize("opts", [dict(batched=0), dict(use_graph=0), dict(restart=5),
+                                  dict(restart=1, max_cycles=2000), dict(tile_override=2048)])
+def test_modes_agree(opts):
+    require_gpu()
+    p = random_problem(31, (33, 30, 28), S=3, fill=0.6)
+    _check_parity(p, 2, **opts)
+
+
+def test_batched_graph_and_unbatched_are_bit_identical():
+    require_gpu()
+    p = random_problem(32, (29, 31, 27), S=3, fill=0.6)
+    ref, _ = gpu_run(p, 2, 1e-10)
+    for opts in (dict(batched=0), dict(use_graph=0), dict(batched=0, use_graph=0)):
+        got, _ = gpu_run(p, 2, 1e-10, **opts)
+        assert np.array_equal(got, ref), opts
+    again, _ = gpu_run(p, 2, 1e-10)                   # run-to-run determinism
+    assert np.array_equal(again, ref)
+
+
+def test_edge_cases_tiny_boxes():
+    require_gpu()
+    # single-voxel box; 1-voxel-thick slab; box exactly filling 1024 domain voxels
+    p = random_problem(41, (6, 5, 4), S=2, fill=1.0, box=((2, 2, 1), (3, 3, 2)))
+    _check_parity(p, 2)
+    p = random_problem(42, (16, 16, 3), S=2, fill=1.0, box=((0, 0, 1), (16, 16, 2)))
+    _check_parity(p, 2)
+    p = random_problem(43, (16, 16, 4), S=1, fill=1.0)       # N = 1024 exactly
+    _check_parity(p, 2)
+
+
+def test_multi_problem_context():
+    torch = require_gpu()
+    from paper_2505_03067_amd import Solver
+    probs = [random_problem(50 + i, dims, S=3, fill=0.6)
+             for i, dims in enumerate([(21, 17, 13), (40, 12, 30), (9, 9, 9)])]
+    fields = [torch.from_numpy(p.c0).cuda() for p in probs]
+    with Solver(3, len(probs)) as s:
+        for i, p in enumerate(probs):
+            d = to_dev(p)
+            s.setup(i, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, 1.0, 1.0)
+        for _ in range(2):
+            s.step(fields, 1e-12)
+    for p, f in zip(probs, fields):
+        want, _ = run(p, steps=2, solver="pcg", tol=1e-13)
+        mb = p.mask[box_slice(p.box)].astype(bool)
+        errs = rel_err_per_species(f.cpu().numpy(), want, mb, p.box)
+        assert max(errs) <= PARITY, errs
+
+
+def test_error_paths():
+    torch = require_gpu()
+    from paper_2505_03067_amd import (MPM_EEMPTY, MPM_EINVAL, MPM_ESTATE, MPM_NOT_CONVERGED,
+                                      MpmError, Solver)
+    p = random_problem(61, (12, 11, 10), S=2, fill=0.6)
+    d = to_dev(p)
+    f = torch.from_numpy(p.c0).cuda()
+    with Solver(2, 1) as s:
+        with pytest.raises(MpmError) as e:
+            s.step([f], 1e-8)
+        assert e.value.code == MPM_ESTATE
+        with pytest.raises(MpmError) as e:
+            s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, -1.0, 1.0)
+        assert e.value.code == MPM_EINVAL
+        with pytest.raises(MpmError) as e:
+            s.setup(0, ((0, 0, 0), (13, 11, 10)), d["mask"], d["D"], d["k"], d["src"], p.c_b, 1, 1)
+        assert e.value.code == MPM_EINVAL
+        empty = torch.zeros_like(d["mask"])
+        with pytest.raises(MpmError) as e:
+            s.setup(0, p.box, empty, d["D"], d["k"], d["src"], p.c_b, 1.0, 1.0)
+        assert e.value.code == MPM_EEMPTY
+        s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, 1.0, 1.0)
+        with pytest.raises(MpmError) as e:
+            s.step([f], 0.0)
+        assert e.value.code == MPM_EINVAL
+    with Solver(2, 1, max_cycles=1, restart=2) as s:
+        s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, 1.0, 1.0)
+        rc = s.step([f], 1e-14)
+        assert rc == MPM_NOT_CONVERGED
+        st = s.stats(0, 0)
+        assert st["converged"] == 0 and st["cycles"] == 1 and st["iterations"] == 2
+        assert st["rel_res_final"] < st["rel_res_initial"]
+        assert np.all(np.isfinite(f.cpu().numpy()))
