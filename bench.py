@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Implicit steps/s of the 128^3-box x 3-species reaction-diffusion workload on one MI355X.
+
+Workload (default): 256x256x160 lattice with a synthetic pleural shell (two nested
+ellipsoid pairs, 6 voxels thick), 4000 Voronoi tumour cells, the 128^3 bounding box
+of the cells plus a 4-voxel margin, three species (oxygen, nutrient, cytokine), one
+implicit-Euler step per "step", each solved to a relative FP64 residual of 1e-8 by
+FP32 GMRES(30) inside FP64 iterative refinement, all species batched in one launch,
+each cycle replayed from a hipGraph.  Inputs are seeded and synthetic.
+
+Prints ONE JSON line (rank 0).  Besides steps/s it reports the dominant kernel's
+achieved algorithmic HBM bandwidth (HIP events on the library's stream), the same
+workload with plain FP64 GMRES, and the CPU FP64 oracle timed on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+KERNELS = {"spmv_dot": 1, "axpy_dot": 2, "axpy_norm": 3, "update": 4, "residual": 5}
+KERNEL_NAMES = {1: "k_spmv_dot", 2: "k_axpy_dot", 3: "k_axpy_norm", 4: "k_update",
+                5: "k_residual"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="config2", choices=["config2", "config2-dense", "config1"])
+    ap.add_argument("--precision", default="fp32ir", choices=["fp32ir", "fp64"])
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--unbatched", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="unknowns per block (0 = library default)")
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--time-kernel", default="axpy_dot:10",
+                    help="kernel:j timed with HIP events for the roofline ('none' to skip)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget of the CPU oracle sample (0 = skip)")
+    return ap.parse_args()
+
+
+def make_workload(name):
+    from synth import config1, config2, config2_dense
+    if name == "config2":
+        return config2()
+    if name == "config2-dense":
+        return config2_dense()
+    return config1()
+
+
+def upload(prob, torch):
+    dev = torch.device("cuda")
+    return {k: torch.from_numpy(getattr(prob, k)).to(dev) for k in ("mask", "D", "k", "src", "cell_id")}
+
+
+def gpu_solver(m, prob, t, box, precision, graph, batched, tile=0):
+    s = m.Solver(prob.nspecies, 1, precision=precision, use_graph=int(graph), batched=int(batched),
+                 tile_override=int(tile))
+    s.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
+    return s
+
+
+def run_steps(s, f, n, tol, torch):
+    its = []
+    for _ in range(n):
+        rc = s.step([f], tol)
+        if rc != 0:
+            raise RuntimeError(f"step did not converge (status {rc})")
+        its.append(sum(s.stats(0, sp)["iterations"] for sp in range(s.nspecies)))
+    torch.cuda.synchronize()
+    return its
+
+
+def cpu_baseline(prob, box, c_start, gpu_after, tol, budget_s):
+    """The oracle (FP64 GMRES(30) + Jacobi, single-threaded) timed on a bounded sample.
+
+    Runs consecutive steps from the same c^n the GPU started from, until the time budget
+    is spent (at least one step), and compares each species with the GPU's fields.
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.fv import box_slice
+    from oracle.step import implicit_step
+
+    sl = box_slice(box)
+    mb = prob.mask[sl].astype(bool)
+    c = c_start.copy()
+    done = 0
+    t0 = time.perf_counter()
+    errs = []
+    with threadpool_limits(limits=1):
+        while done < len(gpu_after):
+            c, _ = implicit_step(c, prob.mask, prob.D, prob.k, prob.src, prob.c_b, box,
+                                 prob.dt, prob.h, solver="gmres", tol=tol, restart=30)
+            done += 1
+            g = gpu_after[done - 1]
+            errs.append([float(np.linalg.norm(g[s][sl][mb] - c[s][sl][mb]) /
+                               np.linalg.norm(c[s][sl][mb])) for s in range(prob.nspecies)])
+            if time.perf_counter() - t0 >= budget_s:
+                break
+    dt = time.perf_counter() - t0
+    return done, dt, errs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the species and problems shard across GPUs with no communication, see the design notes)",
+              file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    import paper_2505_03067_amd as m
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    m.lib()
+    prob = make_workload(args.workload)
+    tol = args.tol if args.tol is not None else prob.tol
+    t = upload(prob, torch)
+    if prob.box is not None:
+        box = prob.box
+    else:
+        box = m.mpm_bbox_from_cells(t["cell_id"], prob.margin)
+    precision = m.MPM_FP32_IR if args.precision == "fp32ir" else m.MPM_FP64
+    f = torch.from_numpy(prob.c0).cuda()
+
+    s = gpu_solver(m, prob, t, box, precision, not args.no_graph, not args.unbatched, args.tile)
+    run_steps(s, f, args.warmup, tol, torch)
+    c_start = f.clone()
+    kname, kj = None, 0
+    if args.time_kernel != "none":
+        kname, _, kj = args.time_kernel.partition(":")
+        kj = int(kj or 0)
+        s.time_kernel(KERNELS[kname], kj)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = run_steps(s, f, args.steps, tol, torch)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timing = s.kernel_timing() if kname else None
+    tile_used = s.tile()
+    final_stats = [s.stats(0, sp) for sp in range(prob.nspecies)]
+    s.close()
+
+    N = int(prob.mask[box[0][2]:box[1][2], box[0][1]:box[1][1], box[0][0]:box[1][0]].sum())
+    U = N * prob.nspecies
+    steps_per_s = args.steps / elapsed
+
+    out = {
+        "metric": "implicit steps/s, 128^3 box x 3 species to 1e-8 resid; HBM GB/s; learned vs plain",
+        "value": round(steps_per_s, 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if precision == m.MPM_FP32_IR else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{prob.name}: lattice {prob.dims}, box {box}, {N} domain voxels, "
+                        f"{prob.nspecies} species, {U} unknowns, tol {tol:g}, "
+                        f"{'FP32 GMRES(30) in FP64 refinement' if precision else 'FP64 GMRES(30)'}, "
+                        f"{'batched' if not args.unbatched else 'one system at a time'}, "
+                        f"{'hipGraph cycles' if not args.no_graph else 'direct launches'}",
+            "unknowns": U,
+            "domain_voxels": N,
+            "box": [list(box[0]), list(box[1])],
+            "unknowns_per_block": tile_used,
+        },
+        "iterations_per_step": round(sum(its) / len(its) / prob.nspecies, 2),
+        "cycles_last_step": [st["cycles"] for st in final_stats],
+        "rel_res_final_last_step": [st["rel_res_final"] for st in final_stats],
+    }
+    if timing and timing["launches"]:
+        avg_ms = timing["ms"] / timing["launches"]
+        achieved = timing["bytes"] / (timing["ms"] * 1e-3) / 1e9
+        out["roofline"] = {
+            "bound": "hbm",
+            "kernel": f"{KERNEL_NAMES[KERNELS[kname]]}<{'float' if precision else 'double'},{kj}>",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_us": round(1000.0 * avg_ms, 3),
+            "launches": timing["launches"],
+            "alg_bytes_per_launch": round(timing["bytes"] / timing["launches"]),
+        }
+
+    if not args.no_plain and precision == m.MPM_FP32_IR:
+        f2 = c_start.clone()
+        s2 = gpu_solver(m, prob, t, box, m.MPM_FP64, not args.no_graph, not args.unbatched, args.tile)
+        run_steps(s2, f2, 2, tol, torch)
+        f2.copy_(c_start)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        its2 = run_steps(s2, f2, args.steps, tol, torch)
+        torch.cuda.synchronize()
+        e2 = time.perf_counter() - t1
+        s2.close()
+        out["plain_fp64"] = {"steps_per_s": round(args.steps / e2, 3),
+                             "iterations_per_step": round(sum(its2) / len(its2) / prob.nspecies, 2),
+                             "speedup_of_value": round(steps_per_s / (args.steps / e2), 3)}
+
+    if args.cpu_seconds > 0:
+        # replay the first steps of the timed run on the GPU (deterministic) to compare
+        s3 = gpu_solver(m, prob, t, box, precision, not args.no_graph, not args.unbatched, args.tile)
+        f3 = c_start.clone()
+        after = []
+        for _ in range(min(args.steps, 8)):
+            s3.step([f3], tol)
+            after.append(f3.cpu().numpy())
+        s3.close()
+        done, cpu_s, errs = cpu_baseline(prob, box, c_start.cpu().numpy(), after, tol,
+                                         args.cpu_seconds)
+        out["cpu_baseline"] = {
+            "value": round(done / cpu_s, 5),
+            "unit": "steps/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"{done} consecutive steps of the same workload from the same c^n "
+                      f"(FP64 GMRES(30) + Jacobi, tol {tol:g}, scipy CSR, 1 thread), {cpu_s:.1f} s",
+        }
+        out["fp64_rel_err_vs_oracle"] = [max(e[sp] for e in errs) for sp in range(prob.nspecies)]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

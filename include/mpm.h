@@ -140,6 +140,33 @@ int32_t mpm_destroy(mpm_ctx ctx);
 /* Message for the last non-OK status returned on the calling thread. */
 const char* mpm_last_error(void);
 
+/* Measurement hook: time every launch of one kernel of the GMRES cycle with HIP
+ * events recorded on the context's own stream (the stream the kernels run on).
+ * kind: MPM_KERNEL_NONE (off), MPM_KERNEL_SPMV_DOT (stencil + first Gram-Schmidt
+ * pass), MPM_KERNEL_AXPY_DOT (second pass), MPM_KERNEL_AXPY_NORM (third pass +
+ * Givens), MPM_KERNEL_UPDATE (x += S V y), MPM_KERNEL_RESIDUAL (FP64 r = b - A x);
+ * j: Arnoldi step of kinds 1-3, ignored otherwise.  Selecting resets the counters
+ * read by mpm_kernel_timing and re-captures the cycle graph. */
+#define MPM_KERNEL_NONE 0
+#define MPM_KERNEL_SPMV_DOT 1
+#define MPM_KERNEL_AXPY_DOT 2
+#define MPM_KERNEL_AXPY_NORM 3
+#define MPM_KERNEL_UPDATE 4
+#define MPM_KERNEL_RESIDUAL 5
+int32_t mpm_time_kernel(mpm_ctx ctx, int32_t kind, int32_t j);
+
+/* Totals since mpm_time_kernel: summed event time in ms, number of launches, and
+ * the algorithmic bytes those launches had to move for the systems that were
+ * active (domain unknowns only, padding excluded; counted per unknown as
+ * K1: t (j + 5) + 16 / S, K2 and K3: t (j + 3), update: t m + 24,
+ * residual: 56 + t + 16 / S, with t = 4 (MPM_FP32_IR) or 8 (MPM_FP64) bytes).
+ * All outputs are host pointers. */
+int32_t mpm_kernel_timing(mpm_ctx ctx, double* ms, int64_t* launches, double* bytes);
+
+/* Unknowns per block of the current work split (after autotuning, if any); *out is a
+ * host int.  MPM_ESTATE before the first step or mpm_debug_apply. */
+int32_t mpm_tile(mpm_ctx ctx, int32_t* out);
+
 /* Test hook: apply the discrete operator of 'problem' to a lattice field.
  * x_lattice, y_lattice: device FP64 [S][z][y][x]; only domain voxels of the box are
  * read / written.  mode 0: y = A x (FP64, unscaled); mode 1: y = S A S x with

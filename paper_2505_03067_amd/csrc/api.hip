@@ -21,14 +21,15 @@ static void destroy_ctx(Ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& ph : c->probs) free_problem(ph);
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    for (auto g : c->graphs)
+        if (g) (void)hipGraphExecDestroy(g);
     (void)hipFree(c->d_probs);
     (void)hipFree(c->d_sk);
     (void)hipFree(c->d_part);
-    (void)hipFree(c->d_cnt);
     (void)hipFree(c->d_prm);
     (void)hipFree(c->d_blocks);
     (void)hipFree(c->d_blocks_sys);
+    (void)hipFree(c->d_sysfc);
     (void)hipFree(c->d_fields);
     (void)hipFree(c->V);
     (void)hipFree(c->W);
@@ -39,6 +40,7 @@ static void destroy_ctx(Ctx* c) {
     if (c->h_sk) (void)hipHostFree(c->h_sk);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    for (auto e : c->tev) (void)hipEventDestroy(e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -113,14 +115,13 @@ extern "C" int32_t mpm_create(mpm_ctx* out, int32_t nspecies, int32_t nproblems,
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&c->d_probs, nproblems * sizeof(ProbDev));
     if (e == hipSuccess) e = hipMalloc(&c->d_sk, nsys * sizeof(SysK));
-    if (e == hipSuccess) e = hipMalloc(&c->d_cnt, kMaxSys * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&c->d_prm, sizeof(Params));
+    if (e == hipSuccess) e = hipMalloc(&c->d_sysfc, 2 * kMaxSys * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&c->d_fields, nproblems * sizeof(double*));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_fields, nproblems * sizeof(double*), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_prm, sizeof(Params), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sk, nsys * sizeof(SysK), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemset(c->d_sk, 0, nsys * sizeof(SysK));
-    if (e == hipSuccess) e = hipMemset(c->d_cnt, 0, kMaxSys * sizeof(int));
     if (e != hipSuccess) {
         int r = hip_fail(e, "mpm_create");
         destroy_ctx(c);
@@ -235,4 +236,39 @@ extern "C" int32_t mpm_debug_apply(mpm_ctx ctx, int32_t problem, const double* x
     rc = debug_apply(c, problem, x_lattice, y_lattice, mode);
     if (rc == MPM_OK) rc = leave(c);
     return rc;
+}
+
+extern "C" int32_t mpm_time_kernel(mpm_ctx ctx, int32_t kind, int32_t j) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || kind < MPM_KERNEL_NONE || kind > MPM_KERNEL_RESIDUAL || j < 0 || j >= c->opt.restart) {
+        set_error("mpm_time_kernel: bad arguments");
+        return MPM_EINVAL;
+    }
+    return select_timing(c, kind, j);
+}
+
+extern "C" int32_t mpm_kernel_timing(mpm_ctx ctx, double* ms, int64_t* launches, double* bytes) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !ms || !launches || !bytes) {
+        set_error("mpm_kernel_timing: null pointer");
+        return MPM_EINVAL;
+    }
+    *ms = c->time_ms;
+    *launches = c->time_launches;
+    *bytes = c->time_bytes;
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_tile(mpm_ctx ctx, int32_t* out) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !out) {
+        set_error("mpm_tile: null pointer");
+        return MPM_EINVAL;
+    }
+    if (c->layout_dirty || c->block_unknowns <= 0) {
+        set_error("mpm_tile: no work split yet");
+        return MPM_ESTATE;
+    }
+    *out = c->block_unknowns;
+    return MPM_OK;
 }

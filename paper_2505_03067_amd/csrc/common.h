@@ -17,7 +17,7 @@ constexpr int kAlign = 1024;             // unknown counts are padded to this
 constexpr long long kLead = 1024;        // zero elements before the first unknown
 constexpr int kMaxM = MPM_MAX_RESTART;   // longest restart
 constexpr int kMaxSys = 64;              // (problem, species) systems per context
-constexpr int kPartRows = kMaxM + 2;     // partial-sum rows per block slot
+constexpr int kPartRows = 2 * (kMaxM + 1) + 4;   // partial-sum rows per block slot
 
 // ---------------------------------------------------------------- device views
 // Per-problem data, addressed with the problem-local unknown index
@@ -47,14 +47,14 @@ struct Block {
     int slot;    // partial-sum slot of this block
 };
 
-// Per-system Krylov state, written by the last block of each reduction.
+// Per-system Krylov state.  Within one launch every block reads it and only the
+// system's first block writes it, at entries no block of that launch reads.
 struct SysK {
     double h1[kMaxM + 2];    // first Gram-Schmidt coefficients v_k . w
-    double c1[kMaxM + 2];    // the same scaled for the stored (unnormalised) vectors
     double h2[kMaxM + 2];    // reorthogonalisation coefficients
-    double c2[kMaxM + 2];
     double vs[kMaxM + 2];    // v_k = vs[k] * V_k
-    double g[kMaxM + 2];     // rotated right-hand side of the least-squares problem
+    double gt[kMaxM + 2];    // right-hand side entry j before rotation j (read by step j)
+    double gf[kMaxM + 2];    // entry j after rotation j (written by step j)
     double cs[kMaxM + 2];    // Givens cosines
     double sn[kMaxM + 2];    // Givens sines
     double y[kMaxM + 2];     // update coefficients of the stored vectors
@@ -86,7 +86,6 @@ struct KArgs {
     const ProbDev* probs;
     SysK* sk;
     double* part;          // [kPartRows][nslots]
-    int* cnt;              // [kMaxSys] arrival counters
     const Params* prm;
     T* V;                  // basis, vector k at V + k * ldv
     T* W;                  // work vector

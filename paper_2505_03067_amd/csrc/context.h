@@ -1,6 +1,8 @@
 // Host-side solver context (not visible through the C ABI).
 #pragma once
 
+#include <map>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -49,15 +51,16 @@ struct Ctx {
     std::vector<int> sys_tab_first;    // start of each system's table in blocks_sys
     int nslots = 0;
     int block_unknowns = 0;            // unknowns per block (autotuned or fixed)
+    std::map<std::string, long long> tile_cache;   // autotuned split per layout
 
     // device buffers
     ProbDev* d_probs = nullptr;
     SysK* d_sk = nullptr;
     double* d_part = nullptr;
-    int* d_cnt = nullptr;
     Params* d_prm = nullptr;
     Block* d_blocks = nullptr;
     Block* d_blocks_sys = nullptr;
+    int* d_sysfc = nullptr;            // [2][kMaxSys] first slot and block count per system
     double** d_fields = nullptr;
     size_t cap_blocks = 0, cap_slots = 0;
     void* V = nullptr;                 // (restart + 1) vectors of the Krylov type
@@ -72,12 +75,21 @@ struct Ctx {
     Params* h_prm = nullptr;
     SysK* h_sk = nullptr;
 
-    // graph of one GMRES cycle
-    hipGraphExec_t graph = nullptr;
+    // graph of one GMRES cycle (three segments while a kernel is timed)
+    hipGraphExec_t graphs[3] = {nullptr, nullptr, nullptr};
+    int ngraphs = 0;
     bool graph_valid = false;
 
     std::vector<mpm_stats> stats;
     bool stepped = false;
+
+    // kernel timing hook
+    int time_kind = 0, time_j = 0;
+    std::vector<hipEvent_t> tev;       // start/stop pairs, one pair per timed launch
+    int tev_used = 0;                  // pairs recorded in the current cycle
+    double time_ms = 0.0, time_bytes = 0.0;
+    long long time_launches = 0;
+    std::vector<int> prev_cycles;
 };
 
 // setup.hip
@@ -91,5 +103,6 @@ int launch_diag_extremes(Ctx* c, int p);
 int run_step(Ctx* c, double* const* fields, double tol);
 int debug_apply(Ctx* c, int p, const double* x, double* y, int mode);
 int ensure_layout(Ctx* c);
+int select_timing(Ctx* c, int kind, int j);
 
 }  // namespace mpm

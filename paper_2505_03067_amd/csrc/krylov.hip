@@ -13,13 +13,19 @@
 //   residual:   r = b - A x in FP64; V_0 = S r (stored unnormalised, scale 1/||S r||)
 //   step j:     K1  w = B v_j,  h = V_j^T w            (stencil + multi-dot)
 //               K2  w -= V_j h, h2 = V_j^T w           (axpy + multi-dot, CGS2 pass 2)
-//               K3  w -= V_j h2, ||w||, V_{j+1} = w     (axpy + norm) + Givens on device
+//               K3  w -= V_j h2, ||w||, V_{j+1} = w     (axpy + norm)
+//   finish:     Givens rotation of the last column and back-substitution
 //   update:     x += S V_m y  (FP64 accumulation)
-// Every global reduction is two-stage and deterministic: per-block partial sums in
-// fixed order, then the last block of the system to arrive (an atomic counter)
-// sums the partials in block order and runs the scalar work (norms, Givens,
-// back-substitution).  The Krylov type T is float (FP32 basis inside FP64
-// iterative refinement) or double (plain FP64 GMRES); both use the same kernels.
+//
+// Global reductions without atomics.  Each kernel publishes one partial sum per
+// block and row; every block of the *next* kernel (which is ordered after it by the
+// launch boundary) sums the partials of its system itself, in block order.  All
+// blocks therefore hold bit-identical totals, the result is deterministic, and no
+// block waits on another inside a launch.  The Givens rotation of column j is
+// computed the same way by every block of the next step's first kernel; one
+// designated block per system (its first) stores the Hessenberg state.  The Krylov
+// type T is float (FP32 basis inside FP64 iterative refinement) or double (plain
+// FP64 GMRES); both use the same kernels.
 #include <algorithm>
 #include <array>
 #include <chrono>
@@ -29,6 +35,14 @@
 #include "context.h"
 
 namespace mpm {
+
+// partial-sum rows
+constexpr int kRowB = 0;                    // ||b||^2
+constexpr int kRowR = 1;                    // ||r||^2, ||S r||^2
+constexpr int kRowP1 = 3;                   // K1: V_j^T w
+constexpr int kRowP2 = kRowP1 + kMaxM + 1;  // K2: V_j^T w
+constexpr int kRowP3 = kRowP2 + kMaxM + 1;  // K3: ||w||^2
+static_assert(kRowP3 + 1 <= kPartRows, "partial rows");
 
 // ------------------------------------------------------------------ helpers
 template <typename T>
@@ -79,30 +93,27 @@ __device__ inline void block_partials(const double (&acc)[NV], double* part, int
     }
 }
 
-// Release this block's partials; true in exactly one block of the system (the last).
-__device__ inline bool arrive_last(int* cnt, int nb) {
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int prev = atomicAdd(cnt, 1);
-        last = (prev == nb - 1);
-        if (last) atomicExch(cnt, 0);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
-// Sum rows 0..NV-1 of the system's partial slots in block order into out[] (shared).
+// Sum rows 0..NV-1 of a system's partial slots, in block order, into out[] (shared).
+// Wave w owns rows w, w + 4, ...; all loads are issued before any row is reduced.
 template <int NV>
-__device__ inline void final_sums(const double* part, int nslots, int slot0, int nb, double* out) {
+__device__ inline void reduce_partials(const double* part, int nslots, int slot0, int nb, double* out) {
+    constexpr int R = (NV + kWaves - 1) / kWaves;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int v = w; v < NV; v += kWaves) {
-        double t = 0.0;
-        for (int i = lane; i < nb; i += 64) t += part[(long long)v * nslots + slot0 + i];
-        t = wsum(t);
-        if (lane == 0) out[v] = t;
+    double t[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) t[r] = 0.0;
+    for (int i = lane; i < nb; i += 64) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int v = w + r * kWaves;
+            if (v < NV) t[r] += part[(long long)v * nslots + slot0 + i];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int v = w + r * kWaves;
+        const double sum = wsum(t[r]);
+        if (v < NV && lane == 0) out[v] = sum;
     }
     __syncthreads();
 }
@@ -184,14 +195,13 @@ __device__ inline double apply_A(const ProbDev& pd, const Where& wh, const doubl
 }
 
 // ------------------------------------------------------------------ kernels
-// Gather c^n from the lattice into x, form b = c^n + q, and ||b||.
+// Gather c^n from the lattice into x, form b = c^n + q; partials of ||b||^2.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gather(KArgs<T> a) {
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
     const ProbDev pd = a.probs[blk.sys / a.S];
     const Where wh = where_of(a, blk, pd);
-    SysK* sk = a.sk + wh.sys;
     const double* f = a.fields[wh.p] + (long long)wh.s * pd.nvox;
     double acc[1] = {0.0};
     for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
@@ -205,33 +215,16 @@ __global__ __launch_bounds__(kThreads) void k_gather(KArgs<T> a) {
         a.b[u] = bb;
         acc[0] += bb * bb;
     }
-    block_partials<1>(acc, a.part, a.nslots, blk.slot);
-    if (!arrive_last(a.cnt + wh.sys, sk->nblocks)) return;
-    __shared__ double tot[1];
-    final_sums<1>(a.part, a.nslots, sk->slot0, sk->nblocks, tot);
-    if (threadIdx.x == 0) {
-        sk->bnorm = sqrt(tot[0]);
-        sk->iters = 0;
-        sk->cycles = 0;
-        sk->refinements = 0;
-        sk->converged = 0;
-        sk->active = 0;
-        sk->need_update = 0;
-        sk->mcount = 0;
-        sk->breakdown = 0;
-        sk->ws_used = 0;
-        sk->fallback = 0;
-        sk->rel_warm = 0.0;
-    }
+    block_partials<1>(acc, a.part + (long long)kRowB * a.nslots, a.nslots, blk.slot);
 }
 
-// r = b - A x (FP64); V_0 = S r; norms; convergence test; start of the next cycle.
+// r = b - A x (FP64); V_0 = S r; partials of ||r||^2 and ||S r||^2.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int first) {
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
     SysK* sk = a.sk + blk.sys;
-    if (sk->converged) return;
+    if (!first && sk->converged) return;
     const ProbDev pd = a.probs[blk.sys / a.S];
     const Where wh = where_of(a, blk, pd);
     T* V0 = a.V;
@@ -247,40 +240,140 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int first) {
         acc[0] += r * r;
         acc[1] += sr * sr;
     }
-    block_partials<2>(acc, a.part, a.nslots, blk.slot);
-    if (!arrive_last(a.cnt + wh.sys, sk->nblocks)) return;
-    __shared__ double tot[2];
-    final_sums<2>(a.part, a.nslots, sk->slot0, sk->nblocks, tot);
-    if (threadIdx.x == 0) {
-        const Params& prm = *a.prm;
-        const double rn = sqrt(tot[0]), srn = sqrt(tot[1]);
-        const double bn = sk->bnorm;
-        const double rel = bn > 0.0 ? rn / bn : (rn > 0.0 ? INFINITY : 0.0);
-        if (first) sk->rel_init = rel;
-        else sk->refinements += 1;
-        sk->rel_final = rel;
-        sk->rnorm = rn;
-        sk->srnorm = srn;
-        sk->need_update = 0;
-        const bool conv = (rn <= prm.tol * bn) || rn == 0.0;
-        const bool bad = !(rn == rn) || !(srn > 0.0) || isinf(rn);
-        sk->converged = conv ? 1 : 0;
-        if (conv || bad) {
-            sk->active = 0;
-            if (bad && !conv) sk->breakdown = 1;
-        } else {
-            double eta = 0.9 * prm.tol * bn / (rn * sk->kappa_s);
-            if (eta < prm.inner_rtol) eta = prm.inner_rtol;
-            if (eta > 0.5) eta = 0.5;
-            sk->eta = eta;
-            sk->vs[0] = 1.0 / srn;
-            sk->g[0] = srn;
-            sk->active = 1;
-        }
+    block_partials<2>(acc, a.part + (long long)kRowR * a.nslots, a.nslots, blk.slot);
+}
+
+// One block per system: norms, convergence test, start of the next cycle.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_res_final(KArgs<T> a, int sys0, int first) {
+    const int sys = sys0 + blockIdx.x;
+    SysK* sk = a.sk + sys;
+    if (!first && sk->converged) return;
+    __shared__ double tot[3];
+    reduce_partials<2>(a.part + (long long)kRowR * a.nslots, a.nslots, sk->slot0, sk->nblocks, tot);
+    if (first) reduce_partials<1>(a.part + (long long)kRowB * a.nslots, a.nslots, sk->slot0, sk->nblocks, tot + 2);
+    if (threadIdx.x != 0) return;
+    const Params& prm = *a.prm;
+    if (first) {
+        sk->bnorm = sqrt(tot[2]);
+        sk->iters = 0;
+        sk->cycles = 0;
+        sk->refinements = 0;
+        sk->mcount = 0;
+        sk->breakdown = 0;
+        sk->ws_used = 0;
+        sk->fallback = 0;
+        sk->rel_warm = 0.0;
+    }
+    const double rn = sqrt(tot[0]), srn = sqrt(tot[1]);
+    const double bn = sk->bnorm;
+    const double rel = bn > 0.0 ? rn / bn : (rn > 0.0 ? INFINITY : 0.0);
+    if (first) sk->rel_init = rel;
+    else sk->refinements += 1;
+    sk->rel_final = rel;
+    sk->rnorm = rn;
+    sk->srnorm = srn;
+    sk->need_update = 0;
+    const bool conv = (rn <= prm.tol * bn) || rn == 0.0;
+    const bool bad = !(rn == rn) || !(srn > 0.0) || isinf(rn);
+    sk->converged = conv ? 1 : 0;
+    if (conv || bad) {
+        sk->active = 0;
+        if (bad && !conv) sk->breakdown = 1;
+    } else {
+        double eta = 0.9 * prm.tol * bn / (rn * sk->kappa_s);
+        if (eta < prm.inner_rtol) eta = prm.inner_rtol;
+        if (eta > 0.5) eta = 0.5;
+        sk->eta = eta;
+        sk->vs[0] = 1.0 / srn;
+        sk->gt[0] = srn;
+        sk->active = 1;
     }
 }
 
-// K1: w = B v_J and h_k = v_k . w for k <= J.
+// Givens rotation of Hessenberg column Jc (the Arnoldi step that just finished,
+// with ||w|| = hn), update of the rotated right-hand side g, and the end-of-cycle
+// test; at the end of the cycle, back-substitution R y = g.  Wave 0 of every block
+// computes the same values in the same order; only the lead block stores them.
+// Returns true (to the whole block) if the cycle ended at step Jc.
+template <int Jc>
+__device__ inline bool givens_tail(SysK* sk, double hn, int restart, bool lead) {
+    constexpr int LD = kMaxM + 1;
+    __shared__ int s_done;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        double col[Jc + 2];
+#pragma unroll
+        for (int k = 0; k <= Jc; ++k) col[k] = sk->h1[k] + sk->h2[k];
+        col[Jc + 1] = hn;
+#pragma unroll
+        for (int i = 0; i < Jc; ++i) {            // earlier rotations, in order
+            const double cs = sk->cs[i], sn = sk->sn[i];
+            const double t = cs * col[i] + sn * col[i + 1];
+            col[i + 1] = -sn * col[i] + cs * col[i + 1];
+            col[i] = t;
+        }
+        const double rho = sqrt(col[Jc] * col[Jc] + col[Jc + 1] * col[Jc + 1]);
+        double cs = 1.0, sn = 0.0;
+        if (rho > 0.0) {
+            cs = col[Jc] / rho;
+            sn = col[Jc + 1] / rho;
+        }
+        col[Jc] = rho;
+        const double gJ = sk->gt[Jc];
+        const double gn = -sn * gJ;
+        const bool breakdown = !(hn > 0.0) || !(rho > 0.0);
+        const bool done = breakdown || fabs(gn) <= sk->eta * sk->gt[0] || Jc + 1 >= restart;
+        if (lead && lane == 0) {
+#pragma unroll
+            for (int k = 0; k <= Jc; ++k) sk->R[Jc * LD + k] = col[k];
+            sk->cs[Jc] = cs;
+            sk->sn[Jc] = sn;
+            sk->gf[Jc] = cs * gJ;
+            sk->gt[Jc + 1] = gn;
+            sk->vs[Jc + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+        }
+        if (done) {
+            // back-substitution by columns: lane i holds row i of R and g_i and
+            // receives y_k in turn; column Jc is still in registers
+            const int m = Jc + 1;
+            double rrow[Jc + 1];
+#pragma unroll
+            for (int k = 0; k < Jc; ++k) rrow[k] = lane < m ? sk->R[k * LD + lane] : 0.0;
+            rrow[Jc] = 0.0;
+#pragma unroll
+            for (int k = 0; k <= Jc; ++k)
+                if (lane == k) rrow[Jc] = col[k];
+            double gi = lane < Jc ? sk->gf[lane] : 0.0;
+            if (lane == Jc) gi = cs * gJ;
+            double yi = 0.0;
+#pragma unroll
+            for (int k = Jc; k >= 0; --k) {
+                const double rkk = __shfl(rrow[k], k);
+                const double gk = __shfl(gi, k);
+                const double yk = rkk != 0.0 ? gk / rkk : 0.0;
+                if (lane == k) yi = yk;
+                if (lane < k) gi -= rrow[k] * yk;
+            }
+            if (lead) {
+                if (lane < m) sk->y[lane] = yi * sk->vs[lane];
+                if (lane == 0) {
+                    sk->mcount = m;
+                    sk->active = 0;
+                    sk->need_update = 1;
+                    sk->iters += m;
+                    sk->cycles += 1;
+                    if (breakdown && !(hn == 0.0)) sk->breakdown = 1;
+                }
+            }
+        }
+        if (lane == 0) s_done = done ? 1 : 0;
+    }
+    __syncthreads();
+    return s_done != 0;
+}
+
+// K1: (J > 0: finish step J-1 first) w = B v_J and partials of V_k . w, k <= J.
 template <typename T, int J>
 __global__ __launch_bounds__(kThreads) void k_spmv_dot(KArgs<T> a) {
     constexpr int n = VW<T>::n;
@@ -288,11 +381,20 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dot(KArgs<T> a) {
     if (blk.sys < 0) return;
     SysK* sk = a.sk + blk.sys;
     if (!sk->active) return;
+    T vsJ;
+    if constexpr (J == 0) {
+        vsJ = (T)sk->vs[0];
+    } else {
+        __shared__ double red[1];
+        reduce_partials<1>(a.part + (long long)kRowP3 * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
+        const double hn = sqrt(red[0]);
+        if (givens_tail<J - 1>(sk, hn, a.prm->restart, blk.slot == sk->slot0)) return;
+        vsJ = (T)(hn > 0.0 ? 1.0 / hn : 0.0);
+    }
     const ProbDev pd = a.probs[blk.sys / a.S];
     const Where wh = where_of(a, blk, pd);
     const T* c = couplings<T>(pd);
     const T* VJ = a.V + (long long)J * a.ldv;
-    const T vsJ = (T)sk->vs[J];
     double acc[J + 1];
 #pragma unroll
     for (int k = 0; k <= J; ++k) acc[k] = 0.0;
@@ -313,18 +415,10 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dot(KArgs<T> a) {
 #pragma unroll
         for (int e = 0; e < n; ++e) acc[J] += (double)xv[e] * (double)w[e];
     }
-    block_partials<J + 1>(acc, a.part, a.nslots, blk.slot);
-    if (!arrive_last(a.cnt + wh.sys, sk->nblocks)) return;
-    __shared__ double tot[J + 1];
-    final_sums<J + 1>(a.part, a.nslots, sk->slot0, sk->nblocks, tot);
-    for (int k = threadIdx.x; k <= J; k += kThreads) {
-        const double h = sk->vs[k] * tot[k];
-        sk->h1[k] = h;
-        sk->c1[k] = h * sk->vs[k];
-    }
+    block_partials<J + 1>(acc, a.part + (long long)kRowP1 * a.nslots, a.nslots, blk.slot);
 }
 
-// K2: w -= sum_k h_k v_k, then h2_k = v_k . w (classical Gram-Schmidt, second pass).
+// K2: h = V_J^T w from K1's partials; w -= V_J h; partials of V_J^T w (CGS2 pass 2).
 template <typename T, int J>
 __global__ __launch_bounds__(kThreads) void k_axpy_dot(KArgs<T> a) {
     constexpr int n = VW<T>::n;
@@ -332,9 +426,16 @@ __global__ __launch_bounds__(kThreads) void k_axpy_dot(KArgs<T> a) {
     if (blk.sys < 0) return;
     SysK* sk = a.sk + blk.sys;
     if (!sk->active) return;
+    __shared__ double red[J + 1];
+    reduce_partials<J + 1>(a.part + (long long)kRowP1 * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
     double cf[J + 1];
 #pragma unroll
-    for (int k = 0; k <= J; ++k) cf[k] = sk->c1[k];
+    for (int k = 0; k <= J; ++k) {
+        const double vsk = sk->vs[k];
+        const double h = vsk * red[k];
+        cf[k] = h * vsk;
+        if (blk.slot == sk->slot0 && threadIdx.x == 0) sk->h1[k] = h;
+    }
     double acc[J + 1];
 #pragma unroll
     for (int k = 0; k <= J; ++k) acc[k] = 0.0;
@@ -358,79 +459,10 @@ __global__ __launch_bounds__(kThreads) void k_axpy_dot(KArgs<T> a) {
 #pragma unroll
             for (int e = 0; e < n; ++e) acc[k] += (double)vk[k][e] * (double)wn[e];
     }
-    block_partials<J + 1>(acc, a.part, a.nslots, blk.slot);
-    if (!arrive_last(a.cnt + blk.sys, sk->nblocks)) return;
-    __shared__ double tot[J + 1];
-    final_sums<J + 1>(a.part, a.nslots, sk->slot0, sk->nblocks, tot);
-    for (int k = threadIdx.x; k <= J; k += kThreads) {
-        const double h = sk->vs[k] * tot[k];
-        sk->h2[k] = h;
-        sk->c2[k] = h * sk->vs[k];
-    }
+    block_partials<J + 1>(acc, a.part + (long long)kRowP2 * a.nslots, a.nslots, blk.slot);
 }
 
-// Givens rotation of Hessenberg column J, residual estimate, and (when the cycle
-// ends) back-substitution R y = g.  Run by all 64 lanes of wave 0 in lock step.
-template <int J>
-__device__ inline void givens_step(SysK* sk, double hn, int restart) {
-    constexpr int LD = kMaxM + 1;
-    double col[J + 2];
-#pragma unroll
-    for (int k = 0; k <= J; ++k) col[k] = sk->h1[k] + sk->h2[k];
-    col[J + 1] = hn;
-#pragma unroll
-    for (int i = 0; i < J; ++i) {            // earlier rotations, in order
-        const double cs = sk->cs[i], sn = sk->sn[i];
-        const double t = cs * col[i] + sn * col[i + 1];
-        col[i + 1] = -sn * col[i] + cs * col[i + 1];
-        col[i] = t;
-    }
-    const double rho = sqrt(col[J] * col[J] + col[J + 1] * col[J + 1]);
-    double cs = 1.0, sn = 0.0;
-    if (rho > 0.0) {
-        cs = col[J] / rho;
-        sn = col[J + 1] / rho;
-    }
-    col[J] = rho;
-    const double gJ = sk->g[J];
-    const double gn = -sn * gJ;
-    const int lane = threadIdx.x & 63;
-    const bool breakdown = !(hn > 0.0) || !(rho > 0.0);
-    const bool done = breakdown || fabs(gn) <= sk->eta * sk->g[0] || J + 1 >= restart;
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k <= J; ++k) sk->R[J * LD + k] = col[k];
-        sk->cs[J] = cs;
-        sk->sn[J] = sn;
-        sk->g[J] = cs * gJ;
-        sk->g[J + 1] = gn;
-        sk->vs[J + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
-    }
-    __threadfence_block();   // lane 0's stores are read back by the other lanes below
-    if (!done) return;
-    // back-substitution by columns: lane i keeps g_i and receives y_k in turn
-    const int m = J + 1;
-    double gi = lane < m ? sk->g[lane] : 0.0;
-    double yi = 0.0;
-    for (int k = m - 1; k >= 0; --k) {
-        const double rkk = sk->R[k * LD + k];
-        const double gk = __shfl(gi, k);
-        const double yk = rkk != 0.0 ? gk / rkk : 0.0;
-        if (lane == k) yi = yk;
-        if (lane < k) gi -= sk->R[k * LD + lane] * yk;
-    }
-    if (lane < m) sk->y[lane] = yi * sk->vs[lane];
-    if (lane == 0) {
-        sk->mcount = m;
-        sk->active = 0;
-        sk->need_update = 1;
-        sk->iters += m;
-        sk->cycles += 1;
-        if (breakdown && !(hn == 0.0)) sk->breakdown = 1;
-    }
-}
-
-// K3: w -= sum_k h2_k v_k, ||w||, V_{J+1} = w; then the Givens update.
+// K3: h2 from K2's partials; w -= V_J h2; V_{J+1} = w; partials of ||w||^2.
 template <typename T, int J>
 __global__ __launch_bounds__(kThreads) void k_axpy_norm(KArgs<T> a) {
     constexpr int n = VW<T>::n;
@@ -438,11 +470,17 @@ __global__ __launch_bounds__(kThreads) void k_axpy_norm(KArgs<T> a) {
     if (blk.sys < 0) return;
     SysK* sk = a.sk + blk.sys;
     if (!sk->active) return;
-    const int restart = a.prm->restart;
-    const bool store = J + 1 < restart;
+    __shared__ double red[J + 1];
+    reduce_partials<J + 1>(a.part + (long long)kRowP2 * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
     double cf[J + 1];
 #pragma unroll
-    for (int k = 0; k <= J; ++k) cf[k] = sk->c2[k];
+    for (int k = 0; k <= J; ++k) {
+        const double vsk = sk->vs[k];
+        const double h = vsk * red[k];
+        cf[k] = h * vsk;
+        if (blk.slot == sk->slot0 && threadIdx.x == 0) sk->h2[k] = h;
+    }
+    const bool store = J + 1 < a.prm->restart;
     T* VN = a.V + (long long)(J + 1) * a.ldv;
     double acc[1] = {0.0};
     for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
@@ -466,11 +504,18 @@ __global__ __launch_bounds__(kThreads) void k_axpy_norm(KArgs<T> a) {
         }
         if (store) st16(VN + u0, wn);
     }
-    block_partials<1>(acc, a.part, a.nslots, blk.slot);
-    if (!arrive_last(a.cnt + blk.sys, sk->nblocks)) return;
-    __shared__ double tot[1];
-    final_sums<1>(a.part, a.nslots, sk->slot0, sk->nblocks, tot);
-    if (threadIdx.x < 64) givens_step<J>(sk, sqrt(tot[0]), restart);
+    block_partials<1>(acc, a.part + (long long)kRowP3 * a.nslots, a.nslots, blk.slot);
+}
+
+// After the last Arnoldi step of a cycle: Givens of column J and back-substitution
+// (one block per system; systems whose cycle already ended are skipped).
+template <typename T, int J>
+__global__ __launch_bounds__(kThreads) void k_finish(KArgs<T> a, int sys0) {
+    SysK* sk = a.sk + sys0 + blockIdx.x;
+    if (!sk->active) return;
+    __shared__ double red[1];
+    reduce_partials<1>(a.part + (long long)kRowP3 * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
+    (void)givens_tail<J>(sk, sqrt(red[0]), a.prm->restart, true);
 }
 
 // x += S sum_k y_k V_k (FP64 accumulation of the FP32 or FP64 basis).
@@ -501,7 +546,6 @@ __global__ __launch_bounds__(kThreads) void k_update(KArgs<T> a) {
     }
 }
 
-// Write x back onto the domain voxels of the lattice fields.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_scatter(KArgs<T> a) {
     const Block blk = a.blocks[blockIdx.x];
@@ -604,6 +648,8 @@ __global__ __launch_bounds__(kThreads) void k_dbg_apply(ProbDev pd, int S, const
 // ------------------------------------------------------------------ dispatch tables
 template <typename T>
 using KFn = void (*)(KArgs<T>);
+template <typename T>
+using KFinFn = void (*)(KArgs<T>, int);
 
 template <typename T, int... Js>
 static std::array<KFn<T>, sizeof...(Js)> table_k1(std::integer_sequence<int, Js...>) {
@@ -617,14 +663,20 @@ template <typename T, int... Js>
 static std::array<KFn<T>, sizeof...(Js)> table_k3(std::integer_sequence<int, Js...>) {
     return {&k_axpy_norm<T, Js>...};
 }
+template <typename T, int... Js>
+static std::array<KFinFn<T>, sizeof...(Js)> table_k4(std::integer_sequence<int, Js...>) {
+    return {&k_finish<T, Js>...};
+}
 
 template <typename T>
 struct Kernels {
     std::array<KFn<T>, kMaxM> k1, k2, k3;
+    std::array<KFinFn<T>, kMaxM> k4;
     Kernels() {
         k1 = table_k1<T>(std::make_integer_sequence<int, kMaxM>{});
         k2 = table_k2<T>(std::make_integer_sequence<int, kMaxM>{});
         k3 = table_k3<T>(std::make_integer_sequence<int, kMaxM>{});
+        k4 = table_k4<T>(std::make_integer_sequence<int, kMaxM>{});
     }
 };
 
@@ -647,27 +699,19 @@ static void free_work(Ctx* c) {
 
 static size_t ksize(const Ctx* c) { return c->opt.precision == MPM_FP64 ? 8 : 4; }
 
-// Split each system into blocks, build the XCD-aware batched table and the
-// per-system tables.
-static void build_tables(Ctx* c) {
+// Split each system into blocks of 'per' unknowns (a multiple of kAlign), build the
+// XCD-aware batched table and the per-system tables.
+static void build_tables(Ctx* c, long long per) {
     const int S = c->S;
     const int nsys = S * c->P;
-    long long maxpad = 0;
-    for (auto& ph : c->probs) maxpad = std::max<long long>(maxpad, ph.Npad);
+    per = std::max<long long>(kAlign, (per + kAlign - 1) / kAlign * kAlign);
+    c->block_unknowns = (int)per;
     std::vector<Block> logical;
     c->sys_first.assign(nsys, 0);
     c->sys_count.assign(nsys, 0);
     int slot = 0;
     for (int p = 0; p < c->P; ++p) {
         const ProbHost& ph = c->probs[p];
-        // unknowns per block: a fixed override, else enough blocks to fill the GPU
-        long long per = c->opt.tile_override > 0 ? c->opt.tile_override : 0;
-        if (per <= 0) {
-            const long long target = std::max(1, 2048 / std::max(1, nsys));
-            per = (ph.Npad + target - 1) / target;
-        }
-        per = std::max<long long>(kAlign, (per + kAlign - 1) / kAlign * kAlign);
-        c->block_unknowns = (int)per;
         for (int s = 0; s < S; ++s) {
             const int sys = p * S + s;
             const long long base = c->off[p] + (long long)s * ph.Npad;
@@ -700,17 +744,127 @@ static void build_tables(Ctx* c) {
     c->blocks.clear();
     swizzle(logical, c->blocks);
     c->blocks_sys.clear();
-    std::vector<int> sfirst(nsys);
+    c->sys_tab_first.assign(nsys, 0);
     for (int sys = 0; sys < nsys; ++sys) {
         std::vector<Block> L(logical.begin() + c->sys_first[sys],
                              logical.begin() + c->sys_first[sys] + c->sys_count[sys]);
-        sfirst[sys] = (int)c->blocks_sys.size();
+        c->sys_tab_first[sys] = (int)c->blocks_sys.size();
         swizzle(L, c->blocks_sys);
     }
-    // reuse sys_first/sys_count as the slice of blocks_sys per system for launches;
-    // the partial-slot ranges go to the device SysK through k_sys_init
-    c->sys_tab_first = sfirst;
 }
+
+// Unknowns per block when nothing is tuned: about 160 blocks per system, since every
+// block re-reads all partial sums of its system.
+static long long model_tile(const Ctx* c) {
+    long long maxpad = 0;
+    for (auto& ph : c->probs) maxpad = std::max<long long>(maxpad, ph.Npad);
+    return std::max<long long>(2048, maxpad / 160);
+}
+
+// Copy the block tables and problem descriptors to the device (growing buffers).
+static int upload_tables(Ctx* c) {
+    hipStream_t st = c->stream;
+    const size_t nb = c->blocks.size(), nbs = c->blocks_sys.size();
+    if (nb > c->cap_blocks || nbs > c->cap_blocks) {
+        if (c->d_blocks) (void)hipFree(c->d_blocks);
+        if (c->d_blocks_sys) (void)hipFree(c->d_blocks_sys);
+        c->d_blocks = c->d_blocks_sys = nullptr;
+        const size_t cap = std::max(nb, nbs) * 2;
+        if (hipMalloc(&c->d_blocks, cap * sizeof(Block)) != hipSuccess ||
+            hipMalloc(&c->d_blocks_sys, cap * sizeof(Block)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->cap_blocks = 0;
+            set_error("device allocation of block tables failed");
+            return MPM_ENOMEM;
+        }
+        c->cap_blocks = cap;
+    }
+    if ((size_t)c->nslots > c->cap_slots) {
+        if (c->d_part) (void)hipFree(c->d_part);
+        c->d_part = nullptr;
+        const size_t cap = (size_t)c->nslots * 2;
+        if (hipMalloc(&c->d_part, cap * kPartRows * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->cap_slots = 0;
+            set_error("device allocation of partial sums failed");
+            return MPM_ENOMEM;
+        }
+        c->cap_slots = cap;
+    }
+    MPM_HIP(hipMemcpyAsync(c->d_blocks, c->blocks.data(), nb * sizeof(Block), hipMemcpyHostToDevice, st));
+    MPM_HIP(hipMemcpyAsync(c->d_blocks_sys, c->blocks_sys.data(), nbs * sizeof(Block), hipMemcpyHostToDevice, st));
+    std::vector<int> fc(2 * (size_t)c->S * c->P);
+    const int nsys = c->S * c->P;
+    for (int s = 0; s < nsys; ++s) {
+        fc[s] = c->sys_first[s];
+        fc[nsys + s] = c->sys_count[s];
+    }
+    MPM_HIP(hipMemcpyAsync(c->d_sysfc, fc.data(), fc.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    k_sys_init<<<1, 64, 0, st>>>(c->d_sk, c->d_sysfc, c->d_sysfc + nsys, nsys);
+    MPM_HIP(hipGetLastError());
+    return MPM_OK;
+}
+
+template <typename T>
+static KArgs<T> make_args(Ctx* c, const Block* blocks);
+
+__global__ void k_tune_state(SysK* sk, int nsys) {
+    const int s = blockIdx.x;
+    if (s >= nsys) return;
+    for (int k = threadIdx.x; k < kMaxM + 2; k += blockDim.x) sk[s].vs[k] = 1.0;
+    if (threadIdx.x == 0) sk[s].active = 1;
+}
+
+// Timing-based choice of the unknowns per block: run the first stencil kernel and
+// the two Gram-Schmidt passes of Arnoldi step 8 (on whatever the vectors hold) for
+// each candidate split and keep the fastest.  The choice is cached per layout.
+template <typename T>
+static int autotune_t(Ctx* c, long long* best_out) {
+    hipStream_t st = c->stream;
+    const Kernels<T>& K = kernels<T>();
+    const int J = std::min(8, c->opt.restart - 1);
+    const int nsys = c->S * c->P;
+    long long maxpad = 0;
+    for (auto& ph : c->probs) maxpad = std::max<long long>(maxpad, ph.Npad);
+    hipEvent_t e0, e1;
+    MPM_HIP(hipEventCreate(&e0));
+    MPM_HIP(hipEventCreate(&e1));
+    double best_ms = 1e30;
+    long long best = model_tile(c);
+    for (long long tile = 1024; tile <= 65536; tile *= 2) {
+        const long long nbsys = (maxpad + tile - 1) / tile;
+        if (nbsys > 1024) continue;            // too many partial sums per system
+        if (tile > 1024 && nbsys < 8) break;   // too few blocks per system
+        build_tables(c, tile);
+        int rc = upload_tables(c);
+        if (rc != MPM_OK) return rc;
+        k_tune_state<<<nsys, 64, 0, st>>>(c->d_sk, nsys);
+        KArgs<T> a = make_args<T>(c, c->d_blocks);
+        const unsigned nb = (unsigned)c->blocks.size();
+        float ms = 0.0f;
+        for (int rep = 0; rep < 3; ++rep) {
+            MPM_HIP(hipEventRecord(e0, st));
+            for (int it = 0; it < 3; ++it) {
+                K.k1[0]<<<nb, kThreads, 0, st>>>(a);
+                K.k2[J]<<<nb, kThreads, 0, st>>>(a);
+                K.k3[J]<<<nb, kThreads, 0, st>>>(a);
+            }
+            MPM_HIP(hipEventRecord(e1, st));
+            MPM_HIP(hipEventSynchronize(e1));
+            MPM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = tile;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *best_out = best;
+    return MPM_OK;
+}
+
+static void drop_graphs(Ctx* c);
 
 int ensure_layout(Ctx* c) {
     if (!c->layout_dirty) return MPM_OK;
@@ -752,34 +906,6 @@ int ensure_layout(Ctx* c) {
         MPM_HIP(hipMemsetAsync(c->x, 0, need * 8, st));
         MPM_HIP(hipMemsetAsync(c->b, 0, need * 8, st));
     }
-    build_tables(c);
-    // device tables
-    const size_t nb = c->blocks.size(), nbs = c->blocks_sys.size();
-    if (nb > c->cap_blocks || nbs > c->cap_blocks) {
-        if (c->d_blocks) (void)hipFree(c->d_blocks);
-        if (c->d_blocks_sys) (void)hipFree(c->d_blocks_sys);
-        const size_t cap = std::max(nb, nbs) * 2;
-        if (hipMalloc(&c->d_blocks, cap * sizeof(Block)) != hipSuccess ||
-            hipMalloc(&c->d_blocks_sys, cap * sizeof(Block)) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("device allocation of block tables failed");
-            return MPM_ENOMEM;
-        }
-        c->cap_blocks = cap;
-    }
-    if ((size_t)c->nslots > c->cap_slots) {
-        if (c->d_part) (void)hipFree(c->d_part);
-        const size_t cap = (size_t)c->nslots * 2;
-        if (hipMalloc(&c->d_part, cap * kPartRows * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("device allocation of partial sums failed");
-            return MPM_ENOMEM;
-        }
-        c->cap_slots = cap;
-    }
-    // the partial rows are addressed with stride nslots
-    MPM_HIP(hipMemcpyAsync(c->d_blocks, c->blocks.data(), nb * sizeof(Block), hipMemcpyHostToDevice, st));
-    MPM_HIP(hipMemcpyAsync(c->d_blocks_sys, c->blocks_sys.data(), nbs * sizeof(Block), hipMemcpyHostToDevice, st));
     std::vector<ProbDev> pd(c->P);
     for (int p = 0; p < c->P; ++p) {
         const ProbHost& ph = c->probs[p];
@@ -797,33 +923,40 @@ int ensure_layout(Ctx* c) {
         pd[p].Npad = ph.Npad;
     }
     MPM_HIP(hipMemcpyAsync(c->d_probs, pd.data(), c->P * sizeof(ProbDev), hipMemcpyHostToDevice, st));
-    // per-system slot ranges and diagonal extremes
-    const int nsys = c->S * c->P;
-    int* tmp = nullptr;
-    MPM_HIP(hipMalloc(&tmp, 2 * nsys * sizeof(int)));
-    std::vector<int> fc(2 * nsys);
-    for (int s = 0; s < nsys; ++s) {
-        fc[s] = c->sys_first[s];
-        fc[nsys + s] = c->sys_count[s];
+    c->h_prm->restart = m;
+    c->h_prm->S = c->S;
+    MPM_HIP(hipMemcpyAsync(c->d_prm, c->h_prm, sizeof(Params), hipMemcpyHostToDevice, st));
+    // work split: fixed override, cached tuning result, or a fresh autotune
+    long long tile = c->opt.tile_override;
+    if (tile <= 0) {
+        std::string key = std::to_string(c->S) + ":" + std::to_string(ksize(c));
+        for (auto& ph : c->probs) key += ":" + std::to_string(ph.Npad);
+        auto it = c->tile_cache.find(key);
+        if (it != c->tile_cache.end()) {
+            tile = it->second;
+        } else if (c->opt.batched) {
+            int rc = ksize(c) == 8 ? autotune_t<double>(c, &tile) : autotune_t<float>(c, &tile);
+            if (rc != MPM_OK) return rc;
+            c->tile_cache[key] = tile;
+        } else {
+            tile = model_tile(c);
+        }
     }
-    MPM_HIP(hipMemcpyAsync(tmp, fc.data(), fc.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    k_sys_init<<<1, 64, 0, st>>>(c->d_sk, tmp, tmp + nsys, nsys);
-    MPM_HIP(hipMemsetAsync(c->d_cnt, 0, kMaxSys * sizeof(int), st));
+    build_tables(c, tile);
+    int rc = upload_tables(c);
+    if (rc != MPM_OK) return rc;
+    // diagonal extremes per system (for the scaled/unscaled residual bound)
+    const int nsys = c->S * c->P;
     KArgs<double> ka{};
     ka.blocks = c->d_blocks;
     ka.probs = c->d_probs;
     ka.sk = c->d_sk;
     ka.S = c->S;
-    k_diag_extremes<double><<<(unsigned)nb, kThreads, 0, st>>>(ka);
+    k_diag_extremes<double><<<(unsigned)c->blocks.size(), kThreads, 0, st>>>(ka);
     k_sys_kappa<<<1, 64, 0, st>>>(c->d_sk, nsys);
     MPM_HIP(hipGetLastError());
     MPM_HIP(hipStreamSynchronize(st));
-    (void)hipFree(tmp);
-    if (c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
-    c->graph_valid = false;
+    drop_graphs(c);
     c->layout_dirty = false;
     return MPM_OK;
 }
@@ -835,7 +968,6 @@ static KArgs<T> make_args(Ctx* c, const Block* blocks) {
     a.probs = c->d_probs;
     a.sk = c->d_sk;
     a.part = c->d_part;
-    a.cnt = c->d_cnt;
     a.prm = c->d_prm;
     a.V = (T*)c->V;
     a.W = (T*)c->W;
@@ -848,32 +980,153 @@ static KArgs<T> make_args(Ctx* c, const Block* blocks) {
     return a;
 }
 
+static bool timed(const Ctx* c, int kind, int j) {
+    return c->time_kind == kind && (kind > MPM_KERNEL_AXPY_NORM || c->time_j == j);
+}
+static void tev_begin(Ctx* c, hipStream_t st) { (void)hipEventRecord(c->tev[2 * c->tev_used], st); }
+static void tev_end(Ctx* c, hipStream_t st) {
+    (void)hipEventRecord(c->tev[2 * c->tev_used + 1], st);
+    ++c->tev_used;
+}
+
 // Enqueue one GMRES cycle (m Arnoldi steps, update, residual) for the given table.
+// 'part' selects a segment of the launch sequence around the timed kernel:
+// 0 = everything, 1 = launches before it, 2 = the timed launch only, 3 = after it.
+// 'events' records a start/stop event pair around the timed launch.
 template <typename T>
-static void enqueue_cycle(Ctx* c, const Block* tab, unsigned nb, hipStream_t st) {
+static void enqueue_cycle(Ctx* c, const Block* tab, unsigned nb, int sys0, int nsys, hipStream_t st, int part,
+                          bool events) {
     const Kernels<T>& K = kernels<T>();
     KArgs<T> a = make_args<T>(c, tab);
-    for (int j = 0; j < c->opt.restart; ++j) {
-        K.k1[j]<<<nb, kThreads, 0, st>>>(a);
-        K.k2[j]<<<nb, kThreads, 0, st>>>(a);
-        K.k3[j]<<<nb, kThreads, 0, st>>>(a);
+    int phase = 1;
+    auto emit = [&](auto launch, bool is_timed) {
+        if (is_timed) {
+            if (part == 0 || part == 2) {
+                if (events) tev_begin(c, st);
+                launch();
+                if (events) tev_end(c, st);
+            }
+            phase = 3;
+        } else if (part == 0 || part == phase) {
+            launch();
+        }
+    };
+    const int m = c->opt.restart;
+    for (int j = 0; j < m; ++j) {
+        const KFn<T> fns[3] = {K.k1[j], K.k2[j], K.k3[j]};
+        for (int q = 0; q < 3; ++q) {
+            KFn<T> fn = fns[q];
+            emit([&] { fn<<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_SPMV_DOT + q, j));
+        }
     }
-    k_update<T><<<nb, kThreads, 0, st>>>(a);
-    k_residual<T><<<nb, kThreads, 0, st>>>(a, 0);
+    KFinFn<T> fin = K.k4[m - 1];
+    emit([&] { fin<<<nsys, kThreads, 0, st>>>(a, sys0); }, false);
+    emit([&] { k_update<T><<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_UPDATE, 0));
+    emit([&] { k_residual<T><<<nb, kThreads, 0, st>>>(a, 0); }, timed(c, MPM_KERNEL_RESIDUAL, 0));
+    emit([&] { k_res_final<T><<<nsys, kThreads, 0, st>>>(a, sys0, 0); }, false);
+}
+
+// Add the event times and algorithmic bytes of the cycle that just finished.
+template <typename T>
+static void account_timing(Ctx* c) {
+    const int nsys = c->S * c->P;
+    for (int i = 0; i < c->tev_used; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]) == hipSuccess) c->time_ms += ms;
+        ++c->time_launches;
+    }
+    const double t = (double)sizeof(T);
+    const int j = c->time_j;
+    for (int s = 0; s < nsys; ++s) {
+        const SysK& k = c->h_sk[s];
+        if (k.cycles <= c->prev_cycles[s]) continue;       // did not run this cycle
+        c->prev_cycles[s] = k.cycles;
+        const double N = (double)c->probs[s / c->S].N;
+        double per = 0.0;
+        switch (c->time_kind) {
+            case MPM_KERNEL_SPMV_DOT: per = k.mcount > j ? t * (j + 5) + 16.0 / c->S : 0.0; break;
+            case MPM_KERNEL_AXPY_DOT: per = k.mcount > j ? t * (j + 3) : 0.0; break;
+            case MPM_KERNEL_AXPY_NORM:
+                per = k.mcount > j ? t * (j + 2) + (j + 1 < c->opt.restart ? t : 0.0) : 0.0;
+                break;
+            case MPM_KERNEL_UPDATE: per = t * k.mcount + 24.0; break;
+            case MPM_KERNEL_RESIDUAL: per = 56.0 + t + 16.0 / c->S; break;
+            default: break;
+        }
+        c->time_bytes += per * N;
+    }
 }
 
 template <typename T>
-static void enqueue_cycle_all(Ctx* c, hipStream_t st) {
+static void enqueue_cycle_all(Ctx* c, hipStream_t st, int part, bool events) {
+    const int nsys = c->S * c->P;
     if (c->opt.batched) {
-        enqueue_cycle<T>(c, c->d_blocks, (unsigned)c->blocks.size(), st);
+        enqueue_cycle<T>(c, c->d_blocks, (unsigned)c->blocks.size(), 0, nsys, st, part, events);
     } else {
-        const int nsys = c->S * c->P;
         for (int s = 0; s < nsys; ++s) {
             const int first = c->sys_tab_first[s];
             const int cnt = (s + 1 < nsys ? c->sys_tab_first[s + 1] : (int)c->blocks_sys.size()) - first;
-            enqueue_cycle<T>(c, c->d_blocks_sys + first, (unsigned)cnt, st);
+            enqueue_cycle<T>(c, c->d_blocks_sys + first, (unsigned)cnt, s, 1, st, part, events);
         }
     }
+}
+
+static void drop_graphs(Ctx* c) {
+    for (auto& g : c->graphs) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    c->ngraphs = 0;
+    c->graph_valid = false;
+}
+
+// Capture the cycle as one graph, or as three segments when a kernel is timed (the
+// timing events are then recorded on the stream between the segment launches).
+template <typename T>
+static int capture_cycle(Ctx* c, hipStream_t st) {
+    drop_graphs(c);
+    const bool split = c->time_kind != MPM_KERNEL_NONE;
+    const int nseg = split ? 3 : 1;
+    for (int i = 0; i < nseg; ++i) {
+        hipGraph_t g = nullptr;
+        MPM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        enqueue_cycle_all<T>(c, st, split ? i + 1 : 0, false);
+        MPM_HIP(hipStreamEndCapture(st, &g));
+        hipError_t e = hipGraphInstantiate(&c->graphs[i], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    }
+    c->ngraphs = nseg;
+    c->graph_valid = true;
+    return MPM_OK;
+}
+
+template <typename T>
+static int launch_cycle(Ctx* c, hipStream_t st) {
+    c->tev_used = 0;
+    // while a kernel is timed the cycle is launched directly, so that the events on
+    // the stream bracket that kernel alone (events inside a captured graph cannot be
+    // timed, and splitting the graph would add its launch latency to the interval)
+    const bool graph = c->opt.use_graph && c->time_kind == MPM_KERNEL_NONE;
+    if (!graph) {
+        enqueue_cycle_all<T>(c, st, 0, c->time_kind != MPM_KERNEL_NONE);
+        MPM_HIP(hipGetLastError());
+        return MPM_OK;
+    }
+    if (!c->graph_valid) {
+        int rc = capture_cycle<T>(c, st);
+        if (rc != MPM_OK) return rc;
+    }
+    if (c->ngraphs == 1) {
+        MPM_HIP(hipGraphLaunch(c->graphs[0], st));
+        return MPM_OK;
+    }
+    MPM_HIP(hipGraphLaunch(c->graphs[0], st));
+    tev_begin(c, st);
+    MPM_HIP(hipGraphLaunch(c->graphs[1], st));
+    tev_end(c, st);
+    MPM_HIP(hipGraphLaunch(c->graphs[2], st));
+    return MPM_OK;
 }
 
 template <typename T>
@@ -884,11 +1137,14 @@ static int run_step_t(Ctx* c, double tol) {
     const unsigned nb = (unsigned)c->blocks.size();
     k_gather<T><<<nb, kThreads, 0, st>>>(a);
     k_residual<T><<<nb, kThreads, 0, st>>>(a, 1);
+    k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, 1);
     MPM_HIP(hipGetLastError());
-    int status = MPM_OK;
+    int status = MPM_OK, rc = MPM_OK;
+    c->prev_cycles.assign(nsys, 0);
     for (int cyc = 0;; ++cyc) {
         MPM_HIP(hipMemcpyAsync(c->h_sk, c->d_sk, nsys * sizeof(SysK), hipMemcpyDeviceToHost, st));
         MPM_HIP(hipStreamSynchronize(st));
+        if (cyc > 0 && c->time_kind != MPM_KERNEL_NONE) account_timing<T>(c);
         bool any = false, bad = false;
         for (int s = 0; s < nsys; ++s) {
             if (c->h_sk[s].breakdown && !c->h_sk[s].converged) bad = true;
@@ -902,24 +1158,8 @@ static int run_step_t(Ctx* c, double tol) {
             status = MPM_NOT_CONVERGED;
             break;
         }
-        if (c->opt.use_graph) {
-            if (!c->graph_valid) {
-                hipGraph_t g = nullptr;
-                MPM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                enqueue_cycle_all<T>(c, st);
-                MPM_HIP(hipStreamEndCapture(st, &g));
-                if (c->graph) (void)hipGraphExecDestroy(c->graph);
-                c->graph = nullptr;
-                hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-                c->graph_valid = true;
-            }
-            MPM_HIP(hipGraphLaunch(c->graph, st));
-        } else {
-            enqueue_cycle_all<T>(c, st);
-            MPM_HIP(hipGetLastError());
-        }
+        rc = launch_cycle<T>(c, st);
+        if (rc != MPM_OK) return rc;
     }
     k_scatter<T><<<nb, kThreads, 0, st>>>(a);
     MPM_HIP(hipGetLastError());
@@ -982,6 +1222,23 @@ static int debug_apply_t(Ctx* c, int p, const double* x, double* y, int mode) {
     k_dbg_apply<T><<<(unsigned)((thr + kThreads - 1) / kThreads), kThreads, 0, st>>>(pd, c->S, c->x, xt, y, mode);
     MPM_HIP(hipGetLastError());
     MPM_HIP(hipStreamSynchronize(st));
+    return MPM_OK;
+}
+
+int select_timing(Ctx* c, int kind, int j) {
+    const size_t need = 2 * (size_t)c->S * c->P;
+    while (c->tev.size() < need) {
+        hipEvent_t e;
+        MPM_HIP(hipEventCreate(&e));
+        c->tev.push_back(e);
+    }
+    c->time_kind = kind;
+    c->time_j = j;
+    c->time_ms = 0.0;
+    c->time_bytes = 0.0;
+    c->time_launches = 0;
+    c->tev_used = 0;
+    drop_graphs(c);
     return MPM_OK;
 }
 

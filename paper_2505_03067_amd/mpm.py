@@ -85,6 +85,10 @@ def lib() -> ctypes.CDLL:
             "mpm_gmres_stats": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mpm_stats)],
             "mpm_destroy": [_vp],
             "mpm_debug_apply": [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32],
+            "mpm_time_kernel": [_vp, ctypes.c_int32, ctypes.c_int32],
+            "mpm_tile": [_vp, _i32p],
+            "mpm_kernel_timing": [_vp, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -215,6 +219,32 @@ def mpm_debug_apply(ctx, problem: int, x, y, mode: int) -> None:
                                  _dev_ptr(y, torch.float64, "y"), int(mode)))
 
 
+MPM_KERNEL_NONE = 0
+MPM_KERNEL_SPMV_DOT = 1
+MPM_KERNEL_AXPY_DOT = 2
+MPM_KERNEL_AXPY_NORM = 3
+MPM_KERNEL_UPDATE = 4
+MPM_KERNEL_RESIDUAL = 5
+
+
+def mpm_time_kernel(ctx, kind: int, j: int = 0) -> None:
+    _check(lib().mpm_time_kernel(ctx, int(kind), int(j)))
+
+
+def mpm_kernel_timing(ctx) -> dict:
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    by = ctypes.c_double()
+    _check(lib().mpm_kernel_timing(ctx, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+    return {"ms": ms.value, "launches": n.value, "bytes": by.value}
+
+
+def mpm_tile(ctx) -> int:
+    v = ctypes.c_int32()
+    _check(lib().mpm_tile(ctx, ctypes.byref(v)))
+    return v.value
+
+
 class Solver:
     """Owns one context; a convenience wrapper over the functions above."""
 
@@ -232,6 +262,15 @@ class Solver:
 
     def stats(self, problem=0, species=0):
         return mpm_gmres_stats(self.ctx, problem, species)
+
+    def time_kernel(self, kind, j=0):
+        return mpm_time_kernel(self.ctx, kind, j)
+
+    def tile(self):
+        return mpm_tile(self.ctx)
+
+    def kernel_timing(self):
+        return mpm_kernel_timing(self.ctx)
 
     def apply(self, problem, x, y, mode):
         return mpm_debug_apply(self.ctx, problem, x, y, mode)

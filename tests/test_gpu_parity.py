@@ -151,11 +151,12 @@ def test_modes_agree(opts):
 def test_batched_graph_and_unbatched_are_bit_identical():
     require_gpu()
     p = random_problem(32, (29, 31, 27), S=3, fill=0.6)
-    ref, _ = gpu_run(p, 2, 1e-10)
+    tile = dict(tile_override=2048)         # the reduction order follows the work split
+    ref, _ = gpu_run(p, 2, 1e-10, **tile)
     for opts in (dict(batched=0), dict(use_graph=0), dict(batched=0, use_graph=0)):
-        got, _ = gpu_run(p, 2, 1e-10, **opts)
+        got, _ = gpu_run(p, 2, 1e-10, **tile, **opts)
         assert np.array_equal(got, ref), opts
-    again, _ = gpu_run(p, 2, 1e-10)                   # run-to-run determinism
+    again, _ = gpu_run(p, 2, 1e-10, **tile)            # run-to-run determinism
     assert np.array_equal(again, ref)
 
 
