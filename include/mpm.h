@@ -167,6 +167,72 @@ int32_t mpm_kernel_timing(mpm_ctx ctx, double* ms, int64_t* launches, double* by
  * host int.  MPM_ESTATE before the first step or mpm_debug_apply. */
 int32_t mpm_tile(mpm_ctx ctx, int32_t* out);
 
+/* ---- learned warm start: a 3-D U-Net on the box grid ----------------------------
+ * Not part of the paper; its shape is this project's specification: 'levels' levels of
+ * widths[l] channels (16, 32, 48 or 64; widths[0] = 16), two 3x3x3 convolutions + ReLU
+ * per level, 2x2x2 average pooling between encoder levels, nearest x2 upsampling and
+ * [upsampled, skip] concatenation in the decoder, and a 1x1x1 head.  Convolution
+ * weights are W[tap][c_in][c_out] (tap = (dz+1)*9 + (dy+1)*3 + (dx+1)) followed by
+ * the bias, layer by layer in forward order, FP32 master copies; compute is BF16 on
+ * the matrix cores with FP32 accumulation.  Tensors are NDHWC ([n][z][y][x][c]),
+ * device memory, all work on 'stream'. */
+typedef struct mpm_net_s* mpm_net;
+
+/* Create a network with He-normal weights drawn from 'seed' (host-side generator). */
+int32_t mpm_net_create(mpm_net* net, int32_t in_ch, int32_t out_ch, int32_t levels, const int32_t* widths,
+                       uint64_t seed, void* stream);
+/* Device pointers to the FP32 parameters and gradients (owned by the net) and their
+ * count.  After writing parameters directly, call mpm_net_sync_weights. */
+int32_t mpm_net_params(mpm_net net, float** params, float** grads, int64_t* count);
+int32_t mpm_net_sync_weights(mpm_net net);
+/* Copy all FP32 parameters (what = 0) or gradients (what = 1) between the net and a
+ * caller device buffer of the parameter count.  Writing parameters refreshes the BF16
+ * copies. */
+int32_t mpm_net_read(mpm_net net, int32_t what, float* dst);
+int32_t mpm_net_write(mpm_net net, int32_t what, const float* src);
+/* in: device BF16 [n][d][h][w][in_ch]; out: device FP32 [n][d][h][w][out_ch]; d, h, w
+ * multiples of 2^(levels-1).  Keeps the activations for mpm_net_backward. */
+int32_t mpm_net_forward(mpm_net net, const uint16_t* in, int32_t n, int32_t d, int32_t h, int32_t w, float* out);
+/* Accumulate parameter gradients for dL/d(out) = grad_out (device FP32, shape of out). */
+int32_t mpm_net_backward(mpm_net net, const float* grad_out);
+int32_t mpm_net_zero_grad(mpm_net net);
+/* Mean squared error of 'count' FP32 values: *loss (host) and grad_out = dL/d(out)
+ * (device).  Synchronises the stream. */
+int32_t mpm_net_mse(mpm_net net, const float* out, const float* target, int64_t count, float* grad_out,
+                    double* loss);
+/* One Adam step (t counts from 1) on the master parameters; refreshes the BF16 copies. */
+int32_t mpm_net_adam_step(mpm_net net, float lr, float b1, float b2, float eps, int32_t t);
+int32_t mpm_net_destroy(mpm_net net);
+
+/* Test hook: one 3x3x3 layer of the net on caller tensors (device, NDHWC, one level's
+ * shape n x d x h x w).  mode 0: out = conv(x) + bias (no ReLU), out FP32 [..][cout];
+ * mode 1: out = input gradient of g * (gate > 0), FP32 [..][cin];
+ * mode 2: out = weight gradient sum_p x[p + off] g[p] * (gate > 0), FP32 [27][cin][cout].
+ * x: BF16 [..][cin rounded up to 16] (zero in the padding channels); g, gate: BF16
+ * [..][cout] (gate may be NULL).  Leaves the net's accumulated gradients unchanged. */
+int32_t mpm_net_debug_layer(mpm_net net, int32_t layer, int32_t mode, int32_t n, int32_t d, int32_t h,
+                            int32_t w, const uint16_t* x, const uint16_t* g, const uint16_t* gate, float* out);
+
+/* Use 'net' (in_ch = 4 S + 1, out_ch = S) as the warm start of a context created with
+ * warm_start = MPM_WS_NET; net = NULL detaches.  Network input on the box grid (box
+ * sizes rounded up to multiples of 8, zero beyond the box): channels c^n (S), k (S),
+ * D (S), s (S), mask, each times in_scale[ch] (host [4 S + 1]); the prediction of
+ * species s is output * out_scale[s] (host [S]) added to c^n.  Each step keeps the
+ * prediction of a system only if its true residual is below that of c^n
+ * (mpm_stats.warm_start_used / fallback).  The net must outlive its use. */
+int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scale, const float* out_scale);
+
+/* Training pair for the warm start of 'problem': the network input built from the
+ * lattice fields c_old (device FP64 [S][z][y][x]) exactly as mpm_implicit_step builds
+ * it (in_bf16: device [gz][gy][gx][4 S + 1]) and the target (c_new - c_old) / out_scale
+ * on domain voxels, 0 elsewhere (target: device FP32 [gz][gy][gx][S]).  grid: see
+ * mpm_ws_grid.  Synchronises the stream. */
+int32_t mpm_ws_pair(mpm_ctx ctx, int32_t problem, const double* c_old, const double* c_new,
+                    const float* in_scale, const float* out_scale, uint16_t* in_bf16, float* target);
+
+/* Grid sizes (gx, gy, gz) of the warm-start network input of 'problem' (host int[3]). */
+int32_t mpm_ws_grid(mpm_ctx ctx, int32_t problem, int32_t* grid);
+
 /* Test hook: apply the discrete operator of 'problem' to a lattice field.
  * x_lattice, y_lattice: device FP64 [S][z][y][x]; only domain voxels of the box are
  * read / written.  mode 0: y = A x (FP64, unscaled); mode 1: y = S A S x with

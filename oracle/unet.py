@@ -28,6 +28,21 @@ import numpy as np
 TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 
 
+def bf16(x):
+    """Round to the nearest BFloat16 value (ties to even), returned as float64.
+
+    BFloat16 keeps the top 16 bits of an IEEE binary32 number; rounding adds
+    0x7fff plus the lowest kept bit before truncation.
+    """
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _keep(x, store):
+    return bf16(x) if store else x
+
+
 def layer_shapes(in_ch, out_ch, widths):
     """(c_in, c_out, taps) of every convolution, in forward order."""
     L = len(widths)
@@ -111,9 +126,17 @@ def up2_backward(dy):
     return dy.reshape(n, D // 2, 2, H // 2, 2, Wd // 2, 2, c).sum(axis=(2, 4, 6))
 
 
-def forward(theta, x, in_ch, out_ch, widths, keep=False):
-    """Network output; with keep=True also the activations needed by backward()."""
+def forward(theta, x, in_ch, out_ch, widths, keep=False, store_bf16=False):
+    """Network output; with keep=True also the activations needed by backward().
+
+    store_bf16=True rounds the 3x3x3 weights and every stored activation (convolution
+    outputs, pooled and upsampled tensors) to BFloat16, the storage format of the
+    GPU kernels, while all arithmetic stays FP64.
+    """
     layers = unpack(theta, in_ch, out_ch, widths)
+    if store_bf16:
+        layers = [(bf16(W), b) if W.shape[0] == 27 else (W, b) for W, b in layers]
+    st = store_bf16
     L = len(widths)
     acts = []                      # (input, output) of each conv, in order
     li = 0
@@ -121,10 +144,10 @@ def forward(theta, x, in_ch, out_ch, widths, keep=False):
     skips = []
     for lvl in range(L):
         if lvl > 0:
-            h = pool2(h)
+            h = _keep(pool2(h), st)
         for _ in range(2):
             W, b = layers[li]
-            y = np.maximum(conv3(h, W, b), 0.0)
+            y = _keep(np.maximum(conv3(h, W, b), 0.0), st)
             acts.append((h, y))
             h = y
             li += 1
@@ -133,7 +156,7 @@ def forward(theta, x, in_ch, out_ch, widths, keep=False):
         h = np.concatenate([up2(h), skips[lvl]], axis=-1)
         for _ in range(2):
             W, b = layers[li]
-            y = np.maximum(conv3(h, W, b), 0.0)
+            y = _keep(np.maximum(conv3(h, W, b), 0.0), st)
             acts.append((h, y))
             h = y
             li += 1
@@ -143,9 +166,17 @@ def forward(theta, x, in_ch, out_ch, widths, keep=False):
     return (out, acts) if keep else out
 
 
-def backward(theta, acts, dout, in_ch, out_ch, widths):
-    """Gradient of the loss with respect to theta (and the input), given dL/dout."""
+def backward(theta, acts, dout, in_ch, out_ch, widths, store_bf16=False):
+    """Gradient of the loss with respect to theta (and the input), given dL/dout.
+
+    store_bf16=True uses BFloat16-rounded 3x3x3 weights and rounds every stored
+    activation gradient (head input gradient, convolution input gradients,
+    upsampling and pooling gradients) to BFloat16, as the GPU kernels store them.
+    """
     layers = unpack(theta, in_ch, out_ch, widths)
+    if store_bf16:
+        layers = [(bf16(W), b) if W.shape[0] == 27 else (W, b) for W, b in layers]
+    st = store_bf16
     grads = [None] * len(layers)
     L = len(widths)
     li = len(layers) - 1
@@ -153,7 +184,7 @@ def backward(theta, acts, dout, in_ch, out_ch, widths):
     W, _ = layers[li]
     grads[li] = (np.tensordot(hin, dout, axes=([0, 1, 2, 3], [0, 1, 2, 3]))[None],
                  dout.sum(axis=(0, 1, 2, 3)))
-    dh = dout @ W[0].T
+    dh = _keep(dout @ W[0].T, st)
     li -= 1
     dskips = [None] * L
     for lvl in range(0, L - 1):
@@ -162,19 +193,21 @@ def backward(theta, acts, dout, in_ch, out_ch, widths):
             W, _ = layers[li]
             dpre = dh * (y > 0)
             dh, dW, db = conv3_backward(hin, W, dpre)
+            dh = _keep(dh, st)
             grads[li] = (dW, db)
             li -= 1
         cu = widths[lvl + 1]
         dskips[lvl] = dh[..., cu:]
-        dh = up2_backward(dh[..., :cu])
+        dh = _keep(up2_backward(dh[..., :cu]), st)
     for lvl in range(L - 1, -1, -1):
         if lvl < L - 1:
-            dh = dh + dskips[lvl]
+            dh = _keep(dh + dskips[lvl], st)
         for _ in range(2):
             hin, y = acts[li]
             W, _ = layers[li]
             dpre = dh * (y > 0)
             dh, dW, db = conv3_backward(hin, W, dpre)
+            dh = _keep(dh, st)
             grads[li] = (dW, db)
             li -= 1
         if lvl > 0:

@@ -38,6 +38,8 @@ static void destroy_ctx(Ctx* c) {
     if (c->h_fields) (void)hipHostFree(c->h_fields);
     if (c->h_prm) (void)hipHostFree(c->h_prm);
     if (c->h_sk) (void)hipHostFree(c->h_sk);
+    (void)hipFree(c->d_scales);
+    (void)hipFree(c->prev);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     for (auto e : c->tev) (void)hipEventDestroy(e);
@@ -117,6 +119,7 @@ extern "C" int32_t mpm_create(mpm_ctx* out, int32_t nspecies, int32_t nproblems,
     if (e == hipSuccess) e = hipMalloc(&c->d_sk, nsys * sizeof(SysK));
     if (e == hipSuccess) e = hipMalloc(&c->d_prm, sizeof(Params));
     if (e == hipSuccess) e = hipMalloc(&c->d_sysfc, 2 * kMaxSys * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&c->d_scales, 20 * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&c->d_fields, nproblems * sizeof(double*));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_fields, nproblems * sizeof(double*), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_prm, sizeof(Params), hipHostMallocDefault);
@@ -270,5 +273,70 @@ extern "C" int32_t mpm_tile(mpm_ctx ctx, int32_t* out) {
         return MPM_ESTATE;
     }
     *out = c->block_unknowns;
+    return MPM_OK;
+}
+
+static int set_scales(Ctx* c, const float* in_scale, const float* out_scale) {
+    const int cin = 4 * c->S + 1;
+    for (int i = 0; i < 20; ++i) c->h_scales[i] = 0.f;
+    for (int i = 0; i < cin; ++i) c->h_scales[i] = in_scale[i];
+    for (int s = 0; s < c->S; ++s) c->h_scales[16 + s] = out_scale[s];
+    MPM_HIP(hipMemcpy(c->d_scales, c->h_scales, 20 * sizeof(float), hipMemcpyHostToDevice));
+    c->have_scales = true;
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scale, const float* out_scale) {
+    Ctx* c = (Ctx*)ctx;
+    Net* n = (Net*)net;
+    if (!c || !in_scale || !out_scale) {
+        set_error("mpm_attach_net: null pointer");
+        return MPM_EINVAL;
+    }
+    if (n && (n->in_ch != 4 * c->S + 1 || n->out_ch != c->S)) {
+        set_error("mpm_attach_net: the network must read 4 S + 1 channels and write S");
+        return MPM_EINVAL;
+    }
+    if (c->opt.warm_start != MPM_WS_NET) {
+        set_error("mpm_attach_net: the context was not created with warm_start = MPM_WS_NET");
+        return MPM_ESTATE;
+    }
+    int rc = set_scales(c, in_scale, out_scale);
+    if (rc != MPM_OK) return rc;
+    c->net = n;
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_ws_pair(mpm_ctx ctx, int32_t problem, const double* c_old, const double* c_new,
+                               const float* in_scale, const float* out_scale, uint16_t* in_bf16, float* target) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !c_old || !c_new || !in_scale || !out_scale || !in_bf16 || !target || problem < 0 || problem >= c->P) {
+        set_error("mpm_ws_pair: bad arguments");
+        return MPM_EINVAL;
+    }
+    if (c->opt.warm_start != MPM_WS_NET || !c->probs[problem].ready) {
+        set_error("mpm_ws_pair: needs a context with warm_start = MPM_WS_NET and a set-up problem");
+        return MPM_ESTATE;
+    }
+    int rc = set_scales(c, in_scale, out_scale);
+    if (rc != MPM_OK) return rc;
+    rc = enter(c);
+    if (rc != MPM_OK) return rc;
+    rc = ws_pair(c, problem, c_old, c_new, in_bf16, target);
+    if (rc == MPM_OK) rc = leave(c);
+    return rc;
+}
+
+extern "C" int32_t mpm_ws_grid(mpm_ctx ctx, int32_t problem, int32_t* grid) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !grid || problem < 0 || problem >= c->P) {
+        set_error("mpm_ws_grid: bad arguments");
+        return MPM_EINVAL;
+    }
+    if (!c->probs[problem].ready || c->probs[problem].gd[0] == 0) {
+        set_error("mpm_ws_grid: no warm-start grid (set up the problem in a MPM_WS_NET context)");
+        return MPM_ESTATE;
+    }
+    for (int d = 0; d < 3; ++d) grid[d] = c->probs[problem].gd[d];
     return MPM_OK;
 }

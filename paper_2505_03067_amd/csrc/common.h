@@ -37,6 +37,13 @@ struct ProbDev {
     long long nvox;        // lattice voxel count (species stride of lattice fields)
     int N;                 // domain voxels in the box
     int Npad;              // padded length per species (multiple of kAlign, >= N + 1)
+    // geometry for the warm start: lattice (nx, ny), box origin and the box grid the
+    // network runs on (box sizes rounded up to multiples of 8)
+    int nx, ny;
+    int lo[3];
+    int gd[3];
+    const float* wsout;    // network output on the grid [G][S] (or null)
+    const double* prev;    // c^{n-1} on the global unknowns (or null)
 };
 
 // One block of work: a contiguous range of one system's unknowns (global indices).

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "common.h"
+#include "unet.h"
 
 namespace mpm {
 
@@ -30,6 +31,12 @@ struct ProbHost {
     float* c32 = nullptr;
     double* c64 = nullptr;
     size_t cap_pad = 0;        // Npad the buffers were sized for
+    // warm start: static network input channels on the box grid (k, D, s, mask)
+    int gd[3] = {0, 0, 0};
+    float* stat = nullptr;
+    uint16_t* wsin = nullptr;  // BF16 network input [G][in_ch]
+    float* wsout = nullptr;    // network output [G][S]
+    size_t cap_grid = 0;
 };
 
 struct Ctx {
@@ -48,6 +55,7 @@ struct Ctx {
     std::vector<Block> blocks;         // batched launch table (XCD-swizzled)
     std::vector<int> sys_first, sys_count;   // per-system slice of blocks_sys
     std::vector<Block> blocks_sys;     // per-system tables, concatenated
+    std::vector<ProbDev> h_probs;      // host copy of the device descriptors
     std::vector<int> sys_tab_first;    // start of each system's table in blocks_sys
     int nslots = 0;
     int block_unknowns = 0;            // unknowns per block (autotuned or fixed)
@@ -83,6 +91,16 @@ struct Ctx {
     std::vector<mpm_stats> stats;
     bool stepped = false;
 
+    // warm start
+    Net* net = nullptr;
+    float* d_scales = nullptr;         // [16] input channel scales, [4] output scales
+    float h_scales[20] = {0};
+    bool have_scales = false;
+    double* prev = nullptr;            // c^n of the previous step on the global unknowns
+    size_t cap_prev = 0;
+    size_t prev_n = 0;                 // elements in each half of prev
+    bool have_prev = false;
+
     // kernel timing hook
     int time_kind = 0, time_j = 0;
     std::vector<hipEvent_t> tev;       // start/stop pairs, one pair per timed launch
@@ -104,5 +122,6 @@ int run_step(Ctx* c, double* const* fields, double tol);
 int debug_apply(Ctx* c, int p, const double* x, double* y, int mode);
 int ensure_layout(Ctx* c);
 int select_timing(Ctx* c, int kind, int j);
+int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* in_bf16, float* target);
 
 }  // namespace mpm

@@ -218,13 +218,26 @@ __global__ __launch_bounds__(kThreads) void k_gather(KArgs<T> a) {
     block_partials<1>(acc, a.part + (long long)kRowB * a.nslots, a.nslots, blk.slot);
 }
 
+// Which systems a residual evaluation covers: the first one of a step covers all;
+// the one after a cycle the not yet converged; the warm-start one the systems not
+// converged at c^n; the revert one the systems whose warm start was rejected.
+enum ResMode { kResCycle = 0, kResFirst = 1, kResWarm = 2, kResRevert = 3 };
+
+__device__ inline bool res_skip(const SysK* sk, int mode) {
+    switch (mode) {
+        case kResFirst: return false;
+        case kResRevert: return !sk->fallback;
+        default: return sk->converged != 0;
+    }
+}
+
 // r = b - A x (FP64); V_0 = S r; partials of ||r||^2 and ||S r||^2.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int first) {
+__global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
     SysK* sk = a.sk + blk.sys;
-    if (!first && sk->converged) return;
+    if (res_skip(sk, mode)) return;
     const ProbDev pd = a.probs[blk.sys / a.S];
     const Where wh = where_of(a, blk, pd);
     T* V0 = a.V;
@@ -243,12 +256,15 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int first) {
     block_partials<2>(acc, a.part + (long long)kRowR * a.nslots, a.nslots, blk.slot);
 }
 
-// One block per system: norms, convergence test, start of the next cycle.
+// One block per system: norms, convergence test, start of the next cycle; in warm
+// mode the acceptance test of the warm start (kept only if its true residual is
+// below that of c^n, else the system falls back to c^n).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_res_final(KArgs<T> a, int sys0, int first) {
+__global__ __launch_bounds__(kThreads) void k_res_final(KArgs<T> a, int sys0, int mode) {
     const int sys = sys0 + blockIdx.x;
     SysK* sk = a.sk + sys;
-    if (!first && sk->converged) return;
+    if (res_skip(sk, mode)) return;
+    const bool first = mode == kResFirst;
     __shared__ double tot[3];
     reduce_partials<2>(a.part + (long long)kRowR * a.nslots, a.nslots, sk->slot0, sk->nblocks, tot);
     if (first) reduce_partials<1>(a.part + (long long)kRowB * a.nslots, a.nslots, sk->slot0, sk->nblocks, tot + 2);
@@ -268,8 +284,17 @@ __global__ __launch_bounds__(kThreads) void k_res_final(KArgs<T> a, int sys0, in
     const double rn = sqrt(tot[0]), srn = sqrt(tot[1]);
     const double bn = sk->bnorm;
     const double rel = bn > 0.0 ? rn / bn : (rn > 0.0 ? INFINITY : 0.0);
+    if (mode == kResWarm) {
+        sk->rel_warm = rel;
+        if (!(rel < sk->rel_init)) {           // rejected (also catches NaN)
+            sk->fallback = 1;
+            sk->active = 0;
+            return;
+        }
+        sk->ws_used = 1;
+    }
     if (first) sk->rel_init = rel;
-    else sk->refinements += 1;
+    else if (mode == kResCycle) sk->refinements += 1;
     sk->rel_final = rel;
     sk->rnorm = rn;
     sk->srnorm = srn;
@@ -645,6 +670,109 @@ __global__ __launch_bounds__(kThreads) void k_dbg_apply(ProbDev pd, int S, const
     }
 }
 
+// ------------------------------------------------------------------ warm start
+__device__ inline uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Network input on the box grid of problem p: channels [c (S), k (S), D (S), s (S), mask],
+// each multiplied by its scale, BF16; zero on grid voxels beyond the box.  c is read
+// from the lattice field; k, D, s and the mask come from the static channels.
+__global__ void k_ws_input(ProbDev pd, int S, int bx, int by, int bz, const double* field, const float* stat,
+                           const float* scales, uint16_t* in) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long G = (long long)pd.gd[0] * pd.gd[1] * pd.gd[2];
+    if (i >= G) return;
+    const int gx = pd.gd[0], gy = pd.gd[1];
+    const int x = (int)(i % gx);
+    const int y = (int)((i / gx) % gy);
+    const int z = (int)(i / ((long long)gx * gy));
+    const int C = 4 * S + 1;
+    const bool inbox = x < bx && y < by && z < bz;
+    const float* st = stat + i * (3 * S + 1);
+    const long long v = ((long long)(pd.lo[2] + z) * pd.ny + (pd.lo[1] + y)) * pd.nx + (pd.lo[0] + x);
+    for (int s = 0; s < S; ++s) {
+        const float cv = inbox ? (float)field[s * pd.nvox + v] : 0.f;
+        in[i * C + s] = to_bf16(cv * scales[s]);
+    }
+    for (int c = 0; c < 3 * S + 1; ++c) in[i * C + S + c] = to_bf16(st[c] * scales[S + c]);
+}
+
+// Grid index of compact voxel l of a problem.
+__device__ inline long long grid_index(const ProbDev& pd, int l) {
+    const int v = pd.vox[l];
+    const int plane = pd.nx * pd.ny;
+    const int z = v / plane;
+    const int rem = v - z * plane;
+    const int y = rem / pd.nx;
+    const int x = rem - y * pd.nx;
+    return ((long long)(z - pd.lo[2]) * pd.gd[1] + (y - pd.lo[1])) * pd.gd[0] + (x - pd.lo[0]);
+}
+
+// x0 = c^n + out * out_scale (network) or 2 c^n - c^{n-1} (extrapolation), for the
+// systems not already converged at c^n.  x holds c^n on entry.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, const float* scales) {
+    const Block blk = a.blocks[blockIdx.x];
+    if (blk.sys < 0) return;
+    const SysK* sk = a.sk + blk.sys;
+    if (sk->converged) return;
+    const ProbDev pd = a.probs[blk.sys / a.S];
+    const Where wh = where_of(a, blk, pd);
+    const float os = scales[16 + wh.s];
+    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
+        const int l = (int)(u - wh.base);
+        if (l >= pd.N) continue;
+        if (mode == MPM_WS_NET) {
+            a.x[u] += (double)(pd.wsout[grid_index(pd, l) * a.S + wh.s] * os);
+        } else {
+            a.x[u] = 2.0 * a.x[u] - pd.prev[u];
+        }
+    }
+}
+
+// Back to x = c^n for the systems whose warm start was rejected.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ws_revert(KArgs<T> a) {
+    const Block blk = a.blocks[blockIdx.x];
+    if (blk.sys < 0) return;
+    const SysK* sk = a.sk + blk.sys;
+    if (!sk->fallback) return;
+    const ProbDev pd = a.probs[blk.sys / a.S];
+    const Where wh = where_of(a, blk, pd);
+    const double* f = a.fields[wh.p] + (long long)wh.s * pd.nvox;
+    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
+        const int l = (int)(u - wh.base);
+        if (l < pd.N) a.x[u] = f[pd.vox[l]];
+    }
+}
+
+__global__ void k_copy64(const double* src, double* dst, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// Training target on the grid: (c_new - c_old) / out_scale on domain voxels, else 0.
+__global__ void k_ws_target(ProbDev pd, int S, int bx, int by, int bz, const double* c_old, const double* c_new,
+                            const float* stat, const float* scales, float* tgt) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long G = (long long)pd.gd[0] * pd.gd[1] * pd.gd[2];
+    if (i >= G) return;
+    const int gx = pd.gd[0], gy = pd.gd[1];
+    const int x = (int)(i % gx);
+    const int y = (int)((i / gx) % gy);
+    const int z = (int)(i / ((long long)gx * gy));
+    const bool dom = x < bx && y < by && z < bz && stat[i * (3 * S + 1) + 3 * S] > 0.f;
+    const long long v = ((long long)(pd.lo[2] + z) * pd.ny + (pd.lo[1] + y)) * pd.nx + (pd.lo[0] + x);
+    for (int s = 0; s < S; ++s) {
+        float t = 0.f;
+        if (dom) t = (float)((c_new[s * pd.nvox + v] - c_old[s * pd.nvox + v]) / (double)scales[16 + s]);
+        tgt[i * S + s] = t;
+    }
+}
+
 // ------------------------------------------------------------------ dispatch tables
 template <typename T>
 using KFn = void (*)(KArgs<T>);
@@ -921,7 +1049,34 @@ int ensure_layout(Ctx* c) {
         pd[p].nvox = ph.nvox;
         pd[p].N = ph.N;
         pd[p].Npad = ph.Npad;
+        pd[p].nx = ph.dims[0];
+        pd[p].ny = ph.dims[1];
+        for (int d = 0; d < 3; ++d) {
+            pd[p].lo[d] = ph.lo[d];
+            pd[p].gd[d] = ph.gd[d];
+        }
+        pd[p].wsout = ph.wsout;
+        pd[p].prev = nullptr;
     }
+    // previous-step values for the extrapolated start live on the global unknowns
+    c->have_prev = false;
+    if (c->opt.warm_start == MPM_WS_EXTRAP) {
+        // [0, need): c^{n-1}; [need, 2 need): this step's c^n
+        if (2 * need > c->cap_prev) {
+            (void)hipFree(c->prev);
+            c->prev = nullptr;
+            c->cap_prev = 0;
+            if (hipMalloc(&c->prev, 2 * need * 8) != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("device allocation of the previous-step buffer failed");
+                return MPM_ENOMEM;
+            }
+            c->cap_prev = 2 * need;
+        }
+        c->prev_n = need;
+        for (int p = 0; p < c->P; ++p) pd[p].prev = c->prev;
+    }
+    c->h_probs = pd;
     MPM_HIP(hipMemcpyAsync(c->d_probs, pd.data(), c->P * sizeof(ProbDev), hipMemcpyHostToDevice, st));
     c->h_prm->restart = m;
     c->h_prm->S = c->S;
@@ -1022,8 +1177,8 @@ static void enqueue_cycle(Ctx* c, const Block* tab, unsigned nb, int sys0, int n
     KFinFn<T> fin = K.k4[m - 1];
     emit([&] { fin<<<nsys, kThreads, 0, st>>>(a, sys0); }, false);
     emit([&] { k_update<T><<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_UPDATE, 0));
-    emit([&] { k_residual<T><<<nb, kThreads, 0, st>>>(a, 0); }, timed(c, MPM_KERNEL_RESIDUAL, 0));
-    emit([&] { k_res_final<T><<<nsys, kThreads, 0, st>>>(a, sys0, 0); }, false);
+    emit([&] { k_residual<T><<<nb, kThreads, 0, st>>>(a, kResCycle); }, timed(c, MPM_KERNEL_RESIDUAL, 0));
+    emit([&] { k_res_final<T><<<nsys, kThreads, 0, st>>>(a, sys0, kResCycle); }, false);
 }
 
 // Add the event times and algorithmic bytes of the cycle that just finished.
@@ -1129,6 +1284,48 @@ static int launch_cycle(Ctx* c, hipStream_t st) {
     return MPM_OK;
 }
 
+// Warm start of every system not converged at c^n: network prediction or linear
+// extrapolation, accepted per system only if its true FP64 residual is smaller than
+// that of c^n (else the system restarts from c^n).  The outcome is recorded in the
+// statistics (warm_start_used, fallback, rel_res_warm).
+template <typename T>
+static int warm_start(Ctx* c, hipStream_t st) {
+    const int nsys = c->S * c->P;
+    KArgs<T> a = make_args<T>(c, c->d_blocks);
+    const unsigned nb = (unsigned)c->blocks.size();
+    const int mode = c->opt.warm_start;
+    if (mode == MPM_WS_NET) {
+        if (!c->have_scales) {
+            set_error("warm start: no network scales (mpm_attach_net)");
+            return MPM_ESTATE;
+        }
+        hipStream_t saved = c->net->stream;
+        c->net->stream = st;
+        for (int p = 0; p < c->P; ++p) {
+            const ProbHost& ph = c->probs[p];
+            const ProbDev& pd = c->h_probs[p];
+            const long long G = (long long)ph.gd[0] * ph.gd[1] * ph.gd[2];
+            k_ws_input<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, ph.hi[0] - ph.lo[0], ph.hi[1] - ph.lo[1],
+                                                                  ph.hi[2] - ph.lo[2], c->h_fields[p], ph.stat,
+                                                                  c->d_scales, ph.wsin);
+            int rc = net_forward(c->net, ph.wsin, 1, ph.gd[2], ph.gd[1], ph.gd[0], ph.wsout);
+            if (rc != MPM_OK) {
+                c->net->stream = saved;
+                return rc;
+            }
+        }
+        c->net->stream = saved;
+    }
+    k_ws_apply<T><<<nb, kThreads, 0, st>>>(a, mode, c->d_scales);
+    k_residual<T><<<nb, kThreads, 0, st>>>(a, kResWarm);
+    k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResWarm);
+    k_ws_revert<T><<<nb, kThreads, 0, st>>>(a);
+    k_residual<T><<<nb, kThreads, 0, st>>>(a, kResRevert);
+    k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResRevert);
+    MPM_HIP(hipGetLastError());
+    return MPM_OK;
+}
+
 template <typename T>
 static int run_step_t(Ctx* c, double tol) {
     hipStream_t st = c->stream;
@@ -1136,8 +1333,16 @@ static int run_step_t(Ctx* c, double tol) {
     KArgs<T> a = make_args<T>(c, c->d_blocks);
     const unsigned nb = (unsigned)c->blocks.size();
     k_gather<T><<<nb, kThreads, 0, st>>>(a);
-    k_residual<T><<<nb, kThreads, 0, st>>>(a, 1);
-    k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, 1);
+    const bool extrap = c->opt.warm_start == MPM_WS_EXTRAP;
+    const long long nall = (long long)c->prev_n;
+    if (extrap) k_copy64<<<(unsigned)((nall + 255) / 256), 256, 0, st>>>(c->x, c->prev + nall, nall);
+    k_residual<T><<<nb, kThreads, 0, st>>>(a, kResFirst);
+    k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResFirst);
+    if ((c->opt.warm_start == MPM_WS_NET && c->net) || (c->opt.warm_start == MPM_WS_EXTRAP && c->have_prev)) {
+        int wrc = warm_start<T>(c, st);
+        if (wrc != MPM_OK) return wrc;
+    }
+
     MPM_HIP(hipGetLastError());
     int status = MPM_OK, rc = MPM_OK;
     c->prev_cycles.assign(nsys, 0);
@@ -1162,6 +1367,11 @@ static int run_step_t(Ctx* c, double tol) {
         if (rc != MPM_OK) return rc;
     }
     k_scatter<T><<<nb, kThreads, 0, st>>>(a);
+    if (extrap) {
+        // this step's c^n becomes the previous step of the next extrapolation
+        k_copy64<<<(unsigned)((nall + 255) / 256), 256, 0, st>>>(c->prev + nall, c->prev, nall);
+        c->have_prev = true;
+    }
     MPM_HIP(hipGetLastError());
     MPM_HIP(hipMemcpyAsync(c->h_sk, c->d_sk, nsys * sizeof(SysK), hipMemcpyDeviceToHost, st));
     MPM_HIP(hipStreamSynchronize(st));
@@ -1255,6 +1465,26 @@ int debug_apply(Ctx* c, int p, const double* x, double* y, int mode) {
     }
     return c->opt.precision == MPM_FP64 ? debug_apply_t<double>(c, p, x, y, mode)
                                         : debug_apply_t<float>(c, p, x, y, mode);
+}
+
+}  // namespace mpm
+
+namespace mpm {
+
+int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* in_bf16, float* target) {
+    int rc = ensure_layout(c);
+    if (rc != MPM_OK) return rc;
+    hipStream_t st = c->stream;
+    const ProbHost& ph = c->probs[p];
+    const ProbDev& pd = c->h_probs[p];
+    const long long G = (long long)ph.gd[0] * ph.gd[1] * ph.gd[2];
+    const int bx = ph.hi[0] - ph.lo[0], by = ph.hi[1] - ph.lo[1], bz = ph.hi[2] - ph.lo[2];
+    k_ws_input<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_old, ph.stat, c->d_scales, in_bf16);
+    k_ws_target<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_old, c_new, ph.stat, c->d_scales,
+                                                           target);
+    MPM_HIP(hipGetLastError());
+    MPM_HIP(hipStreamSynchronize(st));
+    return MPM_OK;
 }
 
 }  // namespace mpm

@@ -254,6 +254,32 @@ static void free_padded(T*& p) {
     p = nullptr;
 }
 
+// Static input channels of the warm-start network on the box grid (box sizes rounded
+// up to multiples of 8): per grid voxel k[0..S), D[0..S), s[0..S), mask; zero outside
+// the box.
+__global__ void k_ws_static(const uint8_t* mask, const double* D, const double* k, const double* src, BoxGeo g,
+                            int gx, int gy, int gz, int S, long long nvox, float* stat) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long G = (long long)gx * gy * gz;
+    if (i >= G) return;
+    const int x = (int)(i % gx);
+    const int y = (int)((i / gx) % gy);
+    const int z = (int)(i / ((long long)gx * gy));
+    const int C = 3 * S + 1;
+    float* o = stat + i * C;
+    if (x >= g.bx || y >= g.by || z >= g.bz) {
+        for (int c = 0; c < C; ++c) o[c] = 0.f;
+        return;
+    }
+    const long long v = ((long long)(g.z0 + z) * g.ny + (g.y0 + y)) * g.nx + (g.x0 + x);
+    for (int s = 0; s < S; ++s) {
+        o[s] = (float)k[s * nvox + v];
+        o[S + s] = (float)D[s * nvox + v];
+        o[2 * S + s] = (float)src[s * nvox + v];
+    }
+    o[3 * S] = mask[v] ? 1.f : 0.f;
+}
+
 void free_problem(ProbHost& ph) {
     free_padded(ph.vox);
     free_padded(ph.nbr);
@@ -264,6 +290,13 @@ void free_problem(ProbHost& ph) {
     free_padded(ph.c32);
     free_padded(ph.c64);
     ph.cap_pad = 0;
+    (void)hipFree(ph.stat);
+    (void)hipFree(ph.wsin);
+    (void)hipFree(ph.wsout);
+    ph.stat = nullptr;
+    ph.wsin = nullptr;
+    ph.wsout = nullptr;
+    ph.cap_grid = 0;
 }
 
 static int alloc_problem(ProbHost& ph, int S, int Npad) {
@@ -365,6 +398,33 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     k_coefs<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ca);
     k_scaled<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ph.a64, ph.sc64, ph.nbr, N, Npad, c->S, ph.c64,
                                                           ph.c32);
+    if (c->opt.warm_start == MPM_WS_NET) {
+        const int gx = (g.bx + 7) / 8 * 8, gy = (g.by + 7) / 8 * 8, gz = (g.bz + 7) / 8 * 8;
+        const size_t G = (size_t)gx * gy * gz;
+        if (G > ph.cap_grid) {
+            (void)hipFree(ph.stat);
+            (void)hipFree(ph.wsin);
+            (void)hipFree(ph.wsout);
+            ph.stat = nullptr;
+            ph.wsin = nullptr;
+            ph.wsout = nullptr;
+            ph.cap_grid = 0;
+            if (hipMalloc(&ph.stat, G * (3 * c->S + 1) * sizeof(float)) != hipSuccess ||
+                hipMalloc(&ph.wsin, G * (4 * c->S + 1) * sizeof(uint16_t)) != hipSuccess ||
+                hipMalloc(&ph.wsout, G * c->S * sizeof(float)) != hipSuccess) {
+                (void)hipGetLastError();
+                cleanup();
+                set_error("mpm_fv_setup: device allocation of the warm-start buffers failed");
+                return MPM_ENOMEM;
+            }
+            ph.cap_grid = G;
+        }
+        ph.gd[0] = gx;
+        ph.gd[1] = gy;
+        ph.gd[2] = gz;
+        k_ws_static<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(mask, D, k, src, g, gx, gy, gz, c->S, ca.nvox,
+                                                              ph.stat);
+    }
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     cleanup();

@@ -1,0 +1,53 @@
+// Host-side U-Net state (not visible through the C ABI).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace mpm {
+
+struct ConvL {
+    int cin = 0, cout = 0, taps = 0;
+    int cin_p = 0, cout_p = 0, kp = 0, kpd = 0;
+    size_t woff = 0, boff = 0;         // offsets in the flat parameter vector
+    uint16_t* wf = nullptr;            // BF16 [cout_p][kp], k = tap * cin_p + c
+    uint16_t* wd = nullptr;            // BF16 [cin_p][kpd], k = tap * cout_p + o, W[26 - tap]
+};
+
+struct Net {
+    int in_ch = 0, out_ch = 0, L = 0;
+    std::vector<int> widths;
+    std::vector<ConvL> layers;         // forward order; the last one is the 1x1x1 head
+    size_t nparam = 0;
+    float* theta = nullptr;            // FP32 master parameters
+    float* grad = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    hipStream_t stream = nullptr;
+    // buffers for the current input shape
+    int dims[4] = {0, 0, 0, 0};        // n, D, H, W
+    std::vector<void*> bufs;
+    uint16_t* xin = nullptr;
+    std::vector<uint16_t*> act, gin, pooled, cat, dcat;
+    std::vector<int> lvl_of;
+    uint16_t* ghead = nullptr;
+    uint16_t* gscratch = nullptr;
+    const uint16_t* head_in = nullptr;
+    float* wpart = nullptr;
+    size_t wpart_cap = 0;
+    float* dpart = nullptr;
+    size_t dpart_cap = 0;
+    float* outbuf = nullptr;
+    bool have_fwd = false;
+    // warm-start use
+    double* mse_part = nullptr;
+};
+
+int net_build(Net* n, int in_ch, int out_ch, int levels, const int* widths, uint64_t seed);
+int net_pack(Net* n);
+void net_free(Net* n);
+int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out);
+int net_backward(Net* n, const float* dout);
+
+}  // namespace mpm

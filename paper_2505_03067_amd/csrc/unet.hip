@@ -1,0 +1,652 @@
+// Warm-start U-Net: parameters, activations and the forward/backward/Adam driver.
+//
+// Shape (fixed by the project's specification, not by the paper): L levels of widths
+// C_0..C_{L-1}; per level two 3x3x3 convolutions + ReLU; 2x2x2 average pooling between
+// encoder levels; decoder levels upsample x2 (nearest), concatenate [upsampled, skip]
+// and apply two 3x3x3 convolutions + ReLU; a 1x1x1 head.  FP32 master parameters,
+// gradients and Adam moments; BF16 copies of the convolution weights in the layouts
+// the MFMA kernels read; BF16 activations; FP32 accumulation.
+#include <cmath>
+#include <random>
+#include <vector>
+
+#include "context.h"
+#include "unet.h"
+#include "unet_kernels.h"
+
+namespace mpm {
+
+static int roundup(int v, int m) { return (v + m - 1) / m * m; }
+
+int net_build(Net* n, int in_ch, int out_ch, int levels, const int* widths, uint64_t seed) {
+    n->in_ch = in_ch;
+    n->out_ch = out_ch;
+    n->L = levels;
+    n->widths.assign(widths, widths + levels);
+    auto add = [&](int cin, int cout, int taps) {
+        ConvL l;
+        l.cin = cin;
+        l.cout = cout;
+        l.taps = taps;
+        l.cin_p = roundup(cin, 16);
+        l.cout_p = roundup(cout, 16);
+        l.kp = roundup(taps * l.cin_p, 32);
+        l.kpd = roundup(taps * l.cout_p, 32);
+        l.woff = n->nparam;
+        n->nparam += (size_t)taps * cin * cout;
+        l.boff = n->nparam;
+        n->nparam += cout;
+        n->layers.push_back(l);
+    };
+    int cin = in_ch;
+    for (int l = 0; l < levels; ++l) {
+        add(cin, widths[l], 27);
+        add(widths[l], widths[l], 27);
+        cin = widths[l];
+    }
+    for (int l = levels - 2; l >= 0; --l) {
+        add(widths[l + 1] + widths[l], widths[l], 27);
+        add(widths[l], widths[l], 27);
+    }
+    add(widths[0], out_ch, 1);
+    hipStream_t st = n->stream;
+    const size_t np = n->nparam;
+    MPM_HIP(hipMalloc(&n->theta, np * 4));
+    MPM_HIP(hipMalloc(&n->grad, np * 4));
+    MPM_HIP(hipMalloc(&n->m, np * 4));
+    MPM_HIP(hipMalloc(&n->v, np * 4));
+    MPM_HIP(hipMemsetAsync(n->grad, 0, np * 4, st));
+    MPM_HIP(hipMemsetAsync(n->m, 0, np * 4, st));
+    MPM_HIP(hipMemsetAsync(n->v, 0, np * 4, st));
+    for (auto& l : n->layers) {
+        if (l.taps != 27) continue;
+        MPM_HIP(hipMalloc(&l.wf, (size_t)l.cout_p * l.kp * 2));
+        MPM_HIP(hipMalloc(&l.wd, (size_t)l.cin_p * l.kpd * 2));
+    }
+    // He-normal initialisation (std sqrt(2 / fan_in)), zero biases, small head
+    std::vector<float> h(np, 0.0f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (size_t li = 0; li < n->layers.size(); ++li) {
+        const ConvL& l = n->layers[li];
+        const bool head = li + 1 == n->layers.size();
+        const double sd = head ? 1e-2 : std::sqrt(2.0 / (double)(l.taps * l.cin));
+        for (size_t i = 0; i < (size_t)l.taps * l.cin * l.cout; ++i) h[l.woff + i] = (float)(sd * nd(rng));
+    }
+    MPM_HIP(hipMemcpyAsync(n->theta, h.data(), np * 4, hipMemcpyHostToDevice, st));
+    MPM_HIP(hipStreamSynchronize(st));
+    return net_pack(n);
+}
+
+int net_pack(Net* n) {
+    hipStream_t st = n->stream;
+    for (auto& l : n->layers) {
+        if (l.taps != 27) continue;
+        const long long tot = (long long)l.cout_p * l.kp + (long long)l.cin_p * l.kpd;
+        k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(n->theta + l.woff, l.cin, l.cout, l.taps, l.cin_p,
+                                                            l.cout_p, l.kp, l.kpd, l.wf, l.wd);
+    }
+    MPM_HIP(hipGetLastError());
+    return MPM_OK;
+}
+
+static void free_acts(Net* n) {
+    for (auto p : n->bufs) (void)hipFree(p);
+    n->bufs.clear();
+    n->act.clear();
+    n->gin.clear();
+    n->pooled.clear();
+    n->cat.clear();
+    n->dcat.clear();
+    (void)hipFree(n->wpart);
+    n->wpart = nullptr;
+    n->wpart_cap = 0;
+    n->dims[0] = n->dims[1] = n->dims[2] = n->dims[3] = 0;
+}
+
+void net_free(Net* n) {
+    if (!n) return;
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    free_acts(n);
+    for (auto& l : n->layers) {
+        (void)hipFree(l.wf);
+        (void)hipFree(l.wd);
+    }
+    (void)hipFree(n->theta);
+    (void)hipFree(n->grad);
+    (void)hipFree(n->m);
+    (void)hipFree(n->v);
+    (void)hipFree(n->outbuf);
+    (void)hipFree(n->dpart);
+}
+
+// Activation, gradient and scratch buffers for one input shape.
+static int ensure_acts(Net* n, int nb, int D, int H, int W) {
+    if (n->dims[0] == nb && n->dims[1] == D && n->dims[2] == H && n->dims[3] == W) return MPM_OK;
+    free_acts(n);
+    const int L = n->L;
+    auto alloc = [&](size_t elems, uint16_t** p) -> int {
+        if (hipMalloc(p, elems * 2) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("U-Net activation allocation failed");
+            return MPM_ENOMEM;
+        }
+        n->bufs.push_back(*p);
+        return MPM_OK;
+    };
+    auto vox = [&](int lvl) { return (size_t)nb * (D >> lvl) * (H >> lvl) * (W >> lvl); };
+    const size_t nl = n->layers.size();
+    n->act.assign(nl, nullptr);
+    n->gin.assign(nl, nullptr);
+    n->pooled.assign(L, nullptr);
+    n->cat.assign(L, nullptr);
+    n->dcat.assign(L, nullptr);
+    int rc = alloc(vox(0) * n->layers[0].cin_p, &n->xin);
+    if (rc) return rc;
+    // level of each conv layer
+    std::vector<int> lvl_of(nl, 0);
+    for (int l = 0; l < L; ++l) lvl_of[2 * l] = lvl_of[2 * l + 1] = l;
+    for (int d = 0; d < L - 1; ++d) {
+        const int l = L - 2 - d;
+        lvl_of[2 * L + 2 * d] = lvl_of[2 * L + 2 * d + 1] = l;
+    }
+    n->lvl_of = lvl_of;
+    for (size_t li = 0; li + 1 < nl; ++li) {
+        const ConvL& c = n->layers[li];
+        if ((rc = alloc(vox(lvl_of[li]) * c.cout, &n->act[li]))) return rc;
+        if ((rc = alloc(vox(lvl_of[li]) * c.cout, &n->gin[li]))) return rc;   // grad wrt this layer's output
+    }
+    for (int l = 1; l < L; ++l)
+        if ((rc = alloc(vox(l) * n->widths[l - 1], &n->pooled[l]))) return rc;
+    for (int l = 0; l < L - 1; ++l) {
+        const size_t c = (size_t)n->widths[l + 1] + n->widths[l];
+        if ((rc = alloc(vox(l) * c, &n->cat[l]))) return rc;
+        if ((rc = alloc(vox(l) * c, &n->dcat[l]))) return rc;
+    }
+    if ((rc = alloc(vox(0) * n->widths[0], &n->ghead))) return rc;
+    if ((rc = alloc(vox(1) * n->widths[0] * 8, &n->gscratch))) return rc;   // pooled-input gradient
+    n->dims[0] = nb;
+    n->dims[1] = D;
+    n->dims[2] = H;
+    n->dims[3] = W;
+    return MPM_OK;
+}
+
+template <int NT>
+static void launch_conv(const ConvArgs& a, hipStream_t st) {
+    constexpr int MT = 2;
+    const long long P = (long long)a.n * a.D * a.H * a.W;
+    const unsigned grid = (unsigned)((P + 4 * MT * 16 - 1) / (4 * MT * 16));
+    k_conv<NT, MT><<<grid, 256, 0, st>>>(a);
+}
+
+static int conv_dispatch(const ConvArgs& a, int nt, hipStream_t st) {
+    switch (nt) {
+        case 1: launch_conv<1>(a, st); break;
+        case 2: launch_conv<2>(a, st); break;
+        case 3: launch_conv<3>(a, st); break;
+        case 4: launch_conv<4>(a, st); break;
+        case 6: launch_conv<6>(a, st); break;
+        case 8: launch_conv<8>(a, st); break;
+        default: set_error("unsupported channel count in the U-Net"); return MPM_EINVAL;
+    }
+    return MPM_OK;
+}
+
+static ConvArgs conv_args(const Net* n, int lvl) {
+    ConvArgs a{};
+    a.n = n->dims[0];
+    a.D = n->dims[1] >> lvl;
+    a.H = n->dims[2] >> lvl;
+    a.W = n->dims[3] >> lvl;
+    return a;
+}
+
+static unsigned blocks_for(long long count) { return (unsigned)((count + 255) / 256); }
+
+int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out) {
+    const int L = n->L;
+    const int div = 1 << (L - 1);
+    if (nb < 1 || D < div || H < div || W < div || D % div || H % div || W % div) {
+        set_error("U-Net input sizes must be positive multiples of 2^(levels-1)");
+        return MPM_EINVAL;
+    }
+    int rc = ensure_acts(n, nb, D, H, W);
+    if (rc) return rc;
+    hipStream_t st = n->stream;
+    const long long P0 = (long long)nb * D * H * W;
+    const ConvL& l0 = n->layers[0];
+    k_pad_channels<<<blocks_for(P0 * l0.cin_p), 256, 0, st>>>(in, n->in_ch, l0.cin_p, P0, n->xin);
+    const uint16_t* h = n->xin;
+    int hch = l0.cin_p;
+    int li = 0;
+    for (int lvl = 0; lvl < L; ++lvl) {
+        if (lvl > 0) {
+            const long long Pl = P0 >> (3 * lvl);
+            k_pool2<<<blocks_for(Pl * hch), 256, 0, st>>>(h, hch, hch, nb, D >> (lvl - 1), H >> (lvl - 1),
+                                                         W >> (lvl - 1), n->pooled[lvl]);
+            h = n->pooled[lvl];
+        }
+        for (int r = 0; r < 2; ++r, ++li) {
+            const ConvL& c = n->layers[li];
+            ConvArgs a = conv_args(n, lvl);
+            a.x = h;
+            a.ldx = hch;
+            a.cin_p = c.cin_p;
+            a.w = c.wf;
+            a.kp = c.kp;
+            a.taps = 27;
+            a.bias = n->theta + c.boff;
+            a.y = n->act[li];
+            a.ldy = c.cout;
+            a.cout = c.cout;
+            a.relu = 1;
+            if ((rc = conv_dispatch(a, c.cout_p / 16, st))) return rc;
+            h = n->act[li];
+            hch = c.cout;
+        }
+    }
+    for (int lvl = L - 2; lvl >= 0; --lvl) {
+        const long long Pl = P0 >> (3 * lvl);
+        const int cu = n->widths[lvl + 1], cs = n->widths[lvl];
+        k_up2_cat<<<blocks_for(Pl * (cu + cs)), 256, 0, st>>>(h, cu, n->act[2 * lvl + 1], cs, nb, D >> lvl, H >> lvl,
+                                                               W >> lvl, n->cat[lvl]);
+        h = n->cat[lvl];
+        hch = cu + cs;
+        for (int r = 0; r < 2; ++r, ++li) {
+            const ConvL& c = n->layers[li];
+            ConvArgs a = conv_args(n, lvl);
+            a.x = h;
+            a.ldx = hch;
+            a.cin_p = c.cin_p;
+            a.w = c.wf;
+            a.kp = c.kp;
+            a.taps = 27;
+            a.bias = n->theta + c.boff;
+            a.y = n->act[li];
+            a.ldy = c.cout;
+            a.cout = c.cout;
+            a.relu = 1;
+            if ((rc = conv_dispatch(a, c.cout_p / 16, st))) return rc;
+            h = n->act[li];
+            hch = c.cout;
+        }
+    }
+    const ConvL& hd = n->layers[li];
+    n->head_in = h;
+    k_head<<<blocks_for(P0), 256, 0, st>>>(h, hch, n->theta + hd.woff, n->theta + hd.boff, hd.cout, P0, out);
+    MPM_HIP(hipGetLastError());
+    n->have_fwd = true;
+    return MPM_OK;
+}
+
+// Weight and bias gradients of 3x3x3 layer li (input x with ldx channels at level lvl,
+// output gradient g gated by the layer's own output).
+static int conv_param_grads(Net* n, int li, int lvl, const uint16_t* x, int ldx, const uint16_t* g,
+                            const uint16_t* gate, float* gw, float* gb) {
+    hipStream_t st = n->stream;
+    const ConvL& c = n->layers[li];
+    const long long P = (long long)n->dims[0] * (n->dims[1] >> lvl) * (n->dims[2] >> lvl) * (n->dims[3] >> lvl);
+    long long nchunk = std::max(1LL, std::min(64LL, P / 2048));
+    const long long per = ((P + nchunk - 1) / nchunk + 63) / 64 * 64;
+    nchunk = (P + per - 1) / per;
+    const size_t need = (size_t)nchunk * 27 * c.cin_p * c.cout_p;
+    if (need > n->wpart_cap) {
+        (void)hipFree(n->wpart);
+        if (hipMalloc(&n->wpart, need * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            n->wpart = nullptr;
+            n->wpart_cap = 0;
+            set_error("U-Net gradient scratch allocation failed");
+            return MPM_ENOMEM;
+        }
+        n->wpart_cap = need;
+    }
+    WgradArgs w{};
+    w.x = x;
+    w.g = g;
+    w.gate = gate;
+    w.part = n->wpart;
+    w.ldx = ldx;
+    w.cin_p = c.cin_p;
+    w.ldg = c.cout;
+    w.cout_p = c.cout_p;
+    w.n = n->dims[0];
+    w.D = n->dims[1] >> lvl;
+    w.H = n->dims[2] >> lvl;
+    w.W = n->dims[3] >> lvl;
+    w.per_chunk = per;
+    k_conv_wgrad<<<dim3((unsigned)nchunk, 27), 256, 0, st>>>(w);
+    const long long tot = 27LL * c.cin * c.cout;
+    k_wgrad_reduce<<<blocks_for(tot), 256, 0, st>>>(n->wpart, (int)nchunk, c.cin, c.cout, c.cin_p, c.cout_p, gw);
+    if ((size_t)nchunk * c.cout > n->dpart_cap) {
+        (void)hipFree(n->dpart);
+        n->dpart_cap = std::max<size_t>((size_t)nchunk * c.cout, 64 * 128);
+        if (hipMalloc(&n->dpart, n->dpart_cap * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            n->dpart = nullptr;
+            n->dpart_cap = 0;
+            set_error("U-Net gradient scratch allocation failed");
+            return MPM_ENOMEM;
+        }
+    }
+    if (gb) {
+        k_bias_part<<<(unsigned)nchunk, 256, 0, st>>>(g, gate, c.cout, c.cout, P, per, n->dpart);
+        k_bias_reduce<<<1, 128, 0, st>>>(n->dpart, (int)nchunk, c.cout, gb);
+    }
+    MPM_HIP(hipGetLastError());
+    return MPM_OK;
+}
+
+// Input gradient of 3x3x3 layer li into dx ([P][cin]), from g gated by the layer output.
+static int conv_input_grad(Net* n, int li, int lvl, const uint16_t* g, const uint16_t* gate, uint16_t* dx,
+                           float* dxf = nullptr) {
+    const ConvL& c = n->layers[li];
+    ConvArgs a = conv_args(n, lvl);
+    a.x = g;
+    a.gate = gate;
+    a.yf = dxf;
+    a.ldx = c.cout;
+    a.cin_p = c.cout_p;
+    a.w = c.wd;
+    a.kp = c.kpd;
+    a.taps = 27;
+    a.y = dx;
+    a.ldy = c.cin;
+    a.cout = c.cin;
+    return conv_dispatch(a, c.cin_p / 16, n->stream);
+}
+
+int net_backward(Net* n, const float* dout) {
+    if (!n->have_fwd) {
+        set_error("mpm_net_backward needs a preceding mpm_net_forward");
+        return MPM_ESTATE;
+    }
+    hipStream_t st = n->stream;
+    const int L = n->L;
+    const int nb = n->dims[0], D = n->dims[1], H = n->dims[2], W = n->dims[3];
+    const long long P0 = (long long)nb * D * H * W;
+    const int nl = (int)n->layers.size();
+    int rc;
+    // head
+    {
+        const ConvL& hd = n->layers[nl - 1];
+        const long long nchunk = std::max(1LL, std::min(256LL, P0 / 4096));
+        const long long per = (P0 + nchunk - 1) / nchunk;
+        const int npar = hd.cin * hd.cout + hd.cout;
+        if ((size_t)nchunk * npar > n->dpart_cap) {
+            (void)hipFree(n->dpart);
+            n->dpart_cap = (size_t)nchunk * npar;
+            if (hipMalloc(&n->dpart, n->dpart_cap * 4) != hipSuccess) {
+                (void)hipGetLastError();
+                n->dpart = nullptr;
+                n->dpart_cap = 0;
+                set_error("U-Net gradient scratch allocation failed");
+                return MPM_ENOMEM;
+            }
+        }
+        k_head_bwd<<<(unsigned)nchunk, 256, 0, st>>>(n->head_in, hd.cin, n->theta + hd.woff, hd.cout, dout, P0, per,
+                                                     n->ghead, n->dpart);
+        k_param_reduce<<<blocks_for(npar), 256, 0, st>>>(n->dpart, (int)nchunk, npar, n->grad + hd.woff);
+    }
+    // decoder, deepest last in forward order -> first here is level 0
+    int li = nl - 2;
+    const uint16_t* g = n->ghead;     // gradient wrt the output of layer li
+    for (int lvl = 0; lvl <= L - 2; ++lvl) {
+        const int cu = n->widths[lvl + 1], cs = n->widths[lvl];
+        // second conv of the level: input act[li - 1]
+        if ((rc = conv_param_grads(n, li, lvl, n->act[li - 1], n->layers[li].cin, g, n->act[li], n->grad + n->layers[li].woff, n->grad + n->layers[li].boff))) return rc;
+        if ((rc = conv_input_grad(n, li, lvl, g, n->act[li], n->gin[li - 1]))) return rc;
+        g = n->gin[li - 1];
+        --li;
+        // first conv of the level: input the concat buffer
+        if ((rc = conv_param_grads(n, li, lvl, n->cat[lvl], cu + cs, g, n->act[li], n->grad + n->layers[li].woff, n->grad + n->layers[li].boff))) return rc;
+        if ((rc = conv_input_grad(n, li, lvl, g, n->act[li], n->dcat[lvl]))) return rc;
+        --li;
+        // gradient wrt the upsampled input -> gradient wrt the output of layer li (one level deeper)
+        const long long Pd = P0 >> (3 * (lvl + 1));
+        k_up2_bwd<<<blocks_for(Pd * cu), 256, 0, st>>>(n->dcat[lvl], cu + cs, cu, nb, D >> (lvl + 1), H >> (lvl + 1),
+                                                      W >> (lvl + 1), n->gin[li]);
+        g = n->gin[li];
+    }
+    // encoder, bottom first; li is the second conv of the bottom level
+    for (int lvl = L - 1; lvl >= 0; --lvl) {
+        const int cinl = lvl == 0 ? n->layers[0].cin_p : n->widths[lvl - 1];
+        if ((rc = conv_param_grads(n, li, lvl, n->act[li - 1], n->layers[li].cin, g, n->act[li], n->grad + n->layers[li].woff, n->grad + n->layers[li].boff))) return rc;
+        if ((rc = conv_input_grad(n, li, lvl, g, n->act[li], n->gin[li - 1]))) return rc;
+        g = n->gin[li - 1];
+        --li;
+        const uint16_t* xin = lvl == 0 ? n->xin : n->pooled[lvl];
+        if ((rc = conv_param_grads(n, li, lvl, xin, cinl, g, n->act[li], n->grad + n->layers[li].woff, n->grad + n->layers[li].boff))) return rc;
+        if (lvl == 0) break;
+        // gradient wrt the pooled input, then wrt the previous level's output (+ its skip)
+        if ((rc = conv_input_grad(n, li, lvl, g, n->act[li], n->gscratch))) return rc;
+        --li;
+        const int c = n->widths[lvl - 1];
+        const long long Pu = P0 >> (3 * (lvl - 1));
+        k_pool2_bwd_add<<<blocks_for(Pu * c), 256, 0, st>>>(n->gscratch, c,
+                                                           lvl - 1 <= L - 2 ? n->dcat[lvl - 1] + n->widths[lvl] : nullptr,
+                                                           n->widths[lvl] + c, nb, D >> (lvl - 1), H >> (lvl - 1),
+                                                           W >> (lvl - 1), n->gin[li]);
+        g = n->gin[li];
+    }
+    MPM_HIP(hipGetLastError());
+    return MPM_OK;
+}
+
+}  // namespace mpm
+
+// ------------------------------------------------------------------ C ABI
+using namespace mpm;
+
+extern "C" int32_t mpm_net_create(mpm_net* out, int32_t in_ch, int32_t out_ch, int32_t levels, const int32_t* widths,
+                                  uint64_t seed, void* stream) {
+    if (!out || !widths) {
+        set_error("mpm_net_create: null pointer");
+        return MPM_EINVAL;
+    }
+    *out = nullptr;
+    if (in_ch < 1 || in_ch > 16 || out_ch < 1 || out_ch > 4 || levels < 1 || levels > 6) {
+        set_error("mpm_net_create: need 1 <= in_ch <= 16, 1 <= out_ch <= 4, 1 <= levels <= 6");
+        return MPM_EINVAL;
+    }
+    for (int l = 0; l < levels; ++l) {
+        if (widths[l] < 16 || widths[l] > 64 || widths[l] % 16 != 0) {
+            set_error("mpm_net_create: widths must be 16, 32, 48 or 64");
+            return MPM_EINVAL;
+        }
+        if (l + 1 < levels && widths[l] + widths[l + 1] > 128) {
+            set_error("mpm_net_create: a decoder concat may hold at most 128 channels");
+            return MPM_EINVAL;
+        }
+    }
+    if (widths[0] > 16) {
+        set_error("mpm_net_create: the head reads at most 16 channels (widths[0] = 16)");
+        return MPM_EINVAL;
+    }
+    Net* n = new Net();
+    n->stream = (hipStream_t)stream;
+    int rc = net_build(n, in_ch, out_ch, levels, widths, seed);
+    if (rc == MPM_OK) {
+        hipError_t e = hipStreamSynchronize(n->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "mpm_net_create");
+    }
+    if (rc != MPM_OK) {
+        net_free(n);
+        delete n;
+        return rc;
+    }
+    *out = (mpm_net)n;
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_net_params(mpm_net net, float** params, float** grads, int64_t* count) {
+    Net* n = (Net*)net;
+    if (!n || !params || !grads || !count) {
+        set_error("mpm_net_params: null pointer");
+        return MPM_EINVAL;
+    }
+    *params = n->theta;
+    *grads = n->grad;
+    *count = (int64_t)n->nparam;
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_net_sync_weights(mpm_net net) {
+    Net* n = (Net*)net;
+    if (!n) {
+        set_error("mpm_net_sync_weights: null pointer");
+        return MPM_EINVAL;
+    }
+    return net_pack(n);
+}
+
+extern "C" int32_t mpm_net_zero_grad(mpm_net net) {
+    Net* n = (Net*)net;
+    if (!n) {
+        set_error("mpm_net_zero_grad: null pointer");
+        return MPM_EINVAL;
+    }
+    MPM_HIP(hipMemsetAsync(n->grad, 0, n->nparam * 4, n->stream));
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_net_forward(mpm_net net, const uint16_t* in, int32_t nb, int32_t d, int32_t h, int32_t w,
+                                   float* out) {
+    Net* n = (Net*)net;
+    if (!n || !in || !out) {
+        set_error("mpm_net_forward: null pointer");
+        return MPM_EINVAL;
+    }
+    return net_forward(n, in, nb, d, h, w, out);
+}
+
+extern "C" int32_t mpm_net_backward(mpm_net net, const float* grad_out) {
+    Net* n = (Net*)net;
+    if (!n || !grad_out) {
+        set_error("mpm_net_backward: null pointer");
+        return MPM_EINVAL;
+    }
+    return net_backward(n, grad_out);
+}
+
+extern "C" int32_t mpm_net_mse(mpm_net net, const float* out, const float* target, int64_t count, float* grad_out,
+                               double* loss) {
+    Net* n = (Net*)net;
+    if (!n || !out || !target || !grad_out || !loss || count <= 0) {
+        set_error("mpm_net_mse: bad arguments");
+        return MPM_EINVAL;
+    }
+    const int nb = 512;
+    if (!n->mse_part) MPM_HIP(hipHostMalloc((void**)&n->mse_part, nb * sizeof(double), hipHostMallocDefault));
+    double* dpart = nullptr;
+    MPM_HIP(hipMalloc(&dpart, nb * sizeof(double)));
+    k_mse<<<nb, 256, 0, n->stream>>>(out, target, count, grad_out, dpart);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(n->mse_part, dpart, nb * sizeof(double), hipMemcpyDeviceToHost, n->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    (void)hipFree(dpart);
+    if (e != hipSuccess) return hip_fail(e, "mpm_net_mse");
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += n->mse_part[i];
+    *loss = s / (double)count;
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_net_adam_step(mpm_net net, float lr, float b1, float b2, float eps, int32_t t) {
+    Net* n = (Net*)net;
+    if (!n || t < 1 || !(lr >= 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps >= 0.f)) {
+        set_error("mpm_net_adam_step: bad arguments");
+        return MPM_EINVAL;
+    }
+    const float c1 = 1.0f - std::pow(b1, (float)t), c2 = 1.0f - std::pow(b2, (float)t);
+    const long long np = (long long)n->nparam;
+    k_adam<<<(unsigned)((np + 255) / 256), 256, 0, n->stream>>>(n->theta, n->grad, n->m, n->v, np, lr, b1, b2, eps, c1,
+                                                                 c2);
+    MPM_HIP(hipGetLastError());
+    return net_pack(n);
+}
+
+extern "C" int32_t mpm_net_destroy(mpm_net net) {
+    Net* n = (Net*)net;
+    if (!n) return MPM_OK;
+    if (n->mse_part) (void)hipHostFree(n->mse_part);
+    net_free(n);
+    delete n;
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_net_read(mpm_net net, int32_t what, float* dst) {
+    Net* n = (Net*)net;
+    if (!n || !dst || (what != 0 && what != 1)) {
+        set_error("mpm_net_read: bad arguments");
+        return MPM_EINVAL;
+    }
+    MPM_HIP(hipMemcpyAsync(dst, what == 0 ? n->theta : n->grad, n->nparam * 4, hipMemcpyDeviceToDevice, n->stream));
+    MPM_HIP(hipStreamSynchronize(n->stream));
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_net_write(mpm_net net, int32_t what, const float* src) {
+    Net* n = (Net*)net;
+    if (!n || !src || (what != 0 && what != 1)) {
+        set_error("mpm_net_write: bad arguments");
+        return MPM_EINVAL;
+    }
+    MPM_HIP(hipMemcpyAsync(what == 0 ? n->theta : n->grad, src, n->nparam * 4, hipMemcpyDeviceToDevice, n->stream));
+    if (what == 0) {
+        int rc = net_pack(n);
+        if (rc != MPM_OK) return rc;
+    }
+    MPM_HIP(hipStreamSynchronize(n->stream));
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_net_debug_layer(mpm_net net, int32_t layer, int32_t mode, int32_t nb, int32_t d, int32_t h,
+                                       int32_t w, const uint16_t* x, const uint16_t* g, const uint16_t* gate,
+                                       float* out) {
+    Net* n = (Net*)net;
+    if (!n || !out || layer < 0 || layer + 1 >= (int)n->layers.size() || mode < 0 || mode > 2 || nb < 1 || d < 1 ||
+        h < 1 || w < 1 || (mode != 1 && !x) || (mode != 0 && !g)) {
+        set_error("mpm_net_debug_layer: bad arguments");
+        return MPM_EINVAL;
+    }
+    const ConvL& c = n->layers[layer];
+    hipStream_t st = n->stream;
+    int saved[4] = {n->dims[0], n->dims[1], n->dims[2], n->dims[3]};
+    n->dims[0] = nb;
+    n->dims[1] = d;
+    n->dims[2] = h;
+    n->dims[3] = w;
+    int rc = MPM_OK;
+    if (mode == 0) {
+        ConvArgs a = conv_args(n, 0);
+        a.x = x;
+        a.ldx = c.cin_p;
+        a.cin_p = c.cin_p;
+        a.w = c.wf;
+        a.kp = c.kp;
+        a.taps = 27;
+        a.bias = n->theta + c.boff;
+        a.yf = out;
+        a.cout = c.cout;
+        rc = conv_dispatch(a, c.cout_p / 16, st);
+    } else if (mode == 1) {
+        rc = conv_input_grad(n, layer, 0, g, gate, nullptr, out);
+    } else {
+        // the reduction accumulates into its target, so start from zero
+        hipError_t e = hipMemsetAsync(out, 0, (size_t)27 * c.cin * c.cout * sizeof(float), st);
+        rc = e == hipSuccess ? conv_param_grads(n, layer, 0, x, c.cin_p, g, gate, out, nullptr)
+                             : hip_fail(e, "mpm_net_debug_layer");
+    }
+    n->dims[0] = saved[0];
+    n->dims[1] = saved[1];
+    n->dims[2] = saved[2];
+    n->dims[3] = saved[3];
+    if (rc == MPM_OK) {
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "mpm_net_debug_layer");
+    }
+    return rc;
+}

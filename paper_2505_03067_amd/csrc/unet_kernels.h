@@ -1,0 +1,497 @@
+// Device kernels of the warm-start U-Net (BF16 storage, FP32 accumulation).
+//
+// Activations are NDHWC [n][z][y][x][c] in BF16.  3x3x3 convolutions are implicit
+// GEMMs on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16): M = output voxels,
+// N = output channels, K = 27 taps x input channels, with the tap/channel index
+// k = tap * Cin_p + c (Cin_p a multiple of 8, so the 8 consecutive k of one lane
+// always belong to one tap).  The input gradient is the same GEMM on the output
+// gradient with the taps mirrored and the weights transposed; the weight gradient
+// stages voxel chunks in LDS, transposed so that K runs over voxels.  For the input
+// gradient, dX[p] = sum_t dY[p - off(t)] W[t] = sum_t dY[p + off(t)] W[26 - t], so the
+// same forward kernel runs on packed weights holding W[26 - t] transposed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpm {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// round to nearest even (finite inputs)
+__device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+struct ConvArgs {
+    const uint16_t* x;     // GEMM input [P][ldx] (activation, or output gradient for dgrad)
+    const uint16_t* gate;  // optional [P][ldx]: use x * (gate > 0) (ReLU backward)
+    const uint16_t* w;     // [cout_p][kp] BF16, k = tap * cin_p + c
+    const float* bias;     // optional [cout]
+    uint16_t* y;           // output [P][ldy], channels [yoff, yoff + cout)
+    float* yf;             // optional FP32 output [P][cout]
+    int ldx, cin_p, kp, taps;
+    int ldy, yoff, cout, relu;
+    int n, D, H, W;
+};
+
+// One wave computes MT x 16 voxels by NT x 16 channels; a block is 4 waves.
+template <int NT, int MT>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const long long P = (long long)a.n * a.D * a.H * a.W;
+    const long long p0 = ((long long)blockIdx.x * 4 + wave) * (MT * 16);
+    if (p0 >= P) return;
+    // decode the voxel of this lane's row in each row tile
+    int vz[MT], vy[MT], vx[MT];
+    long long vb[MT];
+    bool vin[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        long long p = p0 + mt * 16 + (lane & 15);
+        vin[mt] = p < P;
+        if (!vin[mt]) p = 0;
+        vx[mt] = (int)(p % a.W);
+        long long r = p / a.W;
+        vy[mt] = (int)(r % a.H);
+        r /= a.H;
+        vz[mt] = (int)(r % a.D);
+        vb[mt] = r / a.D;
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kg = 8 * (lane >> 4);
+    const int ktot = a.taps * a.cin_p;
+    for (int kk = 0; kk < a.kp; kk += 32) {
+        const int k0 = kk + kg;
+        bf16x8 bfr[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const uint4 t = *reinterpret_cast<const uint4*>(a.w + (long long)(nt * 16 + (lane & 15)) * a.kp + k0);
+            bfr[nt] = __builtin_bit_cast(bf16x8, t);
+        }
+        int dz = 0, dy = 0, dx = 0, c0 = 0;
+        const bool kin = k0 < ktot;
+        if (kin) {
+            const int tap = k0 / a.cin_p;
+            c0 = k0 - tap * a.cin_p;
+            if (a.taps == 27) {
+                dz = tap / 9 - 1;
+                dy = (tap / 3) % 3 - 1;
+                dx = tap % 3 - 1;
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            uint4 t = make_uint4(0, 0, 0, 0);
+            const int z = vz[mt] + dz, yy = vy[mt] + dy, xx = vx[mt] + dx;
+            if (kin && vin[mt] && z >= 0 && z < a.D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+                const long long q = ((vb[mt] * a.D + z) * a.H + yy) * a.W + xx;
+                t = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + c0);
+                if (a.gate) {
+                    const uint4 g = *reinterpret_cast<const uint4*>(a.gate + q * a.ldx + c0);
+                    const uint32_t gw[4] = {g.x, g.y, g.z, g.w};
+                    uint32_t tw[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        // keep each BF16 half only where the gate half is > 0
+                        const uint32_t lo = gw[i] & 0xffffu, hi = gw[i] >> 16;
+                        const bool plo = lo != 0 && !(lo & 0x8000u);
+                        const bool phi = hi != 0 && !(hi & 0x8000u);
+                        tw[i] &= (plo ? 0x0000ffffu : 0u) | (phi ? 0xffff0000u : 0u);
+                    }
+                    t = make_uint4(tw[0], tw[1], tw[2], tw[3]);
+                }
+            }
+            const bf16x8 af = __builtin_bit_cast(bf16x8, t);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+    // D layout: lane holds rows 4 * (lane / 16) + i, column lane % 16
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = nt * 16 + (lane & 15);
+            if (co >= a.cout) continue;
+            const float bv = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long p = p0 + mt * 16 + 4 * (lane >> 4) + i;
+                if (p >= P) continue;
+                float v = acc[mt][nt][i] + bv;
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (a.y) a.y[p * a.ldy + a.yoff + co] = f2bf(v);
+                if (a.yf) a.yf[p * a.cout + co] = v;
+            }
+        }
+    }
+}
+
+struct WgradArgs {
+    const uint16_t* x;     // forward input [P][ldx] (real channels cin, padded cin_p)
+    const uint16_t* g;     // output gradient [P][ldg]
+    const uint16_t* gate;  // layer output [P][ldg] (ReLU gate) or null
+    float* part;           // [nchunk][27][cin_p][cout_p]
+    int ldx, cin_p, ldg, cout_p;
+    int n, D, H, W;
+    long long per_chunk;   // voxels per block (multiple of 64)
+};
+
+// Weight gradient of a 3x3x3 convolution for one tap (blockIdx.y) over one voxel
+// chunk (blockIdx.x): dW[tap][c][o] = sum_p x[p + off(tap)][c] * g[p][o] * (gate > 0).
+// Voxel tiles of 64 are staged in LDS transposed ([channel][voxel]) so that the MFMA
+// K dimension runs over voxels.
+__global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
+    constexpr int PT = 64;
+    __shared__ uint16_t xs[128 * PT];   // [cin_p][PT]
+    __shared__ uint16_t gs[128 * PT];   // [cout_p][PT]
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tap = blockIdx.y;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const long long P = (long long)a.n * a.D * a.H * a.W;
+    const long long pa = (long long)blockIdx.x * a.per_chunk;
+    const long long pb = pa + a.per_chunk < P ? pa + a.per_chunk : P;
+    const int mtc = a.cin_p / 16, ntc = a.cout_p / 16, ntile = mtc * ntc;
+    f32x4 acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int cgx = a.cin_p / 8, cgg = a.cout_p / 8;   // 16-byte groups per voxel
+    for (long long t0 = pa; t0 < pb; t0 += PT) {
+        __syncthreads();
+        // stage x (shifted by the tap) and the gated gradient, transposed
+        for (int e = threadIdx.x; e < PT * (cgx + cgg); e += 256) {
+            const bool isx = e < PT * cgx;
+            const int ee = isx ? e : e - PT * cgx;
+            const int cg = isx ? cgx : cgg;
+            const int pv = ee / cg, grp = ee - pv * cg;
+            const long long p = t0 + pv;
+            uint4 t = make_uint4(0, 0, 0, 0);
+            if (p < pb) {
+                long long r = p;
+                const int xx = (int)(r % a.W); r /= a.W;
+                const int yy = (int)(r % a.H); r /= a.H;
+                const int zz = (int)(r % a.D);
+                const long long nb = r / a.D;
+                if (isx) {
+                    const int z = zz + dz, y = yy + dy, x = xx + dx;
+                    if (z >= 0 && z < a.D && y >= 0 && y < a.H && x >= 0 && x < a.W) {
+                        const long long q = ((nb * a.D + z) * a.H + y) * a.W + x;
+                        t = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + grp * 8);
+                    }
+                } else {
+                    t = *reinterpret_cast<const uint4*>(a.g + p * a.ldg + grp * 8);
+                    if (a.gate) {
+                        const uint4 g = *reinterpret_cast<const uint4*>(a.gate + p * a.ldg + grp * 8);
+                        const uint32_t gw[4] = {g.x, g.y, g.z, g.w};
+                        uint32_t tw[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const uint32_t lo = gw[i] & 0xffffu, hi = gw[i] >> 16;
+                            const bool plo = lo != 0 && !(lo & 0x8000u);
+                            const bool phi = hi != 0 && !(hi & 0x8000u);
+                            tw[i] &= (plo ? 0x0000ffffu : 0u) | (phi ? 0xffff0000u : 0u);
+                        }
+                        t = make_uint4(tw[0], tw[1], tw[2], tw[3]);
+                    }
+                }
+            }
+            const uint32_t w4[4] = {t.x, t.y, t.z, t.w};
+            uint16_t* dst = isx ? xs : gs;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                dst[(grp * 8 + 2 * i) * PT + pv] = (uint16_t)(w4[i] & 0xffffu);
+                dst[(grp * 8 + 2 * i + 1) * PT + pv] = (uint16_t)(w4[i] >> 16);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < PT; kk += 32) {
+            const int kq = kk + 8 * (lane >> 4);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int tile = wave + 4 * i;
+                if (tile < ntile) {
+                    const int mt = tile / ntc, nt = tile - (tile / ntc) * ntc;
+                    const uint4 ta = *reinterpret_cast<const uint4*>(xs + (mt * 16 + (lane & 15)) * PT + kq);
+                    const uint4 tb = *reinterpret_cast<const uint4*>(gs + (nt * 16 + (lane & 15)) * PT + kq);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ta),
+                                                                     __builtin_bit_cast(bf16x8, tb), acc[i], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float* out = a.part + ((long long)blockIdx.x * 27 + tap) * a.cin_p * a.cout_p;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int tile = wave + 4 * i;
+        if (tile < ntile) {
+            const int mt = tile / ntc, nt = tile - (tile / ntc) * ntc;
+            const int co = nt * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ci = mt * 16 + 4 * (lane >> 4) + r;
+                out[ci * a.cout_p + co] = acc[i][r];
+            }
+        }
+    }
+}
+
+// grad[tap][c][o] += sum over chunks of the partials (fixed order).
+__global__ void k_wgrad_reduce(const float* part, int nchunk, int cin, int cout, int cin_p, int cout_p,
+                               float* grad) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = 27LL * cin * cout;
+    if (i >= tot) return;
+    const int o = (int)(i % cout);
+    const long long r = i / cout;
+    const int c = (int)(r % cin);
+    const int tap = (int)(r / cin);
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part[(((long long)k * 27 + tap) * cin_p + c) * cout_p + o];
+    grad[i] += (float)s;
+}
+
+// Bias gradient: per-chunk channel sums of g * (gate > 0), then a fixed-order reduce.
+__global__ __launch_bounds__(256) void k_bias_part(const uint16_t* g, const uint16_t* gate, int ldg, int cout,
+                                                   long long P, long long per_chunk, float* part) {
+    const long long pa = (long long)blockIdx.x * per_chunk;
+    const long long pb = pa + per_chunk < P ? pa + per_chunk : P;
+    __shared__ float sh[256];
+    const int c = threadIdx.x % 64;       // channel (cout <= 64 per pass of 64 lanes)
+    const int row = threadIdx.x / 64;     // 4 voxel phases
+    for (int cb = 0; cb < cout; cb += 64) {
+        float s = 0.f;
+        const int ch = cb + c;
+        if (ch < cout) {
+            for (long long p = pa + row; p < pb; p += 4) {
+                const float v = bf2f(g[p * ldg + ch]);
+                if (!gate || bf2f(gate[p * ldg + ch]) > 0.f) s += v;
+            }
+        }
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        if (row == 0 && ch < cout)
+            part[(long long)blockIdx.x * cout + ch] = sh[c] + sh[64 + c] + sh[128 + c] + sh[192 + c];
+        __syncthreads();
+    }
+}
+
+__global__ void k_bias_reduce(const float* part, int nchunk, int cout, float* grad) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= cout) return;
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part[(long long)k * cout + o];
+    grad[o] += (float)s;
+}
+
+// 2x2x2 average pooling of channels [0, c) (output stride c).
+__global__ void k_pool2(const uint16_t* x, int ldx, int c, int n, int D, int H, int W, uint16_t* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int d = D / 2, h = H / 2, w = W / 2;
+    const long long tot = (long long)n * d * h * w * c;
+    if (i >= tot) return;
+    const int ch = (int)(i % c);
+    long long r = i / c;
+    const int xo = (int)(r % w); r /= w;
+    const int yo = (int)(r % h); r /= h;
+    const int zo = (int)(r % d);
+    const long long nb = r / d;
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) {
+        const long long q = ((nb * D + 2 * zo + (k >> 2)) * H + 2 * yo + ((k >> 1) & 1)) * W + 2 * xo + (k & 1);
+        s += bf2f(x[q * ldx + ch]);
+    }
+    y[i] = f2bf(s * 0.125f);
+}
+
+// out[child] = sum(dpool[parent] / 8 (+ dskip[child] channels)) for the encoder skip.
+__global__ void k_pool2_bwd_add(const uint16_t* dpool, int c, const uint16_t* dskip, int lds, int n, int D, int H,
+                                int W, uint16_t* out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)n * D * H * W * c;
+    if (i >= tot) return;
+    const int ch = (int)(i % c);
+    long long r = i / c;
+    const int x = (int)(r % W); r /= W;
+    const int yv = (int)(r % H); r /= H;
+    const int z = (int)(r % D);
+    const long long nb = r / D;
+    const long long q = ((nb * (D / 2) + z / 2) * (H / 2) + yv / 2) * (W / 2) + x / 2;
+    float v = bf2f(dpool[q * c + ch]) * 0.125f;
+    if (dskip) v += bf2f(dskip[(i / c) * lds + ch]);
+    out[i] = f2bf(v);
+}
+
+// Nearest x2 upsampling of h (c channels) into channels [0, c) of a concat buffer with
+// stride ldc, and a copy of the skip (cs channels) into channels [c, c + cs).
+__global__ void k_up2_cat(const uint16_t* h, int c, const uint16_t* skip, int cs, int n, int D, int H, int W,
+                          uint16_t* cat) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ldc = c + cs;
+    const long long tot = (long long)n * D * H * W * ldc;
+    if (i >= tot) return;
+    const int ch = (int)(i % ldc);
+    const long long p = i / ldc;
+    if (ch < c) {
+        long long r = p;
+        const int x = (int)(r % W); r /= W;
+        const int yv = (int)(r % H); r /= H;
+        const int z = (int)(r % D);
+        const long long nb = r / D;
+        const long long q = ((nb * (D / 2) + z / 2) * (H / 2) + yv / 2) * (W / 2) + x / 2;
+        cat[i] = h[q * c + ch];
+    } else {
+        cat[i] = skip[p * cs + ch - c];
+    }
+}
+
+// Gradient of the upsampling: dh[parent][ch] = sum of the 8 children's dcat[.][ch].
+__global__ void k_up2_bwd(const uint16_t* dcat, int ldc, int c, int n, int d, int h, int w, uint16_t* dh) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)n * d * h * w * c;
+    if (i >= tot) return;
+    const int ch = (int)(i % c);
+    long long r = i / c;
+    const int x = (int)(r % w); r /= w;
+    const int yv = (int)(r % h); r /= h;
+    const int z = (int)(r % d);
+    const long long nb = r / d;
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) {
+        const long long q = ((nb * 2 * d + 2 * z + (k >> 2)) * 2 * h + 2 * yv + ((k >> 1) & 1)) * 2 * w + 2 * x + (k & 1);
+        s += bf2f(dcat[q * ldc + ch]);
+    }
+    dh[i] = f2bf(s);
+}
+
+// 1x1x1 head: out[p][o] = b[o] + sum_c h[p][c] W[c][o] (FP32 weights and output).
+__global__ void k_head(const uint16_t* h, int c, const float* W, const float* b, int cout, long long P, float* out) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    for (int o = 0; o < cout; ++o) {
+        float s = b[o];
+        for (int k = 0; k < c; ++k) s += bf2f(h[p * c + k]) * W[k * cout + o];
+        out[p * cout + o] = s;
+    }
+}
+
+// Head backward: dh[p][c] = sum_o dout[p][o] W[c][o] (BF16), and per-block partials of
+// dW[c][o] = sum_p h[p][c] dout[p][o] and db[o] = sum_p dout[p][o].
+__global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* h, int c, const float* W, int cout, const float* dout,
+                                                  long long P, long long per_chunk, uint16_t* dh, float* part) {
+    const long long pa = (long long)blockIdx.x * per_chunk;
+    const long long pb = pa + per_chunk < P ? pa + per_chunk : P;
+    const int npar = c * cout + cout;
+    float acc[16 * 4 + 4];
+    for (int i = 0; i < npar; ++i) acc[i] = 0.f;
+    for (long long p = pa + threadIdx.x; p < pb; p += blockDim.x) {
+        for (int k = 0; k < c; ++k) {
+            float s = 0.f;
+            const float hv = bf2f(h[p * c + k]);
+            for (int o = 0; o < cout; ++o) {
+                const float g = dout[p * cout + o];
+                s += g * W[k * cout + o];
+                acc[k * cout + o] += hv * g;
+            }
+            dh[p * c + k] = f2bf(s);
+        }
+        for (int o = 0; o < cout; ++o) acc[c * cout + o] += dout[p * cout + o];
+    }
+    __shared__ float sh[256];
+    for (int i = 0; i < npar; ++i) {
+        sh[threadIdx.x] = acc[i];
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(long long)blockIdx.x * npar + i] = sh[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_param_reduce(const float* part, int nchunk, int npar, float* grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npar) return;
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part[(long long)k * npar + i];
+    grad[i] += (float)s;
+}
+
+// MSE: grad = 2 (out - target) / count, per-block partial sums of the squared error.
+__global__ __launch_bounds__(256) void k_mse(const float* out, const float* tgt, long long count, float* grad,
+                                             double* part) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    const float scale = 2.0f / (float)count;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float d = out[i] - tgt[i];
+        grad[i] = scale * d;
+        s += (double)d * d;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Adam (Kingma and Ba) on the FP32 master parameters.
+__global__ void k_adam(float* th, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 copies of one convolution's weights: forward [cout_p][kp] with k = tap * cin_p + c,
+// and input-gradient [cin_p][kpd] with k = tap * cout_p + o holding W[26 - tap][c][o].
+__global__ void k_pack(const float* W, int cin, int cout, int taps, int cin_p, int cout_p, int kp, int kpd,
+                       uint16_t* wf, uint16_t* wd) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nf = (long long)cout_p * kp, nd = (long long)cin_p * kpd;
+    if (i < nf) {
+        const int o = (int)(i / kp), k = (int)(i % kp);
+        const int tap = k / cin_p, c = k % cin_p;
+        float v = 0.f;
+        if (o < cout && tap < taps && c < cin) v = W[((long long)tap * cin + c) * cout + o];
+        wf[i] = f2bf(v);
+    } else if (i < nf + nd && wd) {
+        const long long j = i - nf;
+        const int c = (int)(j / kpd), k = (int)(j % kpd);
+        const int tap = k / cout_p, o = k % cout_p;
+        float v = 0.f;
+        if (c < cin && tap < taps && o < cout) v = W[((long long)(taps - 1 - tap) * cin + c) * cout + o];
+        wd[j] = f2bf(v);
+    }
+}
+
+// Copy an input with 'c' channels into a zero-padded buffer with 'cp' channels.
+__global__ void k_pad_channels(const uint16_t* x, int c, int cp, long long P, uint16_t* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * cp) return;
+    const int ch = (int)(i % cp);
+    y[i] = ch < c ? x[(i / cp) * c + ch] : (uint16_t)0;
+}
+
+}  // namespace mpm

@@ -87,6 +87,27 @@ def lib() -> ctypes.CDLL:
             "mpm_debug_apply": [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32],
             "mpm_time_kernel": [_vp, ctypes.c_int32, ctypes.c_int32],
             "mpm_tile": [_vp, _i32p],
+            "mpm_net_create": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                               _i32p, ctypes.c_uint64, _vp],
+            "mpm_net_params": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                               ctypes.POINTER(ctypes.c_int64)],
+            "mpm_net_sync_weights": [_vp],
+            "mpm_net_read": [_vp, ctypes.c_int32, _vp],
+            "mpm_net_write": [_vp, ctypes.c_int32, _vp],
+            "mpm_net_forward": [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, _vp],
+            "mpm_net_backward": [_vp, _vp],
+            "mpm_net_zero_grad": [_vp],
+            "mpm_net_mse": [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_double)],
+            "mpm_net_adam_step": [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_int32],
+            "mpm_net_destroy": [_vp],
+            "mpm_net_debug_layer": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp],
+            "mpm_attach_net": [_vp, _vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+            "mpm_ws_pair": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_float),
+                            ctypes.POINTER(ctypes.c_float), _vp, _vp],
+            "mpm_ws_grid": [_vp, ctypes.c_int32, _i32p],
             "mpm_kernel_timing": [_vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
         }
@@ -245,6 +266,158 @@ def mpm_tile(ctx) -> int:
     return v.value
 
 
+def mpm_net_create(in_ch: int, out_ch: int, widths, seed: int = 0, stream=None):
+    net = ctypes.c_void_p()
+    w = (ctypes.c_int32 * len(widths))(*[int(v) for v in widths])
+    _check(lib().mpm_net_create(ctypes.byref(net), int(in_ch), int(out_ch), len(widths), w,
+                                int(seed), _stream(stream)))
+    return net
+
+
+def mpm_net_param_count(net) -> int:
+    p = ctypes.c_void_p()
+    g = ctypes.c_void_p()
+    n = ctypes.c_int64()
+    _check(lib().mpm_net_params(net, ctypes.byref(p), ctypes.byref(g), ctypes.byref(n)))
+    return n.value
+
+
+def mpm_net_read(net, what: int, dst) -> None:
+    import torch
+    _check(lib().mpm_net_read(net, int(what), _dev_ptr(dst, torch.float32, "dst")))
+
+
+def mpm_net_write(net, what: int, src) -> None:
+    import torch
+    _check(lib().mpm_net_write(net, int(what), _dev_ptr(src, torch.float32, "src")))
+
+
+def mpm_net_forward(net, x, out) -> None:
+    """x: BF16 data as int16/uint16 tensor [n][d][h][w][c]; out: FP32 [n][d][h][w][out_ch]."""
+    import torch
+    if x.dtype not in (torch.int16, torch.uint16, torch.bfloat16):
+        raise TypeError("x must hold BF16 bit patterns (int16/uint16/bfloat16)")
+    if x.dim() != 5 or not x.is_contiguous() or x.device.type != "cuda":
+        raise ValueError("x must be a contiguous 5-D GPU tensor")
+    nb, d, h, w, _ = x.shape
+    _check(lib().mpm_net_forward(net, ctypes.c_void_p(x.data_ptr()), nb, d, h, w,
+                                 _dev_ptr(out, torch.float32, "out")))
+
+
+def mpm_net_backward(net, grad_out) -> None:
+    import torch
+    _check(lib().mpm_net_backward(net, _dev_ptr(grad_out, torch.float32, "grad_out")))
+
+
+def mpm_net_zero_grad(net) -> None:
+    _check(lib().mpm_net_zero_grad(net))
+
+
+def mpm_net_mse(net, out, target, grad_out) -> float:
+    import torch
+    loss = ctypes.c_double()
+    _check(lib().mpm_net_mse(net, _dev_ptr(out, torch.float32, "out"),
+                             _dev_ptr(target, torch.float32, "target"), out.numel(),
+                             _dev_ptr(grad_out, torch.float32, "grad_out"), ctypes.byref(loss)))
+    return loss.value
+
+
+def mpm_net_adam_step(net, lr, b1=0.9, b2=0.999, eps=1e-8, t=1) -> None:
+    _check(lib().mpm_net_adam_step(net, float(lr), float(b1), float(b2), float(eps), int(t)))
+
+
+def mpm_net_destroy(net) -> None:
+    if net is not None and net.value:
+        lib().mpm_net_destroy(net)
+
+
+def _floats(v):
+    return (ctypes.c_float * len(v))(*[float(a) for a in v])
+
+
+def mpm_attach_net(ctx, net, in_scale, out_scale) -> None:
+    h = net.handle if isinstance(net, Net) else net
+    _check(lib().mpm_attach_net(ctx, h, _floats(in_scale), _floats(out_scale)))
+
+
+def mpm_ws_grid(ctx, problem: int = 0):
+    g = (ctypes.c_int32 * 3)()
+    _check(lib().mpm_ws_grid(ctx, int(problem), g))
+    return tuple(g)
+
+
+def mpm_ws_pair(ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target) -> None:
+    import torch
+    if in_bf16.dtype not in (torch.int16, torch.uint16, torch.bfloat16) or not in_bf16.is_contiguous():
+        raise TypeError("in_bf16 must be a contiguous 16-bit tensor")
+    _check(lib().mpm_ws_pair(ctx, int(problem), _dev_ptr(c_old, torch.float64, "c_old"),
+                             _dev_ptr(c_new, torch.float64, "c_new"), _floats(in_scale),
+                             _floats(out_scale), ctypes.c_void_p(in_bf16.data_ptr()),
+                             _dev_ptr(target, torch.float32, "target")))
+
+
+class Net:
+    """Owns one U-Net handle (convenience wrapper over the mpm_net_* functions)."""
+
+    def __init__(self, in_ch=13, out_ch=3, widths=(16, 32, 64, 64), seed=0, stream=None):
+        self.handle = mpm_net_create(in_ch, out_ch, widths, seed, stream)
+        self.in_ch, self.out_ch, self.widths = in_ch, out_ch, tuple(widths)
+        self.count = mpm_net_param_count(self.handle)
+
+    def params(self):
+        import torch
+        t = torch.empty(self.count, dtype=torch.float32, device="cuda")
+        mpm_net_read(self.handle, 0, t)
+        return t
+
+    def grads(self):
+        import torch
+        t = torch.empty(self.count, dtype=torch.float32, device="cuda")
+        mpm_net_read(self.handle, 1, t)
+        return t
+
+    def set_params(self, t):
+        mpm_net_write(self.handle, 0, t.contiguous())
+
+    def set_grads(self, t):
+        mpm_net_write(self.handle, 1, t.contiguous())
+
+    def forward(self, x, out):
+        mpm_net_forward(self.handle, x, out)
+
+    def backward(self, grad_out):
+        mpm_net_backward(self.handle, grad_out)
+
+    def zero_grad(self):
+        mpm_net_zero_grad(self.handle)
+
+    def mse(self, out, target, grad_out):
+        return mpm_net_mse(self.handle, out, target, grad_out)
+
+    def adam(self, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+        mpm_net_adam_step(self.handle, lr, b1, b2, eps, t)
+
+    def debug_layer(self, layer, mode, x, g, gate, out):
+        """One 3x3x3 layer on caller tensors (see mpm_net_debug_layer); x, g, gate hold
+        BF16 bit patterns (16-bit tensors, NDHWC) or None."""
+        ref = x if x is not None else g
+        nb, d, h, w = ref.shape[:4]
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        _check(lib().mpm_net_debug_layer(self.handle, int(layer), int(mode), nb, d, h, w, ptr(x), ptr(g),
+                                         ptr(gate), ctypes.c_void_p(out.data_ptr())))
+
+    def close(self):
+        mpm_net_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None:
+                self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """Owns one context; a convenience wrapper over the functions above."""
 
@@ -271,6 +444,15 @@ class Solver:
 
     def kernel_timing(self):
         return mpm_kernel_timing(self.ctx)
+
+    def attach(self, net, in_scale, out_scale):
+        mpm_attach_net(self.ctx, net, in_scale, out_scale)
+
+    def ws_grid(self, problem=0):
+        return mpm_ws_grid(self.ctx, problem)
+
+    def ws_pair(self, problem, c_old, c_new, in_scale, out_scale, in_bf16, target):
+        mpm_ws_pair(self.ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target)
 
     def apply(self, problem, x, y, mode):
         return mpm_debug_apply(self.ctx, problem, x, y, mode)

@@ -249,12 +249,12 @@ def config4_patch(seed: int, n: int = 64) -> Problem:
     """One training/evaluation geometry for the learned warm start.
 
     n^3 box, all voxels active.  The tumour is a random ellipsoid (semi-axes
-    U(6, 20), centre uniform with the ellipsoid inside the box) split into
+    U(6, 20) * n / 64, centre uniform with the ellipsoid inside the box) split into
     Voronoi cells of U{20..200} seeds.  Coefficients are the tumour-workload ones,
     each per-species coefficient scaled by U(0.5, 1.5) per patch.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
-    semi = rng.uniform(6.0, 20.0, size=3)
+    semi = rng.uniform(6.0, 20.0, size=3) * (n / 64.0)
     lo = semi + 1.0
     hi = n - semi - 1.0
     centre = rng.uniform(lo, hi)
