@@ -46,7 +46,28 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the CPU oracle sample (0 = skip)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device once (calibrates HBM counters)")
     return ap.parse_args()
+
+
+def alg_bytes_active(kind, j, U, precision, S):
+    """Algorithmic bytes of one launch in which every system is active."""
+    t = 4 if precision else 8
+    per = {1: t * (j + 5) + 16.0 / S, 2: t * (j + 3), 3: t * (j + 3), 4: None, 5: 56 + t + 16.0 / S}[kind]
+    return per * U if per is not None else 0
+
+
+def measured_traffic(kernel, workload, tile):
+    """HBM bytes per active launch from the committed rocprofv3 counter summary of this
+    kernel and workload (None if there is none for it)."""
+    path = os.path.join(ROOT, "profiles", "k_axpy_dot_config2_traffic.md")
+    if kernel != "k_axpy_dot<float,10>" or workload != "config2" or tile or not os.path.exists(path):
+        return None
+    for line in open(path):
+        if "traffic_bytes_per_active_launch:" in line:
+            return int(line.split("traffic_bytes_per_active_launch:")[1].split("*")[0].strip().rstrip("."))
+    return None
 
 
 def make_workload(name):
@@ -123,6 +144,16 @@ def main():
     import numpy as np
     import torch
 
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}))
+        return 0
+
     import paper_2505_03067_amd as m
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -190,17 +221,19 @@ def main():
     if timing and timing["launches"]:
         avg_ms = timing["ms"] / timing["launches"]
         achieved = timing["bytes"] / (timing["ms"] * 1e-3) / 1e9
+        kernel = f"{KERNEL_NAMES[KERNELS[kname]]}<{'float' if precision else 'double'},{kj}>"
         out["roofline"] = {
             "bound": "hbm",
-            "kernel": f"{KERNEL_NAMES[KERNELS[kname]]}<{'float' if precision else 'double'},{kj}>",
+            "kernel": kernel,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(kernel, args.workload, args.tile),
             "avg_launch_us": round(1000.0 * avg_ms, 3),
             "launches": timing["launches"],
             "alg_bytes_per_launch": round(timing["bytes"] / timing["launches"]),
+            "alg_bytes_per_active_launch": round(alg_bytes_active(KERNELS[kname], kj, U, precision, prob.nspecies)),
         }
 
     if not args.no_plain and precision == m.MPM_FP32_IR:

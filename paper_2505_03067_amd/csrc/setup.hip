@@ -145,6 +145,7 @@ struct CoefArgs {
     double dt, inv_h2;
     double cb[MPM_MAX_SPECIES];
     int N, Npad, S;
+    int* bad;         // set to 1 if a domain voxel has D < 0, k < 0 or a non-finite value
 };
 
 __device__ inline double harm(double a, double b) {
@@ -181,6 +182,10 @@ __global__ __launch_bounds__(256) void k_coefs(CoefArgs a) {
     const long long ls[3] = {1, g.nx, (long long)plane};
     const double* Ds = a.D + (long long)s * a.nvox;
     const double DP = Ds[v];
+    {
+        const double kv = a.k[(long long)s * a.nvox + v], sv = a.src[(long long)s * a.nvox + v];
+        if (!(DP >= 0.0) || !(kv >= 0.0) || isinf(DP) || isinf(kv) || !isfinite(sv)) *a.bad = 1;
+    }
     double sumG = 0.0, dir = 0.0;
     double up[3];
     for (int d = 0; d < 3; ++d) {
@@ -394,6 +399,12 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     ca.inv_h2 = 1.0 / (h * h);
     for (int s = 0; s < MPM_MAX_SPECIES; ++s) ca.cb[s] = s < c->S ? cb[s] : 0.0;
     ca.N = N; ca.Npad = Npad; ca.S = c->S;
+    ca.bad = total_d;   // reused as the error flag (the count was read already)
+    e = hipMemsetAsync(total_d, 0, sizeof(int), st);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "mpm_fv_setup (flag)");
+    }
     const long long tot = (long long)c->S * Npad;
     k_coefs<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ca);
     k_scaled<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ph.a64, ph.sc64, ph.nbr, N, Npad, c->S, ph.c64,
@@ -425,10 +436,18 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
         k_ws_static<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(mask, D, k, src, g, gx, gy, gz, c->S, ca.nvox,
                                                               ph.stat);
     }
+    int bad_h = 0;
     e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad_h, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     cleanup();
     if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (coefficients)");
+    if (bad_h) {
+        ph.ready = false;
+        c->layout_dirty = true;
+        set_error("mpm_fv_setup: negative or non-finite D, k or s on a domain voxel");
+        return MPM_EINVAL;
+    }
 
     const bool grew = Npad != ph.Npad;
     ph.N = N;

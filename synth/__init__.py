@@ -25,4 +25,5 @@ from .geometry import (  # noqa: F401
     dilate6,
     fourier_box,
     random_problem,
+    tumour_coefficients,
 )

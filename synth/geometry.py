@@ -323,3 +323,22 @@ def random_problem(seed: int, dims: Vec3, S: int = 3, fill: float = 0.6,
         box = ((0, 0, 0), dims)
     return Problem(f"random-{seed}", dims, mask, cell, D, k, src, c0, cb, dt=dt, h=h,
                    box=box)
+
+
+def tumour_coefficients(tumour: np.ndarray, jitter: np.ndarray):
+    """D, k, s of the three lung species for a given tumour region (tumour workloads).
+
+    D halves inside the tumour; k (uptake on tumour voxels, decay everywhere) is
+    multiplied on tumour voxels by ``jitter[s]`` (an array drawn once per lattice, so
+    that a growing tumour keeps the same factors where it already was).
+    """
+    S = 3
+    shape = (S,) + tumour.shape
+    D = np.empty(shape)
+    k = np.empty(shape)
+    s = np.zeros(shape)
+    for sp in range(S):
+        D[sp] = np.where(tumour, 0.5 * LUNG_D[sp], LUNG_D[sp])
+        k[sp] = np.where(tumour, (LUNG_K_CELL[sp] + LUNG_K_ALL[sp]) * jitter[sp], LUNG_K_ALL[sp])
+        s[sp] = np.where(tumour, LUNG_S_CELL[sp], 0.0)
+    return D, k, s

@@ -1,0 +1,65 @@
+"""Growing tumours with a moving bounding box (the paper's box tracking, Sec. 2.3):
+several problems of uneven size in one context, the box recomputed on the GPU from
+the cell lattice after each growth step, the problems re-set up, and the fields
+carried across box changes on the lattice.  Checked against the oracle running the
+same sequence."""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import require_gpu
+from oracle.bbox import bbox_from_cells
+from oracle.fv import box_slice
+from oracle.step import implicit_step
+from synth import dilate6, tumour_coefficients
+from synth.geometry import _inside_ellipsoid
+
+pytestmark = pytest.mark.gpu
+
+
+def _tumour(dims, semi):
+    mid = tuple(d / 2 for d in dims)
+    return _inside_ellipsoid(dims, mid, semi)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_growing_tumours_track_box(precision):
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    lattices = [(36, 34, 30), (28, 30, 26)]
+    semis = [(6, 5, 4), (3, 4, 3)]
+    rngs = [np.random.default_rng(10 + i) for i in range(2)]
+    tumours = [_tumour(d, s) for d, s in zip(lattices, semis)]
+    jit = [r.uniform(0.8, 1.2, size=(3,) + t.shape) for r, t in zip(rngs, tumours)]
+    cb = np.array([1.0, 1.0, 0.0])
+    fields_h = [np.broadcast_to(cb[:, None, None, None], (3,) + t.shape).copy() for t in tumours]
+    fields_d = [torch.from_numpy(f).cuda() for f in fields_h]
+    masks = [np.ones(t.shape, np.uint8) for t in tumours]
+    boxes_seen = []
+    with m.Solver(3, 2, precision=precision) as s:
+        for step in range(9):
+            if step % 3 == 0:
+                if step > 0:
+                    tumours = [dilate6(t) for t in tumours]
+                for p in range(2):
+                    cell = tumours[p].astype(np.int32)
+                    box = m.mpm_bbox_from_cells(torch.from_numpy(cell).cuda(), 4)
+                    assert box == bbox_from_cells(cell, 4)
+                    D, k, src = tumour_coefficients(tumours[p], jit[p])
+                    s.setup(p, box, torch.from_numpy(masks[p]).cuda(), torch.from_numpy(D).cuda(),
+                            torch.from_numpy(k).cuda(), torch.from_numpy(src).cuda(), cb, 1.0, 1.0)
+                    boxes_seen.append((p, box))
+            s.step(fields_d, 1e-12)
+            for p in range(2):
+                D, k, src = tumour_coefficients(tumours[p], jit[p])
+                box = bbox_from_cells(tumours[p].astype(np.int32), 4)
+                fields_h[p], _ = implicit_step(fields_h[p], masks[p], D, k, src, cb, box, 1.0, 1.0,
+                                               solver="pcg", tol=1e-13)
+    # the boxes grew with the tumours
+    assert boxes_seen[0][1] != boxes_seen[-2][1]
+    for p in range(2):
+        got = fields_d[p].cpu().numpy()
+        want = fields_h[p]
+        for sp in range(3):
+            err = np.linalg.norm(got[sp] - want[sp]) / np.linalg.norm(want[sp])
+            assert err <= 1e-8, (p, sp, err)

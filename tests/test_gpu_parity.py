@@ -207,6 +207,13 @@ def test_error_paths():
         with pytest.raises(MpmError) as e:
             s.setup(0, ((0, 0, 0), (13, 11, 10)), d["mask"], d["D"], d["k"], d["src"], p.c_b, 1, 1)
         assert e.value.code == MPM_EINVAL
+        negD = d["D"].clone()
+        negD[1, 3, 4, 5] = -0.5
+        mask1 = d["mask"].clone()
+        mask1[3, 4, 5] = 1
+        with pytest.raises(MpmError) as e:
+            s.setup(0, p.box, mask1, negD, d["k"], d["src"], p.c_b, 1.0, 1.0)
+        assert e.value.code == MPM_EINVAL
         empty = torch.zeros_like(d["mask"])
         with pytest.raises(MpmError) as e:
             s.setup(0, p.box, empty, d["D"], d["k"], d["src"], p.c_b, 1.0, 1.0)
