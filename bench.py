@@ -28,6 +28,8 @@ HBM_PEAK_GBS = 8000.0
 KERNELS = {"spmv_dot": 1, "axpy_dot": 2, "axpy_norm": 3, "update": 4, "residual": 5}
 KERNEL_NAMES = {1: "k_spmv_dot", 2: "k_axpy_dot", 3: "k_axpy_norm", 4: "k_update",
                 5: "k_residual"}
+# delayed Gram-Schmidt: stencil + multi-dot, and the axpy that finishes q_j and forms u_{j+1}
+KERNEL_NAMES_DCGS2 = {1: "k_dc_spmv_dot", 2: "k_dc_axpy", 4: "k_update", 5: "k_residual"}
 
 
 def parse():
@@ -41,8 +43,16 @@ def parse():
     ap.add_argument("--unbatched", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="unknowns per block (0 = library default)")
     ap.add_argument("--tol", type=float, default=None)
-    ap.add_argument("--time-kernel", default="axpy_dot:10",
-                    help="kernel:j timed with HIP events for the roofline ('none' to skip)")
+    ap.add_argument("--ortho", default="dcgs2", choices=["dcgs2", "cgs2"],
+                    help="Gram-Schmidt variant of the Arnoldi process")
+    ap.add_argument("--time-kernel", default=None,
+                    help="kernel:j timed with HIP events for the roofline ('none' to skip; default "
+                         "spmv_dot:10 under dcgs2, axpy_dot:10 under cgs2)")
+    ap.add_argument("--repeat", type=int, default=None,
+                    help="back-to-back launches per timed event pair (default 10 for the delayed "
+                         "scheme's stencil kernel, else 1)")
+    ap.add_argument("--roofline-steps", type=int, default=10,
+                    help="implicit steps of the roofline phase (after the headline timing)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the CPU oracle sample (0 = skip)")
@@ -51,10 +61,11 @@ def parse():
     return ap.parse_args()
 
 
-def alg_bytes_active(kind, j, U, precision, S):
+def alg_bytes_active(kind, j, U, precision, S, dcgs2):
     """Algorithmic bytes of one launch in which every system is active."""
     t = 4 if precision else 8
-    per = {1: t * (j + 5) + 16.0 / S, 2: t * (j + 3), 3: t * (j + 3), 4: None, 5: 56 + t + 16.0 / S}[kind]
+    axpy = (3 * t if j == 0 else t * (j + 4)) if dcgs2 else t * (j + 3)
+    per = {1: t * (j + 5) + 16.0 / S, 2: axpy, 3: t * (j + 3), 4: None, 5: 56 + t + 16.0 / S}[kind]
     return per * U if per is not None else 0
 
 
@@ -84,9 +95,9 @@ def upload(prob, torch):
     return {k: torch.from_numpy(getattr(prob, k)).to(dev) for k in ("mask", "D", "k", "src", "cell_id")}
 
 
-def gpu_solver(m, prob, t, box, precision, graph, batched, tile=0):
+def gpu_solver(m, prob, t, box, precision, graph, batched, tile=0, ortho=1):
     s = m.Solver(prob.nspecies, 1, precision=precision, use_graph=int(graph), batched=int(batched),
-                 tile_override=int(tile))
+                 tile_override=int(tile), ortho=int(ortho))
     s.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
     return s
 
@@ -166,24 +177,34 @@ def main():
     else:
         box = m.mpm_bbox_from_cells(t["cell_id"], prob.margin)
     precision = m.MPM_FP32_IR if args.precision == "fp32ir" else m.MPM_FP64
+    ortho = m.MPM_ORTHO_DCGS2 if args.ortho == "dcgs2" else m.MPM_ORTHO_CGS2
     f = torch.from_numpy(prob.c0).cuda()
 
-    s = gpu_solver(m, prob, t, box, precision, not args.no_graph, not args.unbatched, args.tile)
+    s = gpu_solver(m, prob, t, box, precision, not args.no_graph, not args.unbatched, args.tile, ortho)
     run_steps(s, f, args.warmup, tol, torch)
     c_start = f.clone()
-    kname, kj = None, 0
-    if args.time_kernel != "none":
-        kname, _, kj = args.time_kernel.partition(":")
-        kj = int(kj or 0)
-        s.time_kernel(KERNELS[kname], kj)
+    # headline: K implicit steps from graphs, nothing else on the stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     its = run_steps(s, f, args.steps, tol, torch)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    timing = s.kernel_timing() if kname else None
     tile_used = s.tile()
     final_stats = [s.stats(0, sp) for sp in range(prob.nspecies)]
+    # roofline phase: the same solver continues for a few steps with one kernel timed by
+    # HIP events on the library's stream (the cycle is then launched directly)
+    dc = ortho == m.MPM_ORTHO_DCGS2
+    time_kernel = args.time_kernel or ("spmv_dot:10" if dc else "axpy_dot:10")
+    kname, kj, timing, repeat = None, 0, None, 1
+    if time_kernel != "none" and args.roofline_steps > 0:
+        kname, _, kj = time_kernel.partition(":")
+        kj = int(kj or 0)
+        pure = KERNELS[kname] == 5 or (KERNELS[kname] == 1 and dc)
+        repeat = args.repeat if args.repeat is not None else (10 if pure else 1)
+        s.time_kernel(KERNELS[kname], kj, repeat)
+        run_steps(s, f, args.roofline_steps, tol, torch)
+        timing = s.kernel_timing()
+        s.time_kernel(0)
     s.close()
 
     N = int(prob.mask[box[0][2]:box[1][2], box[0][1]:box[1][1], box[0][0]:box[1][0]].sum())
@@ -207,6 +228,7 @@ def main():
             "workload": f"{prob.name}: lattice {prob.dims}, box {box}, {N} domain voxels, "
                         f"{prob.nspecies} species, {U} unknowns, tol {tol:g}, "
                         f"{'FP32 GMRES(30) in FP64 refinement' if precision else 'FP64 GMRES(30)'}, "
+                        f"{'delayed CGS2' if ortho == m.MPM_ORTHO_DCGS2 else 'CGS2'} Arnoldi, "
                         f"{'batched' if not args.unbatched else 'one system at a time'}, "
                         f"{'hipGraph cycles' if not args.no_graph else 'direct launches'}",
             "unknowns": U,
@@ -221,7 +243,8 @@ def main():
     if timing and timing["launches"]:
         avg_ms = timing["ms"] / timing["launches"]
         achieved = timing["bytes"] / (timing["ms"] * 1e-3) / 1e9
-        kernel = f"{KERNEL_NAMES[KERNELS[kname]]}<{'float' if precision else 'double'},{kj}>"
+        names = KERNEL_NAMES_DCGS2 if dc else KERNEL_NAMES
+        kernel = f"{names[KERNELS[kname]]}<{'float' if precision else 'double'},{kj}>"
         out["roofline"] = {
             "bound": "hbm",
             "kernel": kernel,
@@ -232,13 +255,16 @@ def main():
             "traffic": measured_traffic(kernel, args.workload, args.tile),
             "avg_launch_us": round(1000.0 * avg_ms, 3),
             "launches": timing["launches"],
+            "launches_per_event_pair": repeat,
+            "phase": f"{args.roofline_steps} steps after the headline timing, cycle launched directly",
             "alg_bytes_per_launch": round(timing["bytes"] / timing["launches"]),
-            "alg_bytes_per_active_launch": round(alg_bytes_active(KERNELS[kname], kj, U, precision, prob.nspecies)),
+            "alg_bytes_per_active_launch": round(alg_bytes_active(KERNELS[kname], kj, U, precision, prob.nspecies,
+                                                                  dc)),
         }
 
     if not args.no_plain and precision == m.MPM_FP32_IR:
         f2 = c_start.clone()
-        s2 = gpu_solver(m, prob, t, box, m.MPM_FP64, not args.no_graph, not args.unbatched, args.tile)
+        s2 = gpu_solver(m, prob, t, box, m.MPM_FP64, not args.no_graph, not args.unbatched, args.tile, ortho)
         run_steps(s2, f2, 2, tol, torch)
         f2.copy_(c_start)
         torch.cuda.synchronize()
@@ -253,7 +279,7 @@ def main():
 
     if args.cpu_seconds > 0:
         # replay the first steps of the timed run on the GPU (deterministic) to compare
-        s3 = gpu_solver(m, prob, t, box, precision, not args.no_graph, not args.unbatched, args.tile)
+        s3 = gpu_solver(m, prob, t, box, precision, not args.no_graph, not args.unbatched, args.tile, ortho)
         f3 = c_start.clone()
         after = []
         for _ in range(min(args.steps, 8)):

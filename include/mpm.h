@@ -60,6 +60,10 @@ extern "C" {
 #define MPM_WS_NET 1    /* learned warm start from the attached network, fallback c^n */
 #define MPM_WS_EXTRAP 2 /* linear extrapolation 2 c^n - c^{n-1}, fallback c^n */
 
+/* orthogonalisation of the Arnoldi basis */
+#define MPM_ORTHO_CGS2 0
+#define MPM_ORTHO_DCGS2 1
+
 #define MPM_MAX_SPECIES 4
 #define MPM_MAX_RESTART 30
 
@@ -74,7 +78,9 @@ typedef struct {
     int32_t use_graph;   /* 1: replay each GMRES cycle from a captured hipGraph */
     int32_t warm_start;  /* MPM_WS_NONE, MPM_WS_NET or MPM_WS_EXTRAP */
     int32_t tile_override; /* 0: autotuned work split; >0: unknowns per block (multiple of 1024) */
-    int32_t reserved;
+    int32_t ortho;       /* MPM_ORTHO_DCGS2 (default): classical Gram-Schmidt with delayed
+                            reorthogonalisation, one global reduction and two passes per step;
+                            MPM_ORTHO_CGS2: reorthogonalised classical Gram-Schmidt, three */
     double inner_rtol;   /* smallest residual reduction asked of one FP32 cycle (default 1e-6) */
 } mpm_options;
 
@@ -142,25 +148,32 @@ const char* mpm_last_error(void);
 
 /* Measurement hook: time every launch of one kernel of the GMRES cycle with HIP
  * events recorded on the context's own stream (the stream the kernels run on).
- * kind: MPM_KERNEL_NONE (off), MPM_KERNEL_SPMV_DOT (stencil + first Gram-Schmidt
- * pass), MPM_KERNEL_AXPY_DOT (second pass), MPM_KERNEL_AXPY_NORM (third pass +
- * Givens), MPM_KERNEL_UPDATE (x += S V y), MPM_KERNEL_RESIDUAL (FP64 r = b - A x);
- * j: Arnoldi step of kinds 1-3, ignored otherwise.  Selecting resets the counters
- * read by mpm_kernel_timing and re-captures the cycle graph. */
+ * kind: MPM_KERNEL_NONE (off), MPM_KERNEL_SPMV_DOT (stencil + multi-dot: the first
+ * Gram-Schmidt pass, or all dot products of the delayed scheme), MPM_KERNEL_AXPY_DOT
+ * (second pass; the delayed scheme's axpy kernel), MPM_KERNEL_AXPY_NORM (third pass;
+ * CGS2 only, MPM_EINVAL under MPM_ORTHO_DCGS2), MPM_KERNEL_UPDATE (x += S V y),
+ * MPM_KERNEL_RESIDUAL (FP64 r = b - A x); j: Arnoldi step of kinds 1-3, ignored
+ * otherwise.  repeat >= 1: each timed launch is issued 'repeat' times back to back
+ * between its two events (amortises the event overhead); repeat > 1 is accepted only
+ * for launches whose output depends on their inputs alone (the delayed scheme's
+ * stencil + multi-dot kernel, and the residual kernel), else MPM_EINVAL.  While a
+ * kernel is timed the cycle is launched directly instead of from graphs.  Selecting
+ * resets the counters read by mpm_kernel_timing. */
 #define MPM_KERNEL_NONE 0
 #define MPM_KERNEL_SPMV_DOT 1
 #define MPM_KERNEL_AXPY_DOT 2
 #define MPM_KERNEL_AXPY_NORM 3
 #define MPM_KERNEL_UPDATE 4
 #define MPM_KERNEL_RESIDUAL 5
-int32_t mpm_time_kernel(mpm_ctx ctx, int32_t kind, int32_t j);
+int32_t mpm_time_kernel(mpm_ctx ctx, int32_t kind, int32_t j, int32_t repeat);
 
-/* Totals since mpm_time_kernel: summed event time in ms, number of launches, and
- * the algorithmic bytes those launches had to move for the systems that were
- * active (domain unknowns only, padding excluded; counted per unknown as
- * K1: t (j + 5) + 16 / S, K2 and K3: t (j + 3), update: t m + 24,
- * residual: 56 + t + 16 / S, with t = 4 (MPM_FP32_IR) or 8 (MPM_FP64) bytes).
- * All outputs are host pointers. */
+/* Totals since mpm_time_kernel: summed event time in ms, number of launches (each
+ * repeat counts), and the algorithmic bytes those launches had to move for the
+ * systems that were active (domain unknowns only, padding excluded; counted per
+ * unknown as stencil + multi-dot: t (j + 5) + 16 / S, CGS2 passes 2 and 3: t (j + 3),
+ * delayed-scheme axpy: 3 t (j = 0) or t (j + 4), update: t m + 24, residual:
+ * 56 + t + 16 / S, with t = 4 (MPM_FP32_IR) or 8 (MPM_FP64) bytes).  All outputs
+ * are host pointers. */
 int32_t mpm_kernel_timing(mpm_ctx ctx, double* ms, int64_t* launches, double* bytes);
 
 /* Unknowns per block of the current work split (after autotuning, if any); *out is a

@@ -12,4 +12,5 @@ from .mpm import (  # noqa: F401
     mpm_default_options, mpm_destroy, mpm_fv_setup, mpm_gmres_stats, mpm_implicit_step,
     mpm_last_error, mpm_tile, mpm_time_kernel, mpm_kernel_timing, MPM_KERNEL_NONE, MPM_KERNEL_SPMV_DOT,
     MPM_KERNEL_AXPY_DOT, MPM_KERNEL_AXPY_NORM, MPM_KERNEL_UPDATE, MPM_KERNEL_RESIDUAL,
+    MPM_ORTHO_CGS2, MPM_ORTHO_DCGS2,
 )

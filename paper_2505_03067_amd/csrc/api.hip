@@ -21,8 +21,8 @@ static void destroy_ctx(Ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& ph : c->probs) free_problem(ph);
-    for (auto g : c->graphs)
-        if (g) (void)hipGraphExecDestroy(g);
+    for (auto& kv : c->graphs)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
     (void)hipFree(c->d_probs);
     (void)hipFree(c->d_sk);
     (void)hipFree(c->d_part);
@@ -80,6 +80,7 @@ extern "C" int32_t mpm_default_options(mpm_options* opt) {
     opt->warm_start = MPM_WS_NONE;
     opt->tile_override = 0;
     opt->inner_rtol = 1e-6;
+    opt->ortho = MPM_ORTHO_DCGS2;
     return MPM_OK;
 }
 
@@ -100,6 +101,7 @@ extern "C" int32_t mpm_create(mpm_ctx* out, int32_t nspecies, int32_t nproblems,
     if (o.restart < 1 || o.restart > MPM_MAX_RESTART || o.max_cycles < 1 ||
         (o.precision != MPM_FP64 && o.precision != MPM_FP32_IR) || !(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0) ||
         o.warm_start < MPM_WS_NONE || o.warm_start > MPM_WS_EXTRAP || o.tile_override < 0 ||
+        (o.ortho != MPM_ORTHO_CGS2 && o.ortho != MPM_ORTHO_DCGS2) ||
         (o.tile_override % kAlign) != 0) {
         set_error("mpm_create: invalid options");
         return MPM_EINVAL;
@@ -241,13 +243,23 @@ extern "C" int32_t mpm_debug_apply(mpm_ctx ctx, int32_t problem, const double* x
     return rc;
 }
 
-extern "C" int32_t mpm_time_kernel(mpm_ctx ctx, int32_t kind, int32_t j) {
+extern "C" int32_t mpm_time_kernel(mpm_ctx ctx, int32_t kind, int32_t j, int32_t repeat) {
     Ctx* c = (Ctx*)ctx;
-    if (!c || kind < MPM_KERNEL_NONE || kind > MPM_KERNEL_RESIDUAL || j < 0 || j >= c->opt.restart) {
+    if (!c || kind < MPM_KERNEL_NONE || kind > MPM_KERNEL_RESIDUAL || j < 0 || j >= c->opt.restart ||
+        repeat < 1 || repeat > 64) {
         set_error("mpm_time_kernel: bad arguments");
         return MPM_EINVAL;
     }
-    return select_timing(c, kind, j);
+    if (kind == MPM_KERNEL_AXPY_NORM && c->opt.ortho == MPM_ORTHO_DCGS2) {
+        set_error("mpm_time_kernel: the delayed Gram-Schmidt cycle has no axpy+norm kernel");
+        return MPM_EINVAL;
+    }
+    const bool pure = kind == MPM_KERNEL_RESIDUAL || (kind == MPM_KERNEL_SPMV_DOT && c->opt.ortho == MPM_ORTHO_DCGS2);
+    if (repeat > 1 && !pure) {
+        set_error("mpm_time_kernel: repeat > 1 needs a kernel whose output depends on its inputs alone");
+        return MPM_EINVAL;
+    }
+    return select_timing(c, kind, j, repeat);
 }
 
 extern "C" int32_t mpm_kernel_timing(mpm_ctx ctx, double* ms, int64_t* launches, double* bytes) {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <string>
@@ -46,17 +47,36 @@ struct ProbDev {
     const double* prev;    // c^{n-1} on the global unknowns (or null)
 };
 
-// One block of work: a contiguous range of one system's unknowns (global indices).
+// One block of work: a contiguous range of one system's unknowns (global indices),
+// with what its kernels need to know about the system up front, so that a block
+// reaches its data in one dependent load.
 struct Block {
     int sys;     // system id = problem * S + species, -1 for an idle block
     int start;   // global unknown index, multiple of kAlign (relative to kLead)
     int end;
     int slot;    // partial-sum slot of this block
+    int slot0;   // first partial-sum slot of the system
+    int nb;      // blocks (slots) of the system
+    int N;       // domain voxels of the problem
+    int tot;     // S * Npad: plane stride of the problem's coupling arrays
+    long long base;      // global index of l = 0 of this system
+    long long locbase;   // problem-local index of l = 0 (species * Npad)
+    const int4* nbr;     // the problem's neighbour table
+    const void* c;       // the problem's scaled couplings in the Krylov type
 };
 
 // Per-system Krylov state.  Within one launch every block reads it and only the
-// system's first block writes it, at entries no block of that launch reads.
+// system's first block writes it, at entries no block of that launch reads.  The
+// status fields come first: the host copies only that head of each record
+// (kSysHead bytes) between cycles.
 struct SysK {
+    int active;        // Arnoldi running in the current cycle
+    int converged;     // true residual met the tolerance this step
+    int need_update;   // a cycle finished and x must be corrected
+    int mcount;        // basis vectors used by the finished cycle
+    int iters, cycles, refinements, breakdown;
+    int ws_used, fallback, nblocks, slot0;
+    double rel_init, rel_final, rel_warm, kappa_s;
     double h1[kMaxM + 2];    // first Gram-Schmidt coefficients v_k . w
     double h2[kMaxM + 2];    // reorthogonalisation coefficients
     double vs[kMaxM + 2];    // v_k = vs[k] * V_k
@@ -66,16 +86,12 @@ struct SysK {
     double sn[kMaxM + 2];    // Givens sines
     double y[kMaxM + 2];     // update coefficients of the stored vectors
     double R[(kMaxM + 1) * (kMaxM + 1)];   // column j at R[j * (kMaxM + 1) + i]
+    double Hraw[(kMaxM + 1) * (kMaxM + 1)];   // unrotated Hessenberg (delayed Gram-Schmidt)
+    double hc[2][kMaxM + 2]; // first-pass coefficients of the column being built (by step parity)
     double bnorm, rnorm, srnorm, eta;
-    double rel_init, rel_final, rel_warm, kappa_s;
     unsigned long long dmin_bits, dmax_bits;   // extremes of A_PP (positive doubles)
-    int active;        // Arnoldi running in the current cycle
-    int converged;     // true residual met the tolerance this step
-    int need_update;   // a cycle finished and x must be corrected
-    int mcount;        // basis vectors used by the finished cycle
-    int iters, cycles, refinements, breakdown;
-    int ws_used, fallback, nblocks, slot0;
 };
+constexpr size_t kSysHead = offsetof(SysK, h1);
 
 struct Params {          // per-step scalars read by the kernels
     double tol;
@@ -102,6 +118,8 @@ struct KArgs {
     long long ldv;
     int nslots;
     int S;
+    int nsys;              // systems of the context (<= 64)
+    int pad;
 };
 
 // ---------------------------------------------------------------- host helpers

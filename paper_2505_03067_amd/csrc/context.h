@@ -83,10 +83,11 @@ struct Ctx {
     Params* h_prm = nullptr;
     SysK* h_sk = nullptr;
 
-    // graph of one GMRES cycle (three segments while a kernel is timed)
-    hipGraphExec_t graphs[3] = {nullptr, nullptr, nullptr};
-    int ngraphs = 0;
-    bool graph_valid = false;
+    // graphs of GMRES cycle segments, keyed by (first step, end step, tail kind)
+    std::map<int, hipGraphExec_t> graphs;
+    // Arnoldi steps taken by each cycle of the previous implicit step (the cycle is
+    // first launched up to that length + kPredictMargin, then continued if needed)
+    std::vector<int> cycle_len, cycle_len_next;
 
     std::vector<mpm_stats> stats;
     bool stepped = false;
@@ -102,7 +103,7 @@ struct Ctx {
     bool have_prev = false;
 
     // kernel timing hook
-    int time_kind = 0, time_j = 0;
+    int time_kind = 0, time_j = 0, time_repeat = 1;
     std::vector<hipEvent_t> tev;       // start/stop pairs, one pair per timed launch
     int tev_used = 0;                  // pairs recorded in the current cycle
     double time_ms = 0.0, time_bytes = 0.0;
@@ -121,7 +122,7 @@ int launch_diag_extremes(Ctx* c, int p);
 int run_step(Ctx* c, double* const* fields, double tol);
 int debug_apply(Ctx* c, int p, const double* x, double* y, int mode);
 int ensure_layout(Ctx* c);
-int select_timing(Ctx* c, int kind, int j);
+int select_timing(Ctx* c, int kind, int j, int repeat);
 int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* in_bf16, float* target);
 
 }  // namespace mpm

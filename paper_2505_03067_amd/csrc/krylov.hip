@@ -36,6 +36,10 @@
 
 namespace mpm {
 
+// Arnoldi steps launched beyond the previous step's cycle length before the host
+// checks whether the cycle has to continue.
+constexpr int kPredictMargin = 2;
+
 // partial-sum rows
 constexpr int kRowB = 0;                    // ||b||^2
 constexpr int kRowR = 1;                    // ||r||^2, ||S r||^2
@@ -316,82 +320,119 @@ __global__ __launch_bounds__(kThreads) void k_res_final(KArgs<T> a, int sys0, in
     }
 }
 
-// Givens rotation of Hessenberg column Jc (the Arnoldi step that just finished,
-// with ||w|| = hn), update of the rotated right-hand side g, and the end-of-cycle
-// test; at the end of the cycle, back-substitution R y = g.  Wave 0 of every block
-// computes the same values in the same order; only the lead block stores them.
-// Returns true (to the whole block) if the cycle ended at step Jc.
+// Value of v in lane i (i uniform), as a wave-uniform double.
+__device__ inline double rdl(double v, int i) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+    return __hiloint2double(hi, lo);
+}
+
+// Wave 0 only, one Hessenberg row per lane.  'v' holds the unrotated column Jc
+// (rows 0..Jc + 1, sub = row Jc + 1).  Applies the earlier Givens rotations (the
+// running value of row i is carried from rotation to rotation), forms rotation Jc,
+// updates the rotated right-hand side g and tests the end of the cycle; at the end,
+// solves R y = g by columns (lane i keeps row i of g and receives y_k in turn).
+// Every block computes the same values in the same order; only 'lead' stores.
+// Registers stay O(1) per row, whatever Jc.  Returns done (uniform over the wave).
+// Per-system scalars column_tail reads, loaded by the caller (lane i: entry i).
+struct TailIn {
+    double csl, snl;   // Givens cosine and sine of column lane (lane < Jc)
+    double vsl;        // vs[lane]
+    double gJ, g0, eta;
+};
+
+__device__ inline TailIn load_tail(const SysK* sk, int Jc) {
+    const int lane = threadIdx.x & 63;
+    TailIn t;
+    t.csl = lane < Jc ? sk->cs[lane] : 0.0;
+    t.snl = lane < Jc ? sk->sn[lane] : 0.0;
+    t.vsl = lane <= Jc ? sk->vs[lane] : 0.0;
+    t.gJ = sk->gt[Jc];
+    t.g0 = sk->gt[0];
+    t.eta = sk->eta;
+    return t;
+}
+
 template <int Jc>
-__device__ inline bool givens_tail(SysK* sk, double hn, int restart, bool lead) {
+__device__ inline bool column_tail(SysK* sk, const TailIn& ti, double v, double sub, int restart, bool lead) {
     constexpr int LD = kMaxM + 1;
-    __shared__ int s_done;
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        double col[Jc + 2];
+    const int lane = threadIdx.x & 63;
+    const double csl = ti.csl, snl = ti.snl;
+    double r = v;
+    double run = rdl(v, 0);
 #pragma unroll
-        for (int k = 0; k <= Jc; ++k) col[k] = sk->h1[k] + sk->h2[k];
-        col[Jc + 1] = hn;
-#pragma unroll
-        for (int i = 0; i < Jc; ++i) {            // earlier rotations, in order
-            const double cs = sk->cs[i], sn = sk->sn[i];
-            const double t = cs * col[i] + sn * col[i + 1];
-            col[i + 1] = -sn * col[i] + cs * col[i + 1];
-            col[i] = t;
-        }
-        const double rho = sqrt(col[Jc] * col[Jc] + col[Jc + 1] * col[Jc + 1]);
-        double cs = 1.0, sn = 0.0;
-        if (rho > 0.0) {
-            cs = col[Jc] / rho;
-            sn = col[Jc + 1] / rho;
-        }
-        col[Jc] = rho;
-        const double gJ = sk->gt[Jc];
-        const double gn = -sn * gJ;
-        const bool breakdown = !(hn > 0.0) || !(rho > 0.0);
-        const bool done = breakdown || fabs(gn) <= sk->eta * sk->gt[0] || Jc + 1 >= restart;
-        if (lead && lane == 0) {
-#pragma unroll
-            for (int k = 0; k <= Jc; ++k) sk->R[Jc * LD + k] = col[k];
+    for (int i = 0; i < Jc; ++i) {
+        const double b = rdl(v, i + 1), c = rdl(csl, i), sn = rdl(snl, i);
+        const double top = c * run + sn * b;
+        run = -sn * run + c * b;
+        if (lane == i) r = top;
+    }
+    const double rho = sqrt(run * run + sub * sub);
+    double cs = 1.0, sn = 0.0;
+    if (rho > 0.0) {
+        cs = run / rho;
+        sn = sub / rho;
+    }
+    if (lane == Jc) r = rho;
+    const double gJ = ti.gJ;
+    const double gn = -sn * gJ;
+    const bool breakdown = !(sub > 0.0) || !(rho > 0.0);
+    const bool done = breakdown || fabs(gn) <= ti.eta * ti.g0 || Jc + 1 >= restart;
+    if (lead) {
+        if (lane <= Jc) sk->R[Jc * LD + lane] = r;
+        if (lane == 0) {
             sk->cs[Jc] = cs;
             sk->sn[Jc] = sn;
             sk->gf[Jc] = cs * gJ;
             sk->gt[Jc + 1] = gn;
-            sk->vs[Jc + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
         }
-        if (done) {
-            // back-substitution by columns: lane i holds row i of R and g_i and
-            // receives y_k in turn; column Jc is still in registers
-            const int m = Jc + 1;
-            double rrow[Jc + 1];
+    }
+    if (done) {
+        const int m = Jc + 1;
+        double rrow[Jc > 0 ? Jc : 1];
 #pragma unroll
-            for (int k = 0; k < Jc; ++k) rrow[k] = lane < m ? sk->R[k * LD + lane] : 0.0;
-            rrow[Jc] = 0.0;
+        for (int k = 0; k < Jc; ++k) rrow[k] = lane <= k ? sk->R[k * LD + lane] : 0.0;
+        double gi = lane < Jc ? sk->gf[lane] : (lane == Jc ? cs * gJ : 0.0);
+        double yi = 0.0;
+        {
+            const double yk = rho != 0.0 ? rdl(gi, Jc) / rho : 0.0;
+            if (lane == Jc) yi = yk;
+            if (lane < Jc) gi -= r * yk;
+        }
 #pragma unroll
-            for (int k = 0; k <= Jc; ++k)
-                if (lane == k) rrow[Jc] = col[k];
-            double gi = lane < Jc ? sk->gf[lane] : 0.0;
-            if (lane == Jc) gi = cs * gJ;
-            double yi = 0.0;
-#pragma unroll
-            for (int k = Jc; k >= 0; --k) {
-                const double rkk = __shfl(rrow[k], k);
-                const double gk = __shfl(gi, k);
-                const double yk = rkk != 0.0 ? gk / rkk : 0.0;
-                if (lane == k) yi = yk;
-                if (lane < k) gi -= rrow[k] * yk;
-            }
-            if (lead) {
-                if (lane < m) sk->y[lane] = yi * sk->vs[lane];
-                if (lane == 0) {
-                    sk->mcount = m;
-                    sk->active = 0;
-                    sk->need_update = 1;
-                    sk->iters += m;
-                    sk->cycles += 1;
-                    if (breakdown && !(hn == 0.0)) sk->breakdown = 1;
-                }
+        for (int k = Jc - 1; k >= 0; --k) {
+            const double rkk = rdl(rrow[k], k);
+            const double gk = rdl(gi, k);
+            const double yk = rkk != 0.0 ? gk / rkk : 0.0;
+            if (lane == k) yi = yk;
+            if (lane < k) gi -= rrow[k] * yk;
+        }
+        if (lead) {
+            if (lane < m) sk->y[lane] = yi * ti.vsl;
+            if (lane == 0) {
+                sk->mcount = m;
+                sk->active = 0;
+                sk->need_update = 1;
+                sk->iters += m;
+                sk->cycles += 1;
+                if (breakdown && !(sub == 0.0)) sk->breakdown = 1;
             }
         }
+    }
+    return done;
+}
+
+// CGS2: column Jc = h1 + h2 with ||w|| = hn below the diagonal; the next basis
+// vector's scale 1/hn.  Returns true (to the whole block) if the cycle ended at Jc.
+template <int Jc>
+__device__ inline bool givens_tail(SysK* sk, double hn, int restart, bool lead) {
+    __shared__ int s_done;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const TailIn ti = load_tail(sk, Jc);
+        const double v = lane <= Jc ? sk->h1[lane] + sk->h2[lane] : (lane == Jc + 1 ? hn : 0.0);
+        const bool done = column_tail<Jc>(sk, ti, v, hn, restart, lead);
+        if (lead && lane == 0) sk->vs[Jc + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
         if (lane == 0) s_done = done ? 1 : 0;
     }
     __syncthreads();
@@ -670,6 +711,378 @@ __global__ __launch_bounds__(kThreads) void k_dbg_apply(ProbDev pd, int S, const
     }
 }
 
+// ------------------------------------------------------------------ delayed CGS2
+// Classical Gram-Schmidt with delayed reorthogonalisation: step j keeps the vector
+// u_j = A q_{j-1} - Q_{j-1} h (orthogonalised once) unnormalised and applies the
+// stencil to it directly, z = B u_j.  One multi-dot gives s = Q^T u_j, t = Q^T z,
+// alpha = u_j.u_j and gamma = u_j.z; then
+//   q_j = (u_j - Q s) / beta_j,      beta_j^2 = alpha - |s|^2          (second pass, lagged)
+//   H[:, j-1] = h_{j-1} + s,         H[j, j-1] = beta_j
+//   A q_j = (z - Q_j g) / beta_j,    g = H s   (Arnoldi relation A Q = Q H)
+//   h_j = Q_j^T A q_j = (Q_j^T z - g) / beta_j,  q_j . z = (gamma - s.t) / beta_j
+//   u_{j+1} = A q_j - Q_j h_j = z / beta_j - Q_j (g / beta_j + h_j)
+// so each step is one stencil + multi-dot kernel and one axpy kernel, one global
+// reduction, two passes over the basis.  The Givens rotation of column j-1 runs in
+// the axpy kernel of step j.  q_0 = vs[0] V_0; every later q_k is stored normalised.
+//
+// Partial rows of step j (base kRowD): J = 0: [0] V_0.z; J >= 1: [k] V_k.u,
+// [J + k] V_k.z (k < J), [2J] u.u, [2J + 1] u.z.
+constexpr int kRowD = 3;
+static_assert(kRowD + 2 * kMaxM + 2 <= kPartRows, "partial rows");
+
+// Scaled stencil B = S A S on VW consecutive unknowns of the block's system, addressed
+// from the block record alone.  Returns the centre values of v in xv.
+template <typename T>
+__device__ inline void stencil_blk(const T* __restrict__ v, const Block& blk, long long u0, int l0,
+                                   T (&xv)[VW<T>::n], T (&out)[VW<T>::n]) {
+    constexpr int n = VW<T>::n;
+    const T* __restrict__ c = (const T*)blk.c;
+    const long long loc0 = blk.locbase + l0;
+    T cx[n], cy[n], cz[n];
+    int4 nb[n];
+    ld16(v + u0, xv);
+    ld16(c + loc0, cx);
+    ld16(c + blk.tot + loc0, cy);
+    ld16(c + 2 * blk.tot + loc0, cz);
+#pragma unroll
+    for (int e = 0; e < n; ++e) nb[e] = blk.nbr[l0 + e];
+    const T vm = v[u0 - 1], vp = v[u0 + n];
+    const T cxm = c[loc0 - 1];
+#pragma unroll
+    for (int e = 0; e < n; ++e) {
+        const T left = e == 0 ? vm : xv[e - 1];
+        const T leftc = e == 0 ? cxm : cx[e - 1];
+        const T right = e == n - 1 ? vp : xv[e + 1];
+        T r = xv[e];
+        r += cx[e] * right;
+        r += leftc * left;
+        r += cy[e] * v[blk.base + nb[e].y];
+        r += c[blk.tot + blk.locbase + nb[e].x] * v[blk.base + nb[e].x];
+        r += cz[e] * v[blk.base + nb[e].w];
+        r += c[2 * blk.tot + blk.locbase + nb[e].z] * v[blk.base + nb[e].z];
+        out[e] = (l0 + e < blk.N) ? r : T(0);
+    }
+}
+
+// Step J, kernel A: z = B u_J (J = 0: z = B q_0) into W, and the partial sums of the
+// step's dot products.  The activity flags of all systems are read with the block
+// record, and the basis vectors of the range are requested with the stencil's own
+// operands, so a block waits for memory three times: block record, operands,
+// neighbour values.
+template <typename T, int J>
+__global__ __launch_bounds__(kThreads) void k_dc_spmv_dot(KArgs<T> a) {
+    constexpr int n = VW<T>::n;
+    constexpr int NR = J == 0 ? 1 : 2 * J + 2;
+    const int lane = threadIdx.x & 63;
+    const int actv = lane < a.nsys ? a.sk[lane].active : 0;
+    double vs0v = 0.0;
+    if constexpr (J == 0) vs0v = lane < a.nsys ? a.sk[lane].vs[0] : 0.0;
+    const Block blk = a.blocks[blockIdx.x];
+    if (blk.sys < 0) return;
+    if (!__builtin_amdgcn_readlane(actv, blk.sys)) return;
+    T sc = T(1);
+    if constexpr (J == 0) sc = (T)rdl(vs0v, blk.sys);
+    const T* U = a.V + (long long)J * a.ldv;
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+    for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
+        const int l0 = (int)(u0 - blk.base);
+        T vk[J > 0 ? J : 1][n];
+#pragma unroll
+        for (int k = 0; k < J; ++k) ld16(a.V + (long long)k * a.ldv + u0, vk[k]);
+        T uv[n], z[n];
+        stencil_blk<T>(U, blk, u0, l0, uv, z);
+        if constexpr (J == 0) {
+#pragma unroll
+            for (int e = 0; e < n; ++e) z[e] *= sc;
+        }
+        st16(a.W + u0, z);
+        if constexpr (J == 0) {
+#pragma unroll
+            for (int e = 0; e < n; ++e) acc[0] += (double)uv[e] * (double)z[e];
+        } else {
+#pragma unroll
+            for (int k = 0; k < J; ++k) {
+#pragma unroll
+                for (int e = 0; e < n; ++e) {
+                    acc[k] += (double)vk[k][e] * (double)uv[e];
+                    acc[J + k] += (double)vk[k][e] * (double)z[e];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < n; ++e) {
+                acc[2 * J] += (double)uv[e] * (double)uv[e];
+                acc[2 * J + 1] += (double)uv[e] * (double)z[e];
+            }
+        }
+    }
+    block_partials<NR>(acc, a.part + (long long)kRowD * a.nslots, a.nslots, blk.slot);
+}
+
+// After the last step: the rows of k_dc_spmv_dot without a stencil (t, gamma = 0).
+template <typename T, int J>
+__global__ __launch_bounds__(kThreads) void k_dc_lastdots(KArgs<T> a) {
+    constexpr int n = VW<T>::n;
+    constexpr int NR = 2 * J + 2;
+    const int lane = threadIdx.x & 63;
+    const int actv = lane < a.nsys ? a.sk[lane].active : 0;
+    const Block blk = a.blocks[blockIdx.x];
+    if (blk.sys < 0) return;
+    if (!__builtin_amdgcn_readlane(actv, blk.sys)) return;
+    const T* U = a.V + (long long)J * a.ldv;
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+    for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
+        T uv[n];
+        ld16(U + u0, uv);
+#pragma unroll
+        for (int k = 0; k < J; ++k) {
+            T vk[n];
+            ld16(a.V + (long long)k * a.ldv + u0, vk);
+#pragma unroll
+            for (int e = 0; e < n; ++e) acc[k] += (double)vk[e] * (double)uv[e];
+        }
+#pragma unroll
+        for (int e = 0; e < n; ++e) acc[2 * J] += (double)uv[e] * (double)uv[e];
+    }
+    block_partials<NR>(acc, a.part + (long long)kRowD * a.nslots, a.nslots, blk.slot);
+}
+
+// Loads of one block's share of a system's partial sums (rows w, w + kWaves, ... of
+// wave w; lane i takes slots i, i + 64, ... up to four of them per row), issued
+// together; sum_partials finishes the reduction into out[] (shared) in block order.
+template <int NV>
+struct PartLoad {
+    static constexpr int R = (NV + kWaves - 1) / kWaves;
+    double t[R][4];
+};
+
+template <int NV>
+__device__ inline void load_partials(const double* part, int nslots, int slot0, int nb, PartLoad<NV>& pl) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < PartLoad<NV>::R; ++r) {
+        const int v = w + r * kWaves;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = lane + 64 * q;
+            pl.t[r][q] = (v < NV && i < nb) ? part[(long long)v * nslots + slot0 + i] : 0.0;
+        }
+    }
+}
+
+template <int NV>
+__device__ inline void sum_partials(const double* part, int nslots, int slot0, int nb, PartLoad<NV>& pl,
+                                    double* out) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < PartLoad<NV>::R; ++r) {
+        const int v = w + r * kWaves;
+        double t = ((pl.t[r][0] + pl.t[r][1]) + pl.t[r][2]) + pl.t[r][3];
+        if (v < NV)
+            for (int i = lane + 256; i < nb; i += 64) t += part[(long long)v * nslots + slot0 + i];
+        const double sum = wsum(t);
+        if (v < NV && lane == 0) out[v] = sum;
+    }
+}
+
+// Scalar work of step J >= 1 (wave 0 of every block, one Hessenberg row per lane; only
+// the lead block stores; the first-pass coefficients alternate between two buffers so
+// that no block reads what the lead block of the same launch writes): finish column
+// J-1 (Givens, convergence, back-substitution when the cycle ends) and, if the cycle
+// goes on, the coefficients of q_J on V_k (sq) and of u_{J+1} on V_k and q_J (sc),
+// and beta_J.  H holds columns 0..J-2 of the Hessenberg matrix.  Returns done.
+template <int J>
+__device__ inline bool dc_scalars(SysK* sk, const TailIn& ti, double hprev, const double* red, const double* H,
+                                  int restart, bool lead, double* sq, double* sc, double* sbeta) {
+    constexpr int LD = kMaxM + 1;
+    constexpr int Jc = J - 1;
+    const int lane = threadIdx.x & 63;
+    const double vsl = lane < J ? ti.vsl : 0.0;
+    const double s = lane < J ? vsl * red[lane] : 0.0;
+    const double t = lane < J ? vsl * red[J + lane] : 0.0;
+    const double ss = wsum(s * s), st = wsum(s * t);
+    const double alpha = red[2 * J], gam = red[2 * J + 1];
+    const double b2 = alpha - ss;
+    const double beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+    // column J-1 of the Hessenberg matrix: first pass + correction, beta below
+    const double v = lane < J ? hprev + s : (lane == J ? beta : 0.0);
+    if (lead) {
+        if (lane <= J) sk->Hraw[Jc * LD + lane] = v;
+        if (lane == 0) sk->vs[J] = 1.0;
+    }
+    const bool done = column_tail<Jc>(sk, ti, v, beta, restart, lead);
+    if (!done) {
+        // g = H[0:J+1, 0:J] s (lane k = row k; column i has rows <= i + 1)
+        double g = 0.0;
+#pragma unroll
+        for (int i = 0; i < Jc; ++i) {
+            const double si = rdl(s, i);
+            if (lane <= i + 1) g += H[i * LD + lane] * si;
+        }
+        g += v * rdl(s, Jc);
+        const double qz = (gam - st) / beta;
+        const double tk = lane < J ? t : qz;
+        const double h = (tk - g) / beta;
+        const double cc = g / beta + h;
+        if (lane <= J) {
+            if (lead) sk->hc[J & 1][lane] = h;
+            sc[lane] = lane < J ? cc * vsl : cc;
+        }
+        if (lane < J) sq[lane] = s * vsl;
+        if (lane == 0) *sbeta = beta;
+    }
+    return done;
+}
+
+// Step J, kernel B: from the reduced dot products, finish q_J = (u_J - Q s) / beta in
+// place and form u_{J+1} = z / beta - Q c (J = 0: u_1 = z - h_00 q_0).  Everything a
+// block reads (partial sums, the system's scalars, the Hessenberg columns and the
+// vectors of its range) is requested in one go once the block record is in.
+template <typename T, int J>
+__global__ __launch_bounds__(kThreads) void k_dc_axpy(KArgs<T> a) {
+    constexpr int n = VW<T>::n;
+    constexpr int NR = J == 0 ? 1 : 2 * J + 2;
+    constexpr int LD = kMaxM + 1;
+    constexpr int NH = J >= 2 ? (J - 1) * LD : 0;
+    constexpr int HPT = (NH + kThreads - 1) / kThreads;
+    __shared__ double red[NR];
+    __shared__ double sH[NH > 0 ? NH : 1];
+    __shared__ double sq[J > 0 ? J : 1];
+    __shared__ double scf[J + 1];
+    __shared__ double sbeta;
+    __shared__ int s_done;
+    const int lane = threadIdx.x & 63;
+    const int actv = lane < a.nsys ? a.sk[lane].active : 0;
+    const Block blk = a.blocks[blockIdx.x];
+    if (blk.sys < 0) return;
+    if (!__builtin_amdgcn_readlane(actv, blk.sys)) return;
+    SysK* sk = a.sk + blk.sys;
+    const bool lead = blk.slot == blk.slot0;
+    const double* part = a.part + (long long)kRowD * a.nslots;
+    // ---- all loads of the block, issued together
+    PartLoad<NR> pl;
+    load_partials<NR>(part, a.nslots, blk.slot0, blk.nb, pl);
+    TailIn ti{};
+    double hprev = 0.0;
+    if (threadIdx.x < 64) {
+        if constexpr (J == 0) {
+            ti.vsl = sk->vs[0];
+        } else {
+            ti = load_tail(sk, J - 1);
+            hprev = lane < J ? sk->hc[(J - 1) & 1][lane] : 0.0;
+        }
+    }
+    double hr[HPT > 0 ? HPT : 1];
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        hr[q] = i < NH ? sk->Hraw[i] : 0.0;
+    }
+    T* UJ = a.V + (long long)J * a.ldv;
+    T* UN = a.V + (long long)(J + 1) * a.ldv;
+    long long u0 = blk.start + threadIdx.x * n;
+    T z[n], uj[n], vk[J > 0 ? J : 1][n];
+    auto load_range = [&](long long u) {
+        ld16(a.W + u, z);
+        if constexpr (J > 0) {
+            ld16(UJ + u, uj);
+#pragma unroll
+            for (int k = 0; k < J; ++k) ld16(a.V + (long long)k * a.ldv + u, vk[k]);
+        } else {
+            ld16(a.V + u, vk[0]);
+        }
+    };
+    if (u0 < blk.end) load_range(u0);
+    // ---- reductions and the scalar work
+    sum_partials<NR>(part, a.nslots, blk.slot0, blk.nb, pl, red);
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        if (i < NH) sH[i] = hr[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        bool done = false;
+        if constexpr (J == 0) {
+            const double vs0 = ti.vsl;
+            const double h0 = vs0 * red[0];
+            if (lane == 0) {
+                if (lead) sk->hc[0][0] = h0;
+                scf[0] = h0 * vs0;
+                sbeta = 1.0;
+            }
+        } else {
+            done = dc_scalars<J>(sk, ti, hprev, red, sH, a.prm->restart, lead, sq, scf, &sbeta);
+        }
+        if (lane == 0) s_done = done ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_done) return;
+    const double ib = 1.0 / sbeta;
+    double cq[J > 0 ? J : 1], cu[J + 1];
+#pragma unroll
+    for (int k = 0; k < J; ++k) cq[k] = sq[k];
+#pragma unroll
+    for (int k = 0; k <= J; ++k) cu[k] = scf[k];
+    while (u0 < blk.end) {
+        double un[n];
+        if constexpr (J > 0) {
+            double q[n];
+#pragma unroll
+            for (int e = 0; e < n; ++e) {
+                q[e] = (double)uj[e];
+                un[e] = (double)z[e] * ib;
+            }
+#pragma unroll
+            for (int k = 0; k < J; ++k)
+#pragma unroll
+                for (int e = 0; e < n; ++e) {
+                    q[e] -= cq[k] * (double)vk[k][e];
+                    un[e] -= cu[k] * (double)vk[k][e];
+                }
+            T qs[n];
+#pragma unroll
+            for (int e = 0; e < n; ++e) {
+                q[e] *= ib;
+                qs[e] = (T)q[e];
+                un[e] -= cu[J] * (double)qs[e];
+            }
+            st16(UJ + u0, qs);
+        } else {
+#pragma unroll
+            for (int e = 0; e < n; ++e) un[e] = (double)z[e] - cu[0] * (double)vk[0][e];
+        }
+        T us[n];
+#pragma unroll
+        for (int e = 0; e < n; ++e) us[e] = (T)un[e];
+        st16(UN + u0, us);
+        u0 += kThreads * n;
+        if (u0 < blk.end) load_range(u0);
+    }
+}
+
+// End of the cycle: finish the last column (one block per system).
+template <typename T, int J>
+__global__ __launch_bounds__(kThreads) void k_dc_finish(KArgs<T> a, int sys0) {
+    constexpr int NR = 2 * J + 2;
+    constexpr int LD = kMaxM + 1;
+    SysK* sk = a.sk + sys0 + blockIdx.x;
+    if (!sk->active) return;
+    __shared__ double red[NR];
+    __shared__ double sq[J], scf[J + 1], sbeta;
+    reduce_partials<NR>(a.part + (long long)kRowD * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
+    if (threadIdx.x < 64) {
+        const TailIn ti = load_tail(sk, J - 1);
+        const double hprev = (threadIdx.x & 63) < J ? sk->hc[(J - 1) & 1][threadIdx.x & 63] : 0.0;
+        // the cycle ends here (J = m): the H columns are not needed
+        (void)dc_scalars<J>(sk, ti, hprev, red, sk->Hraw, a.prm->restart, true, sq, scf, &sbeta);
+        (void)LD;
+    }
+}
+
 // ------------------------------------------------------------------ warm start
 __device__ inline uint16_t to_bf16(float f) {
     uint32_t u = __float_as_uint(f);
@@ -796,15 +1209,38 @@ static std::array<KFinFn<T>, sizeof...(Js)> table_k4(std::integer_sequence<int, 
     return {&k_finish<T, Js>...};
 }
 
+template <typename T, int... Js>
+static std::array<KFn<T>, sizeof...(Js)> table_da(std::integer_sequence<int, Js...>) {
+    return {&k_dc_spmv_dot<T, Js>...};
+}
+template <typename T, int... Js>
+static std::array<KFn<T>, sizeof...(Js)> table_db(std::integer_sequence<int, Js...>) {
+    return {&k_dc_axpy<T, Js>...};
+}
+template <typename T, int... Js>
+static std::array<KFn<T>, sizeof...(Js)> table_dl(std::integer_sequence<int, Js...>) {
+    return {&k_dc_lastdots<T, Js + 1>...};
+}
+template <typename T, int... Js>
+static std::array<KFinFn<T>, sizeof...(Js)> table_df(std::integer_sequence<int, Js...>) {
+    return {&k_dc_finish<T, Js + 1>...};
+}
+
 template <typename T>
 struct Kernels {
     std::array<KFn<T>, kMaxM> k1, k2, k3;
     std::array<KFinFn<T>, kMaxM> k4;
+    std::array<KFn<T>, kMaxM> da, db, dl;   // dl[m - 1], df[m - 1]: after m steps
+    std::array<KFinFn<T>, kMaxM> df;
     Kernels() {
         k1 = table_k1<T>(std::make_integer_sequence<int, kMaxM>{});
         k2 = table_k2<T>(std::make_integer_sequence<int, kMaxM>{});
         k3 = table_k3<T>(std::make_integer_sequence<int, kMaxM>{});
         k4 = table_k4<T>(std::make_integer_sequence<int, kMaxM>{});
+        da = table_da<T>(std::make_integer_sequence<int, kMaxM>{});
+        db = table_db<T>(std::make_integer_sequence<int, kMaxM>{});
+        dl = table_dl<T>(std::make_integer_sequence<int, kMaxM>{});
+        df = table_df<T>(std::make_integer_sequence<int, kMaxM>{});
     }
 };
 
@@ -834,27 +1270,36 @@ static void build_tables(Ctx* c, long long per) {
     const int nsys = S * c->P;
     per = std::max<long long>(kAlign, (per + kAlign - 1) / kAlign * kAlign);
     c->block_unknowns = (int)per;
-    std::vector<Block> logical;
+    std::vector<Block> logical;            // per system, in slot order
     c->sys_first.assign(nsys, 0);
     c->sys_count.assign(nsys, 0);
+    const bool f64 = c->opt.precision == MPM_FP64;
     int slot = 0;
     for (int p = 0; p < c->P; ++p) {
         const ProbHost& ph = c->probs[p];
+        const int nbp = (int)((ph.Npad + per - 1) / per);
         for (int s = 0; s < S; ++s) {
             const int sys = p * S + s;
             const long long base = c->off[p] + (long long)s * ph.Npad;
             c->sys_first[sys] = slot;
-            int nb = 0;
-            for (long long a0 = 0; a0 < ph.Npad; a0 += per) {
-                Block b;
+            for (int i = 0; i < nbp; ++i) {
+                const long long a0 = (long long)i * per;
+                Block b{};
                 b.sys = sys;
                 b.start = (int)(base + a0);
                 b.end = (int)(base + std::min<long long>(ph.Npad, a0 + per));
                 b.slot = slot++;
+                b.slot0 = c->sys_first[sys];
+                b.nb = nbp;
+                b.N = ph.N;
+                b.tot = S * ph.Npad;
+                b.base = base;
+                b.locbase = (long long)s * ph.Npad;
+                b.nbr = ph.nbr;
+                b.c = f64 ? (const void*)ph.c64 : (const void*)ph.c32;
                 logical.push_back(b);
-                ++nb;
             }
-            c->sys_count[sys] = nb;
+            c->sys_count[sys] = nbp;
         }
     }
     c->nslots = slot;
@@ -862,15 +1307,25 @@ static void build_tables(Ctx* c, long long per) {
         const size_t nb = L.size();
         const size_t per = (nb + 7) / 8;
         const size_t padded = per * 8;
-        Block idle{-1, 0, 0, 0};
+        Block idle{};
+        idle.sys = -1;
         for (size_t b = 0; b < padded; ++b) {
             const size_t xcd = b % 8, pos = b / 8;
             const size_t li = xcd * per + pos;
             out.push_back(li < nb ? L[li] : idle);
         }
     };
+    // batched table: the species of one voxel range next to each other, so that an
+    // XCD fetches a range's neighbour table once for all species
+    std::vector<Block> inter;
+    inter.reserve(logical.size());
+    for (int p = 0; p < c->P; ++p) {
+        const int nbp = c->sys_count[p * S];
+        for (int i = 0; i < nbp; ++i)
+            for (int s = 0; s < S; ++s) inter.push_back(logical[c->sys_first[p * S + s] + i]);
+    }
     c->blocks.clear();
-    swizzle(logical, c->blocks);
+    swizzle(inter, c->blocks);
     c->blocks_sys.clear();
     c->sys_tab_first.assign(nsys, 0);
     for (int sys = 0; sys < nsys; ++sys) {
@@ -973,9 +1428,17 @@ static int autotune_t(Ctx* c, long long* best_out) {
         for (int rep = 0; rep < 3; ++rep) {
             MPM_HIP(hipEventRecord(e0, st));
             for (int it = 0; it < 3; ++it) {
-                K.k1[0]<<<nb, kThreads, 0, st>>>(a);
-                K.k2[J]<<<nb, kThreads, 0, st>>>(a);
-                K.k3[J]<<<nb, kThreads, 0, st>>>(a);
+                if (c->opt.ortho == MPM_ORTHO_DCGS2) {
+                    // the axpy kernel of the delayed scheme would end the cycle on
+                    // these contents; the CGS2 pass streams as many vectors
+                    K.da[0]<<<nb, kThreads, 0, st>>>(a);
+                    K.da[J]<<<nb, kThreads, 0, st>>>(a);
+                    K.k2[J]<<<nb, kThreads, 0, st>>>(a);
+                } else {
+                    K.k1[0]<<<nb, kThreads, 0, st>>>(a);
+                    K.k2[J]<<<nb, kThreads, 0, st>>>(a);
+                    K.k3[J]<<<nb, kThreads, 0, st>>>(a);
+                }
             }
             MPM_HIP(hipEventRecord(e1, st));
             MPM_HIP(hipEventSynchronize(e1));
@@ -1132,6 +1595,7 @@ static KArgs<T> make_args(Ctx* c, const Block* blocks) {
     a.ldv = c->ldv;
     a.nslots = c->nslots;
     a.S = c->S;
+    a.nsys = c->S * c->P;
     return a;
 }
 
@@ -1144,38 +1608,56 @@ static void tev_end(Ctx* c, hipStream_t st) {
     ++c->tev_used;
 }
 
-// Enqueue one GMRES cycle (m Arnoldi steps, update, residual) for the given table.
-// 'part' selects a segment of the launch sequence around the timed kernel:
-// 0 = everything, 1 = launches before it, 2 = the timed launch only, 3 = after it.
-// 'events' records a start/stop event pair around the timed launch.
+// What follows the Arnoldi steps of a launched segment.
+enum Tail {
+    kTailNone = 0,     // more steps of this cycle follow
+    kTailUpdate = 1,   // every system ended its cycle: update, residual, next cycle's start
+    kTailFull = 2,     // the segment reached step m: last column, then as kTailUpdate
+};
+
+// Enqueue Arnoldi steps [j0, j1) of a GMRES cycle and the given tail for one block
+// table.  'events' records a start/stop event pair around the timed launch.
 template <typename T>
-static void enqueue_cycle(Ctx* c, const Block* tab, unsigned nb, int sys0, int nsys, hipStream_t st, int part,
-                          bool events) {
+static void enqueue_cycle(Ctx* c, const Block* tab, unsigned nb, int sys0, int nsys, hipStream_t st, int j0,
+                          int j1, int tail, bool events) {
     const Kernels<T>& K = kernels<T>();
     KArgs<T> a = make_args<T>(c, tab);
-    int phase = 1;
     auto emit = [&](auto launch, bool is_timed) {
-        if (is_timed) {
-            if (part == 0 || part == 2) {
-                if (events) tev_begin(c, st);
-                launch();
-                if (events) tev_end(c, st);
-            }
-            phase = 3;
-        } else if (part == 0 || part == phase) {
+        if (is_timed && events) {
+            tev_begin(c, st);
+            for (int r = 0; r < c->time_repeat; ++r) launch();
+            tev_end(c, st);
+        } else {
             launch();
         }
     };
     const int m = c->opt.restart;
-    for (int j = 0; j < m; ++j) {
-        const KFn<T> fns[3] = {K.k1[j], K.k2[j], K.k3[j]};
-        for (int q = 0; q < 3; ++q) {
-            KFn<T> fn = fns[q];
-            emit([&] { fn<<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_SPMV_DOT + q, j));
+    const bool dc = c->opt.ortho == MPM_ORTHO_DCGS2;
+    for (int j = j0; j < j1; ++j) {
+        if (dc) {
+            KFn<T> fa = K.da[j], fb = K.db[j];
+            emit([&] { fa<<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_SPMV_DOT, j));
+            emit([&] { fb<<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_AXPY_DOT, j));
+        } else {
+            const KFn<T> fns[3] = {K.k1[j], K.k2[j], K.k3[j]};
+            for (int q = 0; q < 3; ++q) {
+                KFn<T> fn = fns[q];
+                emit([&] { fn<<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_SPMV_DOT + q, j));
+            }
         }
     }
-    KFinFn<T> fin = K.k4[m - 1];
-    emit([&] { fin<<<nsys, kThreads, 0, st>>>(a, sys0); }, false);
+    if (tail == kTailNone) return;
+    if (tail == kTailFull) {
+        if (dc) {
+            KFn<T> fl = K.dl[m - 1];
+            KFinFn<T> ff = K.df[m - 1];
+            emit([&] { fl<<<nb, kThreads, 0, st>>>(a); }, false);
+            emit([&] { ff<<<nsys, kThreads, 0, st>>>(a, sys0); }, false);
+        } else {
+            KFinFn<T> fin = K.k4[m - 1];
+            emit([&] { fin<<<nsys, kThreads, 0, st>>>(a, sys0); }, false);
+        }
+    }
     emit([&] { k_update<T><<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_UPDATE, 0));
     emit([&] { k_residual<T><<<nb, kThreads, 0, st>>>(a, kResCycle); }, timed(c, MPM_KERNEL_RESIDUAL, 0));
     emit([&] { k_res_final<T><<<nsys, kThreads, 0, st>>>(a, sys0, kResCycle); }, false);
@@ -1188,7 +1670,7 @@ static void account_timing(Ctx* c) {
     for (int i = 0; i < c->tev_used; ++i) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]) == hipSuccess) c->time_ms += ms;
-        ++c->time_launches;
+        c->time_launches += c->time_repeat;
     }
     const double t = (double)sizeof(T);
     const int j = c->time_j;
@@ -1199,8 +1681,17 @@ static void account_timing(Ctx* c) {
         const double N = (double)c->probs[s / c->S].N;
         double per = 0.0;
         switch (c->time_kind) {
-            case MPM_KERNEL_SPMV_DOT: per = k.mcount > j ? t * (j + 5) + 16.0 / c->S : 0.0; break;
-            case MPM_KERNEL_AXPY_DOT: per = k.mcount > j ? t * (j + 3) : 0.0; break;
+            case MPM_KERNEL_SPMV_DOT:
+                // the delayed scheme applies the stencil of step j before it learns that
+                // the cycle ended with column j - 1
+                per = (c->opt.ortho == MPM_ORTHO_DCGS2 ? k.mcount >= j : k.mcount > j) ? t * (j + 5) + 16.0 / c->S
+                                                                                         : 0.0;
+                break;
+            case MPM_KERNEL_AXPY_DOT:
+                // delayed Gram-Schmidt: reads Q_j, u_j, z, writes q_j, u_{j+1}
+                per = k.mcount > j ? (c->opt.ortho != MPM_ORTHO_DCGS2 ? t * (j + 3) : j == 0 ? 3 * t : t * (j + 4))
+                                   : 0.0;
+                break;
             case MPM_KERNEL_AXPY_NORM:
                 per = k.mcount > j ? t * (j + 2) + (j + 1 < c->opt.restart ? t : 0.0) : 0.0;
                 break;
@@ -1208,79 +1699,63 @@ static void account_timing(Ctx* c) {
             case MPM_KERNEL_RESIDUAL: per = 56.0 + t + 16.0 / c->S; break;
             default: break;
         }
-        c->time_bytes += per * N;
+        c->time_bytes += per * N * c->time_repeat;
     }
 }
 
 template <typename T>
-static void enqueue_cycle_all(Ctx* c, hipStream_t st, int part, bool events) {
+static void enqueue_cycle_all(Ctx* c, hipStream_t st, int j0, int j1, int tail, bool events) {
     const int nsys = c->S * c->P;
     if (c->opt.batched) {
-        enqueue_cycle<T>(c, c->d_blocks, (unsigned)c->blocks.size(), 0, nsys, st, part, events);
+        enqueue_cycle<T>(c, c->d_blocks, (unsigned)c->blocks.size(), 0, nsys, st, j0, j1, tail, events);
     } else {
         for (int s = 0; s < nsys; ++s) {
             const int first = c->sys_tab_first[s];
             const int cnt = (s + 1 < nsys ? c->sys_tab_first[s + 1] : (int)c->blocks_sys.size()) - first;
-            enqueue_cycle<T>(c, c->d_blocks_sys + first, (unsigned)cnt, s, 1, st, part, events);
+            enqueue_cycle<T>(c, c->d_blocks_sys + first, (unsigned)cnt, s, 1, st, j0, j1, tail, events);
         }
     }
 }
 
 static void drop_graphs(Ctx* c) {
-    for (auto& g : c->graphs) {
-        if (g) (void)hipGraphExecDestroy(g);
-        g = nullptr;
-    }
-    c->ngraphs = 0;
-    c->graph_valid = false;
+    for (auto& kv : c->graphs)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
 }
 
-// Capture the cycle as one graph, or as three segments when a kernel is timed (the
-// timing events are then recorded on the stream between the segment launches).
+// Launch one segment of a cycle: from a cached graph, or directly while a kernel is
+// timed (events inside a captured graph cannot be timed).
 template <typename T>
-static int capture_cycle(Ctx* c, hipStream_t st) {
-    drop_graphs(c);
-    const bool split = c->time_kind != MPM_KERNEL_NONE;
-    const int nseg = split ? 3 : 1;
-    for (int i = 0; i < nseg; ++i) {
-        hipGraph_t g = nullptr;
-        MPM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        enqueue_cycle_all<T>(c, st, split ? i + 1 : 0, false);
-        MPM_HIP(hipStreamEndCapture(st, &g));
-        hipError_t e = hipGraphInstantiate(&c->graphs[i], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    }
-    c->ngraphs = nseg;
-    c->graph_valid = true;
-    return MPM_OK;
-}
-
-template <typename T>
-static int launch_cycle(Ctx* c, hipStream_t st) {
-    c->tev_used = 0;
-    // while a kernel is timed the cycle is launched directly, so that the events on
-    // the stream bracket that kernel alone (events inside a captured graph cannot be
-    // timed, and splitting the graph would add its launch latency to the interval)
+static int launch_segment(Ctx* c, hipStream_t st, int j0, int j1, int tail) {
     const bool graph = c->opt.use_graph && c->time_kind == MPM_KERNEL_NONE;
     if (!graph) {
-        enqueue_cycle_all<T>(c, st, 0, c->time_kind != MPM_KERNEL_NONE);
+        enqueue_cycle_all<T>(c, st, j0, j1, tail, c->time_kind != MPM_KERNEL_NONE);
         MPM_HIP(hipGetLastError());
         return MPM_OK;
     }
-    if (!c->graph_valid) {
-        int rc = capture_cycle<T>(c, st);
-        if (rc != MPM_OK) return rc;
+    const int key = (j0 * (kMaxM + 1) + j1) * 3 + tail;
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        hipGraph_t g = nullptr;
+        MPM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        enqueue_cycle_all<T>(c, st, j0, j1, tail, false);
+        MPM_HIP(hipStreamEndCapture(st, &g));
+        hipGraphExec_t ge = nullptr;
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        it = c->graphs.emplace(key, ge).first;
     }
-    if (c->ngraphs == 1) {
-        MPM_HIP(hipGraphLaunch(c->graphs[0], st));
-        return MPM_OK;
-    }
-    MPM_HIP(hipGraphLaunch(c->graphs[0], st));
-    tev_begin(c, st);
-    MPM_HIP(hipGraphLaunch(c->graphs[1], st));
-    tev_end(c, st);
-    MPM_HIP(hipGraphLaunch(c->graphs[2], st));
+    MPM_HIP(hipGraphLaunch(it->second, st));
+    return MPM_OK;
+}
+
+// Copy the status head of every system record to the host and wait for it.
+static int fetch_status(Ctx* c, hipStream_t st) {
+    const int nsys = c->S * c->P;
+    MPM_HIP(hipMemcpy2DAsync(c->h_sk, sizeof(SysK), c->d_sk, sizeof(SysK), kSysHead, nsys,
+                             hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipStreamSynchronize(st));
     return MPM_OK;
 }
 
@@ -1346,16 +1821,30 @@ static int run_step_t(Ctx* c, double tol) {
     MPM_HIP(hipGetLastError());
     int status = MPM_OK, rc = MPM_OK;
     c->prev_cycles.assign(nsys, 0);
+    const int m = c->opt.restart;
+    c->cycle_len_next.clear();
+    auto any_active = [&] {
+        for (int s = 0; s < nsys; ++s)
+            if (c->h_sk[s].active) return true;
+        return false;
+    };
     for (int cyc = 0;; ++cyc) {
-        MPM_HIP(hipMemcpyAsync(c->h_sk, c->d_sk, nsys * sizeof(SysK), hipMemcpyDeviceToHost, st));
-        MPM_HIP(hipStreamSynchronize(st));
-        if (cyc > 0 && c->time_kind != MPM_KERNEL_NONE) account_timing<T>(c);
-        bool any = false, bad = false;
-        for (int s = 0; s < nsys; ++s) {
-            if (c->h_sk[s].breakdown && !c->h_sk[s].converged) bad = true;
-            if (c->h_sk[s].active) any = true;
+        rc = fetch_status(c, st);
+        if (rc != MPM_OK) return rc;
+        if (cyc > 0) {
+            // length of the cycle that just ended (longest over the systems that ran it)
+            int len = 0;
+            for (int s = 0; s < nsys; ++s)
+                if (c->h_sk[s].cycles > c->prev_cycles[s]) len = std::max(len, c->h_sk[s].mcount);
+            c->cycle_len_next.push_back(len);
+            if (c->time_kind != MPM_KERNEL_NONE) account_timing<T>(c);
+            else
+                for (int s = 0; s < nsys; ++s) c->prev_cycles[s] = c->h_sk[s].cycles;
         }
-        if (!any) {
+        bool bad = false;
+        for (int s = 0; s < nsys; ++s)
+            if (c->h_sk[s].breakdown && !c->h_sk[s].converged) bad = true;
+        if (!any_active()) {
             if (bad) status = MPM_NOT_CONVERGED;
             break;
         }
@@ -1363,9 +1852,24 @@ static int run_step_t(Ctx* c, double tol) {
             status = MPM_NOT_CONVERGED;
             break;
         }
-        rc = launch_cycle<T>(c, st);
+        c->tev_used = 0;
+        // Launch the cycle up to the length it took in the previous implicit step (plus
+        // a margin); if a system is still running there, continue to step m.  Launches
+        // past the end of every system's cycle would only find inactive systems.
+        int k = m;
+        if (cyc < (int)c->cycle_len.size()) k = std::min(m, c->cycle_len[cyc] + kPredictMargin);
+        if (k < m) {
+            rc = launch_segment<T>(c, st, 0, k, kTailNone);
+            if (rc != MPM_OK) return rc;
+            rc = fetch_status(c, st);
+            if (rc != MPM_OK) return rc;
+            rc = any_active() ? launch_segment<T>(c, st, k, m, kTailFull) : launch_segment<T>(c, st, k, k, kTailUpdate);
+        } else {
+            rc = launch_segment<T>(c, st, 0, m, kTailFull);
+        }
         if (rc != MPM_OK) return rc;
     }
+    c->cycle_len = c->cycle_len_next;
     k_scatter<T><<<nb, kThreads, 0, st>>>(a);
     if (extrap) {
         // this step's c^n becomes the previous step of the next extrapolation
@@ -1373,8 +1877,8 @@ static int run_step_t(Ctx* c, double tol) {
         c->have_prev = true;
     }
     MPM_HIP(hipGetLastError());
-    MPM_HIP(hipMemcpyAsync(c->h_sk, c->d_sk, nsys * sizeof(SysK), hipMemcpyDeviceToHost, st));
-    MPM_HIP(hipStreamSynchronize(st));
+    rc = fetch_status(c, st);
+    if (rc != MPM_OK) return rc;
     for (int s = 0; s < nsys; ++s) {
         const SysK& k = c->h_sk[s];
         mpm_stats& o = c->stats[s];
@@ -1435,7 +1939,7 @@ static int debug_apply_t(Ctx* c, int p, const double* x, double* y, int mode) {
     return MPM_OK;
 }
 
-int select_timing(Ctx* c, int kind, int j) {
+int select_timing(Ctx* c, int kind, int j, int repeat) {
     const size_t need = 2 * (size_t)c->S * c->P;
     while (c->tev.size() < need) {
         hipEvent_t e;
@@ -1444,6 +1948,7 @@ int select_timing(Ctx* c, int kind, int j) {
     }
     c->time_kind = kind;
     c->time_j = j;
+    c->time_repeat = repeat;
     c->time_ms = 0.0;
     c->time_bytes = 0.0;
     c->time_launches = 0;

@@ -30,6 +30,8 @@ MPM_FP32_IR = 1
 MPM_WS_NONE = 0
 MPM_WS_NET = 1
 MPM_WS_EXTRAP = 2
+MPM_ORTHO_CGS2 = 0
+MPM_ORTHO_DCGS2 = 1
 
 _NAMES = {MPM_EINVAL: "MPM_EINVAL", MPM_ENOMEM: "MPM_ENOMEM", MPM_EHIP: "MPM_EHIP",
           MPM_EEMPTY: "MPM_EEMPTY", MPM_ESTATE: "MPM_ESTATE"}
@@ -45,7 +47,7 @@ class mpm_options(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("batched", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("warm_start", ctypes.c_int32),
-                ("tile_override", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tile_override", ctypes.c_int32), ("ortho", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double)]
 
 
@@ -85,7 +87,7 @@ def lib() -> ctypes.CDLL:
             "mpm_gmres_stats": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mpm_stats)],
             "mpm_destroy": [_vp],
             "mpm_debug_apply": [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32],
-            "mpm_time_kernel": [_vp, ctypes.c_int32, ctypes.c_int32],
+            "mpm_time_kernel": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
             "mpm_tile": [_vp, _i32p],
             "mpm_net_create": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                _i32p, ctypes.c_uint64, _vp],
@@ -248,8 +250,8 @@ MPM_KERNEL_UPDATE = 4
 MPM_KERNEL_RESIDUAL = 5
 
 
-def mpm_time_kernel(ctx, kind: int, j: int = 0) -> None:
-    _check(lib().mpm_time_kernel(ctx, int(kind), int(j)))
+def mpm_time_kernel(ctx, kind: int, j: int = 0, repeat: int = 1) -> None:
+    _check(lib().mpm_time_kernel(ctx, int(kind), int(j), int(repeat)))
 
 
 def mpm_kernel_timing(ctx) -> dict:
@@ -436,8 +438,8 @@ class Solver:
     def stats(self, problem=0, species=0):
         return mpm_gmres_stats(self.ctx, problem, species)
 
-    def time_kernel(self, kind, j=0):
-        return mpm_time_kernel(self.ctx, kind, j)
+    def time_kernel(self, kind, j=0, repeat=1):
+        return mpm_time_kernel(self.ctx, kind, j, repeat)
 
     def tile(self):
         return mpm_tile(self.ctx)

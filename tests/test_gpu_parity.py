@@ -108,11 +108,12 @@ def test_stencil_matches_oracle_matrix(seed, dims, box):
 
 
 # ----------------------------------------------------------------- whole steps
+@pytest.mark.parametrize("ortho", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_config1_ten_steps(precision):
+def test_config1_ten_steps(precision, ortho):
     require_gpu()
     p = config1()
-    _, stats = _check_parity(p, 10, precision=precision)
+    _, stats = _check_parity(p, 10, precision=precision, ortho=ortho)
     its = [s[0]["iterations"] for s in stats]
     print("iterations per step", its)
     assert all(5 <= i <= 120 for i in its)
@@ -121,11 +122,12 @@ def test_config1_ten_steps(precision):
 @pytest.mark.parametrize("seed,dims,fill,S", [(11, (37, 29, 23), 0.5, 3), (12, (50, 21, 17), 0.8, 2),
                                               (13, (23, 41, 30), 0.3, 4), (14, (9, 8, 7), 0.9, 1)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_random_masked_boxes(seed, dims, fill, S, precision):
+@pytest.mark.parametrize("ortho", [0, 1])
+def test_random_masked_boxes(seed, dims, fill, S, precision, ortho):
     require_gpu()
     p = random_problem(seed, dims, S=S, fill=fill,
                        box=((1, 2, 0), (dims[0] - 1, dims[1], dims[2] - 2)), dt=1.5, h=0.9)
-    _check_parity(p, 3, precision=precision)
+    _check_parity(p, 3, precision=precision, ortho=ortho)
 
 
 def test_cell_bounding_box_workload_small():
@@ -141,17 +143,21 @@ def test_cell_bounding_box_workload_small():
 
 
 @pytest.mark.parametrize("opts", [dict(batched=0), dict(use_graph=0), dict(restart=5),
-                                  dict(restart=1, max_cycles=2000), dict(tile_override=2048)])
+                                  dict(restart=1, max_cycles=2000), dict(tile_override=2048),
+                                  dict(restart=2, max_cycles=1000), dict(restart=30, tile_override=1024),
+                                  dict(ortho=0, restart=5), dict(ortho=0, restart=1, max_cycles=2000),
+                                  dict(ortho=0, batched=0)])
 def test_modes_agree(opts):
     require_gpu()
     p = random_problem(31, (33, 30, 28), S=3, fill=0.6)
     _check_parity(p, 2, **opts)
 
 
-def test_batched_graph_and_unbatched_are_bit_identical():
+@pytest.mark.parametrize("ortho", [0, 1])
+def test_batched_graph_and_unbatched_are_bit_identical(ortho):
     require_gpu()
     p = random_problem(32, (29, 31, 27), S=3, fill=0.6)
-    tile = dict(tile_override=2048)         # the reduction order follows the work split
+    tile = dict(tile_override=2048, ortho=ortho)   # the reduction order follows the work split
     ref, _ = gpu_run(p, 2, 1e-10, **tile)
     for opts in (dict(batched=0), dict(use_graph=0), dict(batched=0, use_graph=0)):
         got, _ = gpu_run(p, 2, 1e-10, **tile, **opts)

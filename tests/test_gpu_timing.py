@@ -9,11 +9,18 @@ from synth import random_problem
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("opts", [dict(), dict(use_graph=0), dict(batched=0)])
+@pytest.mark.parametrize("opts", [dict(), dict(use_graph=0), dict(batched=0), dict(ortho=0),
+                                  dict(ortho=0, batched=0)])
 @pytest.mark.parametrize("kind,j", [(2, 3), (1, 0), (3, 5), (4, 0), (5, 0)])
 def test_timing_hook(opts, kind, j):
     torch = require_gpu()
-    from paper_2505_03067_amd import Solver
+    from paper_2505_03067_amd import MPM_ORTHO_DCGS2, MpmError, Solver
+    if kind == 3 and opts.get("ortho", MPM_ORTHO_DCGS2) == MPM_ORTHO_DCGS2:
+        # the delayed scheme has no separate axpy+norm kernel: refused
+        with Solver(3, 1) as s:
+            with pytest.raises(MpmError):
+                s.time_kernel(kind, j)
+        return
     p = random_problem(71, (30, 27, 25), S=3, fill=0.6)
     d = to_dev(p)
     res = []
@@ -55,3 +62,29 @@ def test_autotuned_split_is_reported_and_parity_holds():
     for sp in range(3):
         err = np.linalg.norm(got[sp][mb] - want[sp][mb]) / np.linalg.norm(want[sp][mb])
         assert err <= 1e-8
+
+
+@pytest.mark.parametrize("kind,j", [(1, 4), (5, 0)])
+def test_timing_repeat_leaves_results_unchanged(kind, j):
+    """Repeated back-to-back launches of a kernel whose output depends on its inputs
+    alone change nothing; the launch count includes every repeat."""
+    torch = require_gpu()
+    from paper_2505_03067_amd import MpmError, Solver
+    p = random_problem(73, (28, 26, 24), S=3, fill=0.6)
+    d = to_dev(p)
+    res, counts = [], []
+    for rep in (0, 1, 7):
+        f = torch.from_numpy(p.c0).cuda()
+        with Solver(3, 1, tile_override=1024) as s:
+            s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, 1.0, 1.0)
+            if rep:
+                s.time_kernel(kind, j, rep)
+            for _ in range(2):
+                s.step([f], 1e-10)
+            counts.append(s.kernel_timing()["launches"])
+            if rep == 7:
+                with pytest.raises(MpmError):
+                    s.time_kernel(2, j, 2)          # the axpy kernel updates its input in place
+        res.append(f.cpu().numpy())
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
+    assert counts[0] == 0 and counts[1] >= 1 and counts[2] == 7 * counts[1]

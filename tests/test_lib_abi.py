@@ -18,6 +18,21 @@ def test_library_exports_every_header_symbol():
         assert hasattr(L, name), name
 
 
+def test_binding_argument_counts_match_header():
+    """Every declaration in include/mpm.h has as many parameters as the binding passes."""
+    import re
+    text = open(b.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    decls = dict(re.findall(r"\b(mpm_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text))
+    L = m.lib()
+    for name, params in decls.items():
+        params = params.strip()
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        fn = getattr(L, name)
+        if fn.argtypes is not None:
+            assert len(fn.argtypes) == n, (name, n, len(fn.argtypes))
+
+
 def test_default_options():
     o = m.mpm_default_options()
     assert o.restart == 30 and o.max_cycles == 50
@@ -42,7 +57,7 @@ def test_create_rejects_bad_sizes(ns, npb):
 
 @pytest.mark.parametrize("field,value", [("restart", 0), ("restart", 31), ("precision", 7),
                                          ("max_cycles", 0), ("inner_rtol", 2.0),
-                                         ("tile_override", 1000), ("warm_start", 9)])
+                                         ("tile_override", 1000), ("warm_start", 9), ("ortho", 2)])
 def test_create_rejects_bad_options(field, value):
     o = m.mpm_default_options()
     setattr(o, field, value)
