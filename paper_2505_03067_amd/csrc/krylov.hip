@@ -49,6 +49,16 @@ constexpr int kRowP3 = kRowP2 + kMaxM + 1;  // K3: ||w||^2
 static_assert(kRowP3 + 1 <= kPartRows, "partial rows");
 
 // ------------------------------------------------------------------ helpers
+// Pointers read from a block record are generic to the compiler, and generic (flat)
+// loads make it wait for every outstanding load at once; these arrays live in device
+// global memory, which the address-space cast states.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ inline gptr<T> as_global(const T* p) {
+    return (gptr<T>)p;
+}
+
 template <typename T>
 struct VW {
     static constexpr int n = 16 / sizeof(T);
@@ -73,20 +83,49 @@ __device__ inline void st16(T* p, const T (&v)[VW<T>::n]) {
     }
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ inline void ldg16(gptr<T> p, T (&o)[VW<T>::n]) {
+    if constexpr (sizeof(T) == 4) {
+        const f32x4 t = *(const __attribute__((address_space(1))) f32x4*)p;
+        o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+    } else {
+        const f64x2 t = *(const __attribute__((address_space(1))) f64x2*)p;
+        o[0] = t.x; o[1] = t.y;
+    }
+}
+
 __device__ inline double wsum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-// Block-reduce NV per-thread sums and store them in slot 'slot' of rows 0..NV-1.
+// Wave sums of NV values per lane, all rows advancing through the butterfly together
+// (the exchanges of one stage are independent, so they overlap in the LDS pipeline).
 template <int NV>
-__device__ inline void block_partials(const double (&acc)[NV], double* part, int nslots, int slot) {
+__device__ inline void wsum_rows(double (&v)[NV]) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], o);
+    }
+}
+
+// Block-reduce NV per-thread sums and store them in slot 'slot' of rows 0..NV-1.
+template <int NV, typename A>
+__device__ inline void block_partials(const A (&acc)[NV], double* part, int nslots, int slot) {
     __shared__ double sh[kWaves][NV];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double t[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double t = wsum(acc[v]);
-        if (lane == 0) sh[w][v] = t;
+    for (int v = 0; v < NV; ++v) t[v] = (double)acc[v];
+    wsum_rows<NV>(t);
+    if (lane == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sh[w][v] = t[v];
     }
     __syncthreads();
     for (int v = threadIdx.x; v < NV; v += kThreads) {
@@ -97,28 +136,62 @@ __device__ inline void block_partials(const double (&acc)[NV], double* part, int
     }
 }
 
-// Sum rows 0..NV-1 of a system's partial slots, in block order, into out[] (shared).
-// Wave w owns rows w, w + 4, ...; all loads are issued before any row is reduced.
+// Loads of one block's share of a system's partial sums (rows w, w + kWaves, ... of
+// wave w; lane i takes slots i, i + 64, ... up to four of them per row), issued
+// together; sum_partials finishes the reduction into out[] (shared).  Every block
+// sums in the same order, so all hold bit-identical totals.
 template <int NV>
-__device__ inline void reduce_partials(const double* part, int nslots, int slot0, int nb, double* out) {
-    constexpr int R = (NV + kWaves - 1) / kWaves;
+struct PartLoad {
+    static constexpr int R = (NV + kWaves - 1) / kWaves;
+    double t[R][4];
+};
+
+template <int NV>
+__device__ inline void load_partials(const double* part, int nslots, int slot0, int nb, PartLoad<NV>& pl) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < PartLoad<NV>::R; ++r) {
+        const int v = w + r * kWaves;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = lane + 64 * q;
+            pl.t[r][q] = (v < NV && i < nb) ? part[(long long)v * nslots + slot0 + i] : 0.0;
+        }
+    }
+}
+
+template <int NV>
+__device__ inline void sum_partials(const double* part, int nslots, int slot0, int nb, PartLoad<NV>& pl,
+                                    double* out) {
+    constexpr int R = PartLoad<NV>::R;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double t[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) t[r] = 0.0;
-    for (int i = lane; i < nb; i += 64) {
+    for (int r = 0; r < R; ++r) t[r] = ((pl.t[r][0] + pl.t[r][1]) + pl.t[r][2]) + pl.t[r][3];
+    if (nb > 256) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int v = w + r * kWaves;
-            if (v < NV) t[r] += part[(long long)v * nslots + slot0 + i];
+            if (v < NV)
+                for (int i = lane + 256; i < nb; i += 64) t[r] += part[(long long)v * nslots + slot0 + i];
         }
     }
+    wsum_rows<R>(t);
+    if (lane == 0) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int v = w + r * kWaves;
-        const double sum = wsum(t[r]);
-        if (v < NV && lane == 0) out[v] = sum;
+        for (int r = 0; r < R; ++r) {
+            const int v = w + r * kWaves;
+            if (v < NV) out[v] = t[r];
+        }
     }
+}
+
+// Sum rows 0..NV-1 of a system's partial slots into out[] (shared), then synchronise.
+template <int NV>
+__device__ inline void reduce_partials(const double* part, int nslots, int slot0, int nb, double* out) {
+    PartLoad<NV> pl;
+    load_partials<NV>(part, nslots, slot0, nb, pl);
+    sum_partials<NV>(part, nslots, slot0, nb, pl, out);
     __syncthreads();
 }
 
@@ -731,35 +804,73 @@ constexpr int kRowD = 3;
 static_assert(kRowD + 2 * kMaxM + 2 <= kPartRows, "partial rows");
 
 // Scaled stencil B = S A S on VW consecutive unknowns of the block's system, addressed
-// from the block record alone.  Returns the centre values of v in xv.
+// from the block record alone, in three phases so that the memory system sees as few
+// dependent round trips as possible: (1) the neighbour indices are requested first;
+// (2) the caller's own loads (basis vectors) and the stencil's direct operands
+// follow; (3) once the indices are in, the neighbour values are gathered while the
+// rest is still in flight.
 template <typename T>
-__device__ inline void stencil_blk(const T* __restrict__ v, const Block& blk, long long u0, int l0,
-                                   T (&xv)[VW<T>::n], T (&out)[VW<T>::n]) {
-    constexpr int n = VW<T>::n;
-    const T* __restrict__ c = (const T*)blk.c;
-    const long long loc0 = blk.locbase + l0;
-    T cx[n], cy[n], cz[n];
+struct StencilIn {
+    static constexpr int n = VW<T>::n;
     int4 nb[n];
-    ld16(v + u0, xv);
-    ld16(c + loc0, cx);
-    ld16(c + blk.tot + loc0, cy);
-    ld16(c + 2 * blk.tot + loc0, cz);
+    T xv[n], cx[n], cy[n], cz[n];
+    T vm, vp, cxm;
+};
+
+template <typename T>
+__device__ inline void stencil_idx(const Block& blk, int l0, StencilIn<T>& si) {
+    const __attribute__((address_space(1))) i32x4* nbr = (const __attribute__((address_space(1))) i32x4*)blk.nbr;
 #pragma unroll
-    for (int e = 0; e < n; ++e) nb[e] = blk.nbr[l0 + e];
-    const T vm = v[u0 - 1], vp = v[u0 + n];
-    const T cxm = c[loc0 - 1];
+    for (int e = 0; e < StencilIn<T>::n; ++e) {
+        const i32x4 t = nbr[l0 + e];
+        si.nb[e] = make_int4(t.x, t.y, t.z, t.w);
+    }
+}
+
+template <typename T>
+__device__ inline void stencil_direct(const T* __restrict__ v, const Block& blk, long long u0, int l0,
+                                      StencilIn<T>& si) {
+    constexpr int n = VW<T>::n;
+    const gptr<T> c = as_global((const T*)blk.c);
+    const long long loc0 = blk.locbase + l0;
+    ld16(v + u0, si.xv);
+    ldg16(c + loc0, si.cx);
+    ldg16(c + blk.tot + loc0, si.cy);
+    ldg16(c + 2 * blk.tot + loc0, si.cz);
+    si.vm = v[u0 - 1];
+    si.vp = v[u0 + n];
+    si.cxm = c[loc0 - 1];
+}
+
+template <typename T>
+__device__ inline void stencil_finish(const T* __restrict__ v, const Block& blk, int l0, const StencilIn<T>& si,
+                                      T (&out)[VW<T>::n]) {
+    constexpr int n = VW<T>::n;
+    const gptr<T> c = as_global((const T*)blk.c);
+    T gyp[n], gym[n], cym[n], gzp[n], gzm[n], czm[n];
 #pragma unroll
     for (int e = 0; e < n; ++e) {
-        const T left = e == 0 ? vm : xv[e - 1];
-        const T leftc = e == 0 ? cxm : cx[e - 1];
-        const T right = e == n - 1 ? vp : xv[e + 1];
-        T r = xv[e];
-        r += cx[e] * right;
+        gyp[e] = v[blk.base + si.nb[e].y];
+        gym[e] = v[blk.base + si.nb[e].x];
+        cym[e] = c[blk.tot + blk.locbase + si.nb[e].x];
+        gzp[e] = v[blk.base + si.nb[e].w];
+        gzm[e] = v[blk.base + si.nb[e].z];
+        czm[e] = c[2 * blk.tot + blk.locbase + si.nb[e].z];
+    }
+    // keep the gathers ahead of any arithmetic on the direct operands
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < n; ++e) {
+        const T left = e == 0 ? si.vm : si.xv[e - 1];
+        const T leftc = e == 0 ? si.cxm : si.cx[e - 1];
+        const T right = e == n - 1 ? si.vp : si.xv[e + 1];
+        T r = si.xv[e];
+        r += si.cx[e] * right;
         r += leftc * left;
-        r += cy[e] * v[blk.base + nb[e].y];
-        r += c[blk.tot + blk.locbase + nb[e].x] * v[blk.base + nb[e].x];
-        r += cz[e] * v[blk.base + nb[e].w];
-        r += c[2 * blk.tot + blk.locbase + nb[e].z] * v[blk.base + nb[e].z];
+        r += si.cy[e] * gyp[e];
+        r += cym[e] * gym[e];
+        r += si.cz[e] * gzp[e];
+        r += czm[e] * gzm[e];
         out[e] = (l0 + e < blk.N) ? r : T(0);
     }
 }
@@ -783,16 +894,23 @@ __global__ __launch_bounds__(kThreads) void k_dc_spmv_dot(KArgs<T> a) {
     T sc = T(1);
     if constexpr (J == 0) sc = (T)rdl(vs0v, blk.sys);
     const T* U = a.V + (long long)J * a.ldv;
-    double acc[NR];
+    // per-thread sums in the Krylov type (a few products each), block sums in FP64
+    T acc[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+    for (int k = 0; k < NR; ++k) acc[k] = T(0);
     for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
         const int l0 = (int)(u0 - blk.base);
+        StencilIn<T> si;
+        stencil_idx<T>(blk, l0, si);
+        __builtin_amdgcn_sched_barrier(0);
         T vk[J > 0 ? J : 1][n];
 #pragma unroll
         for (int k = 0; k < J; ++k) ld16(a.V + (long long)k * a.ldv + u0, vk[k]);
-        T uv[n], z[n];
-        stencil_blk<T>(U, blk, u0, l0, uv, z);
+        stencil_direct<T>(U, blk, u0, l0, si);
+        __builtin_amdgcn_sched_barrier(0);
+        T z[n];
+        stencil_finish<T>(U, blk, l0, si, z);
+        const T (&uv)[n] = si.xv;
         if constexpr (J == 0) {
 #pragma unroll
             for (int e = 0; e < n; ++e) z[e] *= sc;
@@ -800,20 +918,20 @@ __global__ __launch_bounds__(kThreads) void k_dc_spmv_dot(KArgs<T> a) {
         st16(a.W + u0, z);
         if constexpr (J == 0) {
 #pragma unroll
-            for (int e = 0; e < n; ++e) acc[0] += (double)uv[e] * (double)z[e];
+            for (int e = 0; e < n; ++e) acc[0] += uv[e] * z[e];
         } else {
 #pragma unroll
             for (int k = 0; k < J; ++k) {
 #pragma unroll
                 for (int e = 0; e < n; ++e) {
-                    acc[k] += (double)vk[k][e] * (double)uv[e];
-                    acc[J + k] += (double)vk[k][e] * (double)z[e];
+                    acc[k] += vk[k][e] * uv[e];
+                    acc[J + k] += vk[k][e] * z[e];
                 }
             }
 #pragma unroll
             for (int e = 0; e < n; ++e) {
-                acc[2 * J] += (double)uv[e] * (double)uv[e];
-                acc[2 * J + 1] += (double)uv[e] * (double)z[e];
+                acc[2 * J] += uv[e] * uv[e];
+                acc[2 * J + 1] += uv[e] * z[e];
             }
         }
     }
@@ -831,9 +949,9 @@ __global__ __launch_bounds__(kThreads) void k_dc_lastdots(KArgs<T> a) {
     if (blk.sys < 0) return;
     if (!__builtin_amdgcn_readlane(actv, blk.sys)) return;
     const T* U = a.V + (long long)J * a.ldv;
-    double acc[NR];
+    T acc[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+    for (int k = 0; k < NR; ++k) acc[k] = T(0);
     for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
         T uv[n];
         ld16(U + u0, uv);
@@ -842,50 +960,12 @@ __global__ __launch_bounds__(kThreads) void k_dc_lastdots(KArgs<T> a) {
             T vk[n];
             ld16(a.V + (long long)k * a.ldv + u0, vk);
 #pragma unroll
-            for (int e = 0; e < n; ++e) acc[k] += (double)vk[e] * (double)uv[e];
+            for (int e = 0; e < n; ++e) acc[k] += vk[e] * uv[e];
         }
 #pragma unroll
-        for (int e = 0; e < n; ++e) acc[2 * J] += (double)uv[e] * (double)uv[e];
+        for (int e = 0; e < n; ++e) acc[2 * J] += uv[e] * uv[e];
     }
     block_partials<NR>(acc, a.part + (long long)kRowD * a.nslots, a.nslots, blk.slot);
-}
-
-// Loads of one block's share of a system's partial sums (rows w, w + kWaves, ... of
-// wave w; lane i takes slots i, i + 64, ... up to four of them per row), issued
-// together; sum_partials finishes the reduction into out[] (shared) in block order.
-template <int NV>
-struct PartLoad {
-    static constexpr int R = (NV + kWaves - 1) / kWaves;
-    double t[R][4];
-};
-
-template <int NV>
-__device__ inline void load_partials(const double* part, int nslots, int slot0, int nb, PartLoad<NV>& pl) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int r = 0; r < PartLoad<NV>::R; ++r) {
-        const int v = w + r * kWaves;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = lane + 64 * q;
-            pl.t[r][q] = (v < NV && i < nb) ? part[(long long)v * nslots + slot0 + i] : 0.0;
-        }
-    }
-}
-
-template <int NV>
-__device__ inline void sum_partials(const double* part, int nslots, int slot0, int nb, PartLoad<NV>& pl,
-                                    double* out) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int r = 0; r < PartLoad<NV>::R; ++r) {
-        const int v = w + r * kWaves;
-        double t = ((pl.t[r][0] + pl.t[r][1]) + pl.t[r][2]) + pl.t[r][3];
-        if (v < NV)
-            for (int i = lane + 256; i < nb; i += 64) t += part[(long long)v * nslots + slot0 + i];
-        const double sum = wsum(t);
-        if (v < NV && lane == 0) out[v] = sum;
-    }
 }
 
 // Scalar work of step J >= 1 (wave 0 of every block, one Hessenberg row per lane; only
