@@ -71,11 +71,15 @@ def alg_bytes_active(kind, j, U, precision, S, dcgs2):
 
 def measured_traffic(kernel, workload, tile):
     """HBM bytes per active launch from the committed rocprofv3 counter summary of this
-    kernel and workload (None if there is none for it)."""
-    path = os.path.join(ROOT, "profiles", "k_axpy_dot_config2_traffic.md")
-    if kernel != "k_axpy_dot<float,10>" or workload != "config2" or tile or not os.path.exists(path):
+    kernel and workload (None if there is none for it, or for another work split)."""
+    base = kernel.split("<")[0]
+    path = os.path.join(ROOT, "profiles", f"{base}_{workload}_traffic.md")
+    if tile or not os.path.exists(path):
         return None
-    for line in open(path):
+    text = open(path).read()
+    if f"kernel: {kernel}" not in text:
+        return None
+    for line in text.splitlines():
         if "traffic_bytes_per_active_launch:" in line:
             return int(line.split("traffic_bytes_per_active_launch:")[1].split("*")[0].strip().rstrip("."))
     return None

@@ -103,30 +103,59 @@ __device__ inline double wsum(double v) {
     return v;
 }
 
-// Wave sums of NV values per lane, all rows advancing through the butterfly together
-// (the exchanges of one stage are independent, so they overlap in the LDS pipeline).
+// Reduce-scatter over the wave: NV values per lane in, one row sum per lane out.  Each
+// butterfly stage halves the rows a lane carries (the lane with the stage's bit set
+// keeps the upper half, its partner the lower half), so the exchanges number about
+// 2 NV instead of 6 NV for separate wave sums; the remaining stages are plain
+// exchanges.  Returns the sum of row 'row'; every lane with the same row holds the
+// same value (lane representative when its low bits are zero).  The order of the
+// additions is fixed, so every wave and block computes identical totals.
 template <int NV>
-__device__ inline void wsum_rows(double (&v)[NV]) {
+struct RS {
+    static constexpr int K = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : NV <= 16 ? 16 : NV <= 32 ? 32 : 64;
+    static constexpr int L = K == 1 ? 0 : K == 2 ? 1 : K == 4 ? 2 : K == 8 ? 3 : K == 16 ? 4 : K == 32 ? 5 : 6;
+    static_assert(NV <= 64, "at most 64 rows");
+};
+
+template <int NV>
+__device__ inline double wave_reduce_scatter(const double (&v)[NV], int& row, bool& rep) {
+    constexpr int K = RS<NV>::K, L = RS<NV>::L;
+    const int lane = threadIdx.x & 63;
+    double w[K];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int i = 0; i < K; ++i) w[i] = i < NV ? v[i] : 0.0;
+    row = 0;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], o);
+    for (int st = 0; st < L; ++st) {
+        const int o = 32 >> st, half = K >> (st + 1);
+        const bool bit = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const double send = bit ? w[i] : w[i + half];
+            const double keep = bit ? w[i + half] : w[i];
+            w[i] = keep + __shfl_xor(send, o);
+        }
+        if (bit) row += half;
     }
+    double r = w[0];
+#pragma unroll
+    for (int st = L; st < 6; ++st) r += __shfl_xor(r, 32 >> st);
+    rep = (lane & ((1 << (6 - L)) - 1)) == 0;
+    return r;
 }
 
 // Block-reduce NV per-thread sums and store them in slot 'slot' of rows 0..NV-1.
 template <int NV, typename A>
 __device__ inline void block_partials(const A (&acc)[NV], double* part, int nslots, int slot) {
     __shared__ double sh[kWaves][NV];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int w = threadIdx.x >> 6;
     double t[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) t[v] = (double)acc[v];
-    wsum_rows<NV>(t);
-    if (lane == 0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sh[w][v] = t[v];
-    }
+    int row;
+    bool rep;
+    const double r = wave_reduce_scatter<NV>(t, row, rep);
+    if (rep && row < NV) sh[w][row] = r;
     __syncthreads();
     for (int v = threadIdx.x; v < NV; v += kThreads) {
         double t = sh[0][v];
@@ -176,14 +205,12 @@ __device__ inline void sum_partials(const double* part, int nslots, int slot0, i
                 for (int i = lane + 256; i < nb; i += 64) t[r] += part[(long long)v * nslots + slot0 + i];
         }
     }
-    wsum_rows<R>(t);
-    if (lane == 0) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int v = w + r * kWaves;
-            if (v < NV) out[v] = t[r];
-        }
-    }
+    int row;
+    bool rep;
+    const double sum = wave_reduce_scatter<R>(t, row, rep);
+    const int v = w + row * kWaves;
+    if (rep && row < R && v < NV) out[v] = sum;
+    (void)lane;
 }
 
 // Sum rows 0..NV-1 of a system's partial slots into out[] (shared), then synchronise.
