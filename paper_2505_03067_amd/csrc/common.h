@@ -63,7 +63,16 @@ struct Block {
     long long locbase;   // problem-local index of l = 0 (species * Npad)
     const int4* nbr;     // the problem's neighbour table
     const void* c;       // the problem's scaled couplings in the Krylov type
+    const double* a64;   // the problem's unscaled couplings (+x, +y, +z planes)
+    const double* d64;   // A_PP
+    const double* sc64;  // diag(A)^(-1/2)
+    const double* q64;   // dt s + Dirichlet terms
+    const int* vox;      // lattice index of each compact voxel
+    int p, s;            // problem and species of the system
+    long long nvox;      // lattice voxels of the problem (species stride of the fields)
+    long long pad;
 };
+static_assert(sizeof(Block) == 128, "block record size");
 
 // Per-system Krylov state.  Within one launch every block reads it and only the
 // system's first block writes it, at entries no block of that launch reads.  The

@@ -302,22 +302,35 @@ __device__ inline double apply_A(const ProbDev& pd, const Where& wh, const doubl
 // Gather c^n from the lattice into x, form b = c^n + q; partials of ||b||^2.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gather(KArgs<T> a) {
+    constexpr int n = 4;
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
-    const ProbDev pd = a.probs[blk.sys / a.S];
-    const Where wh = where_of(a, blk, pd);
-    const double* f = a.fields[wh.p] + (long long)wh.s * pd.nvox;
+    const double* f = a.fields[blk.p] + (long long)blk.s * blk.nvox;
+    const gptr<int> vox = as_global(blk.vox);
+    const gptr<double> q = as_global(blk.q64);
     double acc[1] = {0.0};
-    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
-        const int l = (int)(u - wh.base);
-        double cn = 0.0, bb = 0.0;
-        if (l < pd.N) {
-            cn = f[pd.vox[l]];
-            bb = cn + pd.q64[wh.locbase + l];
+    for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
+        const int l0 = (int)(u0 - blk.base);
+        int vx[n];
+        double qq[n];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            vx[e] = vox[l0 + e];
+            qq[e] = q[blk.locbase + l0 + e];
         }
-        a.x[u] = cn;
-        a.b[u] = bb;
-        acc[0] += bb * bb;
+        double cn[n], bb[n];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            const bool in = l0 + e < blk.N;
+            cn[e] = in ? f[vx[e]] : 0.0;
+            bb[e] = in ? cn[e] + qq[e] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            a.x[u0 + e] = cn[e];
+            a.b[u0 + e] = bb[e];
+            acc[0] += bb[e] * bb[e];
+        }
     }
     block_partials<1>(acc, a.part + (long long)kRowB * a.nslots, a.nslots, blk.slot);
 }
@@ -335,27 +348,84 @@ __device__ inline bool res_skip(const SysK* sk, int mode) {
     }
 }
 
-// r = b - A x (FP64); V_0 = S r; partials of ||r||^2 and ||S r||^2.
+// r = b - A x (FP64); V_0 = S r; partials of ||r||^2 and ||S r||^2.  Two unknowns per
+// thread; the neighbour indices are requested first, the direct operands next, and the
+// neighbour values once the indices are in.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
+    constexpr int n = 2;
+    const int lane = threadIdx.x & 63;
+    const int cv = lane < a.nsys ? a.sk[lane].converged : 0;
+    const int fb = lane < a.nsys ? a.sk[lane].fallback : 0;
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
-    SysK* sk = a.sk + blk.sys;
-    if (res_skip(sk, mode)) return;
-    const ProbDev pd = a.probs[blk.sys / a.S];
-    const Where wh = where_of(a, blk, pd);
+    const bool skip = mode == kResFirst ? false
+                      : mode == kResRevert ? !__builtin_amdgcn_readlane(fb, blk.sys)
+                                           : __builtin_amdgcn_readlane(cv, blk.sys) != 0;
+    if (skip) return;
+    const __attribute__((address_space(1))) i32x4* nbr = (const __attribute__((address_space(1))) i32x4*)blk.nbr;
+    const gptr<double> A = as_global(blk.a64);
+    const gptr<double> d = as_global(blk.d64);
+    const gptr<double> sc = as_global(blk.sc64);
+    const long long tot = blk.tot;
     T* V0 = a.V;
     double acc[2] = {0.0, 0.0};
-    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
-        const int l = (int)(u - wh.base);
-        double r = 0.0, sr = 0.0;
-        if (l < pd.N) {
-            r = a.b[u] - apply_A(pd, wh, a.x, u, l);
-            sr = pd.sc64[wh.locbase + l] * r;
+    for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
+        const int l0 = (int)(u0 - blk.base);
+        const long long loc0 = blk.locbase + l0;
+        int4 nb[n];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            const i32x4 t = nbr[l0 + e];
+            nb[e] = make_int4(t.x, t.y, t.z, t.w);
         }
-        V0[u] = (T)sr;
-        acc[0] += r * r;
-        acc[1] += sr * sr;
+        __builtin_amdgcn_sched_barrier(0);
+        double xv[n], bv[n], dv[n], ax[n], ay[n], az[n], sv[n];
+        ld16(a.x + u0, xv);
+        ld16(a.b + u0, bv);
+        ldg16(d + loc0, dv);
+        ldg16(A + loc0, ax);
+        ldg16(A + tot + loc0, ay);
+        ldg16(A + 2 * tot + loc0, az);
+        ldg16(sc + loc0, sv);
+        const double xm = a.x[u0 - 1], xp = a.x[u0 + n];
+        const double axm = A[loc0 - 1];
+        __builtin_amdgcn_sched_barrier(0);
+        double gyp[n], gym[n], aym[n], gzp[n], gzm[n], azm[n];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            gyp[e] = a.x[blk.base + nb[e].y];
+            gym[e] = a.x[blk.base + nb[e].x];
+            aym[e] = A[tot + blk.locbase + nb[e].x];
+            gzp[e] = a.x[blk.base + nb[e].w];
+            gzm[e] = a.x[blk.base + nb[e].z];
+            azm[e] = A[2 * tot + blk.locbase + nb[e].z];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        T v0[n];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            double r = 0.0, sr = 0.0;
+            if (l0 + e < blk.N) {
+                const double left = e == 0 ? xm : xv[e - 1];
+                const double right = e == n - 1 ? xp : xv[e + 1];
+                const double leftc = e == 0 ? axm : ax[e - 1];
+                double Ax = dv[e] * xv[e];
+                Ax += ax[e] * right;
+                Ax += leftc * left;
+                Ax += ay[e] * gyp[e];
+                Ax += aym[e] * gym[e];
+                Ax += az[e] * gzp[e];
+                Ax += azm[e] * gzm[e];
+                r = bv[e] - Ax;
+                sr = sv[e] * r;
+            }
+            v0[e] = (T)sr;
+            acc[0] += r * r;
+            acc[1] += sr * sr;
+        }
+#pragma unroll
+        for (int e = 0; e < n; ++e) V0[u0 + e] = v0[e];
     }
     block_partials<2>(acc, a.part + (long long)kRowR * a.nslots, a.nslots, blk.slot);
 }
@@ -684,44 +754,71 @@ __global__ __launch_bounds__(kThreads) void k_finish(KArgs<T> a, int sys0) {
     (void)givens_tail<J>(sk, sqrt(red[0]), a.prm->restart, true);
 }
 
-// x += S sum_k y_k V_k (FP64 accumulation of the FP32 or FP64 basis).
+// x += S sum_k y_k V_k (FP64 accumulation of the FP32 or FP64 basis).  The basis
+// vectors are read eight at a time, all eight requested before any is used.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update(KArgs<T> a) {
     constexpr int n = VW<T>::n;
+    constexpr int G = 8;
+    const int lane = threadIdx.x & 63;
+    const int nu = lane < a.nsys ? a.sk[lane].need_update : 0;
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
-    SysK* sk = a.sk + blk.sys;
-    if (!sk->need_update) return;
-    const ProbDev pd = a.probs[blk.sys / a.S];
-    const Where wh = where_of(a, blk, pd);
+    if (!__builtin_amdgcn_readlane(nu, blk.sys)) return;
+    const SysK* sk = a.sk + blk.sys;
     const int m = sk->mcount;
+    const gptr<double> sc = as_global(blk.sc64);
     for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
-        double t[n];
+        const long long loc0 = blk.locbase + (u0 - blk.base);
+        double t[n], xv[n], sv[n];
 #pragma unroll
-        for (int e = 0; e < n; ++e) t[e] = 0.0;
-        for (int k = 0; k < m; ++k) {
-            T vk[n];
-            ld16(a.V + (long long)k * a.ldv + u0, vk);
-            const double yk = sk->y[k];
-#pragma unroll
-            for (int e = 0; e < n; ++e) t[e] += yk * (double)vk[e];
+        for (int e = 0; e < n; ++e) {
+            t[e] = 0.0;
+            xv[e] = a.x[u0 + e];
+            sv[e] = sc[loc0 + e];
         }
-        const long long loc0 = wh.locbase + (u0 - wh.base);
+        for (int k0 = 0; k0 < m; k0 += G) {
+            T vk[G][n];
 #pragma unroll
-        for (int e = 0; e < n; ++e) a.x[u0 + e] += pd.sc64[loc0 + e] * t[e];
+            for (int g = 0; g < G; ++g) {
+                if (k0 + g < m) {
+                    ld16(a.V + (long long)(k0 + g) * a.ldv + u0, vk[g]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < n; ++e) vk[g][e] = T(0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const double yk = k0 + g < m ? sk->y[k0 + g] : 0.0;
+#pragma unroll
+                for (int e = 0; e < n; ++e) t[e] += yk * (double)vk[g][e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < n; ++e) a.x[u0 + e] = xv[e] + sv[e] * t[e];
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_scatter(KArgs<T> a) {
+    constexpr int n = 4;
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
-    const ProbDev pd = a.probs[blk.sys / a.S];
-    const Where wh = where_of(a, blk, pd);
-    double* f = a.fields[wh.p] + (long long)wh.s * pd.nvox;
-    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
-        const int l = (int)(u - wh.base);
-        if (l < pd.N) f[pd.vox[l]] = a.x[u];
+    double* f = a.fields[blk.p] + (long long)blk.s * blk.nvox;
+    const gptr<int> vox = as_global(blk.vox);
+    for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
+        const int l0 = (int)(u0 - blk.base);
+        int vx[n];
+        double xv[n];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            vx[e] = vox[l0 + e];
+            xv[e] = a.x[u0 + e];
+        }
+#pragma unroll
+        for (int e = 0; e < n; ++e)
+            if (l0 + e < blk.N) f[vx[e]] = xv[e];
     }
 }
 
@@ -1404,6 +1501,14 @@ static void build_tables(Ctx* c, long long per) {
                 b.locbase = (long long)s * ph.Npad;
                 b.nbr = ph.nbr;
                 b.c = f64 ? (const void*)ph.c64 : (const void*)ph.c32;
+                b.a64 = ph.a64;
+                b.d64 = ph.d64;
+                b.sc64 = ph.sc64;
+                b.q64 = ph.q64;
+                b.vox = ph.vox;
+                b.p = p;
+                b.s = s;
+                b.nvox = ph.nvox;
                 logical.push_back(b);
             }
             c->sys_count[sys] = nbp;

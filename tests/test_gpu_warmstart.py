@@ -120,19 +120,23 @@ def test_extrapolated_start_parity():
 
 
 def test_learned_warm_start_gains_over_plain():
-    """Train on pairs the solver generates (32^3 tumour patches) and evaluate on unseen
-    patches: the learned start must be accepted and cut the GMRES iterations, while the
-    solution stays within 2 kappa tol of the plain solve."""
+    """Train on pairs the solver generates (456 pairs from 24 tumour patches of 32^3) and
+    evaluate on unseen patches: the learned start must be accepted and cut the GMRES
+    iterations, while the solution stays within 2 kappa tol of the plain solve."""
     torch = require_gpu()
     import paper_2505_03067_amd as m
     from paper_2505_03067_amd import train as tr
-    train_probs = [config4_patch(100 + i, n=32) for i in range(12)]
-    out_scale = tr.estimate_out_scale(train_probs[:3], 6)
-    pairs = list(tr.generate_pairs(train_probs, 12, range(1, 12), out_scale))
+    import time
+    train_probs = [config4_patch(100 + i, n=32) for i in range(24)]
+    out_scale = tr.estimate_out_scale(train_probs[:4], 10)
+    pairs = list(tr.generate_pairs(train_probs, 20, range(1, 20), out_scale))
     net = m.Net(13, 3, [16, 32, 64, 64], seed=7)
-    losses = tr.train(net, pairs, epochs=25, batch=4, lr=2e-3, seed=0)
-    print("losses", [f"{v:.3e}" for v in losses])
-    assert losses[-1] < 0.5 * losses[0]
+    t0 = time.perf_counter()
+    losses = tr.train(net, pairs, epochs=60, batch=4, lr=2e-3, seed=0)
+    print(f"{len(pairs)} pairs, training {time.perf_counter() - t0:.1f} s, losses",
+          [f"{v:.3e}" for v in losses[::5]], flush=True)
+    # the normalised target has unit variance: the network must explain most of it
+    assert losses[-1] < 0.1
     evalp = [config4_patch(10_000 + i, n=32) for i in range(2)]
     it_plain, sps_plain, f_plain, _ = tr.evaluate(evalp, 10, 1e-8)
     it_ws, sps_ws, f_ws, acc = tr.evaluate(evalp, 10, 1e-8, net=net, out_scale=out_scale, warm=m.MPM_WS_NET)
