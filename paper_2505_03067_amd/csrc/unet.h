@@ -41,7 +41,8 @@ struct Net {
     float* outbuf = nullptr;
     bool have_fwd = false;
     // warm-start use
-    double* mse_part = nullptr;
+    double* mse_part = nullptr;        // pinned host copy of the MSE partial sums
+    double* mse_dev = nullptr;         // device partial sums of the MSE
 };
 
 int net_build(Net* n, int in_ch, int out_ch, int levels, const int* widths, uint64_t seed);

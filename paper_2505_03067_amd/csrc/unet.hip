@@ -216,14 +216,14 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
     hipStream_t st = n->stream;
     const long long P0 = (long long)nb * D * H * W;
     const ConvL& l0 = n->layers[0];
-    k_pad_channels<<<blocks_for(P0 * l0.cin_p), 256, 0, st>>>(in, n->in_ch, l0.cin_p, P0, n->xin);
+    k_pad_channels<<<blocks_for(P0), 256, 0, st>>>(in, n->in_ch, l0.cin_p, P0, n->xin);
     const uint16_t* h = n->xin;
     int hch = l0.cin_p;
     int li = 0;
     for (int lvl = 0; lvl < L; ++lvl) {
         if (lvl > 0) {
             const long long Pl = P0 >> (3 * lvl);
-            k_pool2<<<blocks_for(Pl * hch), 256, 0, st>>>(h, hch, hch, nb, D >> (lvl - 1), H >> (lvl - 1),
+            k_pool2<<<blocks_for(Pl * hch / 8), 256, 0, st>>>(h, hch, hch, nb, D >> (lvl - 1), H >> (lvl - 1),
                                                          W >> (lvl - 1), n->pooled[lvl]);
             h = n->pooled[lvl];
         }
@@ -249,7 +249,7 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
     for (int lvl = L - 2; lvl >= 0; --lvl) {
         const long long Pl = P0 >> (3 * lvl);
         const int cu = n->widths[lvl + 1], cs = n->widths[lvl];
-        k_up2_cat<<<blocks_for(Pl * (cu + cs)), 256, 0, st>>>(h, cu, n->act[2 * lvl + 1], cs, nb, D >> lvl, H >> lvl,
+        k_up2_cat<<<blocks_for(Pl * (cu + cs) / 8), 256, 0, st>>>(h, cu, n->act[2 * lvl + 1], cs, nb, D >> lvl, H >> lvl,
                                                                W >> lvl, n->cat[lvl]);
         h = n->cat[lvl];
         hch = cu + cs;
@@ -316,9 +316,6 @@ static int conv_param_grads(Net* n, int li, int lvl, const uint16_t* x, int ldx,
     w.H = n->dims[2] >> lvl;
     w.W = n->dims[3] >> lvl;
     w.per_chunk = per;
-    k_conv_wgrad<<<dim3((unsigned)nchunk, 27), 256, 0, st>>>(w);
-    const long long tot = 27LL * c.cin * c.cout;
-    k_wgrad_reduce<<<blocks_for(tot), 256, 0, st>>>(n->wpart, (int)nchunk, c.cin, c.cout, c.cin_p, c.cout_p, gw);
     if ((size_t)nchunk * c.cout > n->dpart_cap) {
         (void)hipFree(n->dpart);
         n->dpart_cap = std::max<size_t>((size_t)nchunk * c.cout, 64 * 128);
@@ -330,10 +327,11 @@ static int conv_param_grads(Net* n, int li, int lvl, const uint16_t* x, int ldx,
             return MPM_ENOMEM;
         }
     }
-    if (gb) {
-        k_bias_part<<<(unsigned)nchunk, 256, 0, st>>>(g, gate, c.cout, c.cout, P, per, n->dpart);
-        k_bias_reduce<<<1, 128, 0, st>>>(n->dpart, (int)nchunk, c.cout, gb);
-    }
+    w.bpart = gb ? n->dpart : nullptr;
+    k_conv_wgrad<<<dim3((unsigned)nchunk, 27), 256, 0, st>>>(w);
+    const long long tot = 27LL * c.cin * c.cout;
+    k_wgrad_reduce<<<blocks_for(tot), 256, 0, st>>>(n->wpart, (int)nchunk, c.cin, c.cout, c.cin_p, c.cout_p, gw);
+    if (gb) k_bias_reduce<<<1, 128, 0, st>>>(n->dpart, (int)nchunk, c.cout, gb);
     MPM_HIP(hipGetLastError());
     return MPM_OK;
 }
@@ -405,7 +403,7 @@ int net_backward(Net* n, const float* dout) {
         --li;
         // gradient wrt the upsampled input -> gradient wrt the output of layer li (one level deeper)
         const long long Pd = P0 >> (3 * (lvl + 1));
-        k_up2_bwd<<<blocks_for(Pd * cu), 256, 0, st>>>(n->dcat[lvl], cu + cs, cu, nb, D >> (lvl + 1), H >> (lvl + 1),
+        k_up2_bwd<<<blocks_for(Pd * cu / 8), 256, 0, st>>>(n->dcat[lvl], cu + cs, cu, nb, D >> (lvl + 1), H >> (lvl + 1),
                                                       W >> (lvl + 1), n->gin[li]);
         g = n->gin[li];
     }
@@ -424,7 +422,7 @@ int net_backward(Net* n, const float* dout) {
         --li;
         const int c = n->widths[lvl - 1];
         const long long Pu = P0 >> (3 * (lvl - 1));
-        k_pool2_bwd_add<<<blocks_for(Pu * c), 256, 0, st>>>(n->gscratch, c,
+        k_pool2_bwd_add<<<blocks_for(Pu * c / 8), 256, 0, st>>>(n->gscratch, c,
                                                            lvl - 1 <= L - 2 ? n->dcat[lvl - 1] + n->widths[lvl] : nullptr,
                                                            n->widths[lvl] + c, nb, D >> (lvl - 1), H >> (lvl - 1),
                                                            W >> (lvl - 1), n->gin[li]);
@@ -539,13 +537,12 @@ extern "C" int32_t mpm_net_mse(mpm_net net, const float* out, const float* targe
     }
     const int nb = 512;
     if (!n->mse_part) MPM_HIP(hipHostMalloc((void**)&n->mse_part, nb * sizeof(double), hipHostMallocDefault));
-    double* dpart = nullptr;
-    MPM_HIP(hipMalloc(&dpart, nb * sizeof(double)));
-    k_mse<<<nb, 256, 0, n->stream>>>(out, target, count, grad_out, dpart);
+    if (!n->mse_dev) MPM_HIP(hipMalloc(&n->mse_dev, nb * sizeof(double)));
+    k_mse<<<nb, 256, 0, n->stream>>>(out, target, count, grad_out, n->mse_dev);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(n->mse_part, dpart, nb * sizeof(double), hipMemcpyDeviceToHost, n->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(n->mse_part, n->mse_dev, nb * sizeof(double), hipMemcpyDeviceToHost, n->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
-    (void)hipFree(dpart);
     if (e != hipSuccess) return hip_fail(e, "mpm_net_mse");
     double s = 0.0;
     for (int i = 0; i < nb; ++i) s += n->mse_part[i];
@@ -571,6 +568,7 @@ extern "C" int32_t mpm_net_destroy(mpm_net net) {
     Net* n = (Net*)net;
     if (!n) return MPM_OK;
     if (n->mse_part) (void)hipHostFree(n->mse_part);
+    (void)hipFree(n->mse_dev);
     net_free(n);
     delete n;
     return MPM_OK;

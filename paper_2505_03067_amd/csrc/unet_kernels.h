@@ -143,6 +143,7 @@ struct WgradArgs {
     const uint16_t* g;     // output gradient [P][ldg]
     const uint16_t* gate;  // layer output [P][ldg] (ReLU gate) or null
     float* part;           // [nchunk][27][cin_p][cout_p]
+    float* bpart;          // optional [nchunk][cout]: bias-gradient partials (from the centre tap)
     int ldx, cin_p, ldg, cout_p;
     int n, D, H, W;
     long long per_chunk;   // voxels per block (multiple of 64)
@@ -168,6 +169,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int cgx = a.cin_p / 8, cgg = a.cout_p / 8;   // 16-byte groups per voxel
+    // the centre tap's block also sums the gated gradient per channel (bias gradient)
+    const bool bias = a.bpart && tap == 13;
+    float bsum = 0.f;
     for (long long t0 = pa; t0 < pb; t0 += PT) {
         __syncthreads();
         // stage x (shifted by the tap) and the gated gradient, transposed
@@ -216,6 +220,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
             }
         }
         __syncthreads();
+        if (bias && (int)threadIdx.x < a.ldg) {
+            const uint16_t* row = gs + threadIdx.x * PT;
+            for (int pv = 0; pv < PT; ++pv) bsum += bf2f(row[pv]);
+        }
 #pragma unroll
         for (int kk = 0; kk < PT; kk += 32) {
             const int kq = kk + 8 * (lane >> 4);
@@ -232,6 +240,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
             }
         }
     }
+    if (bias && (int)threadIdx.x < a.ldg) a.bpart[(long long)blockIdx.x * a.ldg + threadIdx.x] = bsum;
     float* out = a.part + ((long long)blockIdx.x * 27 + tap) * a.cin_p * a.cout_p;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -263,31 +272,6 @@ __global__ void k_wgrad_reduce(const float* part, int nchunk, int cin, int cout,
     grad[i] += (float)s;
 }
 
-// Bias gradient: per-chunk channel sums of g * (gate > 0), then a fixed-order reduce.
-__global__ __launch_bounds__(256) void k_bias_part(const uint16_t* g, const uint16_t* gate, int ldg, int cout,
-                                                   long long P, long long per_chunk, float* part) {
-    const long long pa = (long long)blockIdx.x * per_chunk;
-    const long long pb = pa + per_chunk < P ? pa + per_chunk : P;
-    __shared__ float sh[256];
-    const int c = threadIdx.x % 64;       // channel (cout <= 64 per pass of 64 lanes)
-    const int row = threadIdx.x / 64;     // 4 voxel phases
-    for (int cb = 0; cb < cout; cb += 64) {
-        float s = 0.f;
-        const int ch = cb + c;
-        if (ch < cout) {
-            for (long long p = pa + row; p < pb; p += 4) {
-                const float v = bf2f(g[p * ldg + ch]);
-                if (!gate || bf2f(gate[p * ldg + ch]) > 0.f) s += v;
-            }
-        }
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        if (row == 0 && ch < cout)
-            part[(long long)blockIdx.x * cout + ch] = sh[c] + sh[64 + c] + sh[128 + c] + sh[192 + c];
-        __syncthreads();
-    }
-}
-
 __global__ void k_bias_reduce(const float* part, int nchunk, int cout, float* grad) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= cout) return;
@@ -296,129 +280,206 @@ __global__ void k_bias_reduce(const float* part, int nchunk, int cout, float* gr
     grad[o] += (float)s;
 }
 
-// 2x2x2 average pooling of channels [0, c) (output stride c).
+// Eight BF16 values as one 16-byte word, and their FP32 values.
+__device__ inline void unpack8(const uint4 t, float (&f)[8]) {
+    const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = __uint_as_float(w[i] << 16);
+        f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+}
+__device__ inline uint4 pack8(const float (&f)[8]) {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Voxel coordinates of linear index p in an n x D x H x W grid.
+struct Vox {
+    int x, y, z, b;
+};
+__device__ inline Vox decode(long long p, int D, int H, int W) {
+    Vox v;
+    long long r = p / W;
+    v.x = (int)(p - r * W);
+    const long long r2 = r / H;
+    v.y = (int)(r - r2 * H);
+    const long long r3 = r2 / D;
+    v.z = (int)(r2 - r3 * D);
+    v.b = (int)r3;
+    return v;
+}
+
+// 2x2x2 average pooling of channels [0, c) (input stride ldx, output stride c); one
+// thread per output voxel and group of 8 channels.
 __global__ void k_pool2(const uint16_t* x, int ldx, int c, int n, int D, int H, int W, uint16_t* y) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int d = D / 2, h = H / 2, w = W / 2;
-    const long long tot = (long long)n * d * h * w * c;
+    const int G = c / 8;
+    const long long tot = (long long)n * d * h * w * G;
     if (i >= tot) return;
-    const int ch = (int)(i % c);
-    long long r = i / c;
-    const int xo = (int)(r % w); r /= w;
-    const int yo = (int)(r % h); r /= h;
-    const int zo = (int)(r % d);
-    const long long nb = r / d;
-    float s = 0.f;
+    const int g = (int)(i % G);
+    const long long po = i / G;
+    const Vox v = decode(po, d, h, w);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const long long q = ((nb * D + 2 * zo + (k >> 2)) * H + 2 * yo + ((k >> 1) & 1)) * W + 2 * xo + (k & 1);
-        s += bf2f(x[q * ldx + ch]);
+        const long long q = (((long long)v.b * D + 2 * v.z + (k >> 2)) * H + 2 * v.y + ((k >> 1) & 1)) * W + 2 * v.x + (k & 1);
+        float f[8];
+        unpack8(*reinterpret_cast<const uint4*>(x + q * ldx + 8 * g), f);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] += f[e];
     }
-    y[i] = f2bf(s * 0.125f);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] *= 0.125f;
+    *reinterpret_cast<uint4*>(y + po * c + 8 * g) = pack8(s);
 }
 
-// out[child] = sum(dpool[parent] / 8 (+ dskip[child] channels)) for the encoder skip.
+// out[child] = dpool[parent] / 8 (+ dskip[child] channels) for the encoder skip; one
+// thread per voxel and group of 8 channels.
 __global__ void k_pool2_bwd_add(const uint16_t* dpool, int c, const uint16_t* dskip, int lds, int n, int D, int H,
                                 int W, uint16_t* out) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long tot = (long long)n * D * H * W * c;
+    const int G = c / 8;
+    const long long tot = (long long)n * D * H * W * G;
     if (i >= tot) return;
-    const int ch = (int)(i % c);
-    long long r = i / c;
-    const int x = (int)(r % W); r /= W;
-    const int yv = (int)(r % H); r /= H;
-    const int z = (int)(r % D);
-    const long long nb = r / D;
-    const long long q = ((nb * (D / 2) + z / 2) * (H / 2) + yv / 2) * (W / 2) + x / 2;
-    float v = bf2f(dpool[q * c + ch]) * 0.125f;
-    if (dskip) v += bf2f(dskip[(i / c) * lds + ch]);
-    out[i] = f2bf(v);
+    const int g = (int)(i % G);
+    const long long p = i / G;
+    const Vox v = decode(p, D, H, W);
+    const long long q = (((long long)v.b * (D / 2) + v.z / 2) * (H / 2) + v.y / 2) * (W / 2) + v.x / 2;
+    float f[8];
+    unpack8(*reinterpret_cast<const uint4*>(dpool + q * c + 8 * g), f);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] *= 0.125f;
+    if (dskip) {
+        float k[8];
+        unpack8(*reinterpret_cast<const uint4*>(dskip + p * lds + 8 * g), k);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) f[e] += k[e];
+    }
+    *reinterpret_cast<uint4*>(out + p * c + 8 * g) = pack8(f);
 }
 
 // Nearest x2 upsampling of h (c channels) into channels [0, c) of a concat buffer with
-// stride ldc, and a copy of the skip (cs channels) into channels [c, c + cs).
+// stride c + cs, and a copy of the skip (cs channels) into channels [c, c + cs); one
+// thread per voxel and group of 8 channels (a pure copy of 16-byte words).
 __global__ void k_up2_cat(const uint16_t* h, int c, const uint16_t* skip, int cs, int n, int D, int H, int W,
                           uint16_t* cat) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ldc = c + cs;
-    const long long tot = (long long)n * D * H * W * ldc;
+    const int ldc = c + cs, G = ldc / 8;
+    const long long tot = (long long)n * D * H * W * G;
     if (i >= tot) return;
-    const int ch = (int)(i % ldc);
-    const long long p = i / ldc;
-    if (ch < c) {
-        long long r = p;
-        const int x = (int)(r % W); r /= W;
-        const int yv = (int)(r % H); r /= H;
-        const int z = (int)(r % D);
-        const long long nb = r / D;
-        const long long q = ((nb * (D / 2) + z / 2) * (H / 2) + yv / 2) * (W / 2) + x / 2;
-        cat[i] = h[q * c + ch];
+    const int g = (int)(i % G);
+    const long long p = i / G;
+    uint4 t;
+    if (8 * g < c) {
+        const Vox v = decode(p, D, H, W);
+        const long long q = (((long long)v.b * (D / 2) + v.z / 2) * (H / 2) + v.y / 2) * (W / 2) + v.x / 2;
+        t = *reinterpret_cast<const uint4*>(h + q * c + 8 * g);
     } else {
-        cat[i] = skip[p * cs + ch - c];
+        t = *reinterpret_cast<const uint4*>(skip + p * cs + 8 * g - c);
     }
+    *reinterpret_cast<uint4*>(cat + p * ldc + 8 * g) = t;
 }
 
-// Gradient of the upsampling: dh[parent][ch] = sum of the 8 children's dcat[.][ch].
+// Gradient of the upsampling: dh[parent][ch] = sum of the 8 children's dcat[.][ch]; one
+// thread per parent voxel and group of 8 channels.
 __global__ void k_up2_bwd(const uint16_t* dcat, int ldc, int c, int n, int d, int h, int w, uint16_t* dh) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long tot = (long long)n * d * h * w * c;
+    const int G = c / 8;
+    const long long tot = (long long)n * d * h * w * G;
     if (i >= tot) return;
-    const int ch = (int)(i % c);
-    long long r = i / c;
-    const int x = (int)(r % w); r /= w;
-    const int yv = (int)(r % h); r /= h;
-    const int z = (int)(r % d);
-    const long long nb = r / d;
-    float s = 0.f;
+    const int g = (int)(i % G);
+    const long long p = i / G;
+    const Vox v = decode(p, d, h, w);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const long long q = ((nb * 2 * d + 2 * z + (k >> 2)) * 2 * h + 2 * yv + ((k >> 1) & 1)) * 2 * w + 2 * x + (k & 1);
-        s += bf2f(dcat[q * ldc + ch]);
+        const long long q = (((long long)v.b * 2 * d + 2 * v.z + (k >> 2)) * 2 * h + 2 * v.y + ((k >> 1) & 1)) * 2 * w +
+                            2 * v.x + (k & 1);
+        float f[8];
+        unpack8(*reinterpret_cast<const uint4*>(dcat + q * ldc + 8 * g), f);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] += f[e];
     }
-    dh[i] = f2bf(s);
+    *reinterpret_cast<uint4*>(dh + p * c + 8 * g) = pack8(s);
 }
 
-// 1x1x1 head: out[p][o] = b[o] + sum_c h[p][c] W[c][o] (FP32 weights and output).
+// 1x1x1 head: out[p][o] = b[o] + sum_c h[p][c] W[c][o] (FP32 weights and output), for
+// c = 16 input channels; one thread per voxel.
 __global__ void k_head(const uint16_t* h, int c, const float* W, const float* b, int cout, long long P, float* out) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
+    float hv[16];
+    unpack8(*reinterpret_cast<const uint4*>(h + p * 16), *reinterpret_cast<float(*)[8]>(hv));
+    unpack8(*reinterpret_cast<const uint4*>(h + p * 16 + 8), *reinterpret_cast<float(*)[8]>(hv + 8));
+    (void)c;
     for (int o = 0; o < cout; ++o) {
         float s = b[o];
-        for (int k = 0; k < c; ++k) s += bf2f(h[p * c + k]) * W[k * cout + o];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += hv[k] * W[k * cout + o];
         out[p * cout + o] = s;
     }
 }
 
-// Head backward: dh[p][c] = sum_o dout[p][o] W[c][o] (BF16), and per-block partials of
-// dW[c][o] = sum_p h[p][c] dout[p][o] and db[o] = sum_p dout[p][o].
+// Head backward for c = 16 input channels: dh[p][c] = sum_o dout[p][o] W[c][o] (BF16), and
+// per-block partials of dW[c][o] = sum_p h[p][c] dout[p][o] and db[o] = sum_p dout[p][o]
+// (the per-thread sums go through LDS, each parameter summed by one thread in order).
+constexpr int kHeadPar = 16 * 4 + 4;
 __global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* h, int c, const float* W, int cout, const float* dout,
                                                   long long P, long long per_chunk, uint16_t* dh, float* part) {
     const long long pa = (long long)blockIdx.x * per_chunk;
     const long long pb = pa + per_chunk < P ? pa + per_chunk : P;
-    const int npar = c * cout + cout;
-    float acc[16 * 4 + 4];
-    for (int i = 0; i < npar; ++i) acc[i] = 0.f;
+    const int npar = 16 * cout + cout;
+    float acc[kHeadPar];
+#pragma unroll
+    for (int i = 0; i < kHeadPar; ++i) acc[i] = 0.f;
+    (void)c;
     for (long long p = pa + threadIdx.x; p < pb; p += blockDim.x) {
-        for (int k = 0; k < c; ++k) {
+        float hv[16], g[4] = {0.f, 0.f, 0.f, 0.f};
+        unpack8(*reinterpret_cast<const uint4*>(h + p * 16), *reinterpret_cast<float(*)[8]>(hv));
+        unpack8(*reinterpret_cast<const uint4*>(h + p * 16 + 8), *reinterpret_cast<float(*)[8]>(hv + 8));
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+            if (o < cout) g[o] = dout[p * cout + o];
+        float d[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
             float s = 0.f;
-            const float hv = bf2f(h[p * c + k]);
-            for (int o = 0; o < cout; ++o) {
-                const float g = dout[p * cout + o];
-                s += g * W[k * cout + o];
-                acc[k * cout + o] += hv * g;
-            }
-            dh[p * c + k] = f2bf(s);
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                if (o < cout) {
+                    s += g[o] * W[k * cout + o];
+                    acc[k * 4 + o] += hv[k] * g[o];
+                }
+            d[k] = s;
         }
-        for (int o = 0; o < cout; ++o) acc[c * cout + o] += dout[p * cout + o];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) acc[64 + o] += g[o];
+        *reinterpret_cast<uint4*>(dh + p * 16) = pack8(*reinterpret_cast<float(*)[8]>(d));
+        *reinterpret_cast<uint4*>(dh + p * 16 + 8) = pack8(*reinterpret_cast<float(*)[8]>(d + 8));
     }
-    __shared__ float sh[256];
-    for (int i = 0; i < npar; ++i) {
-        sh[threadIdx.x] = acc[i];
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-            __syncthreads();
+    __shared__ float sh[kHeadPar][65];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float s = 0.f;
+    for (int r = 0; r < 4; ++r) {
+        if (wv == r) {
+#pragma unroll
+            for (int i = 0; i < kHeadPar; ++i) sh[i][lane] = acc[i];
         }
-        if (threadIdx.x == 0) part[(long long)blockIdx.x * npar + i] = sh[0];
         __syncthreads();
+        if (threadIdx.x < kHeadPar)
+            for (int t = 0; t < 64; ++t) s += sh[threadIdx.x][t];
+        __syncthreads();
+    }
+    if (threadIdx.x < kHeadPar) {
+        const int i = threadIdx.x;
+        // parameter order of the flat vector: W[c][o] (c-major), then b[o]
+        const int k = i / 4, o = i % 4;
+        if (i < 64 && o < cout) part[(long long)blockIdx.x * npar + k * cout + o] = s;
+        if (i >= 64 && i - 64 < cout) part[(long long)blockIdx.x * npar + 16 * cout + (i - 64)] = s;
     }
 }
 
@@ -486,12 +547,22 @@ __global__ void k_pack(const float* W, int cin, int cout, int taps, int cin_p, i
     }
 }
 
-// Copy an input with 'c' channels into a zero-padded buffer with 'cp' channels.
+// Copy an input with 'c' channels into a zero-padded buffer with 'cp' channels (cp a
+// multiple of 8); one thread per voxel.
 __global__ void k_pad_channels(const uint16_t* x, int c, int cp, long long P, uint16_t* y) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * cp) return;
-    const int ch = (int)(i % cp);
-    y[i] = ch < c ? x[(i / cp) * c + ch] : (uint16_t)0;
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    for (int g = 0; g < cp / 8; ++g) {
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c0 = 8 * g + 2 * i;
+            const uint32_t lo = c0 < c ? x[p * c + c0] : 0u;
+            const uint32_t hi = c0 + 1 < c ? x[p * c + c0 + 1] : 0u;
+            w[i] = lo | (hi << 16);
+        }
+        *reinterpret_cast<uint4*>(y + p * cp + 8 * g) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
 }
 
 }  // namespace mpm
