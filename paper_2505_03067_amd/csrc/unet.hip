@@ -174,10 +174,8 @@ static int ensure_acts(Net* n, int nb, int D, int H, int W) {
 
 template <int NT>
 static void launch_conv(const ConvArgs& a, hipStream_t st) {
-    constexpr int MT = 2;
-    const long long P = (long long)a.n * a.D * a.H * a.W;
-    const unsigned grid = (unsigned)((P + 4 * MT * 16 - 1) / (4 * MT * 16));
-    k_conv<NT, MT><<<grid, 256, 0, st>>>(a);
+    const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
+    k_conv<NT><<<(unsigned)tiles, 256, 0, st>>>(a);
 }
 
 static int conv_dispatch(const ConvArgs& a, int nt, hipStream_t st) {

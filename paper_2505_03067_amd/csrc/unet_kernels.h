@@ -39,87 +39,118 @@ struct ConvArgs {
     int n, D, H, W;
 };
 
-// One wave computes MT x 16 voxels by NT x 16 channels; a block is 4 waves.
-template <int NT, int MT>
+// Keep each BF16 half of x only where the gate half is > 0 (ReLU backward).
+__device__ inline uint4 apply_gate(uint4 t, const uint4 g) {
+    const uint32_t gw[4] = {g.x, g.y, g.z, g.w};
+    uint32_t tw[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t lo = gw[i] & 0xffffu, hi = gw[i] >> 16;
+        const bool plo = lo != 0 && !(lo & 0x8000u);
+        const bool phi = hi != 0 && !(hi & 0x8000u);
+        tw[i] &= (plo ? 0x0000ffffu : 0u) | (phi ? 0xffff0000u : 0u);
+    }
+    return make_uint4(tw[0], tw[1], tw[2], tw[3]);
+}
+
+// 3x3x3 convolution as an implicit GEMM with the input staged in LDS.  A block owns an
+// output tile of 16 (x) x 4 (y) x 4 (z) voxels of one sample; the input tile with its
+// one-voxel halo (18 x 6 x 6 voxels) is staged once per chunk of up to 32 input channels
+// (voxel stride padded by 8 channels against bank conflicts; every global load of a
+// thread is issued before its LDS writes), and all 27 taps read it from LDS.  Wave w
+// computes rows (y, z) 4w..4w+3 of the tile (four 16-voxel M tiles) for every
+// 16-channel N tile; K runs over tap x channel with k = tap * C + c inside a chunk of C
+// channels (C = 16: one 32-wide step covers two taps).
+constexpr int kTX = 16, kTY = 4, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+constexpr int kHV = kHX * kHY * kHZ;
+constexpr int kCS = 40;   // LDS channel stride per voxel (32 + 8 padding), BF16 units
+
+template <int NT>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+    __shared__ uint4 xs[kHV * kCS / 8];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const long long P = (long long)a.n * a.D * a.H * a.W;
-    const long long p0 = ((long long)blockIdx.x * 4 + wave) * (MT * 16);
-    if (p0 >= P) return;
-    // decode the voxel of this lane's row in each row tile
-    int vz[MT], vy[MT], vx[MT];
-    long long vb[MT];
-    bool vin[MT];
+    const int ntx = (a.W + kTX - 1) / kTX, nty = (a.H + kTY - 1) / kTY, ntz = (a.D + kTZ - 1) / kTZ;
+    int bid = blockIdx.x;
+    const int tx = bid % ntx;
+    bid /= ntx;
+    const int ty = bid % nty;
+    bid /= nty;
+    const int tz = bid % ntz;
+    const int sb = bid / ntz;
+    const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
+    const long long sbase = (long long)sb * a.D * a.H * a.W;
+    f32x4 acc[4][NT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        long long p = p0 + mt * 16 + (lane & 15);
-        vin[mt] = p < P;
-        if (!vin[mt]) p = 0;
-        vx[mt] = (int)(p % a.W);
-        long long r = p / a.W;
-        vy[mt] = (int)(r % a.H);
-        r /= a.H;
-        vz[mt] = (int)(r % a.D);
-        vb[mt] = r / a.D;
-    }
-    f32x4 acc[MT][NT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kg = 8 * (lane >> 4);
-    const int ktot = a.taps * a.cin_p;
-    for (int kk = 0; kk < a.kp; kk += 32) {
-        const int k0 = kk + kg;
-        bf16x8 bfr[NT];
+    for (int cb = 0; cb < a.cin_p; cb += 32) {
+        const int C = a.cin_p - cb < 32 ? a.cin_p - cb : 32;
+        const int G = C / 8;
+        constexpr int SM = (kHV * 4 + 255) / 256;
+        uint4 st[SM], sg[SM];
+        int sidx[SM];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const uint4 t = *reinterpret_cast<const uint4*>(a.w + (long long)(nt * 16 + (lane & 15)) * a.kp + k0);
-            bfr[nt] = __builtin_bit_cast(bf16x8, t);
-        }
-        int dz = 0, dy = 0, dx = 0, c0 = 0;
-        const bool kin = k0 < ktot;
-        if (kin) {
-            const int tap = k0 / a.cin_p;
-            c0 = k0 - tap * a.cin_p;
-            if (a.taps == 27) {
-                dz = tap / 9 - 1;
-                dy = (tap / 3) % 3 - 1;
-                dx = tap % 3 - 1;
-            }
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            uint4 t = make_uint4(0, 0, 0, 0);
-            const int z = vz[mt] + dz, yy = vy[mt] + dy, xx = vx[mt] + dx;
-            if (kin && vin[mt] && z >= 0 && z < a.D && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
-                const long long q = ((vb[mt] * a.D + z) * a.H + yy) * a.W + xx;
-                t = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + c0);
-                if (a.gate) {
-                    const uint4 g = *reinterpret_cast<const uint4*>(a.gate + q * a.ldx + c0);
-                    const uint32_t gw[4] = {g.x, g.y, g.z, g.w};
-                    uint32_t tw[4] = {t.x, t.y, t.z, t.w};
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        // keep each BF16 half only where the gate half is > 0
-                        const uint32_t lo = gw[i] & 0xffffu, hi = gw[i] >> 16;
-                        const bool plo = lo != 0 && !(lo & 0x8000u);
-                        const bool phi = hi != 0 && !(hi & 0x8000u);
-                        tw[i] &= (plo ? 0x0000ffffu : 0u) | (phi ? 0xffff0000u : 0u);
-                    }
-                    t = make_uint4(tw[0], tw[1], tw[2], tw[3]);
+        for (int i = 0; i < SM; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            st[i] = make_uint4(0, 0, 0, 0);
+            sg[i] = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);   // BF16 1.0 (gate open)
+            sidx[i] = -1;
+            if (e < kHV * G) {
+                const int v = e / G, g = e - v * G;
+                const int hx = v % kHX, hy = (v / kHX) % kHY, hz = v / (kHX * kHY);
+                const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
+                sidx[i] = v * (kCS / 8) + g;
+                if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
+                    const long long q = sbase + ((long long)z * a.H + y) * a.W + x;
+                    st[i] = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + cb + 8 * g);
+                    if (a.gate) sg[i] = *reinterpret_cast<const uint4*>(a.gate + q * a.ldx + cb + 8 * g);
                 }
             }
-            const bf16x8 af = __builtin_bit_cast(bf16x8, t);
+        }
+        __syncthreads();
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[nt], acc[mt][nt], 0, 0, 0);
+        for (int i = 0; i < SM; ++i)
+            if (sidx[i] >= 0) xs[sidx[i]] = a.gate ? apply_gate(st[i], sg[i]) : st[i];
+        __syncthreads();
+        const int KC = 27 * C;
+        for (int kk = 0; kk < KC; kk += 32) {
+            const int kl = kk + kg;
+            const int tap = kl / C, c0 = kl - tap * C;
+            const bool tin = tap < 27;
+            bf16x8 bfr[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                uint4 t = make_uint4(0, 0, 0, 0);
+                if (tin)
+                    t = *reinterpret_cast<const uint4*>(a.w + (long long)(nt * 16 + (lane & 15)) * a.kp +
+                                                        tap * a.cin_p + cb + c0);
+                bfr[nt] = __builtin_bit_cast(bf16x8, t);
+            }
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo offsets 0..2
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int r = 4 * wave + mt;
+                const int yy = r % kTY, zz = r / kTY;
+                const int hv = ((zz + dz) * kHY + (yy + dy)) * kHX + (lane & 15) + dx;
+                uint4 t = make_uint4(0, 0, 0, 0);
+                if (tin) t = xs[hv * (kCS / 8) + c0 / 8];
+                const bf16x8 af = __builtin_bit_cast(bf16x8, t);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[nt], acc[mt][nt], 0, 0, 0);
+            }
         }
     }
-    // D layout: lane holds rows 4 * (lane / 16) + i, column lane % 16
+    // D layout: lane holds rows 4 * (lane / 16) + i (voxels x0 + row), column lane % 16
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
+    for (int mt = 0; mt < 4; ++mt) {
+        const int r = 4 * wave + mt;
+        const int y = y0 + r % kTY, z = z0 + r / kTY;
+        if (y >= a.H || z >= a.D) continue;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int co = nt * 16 + (lane & 15);
@@ -127,8 +158,9 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
             const float bv = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const long long p = p0 + mt * 16 + 4 * (lane >> 4) + i;
-                if (p >= P) continue;
+                const int x = x0 + 4 * (lane >> 4) + i;
+                if (x >= a.W) continue;
+                const long long p = sbase + ((long long)z * a.H + y) * a.W + x;
                 float v = acc[mt][nt][i] + bv;
                 if (a.relu) v = fmaxf(v, 0.f);
                 if (a.y) a.y[p * a.ldy + a.yoff + co] = f2bf(v);
