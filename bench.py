@@ -10,7 +10,9 @@ each cycle replayed from a hipGraph.  Inputs are seeded and synthetic.
 
 Prints ONE JSON line (rank 0).  Besides steps/s it reports the dominant kernel's
 achieved algorithmic HBM bandwidth (HIP events on the library's stream), the same
-workload with plain FP64 GMRES, and the CPU FP64 oracle timed on a bounded sample.
+workload with plain FP64 GMRES, the learned warm start against the plain solve (a
+network trained on pairs this workload's solver generates), and the CPU FP64 oracle
+timed on a bounded sample.
 """
 
 import argparse
@@ -56,6 +58,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the CPU oracle sample (0 = skip)")
+    ap.add_argument("--learned-steps", type=int, default=20,
+                    help="implicit steps of the learned-vs-plain comparison (0 = skip)")
+    ap.add_argument("--train-pairs", type=int, default=8,
+                    help="solver steps that produce training pairs for the warm-start network")
+    ap.add_argument("--train-iters", type=int, default=200, help="Adam iterations of the network")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device once (calibrates HBM counters)")
     return ap.parse_args()
@@ -115,6 +122,98 @@ def run_steps(s, f, n, tol, torch):
         its.append(sum(s.stats(0, sp)["iterations"] for sp in range(s.nspecies)))
     torch.cuda.synchronize()
     return its
+
+
+def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
+    """Warm start by a network trained on pairs this workload's own solver generates.
+
+    From the state f0: ``train_pairs`` steps solved to 1e-10 give (input, Δc / RMS)
+    pairs on the box grid; the U-Net (16-32-64-64) is trained on them with the library's
+    kernels; then the same ``learned_steps`` steps are run from the state after the pair
+    steps, once plain and once with the learned start (accepted per system only when it
+    lowers the true residual), both from graphs, at the benchmark tolerance.
+    """
+    import numpy as np
+    from paper_2505_03067_amd.train import IN_SCALE
+    S = prob.nspecies
+    f = f0.clone()
+
+    def make_pairs(out_scale):
+        g = f0.clone()
+        pairs = []
+        with m.Solver(S, 1, warm_start=m.MPM_WS_NET) as s:
+            s.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
+            gx, gy, gz = s.ws_grid(0)
+            for _ in range(args.train_pairs):
+                old = g.clone()
+                s.step([g], 1e-10)
+                inp = torch.empty((gz, gy, gx, 4 * S + 1), dtype=torch.int16, device="cuda")
+                tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
+                s.ws_pair(0, old, g, IN_SCALE, out_scale, inp, tgt)
+                pairs.append((inp, tgt))
+        return pairs, g
+
+    raw, _ = make_pairs([1.0] * S)
+    # per-species RMS of the one-step change over the domain voxels (target scale)
+    sq, cnt = [0.0] * S, 0
+    for inp, tgt in raw:
+        mask = inp[..., -1] != 0
+        cnt += int(mask.sum())
+        for sp in range(S):
+            sq[sp] += float((tgt[..., sp][mask].double() ** 2).sum())
+    out_scale = [max((v / max(cnt, 1)) ** 0.5, 1e-30) for v in sq]
+    del raw
+    pairs, f_after = make_pairs(out_scale)
+    net = m.Net(4 * S + 1, S, [16, 32, 64, 64], seed=7)
+    rng = np.random.default_rng(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for it in range(1, args.train_iters + 1):
+        x, y = pairs[int(rng.integers(len(pairs)))]
+        out = torch.empty_like(y)
+        g = torch.empty_like(y)
+        net.forward(x.unsqueeze(0), out.unsqueeze(0))
+        losses.append(net.mse(out, y, g))
+        net.zero_grad()
+        net.backward(g.unsqueeze(0))
+        net.adam(1e-3, it)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del pairs
+    res = {}
+    for name, warm in (("plain", m.MPM_WS_NONE), ("learned", m.MPM_WS_NET)):
+        g = f_after.clone()
+        s = m.Solver(S, 1, precision=precision, warm_start=warm, ortho=int(ortho))
+        s.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
+        if warm == m.MPM_WS_NET:
+            s.attach(net, IN_SCALE, out_scale)
+        gw = g.clone()
+        s.step([gw], tol)                      # allocations, tuning, graph capture
+        torch.cuda.synchronize()
+        its, acc, rw = 0, 0, []
+        t1 = time.perf_counter()
+        for _ in range(args.learned_steps):
+            s.step([g], tol)
+            st = [s.stats(0, sp) for sp in range(S)]
+            its += sum(x["iterations"] for x in st)
+            acc += sum(x["warm_start_used"] for x in st)
+            rw += [x["rel_res_warm"] / x["rel_res_initial"] for x in st if x["warm_start_used"]]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        s.close()
+        res[name] = {"steps_per_s": round(args.learned_steps / el, 3),
+                     "iterations_per_step": round(its / (args.learned_steps * S), 2)}
+        if warm == m.MPM_WS_NET:
+            res[name]["accepted_fraction"] = round(acc / (args.learned_steps * S), 3)
+            res[name]["residual_ratio_warm_over_cn"] = round(float(np.mean(rw)), 4) if rw else None
+    net.close()
+    res["training"] = {"pairs": args.train_pairs, "iterations": args.train_iters, "seconds": round(train_s, 2),
+                       "loss_first": round(float(np.mean(losses[:10])), 5),
+                       "loss_last": round(float(np.mean(losses[-10:])), 5),
+                       "network": "U-Net 16-32-64-64, BF16 MFMA kernels, FP32 Adam, on the box grid"}
+    res["learned_over_plain"] = round(res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"], 3)
+    return res
 
 
 def cpu_baseline(prob, box, c_start, gpu_after, tol, budget_s):
@@ -280,6 +379,9 @@ def main():
         out["plain_fp64"] = {"steps_per_s": round(args.steps / e2, 3),
                              "iterations_per_step": round(sum(its2) / len(its2) / prob.nspecies, 2),
                              "speedup_of_value": round(steps_per_s / (args.steps / e2), 3)}
+
+    if args.learned_steps > 0:
+        out["learned_vs_plain"] = learned_vs_plain(m, prob, t, box, c_start, tol, precision, ortho, args, torch)
 
     if args.cpu_seconds > 0:
         # replay the first steps of the timed run on the GPU (deterministic) to compare
