@@ -343,6 +343,18 @@ def main():
         "cycles_last_step": [st["cycles"] for st in final_stats],
         "rel_res_final_last_step": [st["rel_res_final"] for st in final_stats],
     }
+    # context for the roofline: what a plain device-to-device copy of 1 GiB sustains
+    nbytes = 1 << 30
+    ca = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(5):
+        cb.copy_(ca)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * nbytes / (time.perf_counter() - t2) / 1e9
+    del ca, cb
     if timing and timing["launches"]:
         avg_ms = timing["ms"] / timing["launches"]
         achieved = timing["bytes"] / (timing["ms"] * 1e-3) / 1e9
@@ -360,6 +372,8 @@ def main():
             "launches": timing["launches"],
             "launches_per_event_pair": repeat,
             "phase": f"{args.roofline_steps} steps after the headline timing, cycle launched directly",
+            "copy_1gib_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
             "alg_bytes_per_launch": round(timing["bytes"] / timing["launches"]),
             "alg_bytes_per_active_launch": round(alg_bytes_active(KERNELS[kname], kj, U, precision, prob.nspecies,
                                                                   dc)),
