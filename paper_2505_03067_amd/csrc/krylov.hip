@@ -1022,18 +1022,26 @@ __global__ __launch_bounds__(kThreads) void k_dc_spmv_dot(KArgs<T> a) {
     T acc[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = T(0);
-    for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
+    // the neighbour indices of the next pass are requested one pass ahead, so that from
+    // the second pass on the gathers only wait for indices already in flight
+    long long u0 = blk.start + threadIdx.x * n;
+    StencilIn<T> si;
+    if (u0 < blk.end) stencil_idx<T>(blk, (int)(u0 - blk.base), si);
+    for (; u0 < blk.end; u0 += kThreads * n) {
         const int l0 = (int)(u0 - blk.base);
-        StencilIn<T> si;
-        stencil_idx<T>(blk, l0, si);
         __builtin_amdgcn_sched_barrier(0);
         T vk[J > 0 ? J : 1][n];
 #pragma unroll
         for (int k = 0; k < J; ++k) ld16(a.V + (long long)k * a.ldv + u0, vk[k]);
         stencil_direct<T>(U, blk, u0, l0, si);
+        StencilIn<T> nx;
+        const long long u1 = u0 + kThreads * n;
+        if (u1 < blk.end) stencil_idx<T>(blk, (int)(u1 - blk.base), nx);
         __builtin_amdgcn_sched_barrier(0);
         T z[n];
         stencil_finish<T>(U, blk, l0, si, z);
+#pragma unroll
+        for (int e = 0; e < n; ++e) si.nb[e] = nx.nb[e];
         const T (&uv)[n] = si.xv;
         if constexpr (J == 0) {
 #pragma unroll
@@ -1603,21 +1611,45 @@ static int upload_tables(Ctx* c) {
 template <typename T>
 static KArgs<T> make_args(Ctx* c, const Block* blocks);
 
-__global__ void k_tune_state(SysK* sk, int nsys) {
+// A state in which every Arnoldi kernel runs its full streaming path and no cycle
+// ends: zero scales (so the Gram-Schmidt coefficients vanish and beta^2 = u.u > 0 on
+// the non-zero fill of the basis), zero tolerance, identity rotations.  The tables
+// are re-initialised and the basis re-zeroed after tuning.
+__global__ void k_tune_state(SysK* sk, int nsys, int mcount) {
     const int s = blockIdx.x;
     if (s >= nsys) return;
-    for (int k = threadIdx.x; k < kMaxM + 2; k += blockDim.x) sk[s].vs[k] = 1.0;
-    if (threadIdx.x == 0) sk[s].active = 1;
+    SysK& k = sk[s];
+    for (int i = threadIdx.x; i < kMaxM + 2; i += blockDim.x) {
+        k.vs[i] = 0.0;
+        k.gt[i] = 1.0;
+        k.cs[i] = 1.0;
+        k.sn[i] = 0.0;
+        k.hc[0][i] = 0.0;
+        k.hc[1][i] = 0.0;
+    }
+    for (int i = threadIdx.x; i < (kMaxM + 1) * (kMaxM + 1); i += blockDim.x) k.Hraw[i] = 0.0;
+    for (int i = threadIdx.x; i < kMaxM + 2; i += blockDim.x) k.y[i] = 0.0;
+    if (threadIdx.x == 0) {
+        k.eta = 0.0;
+        k.active = 1;
+        k.need_update = 1;   // the update streams mcount vectors with zero coefficients
+        k.mcount = mcount;
+    }
 }
 
-// Timing-based choice of the unknowns per block: run the first stencil kernel and
-// the two Gram-Schmidt passes of Arnoldi step 8 (on whatever the vectors hold) for
-// each candidate split and keep the fastest.  The choice is cached per layout.
+// Timing-based choice of the unknowns per block: run the kernels of Arnoldi steps 0
+// and 8 of the selected Gram-Schmidt variant (in the tuning state above) for each
+// candidate split, three times, and keep the split with the fastest repetition.  The
+// choice is cached per layout.
 template <typename T>
 static int autotune_t(Ctx* c, long long* best_out) {
     hipStream_t st = c->stream;
     const Kernels<T>& K = kernels<T>();
     const int J = std::min(8, c->opt.restart - 1);
+    if (J < 0 || J + 1 > c->opt.restart) {
+        set_error("autotune: restart out of range");
+        return MPM_EINVAL;
+    }
     const int nsys = c->S * c->P;
     long long maxpad = 0;
     for (auto& ph : c->probs) maxpad = std::max<long long>(maxpad, ph.Npad);
@@ -1626,26 +1658,36 @@ static int autotune_t(Ctx* c, long long* best_out) {
     MPM_HIP(hipEventCreate(&e1));
     double best_ms = 1e30;
     long long best = model_tile(c);
-    for (long long tile = 1024; tile <= 65536; tile *= 2) {
+    const size_t vbytes = (size_t)(c->opt.restart + 1) * c->ldv * ksize(c);
+    MPM_HIP(hipMemsetAsync(c->V, 0x3c, vbytes, st));   // finite, non-zero fill
+    // at most eight passes per thread (the residual and update kernels do not overlap
+    // their passes), at most 1024 partial-sum slots per system
+    const long long max_tile = 8LL * kThreads * VW<T>::n;
+    for (long long tile = 1024; tile <= max_tile; tile *= 2) {
         const long long nbsys = (maxpad + tile - 1) / tile;
         if (nbsys > 1024) continue;            // too many partial sums per system
         if (tile > 1024 && nbsys < 8) break;   // too few blocks per system
         build_tables(c, tile);
         int rc = upload_tables(c);
         if (rc != MPM_OK) return rc;
-        k_tune_state<<<nsys, 64, 0, st>>>(c->d_sk, nsys);
+        // the update reads V_0..V_{mcount-1}: never more than the restart + 1 stored vectors
+        k_tune_state<<<nsys, 64, 0, st>>>(c->d_sk, nsys, J + 1);
         KArgs<T> a = make_args<T>(c, c->d_blocks);
         const unsigned nb = (unsigned)c->blocks.size();
-        float ms = 0.0f;
+        float ms = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             MPM_HIP(hipEventRecord(e0, st));
             for (int it = 0; it < 3; ++it) {
                 if (c->opt.ortho == MPM_ORTHO_DCGS2) {
-                    // the axpy kernel of the delayed scheme would end the cycle on
-                    // these contents; the CGS2 pass streams as many vectors
                     K.da[0]<<<nb, kThreads, 0, st>>>(a);
+                    K.db[0]<<<nb, kThreads, 0, st>>>(a);
                     K.da[J]<<<nb, kThreads, 0, st>>>(a);
-                    K.k2[J]<<<nb, kThreads, 0, st>>>(a);
+                    K.db[J]<<<nb, kThreads, 0, st>>>(a);
+                    // once per cycle in the solve; here once per two Arnoldi steps
+                    if (it == 0) {
+                        k_residual<T><<<nb, kThreads, 0, st>>>(a, kResCycle);
+                        k_update<T><<<nb, kThreads, 0, st>>>(a);
+                    }
                 } else {
                     K.k1[0]<<<nb, kThreads, 0, st>>>(a);
                     K.k2[J]<<<nb, kThreads, 0, st>>>(a);
@@ -1654,7 +1696,9 @@ static int autotune_t(Ctx* c, long long* best_out) {
             }
             MPM_HIP(hipEventRecord(e1, st));
             MPM_HIP(hipEventSynchronize(e1));
-            MPM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            float t = 0.0f;
+            MPM_HIP(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
         }
         if (ms < best_ms) {
             best_ms = ms;
@@ -1663,6 +1707,7 @@ static int autotune_t(Ctx* c, long long* best_out) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    MPM_HIP(hipMemsetAsync(c->V, 0, vbytes, st));
     *best_out = best;
     return MPM_OK;
 }
