@@ -78,9 +78,10 @@ struct Ctx {
     long long ldv = 0;
     size_t cap_U = 0;
 
-    // pinned host mirrors
+    // pinned host mirrors (up_valid: the device holds what they hold)
     double** h_fields = nullptr;
     Params* h_prm = nullptr;
+    bool up_valid = false;
     SysK* h_sk = nullptr;
 
     // graphs of GMRES cycle segments, keyed by (first step, end step, tail kind)

@@ -30,6 +30,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <utility>
 
 #include "context.h"
@@ -1801,6 +1802,7 @@ int ensure_layout(Ctx* c) {
     c->h_prm->restart = m;
     c->h_prm->S = c->S;
     MPM_HIP(hipMemcpyAsync(c->d_prm, c->h_prm, sizeof(Params), hipMemcpyHostToDevice, st));
+    c->up_valid = false;
     // work split: fixed override, cached tuning result, or a fresh autotune
     long long tile = c->opt.tile_override;
     if (tile <= 0) {
@@ -2085,9 +2087,17 @@ static int run_step_t(Ctx* c, double tol) {
             if (c->h_sk[s].active) return true;
         return false;
     };
+    // The status after the first residual is only needed to skip a cycle nobody runs:
+    // when the previous step needed a cycle, the first one is launched at once (blocks
+    // of systems converged at c^n exit at their first check).
+    const bool speculate = !c->cycle_len.empty() && c->cycle_len[0] > 0;
     for (int cyc = 0;; ++cyc) {
-        rc = fetch_status(c, st);
-        if (rc != MPM_OK) return rc;
+        if (cyc == 0 && speculate) {
+            for (int s = 0; s < nsys; ++s) c->h_sk[s].active = 1;
+        } else {
+            rc = fetch_status(c, st);
+            if (rc != MPM_OK) return rc;
+        }
         if (cyc > 0) {
             // length of the cycle that just ended (longest over the systems that ran it)
             int len = 0;
@@ -2099,8 +2109,9 @@ static int run_step_t(Ctx* c, double tol) {
                 for (int s = 0; s < nsys; ++s) c->prev_cycles[s] = c->h_sk[s].cycles;
         }
         bool bad = false;
-        for (int s = 0; s < nsys; ++s)
-            if (c->h_sk[s].breakdown && !c->h_sk[s].converged) bad = true;
+        if (!(cyc == 0 && speculate))
+            for (int s = 0; s < nsys; ++s)
+                if (c->h_sk[s].breakdown && !c->h_sk[s].converged) bad = true;
         if (!any_active()) {
             if (bad) status = MPM_NOT_CONVERGED;
             break;
@@ -2157,14 +2168,26 @@ int run_step(Ctx* c, double* const* fields, double tol) {
     int rc = ensure_layout(c);
     if (rc != MPM_OK) return rc;
     hipStream_t st = c->stream;
-    for (int p = 0; p < c->P; ++p) c->h_fields[p] = fields[p];
-    MPM_HIP(hipMemcpyAsync(c->d_fields, c->h_fields, c->P * sizeof(double*), hipMemcpyHostToDevice, st));
-    c->h_prm->tol = tol;
-    c->h_prm->inner_rtol = c->opt.precision == MPM_FP64 ? 0.0 : c->opt.inner_rtol;
-    c->h_prm->restart = c->opt.restart;
-    c->h_prm->S = c->S;
-    c->h_prm->first = 1;
-    MPM_HIP(hipMemcpyAsync(c->d_prm, c->h_prm, sizeof(Params), hipMemcpyHostToDevice, st));
+    // field pointers and scalar parameters go to the device only when they change (the
+    // previous step ended with a stream synchronisation, so the pinned copies are free)
+    bool fields_changed = !c->up_valid;
+    for (int p = 0; p < c->P; ++p) {
+        if (c->h_fields[p] != fields[p]) fields_changed = true;
+        c->h_fields[p] = fields[p];
+    }
+    if (fields_changed)
+        MPM_HIP(hipMemcpyAsync(c->d_fields, c->h_fields, c->P * sizeof(double*), hipMemcpyHostToDevice, st));
+    Params np = *c->h_prm;
+    np.tol = tol;
+    np.inner_rtol = c->opt.precision == MPM_FP64 ? 0.0 : c->opt.inner_rtol;
+    np.restart = c->opt.restart;
+    np.S = c->S;
+    np.first = 1;
+    if (!c->up_valid || std::memcmp(&np, c->h_prm, sizeof(Params)) != 0) {
+        *c->h_prm = np;
+        MPM_HIP(hipMemcpyAsync(c->d_prm, c->h_prm, sizeof(Params), hipMemcpyHostToDevice, st));
+    }
+    c->up_valid = true;
     return c->opt.precision == MPM_FP64 ? run_step_t<double>(c, tol) : run_step_t<float>(c, tol);
 }
 
