@@ -79,7 +79,7 @@ static_assert(sizeof(Block) == 128, "block record size");
 // status fields come first: the host copies only that head of each record
 // (kSysHead bytes) between cycles.
 struct SysK {
-    int active;        // Arnoldi running in the current cycle
+    int active;        // kIdle, kRunning (in a cycle) or kPending (a new cycle starts at step 0)
     int converged;     // true residual met the tolerance this step
     int need_update;   // a cycle finished and x must be corrected
     int mcount;        // basis vectors used by the finished cycle
@@ -101,6 +101,11 @@ struct SysK {
     unsigned long long dmin_bits, dmax_bits;   // extremes of A_PP (positive doubles)
 };
 constexpr size_t kSysHead = offsetof(SysK, h1);
+
+// Values of SysK::active.  A system whose cycle ended and that needs another one is
+// pending until the first kernel of the next cycle (Arnoldi step 0) takes it up, so
+// that kernels of later steps launched in the same stretch of work skip it.
+constexpr int kIdle = 0, kRunning = 1, kPending = 2;
 
 struct Params {          // per-step scalars read by the kernels
     double tol;

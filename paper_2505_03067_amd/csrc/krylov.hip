@@ -345,7 +345,8 @@ __device__ inline bool res_skip(const SysK* sk, int mode) {
     switch (mode) {
         case kResFirst: return false;
         case kResRevert: return !sk->fallback;
-        default: return sk->converged != 0;
+        case kResWarm: return sk->converged != 0;
+        default: return sk->converged != 0 || sk->active != kIdle;   // only systems whose cycle ended
     }
 }
 
@@ -358,11 +359,14 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
     const int lane = threadIdx.x & 63;
     const int cv = lane < a.nsys ? a.sk[lane].converged : 0;
     const int fb = lane < a.nsys ? a.sk[lane].fallback : 0;
+    const int ac = lane < a.nsys ? a.sk[lane].active : 0;
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
-    const bool skip = mode == kResFirst ? false
+    const bool skip = mode == kResFirst    ? false
                       : mode == kResRevert ? !__builtin_amdgcn_readlane(fb, blk.sys)
-                                           : __builtin_amdgcn_readlane(cv, blk.sys) != 0;
+                      : mode == kResWarm   ? __builtin_amdgcn_readlane(cv, blk.sys) != 0
+                                           : (__builtin_amdgcn_readlane(cv, blk.sys) != 0 ||
+                                            __builtin_amdgcn_readlane(ac, blk.sys) != kIdle);
     if (skip) return;
     const __attribute__((address_space(1))) i32x4* nbr = (const __attribute__((address_space(1))) i32x4*)blk.nbr;
     const gptr<double> A = as_global(blk.a64);
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(kThreads) void k_res_final(KArgs<T> a, int sys0, in
         sk->eta = eta;
         sk->vs[0] = 1.0 / srn;
         sk->gt[0] = srn;
-        sk->active = 1;
+        sk->active = kPending;
     }
 }
 
@@ -617,11 +621,14 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dot(KArgs<T> a) {
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
     SysK* sk = a.sk + blk.sys;
-    if (!sk->active) return;
     T vsJ;
     if constexpr (J == 0) {
+        // step 0 takes up pending systems (its first block marks them running)
+        if (sk->active == kIdle) return;
+        if (blk.slot == sk->slot0 && threadIdx.x == 0) sk->active = kRunning;
         vsJ = (T)sk->vs[0];
     } else {
+        if (sk->active != kRunning) return;
         __shared__ double red[1];
         reduce_partials<1>(a.part + (long long)kRowP3 * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
         const double hn = sqrt(red[0]);
@@ -662,7 +669,7 @@ __global__ __launch_bounds__(kThreads) void k_axpy_dot(KArgs<T> a) {
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
     SysK* sk = a.sk + blk.sys;
-    if (!sk->active) return;
+    if (sk->active != kRunning) return;
     __shared__ double red[J + 1];
     reduce_partials<J + 1>(a.part + (long long)kRowP1 * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
     double cf[J + 1];
@@ -706,7 +713,7 @@ __global__ __launch_bounds__(kThreads) void k_axpy_norm(KArgs<T> a) {
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
     SysK* sk = a.sk + blk.sys;
-    if (!sk->active) return;
+    if (sk->active != kRunning) return;
     __shared__ double red[J + 1];
     reduce_partials<J + 1>(a.part + (long long)kRowP2 * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
     double cf[J + 1];
@@ -749,7 +756,7 @@ __global__ __launch_bounds__(kThreads) void k_axpy_norm(KArgs<T> a) {
 template <typename T, int J>
 __global__ __launch_bounds__(kThreads) void k_finish(KArgs<T> a, int sys0) {
     SysK* sk = a.sk + sys0 + blockIdx.x;
-    if (!sk->active) return;
+    if (sk->active != kRunning) return;
     __shared__ double red[1];
     reduce_partials<1>(a.part + (long long)kRowP3 * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
     (void)givens_tail<J>(sk, sqrt(red[0]), a.prm->restart, true);
@@ -1015,9 +1022,16 @@ __global__ __launch_bounds__(kThreads) void k_dc_spmv_dot(KArgs<T> a) {
     if constexpr (J == 0) vs0v = lane < a.nsys ? a.sk[lane].vs[0] : 0.0;
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
-    if (!__builtin_amdgcn_readlane(actv, blk.sys)) return;
+    const int act = __builtin_amdgcn_readlane(actv, blk.sys);
     T sc = T(1);
-    if constexpr (J == 0) sc = (T)rdl(vs0v, blk.sys);
+    if constexpr (J == 0) {
+        // step 0 takes up pending systems (its first block marks them running)
+        if (act == kIdle) return;
+        if (blk.slot == blk.slot0 && threadIdx.x == 0) a.sk[blk.sys].active = kRunning;
+        sc = (T)rdl(vs0v, blk.sys);
+    } else {
+        if (act != kRunning) return;
+    }
     const T* U = a.V + (long long)J * a.ldv;
     // per-thread sums in the Krylov type (a few products each), block sums in FP64
     T acc[NR];
@@ -1080,7 +1094,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_lastdots(KArgs<T> a) {
     const int actv = lane < a.nsys ? a.sk[lane].active : 0;
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
-    if (!__builtin_amdgcn_readlane(actv, blk.sys)) return;
+    if (__builtin_amdgcn_readlane(actv, blk.sys) != kRunning) return;
     const T* U = a.V + (long long)J * a.ldv;
     T acc[NR];
 #pragma unroll
@@ -1171,7 +1185,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_axpy(KArgs<T> a) {
     const int actv = lane < a.nsys ? a.sk[lane].active : 0;
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
-    if (!__builtin_amdgcn_readlane(actv, blk.sys)) return;
+    if (__builtin_amdgcn_readlane(actv, blk.sys) != kRunning) return;
     SysK* sk = a.sk + blk.sys;
     const bool lead = blk.slot == blk.slot0;
     const double* part = a.part + (long long)kRowD * a.nslots;
@@ -1283,7 +1297,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_finish(KArgs<T> a, int sys0) {
     constexpr int NR = 2 * J + 2;
     constexpr int LD = kMaxM + 1;
     SysK* sk = a.sk + sys0 + blockIdx.x;
-    if (!sk->active) return;
+    if (sk->active != kRunning) return;
     __shared__ double red[NR];
     __shared__ double sq[J], scf[J + 1], sbeta;
     reduce_partials<NR>(a.part + (long long)kRowD * a.nslots, a.nslots, sk->slot0, sk->nblocks, red);
@@ -1861,8 +1875,13 @@ static KArgs<T> make_args(Ctx* c, const Block* blocks) {
 static bool timed(const Ctx* c, int kind, int j) {
     return c->time_kind == kind && (kind > MPM_KERNEL_AXPY_NORM || c->time_j == j);
 }
-static void tev_begin(Ctx* c, hipStream_t st) { (void)hipEventRecord(c->tev[2 * c->tev_used], st); }
+// Event pairs around timed launches; a launch beyond the allocated pairs is not timed.
+static bool tev_room(const Ctx* c) { return 2 * (size_t)c->tev_used + 1 < c->tev.size(); }
+static void tev_begin(Ctx* c, hipStream_t st) {
+    if (tev_room(c)) (void)hipEventRecord(c->tev[2 * c->tev_used], st);
+}
 static void tev_end(Ctx* c, hipStream_t st) {
+    if (!tev_room(c)) return;
     (void)hipEventRecord(c->tev[2 * c->tev_used + 1], st);
     ++c->tev_used;
 }
@@ -2091,13 +2110,20 @@ static int run_step_t(Ctx* c, double tol) {
     // when the previous step needed a cycle, the first one is launched at once (blocks
     // of systems converged at c^n exit at their first check).
     const bool speculate = !c->cycle_len.empty() && c->cycle_len[0] > 0;
+    auto any_running = [&] {
+        for (int s = 0; s < nsys; ++s)
+            if (c->h_sk[s].active == kRunning) return true;
+        return false;
+    };
+    bool have_status = false;   // h_sk already holds the end state of the last cycle
     for (int cyc = 0;; ++cyc) {
         if (cyc == 0 && speculate) {
-            for (int s = 0; s < nsys; ++s) c->h_sk[s].active = 1;
-        } else {
+            for (int s = 0; s < nsys; ++s) c->h_sk[s].active = kPending;
+        } else if (!have_status) {
             rc = fetch_status(c, st);
             if (rc != MPM_OK) return rc;
         }
+        have_status = false;
         if (cyc > 0) {
             // length of the cycle that just ended (longest over the systems that ran it)
             int len = 0;
@@ -2122,16 +2148,21 @@ static int run_step_t(Ctx* c, double tol) {
         }
         c->tev_used = 0;
         // Launch the cycle up to the length it took in the previous implicit step (plus
-        // a margin); if a system is still running there, continue to step m.  Launches
-        // past the end of every system's cycle would only find inactive systems.
+        // a margin) followed by the end-of-cycle work for the systems whose cycle ended
+        // there; only if a system is still running at that step is it continued to step
+        // m (systems restarted meanwhile are pending and wait for the next step 0).
+        // Launches past the end of every system's cycle would only find idle systems.
         int k = m;
         if (cyc < (int)c->cycle_len.size()) k = std::min(m, c->cycle_len[cyc] + kPredictMargin);
         if (k < m) {
-            rc = launch_segment<T>(c, st, 0, k, kTailNone);
+            rc = launch_segment<T>(c, st, 0, k, kTailUpdate);
             if (rc != MPM_OK) return rc;
             rc = fetch_status(c, st);
             if (rc != MPM_OK) return rc;
-            rc = any_active() ? launch_segment<T>(c, st, k, m, kTailFull) : launch_segment<T>(c, st, k, k, kTailUpdate);
+            if (any_running())
+                rc = launch_segment<T>(c, st, k, m, kTailFull);
+            else
+                have_status = true;
         } else {
             rc = launch_segment<T>(c, st, 0, m, kTailFull);
         }
@@ -2220,7 +2251,8 @@ static int debug_apply_t(Ctx* c, int p, const double* x, double* y, int mode) {
 }
 
 int select_timing(Ctx* c, int kind, int j, int repeat) {
-    const size_t need = 2 * (size_t)c->S * c->P;
+    // per cycle: one timed launch per system and segment, at most two segments
+    const size_t need = 2 * 2 * (size_t)c->S * c->P;
     while (c->tev.size() < need) {
         hipEvent_t e;
         MPM_HIP(hipEventCreate(&e));
