@@ -133,8 +133,11 @@ int32_t mpm_fv_setup(mpm_ctx ctx, int32_t problem, const int32_t* dims, const in
  * fields: host array [nproblems] of device FP64 [S][z][y][x] lattice fields; read as
  * c^n and overwritten with c^{n+1} on the domain voxels of each box.
  * tol > 0: relative FP64 residual to reach per (problem, species).
- * Synchronises the context stream.  Returns MPM_NOT_CONVERGED if some system did
- * not reach tol within max_cycles (the best iterate is written). */
+ * Returns once the outcome of every system is known (the statistics are final); the
+ * writing of c^{n+1} into fields may still be running on the context stream, which the
+ * caller's stream (given to mpm_create) is made to wait for, so work the caller
+ * enqueues on it afterwards sees the new fields.  Returns MPM_NOT_CONVERGED if some
+ * system did not reach tol within max_cycles (the best iterate is written). */
 int32_t mpm_implicit_step(mpm_ctx ctx, double* const* fields, double tol);
 
 /* Statistics of the last step for one (problem, species) system (host output). */
