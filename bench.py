@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--unbatched", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="unknowns per block (0 = library default)")
     ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--start", default="cn", choices=["cn", "extrap"],
+                    help="initial guess of each step: c^n, or 2 c^n - c^{n-1} kept when it lowers the residual")
     ap.add_argument("--ortho", default="dcgs2", choices=["dcgs2", "cgs2"],
                     help="Gram-Schmidt variant of the Arnoldi process")
     ap.add_argument("--time-kernel", default=None,
@@ -106,9 +108,9 @@ def upload(prob, torch):
     return {k: torch.from_numpy(getattr(prob, k)).to(dev) for k in ("mask", "D", "k", "src", "cell_id")}
 
 
-def gpu_solver(m, prob, t, box, precision, graph, batched, tile=0, ortho=1):
+def gpu_solver(m, prob, t, box, precision, graph, batched, tile=0, ortho=1, warm=0):
     s = m.Solver(prob.nspecies, 1, precision=precision, use_graph=int(graph), batched=int(batched),
-                 tile_override=int(tile), ortho=int(ortho))
+                 tile_override=int(tile), ortho=int(ortho), warm_start=int(warm))
     s.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
     return s
 
@@ -130,8 +132,9 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     From the state f0: ``train_pairs`` steps solved to 1e-10 give (input, Δc / RMS)
     pairs on the box grid; the U-Net (16-32-64-64) is trained on them with the library's
     kernels; then the same ``learned_steps`` steps are run from the state after the pair
-    steps, once plain and once with the learned start (accepted per system only when it
-    lowers the true residual), both from graphs, at the benchmark tolerance.
+    steps three times: plain (start c^n), with the extrapolated start 2 c^n - c^{n-1},
+    and with the learned start (each start kept per system only when it lowers the
+    true residual), all from graphs, at the benchmark tolerance.
     """
     import numpy as np
     from paper_2505_03067_amd.train import IN_SCALE
@@ -182,7 +185,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     train_s = time.perf_counter() - t0
     del pairs
     res = {}
-    for name, warm in (("plain", m.MPM_WS_NONE), ("learned", m.MPM_WS_NET)):
+    for name, warm in (("plain", m.MPM_WS_NONE), ("extrapolated", m.MPM_WS_EXTRAP), ("learned", m.MPM_WS_NET)):
         g = f_after.clone()
         s = m.Solver(S, 1, precision=precision, warm_start=warm, ortho=int(ortho))
         s.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
@@ -204,7 +207,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
         s.close()
         res[name] = {"steps_per_s": round(args.learned_steps / el, 3),
                      "iterations_per_step": round(its / (args.learned_steps * S), 2)}
-        if warm == m.MPM_WS_NET:
+        if warm != m.MPM_WS_NONE:
             res[name]["accepted_fraction"] = round(acc / (args.learned_steps * S), 3)
             res[name]["residual_ratio_warm_over_cn"] = round(float(np.mean(rw)), 4) if rw else None
     net.close()
@@ -213,6 +216,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
                        "loss_last": round(float(np.mean(losses[-10:])), 5),
                        "network": "U-Net 16-32-64-64, BF16 MFMA kernels, FP32 Adam, on the box grid"}
     res["learned_over_plain"] = round(res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"], 3)
+    res["extrapolated_over_plain"] = round(res["extrapolated"]["steps_per_s"] / res["plain"]["steps_per_s"], 3)
     return res
 
 
@@ -283,7 +287,8 @@ def main():
     ortho = m.MPM_ORTHO_DCGS2 if args.ortho == "dcgs2" else m.MPM_ORTHO_CGS2
     f = torch.from_numpy(prob.c0).cuda()
 
-    s = gpu_solver(m, prob, t, box, precision, not args.no_graph, not args.unbatched, args.tile, ortho)
+    warm = m.MPM_WS_EXTRAP if args.start == "extrap" else m.MPM_WS_NONE
+    s = gpu_solver(m, prob, t, box, precision, not args.no_graph, not args.unbatched, args.tile, ortho, warm)
     run_steps(s, f, args.warmup, tol, torch)
     c_start = f.clone()
     # headline: K implicit steps from graphs, nothing else on the stream
@@ -332,6 +337,7 @@ def main():
                         f"{prob.nspecies} species, {U} unknowns, tol {tol:g}, "
                         f"{'FP32 GMRES(30) in FP64 refinement' if precision else 'FP64 GMRES(30)'}, "
                         f"{'delayed CGS2' if ortho == m.MPM_ORTHO_DCGS2 else 'CGS2'} Arnoldi, "
+                        f"{'extrapolated start' if warm else 'start c^n'}, "
                         f"{'batched' if not args.unbatched else 'one system at a time'}, "
                         f"{'hipGraph cycles' if not args.no_graph else 'direct launches'}",
             "unknowns": U,
