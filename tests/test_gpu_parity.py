@@ -236,3 +236,35 @@ def test_error_paths():
         assert st["converged"] == 0 and st["cycles"] == 1 and st["iterations"] == 2
         assert st["rel_res_final"] < st["rel_res_initial"]
         assert np.all(np.isfinite(f.cpu().numpy()))
+
+
+@pytest.mark.parametrize("ortho", [0, 1])
+def test_cycle_prediction_miss_is_continued(ortho):
+    """The first launch of a cycle stops at the length the previous step needed; when a
+    harder problem is set up in the same context, systems still running there must be
+    continued to the end of the cycle (and restarted systems wait for the next one)."""
+    torch = require_gpu()
+    from paper_2505_03067_amd import Solver
+    easy = random_problem(91, (30, 26, 22), S=3, fill=0.7, dt=0.05)
+    hard = random_problem(91, (30, 26, 22), S=3, fill=0.7, dt=20.0)
+    f = torch.from_numpy(easy.c0).cuda()
+    with Solver(3, 1, ortho=ortho) as s:
+        d = to_dev(easy)
+        s.setup(0, easy.box, d["mask"], d["D"], d["k"], d["src"], easy.c_b, easy.dt, easy.h)
+        for _ in range(2):
+            s.step([f], 1e-12)
+        its_easy = [s.stats(0, sp)["iterations"] for sp in range(3)]
+        d = to_dev(hard)
+        g = torch.from_numpy(hard.c0).cuda()
+        s.setup(0, hard.box, d["mask"], d["D"], d["k"], d["src"], hard.c_b, hard.dt, hard.h)
+        for _ in range(2):
+            s.step([g], 1e-12)
+        st = [s.stats(0, sp) for sp in range(3)]
+    its_hard = [x["iterations"] for x in st]
+    print("iterations easy", its_easy, "hard", its_hard)
+    assert max(its_hard) > max(its_easy) + 4          # the prediction was short
+    want, _ = run(hard, steps=2, solver="pcg", tol=1e-13)
+    mb = hard.mask[box_slice(hard.box)].astype(bool)
+    errs = rel_err_per_species(g.cpu().numpy(), want, mb, hard.box)
+    assert max(errs) <= PARITY, errs
+    assert all(x["converged"] == 1 for x in st)
