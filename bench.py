@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config2-dense", "config1"])
+    ap.add_argument("--workload", default="config2", choices=["config2", "config2-dense", "config1", "config5"])
     ap.add_argument("--precision", default="fp32ir", choices=["fp32ir", "fp64"])
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--unbatched", action="store_true")
@@ -95,11 +95,13 @@ def measured_traffic(kernel, workload, tile):
 
 
 def make_workload(name):
-    from synth import config1, config2, config2_dense
+    from synth import config1, config2, config2_dense, config5
     if name == "config2":
         return config2()
     if name == "config2-dense":
         return config2_dense()
+    if name == "config5":
+        return config5()
     return config1()
 
 
