@@ -75,7 +75,9 @@ typedef struct {
     int32_t precision;   /* MPM_FP64 or MPM_FP32_IR (default MPM_FP32_IR) */
     int32_t batched;     /* 1: every (problem, species) system in each launch (default);
                             0: one system after another */
-    int32_t use_graph;   /* 1: replay each GMRES cycle from a captured hipGraph */
+    int32_t use_graph;   /* 1: replay each GMRES cycle from a captured hipGraph; 0 (default):
+                            launch the kernels directly (measured at least as fast on MI355X
+                            on every workload tried: each kernel runs longer than its launch) */
     int32_t warm_start;  /* MPM_WS_NONE, MPM_WS_NET or MPM_WS_EXTRAP */
     int32_t tile_override; /* 0: autotuned work split; >0: unknowns per block (multiple of 1024) */
     int32_t ortho;       /* MPM_ORTHO_DCGS2 (default): classical Gram-Schmidt with delayed
@@ -134,9 +136,11 @@ int32_t mpm_fv_setup(mpm_ctx ctx, int32_t problem, const int32_t* dims, const in
  * c^n and overwritten with c^{n+1} on the domain voxels of each box.
  * tol > 0: relative FP64 residual to reach per (problem, species).
  * Returns once the outcome of every system is known (the statistics are final); the
- * writing of c^{n+1} into fields may still be running on the context stream, which the
- * caller's stream (given to mpm_create) is made to wait for, so work the caller
- * enqueues on it afterwards sees the new fields.  Returns MPM_NOT_CONVERGED if some
+ * writing of c^{n+1} into fields may still be running, ordered before the work the
+ * caller enqueues afterwards on the stream given to mpm_create (with use_graph, the
+ * context runs on a private stream which that stream is made to wait for).  At the end of each GMRES cycle the
+ * calling thread reads the state of every system, which the GPU writes into pinned
+ * host memory; it waits for it by polling for up to 5 ms, then blocks.  Returns MPM_NOT_CONVERGED if some
  * system did not reach tol within max_cycles (the best iterate is written). */
 int32_t mpm_implicit_step(mpm_ctx ctx, double* const* fields, double tol);
 
@@ -150,7 +154,7 @@ int32_t mpm_destroy(mpm_ctx ctx);
 const char* mpm_last_error(void);
 
 /* Measurement hook: time every launch of one kernel of the GMRES cycle with HIP
- * events recorded on the context's own stream (the stream the kernels run on).
+ * events recorded on the stream the kernels run on.
  * kind: MPM_KERNEL_NONE (off), MPM_KERNEL_SPMV_DOT (stencil + multi-dot: the first
  * Gram-Schmidt pass, or all dot products of the delayed scheme), MPM_KERNEL_AXPY_DOT
  * (second pass; the delayed scheme's axpy kernel), MPM_KERNEL_AXPY_NORM (third pass;

@@ -19,7 +19,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 static void destroy_ctx(Ctx* c) {
     if (!c) return;
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     for (auto& ph : c->probs) free_problem(ph);
     for (auto& kv : c->graphs)
         if (kv.second) (void)hipGraphExecDestroy(kv.second);
@@ -42,19 +42,23 @@ static void destroy_ctx(Ctx* c) {
     (void)hipFree(c->prev);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->ev_status) (void)hipEventDestroy(c->ev_status);
     for (auto e : c->tev) (void)hipEventDestroy(e);
-    if (c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
-// Order the context's private stream after the caller's stream (entry) and the
-// caller's stream after the private one (exit).
+// With a private stream (graph capture cannot run on the caller's stream, which may be
+// the null stream), order it after the caller's stream (entry) and the caller's stream
+// after it (exit).  Without one, the work is on the caller's stream already.
 static int enter(Ctx* c) {
+    if (!c->own_stream) return MPM_OK;
     MPM_HIP(hipEventRecord(c->ev_in, c->user_stream));
     MPM_HIP(hipStreamWaitEvent(c->stream, c->ev_in, 0));
     return MPM_OK;
 }
 static int leave(Ctx* c) {
+    if (!c->own_stream) return MPM_OK;
     MPM_HIP(hipEventRecord(c->ev_out, c->stream));
     MPM_HIP(hipStreamWaitEvent(c->user_stream, c->ev_out, 0));
     return MPM_OK;
@@ -76,7 +80,7 @@ extern "C" int32_t mpm_default_options(mpm_options* opt) {
     opt->max_cycles = 50;
     opt->precision = MPM_FP32_IR;
     opt->batched = 1;
-    opt->use_graph = 1;
+    opt->use_graph = 0;
     opt->warm_start = MPM_WS_NONE;
     opt->tile_override = 0;
     opt->inner_rtol = 1e-6;
@@ -114,9 +118,13 @@ extern "C" int32_t mpm_create(mpm_ctx* out, int32_t nspecies, int32_t nproblems,
     c->probs.resize(nproblems);
     c->stats.assign((size_t)nspecies * nproblems, mpm_stats{});
     const int nsys = nspecies * nproblems;
-    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    hipError_t e = hipSuccess;
+    c->own_stream = o.use_graph != 0;
+    if (c->own_stream) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    else c->stream = c->user_stream;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_status, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&c->d_probs, nproblems * sizeof(ProbDev));
     if (e == hipSuccess) e = hipMalloc(&c->d_sk, nsys * sizeof(SysK));
     if (e == hipSuccess) e = hipMalloc(&c->d_prm, sizeof(Params));
@@ -125,7 +133,11 @@ extern "C" int32_t mpm_create(mpm_ctx* out, int32_t nspecies, int32_t nproblems,
     if (e == hipSuccess) e = hipMalloc(&c->d_fields, nproblems * sizeof(double*));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_fields, nproblems * sizeof(double*), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_prm, sizeof(Params), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sk, nsys * sizeof(SysK), hipHostMallocDefault);
+    // coherent: the status heads are written there by kernels and read by the host
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&c->h_sk, nsys * sizeof(SysK), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->hsk_dev, c->h_sk, 0);
+    if (e == hipSuccess) std::memset(c->h_sk, 0, nsys * sizeof(SysK));
     if (e == hipSuccess) e = hipMemset(c->d_sk, 0, nsys * sizeof(SysK));
     if (e != hipSuccess) {
         int r = hip_fail(e, "mpm_create");
@@ -224,7 +236,7 @@ extern "C" int32_t mpm_gmres_stats(mpm_ctx ctx, int32_t problem, int32_t species
         set_error("mpm_gmres_stats: no step has run yet");
         return MPM_ESTATE;
     }
-    MPM_HIP(hipStreamSynchronize(c->stream));
+    // filled on the host when mpm_implicit_step returned: nothing to wait for
     *out = c->stats[(size_t)problem * c->S + species];
     return MPM_OK;
 }

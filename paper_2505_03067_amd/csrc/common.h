@@ -129,6 +129,7 @@ struct KArgs {
     double* x;             // FP64 iterate
     double* b;             // FP64 right-hand side
     double* const* fields; // [P] lattice fields (device pointers)
+    SysK* hsk;             // host-visible mirror of the status heads (pinned host memory)
     long long ldv;
     int nslots;
     int S;

@@ -43,8 +43,11 @@ struct Ctx {
     int S = 0, P = 0;
     mpm_options opt{};
     hipStream_t user_stream = nullptr;
-    hipStream_t stream = nullptr;      // private stream (capturable)
+    hipStream_t stream = nullptr;      // where the work goes: the caller's stream, or a private
+                                       // one when cycles are captured into graphs
+    bool own_stream = false;           // stream is private
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t ev_status = nullptr;    // the status head has reached the host
     std::vector<ProbHost> probs;
 
     // global layout of the work vectors: problem p occupies
@@ -83,6 +86,7 @@ struct Ctx {
     Params* h_prm = nullptr;
     bool up_valid = false;
     SysK* h_sk = nullptr;
+    SysK* hsk_dev = nullptr;           // device address of h_sk (k_res_final writes the heads)
 
     // graphs of GMRES cycle segments, keyed by (first step, end step, tail kind)
     std::map<int, hipGraphExec_t> graphs;

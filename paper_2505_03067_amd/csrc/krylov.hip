@@ -435,12 +435,11 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
     block_partials<2>(acc, a.part + (long long)kRowR * a.nslots, a.nslots, blk.slot);
 }
 
-// One block per system: norms, convergence test, start of the next cycle; in warm
-// mode the acceptance test of the warm start (kept only if its true residual is
-// below that of c^n, else the system falls back to c^n).
+// Norms, convergence test, start of the next cycle for one system; in warm mode the
+// acceptance test of the warm start (kept only if its true residual is below that of
+// c^n, else the system falls back to c^n).  Thread 0 stores the outcome.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_res_final(KArgs<T> a, int sys0, int mode) {
-    const int sys = sys0 + blockIdx.x;
+__device__ inline void res_final_sys(const KArgs<T>& a, int sys, int mode) {
     SysK* sk = a.sk + sys;
     if (res_skip(sk, mode)) return;
     const bool first = mode == kResFirst;
@@ -492,6 +491,23 @@ __global__ __launch_bounds__(kThreads) void k_res_final(KArgs<T> a, int sys0, in
         sk->vs[0] = 1.0 / srn;
         sk->gt[0] = srn;
         sk->active = kPending;
+    }
+}
+
+// One block per system.  Ends every launch of the step (first residual, warm start,
+// each cycle), so it also copies each system's status head, whether this launch changed
+// it or not, to the host-visible mirror the host reads between cycles.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_res_final(KArgs<T> a, int sys0, int mode) {
+    const int sys = sys0 + blockIdx.x;
+    res_final_sys<T>(a, sys, mode);
+    __syncthreads();
+    static_assert(kSysHead % 4 == 0 && kSysHead / 4 <= kThreads, "status head copied as words");
+    if (threadIdx.x < kSysHead / 4) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(a.sk + sys);
+        volatile uint32_t* dst = reinterpret_cast<volatile uint32_t*>(a.hsk + sys);
+        dst[threadIdx.x] = src[threadIdx.x];
+        __threadfence_system();
     }
 }
 
@@ -808,11 +824,14 @@ __global__ __launch_bounds__(kThreads) void k_update(KArgs<T> a) {
     }
 }
 
+// Write x into the lattice field on the domain voxels.  only_idle: only for the systems
+// whose solve has ended (neither running nor waiting for another cycle).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scatter(KArgs<T> a) {
+__global__ __launch_bounds__(kThreads) void k_scatter(KArgs<T> a, int only_idle) {
     constexpr int n = 4;
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0) return;
+    if (only_idle && a.sk[blk.sys].active != kIdle) return;
     double* f = a.fields[blk.p] + (long long)blk.s * blk.nvox;
     const gptr<int> vox = as_global(blk.vox);
     for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
@@ -1865,6 +1884,7 @@ static KArgs<T> make_args(Ctx* c, const Block* blocks) {
     a.x = c->x;
     a.b = c->b;
     a.fields = c->d_fields;
+    a.hsk = c->hsk_dev;
     a.ldv = c->ldv;
     a.nslots = c->nslots;
     a.S = c->S;
@@ -2001,6 +2021,10 @@ static void drop_graphs(Ctx* c) {
     c->graphs.clear();
 }
 
+// Arnoldi steps at the head of a segment that are launched directly when the rest of the
+// segment comes from a graph: the GPU runs them while the graph is being submitted.
+constexpr int kGraphHead = 2;
+
 // Launch one segment of a cycle: from a cached graph, or directly while a kernel is
 // timed (events inside a captured graph cannot be timed).
 template <typename T>
@@ -2011,6 +2035,13 @@ static int launch_segment(Ctx* c, hipStream_t st, int j0, int j1, int tail) {
         MPM_HIP(hipGetLastError());
         return MPM_OK;
     }
+    const int jh = std::min(j1, j0 + kGraphHead);
+    if (jh > j0) {
+        enqueue_cycle_all<T>(c, st, j0, jh, kTailNone, false);
+        MPM_HIP(hipGetLastError());
+        j0 = jh;
+    }
+    if (j0 == j1 && tail == kTailNone) return MPM_OK;
     const int key = (j0 * (kMaxM + 1) + j1) * 3 + tail;
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
@@ -2028,12 +2059,27 @@ static int launch_segment(Ctx* c, hipStream_t st, int j0, int j1, int tail) {
     return MPM_OK;
 }
 
-// Copy the status head of every system record to the host and wait for it.
+// Wait until the work enqueued so far has run, when the status heads of every system
+// are in the host mirror (the last kernel enqueued is always k_res_final, which writes
+// them).  Behind that point, the iterates of the systems whose solve has ended go to the
+// lattice fields while the host reads the status: after the last cycle nothing is left
+// to launch.  The wait polls the event for up to kSpinMs (a blocking wait adds tens of
+// microseconds of wake-up latency to every cycle), then blocks.
+constexpr double kSpinMs = 5.0;
+
+template <typename T>
 static int fetch_status(Ctx* c, hipStream_t st) {
-    const int nsys = c->S * c->P;
-    MPM_HIP(hipMemcpy2DAsync(c->h_sk, sizeof(SysK), c->d_sk, sizeof(SysK), kSysHead, nsys,
-                             hipMemcpyDeviceToHost, st));
-    MPM_HIP(hipStreamSynchronize(st));
+    MPM_HIP(hipEventRecord(c->ev_status, st));
+    k_scatter<T><<<(unsigned)c->blocks.size(), kThreads, 0, st>>>(make_args<T>(c, c->d_blocks), 1);
+    MPM_HIP(hipGetLastError());
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipEventQuery(c->ev_status);
+        if (e == hipSuccess) return MPM_OK;
+        if (e != hipErrorNotReady) return hip_fail(e, "hipEventQuery");
+        if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > kSpinMs) break;
+    }
+    MPM_HIP(hipEventSynchronize(c->ev_status));
     return MPM_OK;
 }
 
@@ -2117,10 +2163,9 @@ static int run_step_t(Ctx* c, double tol) {
     };
     bool have_status = false;   // h_sk already holds the end state of the last cycle
     for (int cyc = 0;; ++cyc) {
-        if (cyc == 0 && speculate) {
-            for (int s = 0; s < nsys; ++s) c->h_sk[s].active = kPending;
-        } else if (!have_status) {
-            rc = fetch_status(c, st);
+        const bool spec = cyc == 0 && speculate;   // launched with no status to go by
+        if (!spec && !have_status) {
+            rc = fetch_status<T>(c, st);
             if (rc != MPM_OK) return rc;
         }
         have_status = false;
@@ -2135,10 +2180,10 @@ static int run_step_t(Ctx* c, double tol) {
                 for (int s = 0; s < nsys; ++s) c->prev_cycles[s] = c->h_sk[s].cycles;
         }
         bool bad = false;
-        if (!(cyc == 0 && speculate))
+        if (!spec)
             for (int s = 0; s < nsys; ++s)
                 if (c->h_sk[s].breakdown && !c->h_sk[s].converged) bad = true;
-        if (!any_active()) {
+        if (!spec && !any_active()) {
             if (bad) status = MPM_NOT_CONVERGED;
             break;
         }
@@ -2157,7 +2202,7 @@ static int run_step_t(Ctx* c, double tol) {
         if (k < m) {
             rc = launch_segment<T>(c, st, 0, k, kTailUpdate);
             if (rc != MPM_OK) return rc;
-            rc = fetch_status(c, st);
+            rc = fetch_status<T>(c, st);
             if (rc != MPM_OK) return rc;
             if (any_running())
                 rc = launch_segment<T>(c, st, k, m, kTailFull);
@@ -2169,7 +2214,9 @@ static int run_step_t(Ctx* c, double tol) {
         if (rc != MPM_OK) return rc;
     }
     c->cycle_len = c->cycle_len_next;
-    k_scatter<T><<<nb, kThreads, 0, st>>>(a);
+    // every system that ended its solve was written behind the last status wait; the
+    // others (cycle limit reached) are written here with their best iterate
+    if (any_active()) k_scatter<T><<<nb, kThreads, 0, st>>>(a, 0);
     if (extrap) {
         // this step's c^n becomes the previous step of the next extrapolation
         k_copy64<<<(unsigned)((nall + 255) / 256), 256, 0, st>>>(c->prev + nall, c->prev, nall);
@@ -2200,7 +2247,8 @@ int run_step(Ctx* c, double* const* fields, double tol) {
     if (rc != MPM_OK) return rc;
     hipStream_t st = c->stream;
     // field pointers and scalar parameters go to the device only when they change (the
-    // previous step ended with a stream synchronisation, so the pinned copies are free)
+    // previous step waited for its last status copy, which follows these uploads on the
+    // stream, so the pinned copies are free)
     bool fields_changed = !c->up_valid;
     for (int p = 0; p < c->P; ++p) {
         if (c->h_fields[p] != fields[p]) fields_changed = true;

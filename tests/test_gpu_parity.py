@@ -142,7 +142,7 @@ def test_cell_bounding_box_workload_small():
     _check_parity(p, 2, box=box)
 
 
-@pytest.mark.parametrize("opts", [dict(batched=0), dict(use_graph=0), dict(restart=5),
+@pytest.mark.parametrize("opts", [dict(batched=0), dict(use_graph=1), dict(restart=5),
                                   dict(restart=1, max_cycles=2000), dict(tile_override=2048),
                                   dict(restart=2, max_cycles=1000), dict(restart=30, tile_override=1024),
                                   dict(ortho=0, restart=5), dict(ortho=0, restart=1, max_cycles=2000),
@@ -159,11 +159,40 @@ def test_batched_graph_and_unbatched_are_bit_identical(ortho):
     p = random_problem(32, (29, 31, 27), S=3, fill=0.6)
     tile = dict(tile_override=2048, ortho=ortho)   # the reduction order follows the work split
     ref, _ = gpu_run(p, 2, 1e-10, **tile)
-    for opts in (dict(batched=0), dict(use_graph=0), dict(batched=0, use_graph=0)):
+    for opts in (dict(batched=0), dict(use_graph=1), dict(batched=0, use_graph=1)):
         got, _ = gpu_run(p, 2, 1e-10, **tile, **opts)
         assert np.array_equal(got, ref), opts
     again, _ = gpu_run(p, 2, 1e-10, **tile)            # run-to-run determinism
     assert np.array_equal(again, ref)
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_caller_stream_ordering(use_graph):
+    """A context created on a side stream: the fields written on that stream just before
+    each step and read on it right after are seen in order, with the kernels launched
+    on the caller's stream itself or on a private stream (graphs)."""
+    torch = require_gpu()
+    from paper_2505_03067_amd import Solver
+    p = random_problem(33, (27, 25, 23), S=3, fill=0.6)
+    tile = dict(tile_override=2048)
+    ref, _ = gpu_run(p, 2, 1e-10, **tile)
+    d = to_dev(p)
+    c0 = torch.from_numpy(p.c0).cuda()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        f = torch.empty_like(c0)
+        with Solver(3, 1, stream=side.cuda_stream, use_graph=use_graph, **tile) as s:
+            s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+            f.copy_(c0)
+            s.step([f], 1e-10)
+            mid = f.clone()
+            s.step([f], 1e-10)
+            out = f.clone()
+        side.synchronize()
+    ref1, _ = gpu_run(p, 1, 1e-10, **tile)
+    assert np.array_equal(mid.cpu().numpy(), ref1)
+    assert np.array_equal(out.cpu().numpy(), ref)
 
 
 def test_edge_cases_tiny_boxes():

@@ -9,7 +9,7 @@ from synth import random_problem
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("opts", [dict(), dict(use_graph=0), dict(batched=0), dict(ortho=0),
+@pytest.mark.parametrize("opts", [dict(), dict(use_graph=1), dict(batched=0), dict(ortho=0),
                                   dict(ortho=0, batched=0)])
 @pytest.mark.parametrize("kind,j", [(2, 3), (1, 0), (3, 5), (4, 0), (5, 0)])
 def test_timing_hook(opts, kind, j):
