@@ -40,7 +40,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="config2", choices=["config2", "config2-dense", "config1", "config5"])
+    ap.add_argument("--workload", default="config2",
+                    choices=["config2", "config2-dense", "config1", "config5", "cube100", "cube150", "cube200"])
+    ap.add_argument("--grow", action="store_true",
+                    help="lung workloads: cells grow every step; the box is recomputed and the "
+                         "operator rebuilt before each step (timed with the step)")
+    ap.add_argument("--species", type=int, default=3, choices=[3, 4],
+                    help="4: the interleukins as separate fields (config2/config2-dense/config5/cube*)")
     ap.add_argument("--precision", default="fp32ir", choices=["fp32ir", "fp64"])
     ap.add_argument("--graph", action="store_true",
                     help="replay each GMRES cycle from a captured hipGraph (default: direct launches)")
@@ -96,14 +102,16 @@ def measured_traffic(kernel, workload, tile):
     return None
 
 
-def make_workload(name):
-    from synth import config1, config2, config2_dense, config5
+def make_workload(name, species=3):
+    from synth import config1, config2, config2_dense, config5, cube
     if name == "config2":
-        return config2()
+        return config2(species=species)
     if name == "config2-dense":
-        return config2_dense()
+        return config2_dense(species=species)
     if name == "config5":
-        return config5()
+        return config5(species=species)
+    if name.startswith("cube"):
+        return cube(int(name[4:]), species=species)
     return config1()
 
 
@@ -119,9 +127,43 @@ def gpu_solver(m, prob, t, box, precision, graph, batched, tile=0, ortho=1, warm
     return s
 
 
-def run_steps(s, f, n, tol, torch):
+class Grower:
+    """Cell growth between steps (the cell model's part, outside the solve): each step
+    applies precomputed growth to the device arrays, then recomputes the box
+    (mpm_bbox_from_cells) and rebuilds the operator on it (mpm_fv_setup)."""
+
+    def __init__(self, m, prob, t, steps, torch):
+        from synth.geometry import grow_cells
+        dev = torch.device("cuda")
+        self.m, self.prob, self.t = m, prob, t
+        self.events = [tuple(torch.from_numpy(a).to(dev) for a in (g.index, g.cell, g.k, g.src))
+                       for g in grow_cells(prob, steps)]
+        self.i = 0
+        self.grown = 0
+        self.setup_s = 0.0
+        self.boxes = []
+
+    def __call__(self, s):
+        idx, ids, kv, sv = self.events[self.i]
+        self.i += 1
+        S = self.prob.nspecies
+        self.t["cell_id"].view(-1)[idx] = ids
+        self.t["k"].view(S, -1)[:, idx] = kv
+        self.t["src"].view(S, -1)[:, idx] = sv
+        t0 = time.perf_counter()        # both calls below wait for their results
+        box = self.m.mpm_bbox_from_cells(self.t["cell_id"], self.prob.margin)
+        s.setup(0, box, self.t["mask"], self.t["D"], self.t["k"], self.t["src"], self.prob.c_b,
+                self.prob.dt, self.prob.h)
+        self.setup_s += time.perf_counter() - t0
+        self.boxes.append(box)
+        self.grown += int(idx.numel())
+
+
+def run_steps(s, f, n, tol, torch, grow=None):
     its = []
     for _ in range(n):
+        if grow is not None:
+            grow(s)
         rc = s.step([f], tol)
         if rc != 0:
             raise RuntimeError(f"step did not converge (status {rc})")
@@ -280,7 +322,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     m.lib()
-    prob = make_workload(args.workload)
+    prob = make_workload(args.workload, args.species)
     tol = args.tol if args.tol is not None else prob.tol
     t = upload(prob, torch)
     if prob.box is not None:
@@ -293,14 +335,26 @@ def main():
 
     warm = m.MPM_WS_EXTRAP if args.start == "extrap" else m.MPM_WS_NONE
     s = gpu_solver(m, prob, t, box, precision, args.graph, not args.unbatched, args.tile, ortho, warm)
-    run_steps(s, f, args.warmup, tol, torch)
+    grow = None
+    if args.grow:
+        if prob.box is not None:
+            raise SystemExit("--grow needs a workload whose box follows the cells (config2, config5)")
+        grow = Grower(m, prob, t, args.warmup + args.steps, torch)
+    run_steps(s, f, args.warmup, tol, torch, grow)
     c_start = f.clone()
-    # headline: K implicit steps, nothing else on the stream
+    # headline: K implicit steps, nothing else on the stream (with --grow, each one after
+    # the growth of the cells, the new box and the rebuilt operator)
     torch.cuda.synchronize()
+    box0 = box
+    if grow is not None:
+        grow.setup_s, grow.grown = 0.0, 0
+        box0 = grow.boxes[-1] if grow.boxes else box
     t0 = time.perf_counter()
-    its = run_steps(s, f, args.steps, tol, torch)
+    its = run_steps(s, f, args.steps, tol, torch, grow)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if grow is not None:
+        box = grow.boxes[-1]
     tile_used = s.tile()
     final_stats = [s.stats(0, sp) for sp in range(prob.nspecies)]
     # roofline phase: the same solver continues for a few steps with one kernel timed by
@@ -350,6 +404,14 @@ def main():
             "unknowns_per_block": tile_used,
         },
         "iterations_per_step": round(sum(its) / len(its) / prob.nspecies, 2),
+        **({"growth": {
+            "what": "per step: cell growth, mpm_bbox_from_cells, mpm_fv_setup on the new box, "
+                    "then the step; all inside the timed steps",
+            "voxels_grown_per_step": round(grow.grown / args.steps, 2),
+            "box_first": [list(box0[0]), list(box0[1])],
+            "box_last": [list(box[0]), list(box[1])],
+            "bbox_and_setup_ms_per_step": round(1000.0 * grow.setup_s / args.steps, 4),
+        }} if grow is not None else {}),
         "cycles_last_step": [st["cycles"] for st in final_stats],
         "rel_res_final_last_step": [st["rel_res_final"] for st in final_stats],
     }
@@ -377,11 +439,12 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(kernel, args.workload, args.tile),
+            "traffic": measured_traffic(kernel, prob.name, args.tile),
             "avg_launch_us": round(1000.0 * avg_ms, 3),
             "launches": timing["launches"],
             "launches_per_event_pair": repeat,
-            "phase": f"{args.roofline_steps} steps after the headline timing, cycle launched directly",
+            "phase": f"{args.roofline_steps} steps after the headline timing (no growth), "
+                     f"cycle launched directly",
             "copy_1gib_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
             "alg_bytes_per_launch": round(timing["bytes"] / timing["launches"]),

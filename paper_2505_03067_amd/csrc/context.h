@@ -30,7 +30,15 @@ struct ProbHost {
     double* sc64 = nullptr;
     float* c32 = nullptr;
     double* c64 = nullptr;
-    size_t cap_pad = 0;        // Npad the buffers were sized for
+    size_t cap_pad = 0;        // padded unknowns per species the buffers hold (>= Npad)
+    // scratch of mpm_fv_setup, kept between calls (a box that changes every step
+    // reuses it): per-row counts and starts, box-to-domain map, compacted voxels, total
+    int* s_rowcnt = nullptr;
+    int* s_rowstart = nullptr;
+    int* s_boxmap = nullptr;
+    int* s_vox = nullptr;
+    int* s_total = nullptr;
+    size_t cap_rows = 0, cap_boxvox = 0, cap_svox = 0;
     // warm start: static network input channels on the box grid (k, D, s, mask)
     int gd[3] = {0, 0, 0};
     float* stat = nullptr;

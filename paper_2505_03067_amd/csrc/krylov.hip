@@ -1771,22 +1771,24 @@ int ensure_layout(Ctx* c) {
     const size_t need = (size_t)(run + kAlign);
     const int m = c->opt.restart;
     if (need > c->cap_U) {
+        // room for growth: a box that grows step by step keeps its workspace
         free_work(c);
         const size_t ks = ksize(c);
-        if (hipMalloc(&c->V, (size_t)(m + 1) * need * ks) != hipSuccess ||
-            hipMalloc(&c->W, need * ks) != hipSuccess || hipMalloc(&c->x, need * 8) != hipSuccess ||
-            hipMalloc(&c->b, need * 8) != hipSuccess) {
+        const size_t cap = (need + need / 8 + kAlign - 1) / kAlign * kAlign;
+        if (hipMalloc(&c->V, (size_t)(m + 1) * cap * ks) != hipSuccess ||
+            hipMalloc(&c->W, cap * ks) != hipSuccess || hipMalloc(&c->x, cap * 8) != hipSuccess ||
+            hipMalloc(&c->b, cap * 8) != hipSuccess) {
             (void)hipGetLastError();
             free_work(c);
             set_error("device allocation of the Krylov workspace failed");
             return MPM_ENOMEM;
         }
-        c->cap_U = need;
-        c->ldv = (long long)need;
-        MPM_HIP(hipMemsetAsync(c->V, 0, (size_t)(m + 1) * need * ks, st));
-        MPM_HIP(hipMemsetAsync(c->W, 0, need * ks, st));
-        MPM_HIP(hipMemsetAsync(c->x, 0, need * 8, st));
-        MPM_HIP(hipMemsetAsync(c->b, 0, need * 8, st));
+        c->cap_U = cap;
+        c->ldv = (long long)cap;
+        MPM_HIP(hipMemsetAsync(c->V, 0, (size_t)(m + 1) * cap * ks, st));
+        MPM_HIP(hipMemsetAsync(c->W, 0, cap * ks, st));
+        MPM_HIP(hipMemsetAsync(c->x, 0, cap * 8, st));
+        MPM_HIP(hipMemsetAsync(c->b, 0, cap * 8, st));
     }
     std::vector<ProbDev> pd(c->P);
     for (int p = 0; p < c->P; ++p) {
@@ -1839,8 +1841,10 @@ int ensure_layout(Ctx* c) {
     // work split: fixed override, cached tuning result, or a fresh autotune
     long long tile = c->opt.tile_override;
     if (tile <= 0) {
+        // sizes within about 9% of each other share a tuning result (a box that changes a
+        // little every step is not tuned again)
         std::string key = std::to_string(c->S) + ":" + std::to_string(ksize(c));
-        for (auto& ph : c->probs) key += ":" + std::to_string(ph.Npad);
+        for (auto& ph : c->probs) key += ":" + std::to_string((int)std::floor(8.0 * std::log2((double)ph.Npad)));
         auto it = c->tile_cache.find(key);
         if (it != c->tile_cache.end()) {
             tile = it->second;

@@ -285,7 +285,57 @@ __global__ void k_ws_static(const uint8_t* mask, const double* D, const double* 
     o[3 * S] = mask[v] ? 1.f : 0.f;
 }
 
+// Grow a scratch buffer to hold n elements (with room for later growth).
+template <typename T>
+static hipError_t reserve(T** p, size_t* cap, size_t n) {
+    if (n <= *cap) return hipSuccess;
+    (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const size_t want = n + n / 8 + 1024;
+    hipError_t e = hipMalloc(p, want * sizeof(T));
+    if (e == hipSuccess) *cap = want;
+    return e;
+}
+
+static void free_scratch(ProbHost& ph) {
+    (void)hipFree(ph.s_rowcnt);
+    (void)hipFree(ph.s_rowstart);
+    (void)hipFree(ph.s_boxmap);
+    (void)hipFree(ph.s_vox);
+    (void)hipFree(ph.s_total);
+    ph.s_rowcnt = ph.s_rowstart = ph.s_boxmap = ph.s_vox = ph.s_total = nullptr;
+    ph.cap_rows = ph.cap_boxvox = ph.cap_svox = 0;
+}
+
+// Scratch of one setup call: per-row counts and starts, the box-to-domain map, the
+// compacted voxel list (npad elements, 0 = not needed yet) and the total.
+static int reserve_scratch(ProbHost& ph, size_t rows, size_t boxvox, size_t npad) {
+    hipError_t e = hipSuccess;
+    if (rows > ph.cap_rows) {
+        (void)hipFree(ph.s_rowcnt);
+        (void)hipFree(ph.s_rowstart);
+        ph.s_rowcnt = ph.s_rowstart = nullptr;
+        ph.cap_rows = 0;
+        const size_t want = rows + rows / 8 + 1024;
+        e = hipMalloc(&ph.s_rowcnt, want * sizeof(int));
+        if (e == hipSuccess) e = hipMalloc(&ph.s_rowstart, want * sizeof(int));
+        if (e == hipSuccess) ph.cap_rows = want;
+    }
+    if (e == hipSuccess) e = reserve(&ph.s_boxmap, &ph.cap_boxvox, boxvox);
+    if (e == hipSuccess) e = reserve(&ph.s_vox, &ph.cap_svox, npad);
+    if (e == hipSuccess && !ph.s_total) e = hipMalloc(&ph.s_total, sizeof(int));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_scratch(ph);
+        set_error("mpm_fv_setup: device allocation failed");
+        return MPM_ENOMEM;
+    }
+    return MPM_OK;
+}
+
 void free_problem(ProbHost& ph) {
+    free_scratch(ph);
     free_padded(ph.vox);
     free_padded(ph.nbr);
     free_padded(ph.d64);
@@ -304,20 +354,53 @@ void free_problem(ProbHost& ph) {
     ph.cap_grid = 0;
 }
 
-static int alloc_problem(ProbHost& ph, int S, int Npad) {
-    if ((size_t)Npad <= ph.cap_pad) return MPM_OK;
-    free_problem(ph);
+// Zero elements [from, to) of a padded array (its trailing padding included).
+template <typename T>
+static hipError_t zero_tail(T* p, size_t from, size_t to, hipStream_t st) {
+    return to > from ? hipMemsetAsync(p + from, 0, (to - from) * sizeof(T), st) : hipSuccess;
+}
+
+// Coefficient arrays for Npad padded unknowns per species.  They are sized with room
+// for growth (a box that grows step by step keeps them); when reused, everything past
+// the part the new layout writes is zeroed, so reads past the data see zero couplings
+// exactly as in a fresh allocation.
+static int alloc_problem(ProbHost& ph, int S, int Npad, hipStream_t st) {
     const size_t n = (size_t)Npad, u = (size_t)S * Npad;
-    if (alloc_padded(&ph.vox, n) != hipSuccess || alloc_padded(&ph.nbr, n) != hipSuccess ||
-        alloc_padded(&ph.d64, u) != hipSuccess || alloc_padded(&ph.q64, u) != hipSuccess ||
-        alloc_padded(&ph.a64, 3 * u) != hipSuccess || alloc_padded(&ph.sc64, u) != hipSuccess ||
-        alloc_padded(&ph.c32, 3 * u) != hipSuccess || alloc_padded(&ph.c64, 3 * u) != hipSuccess) {
+    if (n <= ph.cap_pad) {
+        // ends of the allocations (each carries kAlign elements past its capacity)
+        const size_t cn = ph.cap_pad + kAlign, cu = (size_t)S * ph.cap_pad + kAlign;
+        const size_t cu3 = 3 * (size_t)S * ph.cap_pad + kAlign;
+        hipError_t e = zero_tail(ph.vox, n, cn, st);
+        if (e == hipSuccess) e = zero_tail(ph.nbr, n, cn, st);
+        if (e == hipSuccess) e = zero_tail(ph.d64, u, cu, st);
+        if (e == hipSuccess) e = zero_tail(ph.q64, u, cu, st);
+        if (e == hipSuccess) e = zero_tail(ph.sc64, u, cu, st);
+        if (e == hipSuccess) e = zero_tail(ph.a64, 3 * u, cu3, st);
+        if (e == hipSuccess) e = zero_tail(ph.c32, 3 * u, cu3, st);
+        if (e == hipSuccess) e = zero_tail(ph.c64, 3 * u, cu3, st);
+        return e == hipSuccess ? MPM_OK : hip_fail(e, "mpm_fv_setup (reuse)");
+    }
+    // keep the setup scratch, drop the rest
+    free_padded(ph.vox);
+    free_padded(ph.nbr);
+    free_padded(ph.d64);
+    free_padded(ph.q64);
+    free_padded(ph.a64);
+    free_padded(ph.sc64);
+    free_padded(ph.c32);
+    free_padded(ph.c64);
+    ph.cap_pad = 0;
+    const size_t cn = (n + n / 8 + kAlign - 1) / kAlign * kAlign, cu = (size_t)S * cn;
+    if (alloc_padded(&ph.vox, cn) != hipSuccess || alloc_padded(&ph.nbr, cn) != hipSuccess ||
+        alloc_padded(&ph.d64, cu) != hipSuccess || alloc_padded(&ph.q64, cu) != hipSuccess ||
+        alloc_padded(&ph.a64, 3 * cu) != hipSuccess || alloc_padded(&ph.sc64, cu) != hipSuccess ||
+        alloc_padded(&ph.c32, 3 * cu) != hipSuccess || alloc_padded(&ph.c64, 3 * cu) != hipSuccess) {
         free_problem(ph);
         (void)hipGetLastError();
         set_error("mpm_fv_setup: device allocation failed");
         return MPM_ENOMEM;
     }
-    ph.cap_pad = Npad;
+    ph.cap_pad = cn;
     return MPM_OK;
 }
 
@@ -333,63 +416,32 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     const int rows = g.by * g.bz;
     const long long boxvox = (long long)rows * g.bx;
 
-    int* rowcnt = nullptr;
-    int* rowstart = nullptr;
-    int* boxmap = nullptr;
-    int* vox_tmp = nullptr;
-    int* total_d = nullptr;
     int total_h = 0;
-    int rc = MPM_OK;
-    auto cleanup = [&]() {
-        (void)hipFree(rowcnt);
-        (void)hipFree(rowstart);
-        (void)hipFree(boxmap);
-        (void)hipFree(vox_tmp);
-        (void)hipFree(total_d);
-    };
-    if (hipMalloc(&rowcnt, rows * sizeof(int)) != hipSuccess ||
-        hipMalloc(&rowstart, rows * sizeof(int)) != hipSuccess ||
-        hipMalloc(&boxmap, boxvox * sizeof(int)) != hipSuccess || hipMalloc(&total_d, sizeof(int)) != hipSuccess) {
-        (void)hipGetLastError();
-        cleanup();
-        set_error("mpm_fv_setup: device allocation failed");
-        return MPM_ENOMEM;
-    }
+    int rc = reserve_scratch(ph, (size_t)rows, (size_t)boxvox, 0);
+    if (rc != MPM_OK) return rc;
+    int* total_d = ph.s_total;
     const int gr = (rows + kWaves - 1) / kWaves;
-    k_row_count<<<gr, kThreads, 0, st>>>(mask, g, rowcnt);
-    k_scan<<<1, 1024, 0, st>>>(rowcnt, rowstart, rows, total_d);
+    k_row_count<<<gr, kThreads, 0, st>>>(mask, g, ph.s_rowcnt);
+    k_scan<<<1, 1024, 0, st>>>(ph.s_rowcnt, ph.s_rowstart, rows, total_d);
     hipError_t e = hipMemcpyAsync(&total_h, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "mpm_fv_setup (count)");
-    }
+    if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (count)");
     if (total_h == 0) {
-        cleanup();
         set_error("mpm_fv_setup: the box holds no domain voxel");
         return MPM_EEMPTY;
     }
     const int N = total_h;
     const int Npad = (int)(((long long)N + 1 + kAlign - 1) / kAlign * kAlign);
-    rc = alloc_problem(ph, c->S, Npad);
-    if (rc != MPM_OK) {
-        cleanup();
-        return rc;
-    }
-    if (hipMalloc(&vox_tmp, (size_t)Npad * sizeof(int)) != hipSuccess) {
-        (void)hipGetLastError();
-        cleanup();
-        set_error("mpm_fv_setup: device allocation failed");
-        return MPM_ENOMEM;
-    }
-    k_compact<<<gr, kThreads, 0, st>>>(mask, g, rowstart, vox_tmp, boxmap);
-    k_neighbors<<<(Npad + 255) / 256, 256, 0, st>>>(vox_tmp, boxmap, g, N, Npad, ph.nbr, ph.vox);
+    rc = alloc_problem(ph, c->S, Npad, st);
+    if (rc != MPM_OK) return rc;
+    rc = reserve_scratch(ph, (size_t)rows, (size_t)boxvox, (size_t)Npad);
+    if (rc != MPM_OK) return rc;
+    int* vox_tmp = ph.s_vox;
+    k_compact<<<gr, kThreads, 0, st>>>(mask, g, ph.s_rowstart, vox_tmp, ph.s_boxmap);
+    k_neighbors<<<(Npad + 255) / 256, 256, 0, st>>>(vox_tmp, ph.s_boxmap, g, N, Npad, ph.nbr, ph.vox);
     // ph.vox receives -1 on padding from k_neighbors; copy the domain part
     e = hipMemcpyAsync(ph.vox, vox_tmp, (size_t)N * sizeof(int), hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "mpm_fv_setup (vox)");
-    }
+    if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (vox)");
     CoefArgs ca;
     ca.mask = mask; ca.D = D; ca.k = k; ca.src = src; ca.vox = vox_tmp;
     ca.d64 = ph.d64; ca.q64 = ph.q64; ca.a64 = ph.a64; ca.sc64 = ph.sc64;
@@ -401,10 +453,7 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     ca.N = N; ca.Npad = Npad; ca.S = c->S;
     ca.bad = total_d;   // reused as the error flag (the count was read already)
     e = hipMemsetAsync(total_d, 0, sizeof(int), st);
-    if (e != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "mpm_fv_setup (flag)");
-    }
+    if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (flag)");
     const long long tot = (long long)c->S * Npad;
     k_coefs<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ca);
     k_scaled<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ph.a64, ph.sc64, ph.nbr, N, Npad, c->S, ph.c64,
@@ -424,7 +473,6 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
                 hipMalloc(&ph.wsin, G * (4 * c->S + 1) * sizeof(uint16_t)) != hipSuccess ||
                 hipMalloc(&ph.wsout, G * c->S * sizeof(float)) != hipSuccess) {
                 (void)hipGetLastError();
-                cleanup();
                 set_error("mpm_fv_setup: device allocation of the warm-start buffers failed");
                 return MPM_ENOMEM;
             }
@@ -440,7 +488,6 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&bad_h, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    cleanup();
     if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (coefficients)");
     if (bad_h) {
         ph.ready = false;

@@ -22,8 +22,10 @@ from .geometry import (  # noqa: F401
     config3_tumour,
     config4_patch,
     config5,
+    cube,
     dilate6,
     fourier_box,
     random_problem,
+    species_constants,
     tumour_coefficients,
 )

@@ -136,6 +136,24 @@ LUNG_K_ALL = (0.0, 0.0, 0.005)
 LUNG_S_CELL = (0.0, 0.0, 0.01)
 LUNG_CB = (1.0, 1.0, 0.0)
 
+# Four-species variant: the paper's two interleukins as separate fields instead of one
+# cytokine field (oxygen, nutrient, IL-6, IL-8), each decaying everywhere and produced
+# on tumour voxels.  The values are synthetic: the paper gives none.
+LUNG4_D = (1.0, 0.6, 0.3, 0.25)
+LUNG4_K_CELL = (0.05, 0.02, 0.0, 0.0)
+LUNG4_K_ALL = (0.0, 0.0, 0.005, 0.004)
+LUNG4_S_CELL = (0.0, 0.0, 0.01, 0.008)
+LUNG4_CB = (1.0, 1.0, 0.0, 0.0)
+
+
+def species_constants(nspecies: int = 3):
+    """(D, k_cell, k_all, s_cell, c_b) of the 3-species or 4-species set."""
+    if nspecies == 3:
+        return LUNG_D, LUNG_K_CELL, LUNG_K_ALL, LUNG_S_CELL, LUNG_CB
+    if nspecies == 4:
+        return LUNG4_D, LUNG4_K_CELL, LUNG4_K_ALL, LUNG4_S_CELL, LUNG4_CB
+    raise ValueError("species sets exist for 3 and 4 species")
+
 
 def config1() -> Problem:
     """32^3 box, all voxels in the domain, one species (oxygen).
@@ -168,7 +186,7 @@ def _lung_lattice(dims: Vec3, centres, outer, thickness):
 
 
 def _lung_problem(name, dims, centres, outer, window_lo, window_hi, ncells, seed,
-                  steps, tol, thickness=6, dense=False):
+                  steps, tol, thickness=6, dense=False, species=3):
     rng = np.random.Generator(np.random.PCG64(seed))
     shell = _lung_lattice(dims, centres, outer, thickness)
     nx, ny, nz = dims
@@ -182,37 +200,65 @@ def _lung_problem(name, dims, centres, outer, window_lo, window_hi, ncells, seed
     cell = np.zeros(shell.shape, np.int32)
     cell[cand[:, 0], cand[:, 1], cand[:, 2]] = labels + 1
     tumour = cell > 0
-    D, k, s = _species_fields(dims, shell, tumour, rng, D=LUNG_D, k_cell=LUNG_K_CELL,
-                              k_all=LUNG_K_ALL, s_cell=LUNG_S_CELL)
-    c0 = np.broadcast_to(np.array(LUNG_CB)[:, None, None, None], D.shape).copy()
+    Dc, kc, ka, sc, cb = species_constants(species)
+    D, k, s = _species_fields(dims, shell, tumour, rng, D=Dc, k_cell=kc, k_all=ka, s_cell=sc)
+    c0 = np.broadcast_to(np.array(cb)[:, None, None, None], D.shape).copy()
     mask = np.ones_like(shell, dtype=np.uint8) if dense else shell.astype(np.uint8)
-    return Problem(name, dims, mask, cell, D, k, s, c0, np.array(LUNG_CB),
+    return Problem(name, dims, mask, cell, D, k, s, c0, np.array(cb),
                    steps=steps, tol=tol)
 
 
-def config2(seed: int = 20250503, dense: bool = False) -> Problem:
+def config2(seed: int = 20250503, dense: bool = False, species: int = 3) -> Problem:
     """256x256x160 lattice, pleural shell (6 voxels) of two ellipsoidal lungs.
 
     4000 tumour cells: Voronoi regions of seeds drawn without replacement from the
     shell voxels of the window x in [6,126), y in [64,184), z in [8,128).  The
     cell extent is the window, so with margin 4 the box is 128^3.  Three species,
     k on tumour voxels jittered by U(0.8, 1.2), 50 steps at dt = 1, tol 1e-8.
+    ``species=4`` splits the cytokine into IL-6 and IL-8.
     """
-    return _lung_problem("config2-dense" if dense else "config2", (256, 256, 160),
+    name = ("config2-dense" if dense else "config2") + ("-s4" if species == 4 else "")
+    return _lung_problem(name, (256, 256, 160),
                          [(66, 128, 80), (190, 128, 80)], (60, 120, 76),
-                         (6, 64, 8), (126, 184, 128), 4000, seed, 50, 1e-8, dense=dense)
+                         (6, 64, 8), (126, 184, 128), 4000, seed, 50, 1e-8, dense=dense,
+                         species=species)
 
 
-def config2_dense(seed: int = 20250503) -> Problem:
+def config2_dense(seed: int = 20250503, species: int = 3) -> Problem:
     """config2 with every lattice voxel in the domain (same cells and coefficients)."""
-    return config2(seed, dense=True)
+    return config2(seed, dense=True, species=species)
 
 
-def config5(seed: int = 20250503) -> Problem:
+def config5(seed: int = 20250503, species: int = 3) -> Problem:
     """512x512x320 lattice, two lungs, 60000 cells; box 384x384x256 (margin 4)."""
-    return _lung_problem("config5", (512, 512, 320), [(132, 256, 160), (380, 256, 160)],
+    return _lung_problem("config5" + ("-s4" if species == 4 else ""), (512, 512, 320),
+                         [(132, 256, 160), (380, 256, 160)],
                          (120, 240, 152), (12, 68, 8), (388, 444, 256), 60000, seed,
-                         100, 1e-8)
+                         100, 1e-8, species=species)
+
+
+def cube(n: int, species: int = 3, seed: int = 2505) -> Problem:
+    """Dense n^3 box, every voxel in the domain: the mesh-size sweep (n = 100, 150, 200).
+
+    The box is the whole lattice.  The tumour is the ellipsoid with semi-axes
+    (0.30 n, 0.25 n, 0.20 n) centred in the box, split into Voronoi cells of about 50
+    voxels; D is halved and k applies (jittered) on tumour voxels, as in the growing
+    tumour workload.  50 steps at dt = 1, tol 1e-8.
+    """
+    dims = (n, n, n)
+    rng = np.random.Generator(np.random.PCG64(seed + n))
+    tumour = _inside_ellipsoid(dims, (n / 2, n / 2, n / 2), (0.30 * n, 0.25 * n, 0.20 * n))
+    pts = np.argwhere(tumour)
+    nseed = max(1, len(pts) // 50)
+    seeds = pts[np.sort(rng.choice(len(pts), size=nseed, replace=False))]
+    labels = voronoi_labels(pts, seeds)
+    mask = np.ones((n, n, n), np.uint8)
+    prob = _tumour_problem(f"cube{n}" + ("-s4" if species == 4 else ""), dims, mask, tumour, rng,
+                           species=species)
+    prob.cell_id[pts[:, 0], pts[:, 1], pts[:, 2]] = labels + 1
+    prob.box = ((0, 0, 0), dims)
+    prob.steps = 50
+    return prob
 
 
 def config3_tumour(t: int) -> Tuple[Problem, np.ndarray]:
@@ -236,13 +282,13 @@ def config3_tumour(t: int) -> Tuple[Problem, np.ndarray]:
     return prob, tumour
 
 
-def _tumour_problem(name, dims, mask, tumour, rng, coef_scale=None, jitter=0.2):
-    D, k, s = _species_fields(dims, mask, tumour, rng, D=LUNG_D, k_cell=LUNG_K_CELL,
-                              k_all=LUNG_K_ALL, s_cell=LUNG_S_CELL, D_tumour_factor=0.5,
-                              jitter=jitter, coef_scale=coef_scale)
-    c0 = np.broadcast_to(np.array(LUNG_CB)[:, None, None, None], D.shape).copy()
+def _tumour_problem(name, dims, mask, tumour, rng, coef_scale=None, jitter=0.2, species=3):
+    Dc, kc, ka, sc, cb = species_constants(species)
+    D, k, s = _species_fields(dims, mask, tumour, rng, D=Dc, k_cell=kc, k_all=ka, s_cell=sc,
+                              D_tumour_factor=0.5, jitter=jitter, coef_scale=coef_scale)
+    c0 = np.broadcast_to(np.array(cb)[:, None, None, None], D.shape).copy()
     return Problem(name, dims, mask, tumour.astype(np.int32), D, k, s, c0,
-                   np.array(LUNG_CB), steps=1, tol=1e-8)
+                   np.array(cb), steps=1, tol=1e-8)
 
 
 def config4_patch(seed: int, n: int = 64) -> Problem:
@@ -342,3 +388,66 @@ def tumour_coefficients(tumour: np.ndarray, jitter: np.ndarray):
         k[sp] = np.where(tumour, (LUNG_K_CELL[sp] + LUNG_K_ALL[sp]) * jitter[sp], LUNG_K_ALL[sp])
         s[sp] = np.where(tumour, LUNG_S_CELL[sp], 0.0)
     return D, k, s
+
+
+@dataclasses.dataclass
+class Growth:
+    """Changes of one growth step: voxels taken by tumour cells and their new values."""
+
+    index: np.ndarray     # int64 [n] flat lattice indices (C order)
+    cell: np.ndarray      # int32 [n] new cell_id
+    k: np.ndarray         # float64 [S][n] new k
+    src: np.ndarray       # float64 [S][n] new production rate
+
+
+def grow_cells(prob: Problem, steps: int, frac: float = 0.01, seed: int = 7) -> list:
+    """Cell growth of the lung workloads, one list entry per step.
+
+    Each step a seeded ``frac`` of the cells (drawn without replacement) each take one
+    domain voxel that is 6-adjacent to the cell and not yet tumour, chosen uniformly
+    among the candidates of that cell (a cell without candidates does not grow; two
+    cells that pick the same voxel: the lower index wins).  The taken voxel gets the
+    cell's species coefficients: k_cell + k_all jittered by U(0.8, 1.2) per species,
+    and the production s_cell.  ``prob`` is not modified.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    _, kc, ka, sc, _ = species_constants(prob.nspecies)
+    nz, ny, nx = prob.cell_id.shape
+    cell = prob.cell_id.reshape(-1).copy()
+    dom = prob.mask.reshape(-1) != 0
+    ncell = int(cell.max())
+    # voxels of each cell, kept as growing lists
+    order = np.argsort(cell, kind="stable")
+    first = np.searchsorted(cell[order], np.arange(1, ncell + 2))
+    members = [list(order[first[i]:first[i + 1]]) for i in range(ncell)]
+    out = []
+    for _ in range(steps):
+        pick = np.sort(rng.choice(ncell, size=max(1, int(round(frac * ncell))), replace=False))
+        taken = {}
+        for c in pick:
+            v = np.asarray(members[c], np.int64)
+            x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+            cand = []
+            for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                xx, yy, zz = x + dx, y + dy, z + dz
+                ok = (xx >= 0) & (xx < nx) & (yy >= 0) & (yy < ny) & (zz >= 0) & (zz < nz)
+                cand.append(((zz * ny + yy) * nx + xx)[ok])
+            cand = np.unique(np.concatenate(cand))
+            cand = cand[dom[cand] & (cell[cand] == 0)]
+            cand = [u for u in cand.tolist() if u not in taken]
+            if not cand:
+                continue
+            taken[cand[int(rng.integers(len(cand)))]] = int(c) + 1
+        idx = np.fromiter(taken.keys(), np.int64, len(taken))
+        ids = np.fromiter(taken.values(), np.int32, len(taken))
+        for u, c in zip(idx.tolist(), ids.tolist()):
+            cell[u] = c
+            members[c - 1].append(u)
+        S = prob.nspecies
+        k = np.empty((S, len(idx)))
+        s = np.empty((S, len(idx)))
+        for sp in range(S):
+            k[sp] = (kc[sp] + ka[sp]) * rng.uniform(0.8, 1.2, size=len(idx))
+            s[sp] = sc[sp]
+        out.append(Growth(idx, ids, k, s))
+    return out

@@ -63,3 +63,29 @@ def test_growing_tumours_track_box(precision):
         for sp in range(3):
             err = np.linalg.norm(got[sp] - want[sp]) / np.linalg.norm(want[sp])
             assert err <= 1e-8, (p, sp, err)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_box_shrinks_and_grows_again(precision):
+    """One problem re-set up on boxes of changing size: the setup buffers and the Krylov
+    workspace are reused when the new box fits (what lies past the new layout is cleared)
+    and reallocated when it does not; every step matches the oracle on the same box."""
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    from synth import random_problem
+    p = random_problem(61, (40, 36, 30), S=3, fill=0.7)
+    boxes = [((0, 0, 0), (40, 36, 30)), ((5, 4, 3), (21, 19, 14)), ((2, 2, 2), (30, 30, 25)),
+             ((3, 1, 0), (32, 34, 29)), ((0, 0, 0), (40, 36, 30))]
+    d = {k: torch.from_numpy(np.ascontiguousarray(getattr(p, k))).cuda() for k in ("mask", "D", "k", "src")}
+    f_d = torch.from_numpy(p.c0).cuda()
+    f_h = p.c0.copy()
+    with m.Solver(3, 1, precision=precision) as s:
+        for box in boxes:
+            s.setup(0, box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+            s.step([f_d], 1e-12)
+            f_h, _ = implicit_step(f_h, p.mask, p.D, p.k, p.src, p.c_b, box, p.dt, p.h,
+                                   solver="pcg", tol=1e-13)
+            got = f_d.cpu().numpy()
+            for sp in range(3):
+                err = np.linalg.norm(got[sp] - f_h[sp]) / np.linalg.norm(f_h[sp])
+                assert err <= 1e-8, (box, sp, err)

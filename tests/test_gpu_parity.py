@@ -13,7 +13,7 @@ from gpu_helpers import gpu_run, rel_err_per_species, require_gpu, to_dev
 from oracle.bbox import bbox_from_cells
 from oracle.fv import assemble, box_slice
 from oracle.step import problem_box, run
-from synth import config1, random_problem
+from synth import config1, cube, random_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -193,6 +193,15 @@ def test_caller_stream_ordering(use_graph):
     ref1, _ = gpu_run(p, 1, 1e-10, **tile)
     assert np.array_equal(mid.cpu().numpy(), ref1)
     assert np.array_equal(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(batched=0), dict(precision=0)])
+def test_four_species(opts):
+    """Four uncoupled species (the interleukins as separate fields): a random masked
+    problem and the dense tumour cube of the size sweep."""
+    require_gpu()
+    _check_parity(random_problem(34, (26, 23, 21), S=4, fill=0.6), 2, **opts)
+    _check_parity(cube(24, species=4), 2, **opts)
 
 
 def test_edge_cases_tiny_boxes():
