@@ -105,7 +105,10 @@ typedef struct {
  * dims: host (nx, ny, nz).  On return lo/hi (host, 3 each) hold the half-open box
  * lo_d = max(min_d - margin, 0), hi_d = min(max_d + margin + 1, n_d).
  * Synchronises 'stream'.  MPM_EEMPTY if no voxel is positive; MPM_EINVAL for
- * non-positive dims, negative margin or a null pointer. */
+ * non-positive dims, negative margin or a null pointer.  The first call on a device
+ * allocates 24.6 KB of device memory (per-block partial extremes) and 32 bytes of
+ * pinned host memory, kept until the process ends; calls from several threads are
+ * serialised. */
 int32_t mpm_bbox_from_cells(const int32_t* cell_id, const int32_t* dims, int32_t margin,
                             int32_t* lo, int32_t* hi, void* stream);
 

@@ -37,6 +37,7 @@ static void destroy_ctx(Ctx* c) {
     (void)hipFree(c->b);
     if (c->h_fields) (void)hipHostFree(c->h_fields);
     if (c->h_prm) (void)hipHostFree(c->h_prm);
+    if (c->h_small) (void)hipHostFree(c->h_small);
     if (c->h_sk) (void)hipHostFree(c->h_sk);
     (void)hipFree(c->d_scales);
     (void)hipFree(c->prev);
@@ -133,6 +134,7 @@ extern "C" int32_t mpm_create(mpm_ctx* out, int32_t nspecies, int32_t nproblems,
     if (e == hipSuccess) e = hipMalloc(&c->d_fields, nproblems * sizeof(double*));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_fields, nproblems * sizeof(double*), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_prm, sizeof(Params), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_small, 4 * sizeof(int), hipHostMallocDefault);
     // coherent: the status heads are written there by kernels and read by the host
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&c->h_sk, nsys * sizeof(SysK), hipHostMallocMapped | hipHostMallocCoherent);

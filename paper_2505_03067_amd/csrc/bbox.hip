@@ -1,9 +1,14 @@
 // Bounding box of all tumour cells plus a margin (paper Sec. 2.3).
 //
 // One streaming pass over the int32 cell-id lattice.  Each thread keeps the
-// extremes of the voxels it visits, a wave64 reduces them with cross-lane
-// shuffles, and one integer atomic per wave and bound folds them into six device
-// words.  Integer min/max is order independent, so the result is exact.
+// extremes of the voxels it visits; each block reduces them (cross-lane shuffles,
+// then LDS) to one partial, and a second one-block kernel folds the partials.  No
+// atomics: thousands of waves updating the same six words would serialise on one
+// cache line.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "common.h"
 
 namespace mpm {
@@ -17,15 +22,44 @@ __device__ inline int wave_max(int v) {
     return v;
 }
 
-// ext[0..2] = min x, y, z (init INT_MAX); ext[3..5] = max x, y, z (init -1).
-__global__ __launch_bounds__(256) void k_bbox_init(int* ext) {
-    if (threadIdx.x < 3) ext[threadIdx.x] = 0x7fffffff;
-    else if (threadIdx.x < 6) ext[threadIdx.x] = -1;
+constexpr int kBboxBlocks = 1024;   // blocks of the streaming pass (one partial each)
+
+// Extremes of one block: wave reduction, then the block's waves through LDS.  Thread
+// 0 returns them in mn/mx.
+__device__ inline void block_extremes(int (&mn)[3], int (&mx)[3]) {
+    __shared__ int sh[4][6];
+    const int wave = threadIdx.x >> 6;
+    for (int d = 0; d < 3; ++d) {
+        mn[d] = wave_min(mn[d]);
+        mx[d] = wave_max(mx[d]);
+    }
+    if ((threadIdx.x & 63) == 0)
+        for (int d = 0; d < 3; ++d) {
+            sh[wave][d] = mn[d];
+            sh[wave][3 + d] = mx[d];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            for (int d = 0; d < 3; ++d) {
+                mn[d] = min(mn[d], sh[w][d]);
+                mx[d] = max(mx[d], sh[w][3 + d]);
+            }
 }
 
-// Vector path: nx % 4 == 0, so the four voxels of an int4 share one row.
+__device__ inline void store_partial(int* part, const int (&mn)[3], const int (&mx)[3]) {
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) {
+            part[blockIdx.x * 6 + d] = mn[d];
+            part[blockIdx.x * 6 + 3 + d] = mx[d];
+        }
+}
+
+// Vector path: nx % 4 == 0, so the four voxels of an int4 share one row.  Writes the
+// block's extremes to part[block][0..5] (min x, y, z; max x, y, z; INT_MAX / -1 if the
+// block saw no cell voxel).
 __global__ __launch_bounds__(256) void k_bbox_vec4(const int4* __restrict__ cell, long long nquad,
-                                                   int nx, int ny, int* ext) {
+                                                   int nx, int ny, int* __restrict__ part) {
     int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
     int mx[3] = {-1, -1, -1};
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -48,21 +82,13 @@ __global__ __launch_bounds__(256) void k_bbox_vec4(const int4* __restrict__ cell
             mx[2] = max(mx[2], z);
         }
     }
-    for (int d = 0; d < 3; ++d) {
-        int a = wave_min(mn[d]);
-        int b = wave_max(mx[d]);
-        if ((threadIdx.x & 63) == 0) {
-            if (b >= 0) {
-                atomicMin(ext + d, a);
-                atomicMax(ext + 3 + d, b);
-            }
-        }
-    }
+    block_extremes(mn, mx);
+    store_partial(part, mn, mx);
 }
 
-// Scalar path for any nx.
+// Scalar path for any nx (same output).
 __global__ __launch_bounds__(256) void k_bbox_scalar(const int* __restrict__ cell, long long n,
-                                                     int nx, int ny, int* ext) {
+                                                     int nx, int ny, int* __restrict__ part) {
     int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
     int mx[3] = {-1, -1, -1};
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -77,14 +103,27 @@ __global__ __launch_bounds__(256) void k_bbox_scalar(const int* __restrict__ cel
             mn[2] = min(mn[2], z); mx[2] = max(mx[2], z);
         }
     }
-    for (int d = 0; d < 3; ++d) {
-        int a = wave_min(mn[d]);
-        int b = wave_max(mx[d]);
-        if ((threadIdx.x & 63) == 0 && b >= 0) {
-            atomicMin(ext + d, a);
-            atomicMax(ext + 3 + d, b);
+    block_extremes(mn, mx);
+    store_partial(part, mn, mx);
+}
+
+// One block folds the per-block partials into ext[0..5].  Integer min/max does not
+// depend on the order, so the result is exact.
+__global__ __launch_bounds__(256) void k_bbox_final(const int* __restrict__ part, int nparts,
+                                                    int* __restrict__ ext) {
+    int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
+    int mx[3] = {-1, -1, -1};
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = min(mn[d], part[b * 6 + d]);
+            mx[d] = max(mx[d], part[b * 6 + 3 + d]);
         }
-    }
+    block_extremes(mn, mx);
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) {
+            ext[d] = mn[d];
+            ext[3 + d] = mx[d];
+        }
 }
 
 }  // namespace mpm
@@ -103,21 +142,36 @@ extern "C" int32_t mpm_bbox_from_cells(const int32_t* cell_id, const int32_t* di
     }
     hipStream_t st = (hipStream_t)stream;
     const long long n = (long long)dims[0] * dims[1] * dims[2];
-    int* ext = nullptr;
-    int* host = nullptr;
-    MPM_HIP(hipMalloc(&ext, 8 * sizeof(int)));
-    hipError_t e = hipHostMalloc((void**)&host, 8 * sizeof(int), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        (void)hipFree(ext);
-        return hip_fail(e, "hipHostMalloc");
+    // six device words and their pinned host copy, allocated once per device and kept
+    // until the process ends (a box recomputed every step then allocates nothing);
+    // calls from several threads take turns
+    static std::mutex mu;
+    static std::map<int, std::pair<int*, int*>> bufs;
+    std::lock_guard<std::mutex> lock(mu);
+    int dev = 0;
+    MPM_HIP(hipGetDevice(&dev));
+    auto it = bufs.find(dev);
+    if (it == bufs.end()) {
+        int* ext = nullptr;
+        int* host = nullptr;
+        MPM_HIP(hipMalloc(&ext, (8 + 6 * kBboxBlocks) * sizeof(int)));
+        hipError_t e = hipHostMalloc((void**)&host, 8 * sizeof(int), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipFree(ext);
+            return hip_fail(e, "hipHostMalloc");
+        }
+        it = bufs.emplace(dev, std::make_pair(ext, host)).first;
     }
-    k_bbox_init<<<1, 64, 0, st>>>(ext);
-    const int grid = 2048;
+    int* ext = it->second.first;
+    int* host = it->second.second;
+    hipError_t e = hipSuccess;
+    int* part = ext + 8;
     if (dims[0] % 4 == 0 && ((uintptr_t)cell_id % 16) == 0) {
-        k_bbox_vec4<<<grid, 256, 0, st>>>((const int4*)cell_id, n / 4, dims[0], dims[1], ext);
+        k_bbox_vec4<<<kBboxBlocks, 256, 0, st>>>((const int4*)cell_id, n / 4, dims[0], dims[1], part);
     } else {
-        k_bbox_scalar<<<grid, 256, 0, st>>>(cell_id, n, dims[0], dims[1], ext);
+        k_bbox_scalar<<<kBboxBlocks, 256, 0, st>>>(cell_id, n, dims[0], dims[1], part);
     }
+    k_bbox_final<<<1, 256, 0, st>>>(part, kBboxBlocks, ext);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(host, ext, 6 * sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -135,7 +189,5 @@ extern "C" int32_t mpm_bbox_from_cells(const int32_t* cell_id, const int32_t* di
             hi[d] = b > dims[d] ? dims[d] : b;
         }
     }
-    (void)hipFree(ext);
-    (void)hipHostFree(host);
     return r;
 }

@@ -31,6 +31,7 @@ struct ProbHost {
     float* c32 = nullptr;
     double* c64 = nullptr;
     size_t cap_pad = 0;        // padded unknowns per species the buffers hold (>= Npad)
+    size_t hw_pad = 0;         // largest Npad written since the parts past it were zero
     // scratch of mpm_fv_setup, kept between calls (a box that changes every step
     // reuses it): per-row counts and starts, box-to-domain map, compacted voxels, total
     int* s_rowcnt = nullptr;
@@ -92,6 +93,7 @@ struct Ctx {
     // pinned host mirrors (up_valid: the device holds what they hold)
     double** h_fields = nullptr;
     Params* h_prm = nullptr;
+    int* h_small = nullptr;            // pinned words read back by mpm_fv_setup
     bool up_valid = false;
     SysK* h_sk = nullptr;
     SysK* hsk_dev = nullptr;           // device address of h_sk (k_res_final writes the heads)

@@ -345,6 +345,7 @@ void free_problem(ProbHost& ph) {
     free_padded(ph.c32);
     free_padded(ph.c64);
     ph.cap_pad = 0;
+    ph.hw_pad = 0;
     (void)hipFree(ph.stat);
     (void)hipFree(ph.wsin);
     (void)hipFree(ph.wsout);
@@ -361,23 +362,26 @@ static hipError_t zero_tail(T* p, size_t from, size_t to, hipStream_t st) {
 }
 
 // Coefficient arrays for Npad padded unknowns per species.  They are sized with room
-// for growth (a box that grows step by step keeps them); when reused, everything past
-// the part the new layout writes is zeroed, so reads past the data see zero couplings
-// exactly as in a fresh allocation.
+// for growth (a box that grows step by step keeps them).  A layout writes exactly the
+// first Npad (per-voxel arrays), S Npad or 3 S Npad elements; when a reused array had
+// held a larger layout, the part past the new one is zeroed, so reads past the data see
+// zero couplings exactly as in a fresh allocation.
 static int alloc_problem(ProbHost& ph, int S, int Npad, hipStream_t st) {
     const size_t n = (size_t)Npad, u = (size_t)S * Npad;
     if (n <= ph.cap_pad) {
-        // ends of the allocations (each carries kAlign elements past its capacity)
-        const size_t cn = ph.cap_pad + kAlign, cu = (size_t)S * ph.cap_pad + kAlign;
-        const size_t cu3 = 3 * (size_t)S * ph.cap_pad + kAlign;
-        hipError_t e = zero_tail(ph.vox, n, cn, st);
-        if (e == hipSuccess) e = zero_tail(ph.nbr, n, cn, st);
-        if (e == hipSuccess) e = zero_tail(ph.d64, u, cu, st);
-        if (e == hipSuccess) e = zero_tail(ph.q64, u, cu, st);
-        if (e == hipSuccess) e = zero_tail(ph.sc64, u, cu, st);
-        if (e == hipSuccess) e = zero_tail(ph.a64, 3 * u, cu3, st);
-        if (e == hipSuccess) e = zero_tail(ph.c32, 3 * u, cu3, st);
-        if (e == hipSuccess) e = zero_tail(ph.c64, 3 * u, cu3, st);
+        hipError_t e = hipSuccess;
+        if (n < ph.hw_pad) {
+            const size_t hn = ph.hw_pad, hu = (size_t)S * ph.hw_pad;
+            e = zero_tail(ph.vox, n, hn, st);
+            if (e == hipSuccess) e = zero_tail(ph.nbr, n, hn, st);
+            if (e == hipSuccess) e = zero_tail(ph.d64, u, hu, st);
+            if (e == hipSuccess) e = zero_tail(ph.q64, u, hu, st);
+            if (e == hipSuccess) e = zero_tail(ph.sc64, u, hu, st);
+            if (e == hipSuccess) e = zero_tail(ph.a64, 3 * u, 3 * hu, st);
+            if (e == hipSuccess) e = zero_tail(ph.c32, 3 * u, 3 * hu, st);
+            if (e == hipSuccess) e = zero_tail(ph.c64, 3 * u, 3 * hu, st);
+        }
+        ph.hw_pad = n;
         return e == hipSuccess ? MPM_OK : hip_fail(e, "mpm_fv_setup (reuse)");
     }
     // keep the setup scratch, drop the rest
@@ -390,6 +394,7 @@ static int alloc_problem(ProbHost& ph, int S, int Npad, hipStream_t st) {
     free_padded(ph.c32);
     free_padded(ph.c64);
     ph.cap_pad = 0;
+    ph.hw_pad = 0;
     const size_t cn = (n + n / 8 + kAlign - 1) / kAlign * kAlign, cu = (size_t)S * cn;
     if (alloc_padded(&ph.vox, cn) != hipSuccess || alloc_padded(&ph.nbr, cn) != hipSuccess ||
         alloc_padded(&ph.d64, cu) != hipSuccess || alloc_padded(&ph.q64, cu) != hipSuccess ||
@@ -401,6 +406,7 @@ static int alloc_problem(ProbHost& ph, int S, int Npad, hipStream_t st) {
         return MPM_ENOMEM;
     }
     ph.cap_pad = cn;
+    ph.hw_pad = n;
     return MPM_OK;
 }
 
@@ -416,16 +422,16 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     const int rows = g.by * g.bz;
     const long long boxvox = (long long)rows * g.bx;
 
-    int total_h = 0;
     int rc = reserve_scratch(ph, (size_t)rows, (size_t)boxvox, 0);
     if (rc != MPM_OK) return rc;
     int* total_d = ph.s_total;
     const int gr = (rows + kWaves - 1) / kWaves;
     k_row_count<<<gr, kThreads, 0, st>>>(mask, g, ph.s_rowcnt);
     k_scan<<<1, 1024, 0, st>>>(ph.s_rowcnt, ph.s_rowstart, rows, total_d);
-    hipError_t e = hipMemcpyAsync(&total_h, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipError_t e = hipMemcpyAsync(c->h_small, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (count)");
+    const int total_h = c->h_small[0];
     if (total_h == 0) {
         set_error("mpm_fv_setup: the box holds no domain voxel");
         return MPM_EEMPTY;
@@ -484,12 +490,11 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
         k_ws_static<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(mask, D, k, src, g, gx, gy, gz, c->S, ca.nvox,
                                                               ph.stat);
     }
-    int bad_h = 0;
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(&bad_h, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->h_small + 1, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (coefficients)");
-    if (bad_h) {
+    if (c->h_small[1]) {
         ph.ready = false;
         c->layout_dirty = true;
         set_error("mpm_fv_setup: negative or non-finite D, k or s on a domain voxel");
