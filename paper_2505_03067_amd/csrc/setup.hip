@@ -32,7 +32,7 @@ struct BoxGeo {
     int bx, by, bz;      // box size
 };
 
-__global__ __launch_bounds__(256) void k_row_count(const uint8_t* __restrict__ mask, BoxGeo g,
+__global__ __launch_bounds__(kThreads) void k_row_count(const uint8_t* __restrict__ mask, BoxGeo g,
                                                    int* __restrict__ rowcnt) {
     const int r = blockIdx.x * kWaves + threadIdx.x / 64;
     const int lane = threadIdx.x & 63;
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int*
     if (t == 1023) *total = sh[1023];
 }
 
-__global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ mask, BoxGeo g,
+__global__ __launch_bounds__(kThreads) void k_compact(const uint8_t* __restrict__ mask, BoxGeo g,
                                                  const int* __restrict__ rowstart, int* __restrict__ vox,
                                                  int* __restrict__ boxmap) {
     const int r = blockIdx.x * kWaves + threadIdx.x / 64;
@@ -428,7 +428,8 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     const int gr = (rows + kWaves - 1) / kWaves;
     k_row_count<<<gr, kThreads, 0, st>>>(mask, g, ph.s_rowcnt);
     k_scan<<<1, 1024, 0, st>>>(ph.s_rowcnt, ph.s_rowstart, rows, total_d);
-    hipError_t e = hipMemcpyAsync(c->h_small, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(c->h_small, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (count)");
     const int total_h = c->h_small[0];
@@ -445,6 +446,8 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     int* vox_tmp = ph.s_vox;
     k_compact<<<gr, kThreads, 0, st>>>(mask, g, ph.s_rowstart, vox_tmp, ph.s_boxmap);
     k_neighbors<<<(Npad + 255) / 256, 256, 0, st>>>(vox_tmp, ph.s_boxmap, g, N, Npad, ph.nbr, ph.vox);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (compaction)");
     // ph.vox receives -1 on padding from k_neighbors; copy the domain part
     e = hipMemcpyAsync(ph.vox, vox_tmp, (size_t)N * sizeof(int), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (vox)");
