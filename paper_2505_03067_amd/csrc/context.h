@@ -39,6 +39,7 @@ struct ProbHost {
     int* s_boxmap = nullptr;
     int* s_vox = nullptr;
     int* s_total = nullptr;
+    int* s_chunk = nullptr;            // per-chunk row totals of the scan
     size_t cap_rows = 0, cap_boxvox = 0, cap_svox = 0;
     // warm start: static network input channels on the box grid (k, D, s, mask)
     int gd[3] = {0, 0, 0};

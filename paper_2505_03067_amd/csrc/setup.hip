@@ -46,29 +46,62 @@ __global__ __launch_bounds__(kThreads) void k_row_count(const uint8_t* __restric
     if (lane == 0) rowcnt[r] = c;
 }
 
-// Exclusive scan of 'n' counts by one block of 1024 threads; total written to *total.
-__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int* __restrict__ start,
-                                               int n, int* total) {
-    __shared__ int sh[1024];
-    const int t = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int a = min(n, t * per), e = min(n, a + per);
-    int s = 0;
-    for (int i = a; i < e; ++i) s += cnt[i];
-    sh[t] = s;
+// Exclusive scan of the n per-row counts in two launches: k_scan_sums totals each chunk
+// of kScanChunk rows (one block per chunk), k_scan_apply gives each chunk its offset
+// (the sum of the totals before it, summed by the block itself) and scans within the
+// chunk.  The grand total goes to *total.  Integer sums: exact in any order.
+constexpr int kScanChunk = 4096;                  // rows per block
+constexpr int kScanPer = kScanChunk / 256;        // consecutive rows per thread
+
+__device__ inline int block_sum_256(int v, int* sh) {
+    v = wsum_int(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {     // Hillis-Steele inclusive scan
-        int v = t >= o ? sh[t - o] : 0;
+    const int t = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(const int* __restrict__ cnt, int n, int* __restrict__ sums) {
+    __shared__ int sh[4];
+    const int r0 = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+    int v = 0;
+    for (int i = 0; i < kScanPer; ++i)
+        if (r0 + i < n) v += cnt[r0 + i];
+    const int t = block_sum_256(v, sh);
+    if (threadIdx.x == 0) sums[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const int* __restrict__ cnt, int n, const int* __restrict__ sums,
+                                                    int* __restrict__ start, int* __restrict__ total) {
+    __shared__ int sh[4];
+    __shared__ int pre[256];
+    // offset of this chunk
+    int o = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) o += sums[b];
+    const int off = block_sum_256(o, sh);
+    // per-thread totals of kScanPer consecutive rows, scanned across the block
+    const int r0 = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+    int c[kScanPer];
+    int v = 0;
+    for (int i = 0; i < kScanPer; ++i) {
+        c[i] = r0 + i < n ? cnt[r0 + i] : 0;
+        v += c[i];
+    }
+    pre[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {          // Hillis-Steele inclusive scan
+        const int w = threadIdx.x >= d ? pre[threadIdx.x - d] : 0;
         __syncthreads();
-        sh[t] += v;
+        pre[threadIdx.x] += w;
         __syncthreads();
     }
-    int run = sh[t] - s;
-    for (int i = a; i < e; ++i) {
-        start[i] = run;
-        run += cnt[i];
+    int run = off + pre[threadIdx.x] - v;
+    for (int i = 0; i < kScanPer; ++i) {
+        if (r0 + i < n) start[r0 + i] = run;
+        run += c[i];
     }
-    if (t == 1023) *total = sh[1023];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) *total = off + pre[255];
 }
 
 __global__ __launch_bounds__(kThreads) void k_compact(const uint8_t* __restrict__ mask, BoxGeo g,
@@ -304,7 +337,8 @@ static void free_scratch(ProbHost& ph) {
     (void)hipFree(ph.s_boxmap);
     (void)hipFree(ph.s_vox);
     (void)hipFree(ph.s_total);
-    ph.s_rowcnt = ph.s_rowstart = ph.s_boxmap = ph.s_vox = ph.s_total = nullptr;
+    (void)hipFree(ph.s_chunk);
+    ph.s_rowcnt = ph.s_rowstart = ph.s_boxmap = ph.s_vox = ph.s_total = ph.s_chunk = nullptr;
     ph.cap_rows = ph.cap_boxvox = ph.cap_svox = 0;
 }
 
@@ -315,11 +349,13 @@ static int reserve_scratch(ProbHost& ph, size_t rows, size_t boxvox, size_t npad
     if (rows > ph.cap_rows) {
         (void)hipFree(ph.s_rowcnt);
         (void)hipFree(ph.s_rowstart);
-        ph.s_rowcnt = ph.s_rowstart = nullptr;
+        (void)hipFree(ph.s_chunk);
+        ph.s_rowcnt = ph.s_rowstart = ph.s_chunk = nullptr;
         ph.cap_rows = 0;
         const size_t want = rows + rows / 8 + 1024;
         e = hipMalloc(&ph.s_rowcnt, want * sizeof(int));
         if (e == hipSuccess) e = hipMalloc(&ph.s_rowstart, want * sizeof(int));
+        if (e == hipSuccess) e = hipMalloc(&ph.s_chunk, (want / kScanChunk + 2) * sizeof(int));
         if (e == hipSuccess) ph.cap_rows = want;
     }
     if (e == hipSuccess) e = reserve(&ph.s_boxmap, &ph.cap_boxvox, boxvox);
@@ -427,7 +463,9 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     int* total_d = ph.s_total;
     const int gr = (rows + kWaves - 1) / kWaves;
     k_row_count<<<gr, kThreads, 0, st>>>(mask, g, ph.s_rowcnt);
-    k_scan<<<1, 1024, 0, st>>>(ph.s_rowcnt, ph.s_rowstart, rows, total_d);
+    const int nchunk = (rows + kScanChunk - 1) / kScanChunk;
+    k_scan_sums<<<nchunk, 256, 0, st>>>(ph.s_rowcnt, rows, ph.s_chunk);
+    k_scan_apply<<<nchunk, 256, 0, st>>>(ph.s_rowcnt, rows, ph.s_chunk, ph.s_rowstart, total_d);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_small, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -204,6 +204,14 @@ def test_four_species(opts):
     _check_parity(cube(24, species=4), 2, **opts)
 
 
+def test_many_rows_and_ragged_rows():
+    """Boxes of narrow rows: 8,900 and 13,068 rows (the set-up scan runs over several
+    chunks of 4096 rows), rows of 3 and of 5 voxels."""
+    require_gpu()
+    _check_parity(random_problem(35, (3, 89, 100), S=2, fill=0.6), 2)
+    _check_parity(random_problem(36, (5, 132, 99), S=1, fill=0.5), 2)
+
+
 def test_edge_cases_tiny_boxes():
     require_gpu()
     # single-voxel box; 1-voxel-thick slab; box exactly filling 1024 domain voxels
