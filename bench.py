@@ -427,6 +427,28 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * nbytes / (time.perf_counter() - t2) / 1e9
     del ca, cb
+    # rows a1 and a2 on this workload's lattice and box: bounding box and set-up, each
+    # call waits for its result; best of 3
+    lat_bytes = t["cell_id"].numel() * 4
+    tb = []
+    for _ in range(3):
+        t3 = time.perf_counter()
+        m.mpm_bbox_from_cells(t["cell_id"], prob.margin)
+        tb.append(time.perf_counter() - t3)
+    s4 = gpu_solver(m, prob, t, box, precision, False, True, 1024)
+    ts = []
+    for _ in range(3):
+        t3 = time.perf_counter()
+        s4.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
+        ts.append(time.perf_counter() - t3)
+    s4.close()
+    out["bbox_and_setup"] = {
+        "bbox_us": round(1e6 * min(tb), 1),
+        "bbox_lattice_bytes": lat_bytes,
+        "bbox_gbs_incl_host_wait": round(lat_bytes / min(tb) / 1e9, 1),
+        "setup_ms": round(1e3 * min(ts), 3),
+        "note": "host wall time of mpm_bbox_from_cells / mpm_fv_setup (both wait for their result)",
+    }
     if timing and timing["launches"]:
         avg_ms = timing["ms"] / timing["launches"]
         achieved = timing["bytes"] / (timing["ms"] * 1e-3) / 1e9

@@ -52,6 +52,24 @@ def test_bbox_bit_exact(dims, frac, margin):
     assert got == bbox_from_cells(cell, margin)
 
 
+@pytest.mark.parametrize("dims", [(256, 256, 160), (255, 131, 97)])
+def test_bbox_bit_exact_large(dims):
+    """Lattices with far more voxels than the pass has threads (every block folds many
+    quads; most blocks see no cell), on the vector path and the scalar path (nx odd)."""
+    torch = require_gpu()
+    from paper_2505_03067_amd import mpm_bbox_from_cells
+    rng = np.random.default_rng(dims[0])
+    nx, ny, nz = dims
+    cell = np.zeros((nz, ny, nx), np.int32)
+    lo = rng.integers(0, [nx // 2, ny // 2, nz // 2])
+    hi = lo + rng.integers(1, [nx // 2, ny // 2, nz // 2])
+    pts = rng.integers(lo, hi, size=(500, 3))
+    cell[pts[:, 2], pts[:, 1], pts[:, 0]] = rng.integers(1, 100, 500)
+    for margin in (0, 4):
+        got = mpm_bbox_from_cells(torch.from_numpy(cell).cuda(), margin)
+        assert got == bbox_from_cells(cell, margin)
+
+
 def test_bbox_empty_and_single():
     torch = require_gpu()
     from paper_2505_03067_amd import MPM_EEMPTY, MpmError, mpm_bbox_from_cells
