@@ -41,8 +41,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config2-dense", "config1", "config3", "config5", "cube100", "cube150",
-                             "cube200"])
+                    choices=["config2", "config2-dense", "config1", "config3", "config4", "config5", "cube100",
+                             "cube150", "cube200"])
+    ap.add_argument("--c4-geometries", type=int, default=64, help="config4: 64^3 training geometries")
+    ap.add_argument("--c4-pairs", type=int, default=10, help="config4: pairs per training geometry")
+    ap.add_argument("--c4-epochs", type=int, default=4, help="config4: training epochs")
+    ap.add_argument("--c4-eval", type=int, default=4, help="config4: unseen 128^3 evaluation geometries")
     ap.add_argument("--grow", action="store_true",
                     help="lung workloads: cells grow every step; the box is recomputed and the "
                          "operator rebuilt before each step (timed with the step)")
@@ -403,6 +407,83 @@ def config3_run(args, m, torch):
     }
 
 
+def config4_run(args, m, torch):
+    """Config 4: the learned warm start trained on 64^3 tumour patches and evaluated on
+    unseen 128^3 boxes.  Each training geometry (``synth.config4_patch``, seeds 0, 1, ...)
+    is advanced 50 steps at tol 1e-10 and a seeded choice of ``--c4-pairs`` of those steps
+    gives (input, change) pairs, built on the GPU by the solver's own warm-start kernel;
+    the targets are scaled by their per-species RMS.  The U-Net is trained for
+    ``--c4-epochs`` epochs (batch 4, Adam, the library's kernels).  The evaluation
+    geometries (seeds 10^6, 10^6 + 1, ...) run 20 steps at tol 1e-8 from c^n (plain),
+    with the extrapolated start and with the learned start."""
+    import numpy as np
+    from paper_2505_03067_amd import train as tr
+    from synth import config4_patch
+    S = 3
+    t0 = time.perf_counter()
+    pairs = []
+    for seed in range(args.c4_geometries):
+        prob = config4_patch(seed, 64)
+        pick = set(np.random.default_rng(seed).choice(50, size=args.c4_pairs, replace=False).tolist())
+        for inp, tgt in tr.generate_pairs([prob], 50, pick, [1.0] * S, tol=1e-10):
+            pairs.append((inp, tgt))
+    gen_s = time.perf_counter() - t0
+    sq, cnt = [0.0] * S, 0
+    for inp, tgt in pairs:
+        mask = inp[..., -1] != 0
+        cnt += int(mask.sum())
+        for sp in range(S):
+            sq[sp] += float((tgt[..., sp][mask].double() ** 2).sum())
+    out_scale = [max((v / max(cnt, 1)) ** 0.5, 1e-30) for v in sq]
+    for _, tgt in pairs:
+        for sp in range(S):
+            tgt[..., sp] /= out_scale[sp]
+    net = m.Net(4 * S + 1, S, [16, 32, 64, 64], seed=7)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = tr.train(net, pairs, args.c4_epochs, 4, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    del pairs
+    evalp = [config4_patch(10 ** 6 + i, 128) for i in range(args.c4_eval)]
+    tol = args.tol if args.tol is not None else 1e-8
+    res = {}
+    for name, warm in (("plain", m.MPM_WS_NONE), ("extrapolated", m.MPM_WS_EXTRAP), ("learned", m.MPM_WS_NET)):
+        its, sps, _, acc = tr.evaluate(evalp, 20, tol, net=net, out_scale=out_scale, warm=warm)
+        res[name] = {"steps_per_s": round(sps, 3), "iterations_per_step": round(its, 2)}
+        if warm != m.MPM_WS_NONE:
+            res[name]["accepted_fraction"] = round(acc, 3)
+    net.close()
+    return {
+        "metric": "implicit steps/s, 128^3 box x 3 species to 1e-8 resid; HBM GB/s; learned vs plain",
+        "value": res["learned"]["steps_per_s"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": 20 * args.c4_eval,
+        "warmup": args.c4_eval,
+        "ms_per_step": round(1000.0 / res["learned"]["steps_per_s"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64, bf16 network",
+        "data": "synthetic",
+        "config": {
+            "workload": f"config4: learned warm start, trained on {args.c4_geometries} x {args.c4_pairs} pairs of "
+                        f"64^3 tumour patches ({args.c4_epochs} epochs), evaluated on {args.c4_eval} unseen 128^3 "
+                        f"boxes x 20 steps at tol {tol:g}; value = steps/s with the learned start",
+        },
+        "learned_vs_plain": {
+            **res,
+            "learned_over_plain": round(res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"], 3),
+            "extrapolated_over_plain": round(res["extrapolated"]["steps_per_s"] / res["plain"]["steps_per_s"], 3),
+            "training": {"pairs": args.c4_geometries * args.c4_pairs, "epochs": args.c4_epochs,
+                         "generation_s": round(gen_s, 1), "training_s": round(train_s, 1),
+                         "loss_by_epoch": [round(float(x), 5) for x in losses]},
+        },
+        "roofline": None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -429,6 +510,9 @@ def main():
     m.lib()
     if args.workload == "config3":
         print(json.dumps(config3_run(args, m, torch)))
+        return 0
+    if args.workload == "config4":
+        print(json.dumps(config4_run(args, m, torch)))
         return 0
     prob = make_workload(args.workload, args.species)
     tol = args.tol if args.tol is not None else prob.tol
