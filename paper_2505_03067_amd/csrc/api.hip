@@ -29,6 +29,7 @@ static void destroy_ctx(Ctx* c) {
     (void)hipFree(c->d_prm);
     (void)hipFree(c->d_blocks);
     (void)hipFree(c->d_blocks_sys);
+    (void)hipFree(c->d_blocks_ax);
     (void)hipFree(c->d_sysfc);
     (void)hipFree(c->d_fields);
     (void)hipFree(c->V);

@@ -72,7 +72,8 @@ struct Ctx {
     std::vector<int> sys_tab_first;    // start of each system's table in blocks_sys
     int nslots = 0;
     int block_unknowns = 0;            // unknowns per block (autotuned or fixed)
-    std::map<std::string, long long> tile_cache;   // autotuned split per layout
+    int axpy_group = 1;                // blocks of the batched table per block of the axpy table
+    std::map<std::string, std::pair<long long, int>> tile_cache;   // autotuned split and axpy group
 
     // device buffers
     ProbDev* d_probs = nullptr;
@@ -81,6 +82,8 @@ struct Ctx {
     Params* d_prm = nullptr;
     Block* d_blocks = nullptr;
     Block* d_blocks_sys = nullptr;
+    std::vector<Block> blocks_ax;      // batched table of the delayed scheme's axpy kernel
+    Block* d_blocks_ax = nullptr;
     int* d_sysfc = nullptr;            // [2][kMaxSys] first slot and block count per system
     double** d_fields = nullptr;
     size_t cap_blocks = 0, cap_slots = 0;

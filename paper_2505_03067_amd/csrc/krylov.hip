@@ -1511,7 +1511,7 @@ static size_t ksize(const Ctx* c) { return c->opt.precision == MPM_FP64 ? 8 : 4;
 
 // Split each system into blocks of 'per' unknowns (a multiple of kAlign), build the
 // XCD-aware batched table and the per-system tables.
-static void build_tables(Ctx* c, long long per) {
+static void build_tables(Ctx* c, long long per, int group) {
     const int S = c->S;
     const int nsys = S * c->P;
     per = std::max<long long>(kAlign, (per + kAlign - 1) / kAlign * kAlign);
@@ -1580,6 +1580,25 @@ static void build_tables(Ctx* c, long long per) {
     }
     c->blocks.clear();
     swizzle(inter, c->blocks);
+    // The delayed scheme's axpy kernel may run over 'group' consecutive blocks of a
+    // system per block: fewer blocks each read all partial sums of their system (the
+    // bulk of that kernel's traffic at small splits), while the stencil kernel keeps
+    // one pass per thread.  The records keep the system's partial-sum layout (slot0,
+    // nb) of the batched table; only the first block of a system has slot == slot0.
+    c->axpy_group = group;
+    std::vector<Block> ax;
+    for (int p = 0; p < c->P; ++p) {
+        const int nbp = c->sys_count[p * S];
+        for (int i = 0; i < nbp; i += group)
+            for (int s = 0; s < S; ++s) {
+                const int f = c->sys_first[p * S + s];
+                Block b = logical[f + i];
+                b.end = logical[f + std::min(nbp, i + group) - 1].end;
+                ax.push_back(b);
+            }
+    }
+    c->blocks_ax.clear();
+    swizzle(ax, c->blocks_ax);
     c->blocks_sys.clear();
     c->sys_tab_first.assign(nsys, 0);
     for (int sys = 0; sys < nsys; ++sys) {
@@ -1601,14 +1620,16 @@ static long long model_tile(const Ctx* c) {
 // Copy the block tables and problem descriptors to the device (growing buffers).
 static int upload_tables(Ctx* c) {
     hipStream_t st = c->stream;
-    const size_t nb = c->blocks.size(), nbs = c->blocks_sys.size();
-    if (nb > c->cap_blocks || nbs > c->cap_blocks) {
+    const size_t nb = c->blocks.size(), nbs = c->blocks_sys.size(), nbx = c->blocks_ax.size();
+    if (nb > c->cap_blocks || nbs > c->cap_blocks || nbx > c->cap_blocks) {
         if (c->d_blocks) (void)hipFree(c->d_blocks);
         if (c->d_blocks_sys) (void)hipFree(c->d_blocks_sys);
-        c->d_blocks = c->d_blocks_sys = nullptr;
-        const size_t cap = std::max(nb, nbs) * 2;
+        if (c->d_blocks_ax) (void)hipFree(c->d_blocks_ax);
+        c->d_blocks = c->d_blocks_sys = c->d_blocks_ax = nullptr;
+        const size_t cap = std::max(std::max(nb, nbs), nbx) * 2;
         if (hipMalloc(&c->d_blocks, cap * sizeof(Block)) != hipSuccess ||
-            hipMalloc(&c->d_blocks_sys, cap * sizeof(Block)) != hipSuccess) {
+            hipMalloc(&c->d_blocks_sys, cap * sizeof(Block)) != hipSuccess ||
+            hipMalloc(&c->d_blocks_ax, cap * sizeof(Block)) != hipSuccess) {
             (void)hipGetLastError();
             c->cap_blocks = 0;
             set_error("device allocation of block tables failed");
@@ -1630,6 +1651,7 @@ static int upload_tables(Ctx* c) {
     }
     MPM_HIP(hipMemcpyAsync(c->d_blocks, c->blocks.data(), nb * sizeof(Block), hipMemcpyHostToDevice, st));
     MPM_HIP(hipMemcpyAsync(c->d_blocks_sys, c->blocks_sys.data(), nbs * sizeof(Block), hipMemcpyHostToDevice, st));
+    MPM_HIP(hipMemcpyAsync(c->d_blocks_ax, c->blocks_ax.data(), nbx * sizeof(Block), hipMemcpyHostToDevice, st));
     std::vector<int> fc(2 * (size_t)c->S * c->P);
     const int nsys = c->S * c->P;
     for (int s = 0; s < nsys; ++s) {
@@ -1676,7 +1698,7 @@ __global__ void k_tune_state(SysK* sk, int nsys, int mcount) {
 // candidate split, three times, and keep the split with the fastest repetition.  The
 // choice is cached per layout.
 template <typename T>
-static int autotune_t(Ctx* c, long long* best_out) {
+static int autotune_t(Ctx* c, long long* best_out, int* group_out) {
     hipStream_t st = c->stream;
     const Kernels<T>& K = kernels<T>();
     const int J = std::min(8, c->opt.restart - 1);
@@ -1685,38 +1707,34 @@ static int autotune_t(Ctx* c, long long* best_out) {
         return MPM_EINVAL;
     }
     const int nsys = c->S * c->P;
+    const bool dc = c->opt.ortho == MPM_ORTHO_DCGS2;
     long long maxpad = 0;
     for (auto& ph : c->probs) maxpad = std::max<long long>(maxpad, ph.Npad);
     hipEvent_t e0, e1;
     MPM_HIP(hipEventCreate(&e0));
     MPM_HIP(hipEventCreate(&e1));
-    double best_ms = 1e30;
-    long long best = model_tile(c);
     const size_t vbytes = (size_t)(c->opt.restart + 1) * c->ldv * ksize(c);
     MPM_HIP(hipMemsetAsync(c->V, 0x3c, vbytes, st));   // finite, non-zero fill
-    // at most eight passes per thread (the residual and update kernels do not overlap
-    // their passes), at most 1024 partial-sum slots per system
-    const long long max_tile = 8LL * kThreads * VW<T>::n;
-    for (long long tile = 1024; tile <= max_tile; tile *= 2) {
-        const long long nbsys = (maxpad + tile - 1) / tile;
-        if (nbsys > 1024) continue;            // too many partial sums per system
-        if (tile > 1024 && nbsys < 8) break;   // too few blocks per system
-        build_tables(c, tile);
+    // Time one work split: the two kernels of Arnoldi steps 0 and J (the axpy kernel over
+    // its grouped table) three times plus one residual and one update; best of three.
+    auto time_split = [&](long long tile, int group, float* out) -> int {
+        build_tables(c, tile, group);
         int rc = upload_tables(c);
         if (rc != MPM_OK) return rc;
         // the update reads V_0..V_{mcount-1}: never more than the restart + 1 stored vectors
         k_tune_state<<<nsys, 64, 0, st>>>(c->d_sk, nsys, J + 1);
         KArgs<T> a = make_args<T>(c, c->d_blocks);
-        const unsigned nb = (unsigned)c->blocks.size();
+        KArgs<T> ax = make_args<T>(c, c->d_blocks_ax);
+        const unsigned nb = (unsigned)c->blocks.size(), nbx = (unsigned)c->blocks_ax.size();
         float ms = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             MPM_HIP(hipEventRecord(e0, st));
             for (int it = 0; it < 3; ++it) {
-                if (c->opt.ortho == MPM_ORTHO_DCGS2) {
+                if (dc) {
                     K.da[0]<<<nb, kThreads, 0, st>>>(a);
-                    K.db[0]<<<nb, kThreads, 0, st>>>(a);
+                    K.db[0]<<<nbx, kThreads, 0, st>>>(ax);
                     K.da[J]<<<nb, kThreads, 0, st>>>(a);
-                    K.db[J]<<<nb, kThreads, 0, st>>>(a);
+                    K.db[J]<<<nbx, kThreads, 0, st>>>(ax);
                     // once per cycle in the solve; here once per two Arnoldi steps
                     if (it == 0) {
                         k_residual<T><<<nb, kThreads, 0, st>>>(a, kResCycle);
@@ -1734,15 +1752,45 @@ static int autotune_t(Ctx* c, long long* best_out) {
             MPM_HIP(hipEventElapsedTime(&t, e0, e1));
             ms = std::min(ms, t);
         }
+        *out = ms;
+        return MPM_OK;
+    };
+    float best_ms = 1e30f;
+    long long best = model_tile(c);
+    // at most eight passes per thread (the residual and update kernels do not overlap
+    // their passes), at most 1024 partial-sum slots per system
+    const long long max_tile = 8LL * kThreads * VW<T>::n;
+    for (long long tile = 1024; tile <= max_tile; tile *= 2) {
+        const long long nbsys = (maxpad + tile - 1) / tile;
+        if (nbsys > 1024) continue;            // too many partial sums per system
+        if (tile > 1024 && nbsys < 8) break;   // too few blocks per system
+        float ms = 0.0f;
+        int rc = time_split(tile, 1, &ms);
+        if (rc != MPM_OK) return rc;
         if (ms < best_ms) {
             best_ms = ms;
             best = tile;
+        }
+    }
+    // then the grouping of the axpy kernel's blocks for that split
+    int best_group = 1;
+    if (dc) {
+        const long long nbsys = (maxpad + best - 1) / best;
+        for (int group = 2; group <= 4 && nbsys >= 4 * group; group *= 2) {
+            float ms = 0.0f;
+            int rc = time_split(best, group, &ms);
+            if (rc != MPM_OK) return rc;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_group = group;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     MPM_HIP(hipMemsetAsync(c->V, 0, vbytes, st));
     *best_out = best;
+    *group_out = best_group;
     return MPM_OK;
 }
 
@@ -1838,25 +1886,29 @@ int ensure_layout(Ctx* c) {
     c->h_prm->S = c->S;
     MPM_HIP(hipMemcpyAsync(c->d_prm, c->h_prm, sizeof(Params), hipMemcpyHostToDevice, st));
     c->up_valid = false;
-    // work split: fixed override, cached tuning result, or a fresh autotune
+    // work split: fixed override, cached tuning result, or a fresh autotune.  With a
+    // fixed split the axpy kernel of the delayed scheme takes two blocks' ranges per
+    // block (measured faster at 1024 and at 4096 unknowns per block).
     long long tile = c->opt.tile_override;
+    int group = 2;
     if (tile <= 0) {
         // sizes within about 9% of each other share a tuning result (a box that changes a
         // little every step is not tuned again)
-        std::string key = std::to_string(c->S) + ":" + std::to_string(ksize(c));
+        std::string key = std::to_string(c->S) + ":" + std::to_string(ksize(c)) + ":" + std::to_string(c->opt.ortho);
         for (auto& ph : c->probs) key += ":" + std::to_string((int)std::floor(8.0 * std::log2((double)ph.Npad)));
         auto it = c->tile_cache.find(key);
         if (it != c->tile_cache.end()) {
-            tile = it->second;
+            tile = it->second.first;
+            group = it->second.second;
         } else if (c->opt.batched) {
-            int rc = ksize(c) == 8 ? autotune_t<double>(c, &tile) : autotune_t<float>(c, &tile);
+            int rc = ksize(c) == 8 ? autotune_t<double>(c, &tile, &group) : autotune_t<float>(c, &tile, &group);
             if (rc != MPM_OK) return rc;
-            c->tile_cache[key] = tile;
+            c->tile_cache[key] = {tile, group};
         } else {
             tile = model_tile(c);
         }
     }
-    build_tables(c, tile);
+    build_tables(c, tile, group);
     int rc = upload_tables(c);
     if (rc != MPM_OK) return rc;
     // diagonal extremes per system (for the scaled/unscaled residual bound)
@@ -1924,6 +1976,10 @@ static void enqueue_cycle(Ctx* c, const Block* tab, unsigned nb, int sys0, int n
                           int j1, int tail, bool events) {
     const Kernels<T>& K = kernels<T>();
     KArgs<T> a = make_args<T>(c, tab);
+    // the batched launch runs the delayed scheme's axpy kernel over its grouped table
+    const bool grouped = tab == c->d_blocks;
+    KArgs<T> ax = make_args<T>(c, grouped ? c->d_blocks_ax : tab);
+    const unsigned nbx = grouped ? (unsigned)c->blocks_ax.size() : nb;
     auto emit = [&](auto launch, bool is_timed) {
         if (is_timed && events) {
             tev_begin(c, st);
@@ -1939,7 +1995,7 @@ static void enqueue_cycle(Ctx* c, const Block* tab, unsigned nb, int sys0, int n
         if (dc) {
             KFn<T> fa = K.da[j], fb = K.db[j];
             emit([&] { fa<<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_SPMV_DOT, j));
-            emit([&] { fb<<<nb, kThreads, 0, st>>>(a); }, timed(c, MPM_KERNEL_AXPY_DOT, j));
+            emit([&] { fb<<<nbx, kThreads, 0, st>>>(ax); }, timed(c, MPM_KERNEL_AXPY_DOT, j));
         } else {
             const KFn<T> fns[3] = {K.k1[j], K.k2[j], K.k3[j]};
             for (int q = 0; q < 3; ++q) {
