@@ -271,8 +271,9 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     return res
 
 
-def cpu_baseline(prob, box, c_start, gpu_after, tol, budget_s):
-    """The oracle (FP64 GMRES(30) + Jacobi, single-threaded) timed on a bounded sample.
+def cpu_baseline(prob, box, c_start, gpu_after, tol, budget_s, threads=1):
+    """The oracle (FP64 GMRES(30) + Jacobi) timed on a bounded sample, with ``threads``
+    BLAS/OpenMP threads (None: every core the process may use).
 
     Runs consecutive steps from the same c^n the GPU started from, until the time budget
     is spent (at least one step), and compares each species with the GPU's fields.
@@ -289,7 +290,7 @@ def cpu_baseline(prob, box, c_start, gpu_after, tol, budget_s):
     done = 0
     t0 = time.perf_counter()
     errs = []
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         while done < len(gpu_after):
             c, _ = implicit_step(c, prob.mask, prob.D, prob.k, prob.src, prob.c_b, box,
                                  prob.dt, prob.h, solver="gmres", tol=tol, restart=30)
@@ -704,6 +705,18 @@ def main():
                       f"(FP64 GMRES(30) + Jacobi, tol {tol:g}, scipy CSR, 1 thread), {cpu_s:.1f} s",
         }
         out["fp64_rel_err_vs_oracle"] = [max(e[sp] for e in errs) for sp in range(prob.nspecies)]
+        # the same oracle with every core the process may use (scipy's sparse products stay
+        # single-threaded; only numpy's BLAS-2 work spreads)
+        ncores = len(os.sched_getaffinity(0))
+        done2, cpu_s2, _ = cpu_baseline(prob, box, c_start.cpu().numpy(), after[:2], tol,
+                                        min(args.cpu_seconds, 5.0), threads=None)
+        out["cpu_baseline_all_cores"] = {
+            "value": round(done2 / cpu_s2, 5),
+            "unit": "steps/s",
+            "cores": ncores,
+            "kind": "oracle",
+            "sample": f"{done2} consecutive steps as above with {ncores} threads, {cpu_s2:.1f} s",
+        }
     print(json.dumps(out), flush=True)
     return 0
 
