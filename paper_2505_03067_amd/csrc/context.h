@@ -49,6 +49,18 @@ struct ProbHost {
     size_t cap_grid = 0;
 };
 
+// What a tuning result is kept for: species, basis word size, orthogonalisation,
+// problems, and the size classes of the largest problem and of all unknowns.
+struct TuneKey {
+    int S, ks, ortho, P, cmax, ctot;
+    bool operator<(const TuneKey& o) const {
+        const int a[6] = {S, ks, ortho, P, cmax, ctot}, b[6] = {o.S, o.ks, o.ortho, o.P, o.cmax, o.ctot};
+        for (int i = 0; i < 6; ++i)
+            if (a[i] != b[i]) return a[i] < b[i];
+        return false;
+    }
+};
+
 struct Ctx {
     int S = 0, P = 0;
     mpm_options opt{};
@@ -73,7 +85,7 @@ struct Ctx {
     int nslots = 0;
     int block_unknowns = 0;            // unknowns per block (autotuned or fixed)
     int axpy_group = 1;                // blocks of the batched table per block of the axpy table
-    std::map<std::string, std::pair<long long, int>> tile_cache;   // autotuned split and axpy group
+    std::map<TuneKey, std::pair<long long, int>> tile_cache;   // autotuned split and axpy group
 
     // device buffers
     ProbDev* d_probs = nullptr;

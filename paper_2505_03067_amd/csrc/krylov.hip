@@ -1892,14 +1892,30 @@ int ensure_layout(Ctx* c) {
     long long tile = c->opt.tile_override;
     int group = 2;
     if (tile <= 0) {
-        // sizes within about 9% of each other share a tuning result (a box that changes a
-        // little every step is not tuned again)
-        std::string key = std::to_string(c->S) + ":" + std::to_string(ksize(c)) + ":" + std::to_string(c->opt.ortho);
-        for (auto& ph : c->probs) key += ":" + std::to_string((int)std::floor(8.0 * std::log2((double)ph.Npad)));
-        auto it = c->tile_cache.find(key);
-        if (it != c->tile_cache.end()) {
-            tile = it->second.first;
-            group = it->second.second;
+        // The tuning result is kept per species count, precision, orthogonalisation and
+        // problem count, and per size class of the largest problem and of all unknowns
+        // (eight classes per doubling); a layout whose classes are both within one class of
+        // a tuned one reuses that result, so boxes that grow step by step are tuned again
+        // only after they have grown by about a fifth.
+        long long maxpad = 0, total = 0;
+        for (auto& ph : c->probs) {
+            maxpad = std::max<long long>(maxpad, ph.Npad);
+            total += (long long)c->S * ph.Npad;
+        }
+        const TuneKey key{c->S, (int)ksize(c), c->opt.ortho, c->P, (int)std::floor(8.0 * std::log2((double)maxpad)),
+                          (int)std::floor(8.0 * std::log2((double)total))};
+        auto near = c->tile_cache.end();
+        for (auto it = c->tile_cache.begin(); it != c->tile_cache.end(); ++it) {
+            const TuneKey& k = it->first;
+            if (k.S == key.S && k.ks == key.ks && k.ortho == key.ortho && k.P == key.P &&
+                std::abs(k.cmax - key.cmax) <= 1 && std::abs(k.ctot - key.ctot) <= 1) {
+                near = it;
+                if (k.cmax == key.cmax && k.ctot == key.ctot) break;   // exact match first
+            }
+        }
+        if (near != c->tile_cache.end()) {
+            tile = near->second.first;
+            group = near->second.second;
         } else if (c->opt.batched) {
             int rc = ksize(c) == 8 ? autotune_t<double>(c, &tile, &group) : autotune_t<float>(c, &tile, &group);
             if (rc != MPM_OK) return rc;
