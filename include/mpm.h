@@ -264,6 +264,18 @@ int32_t mpm_ws_grid(mpm_ctx ctx, int32_t problem, int32_t* grid);
 int32_t mpm_debug_apply(mpm_ctx ctx, int32_t problem, const double* x_lattice, double* y_lattice,
                         int32_t mode);
 
+/* Test hook: the Krylov state of one (problem, species) system after the last GMRES
+ * cycle of the last step (delayed Gram-Schmidt only), for checks of orthogonality and
+ * of the Arnoldi relation.  Host outputs: *mcount = columns of that cycle (m);
+ * vs[k] and basis[k * N + l] (N = domain voxels of the box, compact C order) for
+ * k < min(m, kmax), the orthonormal basis being v_k = vs[k] * basis[k]; hess[k *
+ * (kmax + 1) + i] = H[i][k], the unrotated Hessenberg matrix (rows i <= k + 1, zero
+ * elsewhere).  The caller sizes vs [kmax], basis [kmax * N], hess [kmax * (kmax + 1)].
+ * 1 <= kmax <= restart.  Synchronises the stream.  MPM_ESTATE before the first step on
+ * the current layout. */
+int32_t mpm_debug_krylov(mpm_ctx ctx, int32_t problem, int32_t species, int32_t kmax, int32_t* mcount,
+                         double* vs, double* basis, double* hess);
+
 #ifdef __cplusplus
 }
 #endif

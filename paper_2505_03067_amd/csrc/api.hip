@@ -258,6 +258,17 @@ extern "C" int32_t mpm_debug_apply(mpm_ctx ctx, int32_t problem, const double* x
     return rc;
 }
 
+extern "C" int32_t mpm_debug_krylov(mpm_ctx ctx, int32_t problem, int32_t species, int32_t kmax, int32_t* mcount,
+                                    double* vs, double* basis, double* hess) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !mcount || !vs || !basis || !hess || problem < 0 || problem >= c->P || species < 0 ||
+        species >= c->S || kmax < 1 || kmax > c->opt.restart) {
+        set_error("mpm_debug_krylov: bad arguments");
+        return MPM_EINVAL;
+    }
+    return debug_krylov(c, problem, species, kmax, mcount, vs, basis, hess);
+}
+
 extern "C" int32_t mpm_time_kernel(mpm_ctx ctx, int32_t kind, int32_t j, int32_t repeat) {
     Ctx* c = (Ctx*)ctx;
     if (!c || kind < MPM_KERNEL_NONE || kind > MPM_KERNEL_RESIDUAL || j < 0 || j >= c->opt.restart ||

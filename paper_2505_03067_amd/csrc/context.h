@@ -152,6 +152,7 @@ int launch_diag_extremes(Ctx* c, int p);
 // krylov.hip
 int run_step(Ctx* c, double* const* fields, double tol);
 int debug_apply(Ctx* c, int p, const double* x, double* y, int mode);
+int debug_krylov(Ctx* c, int p, int sp, int kmax, int* mcount, double* vs, double* basis, double* hess);
 int ensure_layout(Ctx* c);
 int select_timing(Ctx* c, int kind, int j, int repeat);
 int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* in_bf16, float* target);

@@ -2393,6 +2393,46 @@ int select_timing(Ctx* c, int kind, int j, int repeat) {
     return MPM_OK;
 }
 
+// Krylov state of one system after the last cycle (test hook): the stored basis columns
+// V_0..V_{m-1} (m = mcount) of that system's unknowns widened to FP64, their scales
+// vs[0..m-1] (orthonormal v_k = vs[k] V_k) and the unrotated Hessenberg columns
+// 0..m-1 (hess[k * (kmax + 1) + i] = H[i][k], rows 0..k+1).  Copies at most kmax columns.
+template <typename T>
+static int debug_krylov_t(Ctx* c, int p, int sp, int kmax, int* mcount, double* vs, double* basis, double* hess) {
+    hipStream_t st = c->stream;
+    MPM_HIP(hipStreamSynchronize(st));
+    const int sys = p * c->S + sp;
+    SysK k{};
+    MPM_HIP(hipMemcpy(&k, c->d_sk + sys, sizeof(SysK), hipMemcpyDeviceToHost));
+    const ProbHost& ph = c->probs[p];
+    const int m = std::min(k.mcount, kmax);
+    *mcount = k.mcount;
+    std::vector<T> col((size_t)ph.N);
+    const long long base = c->off[p] + (long long)sp * ph.Npad;
+    constexpr int LD = kMaxM + 1;
+    for (int j = 0; j < m; ++j) {
+        const T* src = (const T*)c->V + (long long)j * c->ldv + base;
+        MPM_HIP(hipMemcpy(col.data(), src, (size_t)ph.N * sizeof(T), hipMemcpyDeviceToHost));
+        for (int l = 0; l < ph.N; ++l) basis[(size_t)j * ph.N + l] = (double)col[l];
+        vs[j] = k.vs[j];
+        for (int i = 0; i <= kmax; ++i) hess[(size_t)j * (kmax + 1) + i] = i <= j + 1 && i < LD ? k.Hraw[j * LD + i] : 0.0;
+    }
+    return MPM_OK;
+}
+
+int debug_krylov(Ctx* c, int p, int sp, int kmax, int* mcount, double* vs, double* basis, double* hess) {
+    if (c->opt.ortho != MPM_ORTHO_DCGS2) {
+        set_error("mpm_debug_krylov: needs the delayed Gram-Schmidt scheme (the unrotated Hessenberg)");
+        return MPM_EINVAL;
+    }
+    if (c->layout_dirty || !c->V) {
+        set_error("mpm_debug_krylov: no step has run on the current layout");
+        return MPM_ESTATE;
+    }
+    return c->opt.precision == MPM_FP64 ? debug_krylov_t<double>(c, p, sp, kmax, mcount, vs, basis, hess)
+                                        : debug_krylov_t<float>(c, p, sp, kmax, mcount, vs, basis, hess);
+}
+
 int debug_apply(Ctx* c, int p, const double* x, double* y, int mode) {
     int rc = ensure_layout(c);
     if (rc != MPM_OK) return rc;

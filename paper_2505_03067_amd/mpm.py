@@ -87,6 +87,9 @@ def lib() -> ctypes.CDLL:
             "mpm_gmres_stats": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mpm_stats)],
             "mpm_destroy": [_vp],
             "mpm_debug_apply": [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32],
+            "mpm_debug_krylov": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)],
             "mpm_time_kernel": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
             "mpm_tile": [_vp, _i32p],
             "mpm_net_create": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -240,6 +243,21 @@ def mpm_debug_apply(ctx, problem: int, x, y, mode: int) -> None:
     import torch
     _check(lib().mpm_debug_apply(ctx, int(problem), _dev_ptr(x, torch.float64, "x"),
                                  _dev_ptr(y, torch.float64, "y"), int(mode)))
+
+
+def mpm_debug_krylov(ctx, problem: int, species: int, kmax: int, n: int):
+    """Krylov state of one system after the last cycle: (m, vs [k], basis [k][n], H [k][kmax+1])
+    with k = min(m, kmax) columns; ``n`` = domain voxels of the problem's box."""
+    import numpy as np
+    m = ctypes.c_int32(0)
+    vs = np.zeros(kmax)
+    basis = np.zeros((kmax, n))
+    hess = np.zeros((kmax, kmax + 1))
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().mpm_debug_krylov(ctx, int(problem), int(species), int(kmax), ctypes.byref(m),
+                                  vs.ctypes.data_as(dp), basis.ctypes.data_as(dp), hess.ctypes.data_as(dp)))
+    k = min(m.value, kmax)
+    return m.value, vs[:k], basis[:k], hess[:k]
 
 
 MPM_KERNEL_NONE = 0
@@ -458,6 +476,9 @@ class Solver:
 
     def apply(self, problem, x, y, mode):
         return mpm_debug_apply(self.ctx, problem, x, y, mode)
+
+    def krylov(self, problem, species, kmax, n):
+        return mpm_debug_krylov(self.ctx, problem, species, kmax, n)
 
     def close(self):
         mpm_destroy(self.ctx)
