@@ -27,6 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_FLOPS = 2.5e15      # dense BF16 MFMA
 
 KERNELS = {"spmv_dot": 1, "axpy_dot": 2, "axpy_norm": 3, "update": 4, "residual": 5}
 KERNEL_NAMES = {1: "k_spmv_dot", 2: "k_axpy_dot", 3: "k_axpy_norm", 4: "k_update",
@@ -81,6 +82,21 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device once (calibrates HBM counters)")
     return ap.parse_args()
+
+
+def unet_macs_per_voxel(cin, cout, widths):
+    """Multiply-adds per input-grid voxel of the warm-start U-Net: per level l (1/8^l of
+    the voxels) two 3x3x3 convolutions on the way down (the first from the level above,
+    or the input), two on the way up (the first on the upsampled level below
+    concatenated with the skip), and the 1x1x1 head."""
+    L = len(widths)
+    macs = 0.0
+    for lv in range(L):
+        c = widths[lv]
+        down = (cin if lv == 0 else widths[lv - 1]) * c * 27 + c * c * 27
+        up = ((widths[lv + 1] + c) * c * 27 + c * c * 27) if lv < L - 1 else 0
+        macs += (down + up) / 8 ** lv
+    return macs + widths[0] * cout
 
 
 def alg_bytes_active(kind, j, U, precision, S, dcgs2):
@@ -234,6 +250,19 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
         net.adam(1e-3, it)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    # the network's forward pass on the box grid against the dense BF16 MFMA peak
+    x0 = pairs[0][0].unsqueeze(0)
+    y0 = torch.empty_like(pairs[0][1]).unsqueeze(0)
+    net.forward(x0, y0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        net.forward(x0, y0)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 5
+    grid = int(x0.shape[1] * x0.shape[2] * x0.shape[3])
+    fwd_flop = 2.0 * unet_macs_per_voxel(4 * S + 1, S, [16, 32, 64, 64]) * grid
     del pairs
     res = {}
     for name, warm in (("plain", m.MPM_WS_NONE), ("extrapolated", m.MPM_WS_EXTRAP), ("learned", m.MPM_WS_NET)):
@@ -262,6 +291,9 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
             res[name]["accepted_fraction"] = round(acc / (args.learned_steps * S), 3)
             res[name]["residual_ratio_warm_over_cn"] = round(float(np.mean(rw)), 4) if rw else None
     net.close()
+    res["network_forward"] = {"grid_voxels": grid, "ms": round(fwd_ms, 3), "flop": fwd_flop,
+                              "tflops": round(fwd_flop / (fwd_ms * 1e-3) / 1e12, 1),
+                              "frac_of_bf16_peak": round(fwd_flop / (fwd_ms * 1e-3) / BF16_PEAK_FLOPS, 4)}
     res["training"] = {"pairs": args.train_pairs, "iterations": args.train_iters, "seconds": round(train_s, 2),
                        "loss_first": round(float(np.mean(losses[:10])), 5),
                        "loss_last": round(float(np.mean(losses[-10:])), 5),

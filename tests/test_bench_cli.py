@@ -35,3 +35,12 @@ def test_algorithmic_bytes():
     assert bench.alg_bytes_active(2, 10, U, 1, S, True) == 56 * U
     # CGS2 second pass, FP64: t (j + 3)
     assert bench.alg_bytes_active(2, 10, U, 0, S, False) == 8 * 13 * U
+
+
+def test_unet_work_per_voxel():
+    import bench
+    # 16-32-64-64 U-Net, 13 inputs, 3 outputs: 40,224 multiply-adds per voxel at full
+    # resolution (12,528 down, 27,648 up, 48 head), 152,064 / 8, 497,664 / 64, 221,184 / 512
+    assert bench.unet_macs_per_voxel(13, 3, [16, 32, 64, 64]) == 40224 + 19008 + 7776 + 432
+    # one level, no skips: two convolutions and the head
+    assert bench.unet_macs_per_voxel(2, 1, [4]) == 2 * 4 * 27 + 4 * 4 * 27 + 4
