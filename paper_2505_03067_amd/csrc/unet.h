@@ -11,8 +11,8 @@ struct ConvL {
     int cin = 0, cout = 0, taps = 0;
     int cin_p = 0, cout_p = 0, kp = 0, kpd = 0;
     size_t woff = 0, boff = 0;         // offsets in the flat parameter vector
-    uint16_t* wf = nullptr;            // BF16 [cout_p][kp], k = tap * cin_p + c
-    uint16_t* wd = nullptr;            // BF16 [cin_p][kpd], k = tap * cout_p + o, W[26 - tap]
+    uint16_t* wf = nullptr;            // BF16 forward weights, cout_p x kp values in fragment order
+    uint16_t* wd = nullptr;            // BF16 input-gradient weights (W[26 - tap] transposed), cin_p x kpd
 };
 
 struct Net {

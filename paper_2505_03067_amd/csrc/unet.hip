@@ -82,9 +82,9 @@ int net_pack(Net* n) {
     hipStream_t st = n->stream;
     for (auto& l : n->layers) {
         if (l.taps != 27) continue;
-        const long long tot = (long long)l.cout_p * l.kp + (long long)l.cin_p * l.kpd;
-        k_pack<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(n->theta + l.woff, l.cin, l.cout, l.taps, l.cin_p,
-                                                            l.cout_p, l.kp, l.kpd, l.wf, l.wd);
+        const long long nf = (long long)l.cout_p * l.kp, nd = (long long)l.cin_p * l.kpd;
+        k_pack<<<(unsigned)((nf + nd + 255) / 256), 256, 0, st>>>(n->theta + l.woff, l.cin, l.cout, l.cin_p, l.cout_p,
+                                                                 nf, nd, l.wf, l.wd);
     }
     MPM_HIP(hipGetLastError());
     return MPM_OK;
@@ -172,23 +172,52 @@ static int ensure_acts(Net* n, int nb, int D, int H, int W) {
     return MPM_OK;
 }
 
-template <int NT>
-static void launch_conv(const ConvArgs& a, hipStream_t st) {
+// Launch k_conv<NTB, CS, GATED> over all (voxel tile, output-tile group) items: one persistent
+// block per LDS slot of the device (capped at the item count, rounded down to a multiple
+// of the group count).  The LDS (up to 78 KB) is granted once per kernel and process.
+template <int NTB, int CS, bool GATED>
+static int launch_conv(const ConvArgs& a, hipStream_t st) {
+    constexpr int lds = conv_lds_bytes(CS, NTB);
+    static int slots = 0;   // resident blocks of the device, limited by LDS
+    static const hipError_t granted = [] {
+        int dev = 0, cap = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+        if (e == hipSuccess && cap < lds) e = hipErrorInvalidValue;
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, CS, GATED>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        slots = std::max(1, cus) * std::max(1, per_cu / lds);
+        return e;
+    }();
+    if (granted != hipSuccess) return hip_fail(granted, "U-Net convolution LDS");
     const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
-    k_conv<NT><<<(unsigned)tiles, 256, 0, st>>>(a);
+    const int nsplit = a.nt / NTB;
+    const long long items = tiles * nsplit;
+    long long grid = std::min<long long>(items, slots);
+    grid = std::max<long long>(nsplit, grid / nsplit * nsplit);
+    k_conv<NTB, CS, GATED><<<(unsigned)grid, 256, lds, st>>>(a);
+    return MPM_OK;
 }
 
-static int conv_dispatch(const ConvArgs& a, int nt, hipStream_t st) {
-    switch (nt) {
-        case 1: launch_conv<1>(a, st); break;
-        case 2: launch_conv<2>(a, st); break;
-        case 3: launch_conv<3>(a, st); break;
-        case 4: launch_conv<4>(a, st); break;
-        case 6: launch_conv<6>(a, st); break;
-        case 8: launch_conv<8>(a, st); break;
-        default: set_error("unsupported channel count in the U-Net"); return MPM_EINVAL;
+// Output tiles per block: two for a 16-channel input with an even tile count (each A
+// fragment read from LDS then feeds two MFMAs, and the block's 58 KB of LDS still lets
+// two blocks share a CU), else one (with 32-channel chunks, two tiles per block would
+// take 105 KB of LDS and leave one block per CU, measured slower at every level).
+static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
+    if (nt < 1 || nt > 8 || a.cin_p % 16 || a.cin_p < 16) {
+        set_error("unsupported channel count in the U-Net");
+        return MPM_EINVAL;
     }
-    return MPM_OK;
+    a.nt = nt;
+    if (a.gate) {
+        if (a.cin_p == 16) return nt % 2 ? launch_conv<1, 24, true>(a, st) : launch_conv<2, 24, true>(a, st);
+        return launch_conv<1, 40, true>(a, st);
+    }
+    if (a.cin_p == 16) return nt % 2 ? launch_conv<1, 24, false>(a, st) : launch_conv<2, 24, false>(a, st);
+    return launch_conv<1, 40, false>(a, st);
 }
 
 static ConvArgs conv_args(const Net* n, int lvl) {
@@ -232,8 +261,6 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
             a.ldx = hch;
             a.cin_p = c.cin_p;
             a.w = c.wf;
-            a.kp = c.kp;
-            a.taps = 27;
             a.bias = n->theta + c.boff;
             a.y = n->act[li];
             a.ldy = c.cout;
@@ -258,8 +285,6 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
             a.ldx = hch;
             a.cin_p = c.cin_p;
             a.w = c.wf;
-            a.kp = c.kp;
-            a.taps = 27;
             a.bias = n->theta + c.boff;
             a.y = n->act[li];
             a.ldy = c.cout;
@@ -345,8 +370,6 @@ static int conv_input_grad(Net* n, int li, int lvl, const uint16_t* g, const uin
     a.ldx = c.cout;
     a.cin_p = c.cout_p;
     a.w = c.wd;
-    a.kp = c.kpd;
-    a.taps = 27;
     a.y = dx;
     a.ldy = c.cin;
     a.cout = c.cin;
@@ -621,8 +644,6 @@ extern "C" int32_t mpm_net_debug_layer(mpm_net net, int32_t layer, int32_t mode,
         a.ldx = c.cin_p;
         a.cin_p = c.cin_p;
         a.w = c.wf;
-        a.kp = c.kp;
-        a.taps = 27;
         a.bias = n->theta + c.boff;
         a.yf = out;
         a.cout = c.cout;

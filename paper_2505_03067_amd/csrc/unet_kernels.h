@@ -30,11 +30,11 @@ __device__ inline uint16_t f2bf(float f) {
 struct ConvArgs {
     const uint16_t* x;     // GEMM input [P][ldx] (activation, or output gradient for dgrad)
     const uint16_t* gate;  // optional [P][ldx]: use x * (gate > 0) (ReLU backward)
-    const uint16_t* w;     // [cout_p][kp] BF16, k = tap * cin_p + c
+    const uint16_t* w;     // BF16 weights packed in MFMA fragment order (k_pack)
     const float* bias;     // optional [cout]
     uint16_t* y;           // output [P][ldy], channels [yoff, yoff + cout)
     float* yf;             // optional FP32 output [P][cout]
-    int ldx, cin_p, kp, taps;
+    int ldx, cin_p, nt;    // input stride and padded channels; 16-channel output tiles
     int ldy, yoff, cout, relu;
     int n, D, H, W;
 };
@@ -53,120 +53,300 @@ __device__ inline uint4 apply_gate(uint4 t, const uint4 g) {
     return make_uint4(tw[0], tw[1], tw[2], tw[3]);
 }
 
-// 3x3x3 convolution as an implicit GEMM with the input staged in LDS.  A block owns an
-// output tile of 16 (x) x 4 (y) x 4 (z) voxels of one sample; the input tile with its
-// one-voxel halo (18 x 6 x 6 voxels) is staged once per chunk of up to 32 input channels
-// (voxel stride padded by 8 channels against bank conflicts; every global load of a
-// thread is issued before its LDS writes), and all 27 taps read it from LDS.  Wave w
-// computes rows (y, z) 4w..4w+3 of the tile (four 16-voxel M tiles) for every
-// 16-channel N tile; K runs over tap x channel with k = tap * C + c inside a chunk of C
-// channels (C = 16: one 32-wide step covers two taps).
+// 3x3x3 convolution as an implicit GEMM with the input and the weights staged in LDS.
+// Work items are (voxel tile, output-tile group) pairs: a voxel tile is 16 (x) x 4 (y) x
+// 4 (z) voxels of one sample, a group NTB of the GEMM's NT 16-channel output tiles.
+// Blocks are persistent: block b takes items b, b + G, b + 2G, ... (G = grid size; with
+// G a multiple of NT / NTB a block keeps one output-tile group).  Per item and chunk of
+// 32 input channels (a last chunk of 16 when the padded channel count is an odd multiple
+// of 16), the input tile with its one-voxel halo (18 x 6 x 6 voxels) and the chunk's
+// weights are staged in LDS, and all 27 taps read them from there; the global loads of
+// the next (item, chunk) are issued before the MFMAs of the current one, and weights
+// that do not change between items (one chunk, same output-tile group) are staged once.  Wave w computes rows
+// (y, z) 4w..4w+3 of the tile (four 16-voxel M tiles).  K runs over tap x channel: a
+// 32-channel chunk takes one tap per 32-wide MFMA step (lane group g = lane / 16 holds
+// channels 8g..8g+7); a 16-channel chunk takes two taps per step, taps 2s and 2s+1 in
+// lane halves h = g / 2 (channels 8 (g mod 2) ..), and its 14th step pairs tap 26 with
+// zero weights.  The taps are unrolled at compile time, so every LDS read is a per-lane
+// base plus an immediate.
+//
+// Packed weights (k_pack): one 16-byte B fragment per (step, output tile, lane), steps
+// numbered over the chunks in order; the fragment of lane (n = lane mod 16, g) holds the
+// 8 input channels of g at the step's tap for output channel 16 t + n, so a block's
+// weights for one step are NTB contiguous kilobytes.
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 constexpr int kHV = kHX * kHY * kHZ;
-constexpr int kCS = 40;   // LDS channel stride per voxel (32 + 8 padding), BF16 units
 
-template <int NT>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
-    __shared__ uint4 xs[kHV * kCS / 8];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+// halo-tile voxel offset of tap t = 9 dz + 3 dy + dx (dz, dy, dx in 0..2)
+__host__ __device__ constexpr int tap_vox(int t) { return ((t / 9) * kHY + (t / 3) % 3) * kHX + t % 3; }
+
+// the second tap of each pair of a 16-channel chunk lies 1, 16 or 70 halo voxels past
+// the first (a step along x, to the next y row, or to the next z plane)
+__host__ __device__ constexpr bool tap_pairs_known() {
+    for (int s = 0; s < 13; ++s) {
+        const int d = tap_vox(2 * s + 1) - tap_vox(2 * s);
+        if (d != 1 && d != 16 && d != 70) return false;
+    }
+    return true;
+}
+static_assert(tap_pairs_known(), "tap pair shifts of the 16-channel chunk");
+
+// LDS of one block: the halo tile at a channel stride of CS BF16 values per voxel, then
+// the weights of one chunk (27 steps for CS = 40, which holds 32-channel chunks; 14 for
+// CS = 24, which holds one 16-channel chunk) for NTB output tiles
+__host__ __device__ constexpr int conv_x_bytes(int cs) { return kHV * cs * 2; }
+__host__ __device__ constexpr int conv_lds_bytes(int cs, int ntb) {
+    return conv_x_bytes(cs) + (cs >= 40 ? 27 : 14) * ntb * 1024;
+}
+
+// Origin of a voxel tile (tile index: x fastest, then y, z, sample).
+struct ConvTile {
+    int x0, y0, z0;
+    long long sbase;
+};
+__device__ inline ConvTile conv_tile(const ConvArgs& a, long long tile) {
     const int ntx = (a.W + kTX - 1) / kTX, nty = (a.H + kTY - 1) / kTY, ntz = (a.D + kTZ - 1) / kTZ;
-    int bid = blockIdx.x;
-    const int tx = bid % ntx;
-    bid /= ntx;
-    const int ty = bid % nty;
-    bid /= nty;
-    const int tz = bid % ntz;
-    const int sb = bid / ntz;
-    const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
-    const long long sbase = (long long)sb * a.D * a.H * a.W;
-    f32x4 acc[4][NT];
+    ConvTile t;
+    t.x0 = (int)(tile % ntx) * kTX;
+    tile /= ntx;
+    t.y0 = (int)(tile % nty) * kTY;
+    tile /= nty;
+    t.z0 = (int)(tile % ntz) * kTZ;
+    t.sbase = (tile / ntz) * a.D * a.H * a.W;
+    return t;
+}
+
+// Prefetch registers of one (item, chunk): the halo tile's channels (and ReLU gates when
+// GATED), sized for the widest chunk the kernel stages, and the chunk's weights when
+// they change with the chunk (CS = 40).
+template <int NTB, int CS, bool GATED>
+struct ConvRegs {
+    static constexpr bool kW = CS >= 40;
+    static constexpr int SM = (kHV * (CS >= 40 ? 4 : 2) + 255) / 256;
+    static constexpr int SW = kW ? (27 * NTB * 64 + 255) / 256 : 1;
+    uint4 x[SM], g[GATED ? SM : 1], w[SW];
+};
+
+// Global loads of the chunk's weights (packed steps [sb, sb + S), output tiles
+// [tb, tb + NTB)) into w, and their LDS writes.
+template <int NTB, int CC>
+__device__ inline void conv_fetch_w(const ConvArgs& a, int sb, int tb, uint4* w) {
+    constexpr int EW = (CC == 32 ? 27 : 14) * NTB * 64;
+    constexpr int SW = (EW + 255) / 256;
+    const uint4* wsrc = reinterpret_cast<const uint4*>(a.w);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int kg = 8 * (lane >> 4);
-    for (int cb = 0; cb < a.cin_p; cb += 32) {
-        const int C = a.cin_p - cb < 32 ? a.cin_p - cb : 32;
-        const int G = C / 8;
-        constexpr int SM = (kHV * 4 + 255) / 256;
-        uint4 st[SM], sg[SM];
-        int sidx[SM];
-#pragma unroll
-        for (int i = 0; i < SM; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            st[i] = make_uint4(0, 0, 0, 0);
-            sg[i] = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);   // BF16 1.0 (gate open)
-            sidx[i] = -1;
-            if (e < kHV * G) {
-                const int v = e / G, g = e - v * G;
-                const int hx = v % kHX, hy = (v / kHX) % kHY, hz = v / (kHX * kHY);
-                const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
-                sidx[i] = v * (kCS / 8) + g;
-                if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
-                    const long long q = sbase + ((long long)z * a.H + y) * a.W + x;
-                    st[i] = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + cb + 8 * g);
-                    if (a.gate) sg[i] = *reinterpret_cast<const uint4*>(a.gate + q * a.ldx + cb + 8 * g);
-                }
-            }
+    for (int i = 0; i < SW; ++i) {
+        const int e = threadIdx.x + 256 * i;   // (step, tile, lane) of the block's slice
+        w[i] = make_uint4(0, 0, 0, 0);
+        if (e < EW) {
+            const int s = e / (NTB * 64), q = e - s * (NTB * 64);
+            w[i] = wsrc[((long long)(sb + s) * a.nt + tb) * 64 + q];
         }
-        __syncthreads();
+    }
+}
+template <int NTB, int CC, int CS>
+__device__ inline void conv_store_w(char* xs, const uint4* w) {
+    constexpr int EW = (CC == 32 ? 27 : 14) * NTB * 64;
+    constexpr int SW = (EW + 255) / 256;
+    uint4* wl = reinterpret_cast<uint4*>(xs + conv_x_bytes(CS));
 #pragma unroll
-        for (int i = 0; i < SM; ++i)
-            if (sidx[i] >= 0) xs[sidx[i]] = a.gate ? apply_gate(st[i], sg[i]) : st[i];
-        __syncthreads();
-        const int KC = 27 * C;
-        for (int kk = 0; kk < KC; kk += 32) {
-            const int kl = kk + kg;
-            const int tap = kl / C, c0 = kl - tap * C;
-            const bool tin = tap < 27;
-            bf16x8 bfr[NT];
+    for (int i = 0; i < SW; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        if (e < EW) wl[e] = w[i];
+    }
+}
+
+// Global loads of channels [cb, cb + CC) of tile t (and, for CS = 40, of the chunk's
+// weights).
+template <int NTB, int CC, int CS, bool GATED>
+__device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, int sb, int tb,
+                                  ConvRegs<NTB, CS, GATED>& r) {
+    constexpr int G = CC / 8;
+    constexpr int E = kHV * G;
+    constexpr int SM = (E + 255) / 256;
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                uint4 t = make_uint4(0, 0, 0, 0);
-                if (tin)
-                    t = *reinterpret_cast<const uint4*>(a.w + (long long)(nt * 16 + (lane & 15)) * a.kp +
-                                                        tap * a.cin_p + cb + c0);
-                bfr[nt] = __builtin_bit_cast(bf16x8, t);
-            }
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo offsets 0..2
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int r = 4 * wave + mt;
-                const int yy = r % kTY, zz = r / kTY;
-                const int hv = ((zz + dz) * kHY + (yy + dy)) * kHX + (lane & 15) + dx;
-                uint4 t = make_uint4(0, 0, 0, 0);
-                if (tin) t = xs[hv * (kCS / 8) + c0 / 8];
-                const bf16x8 af = __builtin_bit_cast(bf16x8, t);
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[nt], acc[mt][nt], 0, 0, 0);
+    for (int i = 0; i < SM; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        r.x[i] = make_uint4(0, 0, 0, 0);
+        if (GATED) r.g[i] = make_uint4(0, 0, 0, 0);
+        if (e < E) {
+            const int v = e / G, gi = e - v * G;
+            const int x = t.x0 - 1 + v % kHX, y = t.y0 - 1 + (v / kHX) % kHY, z = t.z0 - 1 + v / (kHX * kHY);
+            if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
+                const long long q = t.sbase + ((long long)z * a.H + y) * a.W + x;
+                r.x[i] = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + cb + 8 * gi);
+                if (GATED) r.g[i] = *reinterpret_cast<const uint4*>(a.gate + q * a.ldx + cb + 8 * gi);
             }
         }
     }
-    // D layout: lane holds rows 4 * (lane / 16) + i (voxels x0 + row), column lane % 16
+    if (ConvRegs<NTB, CS, GATED>::kW) conv_fetch_w<NTB, CC>(a, sb, tb, r.w);
+}
+
+// LDS writes of a fetched (item, chunk); the caller brackets them with barriers.
+template <int NTB, int CC, int CS, bool GATED>
+__device__ inline void conv_store(char* xs, const ConvRegs<NTB, CS, GATED>& r) {
+    constexpr int G = CC / 8;
+    constexpr int E = kHV * G;
+    constexpr int SM = (E + 255) / 256;
+#pragma unroll
+    for (int i = 0; i < SM; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        if (e < E) {
+            const int v = e / G, gi = e - v * G;
+            *reinterpret_cast<uint4*>(xs + (v * CS + 8 * gi) * 2) = GATED ? apply_gate(r.x[i], r.g[i]) : r.x[i];
+        }
+    }
+    if (ConvRegs<NTB, CS, GATED>::kW) conv_store_w<NTB, CC, CS>(xs, r.w);
+}
+
+// One chunk of CC input channels: S MFMA steps over the 27 taps.  abase[mt] is the LDS
+// byte address of the lane's voxel (tap 0, channel 0) in M tile mt.
+template <int NTB, int CC, int CS>
+__device__ inline void conv_chunk(const char* xs, const uint32_t (&abase)[4], f32x4 (&acc)[4][NTB]) {
+    constexpr int S = CC == 32 ? 27 : 14;
+    constexpr int VB = CS * 2;   // LDS bytes per halo voxel
+    const int lane = threadIdx.x & 63, g = lane >> 4;
+    const int h = CC == 32 ? 0 : g >> 1;            // lane half: second tap of a pair
+    const int cl = CC == 32 ? 8 * g : 8 * (g & 1);  // first channel of the lane's 8
+    uint32_t al[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) al[mt] = abase[mt] + 2 * cl;
+    // A address shift of the lane half that takes the second tap of a pair, by pair kind
+    uint32_t dsh[3] = {0, 0, 0};
+    if (CC == 16) {
+        dsh[0] = h ? 1 * VB : 0;
+        dsh[1] = h ? 16 * VB : 0;
+        dsh[2] = h ? 70 * VB : 0;
+    }
+    const char* wl = xs + conv_x_bytes(CS) + 16 * lane;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        bf16x8 b[NTB];
+#pragma unroll
+        for (int nt = 0; nt < NTB; ++nt)
+            b[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wl + (s * NTB + nt) * 1024));
+        // immediate LDS offset of the step's (first) tap and the pair's shift kind
+        const int t0 = CC == 32 ? s : 2 * s;
+        const uint32_t imm = (uint32_t)tap_vox(t0) * VB;
+        int kind = 3;
+        if (CC == 16 && s < 13) {
+            const int d = tap_vox(t0 + 1) - tap_vox(t0);
+            kind = d == 1 ? 0 : d == 16 ? 1 : 2;
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const uint32_t ad = al[mt] + (kind < 3 ? dsh[kind] : 0u) + imm;
+            const bf16x8 af = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(xs + ad));
+#pragma unroll
+            for (int nt = 0; nt < NTB; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+}
+
+// CS: LDS channel stride per halo voxel in BF16 values, 24 when the padded input has
+// 16 channels (one 16-channel chunk), else 40 (32-channel chunks); both strides spread
+// the 16 voxels of an A fragment over distinct banks.  GATED: the input is multiplied by
+// (gate > 0) (ReLU backward).  For CS = 24 the grid size must be a multiple of NT / NTB:
+// the block's weights are staged once.
+template <int NTB, int CS, bool GATED>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+    extern __shared__ uint4 xs_dyn[];
+    char* xs = reinterpret_cast<char*>(xs_dyn);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nsplit = a.nt / NTB;
+    const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
+    const long long nitems = tiles * nsplit;
+    const int nchunk = CS >= 40 ? (a.cin_p + 31) / 32 : 1;
+    long long item = blockIdx.x;
+    if (item >= nitems) return;
+    uint32_t abase[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         const int r = 4 * wave + mt;
-        const int y = y0 + r % kTY, z = z0 + r / kTY;
-        if (y >= a.H || z >= a.D) continue;
+        abase[mt] = (uint32_t)((((r / kTY) * kHY + r % kTY) * kHX + (lane & 15)) * CS * 2);
+    }
+    f32x4 acc[4][NTB];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int co = nt * 16 + (lane & 15);
-            if (co >= a.cout) continue;
-            const float bv = a.bias ? a.bias[co] : 0.f;
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = x0 + 4 * (lane >> 4) + i;
-                if (x >= a.W) continue;
-                const long long p = sbase + ((long long)z * a.H + y) * a.W + x;
-                float v = acc[mt][nt][i] + bv;
-                if (a.relu) v = fmaxf(v, 0.f);
-                if (a.y) a.y[p * a.ldy + a.yoff + co] = f2bf(v);
-                if (a.yf) a.yf[p * a.cout + co] = v;
+        for (int nt = 0; nt < NTB; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (CS < 40) {   // one chunk: the block's weights, read by every item after the first barrier
+        uint4 w[(14 * NTB * 64 + 255) / 256];
+        conv_fetch_w<NTB, 16>(a, 0, (int)(blockIdx.x % nsplit) * NTB, w);
+        conv_store_w<NTB, 16, CS>(xs, w);
+    }
+    ConvRegs<NTB, CS, GATED> regs;
+    // chunk c covers channels [32 c, ..) and packed steps [27 c, ..); it is 16 wide when
+    // fewer than 32 channels remain.  An item's output tiles start at (item mod nsplit) NTB.
+    int chunk = 0;
+    {
+        const ConvTile t = conv_tile(a, item / nsplit);
+        const int tb = (int)(item % nsplit) * NTB;
+        if (CS >= 40 && 32 <= a.cin_p)
+            conv_fetch<NTB, 32, CS, GATED>(a, t, 0, 0, tb, regs);
+        else
+            conv_fetch<NTB, 16, CS, GATED>(a, t, 0, 0, tb, regs);
+    }
+    for (;;) {
+        const bool wc = CS >= 40 && 32 * chunk + 32 <= a.cin_p;
+        __syncthreads();   // every wave is done with the previous chunk's LDS
+        if (wc)
+            conv_store<NTB, 32, CS, GATED>(xs, regs);
+        else
+            conv_store<NTB, 16, CS, GATED>(xs, regs);
+        __syncthreads();
+        long long nitem = item;
+        int nc = chunk + 1;
+        if (nc == nchunk) {
+            nc = 0;
+            nitem += gridDim.x;
+        }
+        const bool more = nitem < nitems;
+        if (more) {   // in flight during the MFMAs below
+            const ConvTile t = conv_tile(a, nitem / nsplit);
+            const int tb = (int)(nitem % nsplit) * NTB;
+            if (CS >= 40 && 32 * nc + 32 <= a.cin_p)
+                conv_fetch<NTB, 32, CS, GATED>(a, t, 32 * nc, 27 * nc, tb, regs);
+            else
+                conv_fetch<NTB, 16, CS, GATED>(a, t, 32 * nc, 27 * nc, tb, regs);
+        }
+        if (wc)
+            conv_chunk<NTB, 32, CS>(xs, abase, acc);
+        else
+            conv_chunk<NTB, 16, CS>(xs, abase, acc);
+        if (chunk == nchunk - 1) {
+            // D layout: lane holds rows 4 * (lane / 16) + i (voxels x0 + row), column lane % 16
+            const ConvTile t = conv_tile(a, item / nsplit);
+            const int tb = (int)(item % nsplit) * NTB;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int r = 4 * wave + mt;
+                const int y = t.y0 + r % kTY, z = t.z0 + r / kTY;
+#pragma unroll
+                for (int nt = 0; nt < NTB; ++nt) {
+                    const int co = (tb + nt) * 16 + (lane & 15);
+                    const float bv = a.bias && co < a.cout ? a.bias[co] : 0.f;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int x = t.x0 + 4 * (lane >> 4) + i;
+                        if (y < a.H && z < a.D && co < a.cout && x < a.W) {
+                            const long long p = t.sbase + ((long long)z * a.H + y) * a.W + x;
+                            float v = acc[mt][nt][i] + bv;
+                            if (a.relu) v = fmaxf(v, 0.f);
+                            if (a.y) a.y[p * a.ldy + a.yoff + co] = f2bf(v);
+                            if (a.yf) a.yf[p * a.cout + co] = v;
+                        }
+                    }
+                    acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
             }
         }
+        if (!more) break;
+        item = nitem;
+        chunk = nc;
     }
 }
 
@@ -557,26 +737,45 @@ __global__ void k_adam(float* th, const float* g, float* m, float* v, long long 
     th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// BF16 copies of one convolution's weights: forward [cout_p][kp] with k = tap * cin_p + c,
-// and input-gradient [cin_p][kpd] with k = tap * cout_p + o holding W[26 - tap][c][o].
-__global__ void k_pack(const float* W, int cin, int cout, int taps, int cin_p, int cout_p, int kp, int kpd,
+// The step of a packed convolution GEMM (ci_p padded input channels, a multiple of 16):
+// 27 steps per 32-channel chunk, then 14 for a last 16-channel chunk.  For lane group g
+// of step sg, returns the tap (27 for the zero half of the last pair) and the first of
+// the group's 8 input channels.
+__device__ inline void packed_step(int sg, int g, int ci_p, int& tap, int& c0) {
+    const int q = ci_p / 32;
+    if (sg < 27 * q) {
+        tap = sg % 27;
+        c0 = 32 * (sg / 27) + 8 * g;
+    } else {
+        const int s = sg - 27 * q;
+        tap = 2 * s + (g >> 1);
+        c0 = 32 * q + 8 * (g & 1);
+    }
+}
+
+// BF16 copies of one convolution's weights W[tap][cin][cout] in the fragment order of
+// k_conv (steps x output tiles x 64 lanes x 8 values): the forward GEMM (input channels
+// cin, output channels cout) into wf, and the input-gradient GEMM into wd, whose input
+// channels are the layer's outputs o and whose output channels are the layer's inputs c,
+// with the taps mirrored: wd(tap, o, c) = W[26 - tap][c][o].
+// nf, nd: packed values of the two GEMMs (steps x 512 x output tiles).
+__global__ void k_pack(const float* W, int cin, int cout, int cin_p, int cout_p, long long nf, long long nd,
                        uint16_t* wf, uint16_t* wd) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long nf = (long long)cout_p * kp, nd = (long long)cin_p * kpd;
-    if (i < nf) {
-        const int o = (int)(i / kp), k = (int)(i % kp);
-        const int tap = k / cin_p, c = k % cin_p;
-        float v = 0.f;
-        if (o < cout && tap < taps && c < cin) v = W[((long long)tap * cin + c) * cout + o];
-        wf[i] = f2bf(v);
-    } else if (i < nf + nd && wd) {
-        const long long j = i - nf;
-        const int c = (int)(j / kpd), k = (int)(j % kpd);
-        const int tap = k / cout_p, o = k % cout_p;
-        float v = 0.f;
-        if (c < cin && tap < taps && o < cout) v = W[((long long)(taps - 1 - tap) * cin + c) * cout + o];
-        wd[j] = f2bf(v);
-    }
+    const bool fwd = i < nf;
+    if (!fwd && (i >= nf + nd || !wd)) return;
+    const long long k = fwd ? i : i - nf;
+    const int gi = fwd ? cin : cout, go = fwd ? cout : cin;           // GEMM input / output channels
+    const int gip = fwd ? cin_p : cout_p, nt = (fwd ? cout_p : cin_p) / 16;
+    const int j = (int)(k % 8), lane = (int)((k / 8) % 64), t = (int)((k / 512) % nt);
+    const int sg = (int)(k / (512LL * nt));
+    int tap, c0;
+    packed_step(sg, lane >> 4, gip, tap, c0);
+    const int ci = c0 + j, co = 16 * t + (lane & 15);
+    float v = 0.f;
+    if (tap < 27 && ci < gi && co < go)
+        v = fwd ? W[((long long)tap * cin + ci) * cout + co] : W[((long long)(26 - tap) * cin + co) * cout + ci];
+    (fwd ? wf : wd)[k] = f2bf(v);
 }
 
 // Copy an input with 'c' channels into a zero-padded buffer with 'cp' channels (cp a

@@ -111,15 +111,18 @@ def test_forward_backward_match_oracle(widths, shape):
     assert _rel(outg, plain) <= 3e-2
 
 
-@pytest.mark.parametrize("li,shape", [(0, (2, 8, 8, 16)), (1, (1, 8, 6, 16)), (2, (1, 4, 4, 8)),
-                                      (4, (2, 8, 8, 8))])
-def test_single_layer_kernels_exact(li, shape):
+@pytest.mark.parametrize("widths,li,shape", [([16, 32], 0, (2, 8, 8, 16)), ([16, 32], 1, (1, 8, 6, 16)),
+                                             ([16, 32], 2, (1, 4, 4, 8)), ([16, 32], 4, (2, 8, 8, 8)),
+                                             ([16, 32], 3, (1, 5, 9, 35)),
+                                             ([16, 32, 64, 64], 4, (1, 6, 7, 20)),
+                                             ([16, 32, 64, 64], 8, (1, 8, 8, 16)),
+                                             ([16, 32, 64, 64], 10, (2, 4, 5, 17))])
+def test_single_layer_kernels_exact(widths, li, shape):
     """Forward, input-gradient and weight-gradient kernels of one layer on small-integer
     data, for which FP32 accumulation is exact: the GPU must equal the FP64 oracle
     bit for bit (catches any index, tap or layout error)."""
     torch = require_gpu()
     from paper_2505_03067_amd import Net
-    widths = [16, 32]
     net = Net(13, 3, widths, seed=3)
     rng = np.random.default_rng(li)
     P = net.count
