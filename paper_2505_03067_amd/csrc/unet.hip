@@ -231,6 +231,14 @@ static ConvArgs conv_args(const Net* n, int lvl) {
 
 static unsigned blocks_for(long long count) { return (unsigned)((count + 255) / 256); }
 
+// Whether the first convolution of decoder level lvl (layer li) stages the upsampled
+// deeper output and the skip directly, without the concatenated buffer: the upsampled
+// channels must fill whole 32-channel chunks and the concatenation needs no padding.
+static bool fused_upcat(const Net* n, int li, int lvl) {
+    const int cu = n->widths[lvl + 1], cs = n->widths[lvl];
+    return cu % 32 == 0 && n->layers[li].cin_p == cu + cs;
+}
+
 int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out) {
     const int L = n->L;
     const int div = 1 << (L - 1);
@@ -274,15 +282,23 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
     for (int lvl = L - 2; lvl >= 0; --lvl) {
         const long long Pl = P0 >> (3 * lvl);
         const int cu = n->widths[lvl + 1], cs = n->widths[lvl];
-        k_up2_cat<<<blocks_for(Pl * (cu + cs) / 8), 256, 0, st>>>(h, cu, n->act[2 * lvl + 1], cs, nb, D >> lvl, H >> lvl,
-                                                               W >> lvl, n->cat[lvl]);
-        h = n->cat[lvl];
-        hch = cu + cs;
+        const bool fuse = fused_upcat(n, li, lvl);
+        if (!fuse) {
+            k_up2_cat<<<blocks_for(Pl * (cu + cs) / 8), 256, 0, st>>>(h, cu, n->act[2 * lvl + 1], cs, nb, D >> lvl,
+                                                                   H >> lvl, W >> lvl, n->cat[lvl]);
+            h = n->cat[lvl];
+            hch = cu + cs;
+        }
         for (int r = 0; r < 2; ++r, ++li) {
             const ConvL& c = n->layers[li];
             ConvArgs a = conv_args(n, lvl);
             a.x = h;
             a.ldx = hch;
+            if (r == 0 && fuse) {   // the convolution reads the upsampled input and the skip itself
+                a.x2 = n->act[2 * lvl + 1];
+                a.ldx2 = cs;
+                a.c1 = cu;
+            }
             a.cin_p = c.cin_p;
             a.w = c.wf;
             a.bias = n->theta + c.boff;
@@ -418,7 +434,13 @@ int net_backward(Net* n, const float* dout) {
         if ((rc = conv_input_grad(n, li, lvl, g, n->act[li], n->gin[li - 1]))) return rc;
         g = n->gin[li - 1];
         --li;
-        // first conv of the level: input the concat buffer
+        // first conv of the level: input the concat buffer (built here if the forward
+        // pass read the upsampled input and the skip directly)
+        if (fused_upcat(n, li, lvl)) {
+            const long long Pl = P0 >> (3 * lvl);
+            k_up2_cat<<<blocks_for(Pl * (cu + cs) / 8), 256, 0, st>>>(n->act[li - 1], cu, n->act[2 * lvl + 1], cs, nb,
+                                                                   D >> lvl, H >> lvl, W >> lvl, n->cat[lvl]);
+        }
         if ((rc = conv_param_grads(n, li, lvl, n->cat[lvl], cu + cs, g, n->act[li], n->grad + n->layers[li].woff, n->grad + n->layers[li].boff))) return rc;
         if ((rc = conv_input_grad(n, li, lvl, g, n->act[li], n->dcat[lvl]))) return rc;
         --li;

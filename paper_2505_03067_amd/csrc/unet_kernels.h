@@ -35,6 +35,11 @@ struct ConvArgs {
     uint16_t* y;           // output [P][ldy], channels [yoff, yoff + cout)
     float* yf;             // optional FP32 output [P][cout]
     int ldx, cin_p, nt;    // input stride and padded channels; 16-channel output tiles
+    // optional upsample-and-concatenate input: channels [0, c1) are x on the grid of half
+    // the resolution (nearest upsampling, stride ldx = c1), channels [c1, cin_p) are x2
+    // (stride ldx2); c1 a multiple of 32, never with a gate
+    const uint16_t* x2;
+    int ldx2, c1;
     int ldy, yoff, cout, relu;
     int n, D, H, W;
 };
@@ -175,7 +180,14 @@ __device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, 
             const int x = t.x0 - 1 + v % kHX, y = t.y0 - 1 + (v / kHX) % kHY, z = t.z0 - 1 + v / (kHX * kHY);
             if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
                 const long long q = t.sbase + ((long long)z * a.H + y) * a.W + x;
-                r.x[i] = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + cb + 8 * gi);
+                if (!GATED && a.x2 && cb < a.c1) {   // upsampled half-resolution input
+                    const long long qc = t.sbase / 8 + ((long long)(z >> 1) * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1);
+                    r.x[i] = *reinterpret_cast<const uint4*>(a.x + qc * a.ldx + cb + 8 * gi);
+                } else if (!GATED && a.x2) {          // concatenated skip input
+                    r.x[i] = *reinterpret_cast<const uint4*>(a.x2 + q * a.ldx2 + cb - a.c1 + 8 * gi);
+                } else {
+                    r.x[i] = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + cb + 8 * gi);
+                }
                 if (GATED) r.g[i] = *reinterpret_cast<const uint4*>(a.gate + q * a.ldx + cb + 8 * gi);
             }
         }
