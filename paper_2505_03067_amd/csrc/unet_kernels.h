@@ -2,13 +2,12 @@
 //
 // Activations are NDHWC [n][z][y][x][c] in BF16.  3x3x3 convolutions are implicit
 // GEMMs on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16): M = output voxels,
-// N = output channels, K = 27 taps x input channels, with the tap/channel index
-// k = tap * Cin_p + c (Cin_p a multiple of 8, so the 8 consecutive k of one lane
-// always belong to one tap).  The input gradient is the same GEMM on the output
-// gradient with the taps mirrored and the weights transposed; the weight gradient
-// stages voxel chunks in LDS, transposed so that K runs over voxels.  For the input
-// gradient, dX[p] = sum_t dY[p - off(t)] W[t] = sum_t dY[p + off(t)] W[26 - t], so the
-// same forward kernel runs on packed weights holding W[26 - t] transposed.
+// N = output channels, K = 27 taps x input channels (padded to a multiple of 16), taken
+// in 32-wide steps whose 8 consecutive k of one lane always belong to one tap.  The
+// input gradient is the same GEMM on the output gradient with the taps mirrored and the
+// weights transposed: dX[p] = sum_t dY[p - off(t)] W[t] = sum_t dY[p + off(t)] W[26 - t],
+// so the forward kernel runs on packed weights holding W[26 - t] transposed.  The weight
+// gradient stages voxel chunks in LDS, transposed so that K runs over voxels.
 #pragma once
 
 #include <hip/hip_runtime.h>
