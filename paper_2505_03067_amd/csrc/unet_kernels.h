@@ -60,13 +60,13 @@ __device__ inline uint4 apply_gate(uint4 t, const uint4 g) {
 // 3x3x3 convolution as an implicit GEMM with the input and the weights staged in LDS.
 // Work items are (voxel tile, output-tile group) pairs: a voxel tile is 16 (x) x 4 (y) x
 // 4 (z) voxels of one sample, a group NTB of the GEMM's NT 16-channel output tiles.
-// Blocks are persistent: block b takes items b, b + G, b + 2G, ... (G = grid size; with
-// G a multiple of NT / NTB a block keeps one output-tile group).  Per item and chunk of
+// Blocks are persistent: block b takes items b, b + G, b + 2G, ... (G = grid size, a
+// multiple of NT / NTB, so a block keeps one output-tile group).  Per item and chunk of
 // 32 input channels (a last chunk of 16 when the padded channel count is an odd multiple
 // of 16), the input tile with its one-voxel halo (18 x 6 x 6 voxels) and the chunk's
 // weights are staged in LDS, and all 27 taps read them from there; the global loads of
 // the next (item, chunk) are issued before the MFMAs of the current one, and weights
-// that do not change between items (one chunk, same output-tile group) are staged once.  Wave w computes rows
+// that do not change between items (one chunk) are staged once.  Wave w computes rows
 // (y, z) 4w..4w+3 of the tile (four 16-voxel M tiles).  K runs over tap x channel: a
 // 32-channel chunk takes one tap per 32-wide MFMA step (lane group g = lane / 16 holds
 // channels 8g..8g+7); a 16-channel chunk takes two taps per step, taps 2s and 2s+1 in
@@ -259,8 +259,10 @@ __device__ inline void conv_chunk(const char* xs, const uint32_t (&abase)[4], f3
 // CS: LDS channel stride per halo voxel in BF16 values, 24 when the padded input has
 // 16 channels (one 16-channel chunk), else 40 (32-channel chunks); both strides spread
 // the 16 voxels of an A fragment over distinct banks.  GATED: the input is multiplied by
-// (gate > 0) (ReLU backward).  For CS = 24 the grid size must be a multiple of NT / NTB:
-// the block's weights are staged once.
+// (gate > 0) (ReLU backward).  The grid size must be a multiple of NT / NTB: a block
+// keeps one output-tile group (its bias is read once, and for CS = 24 its weights are
+// staged once), and its epilogue issues no loads, so the wait for the next item's
+// prefetched input does not also wait for the stores of this one.
 template <int NTB, int CS, bool GATED>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     extern __shared__ uint4 xs_dyn[];
@@ -271,8 +273,15 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
     const long long nitems = tiles * nsplit;
     const int nchunk = CS >= 40 ? (a.cin_p + 31) / 32 : 1;
+    const int tb = (int)(blockIdx.x % nsplit) * NTB;   // the block's first output tile
     long long item = blockIdx.x;
     if (item >= nitems) return;
+    float bias[NTB];
+#pragma unroll
+    for (int nt = 0; nt < NTB; ++nt) {
+        const int co = (tb + nt) * 16 + (lane & 15);
+        bias[nt] = a.bias && co < a.cout ? a.bias[co] : 0.f;
+    }
     uint32_t abase[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
@@ -286,16 +295,15 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         for (int nt = 0; nt < NTB; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (CS < 40) {   // one chunk: the block's weights, read by every item after the first barrier
         uint4 w[(14 * NTB * 64 + 255) / 256];
-        conv_fetch_w<NTB, 16>(a, 0, (int)(blockIdx.x % nsplit) * NTB, w);
+        conv_fetch_w<NTB, 16>(a, 0, tb, w);
         conv_store_w<NTB, 16, CS>(xs, w);
     }
     ConvRegs<NTB, CS, GATED> regs;
     // chunk c covers channels [32 c, ..) and packed steps [27 c, ..); it is 16 wide when
-    // fewer than 32 channels remain.  An item's output tiles start at (item mod nsplit) NTB.
+    // fewer than 32 channels remain.  Item i holds voxel tile i / nsplit.
     int chunk = 0;
     {
         const ConvTile t = conv_tile(a, item / nsplit);
-        const int tb = (int)(item % nsplit) * NTB;
         if (CS >= 40 && 32 <= a.cin_p)
             conv_fetch<NTB, 32, CS, GATED>(a, t, 0, 0, tb, regs);
         else
@@ -318,7 +326,6 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         const bool more = nitem < nitems;
         if (more) {   // in flight during the MFMAs below
             const ConvTile t = conv_tile(a, nitem / nsplit);
-            const int tb = (int)(nitem % nsplit) * NTB;
             if (CS >= 40 && 32 * nc + 32 <= a.cin_p)
                 conv_fetch<NTB, 32, CS, GATED>(a, t, 32 * nc, 27 * nc, tb, regs);
             else
@@ -331,7 +338,6 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         if (chunk == nchunk - 1) {
             // D layout: lane holds rows 4 * (lane / 16) + i (voxels x0 + row), column lane % 16
             const ConvTile t = conv_tile(a, item / nsplit);
-            const int tb = (int)(item % nsplit) * NTB;
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const int r = 4 * wave + mt;
@@ -339,13 +345,12 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 #pragma unroll
                 for (int nt = 0; nt < NTB; ++nt) {
                     const int co = (tb + nt) * 16 + (lane & 15);
-                    const float bv = a.bias && co < a.cout ? a.bias[co] : 0.f;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int x = t.x0 + 4 * (lane >> 4) + i;
                         if (y < a.H && z < a.D && co < a.cout && x < a.W) {
                             const long long p = t.sbase + ((long long)z * a.H + y) * a.W + x;
-                            float v = acc[mt][nt][i] + bv;
+                            float v = acc[mt][nt][i] + bias[nt];
                             if (a.relu) v = fmaxf(v, 0.f);
                             if (a.y) a.y[p * a.ldy + a.yoff + co] = f2bf(v);
                             if (a.yf) a.yf[p * a.cout + co] = v;
