@@ -30,8 +30,8 @@ int net_build(Net* n, int in_ch, int out_ch, int levels, const int* widths, uint
         l.taps = taps;
         l.cin_p = roundup(cin, 16);
         l.cout_p = roundup(cout, 16);
-        l.kp = roundup(taps * l.cin_p, 32);
-        l.kpd = roundup(taps * l.cout_p, 32);
+        l.kp = 2 * kSteps * l.cin_p;    // 14 steps of 32 per 16 input channels
+        l.kpd = 2 * kSteps * l.cout_p;
         l.woff = n->nparam;
         n->nparam += (size_t)taps * cin * cout;
         l.boff = n->nparam;
@@ -172,12 +172,12 @@ static int ensure_acts(Net* n, int nb, int D, int H, int W) {
     return MPM_OK;
 }
 
-// Launch k_conv<NTB, CS, GATED> over all (voxel tile, output-tile group) items: one persistent
-// block per LDS slot of the device (capped at the item count, rounded down to a multiple
-// of the group count).  The LDS (up to 78 KB) is granted once per kernel and process.
-template <int NTB, int CS, bool GATED>
+// Launch k_conv<NTB, WL, GATED> over all (voxel tile, output-tile group) items: one
+// persistent block per LDS slot of the device (capped at the item count, rounded down to
+// a multiple of the group count).
+template <int NTB, bool WL, bool GATED>
 static int launch_conv(const ConvArgs& a, hipStream_t st) {
-    constexpr int lds = conv_lds_bytes(CS, NTB);
+    constexpr int lds = conv_lds_bytes(NTB);
     static int slots = 0;   // resident blocks of the device, limited by LDS
     static const hipError_t granted = [] {
         int dev = 0, cap = 0, cus = 0, per_cu = 0;
@@ -187,7 +187,7 @@ static int launch_conv(const ConvArgs& a, hipStream_t st) {
         if (e == hipSuccess) e = hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
         if (e == hipSuccess && cap < lds) e = hipErrorInvalidValue;
         if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, CS, GATED>),
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, WL, GATED>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         slots = std::max(1, cus) * std::max(1, per_cu / lds);
         return e;
@@ -198,26 +198,27 @@ static int launch_conv(const ConvArgs& a, hipStream_t st) {
     const long long items = tiles * nsplit;
     long long grid = std::min<long long>(items, slots);
     grid = std::max<long long>(nsplit, grid / nsplit * nsplit);
-    k_conv<NTB, CS, GATED><<<(unsigned)grid, 256, lds, st>>>(a);
+    k_conv<NTB, WL, GATED><<<(unsigned)grid, 256, lds, st>>>(a);
     return MPM_OK;
 }
 
 // Output tiles per block: two for a 16-channel input with an even tile count (each A
 // fragment read from LDS then feeds two MFMAs, and the block's 58 KB of LDS still lets
-// two blocks share a CU), else one (with 32-channel chunks, two tiles per block would
-// take 105 KB of LDS and leave one block per CU, measured slower at every level).
+// two blocks share a CU), else one (44 KB, three blocks per CU; measured faster for the
+// wider inputs, whose weights are staged again for every chunk).
 static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
-    if (nt < 1 || nt > 8 || a.cin_p % 16 || a.cin_p < 16) {
+    if (nt < 1 || nt > 8 || a.cin_p % 16 || a.cin_p < 16 || (a.x2 && (a.gate || a.c1 % 16))) {
         set_error("unsupported channel count in the U-Net");
         return MPM_EINVAL;
     }
     a.nt = nt;
+    const bool one = a.cin_p == 16;
     if (a.gate) {
-        if (a.cin_p == 16) return nt % 2 ? launch_conv<1, 24, true>(a, st) : launch_conv<2, 24, true>(a, st);
-        return launch_conv<1, 40, true>(a, st);
+        if (one) return nt % 2 ? launch_conv<1, false, true>(a, st) : launch_conv<2, false, true>(a, st);
+        return launch_conv<1, true, true>(a, st);
     }
-    if (a.cin_p == 16) return nt % 2 ? launch_conv<1, 24, false>(a, st) : launch_conv<2, 24, false>(a, st);
-    return launch_conv<1, 40, false>(a, st);
+    if (one) return nt % 2 ? launch_conv<1, false, false>(a, st) : launch_conv<2, false, false>(a, st);
+    return launch_conv<1, true, false>(a, st);
 }
 
 static ConvArgs conv_args(const Net* n, int lvl) {
@@ -230,14 +231,6 @@ static ConvArgs conv_args(const Net* n, int lvl) {
 }
 
 static unsigned blocks_for(long long count) { return (unsigned)((count + 255) / 256); }
-
-// Whether the first convolution of decoder level lvl (layer li) stages the upsampled
-// deeper output and the skip directly, without the concatenated buffer: the upsampled
-// channels must fill whole 32-channel chunks and the concatenation needs no padding.
-static bool fused_upcat(const Net* n, int li, int lvl) {
-    const int cu = n->widths[lvl + 1], cs = n->widths[lvl];
-    return cu % 32 == 0 && n->layers[li].cin_p == cu + cs;
-}
 
 int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out) {
     const int L = n->L;
@@ -280,21 +273,14 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
         }
     }
     for (int lvl = L - 2; lvl >= 0; --lvl) {
-        const long long Pl = P0 >> (3 * lvl);
         const int cu = n->widths[lvl + 1], cs = n->widths[lvl];
-        const bool fuse = fused_upcat(n, li, lvl);
-        if (!fuse) {
-            k_up2_cat<<<blocks_for(Pl * (cu + cs) / 8), 256, 0, st>>>(h, cu, n->act[2 * lvl + 1], cs, nb, D >> lvl,
-                                                                   H >> lvl, W >> lvl, n->cat[lvl]);
-            h = n->cat[lvl];
-            hch = cu + cs;
-        }
         for (int r = 0; r < 2; ++r, ++li) {
             const ConvL& c = n->layers[li];
             ConvArgs a = conv_args(n, lvl);
             a.x = h;
             a.ldx = hch;
-            if (r == 0 && fuse) {   // the convolution reads the upsampled input and the skip itself
+            if (r == 0) {   // reads the upsampled input and the skip itself (widths are
+                            // multiples of 16: each 16-channel chunk has one source)
                 a.x2 = n->act[2 * lvl + 1];
                 a.ldx2 = cs;
                 a.c1 = cu;
@@ -434,9 +420,9 @@ int net_backward(Net* n, const float* dout) {
         if ((rc = conv_input_grad(n, li, lvl, g, n->act[li], n->gin[li - 1]))) return rc;
         g = n->gin[li - 1];
         --li;
-        // first conv of the level: input the concat buffer (built here if the forward
-        // pass read the upsampled input and the skip directly)
-        if (fused_upcat(n, li, lvl)) {
+        // first conv of the level: its input, the concatenation of the upsampled deeper
+        // output and the skip, which the forward pass read without writing it
+        {
             const long long Pl = P0 >> (3 * lvl);
             k_up2_cat<<<blocks_for(Pl * (cu + cs) / 8), 256, 0, st>>>(n->act[li - 1], cu, n->act[2 * lvl + 1], cs, nb,
                                                                    D >> lvl, H >> lvl, W >> lvl, n->cat[lvl]);

@@ -36,7 +36,7 @@ struct ConvArgs {
     int ldx, cin_p, nt;    // input stride and padded channels; 16-channel output tiles
     // optional upsample-and-concatenate input: channels [0, c1) are x on the grid of half
     // the resolution (nearest upsampling, stride ldx = c1), channels [c1, cin_p) are x2
-    // (stride ldx2); c1 a multiple of 32, never with a gate
+    // (stride ldx2); c1 a multiple of 16, never with a gate
     const uint16_t* x2;
     int ldx2, c1;
     int ldy, yoff, cout, relu;
@@ -62,31 +62,33 @@ __device__ inline uint4 apply_gate(uint4 t, const uint4 g) {
 // 4 (z) voxels of one sample, a group NTB of the GEMM's NT 16-channel output tiles.
 // Blocks are persistent: block b takes items b, b + G, b + 2G, ... (G = grid size, a
 // multiple of NT / NTB, so a block keeps one output-tile group).  Per item and chunk of
-// 32 input channels (a last chunk of 16 when the padded channel count is an odd multiple
-// of 16), the input tile with its one-voxel halo (18 x 6 x 6 voxels) and the chunk's
-// weights are staged in LDS, and all 27 taps read them from there; the global loads of
-// the next (item, chunk) are issued before the MFMAs of the current one, and weights
-// that do not change between items (one chunk) are staged once.  Wave w computes rows
-// (y, z) 4w..4w+3 of the tile (four 16-voxel M tiles).  K runs over tap x channel: a
-// 32-channel chunk takes one tap per 32-wide MFMA step (lane group g = lane / 16 holds
-// channels 8g..8g+7); a 16-channel chunk takes two taps per step, taps 2s and 2s+1 in
-// lane halves h = g / 2 (channels 8 (g mod 2) ..), and its 14th step pairs tap 26 with
-// zero weights.  The taps are unrolled at compile time, so every LDS read is a per-lane
-// base plus an immediate.
+// 16 input channels, the input tile with its one-voxel halo (18 x 6 x 6 voxels) and the
+// chunk's weights are staged in LDS, and all 27 taps read them from there; the global
+// loads of the next (item, chunk) are issued before the MFMAs of the current one, and
+// weights that do not change between items (one chunk) are staged once.  Wave w
+// computes rows (y, z) 4w..4w+3 of the tile (four 16-voxel M tiles).  K runs over tap x
+// channel in 14 MFMA steps of 32 per chunk: step s takes taps 2s and 2s+1 in the two
+// lane halves h = g / 2 (g = lane / 16; channels 8 (g mod 2) .. + 7 of the chunk), and
+// the 14th step pairs tap 26 with zero weights.  The taps are unrolled at compile time,
+// so every LDS read is a per-lane base plus an immediate.  (Chunks of 32 channels, one
+// tap per step, need 27 steps instead of 28 but 78 KB of LDS per block, two blocks per
+// CU instead of three, and measured slower.)
 //
 // Packed weights (k_pack): one 16-byte B fragment per (step, output tile, lane), steps
 // numbered over the chunks in order; the fragment of lane (n = lane mod 16, g) holds the
-// 8 input channels of g at the step's tap for output channel 16 t + n, so a block's
-// weights for one step are NTB contiguous kilobytes.
+// 8 input channels of g at its tap for output channel 16 t + n, so a block's weights for
+// one step are NTB contiguous kilobytes.
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 constexpr int kHV = kHX * kHY * kHZ;
+constexpr int kCS = 24;    // LDS channel stride per halo voxel (16 + 8), BF16 values
+constexpr int kSteps = 14; // MFMA steps per 16-channel chunk
 
 // halo-tile voxel offset of tap t = 9 dz + 3 dy + dx (dz, dy, dx in 0..2)
 __host__ __device__ constexpr int tap_vox(int t) { return ((t / 9) * kHY + (t / 3) % 3) * kHX + t % 3; }
 
-// the second tap of each pair of a 16-channel chunk lies 1, 16 or 70 halo voxels past
-// the first (a step along x, to the next y row, or to the next z plane)
+// the second tap of each pair lies 1, 16 or 70 halo voxels past the first (a step along
+// x, to the next y row, or to the next z plane)
 __host__ __device__ constexpr bool tap_pairs_known() {
     for (int s = 0; s < 13; ++s) {
         const int d = tap_vox(2 * s + 1) - tap_vox(2 * s);
@@ -94,15 +96,12 @@ __host__ __device__ constexpr bool tap_pairs_known() {
     }
     return true;
 }
-static_assert(tap_pairs_known(), "tap pair shifts of the 16-channel chunk");
+static_assert(tap_pairs_known(), "tap pair shifts");
 
-// LDS of one block: the halo tile at a channel stride of CS BF16 values per voxel, then
-// the weights of one chunk (27 steps for CS = 40, which holds 32-channel chunks; 14 for
-// CS = 24, which holds one 16-channel chunk) for NTB output tiles
-__host__ __device__ constexpr int conv_x_bytes(int cs) { return kHV * cs * 2; }
-__host__ __device__ constexpr int conv_lds_bytes(int cs, int ntb) {
-    return conv_x_bytes(cs) + (cs >= 40 ? 27 : 14) * ntb * 1024;
-}
+// LDS of one block: the halo tile (kCS values per voxel; the 48-byte stride spreads the
+// 16 voxels of an A fragment over distinct banks), then one chunk's weights
+__host__ __device__ constexpr int conv_x_bytes() { return kHV * kCS * 2; }
+__host__ __device__ constexpr int conv_lds_bytes(int ntb) { return conv_x_bytes() + kSteps * ntb * 1024; }
 
 // Origin of a voxel tile (tile index: x fastest, then y, z, sample).
 struct ConvTile {
@@ -121,61 +120,55 @@ __device__ inline ConvTile conv_tile(const ConvArgs& a, long long tile) {
     return t;
 }
 
-// Prefetch registers of one (item, chunk): the halo tile's channels (and ReLU gates when
-// GATED), sized for the widest chunk the kernel stages, and the chunk's weights when
-// they change with the chunk (CS = 40).
-template <int NTB, int CS, bool GATED>
-struct ConvRegs {
-    static constexpr bool kW = CS >= 40;
-    static constexpr int SM = (kHV * (CS >= 40 ? 4 : 2) + 255) / 256;
-    static constexpr int SW = kW ? (27 * NTB * 64 + 255) / 256 : 1;
-    uint4 x[SM], g[GATED ? SM : 1], w[SW];
+constexpr int kXM = (kHV * 2 + 255) / 256;   // 16-byte halo words per thread
+template <int NTB>
+struct ConvW {
+    static constexpr int E = kSteps * NTB * 64;   // 16-byte weight fragments per chunk
+    static constexpr int M = (E + 255) / 256;
 };
 
-// Global loads of the chunk's weights (packed steps [sb, sb + S), output tiles
+// Prefetch registers of one (item, chunk): the halo tile's 16 channels (and ReLU gates
+// when GATED), and the chunk's weights when they change with the chunk (WL).
+template <int NTB, bool WL, bool GATED>
+struct ConvRegs {
+    uint4 x[kXM], g[GATED ? kXM : 1], w[WL ? ConvW<NTB>::M : 1];
+};
+
+// Global loads of a chunk's weights (packed steps [sb, sb + 14), output tiles
 // [tb, tb + NTB)) into w, and their LDS writes.
-template <int NTB, int CC>
+template <int NTB>
 __device__ inline void conv_fetch_w(const ConvArgs& a, int sb, int tb, uint4* w) {
-    constexpr int EW = (CC == 32 ? 27 : 14) * NTB * 64;
-    constexpr int SW = (EW + 255) / 256;
     const uint4* wsrc = reinterpret_cast<const uint4*>(a.w);
 #pragma unroll
-    for (int i = 0; i < SW; ++i) {
+    for (int i = 0; i < ConvW<NTB>::M; ++i) {
         const int e = threadIdx.x + 256 * i;   // (step, tile, lane) of the block's slice
         w[i] = make_uint4(0, 0, 0, 0);
-        if (e < EW) {
+        if (e < ConvW<NTB>::E) {
             const int s = e / (NTB * 64), q = e - s * (NTB * 64);
             w[i] = wsrc[((long long)(sb + s) * a.nt + tb) * 64 + q];
         }
     }
 }
-template <int NTB, int CC, int CS>
+template <int NTB>
 __device__ inline void conv_store_w(char* xs, const uint4* w) {
-    constexpr int EW = (CC == 32 ? 27 : 14) * NTB * 64;
-    constexpr int SW = (EW + 255) / 256;
-    uint4* wl = reinterpret_cast<uint4*>(xs + conv_x_bytes(CS));
+    uint4* wl = reinterpret_cast<uint4*>(xs + conv_x_bytes());
 #pragma unroll
-    for (int i = 0; i < SW; ++i) {
+    for (int i = 0; i < ConvW<NTB>::M; ++i) {
         const int e = threadIdx.x + 256 * i;
-        if (e < EW) wl[e] = w[i];
+        if (e < ConvW<NTB>::E) wl[e] = w[i];
     }
 }
 
-// Global loads of channels [cb, cb + CC) of tile t (and, for CS = 40, of the chunk's
-// weights).
-template <int NTB, int CC, int CS, bool GATED>
-__device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, int sb, int tb,
-                                  ConvRegs<NTB, CS, GATED>& r) {
-    constexpr int G = CC / 8;
-    constexpr int E = kHV * G;
-    constexpr int SM = (E + 255) / 256;
+// Global loads of channels [cb, cb + 16) of tile t (and of the chunk's weights when WL).
+template <int NTB, bool WL, bool GATED>
+__device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, int tb, ConvRegs<NTB, WL, GATED>& r) {
 #pragma unroll
-    for (int i = 0; i < SM; ++i) {
+    for (int i = 0; i < kXM; ++i) {
         const int e = threadIdx.x + 256 * i;
         r.x[i] = make_uint4(0, 0, 0, 0);
         if (GATED) r.g[i] = make_uint4(0, 0, 0, 0);
-        if (e < E) {
-            const int v = e / G, gi = e - v * G;
+        if (e < 2 * kHV) {
+            const int v = e >> 1, gi = e & 1;
             const int x = t.x0 - 1 + v % kHX, y = t.y0 - 1 + (v / kHX) % kHY, z = t.z0 - 1 + v / (kHX * kHY);
             if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
                 const long long q = t.sbase + ((long long)z * a.H + y) * a.W + x;
@@ -191,58 +184,46 @@ __device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, 
             }
         }
     }
-    if (ConvRegs<NTB, CS, GATED>::kW) conv_fetch_w<NTB, CC>(a, sb, tb, r.w);
+    if (WL) conv_fetch_w<NTB>(a, kSteps * (cb / 16), tb, r.w);
 }
 
 // LDS writes of a fetched (item, chunk); the caller brackets them with barriers.
-template <int NTB, int CC, int CS, bool GATED>
-__device__ inline void conv_store(char* xs, const ConvRegs<NTB, CS, GATED>& r) {
-    constexpr int G = CC / 8;
-    constexpr int E = kHV * G;
-    constexpr int SM = (E + 255) / 256;
+template <int NTB, bool WL, bool GATED>
+__device__ inline void conv_store(char* xs, const ConvRegs<NTB, WL, GATED>& r) {
 #pragma unroll
-    for (int i = 0; i < SM; ++i) {
+    for (int i = 0; i < kXM; ++i) {
         const int e = threadIdx.x + 256 * i;
-        if (e < E) {
-            const int v = e / G, gi = e - v * G;
-            *reinterpret_cast<uint4*>(xs + (v * CS + 8 * gi) * 2) = GATED ? apply_gate(r.x[i], r.g[i]) : r.x[i];
-        }
+        if (e < 2 * kHV)
+            *reinterpret_cast<uint4*>(xs + ((e >> 1) * kCS + 8 * (e & 1)) * 2) =
+                GATED ? apply_gate(r.x[i], r.g[i]) : r.x[i];
     }
-    if (ConvRegs<NTB, CS, GATED>::kW) conv_store_w<NTB, CC, CS>(xs, r.w);
+    if (WL) conv_store_w<NTB>(xs, r.w);
 }
 
-// One chunk of CC input channels: S MFMA steps over the 27 taps.  abase[mt] is the LDS
-// byte address of the lane's voxel (tap 0, channel 0) in M tile mt.
-template <int NTB, int CC, int CS>
+// One 16-channel chunk: 14 MFMA steps over the 27 taps.  abase[mt] is the LDS byte
+// address of the lane's voxel (tap 0, channel 0) in M tile mt.
+template <int NTB>
 __device__ inline void conv_chunk(const char* xs, const uint32_t (&abase)[4], f32x4 (&acc)[4][NTB]) {
-    constexpr int S = CC == 32 ? 27 : 14;
-    constexpr int VB = CS * 2;   // LDS bytes per halo voxel
+    constexpr int VB = kCS * 2;   // LDS bytes per halo voxel
     const int lane = threadIdx.x & 63, g = lane >> 4;
-    const int h = CC == 32 ? 0 : g >> 1;            // lane half: second tap of a pair
-    const int cl = CC == 32 ? 8 * g : 8 * (g & 1);  // first channel of the lane's 8
+    const int h = g >> 1;         // lane half: second tap of a pair
     uint32_t al[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) al[mt] = abase[mt] + 2 * cl;
+    for (int mt = 0; mt < 4; ++mt) al[mt] = abase[mt] + 16 * (g & 1);
     // A address shift of the lane half that takes the second tap of a pair, by pair kind
-    uint32_t dsh[3] = {0, 0, 0};
-    if (CC == 16) {
-        dsh[0] = h ? 1 * VB : 0;
-        dsh[1] = h ? 16 * VB : 0;
-        dsh[2] = h ? 70 * VB : 0;
-    }
-    const char* wl = xs + conv_x_bytes(CS) + 16 * lane;
+    const uint32_t dsh[3] = {h ? 1u * VB : 0u, h ? 16u * VB : 0u, h ? 70u * VB : 0u};
+    const char* wl = xs + conv_x_bytes() + 16 * lane;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < kSteps; ++s) {
         bf16x8 b[NTB];
 #pragma unroll
         for (int nt = 0; nt < NTB; ++nt)
             b[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wl + (s * NTB + nt) * 1024));
-        // immediate LDS offset of the step's (first) tap and the pair's shift kind
-        const int t0 = CC == 32 ? s : 2 * s;
-        const uint32_t imm = (uint32_t)tap_vox(t0) * VB;
+        // immediate LDS offset of the pair's first tap, and the pair's shift kind
+        const uint32_t imm = (uint32_t)tap_vox(2 * s) * VB;
         int kind = 3;
-        if (CC == 16 && s < 13) {
-            const int d = tap_vox(t0 + 1) - tap_vox(t0);
+        if (s < 13) {
+            const int d = tap_vox(2 * s + 1) - tap_vox(2 * s);
             kind = d == 1 ? 0 : d == 16 ? 1 : 2;
         }
 #pragma unroll
@@ -256,14 +237,12 @@ __device__ inline void conv_chunk(const char* xs, const uint32_t (&abase)[4], f3
     }
 }
 
-// CS: LDS channel stride per halo voxel in BF16 values, 24 when the padded input has
-// 16 channels (one 16-channel chunk), else 40 (32-channel chunks); both strides spread
-// the 16 voxels of an A fragment over distinct banks.  GATED: the input is multiplied by
-// (gate > 0) (ReLU backward).  The grid size must be a multiple of NT / NTB: a block
-// keeps one output-tile group (its bias is read once, and for CS = 24 its weights are
-// staged once), and its epilogue issues no loads, so the wait for the next item's
-// prefetched input does not also wait for the stores of this one.
-template <int NTB, int CS, bool GATED>
+// WL: the weights change with the chunk (more than 16 input channels); GATED: the input
+// is multiplied by (gate > 0) (ReLU backward).  The grid size must be a multiple of
+// NT / NTB: a block keeps one output-tile group (its bias is read once, and without WL
+// its weights are staged once), and its epilogue issues no loads, so the wait for the
+// next item's prefetched input does not also wait for the stores of this one.
+template <int NTB, bool WL, bool GATED>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     extern __shared__ uint4 xs_dyn[];
     char* xs = reinterpret_cast<char*>(xs_dyn);
@@ -272,7 +251,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     const int nsplit = a.nt / NTB;
     const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
     const long long nitems = tiles * nsplit;
-    const int nchunk = CS >= 40 ? (a.cin_p + 31) / 32 : 1;
+    const int nchunk = WL ? a.cin_p / 16 : 1;
     const int tb = (int)(blockIdx.x % nsplit) * NTB;   // the block's first output tile
     long long item = blockIdx.x;
     if (item >= nitems) return;
@@ -286,36 +265,25 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         const int r = 4 * wave + mt;
-        abase[mt] = (uint32_t)((((r / kTY) * kHY + r % kTY) * kHX + (lane & 15)) * CS * 2);
+        abase[mt] = (uint32_t)((((r / kTY) * kHY + r % kTY) * kHX + (lane & 15)) * kCS * 2);
     }
     f32x4 acc[4][NTB];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NTB; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (CS < 40) {   // one chunk: the block's weights, read by every item after the first barrier
-        uint4 w[(14 * NTB * 64 + 255) / 256];
-        conv_fetch_w<NTB, 16>(a, 0, tb, w);
-        conv_store_w<NTB, 16, CS>(xs, w);
+    if (!WL) {   // one chunk: the block's weights, read by every item after the first barrier
+        uint4 w[ConvW<NTB>::M];
+        conv_fetch_w<NTB>(a, 0, tb, w);
+        conv_store_w<NTB>(xs, w);
     }
-    ConvRegs<NTB, CS, GATED> regs;
-    // chunk c covers channels [32 c, ..) and packed steps [27 c, ..); it is 16 wide when
-    // fewer than 32 channels remain.  Item i holds voxel tile i / nsplit.
+    ConvRegs<NTB, WL, GATED> regs;
+    // chunk c covers channels [16 c, 16 c + 16); item i holds voxel tile i / nsplit
     int chunk = 0;
-    {
-        const ConvTile t = conv_tile(a, item / nsplit);
-        if (CS >= 40 && 32 <= a.cin_p)
-            conv_fetch<NTB, 32, CS, GATED>(a, t, 0, 0, tb, regs);
-        else
-            conv_fetch<NTB, 16, CS, GATED>(a, t, 0, 0, tb, regs);
-    }
+    conv_fetch<NTB, WL, GATED>(a, conv_tile(a, item / nsplit), 0, tb, regs);
     for (;;) {
-        const bool wc = CS >= 40 && 32 * chunk + 32 <= a.cin_p;
         __syncthreads();   // every wave is done with the previous chunk's LDS
-        if (wc)
-            conv_store<NTB, 32, CS, GATED>(xs, regs);
-        else
-            conv_store<NTB, 16, CS, GATED>(xs, regs);
+        conv_store<NTB, WL, GATED>(xs, regs);
         __syncthreads();
         long long nitem = item;
         int nc = chunk + 1;
@@ -324,17 +292,8 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
             nitem += gridDim.x;
         }
         const bool more = nitem < nitems;
-        if (more) {   // in flight during the MFMAs below
-            const ConvTile t = conv_tile(a, nitem / nsplit);
-            if (CS >= 40 && 32 * nc + 32 <= a.cin_p)
-                conv_fetch<NTB, 32, CS, GATED>(a, t, 32 * nc, 27 * nc, tb, regs);
-            else
-                conv_fetch<NTB, 16, CS, GATED>(a, t, 32 * nc, 27 * nc, tb, regs);
-        }
-        if (wc)
-            conv_chunk<NTB, 32, CS>(xs, abase, acc);
-        else
-            conv_chunk<NTB, 16, CS>(xs, abase, acc);
+        if (more) conv_fetch<NTB, WL, GATED>(a, conv_tile(a, nitem / nsplit), 16 * nc, tb, regs);   // in flight during the MFMAs
+        conv_chunk<NTB>(xs, abase, acc);
         if (chunk == nchunk - 1) {
             // D layout: lane holds rows 4 * (lane / 16) + i (voxels x0 + row), column lane % 16
             const ConvTile t = conv_tile(a, item / nsplit);
@@ -753,20 +712,13 @@ __global__ void k_adam(float* th, const float* g, float* m, float* v, long long 
     th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// The step of a packed convolution GEMM (ci_p padded input channels, a multiple of 16):
-// 27 steps per 32-channel chunk, then 14 for a last 16-channel chunk.  For lane group g
-// of step sg, returns the tap (27 for the zero half of the last pair) and the first of
+// The step of a packed convolution GEMM: 14 steps per 16-channel chunk.  For lane group
+// g of step sg, returns the tap (27 for the zero half of the last pair) and the first of
 // the group's 8 input channels.
-__device__ inline void packed_step(int sg, int g, int ci_p, int& tap, int& c0) {
-    const int q = ci_p / 32;
-    if (sg < 27 * q) {
-        tap = sg % 27;
-        c0 = 32 * (sg / 27) + 8 * g;
-    } else {
-        const int s = sg - 27 * q;
-        tap = 2 * s + (g >> 1);
-        c0 = 32 * q + 8 * (g & 1);
-    }
+__device__ inline void packed_step(int sg, int g, int& tap, int& c0) {
+    const int s = sg % kSteps;
+    tap = 2 * s + (g >> 1);
+    c0 = 16 * (sg / kSteps) + 8 * (g & 1);
 }
 
 // BF16 copies of one convolution's weights W[tap][cin][cout] in the fragment order of
@@ -782,11 +734,11 @@ __global__ void k_pack(const float* W, int cin, int cout, int cin_p, int cout_p,
     if (!fwd && (i >= nf + nd || !wd)) return;
     const long long k = fwd ? i : i - nf;
     const int gi = fwd ? cin : cout, go = fwd ? cout : cin;           // GEMM input / output channels
-    const int gip = fwd ? cin_p : cout_p, nt = (fwd ? cout_p : cin_p) / 16;
+    const int nt = (fwd ? cout_p : cin_p) / 16;
     const int j = (int)(k % 8), lane = (int)((k / 8) % 64), t = (int)((k / 512) % nt);
     const int sg = (int)(k / (512LL * nt));
     int tap, c0;
-    packed_step(sg, lane >> 4, gip, tap, c0);
+    packed_step(sg, lane >> 4, tap, c0);
     const int ci = c0 + j, co = 16 * t + (lane & 15);
     float v = 0.f;
     if (tap < 27 && ci < gi && co < go)

@@ -79,9 +79,8 @@ def _self_spread(th, x, widths):
     return _rel(alt, ref)
 
 
-# [16, 32] and [16, 32, 64, 64]: the first decoder convolutions read the upsampled input
-# and the skip directly; [16, 48]: 48 upsampled channels do not fill whole 32-channel
-# chunks, so the concatenated buffer is built first
+# the first decoder convolution of each level reads the upsampled deeper output and the
+# skip directly (for [16, 48] the upsampled input is three 16-channel chunks)
 @pytest.mark.parametrize("widths,shape", [([16, 32], (2, 8, 8, 16)), ([16, 32, 64, 64], (1, 16, 16, 16)),
                                           ([16, 32, 64, 64], (2, 8, 16, 24)), ([16, 48], (1, 6, 8, 18))])
 def test_forward_backward_match_oracle(widths, shape):
