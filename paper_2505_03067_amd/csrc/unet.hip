@@ -311,10 +311,12 @@ static int conv_param_grads(Net* n, int li, int lvl, const uint16_t* x, int ldx,
                             const uint16_t* gate, float* gw, float* gb) {
     hipStream_t st = n->stream;
     const ConvL& c = n->layers[li];
-    const long long P = (long long)n->dims[0] * (n->dims[1] >> lvl) * (n->dims[2] >> lvl) * (n->dims[3] >> lvl);
-    long long nchunk = std::max(1LL, std::min(64LL, P / 2048));
-    const long long per = ((P + nchunk - 1) / nchunk + 63) / 64 * 64;
-    nchunk = (P + per - 1) / per;
+    const int D = n->dims[1] >> lvl, H = n->dims[2] >> lvl, W = n->dims[3] >> lvl;
+    const long long tiles = (long long)n->dims[0] * ((D + kTZ - 1) / kTZ) * ((H + kTY - 1) / kTY) * ((W + kTX - 1) / kTX);
+    // one block per (16 x 16 channel block, voxel-tile stride); about 512 blocks in all,
+    // two per CU (63 KB of LDS each)
+    const int cblocks = (c.cin_p / 16) * (c.cout_p / 16);
+    const long long nchunk = std::max(1LL, std::min(tiles, (long long)std::max(1, 512 / cblocks)));
     const size_t need = (size_t)nchunk * 27 * c.cin_p * c.cout_p;
     if (need > n->wpart_cap) {
         (void)hipFree(n->wpart);
@@ -337,13 +339,12 @@ static int conv_param_grads(Net* n, int li, int lvl, const uint16_t* x, int ldx,
     w.ldg = c.cout;
     w.cout_p = c.cout_p;
     w.n = n->dims[0];
-    w.D = n->dims[1] >> lvl;
-    w.H = n->dims[2] >> lvl;
-    w.W = n->dims[3] >> lvl;
-    w.per_chunk = per;
-    if ((size_t)nchunk * c.cout > n->dpart_cap) {
+    w.D = D;
+    w.H = H;
+    w.W = W;
+    if ((size_t)nchunk * c.cout_p > n->dpart_cap) {
         (void)hipFree(n->dpart);
-        n->dpart_cap = std::max<size_t>((size_t)nchunk * c.cout, 64 * 128);
+        n->dpart_cap = std::max<size_t>((size_t)nchunk * c.cout_p, 64 * 128);
         if (hipMalloc(&n->dpart, n->dpart_cap * 4) != hipSuccess) {
             (void)hipGetLastError();
             n->dpart = nullptr;
@@ -353,10 +354,10 @@ static int conv_param_grads(Net* n, int li, int lvl, const uint16_t* x, int ldx,
         }
     }
     w.bpart = gb ? n->dpart : nullptr;
-    k_conv_wgrad<<<dim3((unsigned)nchunk, 27), 256, 0, st>>>(w);
+    k_conv_wgrad<<<dim3((unsigned)nchunk, (unsigned)cblocks), 256, kWgLds, st>>>(w);
     const long long tot = 27LL * c.cin * c.cout;
     k_wgrad_reduce<<<blocks_for(tot), 256, 0, st>>>(n->wpart, (int)nchunk, c.cin, c.cout, c.cin_p, c.cout_p, gw);
-    if (gb) k_bias_reduce<<<1, 128, 0, st>>>(n->dpart, (int)nchunk, c.cout, gb);
+    if (gb) k_bias_reduce<<<1, 128, 0, st>>>(n->dpart, (int)nchunk, c.cout_p, c.cout, gb);
     MPM_HIP(hipGetLastError());
     return MPM_OK;
 }

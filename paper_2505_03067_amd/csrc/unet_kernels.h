@@ -329,117 +329,151 @@ struct WgradArgs {
     const uint16_t* x;     // forward input [P][ldx] (real channels cin, padded cin_p)
     const uint16_t* g;     // output gradient [P][ldg]
     const uint16_t* gate;  // layer output [P][ldg] (ReLU gate) or null
-    float* part;           // [nchunk][27][cin_p][cout_p]
-    float* bpart;          // optional [nchunk][cout]: bias-gradient partials (from the centre tap)
+    float* part;           // [gridDim.x][27][cin_p][cout_p]
+    float* bpart;          // optional [gridDim.x][cout_p]: bias-gradient partials
     int ldx, cin_p, ldg, cout_p;
     int n, D, H, W;
-    long long per_chunk;   // voxels per block (multiple of 64)
 };
 
-// Weight gradient of a 3x3x3 convolution for one tap (blockIdx.y) over one voxel
-// chunk (blockIdx.x): dW[tap][c][o] = sum_p x[p + off(tap)][c] * g[p][o] * (gate > 0).
-// Voxel tiles of 64 are staged in LDS transposed ([channel][voxel]) so that the MFMA
-// K dimension runs over voxels.
+// Weight gradient of a 3x3x3 convolution, dW[tap][c][o] = sum_p x[p + off(tap)][c] *
+// g[p][o] * (gate[p][o] > 0), for one 16 x 16 block of (c, o) (blockIdx.y) over the
+// voxel tiles blockIdx.x, blockIdx.x + gridDim.x, ... (16 x 4 x 4 voxels each, as in
+// k_conv).  Per tile, the input's 18 x 6 x 6 halo and the gated gradient are staged in
+// LDS transposed ([channel][voxel]) so that the MFMA K dimension runs over voxels; the
+// halo is stored three times, shifted by dx = 0, 1, 2 along x, so that the 8 voxels of
+// every A fragment are one aligned 16-byte word for all 27 taps.  K step ks covers the
+// tile's rows (z, y) = (ks / 2, 2 (ks mod 2) + r), r = 0, 1; lane group q = lane / 16
+// holds row r = q / 2, voxels x = 8 (q mod 2) .. + 7.  Wave w accumulates taps w, w + 4,
+// ...; wave 3, which has one tap fewer, also sums the gated gradient over the voxels
+// (an MFMA with an all-ones A) for the bias gradient when blockIdx.y has c block 0.
+constexpr int kWgCi = 36 * 16 + 8;        // BF16 stride between channels of a shifted halo copy
+constexpr int kWgCopy = 16 * kWgCi;        // one shifted copy, 16 channels
+constexpr int kWgCo = 256 + 8;             // BF16 stride between gradient channels
+// LDS bytes: three halo copies and the transposed gradient
+constexpr int kWgLds = (3 * kWgCopy + 16 * kWgCo) * 2;
+
 __global__ __launch_bounds__(256) void k_conv_wgrad(WgradArgs a) {
-    constexpr int PT = 64;
-    __shared__ uint16_t xs[128 * PT];   // [cin_p][PT]
-    __shared__ uint16_t gs[128 * PT];   // [cout_p][PT]
+    extern __shared__ uint4 wg_dyn[];
+    uint16_t* xs = reinterpret_cast<uint16_t*>(wg_dyn);   // [dx][c][hz][hy][x'] with x' = hx - dx
+    uint16_t* gs = xs + 3 * kWgCopy;                       // [o][tile voxel]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int tap = blockIdx.y;
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const long long P = (long long)a.n * a.D * a.H * a.W;
-    const long long pa = (long long)blockIdx.x * a.per_chunk;
-    const long long pb = pa + a.per_chunk < P ? pa + a.per_chunk : P;
-    const int mtc = a.cin_p / 16, ntc = a.cout_p / 16, ntile = mtc * ntc;
-    f32x4 acc[8];
+    const int nob = a.cout_p / 16;
+    const int cbk = blockIdx.y / nob, obk = blockIdx.y - cbk * nob;   // 16-channel blocks of c and o
+    const int c0 = 16 * cbk, o0 = 16 * obk;
+    const bool with_bias = a.bpart && cbk == 0;
+    const int ntx = (a.W + kTX - 1) / kTX, nty = (a.H + kTY - 1) / kTY, ntz = (a.D + kTZ - 1) / kTZ;
+    const long long tiles = (long long)a.n * ntz * nty * ntx;
+    f32x4 acc[7];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int cgx = a.cin_p / 8, cgg = a.cout_p / 8;   // 16-byte groups per voxel
-    // the centre tap's block also sums the gated gradient per channel (bias gradient)
-    const bool bias = a.bpart && tap == 13;
-    float bsum = 0.f;
-    for (long long t0 = pa; t0 < pb; t0 += PT) {
-        __syncthreads();
-        // stage x (shifted by the tap) and the gated gradient, transposed
-        for (int e = threadIdx.x; e < PT * (cgx + cgg); e += 256) {
-            const bool isx = e < PT * cgx;
-            const int ee = isx ? e : e - PT * cgx;
-            const int cg = isx ? cgx : cgg;
-            const int pv = ee / cg, grp = ee - pv * cg;
-            const long long p = t0 + pv;
-            uint4 t = make_uint4(0, 0, 0, 0);
-            if (p < pb) {
-                long long r = p;
-                const int xx = (int)(r % a.W); r /= a.W;
-                const int yy = (int)(r % a.H); r /= a.H;
-                const int zz = (int)(r % a.D);
-                const long long nb = r / a.D;
-                if (isx) {
-                    const int z = zz + dz, y = yy + dy, x = xx + dx;
-                    if (z >= 0 && z < a.D && y >= 0 && y < a.H && x >= 0 && x < a.W) {
-                        const long long q = ((nb * a.D + z) * a.H + y) * a.W + x;
-                        t = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + grp * 8);
-                    }
-                } else {
-                    t = *reinterpret_cast<const uint4*>(a.g + p * a.ldg + grp * 8);
-                    if (a.gate) {
-                        const uint4 g = *reinterpret_cast<const uint4*>(a.gate + p * a.ldg + grp * 8);
-                        const uint32_t gw[4] = {g.x, g.y, g.z, g.w};
-                        uint32_t tw[4] = {t.x, t.y, t.z, t.w};
+    for (int i = 0; i < 7; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int q = lane >> 4, l16 = lane & 15;
+    for (long long tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        long long r = tile;
+        const int x0 = (int)(r % ntx) * kTX;
+        r /= ntx;
+        const int y0 = (int)(r % nty) * kTY;
+        r /= nty;
+        const int z0 = (int)(r % ntz) * kTZ;
+        const long long sbase = (r / ntz) * a.D * a.H * a.W;
+        // global loads: halo words (voxel, 8 channels) and gradient words
+        constexpr int EX = 2 * kHV, EG = 2 * 256;
+        constexpr int SX = (EX + 255) / 256, SG = (EG + 255) / 256;
+        uint4 tx[SX], tg[SG];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const uint32_t lo = gw[i] & 0xffffu, hi = gw[i] >> 16;
-                            const bool plo = lo != 0 && !(lo & 0x8000u);
-                            const bool phi = hi != 0 && !(hi & 0x8000u);
-                            tw[i] &= (plo ? 0x0000ffffu : 0u) | (phi ? 0xffff0000u : 0u);
-                        }
-                        t = make_uint4(tw[0], tw[1], tw[2], tw[3]);
+        for (int i = 0; i < SX; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            tx[i] = make_uint4(0, 0, 0, 0);
+            if (e < EX) {
+                const int v = e >> 1, gi = e & 1;
+                const int x = x0 - 1 + v % kHX, y = y0 - 1 + (v / kHX) % kHY, z = z0 - 1 + v / (kHX * kHY);
+                if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
+                    const long long p = sbase + ((long long)z * a.H + y) * a.W + x;
+                    tx[i] = *reinterpret_cast<const uint4*>(a.x + p * a.ldx + c0 + 8 * gi);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < SG; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            tg[i] = make_uint4(0, 0, 0, 0);
+            if (e < EG) {
+                const int v = e >> 1, gi = e & 1;
+                const int x = x0 + (v & 15), y = y0 + ((v >> 4) & 3), z = z0 + (v >> 6);
+                if (x < a.W && y < a.H && z < a.D) {
+                    const long long p = sbase + ((long long)z * a.H + y) * a.W + x;
+                    tg[i] = *reinterpret_cast<const uint4*>(a.g + p * a.ldg + o0 + 8 * gi);
+                    if (a.gate) tg[i] = apply_gate(tg[i], *reinterpret_cast<const uint4*>(a.gate + p * a.ldg + o0 + 8 * gi));
+                }
+            }
+        }
+        __syncthreads();   // the previous tile's LDS reads are done
+#pragma unroll
+        for (int i = 0; i < SX; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < EX) {
+                const int v = e >> 1, gi = e & 1;
+                const int hx = v % kHX, row = v / kHX;   // row = hz * 6 + hy
+                const uint32_t w4[4] = {tx[i].x, tx[i].y, tx[i].z, tx[i].w};
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int xp = hx - dx;
+                    if (xp >= 0 && xp < 16) {
+                        uint16_t* d = xs + dx * kWgCopy + (8 * gi) * kWgCi + row * 16 + xp;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            d[j * kWgCi] = (uint16_t)(j & 1 ? w4[j >> 1] >> 16 : w4[j >> 1] & 0xffffu);
                     }
                 }
             }
-            const uint32_t w4[4] = {t.x, t.y, t.z, t.w};
-            uint16_t* dst = isx ? xs : gs;
+        }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                dst[(grp * 8 + 2 * i) * PT + pv] = (uint16_t)(w4[i] & 0xffffu);
-                dst[(grp * 8 + 2 * i + 1) * PT + pv] = (uint16_t)(w4[i] >> 16);
+        for (int i = 0; i < SG; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < EG) {
+                const int v = e >> 1, gi = e & 1;
+                const uint32_t w4[4] = {tg[i].x, tg[i].y, tg[i].z, tg[i].w};
+                uint16_t* d = gs + (8 * gi) * kWgCo + v;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) d[j * kWgCo] = (uint16_t)(j & 1 ? w4[j >> 1] >> 16 : w4[j >> 1] & 0xffffu);
             }
         }
         __syncthreads();
-        if (bias && (int)threadIdx.x < a.ldg) {
-            const uint16_t* row = gs + threadIdx.x * PT;
-            for (int pv = 0; pv < PT; ++pv) bsum += bf2f(row[pv]);
-        }
+        // B fragments of the 8 K steps (shared by every tap)
+        bf16x8 bq[8];
 #pragma unroll
-        for (int kk = 0; kk < PT; kk += 32) {
-            const int kq = kk + 8 * (lane >> 4);
+        for (int ks = 0; ks < 8; ++ks)
+            bq[ks] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(gs + l16 * kWgCo + 32 * ks + 8 * q));
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int tile = wave + 4 * i;
-                if (tile < ntile) {
-                    const int mt = tile / ntc, nt = tile - (tile / ntc) * ntc;
-                    const uint4 ta = *reinterpret_cast<const uint4*>(xs + (mt * 16 + (lane & 15)) * PT + kq);
-                    const uint4 tb = *reinterpret_cast<const uint4*>(gs + (nt * 16 + (lane & 15)) * PT + kq);
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ta),
-                                                                     __builtin_bit_cast(bf16x8, tb), acc[i], 0, 0, 0);
+        for (int i = 0; i < 7; ++i) {
+            const int t = wave + 4 * i;   // wave-uniform
+            if (t < 27) {
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+                const uint16_t* xa = xs + dx * kWgCopy + l16 * kWgCi + 8 * (q & 1);
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    const int z = ks >> 1, y = 2 * (ks & 1) + (q >> 1);
+                    const bf16x8 af = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const uint4*>(xa + ((z + dz) * kHY + (y + dy)) * 16));
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bq[ks], acc[i], 0, 0, 0);
                 }
+            } else if (with_bias) {   // t = 27 on wave 3: ones^T g, every row the voxel sum
+                const bf16x8 ones = __builtin_bit_cast(bf16x8, make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u));
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, bq[ks], acc[i], 0, 0, 0);
             }
         }
     }
-    if (bias && (int)threadIdx.x < a.ldg) a.bpart[(long long)blockIdx.x * a.ldg + threadIdx.x] = bsum;
-    float* out = a.part + ((long long)blockIdx.x * 27 + tap) * a.cin_p * a.cout_p;
+    // D layout: lane holds rows c = 4 (lane / 16) + i, column o = lane mod 16
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int tile = wave + 4 * i;
-        if (tile < ntile) {
-            const int mt = tile / ntc, nt = tile - (tile / ntc) * ntc;
-            const int co = nt * 16 + (lane & 15);
+    for (int i = 0; i < 7; ++i) {
+        const int t = wave + 4 * i;
+        if (t < 27) {
+            float* out = a.part + ((long long)blockIdx.x * 27 + t) * a.cin_p * a.cout_p;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ci = mt * 16 + 4 * (lane >> 4) + r;
-                out[ci * a.cout_p + co] = acc[i][r];
-            }
+            for (int rr = 0; rr < 4; ++rr) out[(c0 + 4 * q + rr) * a.cout_p + o0 + l16] = acc[i][rr];
+        } else if (with_bias && q == 0) {
+            a.bpart[(long long)blockIdx.x * a.cout_p + o0 + l16] = acc[i][0];
         }
     }
 }
@@ -459,11 +493,11 @@ __global__ void k_wgrad_reduce(const float* part, int nchunk, int cin, int cout,
     grad[i] += (float)s;
 }
 
-__global__ void k_bias_reduce(const float* part, int nchunk, int cout, float* grad) {
+__global__ void k_bias_reduce(const float* part, int nchunk, int ld, int cout, float* grad) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= cout) return;
     double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += part[(long long)k * cout + o];
+    for (int k = 0; k < nchunk; ++k) s += part[(long long)k * ld + o];
     grad[o] += (float)s;
 }
 
