@@ -488,17 +488,28 @@ __global__ void k_wgrad_reduce(const float* part, int nchunk, int cin, int cout,
     const long long r = i / cout;
     const int c = (int)(r % cin);
     const int tap = (int)(r / cin);
-    double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += part[(((long long)k * 27 + tap) * cin_p + c) * cout_p + o];
-    grad[i] += (float)s;
+    // eight interleaved partial sums keep eight loads in flight (fixed order: deterministic)
+    const long long stride = 27LL * cin_p * cout_p;
+    const float* q = part + ((long long)tap * cin_p + c) * cout_p + o;
+    double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int k = 0;
+    for (; k + 8 <= nchunk; k += 8)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s8[j] += q[(k + j) * stride];
+    for (; k < nchunk; ++k) s8[0] += q[k * stride];
+    grad[i] += (float)(((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7])));
 }
 
 __global__ void k_bias_reduce(const float* part, int nchunk, int ld, int cout, float* grad) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= cout) return;
-    double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += part[(long long)k * ld + o];
-    grad[o] += (float)s;
+    double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int k = 0;
+    for (; k + 8 <= nchunk; k += 8)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s8[j] += part[(long long)(k + j) * ld + o];
+    for (; k < nchunk; ++k) s8[0] += part[(long long)k * ld + o];
+    grad[o] += (float)(((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7])));
 }
 
 // Eight BF16 values as one 16-byte word, and their FP32 values.
