@@ -7,7 +7,8 @@
 // input gradient is the same GEMM on the output gradient with the taps mirrored and the
 // weights transposed: dX[p] = sum_t dY[p - off(t)] W[t] = sum_t dY[p + off(t)] W[26 - t],
 // so the forward kernel runs on packed weights holding W[26 - t] transposed.  The weight
-// gradient stages voxel chunks in LDS, transposed so that K runs over voxels.
+// gradient stages voxel tiles in LDS, transposed so that K runs over voxels, and takes
+// all 27 taps from one staged tile.
 #pragma once
 
 #include <hip/hip_runtime.h>
