@@ -118,11 +118,14 @@ def test_forward_backward_match_oracle(widths, shape):
                                              ([16, 32], 3, (1, 5, 9, 35)),
                                              ([16, 32, 64, 64], 4, (1, 6, 7, 20)),
                                              ([16, 32, 64, 64], 8, (1, 8, 8, 16)),
-                                             ([16, 32, 64, 64], 10, (2, 4, 5, 17))])
+                                             ([16, 32, 64, 64], 10, (2, 4, 5, 17)),
+                                             ([16, 32], 1, (1, 64, 64, 64)), ([16, 32], 3, (1, 32, 64, 64))])
 def test_single_layer_kernels_exact(widths, li, shape):
     """Forward, input-gradient and weight-gradient kernels of one layer on small-integer
     data, for which FP32 accumulation is exact: the GPU must equal the FP64 oracle
-    bit for bit (catches any index, tap or layout error)."""
+    bit for bit (catches any index, tap or layout error).  The two largest grids give
+    the persistent convolution blocks several work items each, and the weight-gradient
+    blocks several voxel tiles each."""
     torch = require_gpu()
     from paper_2505_03067_amd import Net
     net = Net(13, 3, widths, seed=3)
