@@ -31,12 +31,18 @@ TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0,
 def bf16(x):
     """Round to the nearest BFloat16 value (ties to even), returned as float64.
 
-    BFloat16 keeps the top 16 bits of an IEEE binary32 number; rounding adds
-    0x7fff plus the lowest kept bit before truncation.
+    BFloat16 keeps the sign, the 8 exponent bits and the top 7 fraction bits of an
+    IEEE binary32 number.  The value is first rounded to binary32; rounding to nearest
+    with ties to even then adds 0x7fff plus the lowest kept bit to the bit pattern and
+    truncates the low 16 bits (a carry moves into the exponent, so the largest values
+    round to infinity).  NaN stays NaN.  Pinned against PyTorch's CPU cast to
+    ``torch.bfloat16`` in ``tests/test_oracle_unet.py``.
     """
-    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    out = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isnan(f), np.nan, out)
 
 
 def _keep(x, store):
