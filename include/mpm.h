@@ -147,7 +147,12 @@ int32_t mpm_fv_setup(mpm_ctx ctx, int32_t problem, const int32_t* dims, const in
  * system did not reach tol within max_cycles (the best iterate is written). */
 int32_t mpm_implicit_step(mpm_ctx ctx, double* const* fields, double tol);
 
-/* Statistics of the last step for one (problem, species) system (host output). */
+/* Statistics of the last step for one (problem, species) system (host output): how the
+ * solve ended, so that the caller can verify that every system completed before the
+ * fields are handed on to the cell model (the paper's main process checks the
+ * completion of the solve before distributing its result, Sec. 2.5).  Does not
+ * synchronise: the values are final when mpm_implicit_step returns.  MPM_ESTATE
+ * before the first step, MPM_EINVAL for an index out of range or a null pointer. */
 int32_t mpm_gmres_stats(mpm_ctx ctx, int32_t problem, int32_t species, mpm_stats* out);
 
 /* Free the context and all its device memory. */
@@ -201,7 +206,9 @@ int32_t mpm_tile(mpm_ctx ctx, int32_t* out);
  * device memory, all work on 'stream'. */
 typedef struct mpm_net_s* mpm_net;
 
-/* Create a network with He-normal weights drawn from 'seed' (host-side generator). */
+/* Create a network with He-normal weights drawn from 'seed' (host-side generator).
+ * 1 <= in_ch <= 32 (17 for the warm start of four species), 1 <= out_ch <= 4,
+ * 1 <= levels <= 6; MPM_EINVAL otherwise or for widths outside the list above. */
 int32_t mpm_net_create(mpm_net* net, int32_t in_ch, int32_t out_ch, int32_t levels, const int32_t* widths,
                        uint64_t seed, void* stream);
 /* Device pointers to the FP32 parameters and gradients (owned by the net) and their
@@ -236,13 +243,61 @@ int32_t mpm_net_destroy(mpm_net net);
 int32_t mpm_net_debug_layer(mpm_net net, int32_t layer, int32_t mode, int32_t n, int32_t d, int32_t h,
                             int32_t w, const uint16_t* x, const uint16_t* g, const uint16_t* gate, float* out);
 
+/* Test hook: copy a BF16 tensor the network stored in its last forward (and backward)
+ * pass into dst (device, *count 16-bit values).  With dst = NULL only *count is set to
+ * the element count; otherwise *count must equal it.  Tensors (index in brackets; all
+ * NDHWC on the grid of their level):
+ *  MPM_NT_INPUT       the input padded to a multiple of 16 channels (index ignored);
+ *  MPM_NT_ACT [i]     output of 3x3x3 layer i after the ReLU (forward order);
+ *  MPM_NT_ACT_GRAD [i] gradient with respect to that output (after mpm_net_backward;
+ *                     for the last 3x3x3 layer see MPM_NT_HEAD_GRAD);
+ *  MPM_NT_POOLED [l]  pooled input of encoder level l >= 1;
+ *  MPM_NT_CAT [l]     [upsampled deeper output, skip] of decoder level l (built in the
+ *                     backward pass), MPM_NT_CAT_GRAD [l] its gradient;
+ *  MPM_NT_HEAD_GRAD   gradient with respect to the head's input.
+ * MPM_EINVAL for an index out of range or a wrong count, MPM_ESTATE before any forward
+ * pass.  Synchronises the network's stream. */
+#define MPM_NT_INPUT 0
+#define MPM_NT_ACT 1
+#define MPM_NT_ACT_GRAD 2
+#define MPM_NT_POOLED 3
+#define MPM_NT_CAT 4
+#define MPM_NT_CAT_GRAD 5
+#define MPM_NT_HEAD_GRAD 6
+int32_t mpm_net_debug_tensor(mpm_net net, int32_t kind, int32_t index, uint16_t* dst, int64_t* count);
+
+/* Test hook: run one data-movement kernel of the network on caller tensors (device,
+ * NDHWC, BF16 unless stated).  (n, d, h, w) is the finer grid, c and c2 channel counts
+ * (multiples of 8 except the input of MPM_OP_PAD):
+ *  MPM_OP_POOL         out [n][d/2][h/2][w/2][c] = mean of the 8 children in a [..][c];
+ *  MPM_OP_POOL_BWD_ADD out [n][d][h][w][c] = a[parent][c] / 8 + the last c of the c2
+ *                      channels of b (b may be NULL: no sum);
+ *  MPM_OP_UP2_CAT      out [n][d][h][w][c + c2] = [nearest x2 upsampling of a (c
+ *                      channels at half resolution), b (c2 channels)];
+ *  MPM_OP_UP2_BWD      out [n][d/2][h/2][w/2][c] = sum over the 8 children of the first c
+ *                      of the c + c2 channels of a;
+ *  MPM_OP_HEAD         out FP32 [P][out_ch] = the net's 1x1x1 head on a [P][16] (c = 16);
+ *  MPM_OP_HEAD_BWD     b: FP32 [P][out_ch] output gradient; out = input gradient [P][16],
+ *                      out2 = FP32 head weight and bias gradient [16 out_ch + out_ch];
+ *  MPM_OP_PAD          out [P][c2] = a [P][c] padded with zero channels.
+ * d, h, w even for the pooling and upsampling operations.  Synchronises. */
+#define MPM_OP_POOL 0
+#define MPM_OP_POOL_BWD_ADD 1
+#define MPM_OP_UP2_CAT 2
+#define MPM_OP_UP2_BWD 3
+#define MPM_OP_HEAD 4
+#define MPM_OP_HEAD_BWD 5
+#define MPM_OP_PAD 6
+int32_t mpm_net_debug_op(mpm_net net, int32_t op, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c,
+                         int32_t c2, const void* a, const void* b, void* out, void* out2);
+
 /* Use 'net' (in_ch = 4 S + 1, out_ch = S) as the warm start of a context created with
  * warm_start = MPM_WS_NET; net = NULL detaches.  Network input on the box grid (box
  * sizes rounded up to multiples of 8, zero beyond the box): channels c^n (S), k (S),
- * D (S), s (S), mask, each times in_scale[ch] (host [4 S + 1]); the prediction of
- * species s is output * out_scale[s] (host [S]) added to c^n.  Each step keeps the
- * prediction of a system only if its true residual is below that of c^n
- * (mpm_stats.warm_start_used / fallback).  The net must outlive its use. */
+ * D (S), s (S), mask, each times in_scale[ch] (host, exactly 4 S + 1 floats are read);
+ * the prediction of species s is output * out_scale[s] (host, S floats read) added to
+ * c^n.  Each step keeps the prediction of a system only if its true residual is below
+ * that of c^n (mpm_stats.warm_start_used / fallback).  The net must outlive its use. */
 int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scale, const float* out_scale);
 
 /* Training pair for the warm start of 'problem': the network input built from the

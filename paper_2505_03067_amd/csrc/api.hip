@@ -131,7 +131,7 @@ extern "C" int32_t mpm_create(mpm_ctx* out, int32_t nspecies, int32_t nproblems,
     if (e == hipSuccess) e = hipMalloc(&c->d_sk, nsys * sizeof(SysK));
     if (e == hipSuccess) e = hipMalloc(&c->d_prm, sizeof(Params));
     if (e == hipSuccess) e = hipMalloc(&c->d_sysfc, 2 * kMaxSys * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&c->d_scales, 20 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&c->d_scales, kScaleCount * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&c->d_fields, nproblems * sizeof(double*));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_fields, nproblems * sizeof(double*), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_prm, sizeof(Params), hipHostMallocDefault);
@@ -316,10 +316,10 @@ extern "C" int32_t mpm_tile(mpm_ctx ctx, int32_t* out) {
 
 static int set_scales(Ctx* c, const float* in_scale, const float* out_scale) {
     const int cin = 4 * c->S + 1;
-    for (int i = 0; i < 20; ++i) c->h_scales[i] = 0.f;
+    for (int i = 0; i < kScaleCount; ++i) c->h_scales[i] = 0.f;
     for (int i = 0; i < cin; ++i) c->h_scales[i] = in_scale[i];
-    for (int s = 0; s < c->S; ++s) c->h_scales[16 + s] = out_scale[s];
-    MPM_HIP(hipMemcpy(c->d_scales, c->h_scales, 20 * sizeof(float), hipMemcpyHostToDevice));
+    for (int s = 0; s < c->S; ++s) c->h_scales[kScaleOut + s] = out_scale[s];
+    MPM_HIP(hipMemcpy(c->d_scales, c->h_scales, kScaleCount * sizeof(float), hipMemcpyHostToDevice));
     c->have_scales = true;
     return MPM_OK;
 }

@@ -19,6 +19,10 @@ constexpr long long kLead = 1024;        // zero elements before the first unkno
 constexpr int kMaxM = MPM_MAX_RESTART;   // longest restart
 constexpr int kMaxSys = 64;              // (problem, species) systems per context
 constexpr int kPartRows = 2 * (kMaxM + 1) + 4;   // partial-sum rows per block slot
+// warm-start scales on the device: the 4 S + 1 network input channel scales from
+// index 0, the S output scales from kScaleOut (room for the largest S)
+constexpr int kScaleOut = 4 * MPM_MAX_SPECIES + 1;
+constexpr int kScaleCount = kScaleOut + MPM_MAX_SPECIES;
 
 // ---------------------------------------------------------------- device views
 // Per-problem data, addressed with the problem-local unknown index

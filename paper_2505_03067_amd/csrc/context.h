@@ -125,8 +125,8 @@ struct Ctx {
 
     // warm start
     Net* net = nullptr;
-    float* d_scales = nullptr;         // [16] input channel scales, [4] output scales
-    float h_scales[20] = {0};
+    float* d_scales = nullptr;         // [kScaleCount]: input channel scales, then output scales
+    float h_scales[kScaleCount] = {0};
     bool have_scales = false;
     double* prev = nullptr;            // c^n of the previous step on the global unknowns
     size_t cap_prev = 0;

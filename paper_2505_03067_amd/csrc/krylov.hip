@@ -1332,8 +1332,10 @@ __global__ __launch_bounds__(kThreads) void k_dc_finish(KArgs<T> a, int sys0) {
 }
 
 // ------------------------------------------------------------------ warm start
+// BF16 of the network input: round to nearest, ties to even; NaN -> quiet NaN 0x7fc0
 __device__ inline uint16_t to_bf16(float f) {
     uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
@@ -1382,7 +1384,7 @@ __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, con
     if (sk->converged) return;
     const ProbDev pd = a.probs[blk.sys / a.S];
     const Where wh = where_of(a, blk, pd);
-    const float os = scales[16 + wh.s];
+    const float os = scales[kScaleOut + wh.s];
     for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
         const int l = (int)(u - wh.base);
         if (l >= pd.N) continue;
@@ -1429,7 +1431,7 @@ __global__ void k_ws_target(ProbDev pd, int S, int bx, int by, int bz, const dou
     const long long v = ((long long)(pd.lo[2] + z) * pd.ny + (pd.lo[1] + y)) * pd.nx + (pd.lo[0] + x);
     for (int s = 0; s < S; ++s) {
         float t = 0.f;
-        if (dom) t = (float)((c_new[s * pd.nvox + v] - c_old[s * pd.nvox + v]) / (double)scales[16 + s]);
+        if (dom) t = (float)((c_new[s * pd.nvox + v] - c_old[s * pd.nvox + v]) / (double)scales[kScaleOut + s]);
         tgt[i * S + s] = t;
     }
 }

@@ -474,8 +474,8 @@ extern "C" int32_t mpm_net_create(mpm_net* out, int32_t in_ch, int32_t out_ch, i
         return MPM_EINVAL;
     }
     *out = nullptr;
-    if (in_ch < 1 || in_ch > 16 || out_ch < 1 || out_ch > 4 || levels < 1 || levels > 6) {
-        set_error("mpm_net_create: need 1 <= in_ch <= 16, 1 <= out_ch <= 4, 1 <= levels <= 6");
+    if (in_ch < 1 || in_ch > 32 || out_ch < 1 || out_ch > 4 || levels < 1 || levels > 6) {
+        set_error("mpm_net_create: need 1 <= in_ch <= 32, 1 <= out_ch <= 4, 1 <= levels <= 6");
         return MPM_EINVAL;
     }
     for (int l = 0; l < levels; ++l) {
@@ -675,4 +675,140 @@ extern "C" int32_t mpm_net_debug_layer(mpm_net net, int32_t layer, int32_t mode,
         if (e != hipSuccess) rc = hip_fail(e, "mpm_net_debug_layer");
     }
     return rc;
+}
+
+// Test hooks end with a launch check and a stream synchronisation.
+static int net_debug_finish(hipStream_t st) {
+    MPM_HIP(hipGetLastError());
+    MPM_HIP(hipStreamSynchronize(st));
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_net_debug_tensor(mpm_net net, int32_t kind, int32_t index, uint16_t* dst, int64_t* count) {
+    Net* n = (Net*)net;
+    if (!n || !count || kind < MPM_NT_INPUT || kind > MPM_NT_HEAD_GRAD) {
+        set_error("mpm_net_debug_tensor: bad arguments");
+        return MPM_EINVAL;
+    }
+    if (n->dims[0] == 0) {
+        set_error("mpm_net_debug_tensor: no forward pass yet");
+        return MPM_ESTATE;
+    }
+    const int L = n->L;
+    const int nl = (int)n->layers.size();
+    auto vox = [&](int lvl) {
+        return (long long)n->dims[0] * (n->dims[1] >> lvl) * (n->dims[2] >> lvl) * (n->dims[3] >> lvl);
+    };
+    const uint16_t* src = nullptr;
+    long long elems = 0;
+    switch (kind) {
+        case MPM_NT_INPUT:
+            src = n->xin;
+            elems = vox(0) * n->layers[0].cin_p;
+            break;
+        case MPM_NT_ACT:
+        case MPM_NT_ACT_GRAD:
+            if (index < 0 || index >= nl - 1) break;
+            src = kind == MPM_NT_ACT ? n->act[index] : n->gin[index];
+            elems = vox(n->lvl_of[index]) * n->layers[index].cout;
+            break;
+        case MPM_NT_POOLED:
+            if (index < 1 || index >= L) break;
+            src = n->pooled[index];
+            elems = vox(index) * n->widths[index - 1];
+            break;
+        case MPM_NT_CAT:
+        case MPM_NT_CAT_GRAD:
+            if (index < 0 || index >= L - 1) break;
+            src = kind == MPM_NT_CAT ? n->cat[index] : n->dcat[index];
+            elems = vox(index) * (n->widths[index + 1] + n->widths[index]);
+            break;
+        case MPM_NT_HEAD_GRAD:
+            src = n->ghead;
+            elems = vox(0) * n->widths[0];
+            break;
+    }
+    if (!src) {
+        set_error("mpm_net_debug_tensor: index out of range for this tensor kind");
+        return MPM_EINVAL;
+    }
+    if (!dst) {
+        *count = elems;
+        return MPM_OK;
+    }
+    if (*count != elems) {
+        set_error("mpm_net_debug_tensor: *count must equal the tensor's element count");
+        return MPM_EINVAL;
+    }
+    MPM_HIP(hipMemcpyAsync(dst, src, (size_t)elems * 2, hipMemcpyDeviceToDevice, n->stream));
+    MPM_HIP(hipStreamSynchronize(n->stream));
+    return MPM_OK;
+}
+
+extern "C" int32_t mpm_net_debug_op(mpm_net net, int32_t op, int32_t nb, int32_t d, int32_t h, int32_t w, int32_t c,
+                                    int32_t c2, const void* a, const void* b, void* out, void* out2) {
+    Net* n = (Net*)net;
+    const bool even = d % 2 == 0 && h % 2 == 0 && w % 2 == 0;
+    if (!n || !a || !out || nb < 1 || d < 1 || h < 1 || w < 1 || c < 1 || op < MPM_OP_POOL || op > MPM_OP_PAD ||
+        (op != MPM_OP_PAD && c % 8)) {
+        set_error("mpm_net_debug_op: bad arguments");
+        return MPM_EINVAL;
+    }
+    hipStream_t st = n->stream;
+    const long long P = (long long)nb * d * h * w;
+    const uint16_t* A = (const uint16_t*)a;
+    const uint16_t* B = (const uint16_t*)b;
+    uint16_t* O = (uint16_t*)out;
+    switch (op) {
+        case MPM_OP_POOL:
+            if (!even) break;
+            k_pool2<<<blocks_for(P / 8 * c / 8), 256, 0, st>>>(A, c, c, nb, d, h, w, O);
+            return net_debug_finish(st);
+        case MPM_OP_POOL_BWD_ADD:
+            if (!even || (B && (c2 < c || c2 % 8))) break;
+            k_pool2_bwd_add<<<blocks_for(P * c / 8), 256, 0, st>>>(A, c, B ? B + (c2 - c) : nullptr, c2, nb, d, h, w, O);
+            return net_debug_finish(st);
+        case MPM_OP_UP2_CAT:
+            if (!even || !B || c2 < 8 || c2 % 8) break;
+            k_up2_cat<<<blocks_for(P * (c + c2) / 8), 256, 0, st>>>(A, c, B, c2, nb, d, h, w, O);
+            return net_debug_finish(st);
+        case MPM_OP_UP2_BWD:
+            if (!even || c2 < 0 || c2 % 8) break;
+            k_up2_bwd<<<blocks_for(P / 8 * c / 8), 256, 0, st>>>(A, c + c2, c, nb, d / 2, h / 2, w / 2, O);
+            return net_debug_finish(st);
+        case MPM_OP_HEAD:
+        case MPM_OP_HEAD_BWD: {
+            const ConvL& hd = n->layers.back();
+            if (c != 16 || hd.cin != 16) break;
+            if (op == MPM_OP_HEAD) {
+                k_head<<<blocks_for(P), 256, 0, st>>>(A, 16, n->theta + hd.woff, n->theta + hd.boff, hd.cout, P,
+                                                    (float*)out);
+                return net_debug_finish(st);
+            }
+            if (!B || !out2) break;
+            // per-chunk partials as in the backward pass, reduced into out2 (zeroed here)
+            const long long nchunk = std::max(1LL, std::min(256LL, P / 4096));
+            const long long per = (P + nchunk - 1) / nchunk;
+            const int npar = hd.cin * hd.cout + hd.cout;
+            float* part = nullptr;
+            MPM_HIP(hipMalloc(&part, (size_t)nchunk * npar * 4));
+            hipError_t e = hipMemsetAsync(out2, 0, (size_t)npar * 4, st);
+            if (e == hipSuccess) {
+                k_head_bwd<<<(unsigned)nchunk, 256, 0, st>>>(A, 16, n->theta + hd.woff, hd.cout, (const float*)B, P, per,
+                                                             O, part);
+                k_param_reduce<<<blocks_for(npar), 256, 0, st>>>(part, (int)nchunk, npar, (float*)out2);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            (void)hipFree(part);
+            if (e != hipSuccess) return hip_fail(e, "mpm_net_debug_op");
+            return MPM_OK;
+        }
+        case MPM_OP_PAD:
+            if (c2 < c || c2 % 8) break;
+            k_pad_channels<<<blocks_for(P), 256, 0, st>>>(A, c, c2, P, O);
+            return net_debug_finish(st);
+    }
+    set_error("mpm_net_debug_op: unsupported shape or channel counts for this operation");
+    return MPM_EINVAL;
 }

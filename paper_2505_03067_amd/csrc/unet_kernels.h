@@ -20,9 +20,11 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-// round to nearest even (finite inputs)
+// round to nearest, ties to even; overflow rounds to infinity, and every NaN becomes
+// the quiet NaN 0x7fc0 (adding the rounding bias to a NaN could carry into the sign)
 __device__ inline uint16_t f2bf(float f) {
     uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }

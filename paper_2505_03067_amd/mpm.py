@@ -109,6 +109,9 @@ def lib() -> ctypes.CDLL:
             "mpm_net_destroy": [_vp],
             "mpm_net_debug_layer": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp],
+            "mpm_net_debug_tensor": [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int64)],
+            "mpm_net_debug_op": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp],
             "mpm_attach_net": [_vp, _vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
             "mpm_ws_pair": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_float), _vp, _vp],
@@ -351,13 +354,27 @@ def mpm_net_destroy(net) -> None:
         lib().mpm_net_destroy(net)
 
 
-def _floats(v):
-    return (ctypes.c_float * len(v))(*[float(a) for a in v])
+MPM_MAX_SPECIES = 4
 
 
-def mpm_attach_net(ctx, net, in_scale, out_scale) -> None:
+def _scales(in_scale, out_scale, nspecies=None):
+    """ctypes arrays of the warm-start scales.  The library reads 4 S + 1 input and S
+    output scales; with ``nspecies`` the lengths must be exactly those, and the arrays
+    are always at least as long as the largest S needs, so no read runs past them."""
+    if nspecies is not None and (len(in_scale) != 4 * nspecies + 1 or len(out_scale) != nspecies):
+        raise ValueError(f"need {4 * nspecies + 1} input scales and {nspecies} output scales, "
+                         f"got {len(in_scale)} and {len(out_scale)}")
+    ni = max(len(in_scale), 4 * MPM_MAX_SPECIES + 1)
+    no = max(len(out_scale), MPM_MAX_SPECIES)
+    a = (ctypes.c_float * ni)(*[float(v) for v in in_scale])
+    b = (ctypes.c_float * no)(*[float(v) for v in out_scale])
+    return a, b
+
+
+def mpm_attach_net(ctx, net, in_scale, out_scale, nspecies=None) -> None:
     h = net.handle if isinstance(net, Net) else net
-    _check(lib().mpm_attach_net(ctx, h, _floats(in_scale), _floats(out_scale)))
+    a, b = _scales(in_scale, out_scale, nspecies)
+    _check(lib().mpm_attach_net(ctx, h, a, b))
 
 
 def mpm_ws_grid(ctx, problem: int = 0):
@@ -366,14 +383,51 @@ def mpm_ws_grid(ctx, problem: int = 0):
     return tuple(g)
 
 
-def mpm_ws_pair(ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target) -> None:
+def mpm_ws_pair(ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target, nspecies=None) -> None:
     import torch
     if in_bf16.dtype not in (torch.int16, torch.uint16, torch.bfloat16) or not in_bf16.is_contiguous():
         raise TypeError("in_bf16 must be a contiguous 16-bit tensor")
+    a, b = _scales(in_scale, out_scale, nspecies)
     _check(lib().mpm_ws_pair(ctx, int(problem), _dev_ptr(c_old, torch.float64, "c_old"),
-                             _dev_ptr(c_new, torch.float64, "c_new"), _floats(in_scale),
-                             _floats(out_scale), ctypes.c_void_p(in_bf16.data_ptr()),
+                             _dev_ptr(c_new, torch.float64, "c_new"), a, b,
+                             ctypes.c_void_p(in_bf16.data_ptr()),
                              _dev_ptr(target, torch.float32, "target")))
+
+
+MPM_NT_INPUT = 0
+MPM_NT_ACT = 1
+MPM_NT_ACT_GRAD = 2
+MPM_NT_POOLED = 3
+MPM_NT_CAT = 4
+MPM_NT_CAT_GRAD = 5
+MPM_NT_HEAD_GRAD = 6
+MPM_OP_POOL = 0
+MPM_OP_POOL_BWD_ADD = 1
+MPM_OP_UP2_CAT = 2
+MPM_OP_UP2_BWD = 3
+MPM_OP_HEAD = 4
+MPM_OP_HEAD_BWD = 5
+MPM_OP_PAD = 6
+
+
+def mpm_net_debug_tensor(net, kind: int, index: int = 0):
+    import torch
+    cnt = ctypes.c_int64(0)
+    _check(lib().mpm_net_debug_tensor(net, int(kind), int(index), None, ctypes.byref(cnt)))
+    t = torch.empty(cnt.value, dtype=torch.int16, device="cuda")
+    _check(lib().mpm_net_debug_tensor(net, int(kind), int(index), ctypes.c_void_p(t.data_ptr()),
+                                      ctypes.byref(cnt)))
+    return t
+
+
+def mpm_net_debug_op(net, op: int, shape, c: int, c2: int, a, b, out, out2=None) -> None:
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    for name, t in (("a", a), ("b", b), ("out", out), ("out2", out2)):
+        if t is not None and (t.device.type != "cuda" or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous GPU tensor")
+    nb, d, h, w = [int(v) for v in shape]
+    _check(lib().mpm_net_debug_op(net, int(op), nb, d, h, w, int(c), int(c2), ptr(a), ptr(b), ptr(out),
+                                  ptr(out2)))
 
 
 class Net:
@@ -426,6 +480,16 @@ class Net:
         _check(lib().mpm_net_debug_layer(self.handle, int(layer), int(mode), nb, d, h, w, ptr(x), ptr(g),
                                          ptr(gate), ctypes.c_void_p(out.data_ptr())))
 
+    def debug_tensor(self, kind, index=0):
+        """A BF16 tensor stored by the last forward/backward pass (see
+        mpm_net_debug_tensor), returned as a flat int16 GPU tensor of bit patterns."""
+        return mpm_net_debug_tensor(self.handle, kind, index)
+
+    def debug_op(self, op, shape, c, c2, a, b, out, out2=None):
+        """One data-movement kernel on caller tensors (see mpm_net_debug_op); ``shape`` is
+        the finer grid (n, d, h, w)."""
+        mpm_net_debug_op(self.handle, op, shape, c, c2, a, b, out, out2)
+
     def close(self):
         mpm_net_destroy(self.handle)
         self.handle = None
@@ -466,13 +530,13 @@ class Solver:
         return mpm_kernel_timing(self.ctx)
 
     def attach(self, net, in_scale, out_scale):
-        mpm_attach_net(self.ctx, net, in_scale, out_scale)
+        mpm_attach_net(self.ctx, net, in_scale, out_scale, self.nspecies)
 
     def ws_grid(self, problem=0):
         return mpm_ws_grid(self.ctx, problem)
 
     def ws_pair(self, problem, c_old, c_new, in_scale, out_scale, in_bf16, target):
-        mpm_ws_pair(self.ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target)
+        mpm_ws_pair(self.ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target, self.nspecies)
 
     def apply(self, problem, x, y, mode):
         return mpm_debug_apply(self.ctx, problem, x, y, mode)

@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from gpu_helpers import require_gpu, to_dev
+from gpu_helpers import rel_err, require_gpu, to_dev
 from synth import random_problem
 
 pytestmark = pytest.mark.gpu
@@ -60,7 +60,7 @@ def test_autotuned_split_is_reported_and_parity_holds():
     mb = p.mask.astype(bool)
     got = f.cpu().numpy()
     for sp in range(3):
-        err = np.linalg.norm(got[sp][mb] - want[sp][mb]) / np.linalg.norm(want[sp][mb])
+        err = rel_err(got[sp][mb], want[sp][mb])
         assert err <= 1e-8
 
 

@@ -1,11 +1,12 @@
 """GPU parity of the warm-start U-Net kernels against the FP64 oracle.
 
-The oracle runs with ``store_bf16=True``: FP64 arithmetic, with the 3x3x3 weights and
-every stored activation and activation gradient rounded to BFloat16 at the points
-where the GPU stores them, so the remaining difference is FP32 accumulation order
-(plus rare BF16 rounding flips near a tie).  Bar: relative L2 error <= 5e-3 for the
-output and for every layer's weight gradient; the FP64-only oracle (no rounding) is
-checked separately at a BF16-level tolerance.
+Three levels: (1) single layers and every data-movement kernel on small-integer data,
+where FP32 accumulation is exact, bit for bit (here and in test_gpu_unet_ops.py);
+(2) every step of a whole forward and backward pass against the oracle fed the GPU's
+own stored BF16 tensors, relative L2 error <= 1e-3; (3) the whole network against the
+BF16-storage oracle (FP64 arithmetic, BF16 rounding of weights, activations and
+activation gradients where the GPU stores them), with bars derived from the oracle's
+own spread between FP64 and FP32 accumulation.
 """
 
 import numpy as np
@@ -62,55 +63,230 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _self_spread(th, x, widths):
-    """How far the BF16-storage oracle moves when its convolutions accumulate in FP32
-    instead of FP64: a lower bound for any FP32-accumulating implementation."""
-    orig = unet.conv3
+# Tap orders of the FP32-accumulating oracle variants: natural, reversed, even taps then
+# odd taps, centre tap first.  Each is another order of the same FP32 sums.
+TAP_ORDERS = [list(range(27)), list(range(26, -1, -1)), list(range(0, 27, 2)) + list(range(1, 27, 2)),
+              [13] + [t for t in range(27) if t != 13]]
 
-    def conv3_f32(a, W, b):
-        return orig(a.astype(np.float32), W.astype(np.float32), b.astype(np.float32)).astype(np.float64)
 
-    ref = unet.forward(th, x, 13, 3, widths, store_bf16=True)
-    unet.conv3 = conv3_f32
-    try:
-        alt = unet.forward(th, x, 13, 3, widths, store_bf16=True)
-    finally:
-        unet.conv3 = orig
-    return _rel(alt, ref)
+def _conv3_f32(order):
+    """conv3 with FP32 storage and FP32 accumulation over the taps in 'order'."""
+    def conv(a, W, b):
+        a32, W32 = a.astype(np.float32), W.astype(np.float32)
+        n, D, H, Wd, ci = a.shape
+        xp = np.zeros((n, D + 2, H + 2, Wd + 2, ci), np.float32)
+        xp[:, 1:-1, 1:-1, 1:-1, :] = a32
+        out = np.broadcast_to(np.asarray(b, np.float32), (n, D, H, Wd, W.shape[2])).copy()
+        for t in order:
+            dz, dy, dx = unet.TAPS[t]
+            out += xp[:, 1 + dz:1 + dz + D, 1 + dy:1 + dy + H, 1 + dx:1 + dx + Wd, :] @ W32[t]
+        return out.astype(np.float64)
+    return conv
+
+
+def _conv3_backward_f32(order):
+    """conv3_backward with FP32 storage and FP32 accumulation over the taps in 'order'."""
+    def conv_b(a, W, g):
+        a32, W32, g32 = a.astype(np.float32), W.astype(np.float32), g.astype(np.float32)
+        n, D, H, Wd, ci = a.shape
+        xp = np.zeros((n, D + 2, H + 2, Wd + 2, ci), np.float32)
+        xp[:, 1:-1, 1:-1, 1:-1, :] = a32
+        dxp = np.zeros_like(xp)
+        dW = np.zeros(W.shape, np.float32)
+        for t in order:
+            dz, dyy, dx = unet.TAPS[t]
+            sl = (slice(None), slice(1 + dz, 1 + dz + D), slice(1 + dyy, 1 + dyy + H),
+                  slice(1 + dx, 1 + dx + Wd), slice(None))
+            dW[t] = np.tensordot(xp[sl], g32, axes=([0, 1, 2, 3], [0, 1, 2, 3]))
+            dxp[sl] += g32 @ W32[t].T
+        db = g32.sum(axis=(0, 1, 2, 3), dtype=np.float32)
+        return (dxp[:, 1:-1, 1:-1, 1:-1, :].astype(np.float64), dW.astype(np.float64), db.astype(np.float64))
+    return conv_b
+
+
+def _oracle_fp32_accumulation(th, x, target, widths, monkeypatch, order):
+    """The BF16-storage oracle with its convolutions accumulated in FP32 (taps in
+    'order') instead of FP64: output and parameter gradient of an implementation that
+    stores what the GPU stores and accumulates in FP32, in another order than the GPU's.
+    Its distance to the FP64-accumulating oracle is the spread that BF16 rounding flips
+    and ReLU gate flips alone produce, whatever the kernels do."""
+    with monkeypatch.context() as mp:
+        mp.setattr(unet, "conv3", _conv3_f32(order))
+        mp.setattr(unet, "conv3_backward", _conv3_backward_f32(order))
+        out, acts = unet.forward(th, x, 13, 3, widths, keep=True, store_bf16=True)
+        _, dout = unet.mse(out, target.astype(np.float64))
+        g, _ = unet.backward(th, acts, dout, 13, 3, widths, store_bf16=True)
+    return out, g
+
+
+def _per_layer(widths, a, b):
+    errs, o = [], 0
+    for ci, co, t in unet.layer_shapes(13, 3, widths):
+        nw = t * ci * co
+        errs.append(max(_rel(a[o:o + nw], b[o:o + nw]), _rel(a[o + nw:o + nw + co], b[o + nw:o + nw + co])))
+        o += nw + co
+    return errs
 
 
 # the first decoder convolution of each level reads the upsampled deeper output and the
 # skip directly (for [16, 48] the upsampled input is three 16-channel chunks)
 @pytest.mark.parametrize("widths,shape", [([16, 32], (2, 8, 8, 16)), ([16, 32, 64, 64], (1, 16, 16, 16)),
                                           ([16, 32, 64, 64], (2, 8, 16, 24)), ([16, 48], (1, 6, 8, 18))])
-def test_forward_backward_match_oracle(widths, shape):
+def test_forward_backward_match_oracle(widths, shape, monkeypatch):
+    """The whole network against the BF16-storage oracle.  Both round to BF16 at the
+    same points, so they differ only where an FP32 sum and an FP64 sum round to
+    different BF16 values (one unit in the last place) or fall on different sides of a
+    ReLU.  Such a flip changes the 27 C_out outputs that read the voxel slightly, some of
+    those cross a rounding boundary in turn, and the differences spread layer after
+    layer and furthest into the gradients of the first layers (on the GPU the first
+    layer differs from the oracle in 2 of 32,768 stored values and the sixth in 6.5%).
+    The bar is therefore derived per quantity from the oracle itself: the largest
+    distance between the FP64-accumulating oracle and four variants accumulating in FP32
+    with the taps in different orders, with a factor 4 of room, and a floor of 1e-3
+    (the survey's bar for the network kernels).  Each step on its own inputs is held to
+    1e-3 by test_layerwise_chain_matches_oracle and to exact equality on integer data
+    by test_single_layer_kernels_exact and test_gpu_unet_ops.py."""
     outg, ref, grads, gref, loss_gpu, loss_ref, th, x, target = _run(widths, shape, seed=len(widths) * 7 + shape[1])
+    s_out, s_loss, s_layers, s_all = 0.0, 0.0, None, 0.0
+    for order in TAP_ORDERS:
+        alt_out, alt_g = _oracle_fp32_accumulation(th, x, target, widths, monkeypatch, order)
+        loss_alt, _ = unet.mse(alt_out, target.astype(np.float64))
+        s_out = max(s_out, _rel(alt_out, ref))
+        s_loss = max(s_loss, abs(loss_alt - loss_ref) / loss_ref)
+        sl = _per_layer(widths, alt_g, gref)
+        s_layers = sl if s_layers is None else [max(a, c) for a, c in zip(s_layers, sl)]
+        s_all = max(s_all, _rel(alt_g, gref))
     e_out = _rel(outg, ref)
-    spread = _self_spread(th, x, widths)
-    print("output rel err", e_out, "oracle FP32-accumulation spread", spread)
-    assert e_out <= max(5e-3, 5 * spread)
-    assert abs(loss_gpu - loss_ref) <= 1e-2 * loss_ref
-    o = 0
-    errs = []
+    print(f"output rel err {e_out:.2e}, oracle FP32-accumulation spread {s_out:.2e}")
+    assert e_out <= max(1e-3, 4 * s_out)
+    assert abs(loss_gpu - loss_ref) <= max(1e-3, 4 * s_loss) * loss_ref
+    errs = _per_layer(widths, grads, gref)
     for li, (ci, co, t) in enumerate(unet.layer_shapes(13, 3, widths)):
-        nw = t * ci * co
-        ew = _rel(grads[o:o + nw], gref[o:o + nw])
-        eb = _rel(grads[o + nw:o + nw + co], gref[o + nw:o + nw + co])
-        print(f"layer {li} ({ci}->{co}, {t} taps): dW rel {ew:.2e}, db rel {eb:.2e}")
-        errs.append(max(ew, eb))
-        o += nw + co
-    # the gradient chain crosses every stored BF16 tensor; flips of single BF16
-    # roundings (FP32 vs FP64 accumulation) and of ReLU gates near zero are amplified
-    # most at the deepest, smallest levels, so the bar here is BF16 level on each
-    # layer and on the direction of the whole gradient; the exact per-kernel parity
-    # is test_single_layer_kernels_exact
-    assert max(errs) <= 1e-1, errs
-    cos = float(grads @ gref / (np.linalg.norm(grads) * np.linalg.norm(gref)))
-    print("gradient cosine", cos)
-    assert cos >= 0.995
+        print(f"layer {li} ({ci}->{co}, {t} taps): gradient rel err {errs[li]:.2e}, "
+              f"oracle FP32-accumulation spread {s_layers[li]:.2e}")
+    e_all = _rel(grads, gref)
+    print(f"whole gradient rel err {e_all:.2e}, spread {s_all:.2e}")
+    for li in range(len(errs)):
+        assert errs[li] <= max(1e-3, 4 * s_layers[li]), (li, errs[li], s_layers[li])
+    assert e_all <= max(1e-3, 4 * s_all)
     # against the plain FP64 network the difference is at BF16 level
     plain = unet.forward(th, x, 13, 3, widths)
     assert _rel(outg, plain) <= 3e-2
+
+
+def _tensor(net, kind, index, shape, ch):
+    t = net.debug_tensor(kind, index).cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return t.view(np.float32).astype(np.float64).reshape(tuple(shape) + (ch,))
+
+
+@pytest.mark.parametrize("widths,shape", [([16, 32], (2, 8, 8, 16)), ([16, 32, 64, 64], (1, 16, 16, 16)),
+                                          ([16, 32, 64, 64], (2, 8, 16, 24))])
+def test_layerwise_chain_matches_oracle(widths, shape):
+    """Every step of the GPU's forward and backward pass against the oracle fed the
+    GPU's own stored BF16 tensors: each convolution's output, weight and bias gradients
+    and stored input gradient, each pooling, concatenation, upsampling gradient and
+    pooling-gradient-plus-skip, the head and the loss gradient.  From identical inputs
+    the two differ only by FP32 against FP64 accumulation (and the rare BF16 rounding it
+    flips), so each is held to a relative L2 error of 1e-3."""
+    torch = require_gpu()
+    import paper_2505_03067_amd.mpm as b
+    from paper_2505_03067_amd import Net
+    seed = 5 + len(widths)
+    rng = np.random.default_rng(seed)
+    n, d, h, w = shape
+    L = len(widths)
+    in_ch, out_ch = 13, 3
+    net = Net(in_ch, out_ch, widths, seed=seed)
+    theta = np.empty(net.count, np.float32)
+    for W, bias in unet.unpack(theta, in_ch, out_ch, widths):
+        W[:] = rng.normal(scale=np.sqrt(2.0 / (W.shape[0] * W.shape[1])), size=W.shape)
+        bias[:] = rng.normal(scale=0.05, size=bias.shape)
+    net.set_params(torch.from_numpy(theta).cuda())
+    x = unet.bf16(rng.uniform(-1, 1, size=(n, d, h, w, in_ch)))
+    out = torch.empty((n, d, h, w, out_ch), dtype=torch.float32, device="cuda")
+    net.forward(torch.from_numpy(_bf16_bits(x).view(np.int16)).cuda(), out)
+    target = rng.normal(size=(n, d, h, w, out_ch)).astype(np.float32)
+    gout = torch.empty_like(out)
+    net.mse(out, torch.from_numpy(target).cuda(), gout)
+    net.zero_grad()
+    net.backward(gout)
+    grads = net.grads().cpu().numpy().astype(np.float64)
+    outg = out.cpu().numpy().astype(np.float64)
+    goutg = gout.cpu().numpy().astype(np.float64)
+
+    shapes = unet.layer_shapes(in_ch, out_ch, widths)
+    nl = len(shapes)
+    lvl_of = [l for l in range(L) for _ in range(2)] + [l for l in range(L - 2, -1, -1) for _ in range(2)]
+    grid = lambda lvl: (n, d >> lvl, h >> lvl, w >> lvl)
+    acts = [_tensor(net, b.MPM_NT_ACT, li, grid(lvl_of[li]), shapes[li][1]) for li in range(nl - 1)]
+    gacts = [_tensor(net, b.MPM_NT_ACT_GRAD, li, grid(lvl_of[li]), shapes[li][1]) for li in range(nl - 2)]
+    gacts.append(_tensor(net, b.MPM_NT_HEAD_GRAD, 0, grid(0), widths[0]))
+    xin = _tensor(net, b.MPM_NT_INPUT, 0, grid(0), 16)
+    pooled = {l: _tensor(net, b.MPM_NT_POOLED, l, grid(l), widths[l - 1]) for l in range(1, L)}
+    cat = {l: _tensor(net, b.MPM_NT_CAT, l, grid(l), widths[l + 1] + widths[l]) for l in range(L - 1)}
+    dcat = {l: _tensor(net, b.MPM_NT_CAT_GRAD, l, grid(l), widths[l + 1] + widths[l]) for l in range(L - 1)}
+    net.close()
+
+    layers = unet.unpack(theta.astype(np.float64), in_ch, out_ch, widths)
+    bar = 1e-3
+    report = []
+
+    def check(name, got, want, tol=bar):
+        e = _rel(got, want)
+        diff = float(np.mean(np.asarray(got) != np.asarray(want)))
+        report.append(f"{name}: rel err {e:.2e}, elements that differ {diff:.2e}")
+        assert e <= tol, (name, e)
+
+    # input padding is a copy
+    assert np.array_equal(xin[..., :in_ch], x) and not xin[..., in_ch:].any()
+    # head and loss gradient (FP32 on the GPU)
+    Wh, bh = layers[-1]
+    check("head output", outg, unet.conv1(acts[-1], Wh, bh), 1e-6)
+    _, g_ref = unet.mse(outg, target.astype(np.float64))
+    check("loss gradient", goutg, g_ref, 1e-6)
+    check("head input gradient", gacts[-1], unet.bf16(goutg @ Wh[0].T))
+    o_head = sum(t * ci * co + co for ci, co, t in shapes[:-1])
+    dWh = np.tensordot(acts[-1], goutg, axes=([0, 1, 2, 3], [0, 1, 2, 3]))
+    check("head parameter gradient", grads[o_head:], np.concatenate([dWh.ravel(), goutg.sum(axis=(0, 1, 2, 3))]), 1e-5)
+
+    o = 0
+    for li in range(nl - 1):
+        ci, co, _ = shapes[li]
+        W, bias = layers[li]
+        Wb = unet.bf16(W)
+        lvl = lvl_of[li]
+        enc = li < 2 * L
+        first = li % 2 == 0
+        if enc and first:
+            xl = xin[..., :in_ch] if lvl == 0 else pooled[lvl]
+            if lvl > 0:
+                check(f"pooling into level {lvl}", pooled[lvl], unet.bf16(unet.pool2(acts[li - 1])))
+        elif not enc and first:
+            xl = cat[lvl]
+            assert np.array_equal(cat[lvl], np.concatenate([unet.up2(acts[li - 1]), acts[2 * lvl + 1]], axis=-1))
+        else:
+            xl = acts[li - 1]
+        check(f"layer {li} forward", acts[li], unet.bf16(np.maximum(unet.conv3(xl, Wb, bias), 0.0)))
+        dpre = gacts[li] * (acts[li] > 0)
+        dx, dW, db = unet.conv3_backward(xl, Wb, dpre)
+        nw = 27 * ci * co
+        check(f"layer {li} weight gradient", grads[o:o + nw], dW.ravel())
+        check(f"layer {li} bias gradient", grads[o + nw:o + nw + co], db)
+        o += nw + co
+        if enc and not first:
+            check(f"layer {li} input gradient", gacts[li - 1], unet.bf16(dx))
+        elif not enc and not first:
+            check(f"layer {li} input gradient", gacts[li - 1], unet.bf16(dx))
+        elif not enc and first:
+            check(f"layer {li} input gradient (concatenation)", dcat[lvl], unet.bf16(dx))
+            cu = widths[lvl + 1]
+            check(f"upsampling gradient into layer {li - 1}", gacts[li - 1],
+                  unet.bf16(unet.up2_backward(dcat[lvl][..., :cu])))
+        elif lvl > 0:
+            # gradient of the pooled input, then the pooling gradient plus the skip's
+            want = unet.bf16(unet.pool2_backward(unet.bf16(dx)) + dcat[lvl - 1][..., widths[lvl]:])
+            check(f"pooling gradient + skip into layer {li - 1}", gacts[li - 1], want)
+    print("\n".join(report))
 
 
 @pytest.mark.parametrize("widths,li,shape", [([16, 32], 0, (2, 8, 8, 16)), ([16, 32], 1, (1, 8, 6, 16)),

@@ -13,39 +13,92 @@ from synth import config1, config4_patch, random_problem
 pytestmark = pytest.mark.gpu
 
 
-def _bits(a):
-    return (np.asarray(a, np.float32).view(np.uint32) >> 16).astype(np.uint16)
+def _torch_bf16_bits(a):
+    """BF16 bit patterns from PyTorch's CPU float32 -> bfloat16 cast (an implementation
+    of round-to-nearest-even independent of the library's)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).to(torch.bfloat16)
+    return t.view(torch.int16).numpy().view(np.uint16)
 
 
-def test_ws_pair_matches_definition():
+def _ws_pair_case(p, S, box=None):
+    """Network input and training target built by the library, against their
+    definition: each channel (c^n, k, D, s per species, then the mask) times its scale,
+    rounded to BF16 on the box grid (zero past the box); target (c^{n+1} - c^n) /
+    out_scale on domain voxels, zero elsewhere."""
     torch = require_gpu()
     import paper_2505_03067_amd as m
-    from paper_2505_03067_amd.train import IN_SCALE
-    p = config4_patch(3, n=32)
+    from oracle.fv import box_slice
+    from paper_2505_03067_amd.train import input_scales
+    box = box if box is not None else p.box
+    in_scale = input_scales(S)
+    out_scale = [0.5, 0.25, 2e-3, 3e-3][:S]
     d = to_dev(p)
     f = torch.from_numpy(p.c0).cuda()
-    out_scale = [0.5, 0.25, 2e-3]
-    with m.Solver(3, 1, warm_start=m.MPM_WS_NET) as s:
-        s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+    with m.Solver(S, 1, warm_start=m.MPM_WS_NET) as s:
+        s.setup(0, box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
         old = f.clone()
         s.step([f], 1e-10)
         gx, gy, gz = s.ws_grid(0)
-        assert (gx, gy, gz) == (32, 32, 32)
-        inp = torch.empty((gz, gy, gx, 13), dtype=torch.int16, device="cuda")
-        tgt = torch.empty((gz, gy, gx, 3), dtype=torch.float32, device="cuda")
-        s.ws_pair(0, old, f, IN_SCALE, out_scale, inp, tgt)
+        ext = [hi - lo for lo, hi in zip(*box)]
+        assert (gx, gy, gz) == tuple((e + 7) // 8 * 8 for e in ext)
+        inp = torch.empty((gz, gy, gx, 4 * S + 1), dtype=torch.int16, device="cuda")
+        tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
+        s.ws_pair(0, old, f, in_scale, out_scale, inp, tgt)
     got_in = inp.cpu().numpy().view(np.uint16)
     got_t = tgt.cpu().numpy()
     c0 = old.cpu().numpy()
     c1 = f.cpu().numpy()
-    chans = [c0[s] for s in range(3)] + [p.k[s] for s in range(3)] + [p.D[s] for s in range(3)] + \
-            [p.src[s] for s in range(3)] + [p.mask.astype(np.float64)]
+    sl = box_slice(box)
+    chans = [c0[s] for s in range(S)] + [p.k[s] for s in range(S)] + [p.D[s] for s in range(S)] + \
+            [p.src[s] for s in range(S)] + [p.mask.astype(np.float64)]
+    ex, ey, ez = ext
     for ch, a in enumerate(chans):
-        want = _bits(unet.bf16(a.astype(np.float32) * np.float32(IN_SCALE[ch])))
+        want = np.zeros((gz, gy, gx), np.uint16)
+        want[:ez, :ey, :ex] = _torch_bf16_bits(a[sl].astype(np.float32) * np.float32(in_scale[ch]))
         assert np.array_equal(got_in[..., ch], want), ch
-    for s in range(3):
-        want = ((c1[s] - c0[s]) / np.float64(np.float32(out_scale[s]))).astype(np.float32)
-        assert np.array_equal(got_t[..., s], want)
+    dom = np.zeros((gz, gy, gx), bool)
+    dom[:ez, :ey, :ex] = p.mask[sl] != 0
+    for s in range(S):
+        want = np.zeros((gz, gy, gx), np.float32)
+        full = ((c1[s] - c0[s]) / np.float64(np.float32(out_scale[s])))[sl].astype(np.float32)
+        want[:ez, :ey, :ex] = full
+        want[~dom] = 0.0
+        assert np.array_equal(got_t[..., s], want), s
+
+
+def test_ws_pair_matches_definition():
+    _ws_pair_case(config4_patch(3, n=32), 3)
+
+
+def test_ws_pair_matches_definition_four_species():
+    """Four species: 17 input channels, the output scales after all of them (a layout
+    that once let the fourth species' input scales overlap the output scales); a ragged,
+    masked box whose grid is padded past it on every axis."""
+    p = random_problem(91, (30, 27, 21), S=4, fill=0.7)
+    _ws_pair_case(p, 4, box=((2, 3, 1), (27, 26, 18)))
+
+
+def test_four_species_network_attaches_and_falls_back():
+    """A 17-channel network on a four-species context: the zero prediction is rejected
+    for every system and the solve matches the oracle."""
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    from paper_2505_03067_amd.train import input_scales
+    p = random_problem(92, (24, 20, 16), S=4, fill=0.7)
+    d = to_dev(p)
+    f = torch.from_numpy(p.c0).cuda()
+    net = m.Net(17, 4, [16, 32], seed=4)
+    with m.Solver(4, 1, warm_start=m.MPM_WS_NET) as s:
+        s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+        with pytest.raises(ValueError):
+            s.attach(net, input_scales(3), [0.0] * 4)       # 13 scales for 4 species
+        s.attach(net, input_scales(4), [0.0] * 4)
+        for _ in range(2):
+            s.step([f], 1e-10)
+            assert all(s.stats(0, sp)["fallback"] == 1 for sp in range(4))
+    net.close()
+    _check_oracle(p, 2, f.cpu().numpy())
 
 
 def _plain_and_ws(p, steps, setup_net, tile=2048):
@@ -86,6 +139,20 @@ def test_zero_prediction_falls_back_to_plain():
         for s in row:
             assert s["fallback"] == 1 and s["warm_start_used"] == 0
             assert s["rel_res_warm"] == s["rel_res_initial"]
+    _check_oracle(p, 2, f1)
+
+
+def _check_oracle(p, steps, got, tol=1e-10):
+    """The fields against the oracle's CG solve to 1e-13, at the 1e-8 parity bar in the
+    L2 and the max norm (the L2 error is bounded by steps kappa (tol + 1e-13) with
+    kappa <= 1 + dt (k_max + 12 D_max / h^2), which is printed)."""
+    want, _ = run(p, steps=steps, solver="pcg", tol=1e-13)
+    mb = p.mask[box_slice(p.box)].astype(bool)
+    kappa = 1 + p.dt * (p.k.max() + 12 * p.D.max() / p.h ** 2)
+    bound = steps * kappa * (tol + 1e-13)
+    errs = rel_err_per_species(got, want, mb, p.box)
+    print(f"{p.name}: rel err vs oracle {errs}, kappa bound {bound:.2e}", flush=True)
+    assert max(errs) <= 1e-8, errs
 
 
 def test_poisoned_network_falls_back():
@@ -103,6 +170,7 @@ def test_poisoned_network_falls_back():
     (f0, _), (f1, st1) = _plain_and_ws(p, 2, setup)
     assert np.array_equal(f0, f1)
     assert all(s["fallback"] == 1 for row in st1 for s in row)
+    _check_oracle(p, 2, f1)
 
 
 def test_extrapolated_start_parity():
@@ -140,7 +208,6 @@ def test_learned_warm_start_gains_over_plain():
     evalp = [config4_patch(10_000 + i, n=32) for i in range(2)]
     it_plain, sps_plain, f_plain, _ = tr.evaluate(evalp, 10, 1e-8)
     it_ws, sps_ws, f_ws, acc = tr.evaluate(evalp, 10, 1e-8, net=net, out_scale=out_scale, warm=m.MPM_WS_NET)
-    net.close()
     print(f"iterations/step plain {it_plain:.2f} learned {it_ws:.2f}; accepted {acc:.2f}; "
           f"steps/s plain {sps_plain:.1f} learned {sps_ws:.1f}")
     assert acc > 0.5
@@ -148,3 +215,19 @@ def test_learned_warm_start_gains_over_plain():
     kappa = 1 + 1.0 * (0.2 + 12 * 1.5)
     for a, b in zip(f_plain, f_ws):
         assert np.linalg.norm(a - b) <= 2 * kappa * 1e-8 * np.linalg.norm(a)
+    # the learned-start solve itself against the oracle: one unseen patch, solved to
+    # 1e-12 from the accepted learned start, every field within 1e-8 of the oracle's CG
+    p = evalp[0]
+    d = to_dev(p)
+    f = torch.from_numpy(p.c0).cuda()
+    used = 0
+    with m.Solver(3, 1, warm_start=m.MPM_WS_NET) as s:
+        s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+        s.attach(net, tr.input_scales(3), out_scale)
+        for _ in range(4):
+            s.step([f], 1e-12)
+            used += sum(s.stats(0, sp)["warm_start_used"] for sp in range(3))
+    net.close()
+    print(f"learned start accepted for {used} of 12 systems at tol 1e-12", flush=True)
+    assert used >= 6
+    _check_oracle(p, 4, f.cpu().numpy(), tol=1e-12)
