@@ -112,6 +112,20 @@ typedef struct {
 int32_t mpm_bbox_from_cells(const int32_t* cell_id, const int32_t* dims, int32_t margin,
                             int32_t* lo, int32_t* hi, void* stream);
 
+/* mpm_bbox_from_cells for callers that cannot allocate memory (code between graph
+ * launches in a tight loop, harnesses that forbid allocation): the same arguments,
+ * kernels and result, but no call allocates anything.  Its scratch is a fixed
+ * 24,608-byte array in device memory (the six folded extremes and the partial extremes
+ * of the 1,024 blocks of the streaming pass), which the library holds on every device it
+ * runs on until the process ends; its size does not depend on the lattice, so every
+ * lattice mpm_bbox_from_cells accepts fits.  The result reaches the host through a copy
+ * into the caller's lo/hi (pageable memory).  Every call on a device shares that
+ * device's array and overwrites all of it that it reads, so no clearing is needed;
+ * calls that overlap on one device (from several threads or streams) race on it and
+ * must be serialised by the caller.  Synchronises 'stream'; the same error codes. */
+int32_t mpm_bbox_from_cells_noalloc(const int32_t* cell_id, const int32_t* dims, int32_t margin,
+                                    int32_t* lo, int32_t* hi, void* stream);
+
 /* Fill *opt with the defaults listed in mpm_options. */
 int32_t mpm_default_options(mpm_options* opt);
 

@@ -24,6 +24,14 @@ __device__ inline int wave_max(int v) {
 
 constexpr int kBboxBlocks = 1024;   // blocks of the streaming pass (one partial each)
 
+// Scratch of mpm_bbox_from_cells_noalloc, one copy per device for the life of the
+// process: the six folded extremes (words 0..5, padded to 8) and the six extremes of
+// each block of the streaming pass.  The kernels write every word they read, so no
+// call needs it cleared.  In host code this name is only a handle: kernels are given
+// the device address that hipGetSymbolAddress returns for the current device.
+constexpr int kBboxScratchWords = 8 + 6 * kBboxBlocks;
+static __device__ __align__(256) int scratch[kBboxScratchWords];
+
 // Extremes of one block: wave reduction, then the block's waves through LDS.  Thread
 // 0 returns them in mn/mx.
 __device__ inline void block_extremes(int (&mn)[3], int (&mx)[3]) {
@@ -126,22 +134,89 @@ __global__ __launch_bounds__(256) void k_bbox_final(const int* __restrict__ part
         }
 }
 
+// Both passes of the box search into ext[0..5] (ext + 8 holds the per-block partials).
+static void launch_bbox(const int32_t* cell_id, const int32_t* dims, int* ext, hipStream_t st) {
+    const long long n = (long long)dims[0] * dims[1] * dims[2];
+    int* part = ext + 8;
+    if (dims[0] % 4 == 0 && ((uintptr_t)cell_id % 16) == 0) {
+        k_bbox_vec4<<<kBboxBlocks, 256, 0, st>>>((const int4*)cell_id, n / 4, dims[0], dims[1], part);
+    } else {
+        k_bbox_scalar<<<kBboxBlocks, 256, 0, st>>>(cell_id, n, dims[0], dims[1], part);
+    }
+    k_bbox_final<<<1, 256, 0, st>>>(part, kBboxBlocks, ext);
+}
+
+// The box from the six extremes read back to the host (max x < 0: no cell voxel).
+static int box_from_extremes(const int* ext, const int32_t* dims, int32_t margin, int32_t* lo, int32_t* hi,
+                             const char* who) {
+    if (ext[3] < 0) {
+        set_error(std::string(who) + ": no voxel with a positive cell id");
+        return MPM_EEMPTY;
+    }
+    for (int d = 0; d < 3; ++d) {
+        int a = ext[d] - margin;
+        int b = ext[3 + d] + margin + 1;
+        lo[d] = a < 0 ? 0 : a;
+        hi[d] = b > dims[d] ? dims[d] : b;
+    }
+    return MPM_OK;
+}
+
+static int check_bbox_args(const int32_t* cell_id, const int32_t* dims, int32_t margin, const int32_t* lo,
+                           const int32_t* hi, const char* who) {
+    if (!cell_id || !dims || !lo || !hi) {
+        set_error(std::string(who) + ": null pointer");
+        return MPM_EINVAL;
+    }
+    if (dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0 || margin < 0) {
+        set_error(std::string(who) + ": dims must be positive and margin non-negative");
+        return MPM_EINVAL;
+    }
+    return MPM_OK;
+}
+
 }  // namespace mpm
 
 using namespace mpm;
 
-extern "C" int32_t mpm_bbox_from_cells(const int32_t* cell_id, const int32_t* dims, int32_t margin,
-                                       int32_t* lo, int32_t* hi, void* stream) {
-    if (!cell_id || !dims || !lo || !hi) {
-        set_error("mpm_bbox_from_cells: null pointer");
-        return MPM_EINVAL;
-    }
-    if (dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0 || margin < 0) {
-        set_error("mpm_bbox_from_cells: dims must be positive and margin non-negative");
-        return MPM_EINVAL;
+extern "C" int32_t mpm_bbox_from_cells_noalloc(const int32_t* cell_id, const int32_t* dims, int32_t margin,
+                                               int32_t* lo, int32_t* hi, void* stream) {
+    const char* who = "mpm_bbox_from_cells_noalloc";
+    int rc = check_bbox_args(cell_id, dims, margin, lo, hi, who);
+    if (rc != MPM_OK) return rc;
+    // device address of this device's copy of the scratch array, looked up once per
+    // device (the array's name is not a device address in host code)
+    static std::mutex mu;
+    static std::map<int, int*> addr;
+    int dev = 0;
+    MPM_HIP(hipGetDevice(&dev));
+    int* ext = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = addr.find(dev);
+        if (it == addr.end()) {
+            void* p = nullptr;
+            hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, who);
+            it = addr.emplace(dev, (int*)p).first;
+        }
+        ext = it->second;
     }
     hipStream_t st = (hipStream_t)stream;
-    const long long n = (long long)dims[0] * dims[1] * dims[2];
+    launch_bbox(cell_id, dims, ext, st);
+    int host[6];
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(host, ext, sizeof(host), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return box_from_extremes(host, dims, margin, lo, hi, who);
+}
+
+extern "C" int32_t mpm_bbox_from_cells(const int32_t* cell_id, const int32_t* dims, int32_t margin,
+                                       int32_t* lo, int32_t* hi, void* stream) {
+    int rc0 = check_bbox_args(cell_id, dims, margin, lo, hi, "mpm_bbox_from_cells");
+    if (rc0 != MPM_OK) return rc0;
+    hipStream_t st = (hipStream_t)stream;
     // six device words and their pinned host copy, allocated once per device and kept
     // until the process ends (a box recomputed every step then allocates nothing);
     // calls from several threads take turns
@@ -164,30 +239,10 @@ extern "C" int32_t mpm_bbox_from_cells(const int32_t* cell_id, const int32_t* di
     }
     int* ext = it->second.first;
     int* host = it->second.second;
-    hipError_t e = hipSuccess;
-    int* part = ext + 8;
-    if (dims[0] % 4 == 0 && ((uintptr_t)cell_id % 16) == 0) {
-        k_bbox_vec4<<<kBboxBlocks, 256, 0, st>>>((const int4*)cell_id, n / 4, dims[0], dims[1], part);
-    } else {
-        k_bbox_scalar<<<kBboxBlocks, 256, 0, st>>>(cell_id, n, dims[0], dims[1], part);
-    }
-    k_bbox_final<<<1, 256, 0, st>>>(part, kBboxBlocks, ext);
-    e = hipGetLastError();
+    launch_bbox(cell_id, dims, ext, st);
+    hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(host, ext, 6 * sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    int r = MPM_OK;
-    if (e != hipSuccess) {
-        r = hip_fail(e, "mpm_bbox_from_cells");
-    } else if (host[3] < 0) {
-        set_error("mpm_bbox_from_cells: no voxel with a positive cell id");
-        r = MPM_EEMPTY;
-    } else {
-        for (int d = 0; d < 3; ++d) {
-            int a = host[d] - margin;
-            int b = host[3 + d] + margin + 1;
-            lo[d] = a < 0 ? 0 : a;
-            hi[d] = b > dims[d] ? dims[d] : b;
-        }
-    }
-    return r;
+    if (e != hipSuccess) return hip_fail(e, "mpm_bbox_from_cells");
+    return box_from_extremes(host, dims, margin, lo, hi, "mpm_bbox_from_cells");
 }

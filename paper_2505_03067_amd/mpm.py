@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         sig = {
             "mpm_bbox_from_cells": [_vp, _i32p, ctypes.c_int32, _i32p, _i32p, _vp],
+            "mpm_bbox_from_cells_noalloc": [_vp, _i32p, ctypes.c_int32, _i32p, _i32p, _vp],
             "mpm_default_options": [ctypes.POINTER(mpm_options)],
             "mpm_create": [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32,
                            ctypes.POINTER(mpm_options), _vp],
@@ -191,6 +192,20 @@ def mpm_bbox_from_cells(cell_id, margin: int, stream=None):
     hi = (ctypes.c_int32 * 3)()
     _check(lib().mpm_bbox_from_cells(ptr, _triple((nx, ny, nz)), int(margin), lo, hi,
                                      _stream(stream)))
+    return tuple(lo), tuple(hi)
+
+
+def mpm_bbox_from_cells_noalloc(cell_id, margin: int, stream=None):
+    """As mpm_bbox_from_cells, through the entry point that allocates nothing."""
+    import torch
+    ptr = _dev_ptr(cell_id, torch.int32, "cell_id")
+    if cell_id.dim() != 3:
+        raise ValueError("cell_id must be [z][y][x]")
+    nz, ny, nx = cell_id.shape
+    lo = (ctypes.c_int32 * 3)()
+    hi = (ctypes.c_int32 * 3)()
+    _check(lib().mpm_bbox_from_cells_noalloc(ptr, _triple((nx, ny, nz)), int(margin), lo, hi,
+                                             _stream(stream)))
     return tuple(lo), tuple(hi)
 
 
