@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -51,6 +53,14 @@ def parse():
     ap.add_argument("--grow", action="store_true",
                     help="lung workloads: cells grow every step; the box is recomputed and the "
                          "operator rebuilt before each step (timed with the step)")
+    ap.add_argument("--track-every", type=int, default=1,
+                    help="with --grow: recompute the box and set up the operator on it every K steps "
+                         "(mpm_bbox_from_cells + mpm_fv_setup); in between only the coefficients of the "
+                         "grown cells are updated on the standing box (mpm_fv_update)")
+    ap.add_argument("--hbm-workload", default="auto",
+                    help="workload of the in-run HBM roofline block (auto: config2-dense when the "
+                         "headline working set fits in the 256 MB Infinity Cache; none to skip)")
+    ap.add_argument("--no-probe", action="store_true", help="skip the streaming bandwidth probe")
     ap.add_argument("--species", type=int, default=3, choices=[3, 4],
                     help="4: the interleukins as separate fields (config2/config2-dense/config5/cube*)")
     ap.add_argument("--precision", default="fp32ir", choices=["fp32ir", "fp64"])
@@ -150,34 +160,69 @@ def gpu_solver(m, prob, t, box, precision, graph, batched, tile=0, ortho=1, warm
 
 class Grower:
     """Cell growth between steps (the cell model's part, outside the solve): each step
-    applies precomputed growth to the device arrays, then recomputes the box
-    (mpm_bbox_from_cells) and rebuilds the operator on it (mpm_fv_setup)."""
+    applies precomputed growth to the device arrays.  Every ``every`` steps it then
+    recomputes the box (mpm_bbox_from_cells) and rebuilds the operator on it
+    (mpm_fv_setup); in the steps between, the box stands and only the coefficients of
+    the grown cells are updated on it (mpm_fv_update), as the paper re-tracks the box
+    every 50 Monte Carlo steps only.  Cells that grow past the standing box are outside
+    the solve until the next re-tracking (the margin absorbs them)."""
 
-    def __init__(self, m, prob, t, steps, torch):
+    def __init__(self, m, prob, t, steps, torch, every=1):
         from synth.geometry import grow_cells
         dev = torch.device("cuda")
         self.m, self.prob, self.t = m, prob, t
+        self.every = max(1, int(every))
         self.events = [tuple(torch.from_numpy(a).to(dev) for a in (g.index, g.cell, g.k, g.src))
                        for g in grow_cells(prob, steps)]
         self.i = 0
+        self.box = None
+        self.reset()
+
+    def reset(self):
         self.grown = 0
-        self.setup_s = 0.0
-        self.boxes = []
+        self.setup_s = 0.0      # bounding box + set-up (re-tracking steps)
+        self.update_s = 0.0     # coefficient updates (steps between)
+        self.tracks = 0
+        self.updates = 0
+        self.boxes = []         # the box each step was solved on
 
     def __call__(self, s):
         idx, ids, kv, sv = self.events[self.i]
-        self.i += 1
         S = self.prob.nspecies
         self.t["cell_id"].view(-1)[idx] = ids
         self.t["k"].view(S, -1)[:, idx] = kv
         self.t["src"].view(S, -1)[:, idx] = sv
-        t0 = time.perf_counter()        # both calls below wait for their results
-        box = self.m.mpm_bbox_from_cells(self.t["cell_id"], self.prob.margin)
-        s.setup(0, box, self.t["mask"], self.t["D"], self.t["k"], self.t["src"], self.prob.c_b,
-                self.prob.dt, self.prob.h)
-        self.setup_s += time.perf_counter() - t0
-        self.boxes.append(box)
+        t0 = time.perf_counter()        # every call below waits for its result
+        if self.box is None or self.i % self.every == 0:
+            self.box = self.m.mpm_bbox_from_cells(self.t["cell_id"], self.prob.margin)
+            s.setup(0, self.box, self.t["mask"], self.t["D"], self.t["k"], self.t["src"], self.prob.c_b,
+                    self.prob.dt, self.prob.h)
+            self.setup_s += time.perf_counter() - t0
+            self.tracks += 1
+        else:
+            s.update(0, self.t["mask"], self.t["D"], self.t["k"], self.t["src"], self.prob.c_b,
+                     self.prob.dt, self.prob.h)
+            self.update_s += time.perf_counter() - t0
+            self.updates += 1
+        self.i += 1
+        self.boxes.append(self.box)
         self.grown += int(idx.numel())
+
+    def ratios(self):
+        """Mean over the steps of (box voxels / lattice voxels, domain voxels in the box /
+        domain voxels of the lattice), the measure of the paper's Fig. 7."""
+        mask = self.prob.mask
+        dom_total = float(mask.sum())
+        cache = {}
+        br, dr = [], []
+        for b in self.boxes:
+            if b not in cache:
+                (x0, y0, z0), (x1, y1, z1) = b
+                cache[b] = ((x1 - x0) * (y1 - y0) * (z1 - z0) / mask.size,
+                            float(mask[z0:z1, y0:y1, x0:x1].sum()) / dom_total)
+            br.append(cache[b][0])
+            dr.append(cache[b][1])
+        return float(np.mean(br)), float(np.mean(dr))
 
 
 def run_steps(s, f, n, tol, torch, grow=None):
@@ -334,6 +379,113 @@ def cpu_baseline(prob, box, c_start, gpu_after, tol, budget_s, threads=1):
                 break
     dt = time.perf_counter() - t0
     return done, dt, errs
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def stream_probe(m, torch):
+    """Rates of the library's hand-written streaming kernels (read, copy, triad) over
+    buffers far larger than the 256 MB Infinity Cache: the practical ceiling of an
+    HBM-bound kernel on this GPU, reported beside the 8 TB/s datasheet peak.  The best
+    of a few grid sizes, with and without nontemporal accesses."""
+    gib = 1 << 30
+    a = torch.ones(gib // 4, dtype=torch.float32, device="cuda")        # 1 GiB each
+    b = torch.ones(gib // 4, dtype=torch.float32, device="cuda")
+    c = torch.empty(gib // 4, dtype=torch.float32, device="cuda")
+    big = torch.ones(4 * gib // 4, dtype=torch.float32, device="cuda")  # 4 GiB for the read
+    part = torch.empty(1 << 20, dtype=torch.float32, device="cuda")
+    res = {}
+    cases = ((m.MPM_PROBE_READ, "read", (big, None, part), 4 * gib, 1),
+             (m.MPM_PROBE_COPY, "copy", (a, None, c), gib, 2),
+             (m.MPM_PROBE_TRIAD, "triad", (a, b, c), gib, 3))
+    for kind, name, (x, y, z), nbytes, moved in cases:
+        best = None
+        for blocks in (2048, 4096, 8192, 16384):
+            for nt in (0, m.MPM_PROBE_NONTEMPORAL):
+                ms = m.mpm_hbm_probe(kind | nt, x, y, z, nbytes, blocks, 5)
+                gbs = moved * nbytes / (ms * 1e-3) / 1e9
+                if best is None or gbs > best[0]:
+                    best = (gbs, blocks, bool(nt))
+        res[name] = {"gbs": round(best[0], 1), "bytes_per_launch": moved * nbytes, "blocks": best[1],
+                     "nontemporal": best[2]}
+    del a, b, c, big, part
+    res["note"] = ("hand-written streaming kernels of the library (mpm_hbm_probe: 256-thread blocks, "
+                   "16-byte accesses, grid-stride loops), best over 2048-16384 blocks with and without "
+                   "nontemporal accesses; 4 GiB read, 1 GiB buffers for copy and triad, far past the "
+                   "256 MB Infinity Cache")
+    return res
+
+
+def working_set_bytes(U, N, precision, restart=30):
+    """Device bytes the GMRES cycle streams through: the Krylov basis and work vector,
+    the FP64 iterate and right-hand side, the couplings (scaled in the Krylov type, FP64
+    unscaled), diagonal, scaling and source terms, and the neighbour table."""
+    t = 4 if precision else 8
+    return U * (t * (restart + 2) + 16 + 3 * t + 24 + 24) + N * 20
+
+
+def roofline_block(timing, kname, kj, precision, U, S, dc, repeat, names, workload, tile):
+    avg_ms = timing["ms"] / timing["launches"]
+    achieved = timing["bytes"] / (timing["ms"] * 1e-3) / 1e9
+    kernel = f"{names[KERNELS[kname]]}<{'float' if precision else 'double'},{kj}>"
+    traffic = measured_traffic(kernel, workload, tile)
+    return {
+        "bound": "hbm",
+        "kernel": kernel,
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "traffic_source": (f"profiles/{kernel.split('<')[0]}_{workload}_traffic.md: rocprofv3 --pmc FETCH_SIZE "
+                           f"and WRITE_SIZE of this kernel on this workload, scaled by the factors a device "
+                           f"copy of known size reads, per active launch; taken from the committed profile, "
+                           f"not counted in this run" if traffic is not None else None),
+        "avg_launch_us": round(1000.0 * avg_ms, 3),
+        "launches": timing["launches"],
+        "launches_per_event_pair": repeat,
+        "alg_bytes_per_launch": round(timing["bytes"] / timing["launches"]),
+        "alg_bytes_per_active_launch": round(alg_bytes_active(KERNELS[kname], kj, U, precision, S, dc)),
+    }
+
+
+def hbm_roofline(m, args, torch, name, precision, ortho, dc, kname, kj, repeat):
+    """The roofline kernel timed on a workload whose working set exceeds the Infinity
+    Cache (so the bytes it streams come from HBM): warm-up steps, then
+    ``roofline_steps`` steps with the kernel timed as for the headline."""
+    prob = make_workload(name, args.species)
+    t = upload(prob, torch)
+    box = prob.box if prob.box is not None else m.mpm_bbox_from_cells(t["cell_id"], prob.margin)
+    tol = args.tol if args.tol is not None else prob.tol
+    f = torch.from_numpy(prob.c0).cuda()
+    s = gpu_solver(m, prob, t, box, precision, False, True, 0, ortho)
+    run_steps(s, f, 3, tol, torch)
+    s.time_kernel(KERNELS[kname], kj, repeat)
+    run_steps(s, f, args.roofline_steps, tol, torch)
+    timing = s.kernel_timing()
+    s.time_kernel(0)
+    s.close()
+    N = int(prob.mask[box[0][2]:box[1][2], box[0][1]:box[1][1], box[0][0]:box[1][0]].sum())
+    U = N * prob.nspecies
+    if not timing["launches"]:
+        return None
+    names = KERNEL_NAMES_DCGS2 if dc else KERNEL_NAMES
+    out = roofline_block(timing, kname, kj, precision, U, prob.nspecies, dc, repeat, names, prob.name, 0)
+    out["workload"] = f"{prob.name}: box {box}, {U} unknowns"
+    out["working_set_bytes"] = working_set_bytes(U, N, precision)
+    out["memory"] = "HBM (working set larger than the 256 MB Infinity Cache)"
+    return out
 
 
 def config3_run(args, m, torch):
@@ -564,7 +716,7 @@ def main():
     if args.grow:
         if prob.box is not None:
             raise SystemExit("--grow needs a workload whose box follows the cells (config2, config5)")
-        grow = Grower(m, prob, t, args.warmup + args.steps, torch)
+        grow = Grower(m, prob, t, args.warmup + args.steps, torch, args.track_every)
     run_steps(s, f, args.warmup, tol, torch, grow)
     c_start = f.clone()
     # headline: K implicit steps, nothing else on the stream (with --grow, each one after
@@ -572,8 +724,8 @@ def main():
     torch.cuda.synchronize()
     box0 = box
     if grow is not None:
-        grow.setup_s, grow.grown = 0.0, 0
         box0 = grow.boxes[-1] if grow.boxes else box
+        grow.reset()
     t0 = time.perf_counter()
     its = run_steps(s, f, args.steps, tol, torch, grow)
     torch.cuda.synchronize()
@@ -630,12 +782,20 @@ def main():
         },
         "iterations_per_step": round(sum(its) / len(its) / prob.nspecies, 2),
         **({"growth": {
-            "what": "per step: cell growth, mpm_bbox_from_cells, mpm_fv_setup on the new box, "
-                    "then the step; all inside the timed steps",
+            "what": f"per step: cell growth; every {grow.every} step(s) mpm_bbox_from_cells and "
+                    f"mpm_fv_setup on the new box, in the steps between mpm_fv_update of the "
+                    f"coefficients on the standing box; then the step; all inside the timed steps",
+            "track_every": grow.every,
             "voxels_grown_per_step": round(grow.grown / args.steps, 2),
             "box_first": [list(box0[0]), list(box0[1])],
             "box_last": [list(box[0]), list(box[1])],
-            "bbox_and_setup_ms_per_step": round(1000.0 * grow.setup_s / args.steps, 4),
+            "retrackings": grow.tracks,
+            "updates": grow.updates,
+            "bbox_and_setup_ms_per_retracking": round(1000.0 * grow.setup_s / max(grow.tracks, 1), 4),
+            "update_ms_per_update": round(1000.0 * grow.update_s / max(grow.updates, 1), 4),
+            "remap_ms_per_step": round(1000.0 * (grow.setup_s + grow.update_s) / args.steps, 4),
+            "box_over_lattice_voxels": round(grow.ratios()[0], 5),
+            "box_domain_over_lattice_domain": round(grow.ratios()[1], 5),
         }} if grow is not None else {}),
         "cycles_last_step": [st["cycles"] for st in final_stats],
         "rel_res_final_last_step": [st["rel_res_final"] for st in final_stats],
@@ -675,29 +835,29 @@ def main():
         "note": "host wall time of mpm_bbox_from_cells / mpm_fv_setup (both wait for their result)",
     }
     if timing and timing["launches"]:
-        avg_ms = timing["ms"] / timing["launches"]
-        achieved = timing["bytes"] / (timing["ms"] * 1e-3) / 1e9
         names = KERNEL_NAMES_DCGS2 if dc else KERNEL_NAMES
-        kernel = f"{names[KERNELS[kname]]}<{'float' if precision else 'double'},{kj}>"
-        out["roofline"] = {
-            "bound": "hbm",
-            "kernel": kernel,
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(kernel, prob.name, args.tile),
-            "avg_launch_us": round(1000.0 * avg_ms, 3),
-            "launches": timing["launches"],
-            "launches_per_event_pair": repeat,
-            "phase": f"{args.roofline_steps} steps after the headline timing (no growth), "
-                     f"cycle launched directly",
-            "copy_1gib_gbs": round(copy_gbs, 1),
-            "frac_of_copy": round(achieved / copy_gbs, 4),
-            "alg_bytes_per_launch": round(timing["bytes"] / timing["launches"]),
-            "alg_bytes_per_active_launch": round(alg_bytes_active(KERNELS[kname], kj, U, precision, prob.nspecies,
-                                                                  dc)),
-        }
+        ws = working_set_bytes(U, N, precision)
+        rl = roofline_block(timing, kname, kj, precision, U, prob.nspecies, dc, repeat, names, prob.name,
+                            args.tile)
+        rl["phase"] = f"{args.roofline_steps} steps after the headline timing (no growth), cycle launched directly"
+        rl["working_set_bytes"] = ws
+        rl["memory"] = ("Infinity Cache: the working set fits in the 256 MB last-level cache, so this rate is "
+                        "the cache fabric's, not HBM's; see roofline_hbm" if ws < 256e6 else
+                        "HBM (working set larger than the 256 MB Infinity Cache)")
+        rl["copy_1gib_gbs"] = round(copy_gbs, 1)
+        rl["frac_of_copy"] = round(rl["achieved"] / copy_gbs, 4)
+        out["roofline"] = rl
+        hbm_name = args.hbm_workload
+        if hbm_name == "auto":
+            hbm_name = "config2-dense" if ws < 256e6 and prob.name.startswith("config2") else "none"
+        if hbm_name != "none":
+            out["roofline_hbm"] = hbm_roofline(m, args, torch, hbm_name, precision, ortho, dc, kname, kj, repeat)
+    if not args.no_probe:
+        out["stream_probe"] = stream_probe(m, torch)
+        for key in ("roofline", "roofline_hbm"):
+            if out.get(key):
+                out[key]["frac_of_probe_read"] = round(out[key]["achieved"] / out["stream_probe"]["read"]["gbs"], 4)
+                out[key]["frac_of_probe_copy"] = round(out[key]["achieved"] / out["stream_probe"]["copy"]["gbs"], 4)
 
     if not args.no_plain and precision == m.MPM_FP32_IR:
         f2 = c_start.clone()
@@ -733,6 +893,7 @@ def main():
             "unit": "steps/s",
             "cores": 1,
             "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{done} consecutive steps of the same workload from the same c^n "
                       f"(FP64 GMRES(30) + Jacobi, tol {tol:g}, scipy CSR, 1 thread), {cpu_s:.1f} s",
         }
@@ -747,6 +908,7 @@ def main():
             "unit": "steps/s",
             "cores": ncores,
             "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{done2} consecutive steps as above with {ncores} threads, {cpu_s2:.1f} s",
         }
     print(json.dumps(out), flush=True)

@@ -148,6 +148,19 @@ int32_t mpm_fv_setup(mpm_ctx ctx, int32_t problem, const int32_t* dims, const in
                      const int32_t* hi, const uint8_t* mask, const double* D, const double* k,
                      const double* src, const double* c_dirichlet, double dt, double h);
 
+/* New coefficients for problem 'problem' on the box of its last mpm_fv_setup: the
+ * paper re-tracks the box only every 50 Monte Carlo steps (Sec. 2.3), while the cells,
+ * and with them k and s, change every step.  The caller guarantees that the box and
+ * the mask's domain voxels inside it are those of the last mpm_fv_setup (mask is read
+ * for the zero-flux faces); D, k, src, c_dirichlet, dt, h as in mpm_fv_setup.  The
+ * compaction, the neighbour table, the launch layout, the tuned work split and the
+ * previous step's cycle lengths are kept; only the couplings, the diagonal, the
+ * right-hand-side terms and the Jacobi scaling are recomputed.  Synchronises the
+ * stream.  MPM_ESTATE before the first mpm_fv_setup of the problem; MPM_EINVAL as in
+ * mpm_fv_setup. */
+int32_t mpm_fv_update(mpm_ctx ctx, int32_t problem, const uint8_t* mask, const double* D, const double* k,
+                      const double* src, const double* c_dirichlet, double dt, double h);
+
 /* One implicit-Euler step of every problem and species (Sec. 2.4).
  * fields: host array [nproblems] of device FP64 [S][z][y][x] lattice fields; read as
  * c^n and overwritten with c^{n+1} on the domain voxels of each box.
@@ -208,6 +221,22 @@ int32_t mpm_kernel_timing(mpm_ctx ctx, double* ms, int64_t* launches, double* by
 /* Unknowns per block of the current work split (after autotuning, if any); *out is a
  * host int.  MPM_ESTATE before the first step or mpm_debug_apply. */
 int32_t mpm_tile(mpm_ctx ctx, int32_t* out);
+
+/* Measurement hook: the bandwidth a plain streaming kernel sustains, as the practical
+ * ceiling beside the datasheet peak.  kind: MPM_PROBE_READ (sum of 'bytes' of a; c
+ * receives one float per block), MPM_PROBE_COPY (c = a, 'bytes' each), MPM_PROBE_TRIAD
+ * (c = a + 3 b as floats, 'bytes' each), optionally | MPM_PROBE_NONTEMPORAL
+ * (nontemporal loads for READ, nontemporal stores otherwise).  a, b, c: device, 16-byte
+ * aligned; bytes a positive multiple of 16; 256-thread blocks, 'blocks' of them, grid-
+ * stride loops over 16-byte words.  One untimed launch, then 'repeat' launches between
+ * two HIP events on 'stream'; *ms (host) = their average duration.  Bytes moved per
+ * launch: bytes (READ), 2 bytes (COPY), 3 bytes (TRIAD).  Synchronises 'stream'. */
+#define MPM_PROBE_READ 0
+#define MPM_PROBE_COPY 1
+#define MPM_PROBE_TRIAD 2
+#define MPM_PROBE_NONTEMPORAL 0x100
+int32_t mpm_hbm_probe(int32_t kind, const void* a, const void* b, void* c, int64_t bytes, int32_t blocks,
+                      int32_t repeat, void* stream, double* ms);
 
 /* ---- learned warm start: a 3-D U-Net on the box grid ----------------------------
  * Not part of the paper; its shape is this project's specification: 'levels' levels of

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmpm.so")
 
-SOURCES = ["api.hip", "bbox.hip", "setup.hip", "krylov.hip", "unet.hip"]
+SOURCES = ["api.hip", "bbox.hip", "setup.hip", "krylov.hip", "unet.hip", "probe.hip"]
 ARCH = "gfx950"
 
 

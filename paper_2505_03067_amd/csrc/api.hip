@@ -199,6 +199,38 @@ extern "C" int32_t mpm_fv_setup(mpm_ctx ctx, int32_t problem, const int32_t* dim
     return rc;
 }
 
+extern "C" int32_t mpm_fv_update(mpm_ctx ctx, int32_t problem, const uint8_t* mask, const double* D, const double* k,
+                                 const double* src, const double* c_dirichlet, double dt, double h) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !mask || !D || !k || !src || !c_dirichlet) {
+        set_error("mpm_fv_update: null pointer");
+        return MPM_EINVAL;
+    }
+    if (problem < 0 || problem >= c->P) {
+        set_error("mpm_fv_update: problem index out of range");
+        return MPM_EINVAL;
+    }
+    if (!(dt > 0.0) || !(h > 0.0) || !std::isfinite(dt) || !std::isfinite(h)) {
+        set_error("mpm_fv_update: dt and h must be positive and finite");
+        return MPM_EINVAL;
+    }
+    for (int s = 0; s < c->S; ++s) {
+        if (!std::isfinite(c_dirichlet[s])) {
+            set_error("mpm_fv_update: non-finite Dirichlet value");
+            return MPM_EINVAL;
+        }
+    }
+    if (((uintptr_t)D | (uintptr_t)k | (uintptr_t)src) % 8 != 0) {
+        set_error("mpm_fv_update: coefficient arrays must be 8-byte aligned");
+        return MPM_EINVAL;
+    }
+    int rc = enter(c);
+    if (rc != MPM_OK) return rc;
+    rc = update_problem(c, problem, mask, D, k, src, c_dirichlet, dt, h);
+    if (rc == MPM_OK) rc = leave(c);
+    return rc;
+}
+
 extern "C" int32_t mpm_implicit_step(mpm_ctx ctx, double* const* fields, double tol) {
     Ctx* c = (Ctx*)ctx;
     if (!c || !fields) {

@@ -75,6 +75,7 @@ struct Ctx {
     // global layout of the work vectors: problem p occupies
     // [off_p, off_p + S * Npad_p) starting at kLead.
     bool layout_dirty = true;
+    bool coef_dirty = false;           // coefficients changed on a standing layout (mpm_fv_update)
     long long U = 0;                   // unknowns over all problems (padded)
     std::vector<long long> off;
     std::vector<Block> blocks;         // batched launch table (XCD-swizzled)
@@ -148,6 +149,8 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi,
                   const double* cb, double dt, double h);
 void free_problem(ProbHost& ph);
 int launch_diag_extremes(Ctx* c, int p);
+int update_problem(Ctx* c, int p, const uint8_t* mask, const double* D, const double* k, const double* src,
+                   const double* cb, double dt, double h);
 
 // krylov.hip
 int run_step(Ctx* c, double* const* fields, double tol);

@@ -1800,8 +1800,26 @@ static int autotune_t(Ctx* c, long long* best_out, int* group_out) {
 
 static void drop_graphs(Ctx* c);
 
+// Diagonal extremes per system (for the bound between the scaled and the unscaled
+// residual), after the layout or the coefficients changed.
+static int refresh_diag_extremes(Ctx* c) {
+    KArgs<double> ka{};
+    ka.blocks = c->d_blocks;
+    ka.probs = c->d_probs;
+    ka.sk = c->d_sk;
+    ka.S = c->S;
+    k_diag_extremes<double><<<(unsigned)c->blocks.size(), kThreads, 0, c->stream>>>(ka);
+    k_sys_kappa<<<1, 64, 0, c->stream>>>(c->d_sk, c->S * c->P);
+    MPM_HIP(hipGetLastError());
+    c->coef_dirty = false;
+    return MPM_OK;
+}
+
 int ensure_layout(Ctx* c) {
-    if (!c->layout_dirty) return MPM_OK;
+    if (!c->layout_dirty) {
+        // new coefficients on the standing layout: only the per-system extremes change
+        return c->coef_dirty ? refresh_diag_extremes(c) : MPM_OK;
+    }
     for (int p = 0; p < c->P; ++p) {
         if (!c->probs[p].ready) {
             set_error("problem " + std::to_string(p) + " has not been set up (mpm_fv_setup)");
@@ -1931,16 +1949,8 @@ int ensure_layout(Ctx* c) {
     build_tables(c, tile, group);
     int rc = upload_tables(c);
     if (rc != MPM_OK) return rc;
-    // diagonal extremes per system (for the scaled/unscaled residual bound)
-    const int nsys = c->S * c->P;
-    KArgs<double> ka{};
-    ka.blocks = c->d_blocks;
-    ka.probs = c->d_probs;
-    ka.sk = c->d_sk;
-    ka.S = c->S;
-    k_diag_extremes<double><<<(unsigned)c->blocks.size(), kThreads, 0, st>>>(ka);
-    k_sys_kappa<<<1, 64, 0, st>>>(c->d_sk, nsys);
-    MPM_HIP(hipGetLastError());
+    rc = refresh_diag_extremes(c);
+    if (rc != MPM_OK) return rc;
     MPM_HIP(hipStreamSynchronize(st));
     drop_graphs(c);
     c->layout_dirty = false;

@@ -446,6 +446,68 @@ static int alloc_problem(ProbHost& ph, int S, int Npad, hipStream_t st) {
     return MPM_OK;
 }
 
+// Coefficients of problem ph on its compacted layout (N domain voxels, vox their lattice
+// indices): face couplings, diagonal, right-hand-side terms, Jacobi scaling, the scaled
+// copies and, for the learned warm start, the static network input channels.  flag is a
+// device word used as the error flag (negative or non-finite input on a domain voxel);
+// synchronises the stream to read it.
+static int discretise(Ctx* c, ProbHost& ph, const BoxGeo& g, const uint8_t* mask, const double* D, const double* k,
+                      const double* src, const double* cb, double dt, double h, int N, int Npad, const int* vox,
+                      int* flag) {
+    hipStream_t st = c->stream;
+    CoefArgs ca;
+    ca.mask = mask; ca.D = D; ca.k = k; ca.src = src; ca.vox = vox;
+    ca.d64 = ph.d64; ca.q64 = ph.q64; ca.a64 = ph.a64; ca.sc64 = ph.sc64;
+    ca.g = g;
+    ca.nvox = (long long)g.nx * g.ny * g.nz;
+    ca.dt = dt;
+    ca.inv_h2 = 1.0 / (h * h);
+    for (int s = 0; s < MPM_MAX_SPECIES; ++s) ca.cb[s] = s < c->S ? cb[s] : 0.0;
+    ca.N = N; ca.Npad = Npad; ca.S = c->S;
+    ca.bad = flag;
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), st);
+    if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (flag)");
+    const long long tot = (long long)c->S * Npad;
+    k_coefs<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ca);
+    k_scaled<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ph.a64, ph.sc64, ph.nbr, N, Npad, c->S, ph.c64,
+                                                          ph.c32);
+    if (c->opt.warm_start == MPM_WS_NET) {
+        const int gx = (g.bx + 7) / 8 * 8, gy = (g.by + 7) / 8 * 8, gz = (g.bz + 7) / 8 * 8;
+        const size_t G = (size_t)gx * gy * gz;
+        if (G > ph.cap_grid) {
+            (void)hipFree(ph.stat);
+            (void)hipFree(ph.wsin);
+            (void)hipFree(ph.wsout);
+            ph.stat = nullptr;
+            ph.wsin = nullptr;
+            ph.wsout = nullptr;
+            ph.cap_grid = 0;
+            if (hipMalloc(&ph.stat, G * (3 * c->S + 1) * sizeof(float)) != hipSuccess ||
+                hipMalloc(&ph.wsin, G * (4 * c->S + 1) * sizeof(uint16_t)) != hipSuccess ||
+                hipMalloc(&ph.wsout, G * c->S * sizeof(float)) != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("mpm_fv_setup: device allocation of the warm-start buffers failed");
+                return MPM_ENOMEM;
+            }
+            ph.cap_grid = G;
+        }
+        ph.gd[0] = gx;
+        ph.gd[1] = gy;
+        ph.gd[2] = gz;
+        k_ws_static<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(mask, D, k, src, g, gx, gy, gz, c->S, ca.nvox,
+                                                              ph.stat);
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(c->h_small + 1, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (coefficients)");
+    if (c->h_small[1]) {
+        set_error("mpm_fv_setup: negative or non-finite D, k or s on a domain voxel");
+        return MPM_EINVAL;
+    }
+    return MPM_OK;
+}
+
 int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, const uint8_t* mask,
                   const double* D, const double* k, const double* src, const double* cb, double dt,
                   double h) {
@@ -489,57 +551,12 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     // ph.vox receives -1 on padding from k_neighbors; copy the domain part
     e = hipMemcpyAsync(ph.vox, vox_tmp, (size_t)N * sizeof(int), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (vox)");
-    CoefArgs ca;
-    ca.mask = mask; ca.D = D; ca.k = k; ca.src = src; ca.vox = vox_tmp;
-    ca.d64 = ph.d64; ca.q64 = ph.q64; ca.a64 = ph.a64; ca.sc64 = ph.sc64;
-    ca.g = g;
-    ca.nvox = (long long)dims[0] * dims[1] * dims[2];
-    ca.dt = dt;
-    ca.inv_h2 = 1.0 / (h * h);
-    for (int s = 0; s < MPM_MAX_SPECIES; ++s) ca.cb[s] = s < c->S ? cb[s] : 0.0;
-    ca.N = N; ca.Npad = Npad; ca.S = c->S;
-    ca.bad = total_d;   // reused as the error flag (the count was read already)
-    e = hipMemsetAsync(total_d, 0, sizeof(int), st);
-    if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (flag)");
-    const long long tot = (long long)c->S * Npad;
-    k_coefs<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ca);
-    k_scaled<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ph.a64, ph.sc64, ph.nbr, N, Npad, c->S, ph.c64,
-                                                          ph.c32);
-    if (c->opt.warm_start == MPM_WS_NET) {
-        const int gx = (g.bx + 7) / 8 * 8, gy = (g.by + 7) / 8 * 8, gz = (g.bz + 7) / 8 * 8;
-        const size_t G = (size_t)gx * gy * gz;
-        if (G > ph.cap_grid) {
-            (void)hipFree(ph.stat);
-            (void)hipFree(ph.wsin);
-            (void)hipFree(ph.wsout);
-            ph.stat = nullptr;
-            ph.wsin = nullptr;
-            ph.wsout = nullptr;
-            ph.cap_grid = 0;
-            if (hipMalloc(&ph.stat, G * (3 * c->S + 1) * sizeof(float)) != hipSuccess ||
-                hipMalloc(&ph.wsin, G * (4 * c->S + 1) * sizeof(uint16_t)) != hipSuccess ||
-                hipMalloc(&ph.wsout, G * c->S * sizeof(float)) != hipSuccess) {
-                (void)hipGetLastError();
-                set_error("mpm_fv_setup: device allocation of the warm-start buffers failed");
-                return MPM_ENOMEM;
-            }
-            ph.cap_grid = G;
-        }
-        ph.gd[0] = gx;
-        ph.gd[1] = gy;
-        ph.gd[2] = gz;
-        k_ws_static<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(mask, D, k, src, g, gx, gy, gz, c->S, ca.nvox,
-                                                              ph.stat);
-    }
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(c->h_small + 1, total_d, sizeof(int), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (coefficients)");
-    if (c->h_small[1]) {
+    ph.nvox = (long long)dims[0] * dims[1] * dims[2];
+    rc = discretise(c, ph, g, mask, D, k, src, cb, dt, h, N, Npad, vox_tmp, total_d);
+    if (rc != MPM_OK) {
         ph.ready = false;
         c->layout_dirty = true;
-        set_error("mpm_fv_setup: negative or non-finite D, k or s on a domain voxel");
-        return MPM_EINVAL;
+        return rc;
     }
 
     const bool grew = Npad != ph.Npad;
@@ -550,7 +567,6 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
         ph.lo[d] = lo[d];
         ph.hi[d] = hi[d];
     }
-    ph.nvox = ca.nvox;
     ph.dt = dt;
     ph.h = h;
     for (int s = 0; s < c->S; ++s) ph.cb[s] = cb[s];
@@ -558,6 +574,34 @@ int setup_problem(Ctx* c, int p, const int* dims, const int* lo, const int* hi, 
     // descriptors (pointers may have moved) and the layout are rebuilt lazily
     c->layout_dirty = true;
     (void)grew;
+    return MPM_OK;
+}
+
+// New coefficients on the box and domain of the last set-up: the compaction, the
+// neighbour table and the launch layout are kept (the caller guarantees that the box and
+// the domain voxels are unchanged), only the discretisation is redone.
+int update_problem(Ctx* c, int p, const uint8_t* mask, const double* D, const double* k, const double* src,
+                   const double* cb, double dt, double h) {
+    ProbHost& ph = c->probs[p];
+    if (!ph.ready) {
+        set_error("mpm_fv_update: the problem has not been set up (mpm_fv_setup)");
+        return MPM_ESTATE;
+    }
+    BoxGeo g;
+    g.nx = ph.dims[0]; g.ny = ph.dims[1]; g.nz = ph.dims[2];
+    g.x0 = ph.lo[0]; g.y0 = ph.lo[1]; g.z0 = ph.lo[2];
+    g.bx = ph.hi[0] - ph.lo[0]; g.by = ph.hi[1] - ph.lo[1]; g.bz = ph.hi[2] - ph.lo[2];
+    int rc = discretise(c, ph, g, mask, D, k, src, cb, dt, h, ph.N, ph.Npad, ph.vox, ph.s_total);
+    if (rc != MPM_OK) {
+        ph.ready = false;
+        c->layout_dirty = true;
+        return rc;
+    }
+    ph.dt = dt;
+    ph.h = h;
+    for (int s = 0; s < c->S; ++s) ph.cb[s] = cb[s];
+    // the layout stands; the per-system diagonal extremes are refreshed before the next step
+    c->coef_dirty = true;
     return MPM_OK;
 }
 

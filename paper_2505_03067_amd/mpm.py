@@ -84,6 +84,8 @@ def lib() -> ctypes.CDLL:
                            ctypes.POINTER(mpm_options), _vp],
             "mpm_fv_setup": [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _vp, _vp, _vp, _vp,
                              ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double],
+            "mpm_fv_update": [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double),
+                              ctypes.c_double, ctypes.c_double],
             "mpm_implicit_step": [_vp, ctypes.POINTER(_vp), ctypes.c_double],
             "mpm_gmres_stats": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mpm_stats)],
             "mpm_destroy": [_vp],
@@ -117,6 +119,8 @@ def lib() -> ctypes.CDLL:
             "mpm_ws_pair": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_float), _vp, _vp],
             "mpm_ws_grid": [_vp, ctypes.c_int32, _i32p],
+            "mpm_hbm_probe": [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                              _vp, ctypes.POINTER(ctypes.c_double)],
             "mpm_kernel_timing": [_vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
         }
@@ -238,6 +242,15 @@ def mpm_fv_setup(ctx, problem: int, box, mask, D, k, src, c_dirichlet: Sequence[
                                      float(h)))
 
 
+def mpm_fv_update(ctx, problem: int, mask, D, k, src, c_dirichlet: Sequence[float], dt: float, h: float):
+    """New coefficients on the box and domain of the last mpm_fv_setup of ``problem``."""
+    import torch
+    cb = (ctypes.c_double * len(c_dirichlet))(*[float(v) for v in c_dirichlet])
+    return _check(lib().mpm_fv_update(ctx, int(problem), _dev_ptr(mask, torch.uint8, "mask"),
+                                      _dev_ptr(D, torch.float64, "D"), _dev_ptr(k, torch.float64, "k"),
+                                      _dev_ptr(src, torch.float64, "src"), cb, float(dt), float(h)))
+
+
 def mpm_implicit_step(ctx, fields, tol: float) -> int:
     """One step for every problem; ``fields`` is a list of FP64 [S][z][y][x] tensors."""
     import torch
@@ -296,6 +309,30 @@ def mpm_kernel_timing(ctx) -> dict:
     by = ctypes.c_double()
     _check(lib().mpm_kernel_timing(ctx, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
     return {"ms": ms.value, "launches": n.value, "bytes": by.value}
+
+
+MPM_PROBE_READ = 0
+MPM_PROBE_COPY = 1
+MPM_PROBE_TRIAD = 2
+MPM_PROBE_NONTEMPORAL = 0x100
+
+
+def mpm_hbm_probe(kind: int, a, b, c, nbytes: int, blocks: int = 4096, repeat: int = 5, stream=None) -> float:
+    """Average duration in ms of one streaming-probe launch (see include/mpm.h)."""
+    ms = ctypes.c_double()
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    base = int(kind) & 0xFF
+    need = {"a": int(nbytes), "b": int(nbytes) if base == MPM_PROBE_TRIAD else 0,
+            "c": 4 * int(blocks) if base == MPM_PROBE_READ else int(nbytes)}
+    for name, t in (("a", a), ("b", b), ("c", c)):
+        if t is not None and (t.device.type != "cuda" or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous GPU tensor")
+        size = 0 if t is None else t.numel() * t.element_size()
+        if size < need[name]:
+            raise ValueError(f"{name} holds {size} bytes, the probe needs {need[name]}")
+    _check(lib().mpm_hbm_probe(int(kind), ptr(a), ptr(b), ptr(c), int(nbytes), int(blocks), int(repeat),
+                               _stream(stream), ctypes.byref(ms)))
+    return ms.value
 
 
 def mpm_tile(ctx) -> int:
@@ -528,6 +565,9 @@ class Solver:
 
     def setup(self, problem, box, mask, D, k, src, c_dirichlet, dt, h):
         return mpm_fv_setup(self.ctx, problem, box, mask, D, k, src, c_dirichlet, dt, h)
+
+    def update(self, problem, mask, D, k, src, c_dirichlet, dt, h):
+        return mpm_fv_update(self.ctx, problem, mask, D, k, src, c_dirichlet, dt, h)
 
     def step(self, fields, tol):
         return mpm_implicit_step(self.ctx, list(fields), tol)
