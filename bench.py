@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--c4-geometries", type=int, default=64, help="config4: 64^3 training geometries")
     ap.add_argument("--c4-pairs", type=int, default=10, help="config4: pairs per training geometry")
     ap.add_argument("--c4-epochs", type=int, default=4, help="config4: training epochs")
+    ap.add_argument("--c4-chunk", type=int, default=16,
+                    help="config4: geometries whose pairs are generated and trained on together")
+    ap.add_argument("--c4-lr", type=float, default=1e-3, help="config4: Adam learning rate")
     ap.add_argument("--c4-eval", type=int, default=4, help="config4: unseen 128^3 evaluation geometries")
     ap.add_argument("--grow", action="store_true",
                     help="lung workloads: cells grow every step; the box is recomputed and the "
@@ -249,7 +252,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     true residual), all with the launch mode of the headline, at the benchmark tolerance.
     """
     import numpy as np
-    from paper_2505_03067_amd.train import IN_SCALE
+    from paper_2505_03067_amd.train import input_scales
     S = prob.nspecies
     f = f0.clone()
 
@@ -262,9 +265,9 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
             for _ in range(args.train_pairs):
                 old = g.clone()
                 s.step([g], 1e-10)
-                inp = torch.empty((gz, gy, gx, 4 * S + 1), dtype=torch.int16, device="cuda")
+                inp = torch.empty((gz, gy, gx, 5 * S + 1), dtype=torch.int16, device="cuda")
                 tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
-                s.ws_pair(0, old, g, IN_SCALE, out_scale, inp, tgt)
+                s.ws_pair(0, old, g, input_scales(S, out_scale), out_scale, inp, tgt)
                 pairs.append((inp, tgt))
         return pairs, g
 
@@ -272,14 +275,14 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     # per-species RMS of the one-step change over the domain voxels (target scale)
     sq, cnt = [0.0] * S, 0
     for inp, tgt in raw:
-        mask = inp[..., -1] != 0
+        mask = inp[..., 4 * S] != 0
         cnt += int(mask.sum())
         for sp in range(S):
             sq[sp] += float((tgt[..., sp][mask].double() ** 2).sum())
     out_scale = [max((v / max(cnt, 1)) ** 0.5, 1e-30) for v in sq]
     del raw
     pairs, f_after = make_pairs(out_scale)
-    net = m.Net(4 * S + 1, S, [16, 32, 64, 64], seed=7)
+    net = m.Net(5 * S + 1, S, [16, 32, 64, 64], seed=7)
     rng = np.random.default_rng(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -307,7 +310,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     torch.cuda.synchronize()
     fwd_ms = e0.elapsed_time(e1) / 5
     grid = int(x0.shape[1] * x0.shape[2] * x0.shape[3])
-    fwd_flop = 2.0 * unet_macs_per_voxel(4 * S + 1, S, [16, 32, 64, 64]) * grid
+    fwd_flop = 2.0 * unet_macs_per_voxel(5 * S + 1, S, [16, 32, 64, 64]) * grid
     del pairs
     res = {}
     for name, warm in (("plain", m.MPM_WS_NONE), ("extrapolated", m.MPM_WS_EXTRAP), ("learned", m.MPM_WS_NET)):
@@ -315,7 +318,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
         s = m.Solver(S, 1, precision=precision, warm_start=warm, ortho=int(ortho))
         s.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
         if warm == m.MPM_WS_NET:
-            s.attach(net, IN_SCALE, out_scale)
+            s.attach(net, input_scales(S, out_scale), out_scale)
         gw = g.clone()
         s.step([gw], tol)                      # allocations, tuning, graph capture
         torch.cuda.synchronize()
@@ -606,29 +609,48 @@ def config4_run(args, m, torch):
     from synth import config4_patch
     S = 3
     t0 = time.perf_counter()
-    pairs = []
-    for seed in range(args.c4_geometries):
-        prob = config4_patch(seed, 64)
-        pick = set(np.random.default_rng(seed).choice(50, size=args.c4_pairs, replace=False).tolist())
-        for inp, tgt in tr.generate_pairs([prob], 50, pick, [1.0] * S, tol=1e-10):
-            pairs.append((inp, tgt))
-    gen_s = time.perf_counter() - t0
-    sq, cnt = [0.0] * S, 0
-    for inp, tgt in pairs:
-        mask = inp[..., -1] != 0
-        cnt += int(mask.sum())
-        for sp in range(S):
-            sq[sp] += float((tgt[..., sp][mask].double() ** 2).sum())
-    out_scale = [max((v / max(cnt, 1)) ** 0.5, 1e-30) for v in sq]
-    for _, tgt in pairs:
-        for sp in range(S):
-            tgt[..., sp] /= out_scale[sp]
-    net = m.Net(4 * S + 1, S, [16, 32, 64, 64], seed=7)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    losses = tr.train(net, pairs, args.c4_epochs, 4, lr=1e-3, seed=0)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t1
+    # target scale: per-species RMS of the one-step change on four training geometries
+    out_scale = tr.estimate_out_scale([config4_patch(seed, 64) for seed in range(4)], 10)
+    net = m.Net(5 * S + 1, S, [16, 32, 64, 64], seed=7)
+    rng = np.random.default_rng(0)
+    losses, gen_s, train_s, npairs, t = [], 0.0, 0.0, 0, 0
+    # streamed: every epoch regenerates the pairs of a chunk of geometries on the GPU from
+    # their seeds (the solver's trajectories are deterministic), trains on them shuffled,
+    # and drops them (20,000 64^3 pairs would need about 230 GB)
+    for ep in range(args.c4_epochs):
+        tot, nb = 0.0, 0
+        order = rng.permutation(args.c4_geometries)
+        for c0 in range(0, args.c4_geometries, args.c4_chunk):
+            tg = time.perf_counter()
+            pairs = []
+            for seed in order[c0:c0 + args.c4_chunk]:
+                seed = int(seed)
+                pick = set(np.random.default_rng(seed).choice(50, size=args.c4_pairs, replace=False).tolist())
+                pairs += list(tr.generate_pairs([config4_patch(seed, 64)], 50, pick, out_scale, tol=1e-10))
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            gen_s += tt - tg
+            perm = rng.permutation(len(pairs))
+            for i in range(0, len(perm), 4):
+                idx = perm[i:i + 4]
+                x = torch.stack([pairs[j][0] for j in idx]).contiguous()
+                y = torch.stack([pairs[j][1] for j in idx]).contiguous()
+                out = torch.empty_like(y)
+                g = torch.empty_like(y)
+                net.forward(x, out)
+                tot += net.mse(out, y, g)
+                nb += 1
+                net.zero_grad()
+                net.backward(g)
+                t += 1
+                net.adam(args.c4_lr, t)
+            torch.cuda.synchronize()
+            train_s += time.perf_counter() - tt
+            if ep == 0:
+                npairs += len(pairs)
+            del pairs
+        losses.append(tot / max(nb, 1))
+    pairs = None
     del pairs
     evalp = [config4_patch(10 ** 6 + i, 128) for i in range(args.c4_eval)]
     tol = args.tol if args.tol is not None else 1e-8
@@ -661,7 +683,9 @@ def config4_run(args, m, torch):
             **res,
             "learned_over_plain": round(res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"], 3),
             "extrapolated_over_plain": round(res["extrapolated"]["steps_per_s"] / res["plain"]["steps_per_s"], 3),
-            "training": {"pairs": args.c4_geometries * args.c4_pairs, "epochs": args.c4_epochs,
+            "training": {"pairs_per_epoch": npairs, "epochs": args.c4_epochs, "batch": 4, "lr": args.c4_lr,
+                         "streamed": f"pairs of {args.c4_chunk} geometries at a time, regenerated on the GPU "
+                                     f"from their seeds every epoch",
                          "generation_s": round(gen_s, 1), "training_s": round(train_s, 1),
                          "loss_by_epoch": [round(float(x), 5) for x in losses]},
         },

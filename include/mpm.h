@@ -250,7 +250,7 @@ int32_t mpm_hbm_probe(int32_t kind, const void* a, const void* b, void* c, int64
 typedef struct mpm_net_s* mpm_net;
 
 /* Create a network with He-normal weights drawn from 'seed' (host-side generator).
- * 1 <= in_ch <= 32 (17 for the warm start of four species), 1 <= out_ch <= 4,
+ * 1 <= in_ch <= 32 (16 for the warm start of three species, 21 for four), 1 <= out_ch <= 4,
  * 1 <= levels <= 6; MPM_EINVAL otherwise or for widths outside the list above. */
 int32_t mpm_net_create(mpm_net* net, int32_t in_ch, int32_t out_ch, int32_t levels, const int32_t* widths,
                        uint64_t seed, void* stream);
@@ -334,20 +334,25 @@ int32_t mpm_net_debug_tensor(mpm_net net, int32_t kind, int32_t index, uint16_t*
 int32_t mpm_net_debug_op(mpm_net net, int32_t op, int32_t n, int32_t d, int32_t h, int32_t w, int32_t c,
                          int32_t c2, const void* a, const void* b, void* out, void* out2);
 
-/* Use 'net' (in_ch = 4 S + 1, out_ch = S) as the warm start of a context created with
+/* Use 'net' (in_ch = 5 S + 1, out_ch = S) as the warm start of a context created with
  * warm_start = MPM_WS_NET; net = NULL detaches.  Network input on the box grid (box
- * sizes rounded up to multiples of 8, zero beyond the box): channels c^n (S), k (S),
- * D (S), s (S), mask, each times in_scale[ch] (host, exactly 4 S + 1 floats are read);
- * the prediction of species s is output * out_scale[s] (host, S floats read) added to
- * c^n.  Each step keeps the prediction of a system only if its true residual is below
- * that of c^n (mpm_stats.warm_start_used / fallback).  The net must outlive its use. */
+ * sizes rounded up to multiples of 8, zero beyond the box), each channel times
+ * in_scale[ch] (host, exactly 5 S + 1 floats are read): c^n (S), k (S), D (S), s (S),
+ * the mask, and the Jacobi-scaled residual of c^n, d = (b - A c^n) / A_PP (S; zero
+ * off the domain), which is the first Jacobi correction and is computed from the same
+ * inputs by the step's first residual.  The prediction of species s is output *
+ * out_scale[s] (host, S floats read) added to c^n.  Each step keeps the prediction of
+ * a system only if its true residual is below that of c^n
+ * (mpm_stats.warm_start_used / fallback).  The net must outlive its use. */
 int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scale, const float* out_scale);
 
 /* Training pair for the warm start of 'problem': the network input built from the
  * lattice fields c_old (device FP64 [S][z][y][x]) exactly as mpm_implicit_step builds
- * it (in_bf16: device [gz][gy][gx][4 S + 1]) and the target (c_new - c_old) / out_scale
+ * it (in_bf16: device [gz][gy][gx][5 S + 1]) and the target (c_new - c_old) / out_scale
  * on domain voxels, 0 elsewhere (target: device FP32 [gz][gy][gx][S]).  grid: see
- * mpm_ws_grid.  Synchronises the stream. */
+ * mpm_ws_grid.  The residual of c_old is computed with the step's own kernels, which
+ * use the context's solver workspace as scratch (the next step recomputes it).
+ * Synchronises the stream. */
 int32_t mpm_ws_pair(mpm_ctx ctx, int32_t problem, const double* c_old, const double* c_new,
                     const float* in_scale, const float* out_scale, uint16_t* in_bf16, float* target);
 

@@ -347,7 +347,7 @@ extern "C" int32_t mpm_tile(mpm_ctx ctx, int32_t* out) {
 }
 
 static int set_scales(Ctx* c, const float* in_scale, const float* out_scale) {
-    const int cin = 4 * c->S + 1;
+    const int cin = ws_channels(c->S);
     for (int i = 0; i < kScaleCount; ++i) c->h_scales[i] = 0.f;
     for (int i = 0; i < cin; ++i) c->h_scales[i] = in_scale[i];
     for (int s = 0; s < c->S; ++s) c->h_scales[kScaleOut + s] = out_scale[s];
@@ -363,8 +363,8 @@ extern "C" int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scal
         set_error("mpm_attach_net: null pointer");
         return MPM_EINVAL;
     }
-    if (n && (n->in_ch != 4 * c->S + 1 || n->out_ch != c->S)) {
-        set_error("mpm_attach_net: the network must read 4 S + 1 channels and write S");
+    if (n && (n->in_ch != ws_channels(c->S) || n->out_ch != c->S)) {
+        set_error("mpm_attach_net: the network must read 5 S + 1 channels and write S");
         return MPM_EINVAL;
     }
     if (c->opt.warm_start != MPM_WS_NET) {

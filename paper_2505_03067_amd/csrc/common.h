@@ -19,10 +19,15 @@ constexpr long long kLead = 1024;        // zero elements before the first unkno
 constexpr int kMaxM = MPM_MAX_RESTART;   // longest restart
 constexpr int kMaxSys = 64;              // (problem, species) systems per context
 constexpr int kPartRows = 2 * (kMaxM + 1) + 4;   // partial-sum rows per block slot
-// warm-start scales on the device: the 4 S + 1 network input channel scales from
+// warm-start scales on the device: the 5 S + 1 network input channel scales from
 // index 0, the S output scales from kScaleOut (room for the largest S)
-constexpr int kScaleOut = 4 * MPM_MAX_SPECIES + 1;
+constexpr int kScaleOut = 5 * MPM_MAX_SPECIES + 1;
 constexpr int kScaleCount = kScaleOut + MPM_MAX_SPECIES;
+// channels of the warm-start network input: c^n, k, D, s (S each), the mask, and the
+// Jacobi-scaled residual of c^n (S)
+__host__ __device__ constexpr int ws_channels(int S) { return 5 * S + 1; }
+// channels of the static part of that input kept per problem: k, D, s, mask
+__host__ __device__ constexpr int ws_static_channels(int S) { return 3 * S + 1; }
 
 // ---------------------------------------------------------------- device views
 // Per-problem data, addressed with the problem-local unknown index

@@ -44,9 +44,9 @@ struct ProbHost {
     // warm start: static network input channels on the box grid (k, D, s, mask)
     int gd[3] = {0, 0, 0};
     float* stat = nullptr;
-    uint16_t* wsin = nullptr;  // BF16 network input [G][in_ch]
+    uint16_t* wsin = nullptr;  // BF16 network input [G][ws_channels(S)]
     float* wsout = nullptr;    // network output [G][S]
-    size_t cap_grid = 0;
+    size_t cap_grid = 0;       // grid voxels the three buffers above hold
 };
 
 // What a tuning result is kept for: species, basis word size, orthogonalisation,

@@ -1340,9 +1340,11 @@ __device__ inline uint16_t to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
-// Network input on the box grid of problem p: channels [c (S), k (S), D (S), s (S), mask],
-// each multiplied by its scale, BF16; zero on grid voxels beyond the box.  c is read
-// from the lattice field; k, D, s and the mask come from the static channels.
+// Network input on the box grid of problem p: channels [c (S), k (S), D (S), s (S), mask,
+// d (S)], each multiplied by its scale, BF16; zero on grid voxels beyond the box.  c is
+// read from the lattice field; k, D, s and the mask come from the static channels; the
+// channels d (the Jacobi-scaled residual of c^n) are written as zero here and filled on
+// the domain voxels by k_ws_resid.
 __global__ void k_ws_input(ProbDev pd, int S, int bx, int by, int bz, const double* field, const float* stat,
                            const float* scales, uint16_t* in) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1352,15 +1354,27 @@ __global__ void k_ws_input(ProbDev pd, int S, int bx, int by, int bz, const doub
     const int x = (int)(i % gx);
     const int y = (int)((i / gx) % gy);
     const int z = (int)(i / ((long long)gx * gy));
-    const int C = 4 * S + 1;
+    const int C = ws_channels(S);
     const bool inbox = x < bx && y < by && z < bz;
-    const float* st = stat + i * (3 * S + 1);
+    const float* st = stat + i * ws_static_channels(S);
     const long long v = ((long long)(pd.lo[2] + z) * pd.ny + (pd.lo[1] + y)) * pd.nx + (pd.lo[0] + x);
+    uint16_t val[ws_channels(MPM_MAX_SPECIES)];
     for (int s = 0; s < S; ++s) {
         const float cv = inbox ? (float)field[s * pd.nvox + v] : 0.f;
-        in[i * C + s] = to_bf16(cv * scales[s]);
+        val[s] = to_bf16(cv * scales[s]);
     }
-    for (int c = 0; c < 3 * S + 1; ++c) in[i * C + S + c] = to_bf16(st[c] * scales[S + c]);
+    for (int c = 0; c < ws_static_channels(S); ++c) val[S + c] = to_bf16(st[c] * scales[S + c]);
+    for (int c = 4 * S + 1; c < C; ++c) val[c] = 0;
+    if (C % 8 == 0 && ((uintptr_t)in & 15) == 0) {   // three species: 16 channels, two 16-byte stores
+        uint4* o = reinterpret_cast<uint4*>(in + i * C);
+        for (int q = 0; q < C / 8; ++q) {
+            const uint16_t* w = val + 8 * q;
+            o[q] = make_uint4(w[0] | ((uint32_t)w[1] << 16), w[2] | ((uint32_t)w[3] << 16),
+                              w[4] | ((uint32_t)w[5] << 16), w[6] | ((uint32_t)w[7] << 16));
+        }
+    } else {
+        for (int c = 0; c < C; ++c) in[i * C + c] = val[c];
+    }
 }
 
 // Grid index of compact voxel l of a problem.
@@ -1396,6 +1410,26 @@ __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, con
     }
 }
 
+// Jacobi-scaled residual of c^n, d = r / A_PP = S (S r), on the domain voxels of problem
+// p into channel 4 S + 1 + s of the network input dst (times its scale, BF16).  V holds
+// S r from the first residual of the step (before any Arnoldi step overwrites it).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ws_resid(KArgs<T> a, int p, const float* scales, uint16_t* dst) {
+    const Block blk = a.blocks[blockIdx.x];
+    if (blk.sys < 0 || blk.p != p) return;
+    const ProbDev pd = a.probs[p];
+    const Where wh = where_of(a, blk, pd);
+    const int C = ws_channels(a.S);
+    const int ch = 4 * a.S + 1 + wh.s;
+    const float scale = scales[ch];
+    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
+        const int l = (int)(u - wh.base);
+        if (l >= pd.N) continue;
+        const double d = pd.sc64[wh.locbase + l] * (double)a.V[u];
+        dst[grid_index(pd, l) * C + ch] = to_bf16((float)d * scale);
+    }
+}
+
 // Back to x = c^n for the systems whose warm start was rejected.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_ws_revert(KArgs<T> a) {
@@ -1427,7 +1461,7 @@ __global__ void k_ws_target(ProbDev pd, int S, int bx, int by, int bz, const dou
     const int x = (int)(i % gx);
     const int y = (int)((i / gx) % gy);
     const int z = (int)(i / ((long long)gx * gy));
-    const bool dom = x < bx && y < by && z < bz && stat[i * (3 * S + 1) + 3 * S] > 0.f;
+    const bool dom = x < bx && y < by && z < bz && stat[i * ws_static_channels(S) + 3 * S] > 0.f;
     const long long v = ((long long)(pd.lo[2] + z) * pd.ny + (pd.lo[1] + y)) * pd.nx + (pd.lo[0] + x);
     for (int s = 0; s < S; ++s) {
         float t = 0.f;
@@ -2194,9 +2228,15 @@ static int warm_start(Ctx* c, hipStream_t st) {
             const ProbHost& ph = c->probs[p];
             const ProbDev& pd = c->h_probs[p];
             const long long G = (long long)ph.gd[0] * ph.gd[1] * ph.gd[2];
+            if (G <= 0 || (size_t)G > ph.cap_grid || !ph.wsin || !ph.wsout || !ph.stat) {
+                c->net->stream = saved;
+                set_error("warm start: the network buffers of a problem do not cover its grid");
+                return MPM_ESTATE;
+            }
             k_ws_input<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, ph.hi[0] - ph.lo[0], ph.hi[1] - ph.lo[1],
                                                                   ph.hi[2] - ph.lo[2], c->h_fields[p], ph.stat,
                                                                   c->d_scales, ph.wsin);
+            k_ws_resid<T><<<nb, kThreads, 0, st>>>(a, p, c->d_scales, ph.wsin);
             int rc = net_forward(c->net, ph.wsin, 1, ph.gd[2], ph.gd[1], ph.gd[0], ph.wsout);
             if (rc != MPM_OK) {
                 c->net->stream = saved;
@@ -2466,6 +2506,24 @@ int debug_apply(Ctx* c, int p, const double* x, double* y, int mode) {
 
 namespace mpm {
 
+// The first residual of a step from c_old for the systems of problem p, with the
+// solver's own kernels: c_old gathered as c^n (x, b) and r = b - A x (V holds S r).
+template <typename T>
+static int ws_first_residual(Ctx* c, int p, const double* c_old) {
+    hipStream_t st = c->stream;
+    const int nsys = c->S * c->P;
+    const int first = c->sys_tab_first[p * c->S];
+    const int end = (p + 1) * c->S < nsys ? c->sys_tab_first[(p + 1) * c->S] : (int)c->blocks_sys.size();
+    // the field pointer of problem p, uploaded alone (the other entries may not be set)
+    c->h_fields[p] = const_cast<double*>(c_old);
+    MPM_HIP(hipMemcpyAsync(c->d_fields + p, c->h_fields + p, sizeof(double*), hipMemcpyHostToDevice, st));
+    KArgs<T> a = make_args<T>(c, c->d_blocks_sys + first);
+    k_gather<T><<<(unsigned)(end - first), kThreads, 0, st>>>(a);
+    k_residual<T><<<(unsigned)(end - first), kThreads, 0, st>>>(a, kResFirst);
+    MPM_HIP(hipGetLastError());
+    return MPM_OK;
+}
+
 int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* in_bf16, float* target) {
     int rc = ensure_layout(c);
     if (rc != MPM_OK) return rc;
@@ -2474,11 +2532,25 @@ int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* i
     const ProbDev& pd = c->h_probs[p];
     const long long G = (long long)ph.gd[0] * ph.gd[1] * ph.gd[2];
     const int bx = ph.hi[0] - ph.lo[0], by = ph.hi[1] - ph.lo[1], bz = ph.hi[2] - ph.lo[2];
-    k_ws_input<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_old, ph.stat, c->d_scales, in_bf16);
-    k_ws_target<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_old, c_new, ph.stat, c->d_scales,
-                                                           target);
-    MPM_HIP(hipGetLastError());
-    MPM_HIP(hipStreamSynchronize(st));
+    // x, b, V and the partial sums are scratch until the next step recomputes them; the
+    // next step uploads its own field pointers
+    double* saved = c->h_fields[p];
+    c->up_valid = false;
+    rc = ksize(c) == 8 ? ws_first_residual<double>(c, p, c_old) : ws_first_residual<float>(c, p, c_old);
+    if (rc == MPM_OK) {
+        k_ws_input<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_old, ph.stat, c->d_scales,
+                                                              in_bf16);
+        const unsigned nb = (unsigned)c->blocks.size();
+        if (ksize(c) == 8) k_ws_resid<double><<<nb, kThreads, 0, st>>>(make_args<double>(c, c->d_blocks), p, c->d_scales, in_bf16);
+        else k_ws_resid<float><<<nb, kThreads, 0, st>>>(make_args<float>(c, c->d_blocks), p, c->d_scales, in_bf16);
+        k_ws_target<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_old, c_new, ph.stat,
+                                                               c->d_scales, target);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    c->h_fields[p] = saved;   // after the copy that read it has run
+    if (rc != MPM_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "mpm_ws_pair");
     return MPM_OK;
 }
 

@@ -303,7 +303,7 @@ __global__ void k_ws_static(const uint8_t* mask, const double* D, const double* 
     const int x = (int)(i % gx);
     const int y = (int)((i / gx) % gy);
     const int z = (int)(i / ((long long)gx * gy));
-    const int C = 3 * S + 1;
+    const int C = ws_static_channels(S);
     float* o = stat + i * C;
     if (x >= g.bx || y >= g.by || z >= g.bz) {
         for (int c = 0; c < C; ++c) o[c] = 0.f;
@@ -482,8 +482,8 @@ static int discretise(Ctx* c, ProbHost& ph, const BoxGeo& g, const uint8_t* mask
             ph.wsin = nullptr;
             ph.wsout = nullptr;
             ph.cap_grid = 0;
-            if (hipMalloc(&ph.stat, G * (3 * c->S + 1) * sizeof(float)) != hipSuccess ||
-                hipMalloc(&ph.wsin, G * (4 * c->S + 1) * sizeof(uint16_t)) != hipSuccess ||
+            if (hipMalloc(&ph.stat, G * ws_static_channels(c->S) * sizeof(float)) != hipSuccess ||
+                hipMalloc(&ph.wsin, G * ws_channels(c->S) * sizeof(uint16_t)) != hipSuccess ||
                 hipMalloc(&ph.wsout, G * c->S * sizeof(float)) != hipSuccess) {
                 (void)hipGetLastError();
                 set_error("mpm_fv_setup: device allocation of the warm-start buffers failed");

@@ -410,13 +410,13 @@ MPM_MAX_SPECIES = 4
 
 
 def _scales(in_scale, out_scale, nspecies=None):
-    """ctypes arrays of the warm-start scales.  The library reads 4 S + 1 input and S
+    """ctypes arrays of the warm-start scales.  The library reads 5 S + 1 input and S
     output scales; with ``nspecies`` the lengths must be exactly those, and the arrays
     are always at least as long as the largest S needs, so no read runs past them."""
-    if nspecies is not None and (len(in_scale) != 4 * nspecies + 1 or len(out_scale) != nspecies):
-        raise ValueError(f"need {4 * nspecies + 1} input scales and {nspecies} output scales, "
+    if nspecies is not None and (len(in_scale) != 5 * nspecies + 1 or len(out_scale) != nspecies):
+        raise ValueError(f"need {5 * nspecies + 1} input scales and {nspecies} output scales, "
                          f"got {len(in_scale)} and {len(out_scale)}")
-    ni = max(len(in_scale), 4 * MPM_MAX_SPECIES + 1)
+    ni = max(len(in_scale), 5 * MPM_MAX_SPECIES + 1)
     no = max(len(out_scale), MPM_MAX_SPECIES)
     a = (ctypes.c_float * ni)(*[float(v) for v in in_scale])
     b = (ctypes.c_float * no)(*[float(v) for v in out_scale])
@@ -509,15 +509,24 @@ class Net:
         mpm_net_write(self.handle, 1, t.contiguous())
 
     def forward(self, x, out):
+        if x.dim() != 5 or x.shape[-1] != self.in_ch:
+            raise ValueError(f"x must be [n][d][h][w][{self.in_ch}]")
+        if tuple(out.shape) != tuple(x.shape[:4]) + (self.out_ch,):
+            raise ValueError(f"out must be [n][d][h][w][{self.out_ch}] matching x")
         mpm_net_forward(self.handle, x, out)
+        self._out_numel = out.numel()
 
     def backward(self, grad_out):
+        if grad_out.numel() != getattr(self, "_out_numel", -1):
+            raise ValueError("grad_out must have the shape of the last forward pass's output")
         mpm_net_backward(self.handle, grad_out)
 
     def zero_grad(self):
         mpm_net_zero_grad(self.handle)
 
     def mse(self, out, target, grad_out):
+        if target.numel() != out.numel() or grad_out.numel() != out.numel():
+            raise ValueError("out, target and grad_out must have the same number of values")
         return mpm_net_mse(self.handle, out, target, grad_out)
 
     def adam(self, lr, t, b1=0.9, b2=0.999, eps=1e-8):
@@ -591,6 +600,14 @@ class Solver:
         return mpm_ws_grid(self.ctx, problem)
 
     def ws_pair(self, problem, c_old, c_new, in_scale, out_scale, in_bf16, target):
+        gx, gy, gz = self.ws_grid(problem)
+        S = self.nspecies
+        if in_bf16.numel() != gx * gy * gz * (5 * S + 1) or target.numel() != gx * gy * gz * S:
+            raise ValueError(f"in_bf16 must hold {gx * gy * gz * (5 * S + 1)} values and target "
+                             f"{gx * gy * gz * S} (grid {gx} x {gy} x {gz}, {S} species)")
+        for name, f in (("c_old", c_old), ("c_new", c_new)):
+            if f.dim() != 4 or f.shape[0] != S:
+                raise ValueError(f"{name} must be [S][z][y][x]")
         mpm_ws_pair(self.ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target, self.nspecies)
 
     def apply(self, problem, x, y, mode):

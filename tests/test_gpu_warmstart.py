@@ -6,7 +6,7 @@ import pytest
 
 from gpu_helpers import gpu_run, rel_err_per_species, require_gpu, to_dev
 from oracle import unet
-from oracle.fv import box_slice
+from oracle.fv import assemble, box_slice
 from oracle.step import run
 from synth import config1, config4_patch, random_problem
 
@@ -21,28 +21,35 @@ def _torch_bf16_bits(a):
     return t.view(torch.int16).numpy().view(np.uint16)
 
 
+def _bf16_values(bits):
+    return (np.asarray(bits, np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
 def _ws_pair_case(p, S, box=None):
     """Network input and training target built by the library, against their
     definition: each channel (c^n, k, D, s per species, then the mask) times its scale,
-    rounded to BF16 on the box grid (zero past the box); target (c^{n+1} - c^n) /
-    out_scale on domain voxels, zero elsewhere."""
+    rounded to BF16 on the box grid (zero past the box), the Jacobi-scaled residual of
+    c^n per species; target (c^{n+1} - c^n) / out_scale on domain voxels, zero
+    elsewhere."""
     torch = require_gpu()
     import paper_2505_03067_amd as m
-    from oracle.fv import box_slice
+    from oracle.fv import assemble, box_slice
     from paper_2505_03067_amd.train import input_scales
     box = box if box is not None else p.box
-    in_scale = input_scales(S)
     out_scale = [0.5, 0.25, 2e-3, 3e-3][:S]
+    in_scale = input_scales(S, out_scale)
     d = to_dev(p)
     f = torch.from_numpy(p.c0).cuda()
     with m.Solver(S, 1, warm_start=m.MPM_WS_NET) as s:
         s.setup(0, box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+        for _ in range(2):          # a c^n away from the uniform initial state
+            s.step([f], 1e-10)
         old = f.clone()
         s.step([f], 1e-10)
         gx, gy, gz = s.ws_grid(0)
         ext = [hi - lo for lo, hi in zip(*box)]
         assert (gx, gy, gz) == tuple((e + 7) // 8 * 8 for e in ext)
-        inp = torch.empty((gz, gy, gx, 4 * S + 1), dtype=torch.int16, device="cuda")
+        inp = torch.empty((gz, gy, gx, 5 * S + 1), dtype=torch.int16, device="cuda")
         tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
         s.ws_pair(0, old, f, in_scale, out_scale, inp, tgt)
     got_in = inp.cpu().numpy().view(np.uint16)
@@ -59,6 +66,24 @@ def _ws_pair_case(p, S, box=None):
         assert np.array_equal(got_in[..., ch], want), ch
     dom = np.zeros((gz, gy, gx), bool)
     dom[:ez, :ey, :ex] = p.mask[sl] != 0
+    # residual channels: d = (b - A c_old) / A_PP on the domain voxels, zero elsewhere,
+    # from the oracle's assembly.  The GPU forms S (S r) with S r stored in the Krylov
+    # type, so its BF16 value may differ by one unit in the last place, and r carries
+    # the cancellation error of b - A x (about 1e-15 of |b| + |A||x|) on both sides
+    mb = p.mask[sl].astype(bool)
+    for s in range(S):
+        A, q = assemble(mb, p.D[s][sl], p.k[s][sl], p.src[s][sl], float(p.c_b[s]), p.dt, p.h)
+        x = c0[s][sl][mb]
+        dvals = (x + q - A @ x) / A.diagonal()
+        scale = np.float32(in_scale[4 * S + 1 + s])
+        want = np.zeros((gz, gy, gx))
+        want[:ez, :ey, :ex][mb] = unet.bf16(dvals.astype(np.float32) * scale)
+        got = _bf16_values(got_in[..., 4 * S + 1 + s])
+        assert np.all(got[~dom] == 0.0)
+        atol = float(scale) * 1e-13 * (1.0 + np.abs(x).max() + np.abs(q).max())
+        assert np.all(np.abs(got - want) <= np.abs(want) * 2.0 ** -7 + atol), s
+        big = np.abs(want) > 1e3 * atol     # values far above the cancellation error
+        assert big.sum() > 1000 and np.mean(got[big] != want[big]) < 0.01, s
     for s in range(S):
         want = np.zeros((gz, gy, gx), np.float32)
         full = ((c1[s] - c0[s]) / np.float64(np.float32(out_scale[s])))[sl].astype(np.float32)
@@ -72,7 +97,7 @@ def test_ws_pair_matches_definition():
 
 
 def test_ws_pair_matches_definition_four_species():
-    """Four species: 17 input channels, the output scales after all of them (a layout
+    """Four species: 21 input channels, the output scales after all of them (a layout
     that once let the fourth species' input scales overlap the output scales); a ragged,
     masked box whose grid is padded past it on every axis."""
     p = random_problem(91, (30, 27, 21), S=4, fill=0.7)
@@ -80,7 +105,7 @@ def test_ws_pair_matches_definition_four_species():
 
 
 def test_four_species_network_attaches_and_falls_back():
-    """A 17-channel network on a four-species context: the zero prediction is rejected
+    """A 21-channel network on a four-species context: the zero prediction is rejected
     for every system and the solve matches the oracle."""
     torch = require_gpu()
     import paper_2505_03067_amd as m
@@ -88,11 +113,11 @@ def test_four_species_network_attaches_and_falls_back():
     p = random_problem(92, (24, 20, 16), S=4, fill=0.7)
     d = to_dev(p)
     f = torch.from_numpy(p.c0).cuda()
-    net = m.Net(17, 4, [16, 32], seed=4)
+    net = m.Net(21, 4, [16, 32], seed=4)
     with m.Solver(4, 1, warm_start=m.MPM_WS_NET) as s:
         s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
         with pytest.raises(ValueError):
-            s.attach(net, input_scales(3), [0.0] * 4)       # 13 scales for 4 species
+            s.attach(net, input_scales(3), [0.0] * 4)       # 16 scales for 4 species
         s.attach(net, input_scales(4), [0.0] * 4)
         for _ in range(2):
             s.step([f], 1e-10)
@@ -125,12 +150,12 @@ def _plain_and_ws(p, steps, setup_net, tile=2048):
 
 def test_zero_prediction_falls_back_to_plain():
     import paper_2505_03067_amd as m
-    from paper_2505_03067_amd.train import IN_SCALE
+    from paper_2505_03067_amd.train import input_scales
     p = random_problem(81, (24, 24, 16), S=3, fill=0.7)
 
     def setup(s):
-        net = m.Net(13, 3, [16, 32], seed=1)
-        s.attach(net, IN_SCALE, [0.0, 0.0, 0.0])
+        net = m.Net(16, 3, [16, 32], seed=1)
+        s.attach(net, input_scales(3), [0.0, 0.0, 0.0])
         return net
 
     (f0, st0), (f1, st1) = _plain_and_ws(p, 2, setup)
@@ -158,13 +183,13 @@ def _check_oracle(p, steps, got, tol=1e-10):
 def test_poisoned_network_falls_back():
     torch = require_gpu()
     import paper_2505_03067_amd as m
-    from paper_2505_03067_amd.train import IN_SCALE
+    from paper_2505_03067_amd.train import input_scales
     p = random_problem(82, (24, 24, 16), S=3, fill=0.7)
 
     def setup(s):
-        net = m.Net(13, 3, [16, 32], seed=2)
+        net = m.Net(16, 3, [16, 32], seed=2)
         net.set_params(torch.full((net.count,), float("nan"), device="cuda"))
-        s.attach(net, IN_SCALE, [1.0, 1.0, 1.0])
+        s.attach(net, input_scales(3), [1.0, 1.0, 1.0])
         return net
 
     (f0, _), (f1, st1) = _plain_and_ws(p, 2, setup)
@@ -198,7 +223,7 @@ def test_learned_warm_start_gains_over_plain():
     train_probs = [config4_patch(100 + i, n=32) for i in range(24)]
     out_scale = tr.estimate_out_scale(train_probs[:4], 10)
     pairs = list(tr.generate_pairs(train_probs, 20, range(1, 20), out_scale))
-    net = m.Net(13, 3, [16, 32, 64, 64], seed=7)
+    net = m.Net(16, 3, [16, 32, 64, 64], seed=7)
     t0 = time.perf_counter()
     losses = tr.train(net, pairs, epochs=60, batch=4, lr=2e-3, seed=0)
     print(f"{len(pairs)} pairs, training {time.perf_counter() - t0:.1f} s, losses",
@@ -223,7 +248,7 @@ def test_learned_warm_start_gains_over_plain():
     used = 0
     with m.Solver(3, 1, warm_start=m.MPM_WS_NET) as s:
         s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
-        s.attach(net, tr.input_scales(3), out_scale)
+        s.attach(net, tr.input_scales(3, out_scale), out_scale)
         for _ in range(4):
             s.step([f], 1e-12)
             used += sum(s.stats(0, sp)["warm_start_used"] for sp in range(3))
