@@ -264,7 +264,9 @@ int32_t mpm_net_sync_weights(mpm_net net);
 int32_t mpm_net_read(mpm_net net, int32_t what, float* dst);
 int32_t mpm_net_write(mpm_net net, int32_t what, const float* src);
 /* in: device BF16 [n][d][h][w][in_ch]; out: device FP32 [n][d][h][w][out_ch]; d, h, w
- * multiples of 2^(levels-1).  Keeps the activations for mpm_net_backward. */
+ * multiples of 2^(levels-1).  Keeps the activations for mpm_net_backward.  When in_ch is
+ * a multiple of 16 the input is read in place, so it must stay unchanged until the
+ * backward pass; otherwise it is copied into a padded buffer. */
 int32_t mpm_net_forward(mpm_net net, const uint16_t* in, int32_t n, int32_t d, int32_t h, int32_t w, float* out);
 /* Accumulate parameter gradients for dL/d(out) = grad_out (device FP32, shape of out). */
 int32_t mpm_net_backward(mpm_net net, const float* grad_out);
@@ -290,7 +292,8 @@ int32_t mpm_net_debug_layer(mpm_net net, int32_t layer, int32_t mode, int32_t n,
  * pass into dst (device, *count 16-bit values).  With dst = NULL only *count is set to
  * the element count; otherwise *count must equal it.  Tensors (index in brackets; all
  * NDHWC on the grid of their level):
- *  MPM_NT_INPUT       the input padded to a multiple of 16 channels (index ignored);
+ *  MPM_NT_INPUT       the input as the first layer read it, padded to a multiple of
+ *                     16 channels (index ignored);
  *  MPM_NT_ACT [i]     output of 3x3x3 layer i after the ReLU (forward order);
  *  MPM_NT_ACT_GRAD [i] gradient with respect to that output (after mpm_net_backward;
  *                     for the last 3x3x3 layer see MPM_NT_HEAD_GRAD);

@@ -28,7 +28,8 @@ struct Net {
     // buffers for the current input shape
     int dims[4] = {0, 0, 0, 0};        // n, D, H, W
     std::vector<void*> bufs;
-    uint16_t* xin = nullptr;
+    uint16_t* xin = nullptr;           // the input padded to cin_p channels (when in_ch < cin_p)
+    const uint16_t* x0 = nullptr;      // what the first layer read in the last forward pass
     std::vector<uint16_t*> act, gin, pooled, cat, dcat;
     std::vector<int> lvl_of;
     uint16_t* ghead = nullptr;

@@ -141,8 +141,9 @@ static int ensure_acts(Net* n, int nb, int D, int H, int W) {
     n->pooled.assign(L, nullptr);
     n->cat.assign(L, nullptr);
     n->dcat.assign(L, nullptr);
-    int rc = alloc(vox(0) * n->layers[0].cin_p, &n->xin);
-    if (rc) return rc;
+    int rc = MPM_OK;
+    n->xin = nullptr;
+    if (n->in_ch != n->layers[0].cin_p && (rc = alloc(vox(0) * n->layers[0].cin_p, &n->xin))) return rc;
     // level of each conv layer
     std::vector<int> lvl_of(nl, 0);
     for (int l = 0; l < L; ++l) lvl_of[2 * l] = lvl_of[2 * l + 1] = l;
@@ -177,19 +178,20 @@ static int ensure_acts(Net* n, int nb, int D, int H, int W) {
 // a multiple of the group count).
 template <int NTB, bool WL, bool GATED>
 static int launch_conv(const ConvArgs& a, hipStream_t st) {
-    constexpr int lds = conv_lds_bytes(NTB);
-    static int slots = 0;   // resident blocks of the device, limited by LDS
+    constexpr int lds = conv_lds_bytes(NTB, WL);
+    static int slots = 0;   // resident blocks of the device (registers and LDS permitting)
     static const hipError_t granted = [] {
         int dev = 0, cap = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
         if (e == hipSuccess && cap < lds) e = hipErrorInvalidValue;
         if (e == hipSuccess)
             e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, WL, GATED>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        slots = std::max(1, cus) * std::max(1, per_cu / lds);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv<NTB, WL, GATED>, 256, lds);
+        slots = std::max(1, cus) * std::max(1, per_cu);
         return e;
     }();
     if (granted != hipSuccess) return hip_fail(granted, "U-Net convolution LDS");
@@ -244,8 +246,15 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
     hipStream_t st = n->stream;
     const long long P0 = (long long)nb * D * H * W;
     const ConvL& l0 = n->layers[0];
-    k_pad_channels<<<blocks_for(P0), 256, 0, st>>>(in, n->in_ch, l0.cin_p, P0, n->xin);
-    const uint16_t* h = n->xin;
+    // an input whose channel count is a multiple of 16 is read in place (and must stay
+    // unchanged until the backward pass); others are padded with zero channels
+    if (n->in_ch == l0.cin_p) {
+        n->x0 = in;
+    } else {
+        k_pad_channels<<<blocks_for(P0), 256, 0, st>>>(in, n->in_ch, l0.cin_p, P0, n->xin);
+        n->x0 = n->xin;
+    }
+    const uint16_t* h = n->x0;
     int hch = l0.cin_p;
     int li = 0;
     for (int lvl = 0; lvl < L; ++lvl) {
@@ -444,7 +453,7 @@ int net_backward(Net* n, const float* dout) {
         if ((rc = conv_input_grad(n, li, lvl, g, n->act[li], n->gin[li - 1]))) return rc;
         g = n->gin[li - 1];
         --li;
-        const uint16_t* xin = lvl == 0 ? n->xin : n->pooled[lvl];
+        const uint16_t* xin = lvl == 0 ? n->x0 : n->pooled[lvl];
         if ((rc = conv_param_grads(n, li, lvl, xin, cinl, g, n->act[li], n->grad + n->layers[li].woff, n->grad + n->layers[li].boff))) return rc;
         if (lvl == 0) break;
         // gradient wrt the pooled input, then wrt the previous level's output (+ its skip)
@@ -703,7 +712,7 @@ extern "C" int32_t mpm_net_debug_tensor(mpm_net net, int32_t kind, int32_t index
     long long elems = 0;
     switch (kind) {
         case MPM_NT_INPUT:
-            src = n->xin;
+            src = n->x0;
             elems = vox(0) * n->layers[0].cin_p;
             break;
         case MPM_NT_ACT:

@@ -60,22 +60,24 @@ __device__ inline uint4 apply_gate(uint4 t, const uint4 g) {
     return make_uint4(tw[0], tw[1], tw[2], tw[3]);
 }
 
-// 3x3x3 convolution as an implicit GEMM with the input and the weights staged in LDS.
+// 3x3x3 convolution as an implicit GEMM with the input staged in LDS.
 // Work items are (voxel tile, output-tile group) pairs: a voxel tile is 16 (x) x 4 (y) x
 // 4 (z) voxels of one sample, a group NTB of the GEMM's NT 16-channel output tiles.
 // Blocks are persistent: block b takes items b, b + G, b + 2G, ... (G = grid size, a
 // multiple of NT / NTB, so a block keeps one output-tile group).  Per item and chunk of
-// 16 input channels, the input tile with its one-voxel halo (18 x 6 x 6 voxels) and the
-// chunk's weights are staged in LDS, and all 27 taps read them from there; the global
-// loads of the next (item, chunk) are issued before the MFMAs of the current one, and
-// weights that do not change between items (one chunk) are staged once.  Wave w
-// computes rows (y, z) 4w..4w+3 of the tile (four 16-voxel M tiles).  K runs over tap x
-// channel in 14 MFMA steps of 32 per chunk: step s takes taps 2s and 2s+1 in the two
-// lane halves h = g / 2 (g = lane / 16; channels 8 (g mod 2) .. + 7 of the chunk), and
-// the 14th step pairs tap 26 with zero weights.  The taps are unrolled at compile time,
-// so every LDS read is a per-lane base plus an immediate.  (Chunks of 32 channels, one
-// tap per step, need 27 steps instead of 28 but 78 KB of LDS per block, two blocks per
-// CU instead of three, and measured slower.)
+// 16 input channels, the input tile with its one-voxel halo (18 x 6 x 6 voxels) is
+// staged in LDS, and all 27 taps read it from there; the global loads of the next
+// (item, chunk) are issued before the MFMAs of the current one.  With one chunk (16
+// input channels) the block's weights stay in registers for all its items; with more,
+// each chunk's weights are staged in LDS beside the tile.  Wave w computes rows (y, z)
+// = (0..3, w) of the tile (four 16-voxel M tiles).  K runs over tap x channel in 14 MFMA
+// steps of 32 per chunk: the two lane halves h = g / 2 (g = lane / 16; channels
+// 8 (g mod 2) .. + 7 of the chunk) take the two taps step_tap(s, h).  Nine of the steps
+// pair the taps dx = 0 and 1 of one halo row, so each row read from LDS feeds the MFMAs
+// of up to three M tiles (38 A-fragment reads per chunk and wave instead of 56).  The
+// taps are unrolled at compile time, so every LDS read is a per-lane base plus an
+// immediate.  (Chunks of 32 channels, one tap per step, need 27 steps instead of 28 but
+// 78 KB of LDS per block, two blocks per CU instead of three, and measured slower.)
 //
 // Packed weights (k_pack): one 16-byte B fragment per (step, output tile, lane), steps
 // numbered over the chunks in order; the fragment of lane (n = lane mod 16, g) holds the
@@ -84,27 +86,47 @@ __device__ inline uint4 apply_gate(uint4 t, const uint4 g) {
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 constexpr int kHV = kHX * kHY * kHZ;
-constexpr int kCS = 24;    // LDS channel stride per halo voxel (16 + 8), BF16 values
+#ifndef MPM_CONV_CS
+#define MPM_CONV_CS 16
+#endif
+constexpr int kCS = MPM_CONV_CS;   // LDS channel stride per halo voxel, BF16 values (16: no padding)
+static_assert(kCS % 8 == 0 && kCS >= 16, "16-byte aligned halo voxels of 16 channels");
 constexpr int kSteps = 14; // MFMA steps per 16-channel chunk
 
 // halo-tile voxel offset of tap t = 9 dz + 3 dy + dx (dz, dy, dx in 0..2)
 __host__ __device__ constexpr int tap_vox(int t) { return ((t / 9) * kHY + (t / 3) % 3) * kHX + t % 3; }
 
-// the second tap of each pair lies 1, 16 or 70 halo voxels past the first (a step along
-// x, to the next y row, or to the next z plane)
-__host__ __device__ constexpr bool tap_pairs_known() {
-    for (int s = 0; s < 13; ++s) {
-        const int d = tap_vox(2 * s + 1) - tap_vox(2 * s);
-        if (d != 1 && d != 16 && d != 70) return false;
-    }
+// The taps of MFMA step s of a 16-channel chunk in lane half h (lanes 32 h .. 32 h + 31),
+// paired so that one A fragment read from LDS serves several M tiles: steps 0-8 pair
+// (dz, dy, 0) with (dz, dy, 1) (one halo row; the second tap one voxel further along x),
+// so the fragment of M tile mt at dy is that of M tile mt + 1 at dy - 1; steps 9-11 pair
+// (dz, 0, 2) with (dz, 1, 2) (the next row), step 12 (0, 2, 2) with (1, 2, 2) (the next
+// plane), step 13 (2, 2, 2) with zero weights (tap 27).
+__host__ __device__ constexpr int step_tap(int s, int h) {
+    return s < 9 ? 9 * (s / 3) + 3 * (s % 3) + h : s < 12 ? 9 * (s - 9) + 2 + 3 * h : s == 12 ? 8 + 9 * h : (h ? 27 : 26);
+}
+__host__ __device__ constexpr bool step_taps_cover() {
+    int seen[28] = {};
+    for (int s = 0; s < kSteps; ++s)
+        for (int h = 0; h < 2; ++h) ++seen[step_tap(s, h)];
+    for (int t = 0; t < 28; ++t)
+        if (seen[t] != 1) return false;
     return true;
 }
-static_assert(tap_pairs_known(), "tap pair shifts");
+static_assert(step_taps_cover(), "every tap (and the zero tap 27) in exactly one step half");
 
-// LDS of one block: the halo tile (kCS values per voxel; the 48-byte stride spreads the
-// 16 voxels of an A fragment over distinct banks), then one chunk's weights
+// LDS of one block: the halo tile (kCS values per voxel: 32 bytes, unpadded; padded
+// strides of 48, 64 and 80 bytes measured no faster), then one chunk's weights
 __host__ __device__ constexpr int conv_x_bytes() { return kHV * kCS * 2; }
-__host__ __device__ constexpr int conv_lds_bytes(int ntb) { return conv_x_bytes() + kSteps * ntb * 1024; }
+// the block's weights (one chunk's) staged in LDS after the halo tile, except with one
+// chunk and one output tile (then they live in registers); then each wave's epilogue
+// scratch, where the output tiles are transposed to voxel-major rows of 16 channels
+constexpr int kEpRow = 48;   // LDS bytes per voxel row of the epilogue (16 BF16 + 8 of padding)
+__host__ __device__ constexpr int conv_w_bytes(int ntb, bool wl) { return wl || ntb > 1 ? kSteps * ntb * 1024 : 0; }
+__host__ __device__ constexpr int conv_ep_bytes(int ntb) { return 4 * (4 * ntb * 16 * kEpRow); }
+__host__ __device__ constexpr int conv_lds_bytes(int ntb, bool wl) {
+    return conv_x_bytes() + conv_w_bytes(ntb, wl) + conv_ep_bytes(ntb);
+}
 
 // Origin of a voxel tile (tile index: x fastest, then y, z, sample).
 struct ConvTile {
@@ -203,36 +225,57 @@ __device__ inline void conv_store(char* xs, const ConvRegs<NTB, WL, GATED>& r) {
     if (WL) conv_store_w<NTB>(xs, r.w);
 }
 
-// One 16-channel chunk: 14 MFMA steps over the 27 taps.  abase[mt] is the LDS byte
-// address of the lane's voxel (tap 0, channel 0) in M tile mt.
-template <int NTB>
-__device__ inline void conv_chunk(const char* xs, const uint32_t (&abase)[4], f32x4 (&acc)[4][NTB]) {
-    constexpr int VB = kCS * 2;   // LDS bytes per halo voxel
-    const int lane = threadIdx.x & 63, g = lane >> 4;
-    const int h = g >> 1;         // lane half: second tap of a pair
-    uint32_t al[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) al[mt] = abase[mt] + 16 * (g & 1);
-    // A address shift of the lane half that takes the second tap of a pair, by pair kind
-    const uint32_t dsh[3] = {h ? 1u * VB : 0u, h ? 16u * VB : 0u, h ? 70u * VB : 0u};
+// One 16-channel chunk: 14 MFMA steps over the 27 taps (step_tap).  lb is the LDS byte
+// address of the lane's voxel x = lane % 16 in halo row 0 of the wave's plane, channels
+// 8 (g mod 2) .. + 7 (g = lane / 16).  M tile mt covers output row y = mt, which reads
+// halo row mt + dy for tap row dy.  B fragments come from registers (breg, weights
+// fixed for the block) or from the chunk's weights in LDS.
+template <int NTB, bool BREG>
+__device__ inline void conv_chunk(const char* xs, uint32_t lb, const uint4 (&breg)[kSteps][NTB],
+                                  f32x4 (&acc)[4][NTB]) {
+    constexpr int VB = kCS * 2;         // LDS bytes per halo voxel
+    constexpr int ROW = kHX * VB;       // per halo row
+    constexpr int PLANE = kHY * ROW;    // per halo plane
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const uint32_t b1 = lb + h * VB, bR = lb + h * ROW, bZ = lb + h * PLANE;
     const char* wl = xs + conv_x_bytes() + 16 * lane;
+    auto bfrag = [&](int s, int nt) -> bf16x8 {
+        if (BREG) return __builtin_bit_cast(bf16x8, breg[s][nt]);
+        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wl + (s * NTB + nt) * 1024));
+    };
+    auto afrag = [&](uint32_t addr) -> bf16x8 {
+        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(xs + addr));
+    };
+    // steps 0-8: six halo rows per plane feed the 12 (M tile, dy) products of taps dx = 0, 1
 #pragma unroll
-    for (int s = 0; s < kSteps; ++s) {
+    for (int dz = 0; dz < 3; ++dz) {
+        bf16x8 a[6];
+#pragma unroll
+        for (int y = 0; y < 6; ++y) a[y] = afrag(b1 + (dz * kHY + y) * ROW);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            bf16x8 b[NTB];
+#pragma unroll
+            for (int nt = 0; nt < NTB; ++nt) b[nt] = bfrag(3 * dz + dy, nt);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NTB; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt + dy], b[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+    // steps 9-13: taps dx = 2, paired across rows, across planes, and with zero weights
+#pragma unroll
+    for (int s = 9; s < kSteps; ++s) {
         bf16x8 b[NTB];
 #pragma unroll
-        for (int nt = 0; nt < NTB; ++nt)
-            b[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wl + (s * NTB + nt) * 1024));
-        // immediate LDS offset of the pair's first tap, and the pair's shift kind
-        const uint32_t imm = (uint32_t)tap_vox(2 * s) * VB;
-        int kind = 3;
-        if (s < 13) {
-            const int d = tap_vox(2 * s + 1) - tap_vox(2 * s);
-            kind = d == 1 ? 0 : d == 16 ? 1 : 2;
-        }
+        for (int nt = 0; nt < NTB; ++nt) b[nt] = bfrag(s, nt);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-            const uint32_t ad = al[mt] + (kind < 3 ? dsh[kind] : 0u) + imm;
-            const bf16x8 af = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(xs + ad));
+            const uint32_t ad = s < 12 ? bR + (((s - 9) * kHY + mt) * kHX + 2) * VB
+                              : s == 12 ? bZ + ((mt + 2) * kHX + 2) * VB
+                                        : lb + ((2 * kHY + mt + 2) * kHX + 2) * VB;
+            const bf16x8 af = afrag(ad);
 #pragma unroll
             for (int nt = 0; nt < NTB; ++nt)
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b[nt], acc[mt][nt], 0, 0, 0);
@@ -246,7 +289,7 @@ __device__ inline void conv_chunk(const char* xs, const uint32_t (&abase)[4], f3
 // its weights are staged once), and its epilogue issues no loads, so the wait for the
 // next item's prefetched input does not also wait for the stores of this one.
 template <int NTB, bool WL, bool GATED>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+__global__ __launch_bounds__(256, (NTB == 1 && !GATED) ? 3 : 2) void k_conv(ConvArgs a) {
     extern __shared__ uint4 xs_dyn[];
     char* xs = reinterpret_cast<char*>(xs_dyn);
     const int lane = threadIdx.x & 63;
@@ -264,18 +307,28 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         const int co = (tb + nt) * 16 + (lane & 15);
         bias[nt] = a.bias && co < a.cout ? a.bias[co] : 0.f;
     }
-    uint32_t abase[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const int r = 4 * wave + mt;
-        abase[mt] = (uint32_t)((((r / kTY) * kHY + r % kTY) * kHX + (lane & 15)) * kCS * 2);
-    }
+    // BF16 output in whole 16-byte halves of voxel rows: through the LDS epilogue
+    const bool vec = a.y && !a.yf && a.ldy % 8 == 0 && a.yoff % 8 == 0 && ((uintptr_t)a.y & 15) == 0;
+    // the lane's voxel x = lane % 16 in halo row 0 of plane 'wave' (M tile mt adds mt rows)
+    const uint32_t lb = (uint32_t)(((wave * kHY) * kHX + (lane & 15)) * kCS * 2 + 16 * ((lane >> 4) & 1));
     f32x4 acc[4][NTB];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NTB; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (!WL) {   // one chunk: the block's weights, read by every item after the first barrier
+    // one chunk (16 input channels) and one output tile: the block's B fragments stay in
+    // registers for every item (packed in fragment order: step, output tile, lane); with
+    // two output tiles they are staged once in LDS (112 more registers would leave one
+    // wave per SIMD)
+    constexpr bool BREG = !WL && NTB == 1;
+    uint4 breg[kSteps][NTB];
+    if (BREG) {
+        const uint4* wsrc = reinterpret_cast<const uint4*>(a.w);
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s)
+#pragma unroll
+            for (int nt = 0; nt < NTB; ++nt) breg[s][nt] = wsrc[((long long)s * a.nt + tb + nt) * 64 + lane];
+    } else if (!WL) {   // read from LDS by every item after the first barrier
         uint4 w[ConvW<NTB>::M];
         conv_fetch_w<NTB>(a, 0, tb, w);
         conv_store_w<NTB>(xs, w);
@@ -296,8 +349,46 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         }
         const bool more = nitem < nitems;
         if (more) conv_fetch<NTB, WL, GATED>(a, conv_tile(a, nitem / nsplit), 16 * nc, tb, regs);   // in flight during the MFMAs
-        conv_chunk<NTB>(xs, abase, acc);
-        if (chunk == nchunk - 1) {
+        conv_chunk<NTB, BREG>(xs, lb, breg, acc);
+        if (chunk == nchunk - 1 && vec) {
+            // D layout: lane holds rows 4 * (lane / 16) + i (voxels x0 + row), column lane % 16.
+            // The wave writes its tiles to its LDS scratch as BF16, reads them back as 16-byte
+            // halves of voxel rows (8 channels) and stores those: two global stores per lane
+            // and tile pair instead of sixteen 2-byte stores
+            const ConvTile t = conv_tile(a, item / nsplit);
+            char* ep = xs + conv_x_bytes() + conv_w_bytes(NTB, WL) + wave * (4 * NTB * 16 * kEpRow);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NTB; ++nt) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float v = acc[mt][nt][i] + bias[nt];
+                        if (a.relu) v = fmaxf(v, 0.f);
+                        *reinterpret_cast<uint16_t*>(ep + ((mt * NTB + nt) * 16 + 4 * (lane >> 4) + i) * kEpRow +
+                                                     2 * (lane & 15)) = f2bf(v);
+                    }
+                    acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+            // LDS operations of one wave complete in order; keep the compiler from moving
+            // the reads above the writes of other lanes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int j = 0; j < 2 * NTB; ++j) {
+                const int R = 32 * j + (lane >> 1);      // row of the wave's 4 NTB tiles x 16 voxels
+                const int T = R >> 4, m = R & 15;
+                const int mt = T / NTB, nt = T % NTB;
+                const uint4 val = *reinterpret_cast<const uint4*>(ep + R * kEpRow + 16 * (lane & 1));
+                const int x = t.x0 + m, y = t.y0 + mt, z = t.z0 + wave;
+                const int co0 = (tb + nt) * 16 + 8 * (lane & 1);
+                if (x < a.W && y < a.H && z < a.D && co0 + 8 <= a.cout) {
+                    const long long p = t.sbase + ((long long)z * a.H + y) * a.W + x;
+                    *reinterpret_cast<uint4*>(a.y + p * a.ldy + a.yoff + co0) = val;
+                }
+            }
+        } else if (chunk == nchunk - 1) {
             // D layout: lane holds rows 4 * (lane / 16) + i (voxels x0 + row), column lane % 16
             const ConvTile t = conv_tile(a, item / nsplit);
 #pragma unroll
@@ -764,8 +855,7 @@ __global__ void k_adam(float* th, const float* g, float* m, float* v, long long 
 // g of step sg, returns the tap (27 for the zero half of the last pair) and the first of
 // the group's 8 input channels.
 __device__ inline void packed_step(int sg, int g, int& tap, int& c0) {
-    const int s = sg % kSteps;
-    tap = 2 * s + (g >> 1);
+    tap = step_tap(sg % kSteps, g >> 1);
     c0 = 16 * (sg / kSteps) + 8 * (g & 1);
 }
 
