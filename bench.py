@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--c4-chunk", type=int, default=16,
                     help="config4: geometries whose pairs are generated and trained on together")
     ap.add_argument("--c4-lr", type=float, default=1e-3, help="config4: Adam learning rate")
+    ap.add_argument("--c4-save", default=None, help="config4: save the trained parameters and scales here")
+    ap.add_argument("--c4-load", default=None,
+                    help="config4: evaluate a network saved by --c4-save instead of training one")
     ap.add_argument("--c4-eval", type=int, default=4, help="config4: unseen 128^3 evaluation geometries")
     ap.add_argument("--grow", action="store_true",
                     help="lung workloads: cells grow every step; the box is recomputed and the "
@@ -609,11 +612,17 @@ def config4_run(args, m, torch):
     from synth import config4_patch
     S = 3
     t0 = time.perf_counter()
-    # target scale: per-species RMS of the one-step change on four training geometries
-    out_scale = tr.estimate_out_scale([config4_patch(seed, 64) for seed in range(4)], 10)
     net = m.Net(5 * S + 1, S, [16, 32, 64, 64], seed=7)
     rng = np.random.default_rng(0)
     losses, gen_s, train_s, npairs, t = [], 0.0, 0.0, 0, 0
+    if args.c4_load:
+        saved = torch.load(args.c4_load, weights_only=True)
+        net.set_params(saved["params"].cuda())
+        out_scale = list(saved["out_scale"])
+        args.c4_epochs = 0
+    else:
+        # target scale: per-species RMS of the one-step change on four training geometries
+        out_scale = tr.estimate_out_scale([config4_patch(seed, 64) for seed in range(4)], 10)
     # streamed: every epoch regenerates the pairs of a chunk of geometries on the GPU from
     # their seeds (the solver's trajectories are deterministic), trains on them shuffled,
     # and drops them (20,000 64^3 pairs would need about 230 GB)
@@ -643,23 +652,35 @@ def config4_run(args, m, torch):
                 net.zero_grad()
                 net.backward(g)
                 t += 1
-                net.adam(args.c4_lr, t)
+                # cosine decay of the learning rate over the whole run
+                frac = min(1.0, t / max(1, args.c4_epochs * args.c4_geometries * args.c4_pairs // 4))
+                net.adam(args.c4_lr * 0.5 * (1.0 + np.cos(np.pi * frac)), t)
             torch.cuda.synchronize()
             train_s += time.perf_counter() - tt
             if ep == 0:
                 npairs += len(pairs)
             del pairs
+            print(f"config4: epoch {ep}, geometries {c0 + args.c4_chunk}/{args.c4_geometries}, "
+                  f"running loss {tot / max(nb, 1):.4e}", file=sys.stderr, flush=True)
         losses.append(tot / max(nb, 1))
     pairs = None
+    if args.c4_save:
+        torch.save({"params": net.params().cpu(), "out_scale": list(out_scale), "widths": [16, 32, 64, 64],
+                    "in_ch": 5 * S + 1, "out_ch": S}, args.c4_save)
     del pairs
     evalp = [config4_patch(10 ** 6 + i, 128) for i in range(args.c4_eval)]
     tol = args.tol if args.tol is not None else 1e-8
     res = {}
-    for name, warm in (("plain", m.MPM_WS_NONE), ("extrapolated", m.MPM_WS_EXTRAP), ("learned", m.MPM_WS_NET)):
-        its, sps, _, acc = tr.evaluate(evalp, 20, tol, net=net, out_scale=out_scale, warm=warm)
+    for name, warm, prec in (("plain", m.MPM_WS_NONE, m.MPM_FP32_IR), ("plain_fp64", m.MPM_WS_NONE, m.MPM_FP64),
+                             ("extrapolated", m.MPM_WS_EXTRAP, m.MPM_FP32_IR),
+                             ("learned", m.MPM_WS_NET, m.MPM_FP32_IR)):
+        ratios = []
+        its, sps, _, acc = tr.evaluate(evalp, 20, tol, net=net, out_scale=out_scale, warm=warm, precision=prec,
+                                       ratios=ratios)
         res[name] = {"steps_per_s": round(sps, 3), "iterations_per_step": round(its, 2)}
         if warm != m.MPM_WS_NONE:
             res[name]["accepted_fraction"] = round(acc, 3)
+            res[name]["residual_ratio_warm_over_cn"] = round(float(np.mean(ratios)), 4) if ratios else None
     net.close()
     return {
         "metric": "implicit steps/s, 128^3 box x 3 species to 1e-8 resid; HBM GB/s; learned vs plain",
@@ -682,6 +703,7 @@ def config4_run(args, m, torch):
         "learned_vs_plain": {
             **res,
             "learned_over_plain": round(res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"], 3),
+            "learned_over_plain_fp64": round(res["learned"]["steps_per_s"] / res["plain_fp64"]["steps_per_s"], 3),
             "extrapolated_over_plain": round(res["extrapolated"]["steps_per_s"] / res["plain"]["steps_per_s"], 3),
             "training": {"pairs_per_epoch": npairs, "epochs": args.c4_epochs, "batch": 4, "lr": args.c4_lr,
                          "streamed": f"pairs of {args.c4_chunk} geometries at a time, regenerated on the GPU "

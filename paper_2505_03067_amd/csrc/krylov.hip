@@ -995,20 +995,52 @@ __device__ inline void stencil_direct(const T* __restrict__ v, const Block& blk,
     si.cxm = c[loc0 - 1];
 }
 
+// 16-byte loads at element alignment (a run of neighbours starts anywhere)
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef double f64x2u __attribute__((ext_vector_type(2), aligned(8)));
+template <typename T>
+__device__ inline void ldg16u(gptr<T> p, T (&o)[VW<T>::n]) {
+    if constexpr (sizeof(T) == 4) {
+        const f32x4u t = *(const __attribute__((address_space(1))) f32x4u*)p;
+        o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+    } else {
+        const f64x2u t = *(const __attribute__((address_space(1))) f64x2u*)p;
+        o[0] = t.x; o[1] = t.y;
+    }
+}
+
 template <typename T>
 __device__ inline void stencil_finish(const T* __restrict__ v, const Block& blk, int l0, const StencilIn<T>& si,
                                       T (&out)[VW<T>::n]) {
     constexpr int n = VW<T>::n;
     const gptr<T> c = as_global((const T*)blk.c);
+    const gptr<T> vg = as_global(v);
     T gyp[n], gym[n], cym[n], gzp[n], gzm[n], czm[n];
+    // When the neighbours of the lane's n consecutive unknowns are n consecutive unknowns
+    // in every direction (rows inside the domain), each neighbour operand is one 16-byte
+    // load instead of n single-element gathers; the whole wave takes one path
+    bool run = true;
 #pragma unroll
-    for (int e = 0; e < n; ++e) {
-        gyp[e] = v[blk.base + si.nb[e].y];
-        gym[e] = v[blk.base + si.nb[e].x];
-        cym[e] = c[blk.tot + blk.locbase + si.nb[e].x];
-        gzp[e] = v[blk.base + si.nb[e].w];
-        gzm[e] = v[blk.base + si.nb[e].z];
-        czm[e] = c[2 * blk.tot + blk.locbase + si.nb[e].z];
+    for (int e = 1; e < n; ++e)
+        run = run && si.nb[e].x == si.nb[0].x + e && si.nb[e].y == si.nb[0].y + e && si.nb[e].z == si.nb[0].z + e &&
+              si.nb[e].w == si.nb[0].w + e;
+    if (__all(run)) {
+        ldg16u<T>(vg + blk.base + si.nb[0].y, gyp);
+        ldg16u<T>(vg + blk.base + si.nb[0].x, gym);
+        ldg16u<T>(c + blk.tot + blk.locbase + si.nb[0].x, cym);
+        ldg16u<T>(vg + blk.base + si.nb[0].w, gzp);
+        ldg16u<T>(vg + blk.base + si.nb[0].z, gzm);
+        ldg16u<T>(c + 2 * blk.tot + blk.locbase + si.nb[0].z, czm);
+    } else {
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            gyp[e] = v[blk.base + si.nb[e].y];
+            gym[e] = v[blk.base + si.nb[e].x];
+            cym[e] = c[blk.tot + blk.locbase + si.nb[e].x];
+            gzp[e] = v[blk.base + si.nb[e].w];
+            gzm[e] = v[blk.base + si.nb[e].z];
+            czm[e] = c[2 * blk.tot + blk.locbase + si.nb[e].z];
+        }
     }
     // keep the gathers ahead of any arithmetic on the direct operands
     __builtin_amdgcn_sched_barrier(0);
