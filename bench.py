@@ -53,6 +53,9 @@ def parse():
                     help="config4: geometries whose pairs are generated and trained on together")
     ap.add_argument("--c4-lr", type=float, default=1e-3, help="config4: Adam learning rate")
     ap.add_argument("--c4-save", default=None, help="config4: save the trained parameters and scales here")
+    ap.add_argument("--c4-loss", default="residual", choices=["residual", "mse"],
+                    help="config4: train on the Jacobi-scaled residual each prediction leaves (mpm_ws_loss), "
+                         "or on the mean squared error of the predicted change")
     ap.add_argument("--c4-load", default=None,
                     help="config4: evaluate a network saved by --c4-save instead of training one")
     ap.add_argument("--c4-eval", type=int, default=4, help="config4: unseen 128^3 evaluation geometries")
@@ -92,9 +95,9 @@ def parse():
                     help="budget of the CPU oracle sample (0 = skip)")
     ap.add_argument("--learned-steps", type=int, default=20,
                     help="implicit steps of the learned-vs-plain comparison (0 = skip)")
-    ap.add_argument("--train-pairs", type=int, default=8,
+    ap.add_argument("--train-pairs", type=int, default=16,
                     help="solver steps that produce training pairs for the warm-start network")
-    ap.add_argument("--train-iters", type=int, default=200, help="Adam iterations of the network")
+    ap.add_argument("--train-iters", type=int, default=600, help="Adam iterations of the network")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device once (calibrates HBM counters)")
     return ap.parse_args()
@@ -255,55 +258,55 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     true residual), all with the launch mode of the headline, at the benchmark tolerance.
     """
     import numpy as np
+    from paper_2505_03067_amd import train as tr
     from paper_2505_03067_amd.train import input_scales
     S = prob.nspecies
     f = f0.clone()
 
-    def make_pairs(out_scale):
+    def make_pairs(out_scale, keep=False):
         g = f0.clone()
         pairs = []
-        with m.Solver(S, 1, warm_start=m.MPM_WS_NET) as s:
-            s.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
-            gx, gy, gz = s.ws_grid(0)
-            for _ in range(args.train_pairs):
-                old = g.clone()
-                s.step([g], 1e-10)
-                inp = torch.empty((gz, gy, gx, 5 * S + 1), dtype=torch.int16, device="cuda")
-                tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
-                s.ws_pair(0, old, g, input_scales(S, out_scale), out_scale, inp, tgt)
-                pairs.append((inp, tgt))
-        return pairs, g
+        s = m.Solver(S, 1, warm_start=m.MPM_WS_NET)
+        s.setup(0, box, t["mask"], t["D"], t["k"], t["src"], prob.c_b, prob.dt, prob.h)
+        gx, gy, gz = s.ws_grid(0)
+        for _ in range(args.train_pairs):
+            old = g.clone()
+            s.step([g], 1e-10)
+            inp = torch.empty((gz, gy, gx, 5 * S + 1), dtype=torch.int16, device="cuda")
+            tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
+            s.ws_pair(0, old, g, input_scales(S, out_scale), out_scale, inp, tgt)
+            pairs.append((s, inp, tgt))
+        if not keep:
+            s.close()
+        return pairs, g, s
 
-    raw, _ = make_pairs([1.0] * S)
+    raw, _, _ = make_pairs([1.0] * S)
     # per-species RMS of the one-step change over the domain voxels (target scale)
     sq, cnt = [0.0] * S, 0
-    for inp, tgt in raw:
+    for _, inp, tgt in raw:
         mask = inp[..., 4 * S] != 0
         cnt += int(mask.sum())
         for sp in range(S):
             sq[sp] += float((tgt[..., sp][mask].double() ** 2).sum())
     out_scale = [max((v / max(cnt, 1)) ** 0.5, 1e-30) for v in sq]
     del raw
-    pairs, f_after = make_pairs(out_scale)
+    pairs, f_after, pair_solver = make_pairs(out_scale, keep=True)
     net = m.Net(5 * S + 1, S, [16, 32, 64, 64], seed=7)
     rng = np.random.default_rng(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = []
     for it in range(1, args.train_iters + 1):
-        x, y = pairs[int(rng.integers(len(pairs)))]
-        out = torch.empty_like(y)
-        g = torch.empty_like(y)
-        net.forward(x.unsqueeze(0), out.unsqueeze(0))
-        losses.append(net.mse(out, y, g))
+        # the residual each prediction leaves (mpm_ws_loss), cosine-annealed learning rate
         net.zero_grad()
-        net.backward(g.unsqueeze(0))
-        net.adam(1e-3, it)
+        losses.append(tr.residual_step(net, [pairs[int(rng.integers(len(pairs)))]], out_scale))
+        net.adam(1e-3 * 0.5 * (1.0 + np.cos(np.pi * it / args.train_iters)), it)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    pair_solver.close()
     # the network's forward pass on the box grid against the dense BF16 MFMA peak
-    x0 = pairs[0][0].unsqueeze(0)
-    y0 = torch.empty_like(pairs[0][1]).unsqueeze(0)
+    x0 = pairs[0][1].unsqueeze(0)
+    y0 = torch.empty_like(pairs[0][2]).unsqueeze(0)
     net.forward(x0, y0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -348,6 +351,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     res["training"] = {"pairs": args.train_pairs, "iterations": args.train_iters, "seconds": round(train_s, 2),
                        "loss_first": round(float(np.mean(losses[:10])), 5),
                        "loss_last": round(float(np.mean(losses[-10:])), 5),
+                       "loss": "Jacobi-scaled residual left by the prediction (mpm_ws_loss)",
                        "network": "U-Net 16-32-64-64, BF16 MFMA kernels, FP32 Adam, on the box grid"}
     res["learned_over_plain"] = round(res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"], 3)
     res["extrapolated_over_plain"] = round(res["extrapolated"]["steps_per_s"] / res["plain"]["steps_per_s"], 3)
@@ -631,26 +635,35 @@ def config4_run(args, m, torch):
         order = rng.permutation(args.c4_geometries)
         for c0 in range(0, args.c4_geometries, args.c4_chunk):
             tg = time.perf_counter()
-            pairs = []
+            pairs, solvers = [], []
             for seed in order[c0:c0 + args.c4_chunk]:
                 seed = int(seed)
                 pick = set(np.random.default_rng(seed).choice(50, size=args.c4_pairs, replace=False).tolist())
-                pairs += list(tr.generate_pairs([config4_patch(seed, 64)], 50, pick, out_scale, tol=1e-10))
+                if args.c4_loss == "residual":
+                    sv, items = tr.solver_pairs(config4_patch(seed, 64), 50, pick, out_scale, tol=1e-10)
+                    solvers.append(sv)
+                    pairs += [(sv, inp, tgt) for inp, tgt in items]
+                else:
+                    pairs += [(None, inp, tgt) for inp, tgt in
+                              tr.generate_pairs([config4_patch(seed, 64)], 50, pick, out_scale, tol=1e-10)]
             torch.cuda.synchronize()
             tt = time.perf_counter()
             gen_s += tt - tg
             perm = rng.permutation(len(pairs))
             for i in range(0, len(perm), 4):
                 idx = perm[i:i + 4]
-                x = torch.stack([pairs[j][0] for j in idx]).contiguous()
-                y = torch.stack([pairs[j][1] for j in idx]).contiguous()
-                out = torch.empty_like(y)
-                g = torch.empty_like(y)
-                net.forward(x, out)
-                tot += net.mse(out, y, g)
-                nb += 1
                 net.zero_grad()
-                net.backward(g)
+                if args.c4_loss == "residual":
+                    tot += tr.residual_step(net, [pairs[j] for j in idx], out_scale)
+                else:
+                    x = torch.stack([pairs[j][1] for j in idx]).contiguous()
+                    y = torch.stack([pairs[j][2] for j in idx]).contiguous()
+                    out = torch.empty_like(y)
+                    g = torch.empty_like(y)
+                    net.forward(x, out)
+                    tot += net.mse(out, y, g)
+                    net.backward(g)
+                nb += 1
                 t += 1
                 # cosine decay of the learning rate over the whole run
                 frac = min(1.0, t / max(1, args.c4_epochs * args.c4_geometries * args.c4_pairs // 4))
@@ -660,6 +673,8 @@ def config4_run(args, m, torch):
             if ep == 0:
                 npairs += len(pairs)
             del pairs
+            for sv in solvers:
+                sv.close()
             print(f"config4: epoch {ep}, geometries {c0 + args.c4_chunk}/{args.c4_geometries}, "
                   f"running loss {tot / max(nb, 1):.4e}", file=sys.stderr, flush=True)
         losses.append(tot / max(nb, 1))
@@ -706,6 +721,7 @@ def config4_run(args, m, torch):
             "learned_over_plain_fp64": round(res["learned"]["steps_per_s"] / res["plain_fp64"]["steps_per_s"], 3),
             "extrapolated_over_plain": round(res["extrapolated"]["steps_per_s"] / res["plain"]["steps_per_s"], 3),
             "training": {"pairs_per_epoch": npairs, "epochs": args.c4_epochs, "batch": 4, "lr": args.c4_lr,
+                         "loss": args.c4_loss,
                          "streamed": f"pairs of {args.c4_chunk} geometries at a time, regenerated on the GPU "
                                      f"from their seeds every epoch",
                          "generation_s": round(gen_s, 1), "training_s": round(train_s, 1),

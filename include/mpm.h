@@ -359,6 +359,18 @@ int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scale, const fl
 int32_t mpm_ws_pair(mpm_ctx ctx, int32_t problem, const double* c_old, const double* c_new,
                     const float* in_scale, const float* out_scale, uint16_t* in_bf16, float* target);
 
+/* Training loss of the warm start by the residual its prediction leaves.  out: device
+ * FP32 [gz][gy][gx][S], the network's output for a pair of 'problem' (units of
+ * out_scale); target: that pair's target (mpm_ws_pair).  With e = (out - target) *
+ * out_scale on the domain voxels (the start's error) and w = S A e (S = diag(A)^(-1/2),
+ * A the problem's operator), *loss (host) = sum (w / out_scale)^2 / (S N) over the
+ * S species and N domain voxels, and grad_out (device FP32, shape of out) = dloss/dout
+ * = 2 A S w / (S N out_scale), zero off the domain.  out_scale: host FP32 [S], positive.
+ * Uses the context's solver workspace as scratch (the next step recomputes it);
+ * synchronises the stream.  MPM_ESTATE without MPM_WS_NET or before mpm_fv_setup. */
+int32_t mpm_ws_loss(mpm_ctx ctx, int32_t problem, const float* out, const float* target, const float* out_scale,
+                    float* grad_out, double* loss);
+
 /* Grid sizes (gx, gy, gz) of the warm-start network input of 'problem' (host int[3]). */
 int32_t mpm_ws_grid(mpm_ctx ctx, int32_t problem, int32_t* grid);
 

@@ -41,7 +41,8 @@ def bf16(x):
     f = np.asarray(x, dtype=np.float32)
     u = f.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    out = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    with np.errstate(invalid="ignore"):          # signalling NaN patterns widen quietly
+        out = u.astype(np.uint32).view(np.float32).astype(np.float64)
     return np.where(np.isnan(f), np.nan, out)
 
 

@@ -40,6 +40,8 @@ static void destroy_ctx(Ctx* c) {
     if (c->h_prm) (void)hipHostFree(c->h_prm);
     if (c->h_small) (void)hipHostFree(c->h_small);
     if (c->h_sk) (void)hipHostFree(c->h_sk);
+    if (c->h_lossp) (void)hipHostFree(c->h_lossp);
+    (void)hipFree(c->d_lossp);
     (void)hipFree(c->d_scales);
     (void)hipFree(c->prev);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
@@ -393,6 +395,33 @@ extern "C" int32_t mpm_ws_pair(mpm_ctx ctx, int32_t problem, const double* c_old
     rc = enter(c);
     if (rc != MPM_OK) return rc;
     rc = ws_pair(c, problem, c_old, c_new, in_bf16, target);
+    if (rc == MPM_OK) rc = leave(c);
+    return rc;
+}
+
+extern "C" int32_t mpm_ws_loss(mpm_ctx ctx, int32_t problem, const float* out, const float* target,
+                               const float* out_scale, float* grad_out, double* loss) {
+    Ctx* c = (Ctx*)ctx;
+    if (!c || !out || !target || !out_scale || !grad_out || !loss || problem < 0 || problem >= c->P) {
+        set_error("mpm_ws_loss: bad arguments");
+        return MPM_EINVAL;
+    }
+    if (c->opt.warm_start != MPM_WS_NET || !c->probs[problem].ready) {
+        set_error("mpm_ws_loss: needs a context with warm_start = MPM_WS_NET and a set-up problem");
+        return MPM_ESTATE;
+    }
+    for (int s = 0; s < c->S; ++s) {
+        if (!(out_scale[s] > 0.f) || !std::isfinite(out_scale[s])) {
+            set_error("mpm_ws_loss: output scales must be positive");
+            return MPM_EINVAL;
+        }
+    }
+    // the output scales go where the warm-start kernels read them; the input scales stay
+    for (int s = 0; s < c->S; ++s) c->h_scales[kScaleOut + s] = out_scale[s];
+    MPM_HIP(hipMemcpy(c->d_scales, c->h_scales, kScaleCount * sizeof(float), hipMemcpyHostToDevice));
+    int rc = enter(c);
+    if (rc != MPM_OK) return rc;
+    rc = ws_loss(c, problem, out, target, grad_out, loss);
     if (rc == MPM_OK) rc = leave(c);
     return rc;
 }

@@ -129,6 +129,9 @@ struct Ctx {
     float* d_scales = nullptr;         // [kScaleCount]: input channel scales, then output scales
     float h_scales[kScaleCount] = {0};
     bool have_scales = false;
+    double* d_lossp = nullptr;         // per-block partial sums of the warm-start loss
+    double* h_lossp = nullptr;         // their pinned host copy
+    size_t cap_lossp = 0;
     double* prev = nullptr;            // c^n of the previous step on the global unknowns
     size_t cap_prev = 0;
     size_t prev_n = 0;                 // elements in each half of prev
@@ -159,5 +162,6 @@ int debug_krylov(Ctx* c, int p, int sp, int kmax, int* mcount, double* vs, doubl
 int ensure_layout(Ctx* c);
 int select_timing(Ctx* c, int kind, int j, int repeat);
 int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* in_bf16, float* target);
+int ws_loss(Ctx* c, int p, const float* out, const float* target, float* grad, double* loss);
 
 }  // namespace mpm

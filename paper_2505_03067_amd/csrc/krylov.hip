@@ -1502,6 +1502,95 @@ __global__ void k_ws_target(ProbDev pd, int S, int bx, int by, int bz, const dou
     }
 }
 
+// ------------------------------------------------------------------ residual loss
+// Training loss of the warm start measured by the residual its prediction leaves: for a
+// predicted change o (network output, in units of out_scale) and the solved change t of
+// the same step, the start c^n + o out_scale leaves b - A (c^n + o out_scale) = -A e
+// with e = (o - t) out_scale, so the loss is the Jacobi-scaled residual
+//   L = sum_{s,l} (w_{s,l} / out_scale_s)^2 / (S N),  w = S A e  (S = diag(A)^(-1/2)),
+// and, A being symmetric, dL/do_{s,l} = 2 (A S w)_{s,l} / (S N out_scale_s).  All in
+// FP64 on the domain unknowns of one problem; the grid maps to them by grid_index.
+
+// 7-point product (A y)_P over a problem's compact unknowns, y read through 'val', with
+// the couplings of the block's system (FP64, unscaled; the -d coupling of P is the +d
+// coupling of its -d neighbour).
+template <typename F>
+__device__ inline double apply_a64(const Block& blk, int l, F val) {
+    const long long loc = blk.locbase + l;
+    const int4 nb = blk.nbr[l];
+    double r = blk.d64[loc] * val(l);
+    r += blk.a64[loc] * val(l + 1) + blk.a64[loc - 1] * val(l - 1);
+    r += blk.a64[blk.tot + loc] * val(nb.y) + blk.a64[blk.tot + blk.locbase + nb.x] * val(nb.x);
+    r += blk.a64[2 * blk.tot + loc] * val(nb.w) + blk.a64[2 * blk.tot + blk.locbase + nb.z] * val(nb.z);
+    return r;
+}
+
+// e = (out - target) out_scale on the domain unknowns of problem p (0 on padding).
+__global__ __launch_bounds__(kThreads) void k_wsl_err(const Block* blocks, const ProbDev* probs, int S, int p,
+                                                      const float* out, const float* tgt, const float* scales,
+                                                      double* e) {
+    const Block blk = blocks[blockIdx.x];
+    if (blk.sys < 0 || blk.p != p) return;
+    const ProbDev pd = probs[p];
+    const double os = scales[kScaleOut + blk.s];
+    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
+        const int l = (int)(u - blk.base);
+        double v = 0.0;
+        if (l < pd.N) {
+            const long long gi = grid_index(pd, l) * S + blk.s;
+            v = ((double)out[gi] - (double)tgt[gi]) * os;
+        }
+        e[u] = v;
+    }
+}
+
+// mode 0: w = S (A e) and per-block partial sums of (w / out_scale)^2 in part[block];
+// mode 1: g = A (S w).  x is read on the block's system, y written on it.
+__global__ __launch_bounds__(kThreads) void k_wsl_apply(const Block* blocks, int p, int mode, const float* scales,
+                                                        const double* x, double* y, double* part) {
+    const Block blk = blocks[blockIdx.x];
+    const bool mine = blk.sys >= 0 && blk.p == p;
+    double acc[1] = {0.0};
+    if (mine) {
+        const double* xs = x + blk.base;
+        const double* sc = blk.sc64 + blk.locbase;
+        const double os = scales[kScaleOut + blk.s];
+        for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
+            const int l = (int)(u - blk.base);
+            double r = 0.0;
+            if (l < blk.N) {
+                if (mode == 0) {
+                    r = sc[l] * apply_a64(blk, l, [&](int q) { return xs[q]; });
+                    acc[0] += (r / os) * (r / os);
+                } else {
+                    r = apply_a64(blk, l, [&](int q) { return sc[q] * xs[q]; });
+                }
+            }
+            y[u] = r;
+        }
+    }
+    if (mode == 0) block_partials<1>(acc, part, 1, blockIdx.x);
+}
+
+// grad[grid voxel of l][s] = coef_s g (domain voxels only; the caller zeroes the grid).
+__global__ __launch_bounds__(kThreads) void k_wsl_grad(const Block* blocks, const ProbDev* probs, int S, int p,
+                                                       const double* g, double coef, const float* scales,
+                                                       float* grad) {
+    const Block blk = blocks[blockIdx.x];
+    if (blk.sys < 0 || blk.p != p) return;
+    const ProbDev pd = probs[p];
+    const double cs = coef / (double)scales[kScaleOut + blk.s];
+    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
+        const int l = (int)(u - blk.base);
+        if (l < pd.N) grad[grid_index(pd, l) * S + blk.s] = (float)(cs * g[u]);
+    }
+}
+
+__global__ void k_fill0(float* p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
 // ------------------------------------------------------------------ dispatch tables
 template <typename T>
 using KFn = void (*)(KArgs<T>);
@@ -2553,6 +2642,39 @@ static int ws_first_residual(Ctx* c, int p, const double* c_old) {
     k_gather<T><<<(unsigned)(end - first), kThreads, 0, st>>>(a);
     k_residual<T><<<(unsigned)(end - first), kThreads, 0, st>>>(a, kResFirst);
     MPM_HIP(hipGetLastError());
+    return MPM_OK;
+}
+
+int ws_loss(Ctx* c, int p, const float* out, const float* target, float* grad, double* loss) {
+    int rc = ensure_layout(c);
+    if (rc != MPM_OK) return rc;
+    hipStream_t st = c->stream;
+    const ProbHost& ph = c->probs[p];
+    const long long G = (long long)ph.gd[0] * ph.gd[1] * ph.gd[2];
+    const unsigned nb = (unsigned)c->blocks.size();
+    if (nb > c->cap_lossp) {
+        (void)hipFree(c->d_lossp);
+        if (c->h_lossp) (void)hipHostFree(c->h_lossp);
+        c->d_lossp = nullptr;
+        c->h_lossp = nullptr;
+        c->cap_lossp = 0;
+        MPM_HIP(hipMalloc(&c->d_lossp, nb * sizeof(double)));
+        MPM_HIP(hipHostMalloc((void**)&c->h_lossp, nb * sizeof(double), hipHostMallocDefault));
+        c->cap_lossp = nb;
+    }
+    // x and b are scratch between steps (the next step gathers them again)
+    k_wsl_err<<<nb, kThreads, 0, st>>>(c->d_blocks, c->d_probs, c->S, p, out, target, c->d_scales, c->x);
+    k_wsl_apply<<<nb, kThreads, 0, st>>>(c->d_blocks, p, 0, c->d_scales, c->x, c->b, c->d_lossp);
+    k_wsl_apply<<<nb, kThreads, 0, st>>>(c->d_blocks, p, 1, c->d_scales, c->b, c->x, nullptr);
+    k_fill0<<<(unsigned)((G * c->S + 255) / 256), 256, 0, st>>>(grad, G * c->S);
+    const double count = (double)c->S * ph.N;
+    k_wsl_grad<<<nb, kThreads, 0, st>>>(c->d_blocks, c->d_probs, c->S, p, c->x, 2.0 / count, c->d_scales, grad);
+    MPM_HIP(hipGetLastError());
+    MPM_HIP(hipMemcpyAsync(c->h_lossp, c->d_lossp, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipStreamSynchronize(st));
+    double sum = 0.0;
+    for (unsigned i = 0; i < nb; ++i) sum += c->h_lossp[i];
+    *loss = sum / count;
     return MPM_OK;
 }
 

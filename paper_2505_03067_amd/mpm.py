@@ -119,6 +119,8 @@ def lib() -> ctypes.CDLL:
             "mpm_ws_pair": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_float), _vp, _vp],
             "mpm_ws_grid": [_vp, ctypes.c_int32, _i32p],
+            "mpm_ws_loss": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_float), _vp,
+                            ctypes.POINTER(ctypes.c_double)],
             "mpm_hbm_probe": [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                               _vp, ctypes.POINTER(ctypes.c_double)],
             "mpm_kernel_timing": [_vp, ctypes.POINTER(ctypes.c_double),
@@ -482,6 +484,16 @@ def mpm_net_debug_op(net, op: int, shape, c: int, c2: int, a, b, out, out2=None)
                                   ptr(out2)))
 
 
+def mpm_ws_loss(ctx, problem, out, target, out_scale, grad_out) -> float:
+    import torch
+    loss = ctypes.c_double()
+    sc = (ctypes.c_float * max(len(out_scale), MPM_MAX_SPECIES))(*[float(v) for v in out_scale])
+    _check(lib().mpm_ws_loss(ctx, int(problem), _dev_ptr(out, torch.float32, "out"),
+                             _dev_ptr(target, torch.float32, "target"), sc,
+                             _dev_ptr(grad_out, torch.float32, "grad_out"), ctypes.byref(loss)))
+    return loss.value
+
+
 class Net:
     """Owns one U-Net handle (convenience wrapper over the mpm_net_* functions)."""
 
@@ -609,6 +621,14 @@ class Solver:
             if f.dim() != 4 or f.shape[0] != S:
                 raise ValueError(f"{name} must be [S][z][y][x]")
         mpm_ws_pair(self.ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target, self.nspecies)
+
+    def ws_loss(self, problem, out, target, out_scale, grad_out):
+        """Residual loss of a warm-start prediction and its gradient (see mpm_ws_loss)."""
+        gx, gy, gz = self.ws_grid(problem)
+        n = gx * gy * gz * self.nspecies
+        if out.numel() != n or target.numel() != n or grad_out.numel() != n or len(out_scale) != self.nspecies:
+            raise ValueError(f"out, target and grad_out must hold {n} values, out_scale {self.nspecies}")
+        return mpm_ws_loss(self.ctx, problem, out, target, out_scale, grad_out)
 
     def apply(self, problem, x, y, mode):
         return mpm_debug_apply(self.ctx, problem, x, y, mode)

@@ -256,3 +256,59 @@ def test_learned_warm_start_gains_over_plain():
     print(f"learned start accepted for {used} of 12 systems at tol 1e-12", flush=True)
     assert used >= 6
     _check_oracle(p, 4, f.cpu().numpy(), tol=1e-12)
+
+
+def test_ws_loss_matches_definition():
+    """The residual loss of a prediction and its gradient against the oracle's
+    assembly: e = (out - target) out_scale on the domain voxels, w = S A e,
+    loss = sum (w / out_scale)^2 / (S N), grad = 2 A S w / (S N out_scale), zero off the
+    domain; a ragged masked box whose grid is padded past it."""
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    from paper_2505_03067_amd.train import input_scales
+    p = random_problem(93, (26, 22, 18), S=3, fill=0.7)
+    box = ((1, 2, 1), (24, 21, 17))
+    S = 3
+    out_scale = [0.3, 0.2, 4e-3]
+    d = to_dev(p)
+    f = torch.from_numpy(p.c0).cuda()
+    with m.Solver(S, 1, warm_start=m.MPM_WS_NET) as s:
+        s.setup(0, box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+        s.step([f], 1e-10)
+        old = f.clone()
+        s.step([f], 1e-10)
+        gx, gy, gz = s.ws_grid(0)
+        inp = torch.empty((gz, gy, gx, 5 * S + 1), dtype=torch.int16, device="cuda")
+        tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
+        s.ws_pair(0, old, f, input_scales(S, out_scale), out_scale, inp, tgt)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(5)
+        out = tgt + 0.1 * torch.randn(tgt.shape, generator=gen, device="cuda")
+        grad = torch.empty_like(out)
+        loss = s.ws_loss(0, out, tgt, out_scale, grad)
+    sl = box_slice(box)
+    mb = p.mask[sl].astype(bool)
+    ex, ey, ez = [hi - lo for lo, hi in zip(*box)]
+    o = out.cpu().numpy().astype(np.float64)[:ez, :ey, :ex]
+    t = tgt.cpu().numpy().astype(np.float64)[:ez, :ey, :ex]
+    g = grad.cpu().numpy().astype(np.float64)
+    N = int(mb.sum())
+    want_loss = 0.0
+    want_grad = np.zeros((gz, gy, gx, S))
+    for sp in range(S):
+        A, _ = assemble(mb, p.D[sp][sl], p.k[sp][sl], p.src[sp][sl], float(p.c_b[sp]), p.dt, p.h)
+        os_ = float(np.float32(out_scale[sp]))
+        e = (o[..., sp][mb] - t[..., sp][mb]) * os_
+        sc = 1.0 / np.sqrt(A.diagonal())
+        w = sc * (A @ e)
+        want_loss += float(((w / os_) ** 2).sum())
+        gv = 2.0 / (S * N * os_) * (A @ (sc * w))
+        want_grad[:ez, :ey, :ex, sp][mb] = gv
+    want_loss /= S * N
+    print(f"loss {loss:.6e} oracle {want_loss:.6e}", flush=True)
+    assert abs(loss - want_loss) <= 1e-12 * want_loss
+    dom = np.zeros((gz, gy, gx), bool)
+    dom[:ez, :ey, :ex] = mb
+    assert np.all(g[~dom] == 0.0)
+    err = np.abs(g - want_grad)
+    assert np.all(err <= 2.0 ** -23 * np.abs(want_grad) + 1e-12 * np.abs(want_grad).max())
