@@ -18,6 +18,7 @@ namespace mpm {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 // round to nearest, ties to even; overflow rounds to infinity, and every NaN becomes
@@ -78,6 +79,13 @@ __device__ inline uint4 apply_gate(uint4 t, const uint4 g) {
 // taps are unrolled at compile time, so every LDS read is a per-lane base plus an
 // immediate.  (Chunks of 32 channels, one tap per step, need 27 steps instead of 28 but
 // 78 KB of LDS per block, two blocks per CU instead of three, and measured slower.)
+// The MFMAs take the weight fragment as their A operand and the input fragment as B,
+// which yields the transposed tile: lane l then holds output channels 4 (l / 16) .. + 3
+// of voxel l mod 16, stored straight to global memory as one 8-byte word (16 lanes
+// cover 16 consecutive voxels of a row).  The item's tile comes from a mixed-radix
+// cursor and every address is a uniform base plus a 32-bit per-lane offset, so the
+// per-item integer work is a few instructions (64-bit divisions and per-word address
+// arithmetic had cost more issue cycles than the MFMAs).
 //
 // Packed weights (k_pack): one 16-byte B fragment per (step, output tile, lane), steps
 // numbered over the chunks in order; the fragment of lane (n = lane mod 16, g) holds the
@@ -119,29 +127,62 @@ static_assert(step_taps_cover(), "every tap (and the zero tap 27) in exactly one
 // strides of 48, 64 and 80 bytes measured no faster), then one chunk's weights
 __host__ __device__ constexpr int conv_x_bytes() { return kHV * kCS * 2; }
 // the block's weights (one chunk's) staged in LDS after the halo tile, except with one
-// chunk and one output tile (then they live in registers); then each wave's epilogue
-// scratch, where the output tiles are transposed to voxel-major rows of 16 channels
-constexpr int kEpRow = 48;   // LDS bytes per voxel row of the epilogue (16 BF16 + 8 of padding)
+// chunk and one output tile (then they live in registers); then the block's bias values
 __host__ __device__ constexpr int conv_w_bytes(int ntb, bool wl) { return wl || ntb > 1 ? kSteps * ntb * 1024 : 0; }
-__host__ __device__ constexpr int conv_ep_bytes(int ntb) { return 4 * (4 * ntb * 16 * kEpRow); }
 __host__ __device__ constexpr int conv_lds_bytes(int ntb, bool wl) {
-    return conv_x_bytes() + conv_w_bytes(ntb, wl) + conv_ep_bytes(ntb);
+    return conv_x_bytes() + conv_w_bytes(ntb, wl) + 64 * ntb;   // + the block's bias values
 }
 
-// Origin of a voxel tile (tile index: x fastest, then y, z, sample).
+// Origin of a voxel tile (tile index: x fastest, then y, z, sample), and whether its
+// halo (in) and the tile itself (out) lie inside the grid.
 struct ConvTile {
     int x0, y0, z0;
     long long sbase;
+    bool in, out;
 };
-__device__ inline ConvTile conv_tile(const ConvArgs& a, long long tile) {
+// Tile index as mixed-radix digits (x, y, z tile, sample), advanced by a fixed stride
+// (the grid's tiles per round) without divisions.
+struct ConvCursor {
+    int tx, ty, tz, n;
+    int sx, sy, sz, sn;
+};
+__device__ inline void conv_digits(const ConvArgs& a, unsigned t, int& x, int& y, int& z, int& n) {
+    const unsigned ntx = (a.W + kTX - 1) / kTX, nty = (a.H + kTY - 1) / kTY, ntz = (a.D + kTZ - 1) / kTZ;
+    x = (int)(t % ntx);
+    t /= ntx;
+    y = (int)(t % nty);
+    t /= nty;
+    z = (int)(t % ntz);
+    n = (int)(t / ntz);
+}
+__device__ inline ConvCursor conv_cursor(const ConvArgs& a, unsigned tile, unsigned stride) {
+    ConvCursor c;
+    conv_digits(a, tile, c.tx, c.ty, c.tz, c.n);
+    conv_digits(a, stride, c.sx, c.sy, c.sz, c.sn);
+    return c;
+}
+__device__ inline void conv_advance(const ConvArgs& a, ConvCursor& c) {
     const int ntx = (a.W + kTX - 1) / kTX, nty = (a.H + kTY - 1) / kTY, ntz = (a.D + kTZ - 1) / kTZ;
+    c.tx += c.sx;
+    int k = c.tx >= ntx;
+    c.tx -= k ? ntx : 0;
+    c.ty += c.sy + k;
+    k = c.ty >= nty;
+    c.ty -= k ? nty : 0;
+    c.tz += c.sz + k;
+    k = c.tz >= ntz;
+    c.tz -= k ? ntz : 0;
+    c.n += c.sn + k;
+}
+__device__ inline ConvTile conv_tile(const ConvArgs& a, const ConvCursor& c) {
     ConvTile t;
-    t.x0 = (int)(tile % ntx) * kTX;
-    tile /= ntx;
-    t.y0 = (int)(tile % nty) * kTY;
-    tile /= nty;
-    t.z0 = (int)(tile % ntz) * kTZ;
-    t.sbase = (tile / ntz) * a.D * a.H * a.W;
+    t.x0 = c.tx * kTX;
+    t.y0 = c.ty * kTY;
+    t.z0 = c.tz * kTZ;
+    t.sbase = (long long)c.n * a.D * a.H * a.W;
+    t.in = t.x0 >= 1 && t.x0 + kTX + 1 <= a.W && t.y0 >= 1 && t.y0 + kTY + 1 <= a.H && t.z0 >= 1 &&
+           t.z0 + kTZ + 1 <= a.D;
+    t.out = t.x0 + kTX <= a.W && t.y0 + kTY <= a.H && t.z0 + kTZ <= a.D;
     return t;
 }
 
@@ -184,28 +225,78 @@ __device__ inline void conv_store_w(char* xs, const uint4* w) {
     }
 }
 
-// Global loads of channels [cb, cb + 16) of tile t (and of the chunk's weights when WL).
-template <int NTB, bool WL, bool GATED>
-__device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, int tb, ConvRegs<NTB, WL, GATED>& r) {
+// The thread's halo words: word e = threadIdx.x + 256 i holds channels 8 (e mod 2) .. + 7
+// of halo voxel e / 2, packed as hx | hy << 5 | hz << 8 | (e mod 2) << 11 (offsets from
+// the halo origin (x0 - 1, y0 - 1, z0 - 1)); -1 past the halo.
+__device__ inline int conv_halo_word(int i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e >= 2 * kHV) return -1;
+    const int v = e >> 1;
+    return v % kHX | ((v / kHX) % kHY) << 5 | (v / (kHX * kHY)) << 8 | (e & 1) << 11;
+}
+
+// Byte offsets of the thread's halo words from the halo origin on a full-resolution
+// source with channel stride ld (~0 past the halo); fixed for a launch.
+struct ConvLane {
+    unsigned off[kXM];
+};
+__device__ inline ConvLane conv_lane(const ConvArgs& a, int ld) {
+    ConvLane l;
 #pragma unroll
     for (int i = 0; i < kXM; ++i) {
-        const int e = threadIdx.x + 256 * i;
+        const int p = conv_halo_word(i);
+        const unsigned hx = p & 31, hy = (p >> 5) & 7, hz = (p >> 8) & 7, gi = p >> 11;
+        l.off[i] = p < 0 ? ~0u : 2u * (((hz * a.H + hy) * a.W + hx) * ld + 8 * gi);
+    }
+    return l;
+}
+
+// Global loads of channels [cb, cb + 16) of tile t (and of the chunk's weights when WL).
+// Addresses are a per-item base (the halo origin, uniform) plus the lane's 32-bit offset;
+// only tiles whose halo crosses the grid's boundary test each word.  XCAT: the kernel
+// may read an upsampled half-resolution input and a concatenated skip (a.x2).
+template <int NTB, bool WL, bool GATED>
+__device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, int tb, const ConvLane& ln,
+                                  ConvRegs<NTB, WL, GATED>& r) {
+    constexpr bool XCAT = WL && !GATED;
+    const bool up = XCAT && a.x2 && cb < a.c1;       // upsampled half-resolution input
+    const bool cat = XCAT && a.x2 && cb >= a.c1;     // concatenated skip input
+    const int ld = cat ? a.ldx2 : a.ldx;
+    const int Hh = a.H >> 1, Wh = a.W >> 1;
+    long long org;
+    if (up)   // half-resolution voxel of the halo origin (x0, y0, z0 are even)
+        org = t.sbase / 8 + ((long long)((t.z0 >> 1) - 1) * Hh + ((t.y0 >> 1) - 1)) * Wh + ((t.x0 >> 1) - 1);
+    else
+        org = t.sbase + ((long long)(t.z0 - 1) * a.H + (t.y0 - 1)) * a.W + (t.x0 - 1);
+    // byte address of the origin's first channel (integer arithmetic: it may lie before
+    // the buffer when the halo crosses the grid's low faces; such words are not loaded)
+    const uintptr_t base = (cat ? (uintptr_t)a.x2 + 2 * (uintptr_t)(cb - a.c1) : (uintptr_t)a.x + 2 * (uintptr_t)cb) +
+                           (uintptr_t)(org * ld * 2);
+    const uintptr_t gbase = GATED ? (uintptr_t)a.gate + 2 * (uintptr_t)cb + (uintptr_t)(org * a.ldx * 2) : 0;
+#pragma unroll
+    for (int i = 0; i < kXM; ++i) {
         r.x[i] = make_uint4(0, 0, 0, 0);
         if (GATED) r.g[i] = make_uint4(0, 0, 0, 0);
-        if (e < 2 * kHV) {
-            const int v = e >> 1, gi = e & 1;
-            const int x = t.x0 - 1 + v % kHX, y = t.y0 - 1 + (v / kHX) % kHY, z = t.z0 - 1 + v / (kHX * kHY);
-            if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
-                const long long q = t.sbase + ((long long)z * a.H + y) * a.W + x;
-                if (!GATED && a.x2 && cb < a.c1) {   // upsampled half-resolution input
-                    const long long qc = t.sbase / 8 + ((long long)(z >> 1) * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1);
-                    r.x[i] = *reinterpret_cast<const uint4*>(a.x + qc * a.ldx + cb + 8 * gi);
-                } else if (!GATED && a.x2) {          // concatenated skip input
-                    r.x[i] = *reinterpret_cast<const uint4*>(a.x2 + q * a.ldx2 + cb - a.c1 + 8 * gi);
-                } else {
-                    r.x[i] = *reinterpret_cast<const uint4*>(a.x + q * a.ldx + cb + 8 * gi);
-                }
-                if (GATED) r.g[i] = *reinterpret_cast<const uint4*>(a.gate + q * a.ldx + cb + 8 * gi);
+    }
+    if (t.in && !up) {   // every word inside the grid: one base and the lane's offsets
+#pragma unroll
+        for (int i = 0; i < kXM; ++i) {
+            if (ln.off[i] == ~0u) continue;
+            r.x[i] = *reinterpret_cast<const uint4*>(base + ln.off[i]);
+            if (GATED) r.g[i] = *reinterpret_cast<const uint4*>(gbase + ln.off[i]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kXM; ++i) {
+            const int p = conv_halo_word(i);
+            if (p < 0) continue;
+            const int hx = p & 31, hy = (p >> 5) & 7, hz = (p >> 8) & 7, gi = p >> 11;
+            if ((unsigned)(t.x0 - 1 + hx) < (unsigned)a.W && (unsigned)(t.y0 - 1 + hy) < (unsigned)a.H &&
+                (unsigned)(t.z0 - 1 + hz) < (unsigned)a.D) {
+                const unsigned o = up ? 2u * ((((unsigned)((hz + 1) >> 1) * Hh + ((hy + 1) >> 1)) * Wh + ((hx + 1) >> 1)) * ld + 8 * gi)
+                                      : ln.off[i];
+                r.x[i] = *reinterpret_cast<const uint4*>(base + o);
+                if (GATED) r.g[i] = *reinterpret_cast<const uint4*>(gbase + o);
             }
         }
     }
@@ -261,7 +352,7 @@ __device__ inline void conv_chunk(const char* xs, uint32_t lb, const uint4 (&bre
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < NTB; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt + dy], b[nt], acc[mt][nt], 0, 0, 0);
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[nt], a[mt + dy], acc[mt][nt], 0, 0, 0);
         }
     }
     // steps 9-13: taps dx = 2, paired across rows, across planes, and with zero weights
@@ -278,7 +369,7 @@ __device__ inline void conv_chunk(const char* xs, uint32_t lb, const uint4 (&bre
             const bf16x8 af = afrag(ad);
 #pragma unroll
             for (int nt = 0; nt < NTB; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, b[nt], acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[nt], af, acc[mt][nt], 0, 0, 0);
         }
     }
 }
@@ -287,28 +378,31 @@ __device__ inline void conv_chunk(const char* xs, uint32_t lb, const uint4 (&bre
 // is multiplied by (gate > 0) (ReLU backward).  The grid size must be a multiple of
 // NT / NTB: a block keeps one output-tile group (its bias is read once, and without WL
 // its weights are staged once), and its epilogue issues no loads, so the wait for the
-// next item's prefetched input does not also wait for the stores of this one.
+// next item's prefetched input does not also wait for the stores of this one.  Three
+// blocks per CU for the chunk-staged weights (WL); two for the others, whose registers
+// (the weights held in registers, or the ReLU gates) would not fit three.
 template <int NTB, bool WL, bool GATED>
-__global__ __launch_bounds__(256, (NTB == 1 && !GATED) ? 3 : 2) void k_conv(ConvArgs a) {
+__global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_conv(ConvArgs a) {
     extern __shared__ uint4 xs_dyn[];
     char* xs = reinterpret_cast<char*>(xs_dyn);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nsplit = a.nt / NTB;
-    const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
-    const long long nitems = tiles * nsplit;
     const int nchunk = WL ? a.cin_p / 16 : 1;
     const int tb = (int)(blockIdx.x % nsplit) * NTB;   // the block's first output tile
-    long long item = blockIdx.x;
-    if (item >= nitems) return;
-    float bias[NTB];
-#pragma unroll
-    for (int nt = 0; nt < NTB; ++nt) {
-        const int co = (tb + nt) * 16 + (lane & 15);
-        bias[nt] = a.bias && co < a.cout ? a.bias[co] : 0.f;
+    // the block's tiles: blockIdx.x / nsplit, then every gridDim.x / nsplit-th
+    ConvCursor cur = conv_cursor(a, blockIdx.x / nsplit, gridDim.x / nsplit);
+    if (cur.n >= a.n) return;
+    // the MFMAs take the weights as their A operand, so the accumulator of M tile mt holds
+    // output channels 4 (lane / 16) .. + 3 of voxel lane % 16: the lane's bias values
+    // the block's bias values sit in LDS after the halo tile and the weights
+    float* bias_l = reinterpret_cast<float*>(xs + conv_x_bytes() + conv_w_bytes(NTB, WL));
+    if (threadIdx.x < 16 * NTB) {
+        const int co = tb * 16 + threadIdx.x;
+        bias_l[threadIdx.x] = a.bias && co < a.cout ? a.bias[co] : 0.f;
     }
-    // BF16 output in whole 16-byte halves of voxel rows: through the LDS epilogue
-    const bool vec = a.y && !a.yf && a.ldy % 8 == 0 && a.yoff % 8 == 0 && ((uintptr_t)a.y & 15) == 0;
+    // BF16 output as one 8-byte word of four channels per lane and M tile
+    const bool vec = a.y && a.ldy % 4 == 0 && a.yoff % 4 == 0 && ((uintptr_t)a.y & 7) == 0;
     // the lane's voxel x = lane % 16 in halo row 0 of plane 'wave' (M tile mt adds mt rows)
     const uint32_t lb = (uint32_t)(((wave * kHY) * kHX + (lane & 15)) * kCS * 2 + 16 * ((lane >> 4) & 1));
     f32x4 acc[4][NTB];
@@ -333,88 +427,70 @@ __global__ __launch_bounds__(256, (NTB == 1 && !GATED) ? 3 : 2) void k_conv(Conv
         conv_fetch_w<NTB>(a, 0, tb, w);
         conv_store_w<NTB>(xs, w);
     }
+    // halo word offsets of the full-resolution source (the skip input when a.x2 is set)
+    const ConvLane ln = conv_lane(a, (WL && !GATED && a.x2) ? a.ldx2 : a.ldx);
     ConvRegs<NTB, WL, GATED> regs;
-    // chunk c covers channels [16 c, 16 c + 16); item i holds voxel tile i / nsplit
+    // chunk c covers channels [16 c, 16 c + 16)
     int chunk = 0;
-    conv_fetch<NTB, WL, GATED>(a, conv_tile(a, item / nsplit), 0, tb, regs);
+    ConvTile t = conv_tile(a, cur);
+    conv_fetch<NTB, WL, GATED>(a, t, 0, tb, ln, regs);
     for (;;) {
         __syncthreads();   // every wave is done with the previous chunk's LDS
         conv_store<NTB, WL, GATED>(xs, regs);
         __syncthreads();
-        long long nitem = item;
+        ConvCursor nxt = cur;
         int nc = chunk + 1;
         if (nc == nchunk) {
             nc = 0;
-            nitem += gridDim.x;
+            conv_advance(a, nxt);
         }
-        const bool more = nitem < nitems;
-        if (more) conv_fetch<NTB, WL, GATED>(a, conv_tile(a, nitem / nsplit), 16 * nc, tb, regs);   // in flight during the MFMAs
+        const bool more = nxt.n < a.n;
+        const ConvTile tn = nc == 0 ? conv_tile(a, nxt) : t;
+        if (more) conv_fetch<NTB, WL, GATED>(a, tn, 16 * nc, tb, ln, regs);   // in flight during the MFMAs
         conv_chunk<NTB, BREG>(xs, lb, breg, acc);
-        if (chunk == nchunk - 1 && vec) {
-            // D layout: lane holds rows 4 * (lane / 16) + i (voxels x0 + row), column lane % 16.
-            // The wave writes its tiles to its LDS scratch as BF16, reads them back as 16-byte
-            // halves of voxel rows (8 channels) and stores those: two global stores per lane
-            // and tile pair instead of sixteen 2-byte stores
-            const ConvTile t = conv_tile(a, item / nsplit);
-            char* ep = xs + conv_x_bytes() + conv_w_bytes(NTB, WL) + wave * (4 * NTB * 16 * kEpRow);
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < NTB; ++nt) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        float v = acc[mt][nt][i] + bias[nt];
-                        if (a.relu) v = fmaxf(v, 0.f);
-                        *reinterpret_cast<uint16_t*>(ep + ((mt * NTB + nt) * 16 + 4 * (lane >> 4) + i) * kEpRow +
-                                                     2 * (lane & 15)) = f2bf(v);
-                    }
-                    acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-                }
-            // LDS operations of one wave complete in order; keep the compiler from moving
-            // the reads above the writes of other lanes
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int j = 0; j < 2 * NTB; ++j) {
-                const int R = 32 * j + (lane >> 1);      // row of the wave's 4 NTB tiles x 16 voxels
-                const int T = R >> 4, m = R & 15;
-                const int mt = T / NTB, nt = T % NTB;
-                const uint4 val = *reinterpret_cast<const uint4*>(ep + R * kEpRow + 16 * (lane & 1));
-                const int x = t.x0 + m, y = t.y0 + mt, z = t.z0 + wave;
-                const int co0 = (tb + nt) * 16 + 8 * (lane & 1);
-                if (x < a.W && y < a.H && z < a.D && co0 + 8 <= a.cout) {
-                    const long long p = t.sbase + ((long long)z * a.H + y) * a.W + x;
-                    *reinterpret_cast<uint4*>(a.y + p * a.ldy + a.yoff + co0) = val;
-                }
-            }
-        } else if (chunk == nchunk - 1) {
-            // D layout: lane holds rows 4 * (lane / 16) + i (voxels x0 + row), column lane % 16
-            const ConvTile t = conv_tile(a, item / nsplit);
+        if (chunk == nchunk - 1) {
+            // voxel x0 + lane % 16 of row (y0 + mt, z0 + wave); the tile's origin is uniform
+            const int m = lane & 15;
+            const long long ob = t.sbase + ((long long)t.z0 * a.H + t.y0) * a.W + t.x0;
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const int r = 4 * wave + mt;
-                const int y = t.y0 + r % kTY, z = t.z0 + r / kTY;
+                const bool inb = t.out || (t.x0 + m < a.W && t.y0 + mt < a.H && t.z0 + wave < a.D);
+                const unsigned pv = ((unsigned)wave * a.H + mt) * a.W + m;   // voxel offset from the origin
 #pragma unroll
                 for (int nt = 0; nt < NTB; ++nt) {
-                    const int co = (tb + nt) * 16 + (lane & 15);
+                    const int co = (tb + nt) * 16 + 4 * (lane >> 4);
+                    const float4 bq = *reinterpret_cast<const float4*>(bias_l + nt * 16 + 4 * (lane >> 4));
+                    const float bv[4] = {bq.x, bq.y, bq.z, bq.w};
+                    float v[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int x = t.x0 + 4 * (lane >> 4) + i;
-                        if (y < a.H && z < a.D && co < a.cout && x < a.W) {
-                            const long long p = t.sbase + ((long long)z * a.H + y) * a.W + x;
-                            float v = acc[mt][nt][i] + bias[nt];
-                            if (a.relu) v = fmaxf(v, 0.f);
-                            if (a.y) a.y[p * a.ldy + a.yoff + co] = f2bf(v);
-                            if (a.yf) a.yf[p * a.cout + co] = v;
-                        }
+                        v[i] = acc[mt][nt][i] + bv[i];
+                        if (a.relu) v[i] = fmaxf(v[i], 0.f);
                     }
                     acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    if (!inb) continue;
+                    if (vec && co + 4 <= a.cout) {
+                        const bf16x2 lo = {(__bf16)v[0], (__bf16)v[1]}, hi = {(__bf16)v[2], (__bf16)v[3]};
+                        uint16_t* yp = a.y + ob * a.ldy + a.yoff;
+                        *reinterpret_cast<uint2*>(yp + pv * a.ldy + co) =
+                            make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+                    } else if (a.y) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (co + i < a.cout)
+                                a.y[(ob + pv) * a.ldy + a.yoff + co + i] = __builtin_bit_cast(uint16_t, (__bf16)v[i]);
+                    }
+                    if (a.yf) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (co + i < a.cout) a.yf[(ob + pv) * a.cout + co + i] = v[i];
+                    }
                 }
             }
         }
         if (!more) break;
-        item = nitem;
+        t = tn;
+        cur = nxt;
         chunk = nc;
     }
 }
