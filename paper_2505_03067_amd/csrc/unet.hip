@@ -176,10 +176,12 @@ static int ensure_acts(Net* n, int nb, int D, int H, int W) {
 // Launch k_conv<NTB, WL, GATED> over all (voxel tile, output-tile group) items: one
 // persistent block per LDS slot of the device (capped at the item count, rounded down to
 // a multiple of the group count).
+// Resident blocks of k_conv<NTB, WL, GATED> on the device (registers and LDS
+// permitting), found once; the first call also grants the kernel its LDS.
 template <int NTB, bool WL, bool GATED>
-static int launch_conv(const ConvArgs& a, hipStream_t st) {
+static hipError_t conv_slots(int* out) {
     constexpr int lds = conv_lds_bytes(NTB, WL);
-    static int slots = 0;   // resident blocks of the device (registers and LDS permitting)
+    static int slots = 0;
     static const hipError_t granted = [] {
         int dev = 0, cap = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
@@ -194,6 +196,15 @@ static int launch_conv(const ConvArgs& a, hipStream_t st) {
         slots = std::max(1, cus) * std::max(1, per_cu);
         return e;
     }();
+    *out = slots;
+    return granted;
+}
+
+template <int NTB, bool WL, bool GATED>
+static int launch_conv(const ConvArgs& a, hipStream_t st) {
+    constexpr int lds = conv_lds_bytes(NTB, WL);
+    int slots = 0;
+    const hipError_t granted = conv_slots<NTB, WL, GATED>(&slots);
     if (granted != hipSuccess) return hip_fail(granted, "U-Net convolution LDS");
     const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
     const int nsplit = a.nt / NTB;
@@ -205,9 +216,10 @@ static int launch_conv(const ConvArgs& a, hipStream_t st) {
 }
 
 // Output tiles per block: two for a 16-channel input with an even tile count (each A
-// fragment read from LDS then feeds two MFMAs, and the block's 58 KB of LDS still lets
-// two blocks share a CU), else one (44 KB, three blocks per CU; measured faster for the
-// wider inputs, whose weights are staged again for every chunk).
+// fragment read from LDS then feeds two MFMAs); for wider inputs two when the grid has
+// tiles for at least two rounds of the resident blocks (64^3 layers with 32 outputs:
+// 29.3 -> 26.4 us), else one (three blocks per CU instead of two, which the smaller
+// grids need to fill the device).
 static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
     if (nt < 1 || nt > 8 || a.cin_p % 16 || a.cin_p < 16 || (a.x2 && (a.gate || a.c1 % 16))) {
         set_error("unsupported channel count in the U-Net");
@@ -220,6 +232,13 @@ static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
         return launch_conv<1, true, true>(a, st);
     }
     if (one) return nt % 2 ? launch_conv<1, false, false>(a, st) : launch_conv<2, false, false>(a, st);
+    if (nt % 2 == 0) {
+        int slots = 0;
+        const hipError_t e = conv_slots<2, true, false>(&slots);
+        if (e != hipSuccess) return hip_fail(e, "U-Net convolution LDS");
+        const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
+        if (tiles * (nt / 2) >= 2LL * slots) return launch_conv<2, true, false>(a, st);
+    }
     return launch_conv<1, true, false>(a, st);
 }
 

@@ -298,13 +298,15 @@ def test_layerwise_chain_matches_oracle(widths, shape):
                                              ([16, 32, 64, 64], 4, (1, 6, 7, 20)),
                                              ([16, 32, 64, 64], 8, (1, 8, 8, 16)),
                                              ([16, 32, 64, 64], 10, (2, 4, 5, 17)),
-                                             ([16, 32], 1, (1, 64, 64, 64)), ([16, 32], 3, (1, 32, 64, 64))])
+                                             ([16, 32], 1, (1, 64, 64, 64)), ([16, 32], 3, (1, 32, 64, 64)),
+                                             ([16, 32], 3, (1, 64, 64, 64))])
 def test_single_layer_kernels_exact(widths, li, shape):
     """Forward, input-gradient and weight-gradient kernels of one layer on small-integer
     data, for which FP32 accumulation is exact: the GPU must equal the FP64 oracle
-    bit for bit (catches any index, tap or layout error).  The two largest grids give
-    the persistent convolution blocks several work items each, and the weight-gradient
-    blocks several voxel tiles each."""
+    bit for bit (catches any index, tap or layout error).  The largest grids give the
+    persistent convolution blocks several work items each, and the weight-gradient
+    blocks several voxel tiles each; the 32-channel layer on 64^3 runs the variant with
+    two output tiles per block."""
     torch = require_gpu()
     from paper_2505_03067_amd import Net
     net = Net(13, 3, widths, seed=3)
@@ -339,6 +341,56 @@ def test_single_layer_kernels_exact(widths, li, shape):
     assert np.array_equal(out0.cpu().numpy().astype(np.float64), want0)
     assert np.array_equal(out1.cpu().numpy().astype(np.float64), want1)
     assert np.array_equal(out2.cpu().numpy().astype(np.float64), want2)
+
+
+def test_full_grid_forward_sampled():
+    """The 16-32-64-64 network's forward pass on a 128^3 grid (the warm start's box grid),
+    where the launches take their production shapes: the 64^3 layers with 32 outputs run
+    two output tiles per block, and the decoder's first layer there reads the upsampled
+    deeper output and the skip directly.  Those layers are recomputed by the oracle at
+    sampled voxels (the grid's corners and some face voxels among them) from the GPU's
+    own stored BF16 inputs and held to the layerwise bar: relative L2 error 1e-3."""
+    torch = require_gpu()
+    import paper_2505_03067_amd.mpm as b
+    from paper_2505_03067_amd import Net
+    widths, in_ch, out_ch, S = [16, 32, 64, 64], 16, 3, 128
+    rng = np.random.default_rng(21)
+    net = Net(in_ch, out_ch, widths, seed=21)
+    theta = np.empty(net.count, np.float32)
+    for W, bias in unet.unpack(theta, in_ch, out_ch, widths):
+        W[:] = rng.normal(scale=np.sqrt(2.0 / (W.shape[0] * W.shape[1])), size=W.shape)
+        bias[:] = rng.normal(scale=0.05, size=bias.shape)
+    net.set_params(torch.from_numpy(theta).cuda())
+    x = unet.bf16(rng.uniform(-1, 1, size=(1, S, S, S, in_ch)))
+    out = torch.empty((1, S, S, S, out_ch), dtype=torch.float32, device="cuda")
+    net.forward(torch.from_numpy(_bf16_bits(x).view(np.int16)).cuda(), out)
+    shapes = unet.layer_shapes(in_ch, out_ch, widths)
+    lvl_of = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0]
+    keep = [2, 3, 9, 10, 11]
+    acts = {li: _tensor(net, b.MPM_NT_ACT, li, (1,) + (S >> lvl_of[li],) * 3, shapes[li][1]) for li in keep}
+    net.close()
+    layers = unet.unpack(theta.astype(np.float64), in_ch, out_ch, widths)
+
+    def sampled(xl, li, k):
+        n = xl.shape[1]
+        pts = rng.integers(0, n, size=(k, 3))
+        pts = np.concatenate([pts, [[z, y, xx] for z in (0, n - 1) for y in (0, n - 1) for xx in (0, n - 1)],
+                              [[0, n // 2, 3], [n - 1, 5, n // 2], [7, 0, n - 1]]])
+        xp = np.zeros((n + 2, n + 2, n + 2, xl.shape[-1]))
+        xp[1:-1, 1:-1, 1:-1] = xl[0]
+        patches = np.stack([xp[z:z + 3, y:y + 3, xx:xx + 3] for z, y, xx in pts])
+        W, bias = layers[li]
+        want = unet.bf16(np.maximum(unet.conv3(patches, unet.bf16(W), bias)[:, 1, 1, 1], 0.0))
+        got = acts[li][0][pts[:, 0], pts[:, 1], pts[:, 2]]
+        return got, want
+
+    for li, xl in ((3, acts[2]), (11, acts[10])):
+        got, want = sampled(xl, li, 400)
+        assert _rel(got, want) <= 1e-3, (li, _rel(got, want))
+    # decoder level 1, first layer: upsampled level-2 output concatenated with the skip
+    cat = np.concatenate([unet.up2(acts[9]), acts[3]], axis=-1)
+    got, want = sampled(cat, 10, 400)
+    assert _rel(got, want) <= 1e-3, (10, _rel(got, want))
 
 
 def test_adam_step_matches_oracle():
