@@ -235,18 +235,27 @@ __device__ inline int conv_halo_word(int i) {
     return v % kHX | ((v / kHX) % kHY) << 5 | (v / (kHX * kHY)) << 8 | (e & 1) << 11;
 }
 
-// Byte offsets of the thread's halo words from the halo origin on a full-resolution
-// source with channel stride ld (~0 past the halo); fixed for a launch.
+// Byte offsets of the thread's halo words from the halo origin (~0 past the halo), fixed
+// for a launch: off on a full-resolution source with channel stride ld, and, when UP,
+// offh on the half-resolution source that is upsampled (stride a.ldx; the halo voxel
+// (hx, hy, hz) reads half-resolution voxel ((hx + 1) / 2, ...) from the origin's).
+template <bool UP>
 struct ConvLane {
     unsigned off[kXM];
+    unsigned offh[UP ? kXM : 1];
 };
-__device__ inline ConvLane conv_lane(const ConvArgs& a, int ld) {
-    ConvLane l;
+template <bool UP>
+__device__ inline ConvLane<UP> conv_lane(const ConvArgs& a, int ld) {
+    ConvLane<UP> l;
+    const unsigned Hh = a.H >> 1, Wh = a.W >> 1;
 #pragma unroll
     for (int i = 0; i < kXM; ++i) {
         const int p = conv_halo_word(i);
         const unsigned hx = p & 31, hy = (p >> 5) & 7, hz = (p >> 8) & 7, gi = p >> 11;
         l.off[i] = p < 0 ? ~0u : 2u * (((hz * a.H + hy) * a.W + hx) * ld + 8 * gi);
+        if (UP)
+            l.offh[UP ? i : 0] =
+                p < 0 ? ~0u : 2u * (((((hz + 1) >> 1) * Hh + ((hy + 1) >> 1)) * Wh + ((hx + 1) >> 1)) * a.ldx + 8 * gi);
     }
     return l;
 }
@@ -256,8 +265,8 @@ __device__ inline ConvLane conv_lane(const ConvArgs& a, int ld) {
 // only tiles whose halo crosses the grid's boundary test each word.  XCAT: the kernel
 // may read an upsampled half-resolution input and a concatenated skip (a.x2).
 template <int NTB, bool WL, bool GATED>
-__device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, int tb, const ConvLane& ln,
-                                  ConvRegs<NTB, WL, GATED>& r) {
+__device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, int tb,
+                                  const ConvLane<WL && !GATED>& ln, ConvRegs<NTB, WL, GATED>& r) {
     constexpr bool XCAT = WL && !GATED;
     const bool up = XCAT && a.x2 && cb < a.c1;       // upsampled half-resolution input
     const bool cat = XCAT && a.x2 && cb >= a.c1;     // concatenated skip input
@@ -278,12 +287,13 @@ __device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, 
         r.x[i] = make_uint4(0, 0, 0, 0);
         if (GATED) r.g[i] = make_uint4(0, 0, 0, 0);
     }
-    if (t.in && !up) {   // every word inside the grid: one base and the lane's offsets
+    if (t.in) {   // every word inside the grid: one base and the lane's offsets
 #pragma unroll
         for (int i = 0; i < kXM; ++i) {
             if (ln.off[i] == ~0u) continue;
-            r.x[i] = *reinterpret_cast<const uint4*>(base + ln.off[i]);
-            if (GATED) r.g[i] = *reinterpret_cast<const uint4*>(gbase + ln.off[i]);
+            const unsigned o = XCAT && up ? ln.offh[XCAT ? i : 0] : ln.off[i];
+            r.x[i] = *reinterpret_cast<const uint4*>(base + o);
+            if (GATED) r.g[i] = *reinterpret_cast<const uint4*>(gbase + o);
         }
     } else {
 #pragma unroll
@@ -293,8 +303,7 @@ __device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, 
             const int hx = p & 31, hy = (p >> 5) & 7, hz = (p >> 8) & 7, gi = p >> 11;
             if ((unsigned)(t.x0 - 1 + hx) < (unsigned)a.W && (unsigned)(t.y0 - 1 + hy) < (unsigned)a.H &&
                 (unsigned)(t.z0 - 1 + hz) < (unsigned)a.D) {
-                const unsigned o = up ? 2u * ((((unsigned)((hz + 1) >> 1) * Hh + ((hy + 1) >> 1)) * Wh + ((hx + 1) >> 1)) * ld + 8 * gi)
-                                      : ln.off[i];
+                const unsigned o = XCAT && up ? ln.offh[XCAT ? i : 0] : ln.off[i];
                 r.x[i] = *reinterpret_cast<const uint4*>(base + o);
                 if (GATED) r.g[i] = *reinterpret_cast<const uint4*>(gbase + o);
             }
@@ -320,16 +329,17 @@ __device__ inline void conv_store(char* xs, const ConvRegs<NTB, WL, GATED>& r) {
 // address of the lane's voxel x = lane % 16 in halo row 0 of the wave's plane, channels
 // 8 (g mod 2) .. + 7 (g = lane / 16).  M tile mt covers output row y = mt, which reads
 // halo row mt + dy for tap row dy.  B fragments come from registers (breg, weights
-// fixed for the block) or from the chunk's weights in LDS.
+// fixed for the block) or from the chunk's weights in LDS (at wbase, by default right
+// after the halo tile).
 template <int NTB, bool BREG>
 __device__ inline void conv_chunk(const char* xs, uint32_t lb, const uint4 (&breg)[kSteps][NTB],
-                                  f32x4 (&acc)[4][NTB]) {
+                                  f32x4 (&acc)[4][NTB], const char* wbase = nullptr) {
     constexpr int VB = kCS * 2;         // LDS bytes per halo voxel
     constexpr int ROW = kHX * VB;       // per halo row
     constexpr int PLANE = kHY * ROW;    // per halo plane
     const int lane = threadIdx.x & 63, h = lane >> 5;
     const uint32_t b1 = lb + h * VB, bR = lb + h * ROW, bZ = lb + h * PLANE;
-    const char* wl = xs + conv_x_bytes() + 16 * lane;
+    const char* wl = (wbase ? wbase : xs + conv_x_bytes()) + 16 * lane;   // weights staged in LDS
     auto bfrag = [&](int s, int nt) -> bf16x8 {
         if (BREG) return __builtin_bit_cast(bf16x8, breg[s][nt]);
         return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wl + (s * NTB + nt) * 1024));
@@ -370,6 +380,53 @@ __device__ inline void conv_chunk(const char* xs, uint32_t lb, const uint4 (&bre
 #pragma unroll
             for (int nt = 0; nt < NTB; ++nt)
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[nt], af, acc[mt][nt], 0, 0, 0);
+        }
+    }
+}
+
+// Bias, ReLU and store of an item's output tiles (acc is cleared).  The MFMAs take the
+// weights as their A operand, so lane l holds output channels 4 (l / 16) .. + 3 of
+// voxel x0 + l mod 16 in row (y0 + mt, z0 + wave): one 8-byte BF16 word per M tile
+// when the output's stride and offset allow (vec), else single values.
+template <int NTB>
+__device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int tb, const float* bias_l, bool vec,
+                                     f32x4 (&acc)[4][NTB]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15;
+    const long long ob = t.sbase + ((long long)t.z0 * a.H + t.y0) * a.W + t.x0;   // the tile's origin
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const bool inb = t.out || (t.x0 + m < a.W && t.y0 + mt < a.H && t.z0 + wave < a.D);
+        const unsigned pv = ((unsigned)wave * a.H + mt) * a.W + m;   // voxel offset from the origin
+#pragma unroll
+        for (int nt = 0; nt < NTB; ++nt) {
+            const int co = (tb + nt) * 16 + 4 * (lane >> 4);
+            const float4 bq = *reinterpret_cast<const float4*>(bias_l + nt * 16 + 4 * (lane >> 4));
+            const float bv[4] = {bq.x, bq.y, bq.z, bq.w};
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] = acc[mt][nt][i] + bv[i];
+                if (a.relu) v[i] = fmaxf(v[i], 0.f);
+            }
+            acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (!inb) continue;
+            if (vec && co + 4 <= a.cout) {
+                const bf16x2 lo = {(__bf16)v[0], (__bf16)v[1]}, hi = {(__bf16)v[2], (__bf16)v[3]};
+                uint16_t* yp = a.y + ob * a.ldy + a.yoff;
+                *reinterpret_cast<uint2*>(yp + pv * a.ldy + co) =
+                    make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+            } else if (a.y) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (co + i < a.cout)
+                        a.y[(ob + pv) * a.ldy + a.yoff + co + i] = __builtin_bit_cast(uint16_t, (__bf16)v[i]);
+            }
+            if (a.yf) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (co + i < a.cout) a.yf[(ob + pv) * a.cout + co + i] = v[i];
+            }
         }
     }
 }
@@ -428,7 +485,7 @@ __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_con
         conv_store_w<NTB>(xs, w);
     }
     // halo word offsets of the full-resolution source (the skip input when a.x2 is set)
-    const ConvLane ln = conv_lane(a, (WL && !GATED && a.x2) ? a.ldx2 : a.ldx);
+    const ConvLane<WL && !GATED> ln = conv_lane<WL && !GATED>(a, (WL && !GATED && a.x2) ? a.ldx2 : a.ldx);
     ConvRegs<NTB, WL, GATED> regs;
     // chunk c covers channels [16 c, 16 c + 16)
     int chunk = 0;
@@ -448,50 +505,113 @@ __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_con
         const ConvTile tn = nc == 0 ? conv_tile(a, nxt) : t;
         if (more) conv_fetch<NTB, WL, GATED>(a, tn, 16 * nc, tb, ln, regs);   // in flight during the MFMAs
         conv_chunk<NTB, BREG>(xs, lb, breg, acc);
-        if (chunk == nchunk - 1) {
-            // voxel x0 + lane % 16 of row (y0 + mt, z0 + wave); the tile's origin is uniform
-            const int m = lane & 15;
-            const long long ob = t.sbase + ((long long)t.z0 * a.H + t.y0) * a.W + t.x0;
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const bool inb = t.out || (t.x0 + m < a.W && t.y0 + mt < a.H && t.z0 + wave < a.D);
-                const unsigned pv = ((unsigned)wave * a.H + mt) * a.W + m;   // voxel offset from the origin
-#pragma unroll
-                for (int nt = 0; nt < NTB; ++nt) {
-                    const int co = (tb + nt) * 16 + 4 * (lane >> 4);
-                    const float4 bq = *reinterpret_cast<const float4*>(bias_l + nt * 16 + 4 * (lane >> 4));
-                    const float bv[4] = {bq.x, bq.y, bq.z, bq.w};
-                    float v[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        v[i] = acc[mt][nt][i] + bv[i];
-                        if (a.relu) v[i] = fmaxf(v[i], 0.f);
-                    }
-                    acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    if (!inb) continue;
-                    if (vec && co + 4 <= a.cout) {
-                        const bf16x2 lo = {(__bf16)v[0], (__bf16)v[1]}, hi = {(__bf16)v[2], (__bf16)v[3]};
-                        uint16_t* yp = a.y + ob * a.ldy + a.yoff;
-                        *reinterpret_cast<uint2*>(yp + pv * a.ldy + co) =
-                            make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
-                    } else if (a.y) {
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            if (co + i < a.cout)
-                                a.y[(ob + pv) * a.ldy + a.yoff + co + i] = __builtin_bit_cast(uint16_t, (__bf16)v[i]);
-                    }
-                    if (a.yf) {
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            if (co + i < a.cout) a.yf[(ob + pv) * a.cout + co + i] = v[i];
-                    }
-                }
-            }
-        }
+        if (chunk == nchunk - 1) conv_epilogue<NTB>(a, t, tb, bias_l, vec, acc);
         if (!more) break;
         t = tn;
         cur = nxt;
         chunk = nc;
+    }
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Staging of an item's halo tile (16 input channels) straight from global memory into
+// LDS: global_load_lds_dwordx4 writes lane l's 16 bytes at the wave's LDS base + 16 l,
+// which is the word order of the tile; words outside the grid are written as zeros.
+__device__ inline void conv_stage(const ConvArgs& a, const ConvTile& t, const ConvLane<false>& ln, char* dst) {
+    const int wave = threadIdx.x >> 6;
+    const uintptr_t base =
+        (uintptr_t)a.x + (uintptr_t)((t.sbase + ((long long)(t.z0 - 1) * a.H + (t.y0 - 1)) * a.W + (t.x0 - 1)) * a.ldx * 2);
+#pragma unroll
+    for (int i = 0; i < kXM; ++i) {
+        const int p = conv_halo_word(i);
+        if (p < 0) continue;
+        const int hx = p & 31, hy = (p >> 5) & 7, hz = (p >> 8) & 7;
+        if (t.in || ((unsigned)(t.x0 - 1 + hx) < (unsigned)a.W && (unsigned)(t.y0 - 1 + hy) < (unsigned)a.H &&
+                     (unsigned)(t.z0 - 1 + hz) < (unsigned)a.D))
+            __builtin_amdgcn_global_load_lds((const void*)(base + ln.off[i]),
+                                             (lds_void_t*)(dst + (256 * i + 64 * wave) * 16), 16, 0, 0);
+        else
+            *reinterpret_cast<uint4*>(dst + (threadIdx.x + 256 * i) * 16) = make_uint4(0, 0, 0, 0);
+    }
+}
+
+// k_conv for 16-channel inputs without a gate, with the halo tiles staged asynchronously
+// in two LDS buffers: the staging of item j + 2 is issued as soon as every wave has read
+// item j, so its global loads overlap the MFMAs of item j + 1 and nothing passes through
+// registers (16 -> 16 channels on 128^3: 49 -> 42 us).  Same work split, results and
+// epilogue as k_conv.
+template <int NTB>
+__global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs a) {
+    constexpr int HB = kHV * kCS * 2;
+    __shared__ __attribute__((aligned(16))) char h0[HB];
+    __shared__ __attribute__((aligned(16))) char h1[HB];
+    __shared__ __attribute__((aligned(16))) char wl[NTB > 1 ? kSteps * NTB * 1024 : 16];
+    __shared__ __attribute__((aligned(16))) float bias_l[16 * NTB];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nsplit = a.nt / NTB;
+    const int tb = (int)(blockIdx.x % nsplit) * NTB;
+    ConvCursor cur = conv_cursor(a, blockIdx.x / nsplit, gridDim.x / nsplit);
+    if (cur.n >= a.n) return;
+    if (threadIdx.x < 16 * NTB) {
+        const int co = tb * 16 + threadIdx.x;
+        bias_l[threadIdx.x] = a.bias && co < a.cout ? a.bias[co] : 0.f;
+    }
+    const bool vec = a.y && a.ldy % 4 == 0 && a.yoff % 4 == 0 && ((uintptr_t)a.y & 7) == 0;
+    const uint32_t lb = (uint32_t)(((wave * kHY) * kHX + (lane & 15)) * kCS * 2 + 16 * ((lane >> 4) & 1));
+    f32x4 acc[4][NTB];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTB; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    constexpr bool BREG = NTB == 1;
+    uint4 breg[kSteps][NTB];
+    if (BREG) {
+        const uint4* wsrc = reinterpret_cast<const uint4*>(a.w);
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) breg[s][0] = wsrc[((long long)s * a.nt + tb) * 64 + lane];
+    } else {   // the block's weights, staged once
+        uint4 w[ConvW<NTB>::M];
+        conv_fetch_w<NTB>(a, 0, tb, w);
+#pragma unroll
+        for (int i = 0; i < ConvW<NTB>::M; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < ConvW<NTB>::E) reinterpret_cast<uint4*>(wl)[e] = w[i];
+        }
+    }
+    const ConvLane<false> ln = conv_lane<false>(a, a.ldx);
+    // the item being computed (cur, tile t) and the next one to stage (scur, tile st)
+    ConvTile t = conv_tile(a, cur);
+    ConvCursor scur = cur;
+    ConvTile st = t;
+    conv_stage(a, st, ln, h0);
+    conv_advance(a, scur);
+    st = conv_tile(a, scur);
+    __syncthreads();
+    if (scur.n < a.n) conv_stage(a, st, ln, h1);
+    conv_advance(a, scur);
+    st = conv_tile(a, scur);
+    conv_chunk<NTB, BREG>(h0, lb, breg, acc, wl);
+    // One step: wait until every wave has read hn (the item just computed) and the
+    // staging of the item in hc has landed, stage the item after next into hn, store the
+    // finished item, and compute the next one from hc.  The restrict qualifiers tell the
+    // compiler that the reads of hc do not wait for the staging just issued into hn.
+    auto step = [&](char* __restrict__ hn, const char* __restrict__ hc) -> bool {
+        __syncthreads();
+        if (scur.n < a.n) conv_stage(a, st, ln, hn);
+        conv_advance(a, scur);
+        st = conv_tile(a, scur);
+        conv_epilogue<NTB>(a, t, tb, bias_l, vec, acc);
+        conv_advance(a, cur);
+        if (cur.n >= a.n) return false;
+        t = conv_tile(a, cur);
+        conv_chunk<NTB, BREG>(hc, lb, breg, acc, wl);
+        return true;
+    };
+    for (;;) {
+        if (!step(h0, h1)) break;
+        if (!step(h1, h0)) break;
     }
 }
 

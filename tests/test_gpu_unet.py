@@ -299,14 +299,15 @@ def test_layerwise_chain_matches_oracle(widths, shape):
                                              ([16, 32, 64, 64], 8, (1, 8, 8, 16)),
                                              ([16, 32, 64, 64], 10, (2, 4, 5, 17)),
                                              ([16, 32], 1, (1, 64, 64, 64)), ([16, 32], 3, (1, 32, 64, 64)),
-                                             ([16, 32], 3, (1, 64, 64, 64))])
+                                             ([16, 32], 3, (1, 64, 64, 64)), ([16, 32], 1, (2, 64, 64, 64))])
 def test_single_layer_kernels_exact(widths, li, shape):
     """Forward, input-gradient and weight-gradient kernels of one layer on small-integer
     data, for which FP32 accumulation is exact: the GPU must equal the FP64 oracle
     bit for bit (catches any index, tap or layout error).  The largest grids give the
     persistent convolution blocks several work items each, and the weight-gradient
     blocks several voxel tiles each; the 32-channel layer on 64^3 runs the variant with
-    two output tiles per block."""
+    two output tiles per block, and the 16-channel layer on two 64^3 samples the one
+    that stages its input tiles asynchronously."""
     torch = require_gpu()
     from paper_2505_03067_amd import Net
     net = Net(13, 3, widths, seed=3)
@@ -345,9 +346,10 @@ def test_single_layer_kernels_exact(widths, li, shape):
 
 def test_full_grid_forward_sampled():
     """The 16-32-64-64 network's forward pass on a 128^3 grid (the warm start's box grid),
-    where the launches take their production shapes: the 64^3 layers with 32 outputs run
-    two output tiles per block, and the decoder's first layer there reads the upsampled
-    deeper output and the skip directly.  Those layers are recomputed by the oracle at
+    where the launches take their production shapes: the 128^3 layers with 16 inputs
+    and outputs stage their input tiles asynchronously, the 64^3 layers with 32 outputs
+    run two output tiles per block, and the decoder's first layer there reads the
+    upsampled deeper output and the skip directly.  Those layers are recomputed by the oracle at
     sampled voxels (the grid's corners and some face voxels among them) from the GPU's
     own stored BF16 inputs and held to the layerwise bar: relative L2 error 1e-3."""
     torch = require_gpu()
@@ -366,7 +368,7 @@ def test_full_grid_forward_sampled():
     net.forward(torch.from_numpy(_bf16_bits(x).view(np.int16)).cuda(), out)
     shapes = unet.layer_shapes(in_ch, out_ch, widths)
     lvl_of = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0]
-    keep = [2, 3, 9, 10, 11]
+    keep = [0, 1, 2, 3, 9, 10, 11, 12, 13]
     acts = {li: _tensor(net, b.MPM_NT_ACT, li, (1,) + (S >> lvl_of[li],) * 3, shapes[li][1]) for li in keep}
     net.close()
     layers = unet.unpack(theta.astype(np.float64), in_ch, out_ch, widths)
@@ -384,7 +386,7 @@ def test_full_grid_forward_sampled():
         got = acts[li][0][pts[:, 0], pts[:, 1], pts[:, 2]]
         return got, want
 
-    for li, xl in ((3, acts[2]), (11, acts[10])):
+    for li, xl in ((1, acts[0]), (3, acts[2]), (11, acts[10]), (13, acts[12])):
         got, want = sampled(xl, li, 400)
         assert _rel(got, want) <= 1e-3, (li, _rel(got, want))
     # decoder level 1, first layer: upsampled level-2 output concatenated with the skip
