@@ -59,6 +59,8 @@ extern "C" {
 #define MPM_WS_NONE 0   /* start from c^n */
 #define MPM_WS_NET 1    /* learned warm start from the attached network, fallback c^n */
 #define MPM_WS_EXTRAP 2 /* linear extrapolation 2 c^n - c^{n-1}, fallback c^n */
+#define MPM_WS_NET_EXTRAP 3 /* the attached network's correction of the extrapolated start,
+                               fallback c^n; no warm start while c^{n-1} is unknown */
 
 /* orthogonalisation of the Arnoldi basis */
 #define MPM_ORTHO_CGS2 0
@@ -78,7 +80,7 @@ typedef struct {
     int32_t use_graph;   /* 1: replay each GMRES cycle from a captured hipGraph; 0 (default):
                             launch the kernels directly (measured at least as fast on MI355X
                             on every workload tried: each kernel runs longer than its launch) */
-    int32_t warm_start;  /* MPM_WS_NONE, MPM_WS_NET or MPM_WS_EXTRAP */
+    int32_t warm_start;  /* MPM_WS_NONE, MPM_WS_NET, MPM_WS_EXTRAP or MPM_WS_NET_EXTRAP */
     int32_t tile_override; /* 0: autotuned work split; >0: unknowns per block (multiple of 1024) */
     int32_t ortho;       /* MPM_ORTHO_DCGS2 (default): classical Gram-Schmidt with delayed
                             reorthogonalisation, one global reduction and two passes per step;
@@ -338,15 +340,17 @@ int32_t mpm_net_debug_op(mpm_net net, int32_t op, int32_t n, int32_t d, int32_t 
                          int32_t c2, const void* a, const void* b, void* out, void* out2);
 
 /* Use 'net' (in_ch = 5 S + 1, out_ch = S) as the warm start of a context created with
- * warm_start = MPM_WS_NET; net = NULL detaches.  Network input on the box grid (box
- * sizes rounded up to multiples of 8, zero beyond the box), each channel times
- * in_scale[ch] (host, exactly 5 S + 1 floats are read): c^n (S), k (S), D (S), s (S),
- * the mask, and the Jacobi-scaled residual of c^n, d = (b - A c^n) / A_PP (S; zero
- * off the domain), which is the first Jacobi correction and is computed from the same
- * inputs by the step's first residual.  The prediction of species s is output *
- * out_scale[s] (host, S floats read) added to c^n.  Each step keeps the prediction of
- * a system only if its true residual is below that of c^n
- * (mpm_stats.warm_start_used / fallback).  The net must outlive its use. */
+ * warm_start = MPM_WS_NET or MPM_WS_NET_EXTRAP; net = NULL detaches.  Network input on
+ * the box grid (box sizes rounded up to multiples of 8, zero beyond the box), each
+ * channel times in_scale[ch] (host, exactly 5 S + 1 floats are read): c^n (S), k (S),
+ * D (S), s (S), the mask, and the Jacobi-scaled residual d = (b - A x_b) / A_PP of the
+ * base start x_b (S; zero off the domain), the first Jacobi correction of x_b, computed
+ * with the step's own residual kernel.  The base start is c^n (MPM_WS_NET) or the
+ * extrapolation 2 c^n - c^{n-1} (MPM_WS_NET_EXTRAP, from the second step of the context
+ * on).  The prediction of species s is output * out_scale[s] (host, S floats read)
+ * added to x_b.  Each step keeps the prediction of a system only if its true residual
+ * is below that of c^n (mpm_stats.warm_start_used / fallback).  The net must outlive
+ * its use. */
 int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scale, const float* out_scale);
 
 /* Training pair for the warm start of 'problem': the network input built from the
@@ -359,6 +363,14 @@ int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scale, const fl
 int32_t mpm_ws_pair(mpm_ctx ctx, int32_t problem, const double* c_old, const double* c_new,
                     const float* in_scale, const float* out_scale, uint16_t* in_bf16, float* target);
 
+/* The same for MPM_WS_NET_EXTRAP: the base start is x_b = 2 c_old - c_prev (c_prev:
+ * device FP64 lattice fields of the step before c_old) on the domain voxels of the
+ * box, the input's last S channels hold the Jacobi-scaled residual of x_b, and the
+ * target is (c_new - x_b) / out_scale. */
+int32_t mpm_ws_pair_extrap(mpm_ctx ctx, int32_t problem, const double* c_prev, const double* c_old,
+                           const double* c_new, const float* in_scale, const float* out_scale, uint16_t* in_bf16,
+                           float* target);
+
 /* Training loss of the warm start by the residual its prediction leaves.  out: device
  * FP32 [gz][gy][gx][S], the network's output for a pair of 'problem' (units of
  * out_scale); target: that pair's target (mpm_ws_pair).  With e = (out - target) *
@@ -367,7 +379,8 @@ int32_t mpm_ws_pair(mpm_ctx ctx, int32_t problem, const double* c_old, const dou
  * S species and N domain voxels, and grad_out (device FP32, shape of out) = dloss/dout
  * = 2 A S w / (S N out_scale), zero off the domain.  out_scale: host FP32 [S], positive.
  * Uses the context's solver workspace as scratch (the next step recomputes it);
- * synchronises the stream.  MPM_ESTATE without MPM_WS_NET or before mpm_fv_setup. */
+ * synchronises the stream.  MPM_ESTATE without a network warm start (MPM_WS_NET or
+ * MPM_WS_NET_EXTRAP) or before mpm_fv_setup. */
 int32_t mpm_ws_loss(mpm_ctx ctx, int32_t problem, const float* out, const float* target, const float* out_scale,
                     float* grad_out, double* loss);
 

@@ -108,7 +108,7 @@ extern "C" int32_t mpm_create(mpm_ctx* out, int32_t nspecies, int32_t nproblems,
     else mpm_default_options(&o);
     if (o.restart < 1 || o.restart > MPM_MAX_RESTART || o.max_cycles < 1 ||
         (o.precision != MPM_FP64 && o.precision != MPM_FP32_IR) || !(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0) ||
-        o.warm_start < MPM_WS_NONE || o.warm_start > MPM_WS_EXTRAP || o.tile_override < 0 ||
+        o.warm_start < MPM_WS_NONE || o.warm_start > MPM_WS_NET_EXTRAP || o.tile_override < 0 ||
         (o.ortho != MPM_ORTHO_CGS2 && o.ortho != MPM_ORTHO_DCGS2) ||
         (o.tile_override % kAlign) != 0) {
         set_error("mpm_create: invalid options");
@@ -369,8 +369,8 @@ extern "C" int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scal
         set_error("mpm_attach_net: the network must read 5 S + 1 channels and write S");
         return MPM_EINVAL;
     }
-    if (c->opt.warm_start != MPM_WS_NET) {
-        set_error("mpm_attach_net: the context was not created with warm_start = MPM_WS_NET");
+    if (!net_warm_start(c)) {
+        set_error("mpm_attach_net: the context was not created with a network warm start");
         return MPM_ESTATE;
     }
     int rc = set_scales(c, in_scale, out_scale);
@@ -379,24 +379,41 @@ extern "C" int32_t mpm_attach_net(mpm_ctx ctx, mpm_net net, const float* in_scal
     return MPM_OK;
 }
 
-extern "C" int32_t mpm_ws_pair(mpm_ctx ctx, int32_t problem, const double* c_old, const double* c_new,
-                               const float* in_scale, const float* out_scale, uint16_t* in_bf16, float* target) {
+static int32_t ws_pair_call(const char* name, mpm_ctx ctx, int32_t problem, const double* c_prev, const double* c_old,
+                            const double* c_new, const float* in_scale, const float* out_scale, uint16_t* in_bf16,
+                            float* target) {
     Ctx* c = (Ctx*)ctx;
     if (!c || !c_old || !c_new || !in_scale || !out_scale || !in_bf16 || !target || problem < 0 || problem >= c->P) {
-        set_error("mpm_ws_pair: bad arguments");
+        set_error(std::string(name) + ": bad arguments");
         return MPM_EINVAL;
     }
-    if (c->opt.warm_start != MPM_WS_NET || !c->probs[problem].ready) {
-        set_error("mpm_ws_pair: needs a context with warm_start = MPM_WS_NET and a set-up problem");
+    if (!net_warm_start(c) || !c->probs[problem].ready) {
+        set_error(std::string(name) + ": needs a context with a network warm start and a set-up problem");
         return MPM_ESTATE;
     }
     int rc = set_scales(c, in_scale, out_scale);
     if (rc != MPM_OK) return rc;
     rc = enter(c);
     if (rc != MPM_OK) return rc;
-    rc = ws_pair(c, problem, c_old, c_new, in_bf16, target);
+    rc = ws_pair(c, problem, c_prev, c_old, c_new, in_bf16, target);
     if (rc == MPM_OK) rc = leave(c);
     return rc;
+}
+
+extern "C" int32_t mpm_ws_pair(mpm_ctx ctx, int32_t problem, const double* c_old, const double* c_new,
+                               const float* in_scale, const float* out_scale, uint16_t* in_bf16, float* target) {
+    return ws_pair_call("mpm_ws_pair", ctx, problem, nullptr, c_old, c_new, in_scale, out_scale, in_bf16, target);
+}
+
+extern "C" int32_t mpm_ws_pair_extrap(mpm_ctx ctx, int32_t problem, const double* c_prev, const double* c_old,
+                                      const double* c_new, const float* in_scale, const float* out_scale,
+                                      uint16_t* in_bf16, float* target) {
+    if (!c_prev) {
+        set_error("mpm_ws_pair_extrap: bad arguments");
+        return MPM_EINVAL;
+    }
+    return ws_pair_call("mpm_ws_pair_extrap", ctx, problem, c_prev, c_old, c_new, in_scale, out_scale, in_bf16,
+                        target);
 }
 
 extern "C" int32_t mpm_ws_loss(mpm_ctx ctx, int32_t problem, const float* out, const float* target,
@@ -406,8 +423,8 @@ extern "C" int32_t mpm_ws_loss(mpm_ctx ctx, int32_t problem, const float* out, c
         set_error("mpm_ws_loss: bad arguments");
         return MPM_EINVAL;
     }
-    if (c->opt.warm_start != MPM_WS_NET || !c->probs[problem].ready) {
-        set_error("mpm_ws_loss: needs a context with warm_start = MPM_WS_NET and a set-up problem");
+    if (!net_warm_start(c) || !c->probs[problem].ready) {
+        set_error("mpm_ws_loss: needs a context with a network warm start and a set-up problem");
         return MPM_ESTATE;
     }
     for (int s = 0; s < c->S; ++s) {
@@ -433,7 +450,7 @@ extern "C" int32_t mpm_ws_grid(mpm_ctx ctx, int32_t problem, int32_t* grid) {
         return MPM_EINVAL;
     }
     if (!c->probs[problem].ready || c->probs[problem].gd[0] == 0) {
-        set_error("mpm_ws_grid: no warm-start grid (set up the problem in a MPM_WS_NET context)");
+        set_error("mpm_ws_grid: no warm-start grid (set up the problem in a context with a network warm start)");
         return MPM_ESTATE;
     }
     for (int d = 0; d < 3; ++d) grid[d] = c->probs[problem].gd[d];

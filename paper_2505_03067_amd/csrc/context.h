@@ -161,7 +161,16 @@ int debug_apply(Ctx* c, int p, const double* x, double* y, int mode);
 int debug_krylov(Ctx* c, int p, int sp, int kmax, int* mcount, double* vs, double* basis, double* hess);
 int ensure_layout(Ctx* c);
 int select_timing(Ctx* c, int kind, int j, int repeat);
-int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* in_bf16, float* target);
+int ws_pair(Ctx* c, int p, const double* c_prev, const double* c_old, const double* c_new, uint16_t* in_bf16,
+            float* target);
+// the network warm starts (network buffers on the box grid, mpm_attach_net)
+inline bool net_warm_start(const Ctx* c) {
+    return c->opt.warm_start == MPM_WS_NET || c->opt.warm_start == MPM_WS_NET_EXTRAP;
+}
+// the starts that keep c^{n-1}
+inline bool extrap_warm_start(const Ctx* c) {
+    return c->opt.warm_start == MPM_WS_EXTRAP || c->opt.warm_start == MPM_WS_NET_EXTRAP;
+}
 int ws_loss(Ctx* c, int p, const float* out, const float* target, float* grad, double* loss);
 
 }  // namespace mpm

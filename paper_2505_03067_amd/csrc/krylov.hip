@@ -1422,8 +1422,8 @@ __device__ inline long long grid_index(const ProbDev& pd, int l) {
     return ((long long)(z - pd.lo[2]) * pd.gd[1] + (y - pd.lo[1])) * pd.gd[0] + (x - pd.lo[0]);
 }
 
-// x0 = c^n + out * out_scale (network) or 2 c^n - c^{n-1} (extrapolation), for the
-// systems not already converged at c^n.  x holds c^n on entry.
+// For the systems not already converged at c^n: x += out * out_scale (network; x holds
+// the base start) or x = 2 x - c^{n-1} (extrapolation; x holds c^n).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, const float* scales) {
     const Block blk = a.blocks[blockIdx.x];
@@ -1444,9 +1444,10 @@ __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, con
     }
 }
 
-// Jacobi-scaled residual of c^n, d = r / A_PP = S (S r), on the domain voxels of problem
-// p into channel 4 S + 1 + s of the network input dst (times its scale, BF16).  V holds
-// S r from the first residual of the step (before any Arnoldi step overwrites it).
+// Jacobi-scaled residual of the base start, d = r / A_PP = S (S r), on the domain voxels
+// of problem p into channel 4 S + 1 + s of the network input dst (times its scale,
+// BF16).  V holds S r from the residual of the base start (c^n: the step's first
+// residual; the extrapolation: its own), before any Arnoldi step overwrites it.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_ws_resid(KArgs<T> a, int p, const float* scales, uint16_t* dst) {
     const Block blk = a.blocks[blockIdx.x];
@@ -1485,9 +1486,25 @@ __global__ void k_copy64(const double* src, double* dst, long long n) {
     if (i < n) dst[i] = src[i];
 }
 
-// Training target on the grid: (c_new - c_old) / out_scale on domain voxels, else 0.
-__global__ void k_ws_target(ProbDev pd, int S, int bx, int by, int bz, const double* c_old, const double* c_new,
-                            const float* stat, const float* scales, float* tgt) {
+// x = 2 x - c_prev on the domain unknowns of the blocks' systems (x holds c_old gathered
+// from the lattice; c_prev: lattice fields of the step before).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ws_extrap_x(KArgs<T> a, const double* c_prev) {
+    const Block blk = a.blocks[blockIdx.x];
+    if (blk.sys < 0) return;
+    const ProbDev pd = a.probs[blk.sys / a.S];
+    const Where wh = where_of(a, blk, pd);
+    const double* f = c_prev + (long long)wh.s * pd.nvox;
+    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
+        const int l = (int)(u - wh.base);
+        if (l < pd.N) a.x[u] = 2.0 * a.x[u] - f[pd.vox[l]];
+    }
+}
+
+// Training target on the grid: (c_new - x_b) / out_scale on domain voxels, else 0, with
+// the base start x_b = c_old, or 2 c_old - c_prev when c_prev is given.
+__global__ void k_ws_target(ProbDev pd, int S, int bx, int by, int bz, const double* c_prev, const double* c_old,
+                            const double* c_new, const float* stat, const float* scales, float* tgt) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long G = (long long)pd.gd[0] * pd.gd[1] * pd.gd[2];
     if (i >= G) return;
@@ -1499,7 +1516,10 @@ __global__ void k_ws_target(ProbDev pd, int S, int bx, int by, int bz, const dou
     const long long v = ((long long)(pd.lo[2] + z) * pd.ny + (pd.lo[1] + y)) * pd.nx + (pd.lo[0] + x);
     for (int s = 0; s < S; ++s) {
         float t = 0.f;
-        if (dom) t = (float)((c_new[s * pd.nvox + v] - c_old[s * pd.nvox + v]) / (double)scales[kScaleOut + s]);
+        if (dom) {
+            const double xb = c_prev ? 2.0 * c_old[s * pd.nvox + v] - c_prev[s * pd.nvox + v] : c_old[s * pd.nvox + v];
+            t = (float)((c_new[s * pd.nvox + v] - xb) / (double)scales[kScaleOut + s]);
+        }
         tgt[i * S + s] = t;
     }
 }
@@ -2043,7 +2063,7 @@ int ensure_layout(Ctx* c) {
     }
     // previous-step values for the extrapolated start live on the global unknowns
     c->have_prev = false;
-    if (c->opt.warm_start == MPM_WS_EXTRAP) {
+    if (extrap_warm_start(c)) {
         // [0, need): c^{n-1}; [need, 2 need): this step's c^n
         if (2 * need > c->cap_prev) {
             (void)hipFree(c->prev);
@@ -2330,17 +2350,24 @@ static int fetch_status(Ctx* c, hipStream_t st) {
     return MPM_OK;
 }
 
-// Warm start of every system not converged at c^n: network prediction or linear
-// extrapolation, accepted per system only if its true FP64 residual is smaller than
-// that of c^n (else the system restarts from c^n).  The outcome is recorded in the
-// statistics (warm_start_used, fallback, rel_res_warm).
+// Warm start of every system not converged at c^n: network prediction, linear
+// extrapolation, or the network's correction of the extrapolation, accepted per system
+// only if its true FP64 residual is smaller than that of c^n (else the system restarts
+// from c^n).  The outcome is recorded in the statistics (warm_start_used, fallback,
+// rel_res_warm).
 template <typename T>
 static int warm_start(Ctx* c, hipStream_t st) {
     const int nsys = c->S * c->P;
     KArgs<T> a = make_args<T>(c, c->d_blocks);
     const unsigned nb = (unsigned)c->blocks.size();
     const int mode = c->opt.warm_start;
-    if (mode == MPM_WS_NET) {
+    if (mode == MPM_WS_NET_EXTRAP) {
+        // base start x_b = 2 c^n - c^{n-1}; V = S (b - A x_b) for the network's input (the
+        // residual's partial sums are scratch: the acceptance test recomputes them)
+        k_ws_apply<T><<<nb, kThreads, 0, st>>>(a, MPM_WS_EXTRAP, c->d_scales);
+        k_residual<T><<<nb, kThreads, 0, st>>>(a, kResWarm);
+    }
+    if (net_warm_start(c)) {
         if (!c->have_scales) {
             set_error("warm start: no network scales (mpm_attach_net)");
             return MPM_ESTATE;
@@ -2368,7 +2395,7 @@ static int warm_start(Ctx* c, hipStream_t st) {
         }
         c->net->stream = saved;
     }
-    k_ws_apply<T><<<nb, kThreads, 0, st>>>(a, mode, c->d_scales);
+    k_ws_apply<T><<<nb, kThreads, 0, st>>>(a, mode == MPM_WS_NET_EXTRAP ? MPM_WS_NET : mode, c->d_scales);
     k_residual<T><<<nb, kThreads, 0, st>>>(a, kResWarm);
     k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResWarm);
     k_ws_revert<T><<<nb, kThreads, 0, st>>>(a);
@@ -2385,12 +2412,14 @@ static int run_step_t(Ctx* c, double tol) {
     KArgs<T> a = make_args<T>(c, c->d_blocks);
     const unsigned nb = (unsigned)c->blocks.size();
     k_gather<T><<<nb, kThreads, 0, st>>>(a);
-    const bool extrap = c->opt.warm_start == MPM_WS_EXTRAP;
+    const bool extrap = extrap_warm_start(c);
     const long long nall = (long long)c->prev_n;
     if (extrap) k_copy64<<<(unsigned)((nall + 255) / 256), 256, 0, st>>>(c->x, c->prev + nall, nall);
     k_residual<T><<<nb, kThreads, 0, st>>>(a, kResFirst);
     k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResFirst);
-    if ((c->opt.warm_start == MPM_WS_NET && c->net) || (c->opt.warm_start == MPM_WS_EXTRAP && c->have_prev)) {
+    const int wsm = c->opt.warm_start;
+    if ((wsm == MPM_WS_NET && c->net) || (wsm == MPM_WS_EXTRAP && c->have_prev) ||
+        (wsm == MPM_WS_NET_EXTRAP && c->net && c->have_prev)) {
         int wrc = warm_start<T>(c, st);
         if (wrc != MPM_OK) return wrc;
     }
@@ -2629,10 +2658,11 @@ int debug_apply(Ctx* c, int p, const double* x, double* y, int mode) {
 
 namespace mpm {
 
-// The first residual of a step from c_old for the systems of problem p, with the
-// solver's own kernels: c_old gathered as c^n (x, b) and r = b - A x (V holds S r).
+// The residual of a base start for the systems of problem p, with the solver's own
+// kernels: c_old gathered as c^n (x, b), x = 2 x - c_prev when c_prev is given, and
+// r = b - A x (V holds S r).
 template <typename T>
-static int ws_first_residual(Ctx* c, int p, const double* c_old) {
+static int ws_first_residual(Ctx* c, int p, const double* c_prev, const double* c_old) {
     hipStream_t st = c->stream;
     const int nsys = c->S * c->P;
     const int first = c->sys_tab_first[p * c->S];
@@ -2642,6 +2672,7 @@ static int ws_first_residual(Ctx* c, int p, const double* c_old) {
     MPM_HIP(hipMemcpyAsync(c->d_fields + p, c->h_fields + p, sizeof(double*), hipMemcpyHostToDevice, st));
     KArgs<T> a = make_args<T>(c, c->d_blocks_sys + first);
     k_gather<T><<<(unsigned)(end - first), kThreads, 0, st>>>(a);
+    if (c_prev) k_ws_extrap_x<T><<<(unsigned)(end - first), kThreads, 0, st>>>(a, c_prev);
     k_residual<T><<<(unsigned)(end - first), kThreads, 0, st>>>(a, kResFirst);
     MPM_HIP(hipGetLastError());
     return MPM_OK;
@@ -2680,7 +2711,8 @@ int ws_loss(Ctx* c, int p, const float* out, const float* target, float* grad, d
     return MPM_OK;
 }
 
-int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* in_bf16, float* target) {
+int ws_pair(Ctx* c, int p, const double* c_prev, const double* c_old, const double* c_new, uint16_t* in_bf16,
+            float* target) {
     int rc = ensure_layout(c);
     if (rc != MPM_OK) return rc;
     hipStream_t st = c->stream;
@@ -2692,15 +2724,15 @@ int ws_pair(Ctx* c, int p, const double* c_old, const double* c_new, uint16_t* i
     // next step uploads its own field pointers
     double* saved = c->h_fields[p];
     c->up_valid = false;
-    rc = ksize(c) == 8 ? ws_first_residual<double>(c, p, c_old) : ws_first_residual<float>(c, p, c_old);
+    rc = ksize(c) == 8 ? ws_first_residual<double>(c, p, c_prev, c_old) : ws_first_residual<float>(c, p, c_prev, c_old);
     if (rc == MPM_OK) {
         k_ws_input<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_old, ph.stat, c->d_scales,
                                                               in_bf16);
         const unsigned nb = (unsigned)c->blocks.size();
         if (ksize(c) == 8) k_ws_resid<double><<<nb, kThreads, 0, st>>>(make_args<double>(c, c->d_blocks), p, c->d_scales, in_bf16);
         else k_ws_resid<float><<<nb, kThreads, 0, st>>>(make_args<float>(c, c->d_blocks), p, c->d_scales, in_bf16);
-        k_ws_target<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_old, c_new, ph.stat,
-                                                               c->d_scales, target);
+        k_ws_target<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_prev, c_old, c_new,
+                                                               ph.stat, c->d_scales, target);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);

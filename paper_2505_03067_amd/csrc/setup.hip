@@ -471,7 +471,7 @@ static int discretise(Ctx* c, ProbHost& ph, const BoxGeo& g, const uint8_t* mask
     k_coefs<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ca);
     k_scaled<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(ph.a64, ph.sc64, ph.nbr, N, Npad, c->S, ph.c64,
                                                           ph.c32);
-    if (c->opt.warm_start == MPM_WS_NET) {
+    if (net_warm_start(c)) {
         const int gx = (g.bx + 7) / 8 * 8, gy = (g.by + 7) / 8 * 8, gz = (g.bz + 7) / 8 * 8;
         const size_t G = (size_t)gx * gy * gz;
         if (G > ph.cap_grid) {

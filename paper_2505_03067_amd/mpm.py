@@ -30,6 +30,7 @@ MPM_FP32_IR = 1
 MPM_WS_NONE = 0
 MPM_WS_NET = 1
 MPM_WS_EXTRAP = 2
+MPM_WS_NET_EXTRAP = 3
 MPM_ORTHO_CGS2 = 0
 MPM_ORTHO_DCGS2 = 1
 
@@ -118,6 +119,8 @@ def lib() -> ctypes.CDLL:
             "mpm_attach_net": [_vp, _vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
             "mpm_ws_pair": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_float), _vp, _vp],
+            "mpm_ws_pair_extrap": [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_float),
+                                   ctypes.POINTER(ctypes.c_float), _vp, _vp],
             "mpm_ws_grid": [_vp, ctypes.c_int32, _i32p],
             "mpm_ws_loss": [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_float), _vp,
                             ctypes.POINTER(ctypes.c_double)],
@@ -448,6 +451,18 @@ def mpm_ws_pair(ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target
                              _dev_ptr(target, torch.float32, "target")))
 
 
+def mpm_ws_pair_extrap(ctx, problem, c_prev, c_old, c_new, in_scale, out_scale, in_bf16, target,
+                       nspecies=None) -> None:
+    import torch
+    if in_bf16.dtype not in (torch.int16, torch.uint16, torch.bfloat16) or not in_bf16.is_contiguous():
+        raise TypeError("in_bf16 must be a contiguous 16-bit tensor")
+    a, b = _scales(in_scale, out_scale, nspecies)
+    _check(lib().mpm_ws_pair_extrap(ctx, int(problem), _dev_ptr(c_prev, torch.float64, "c_prev"),
+                                    _dev_ptr(c_old, torch.float64, "c_old"), _dev_ptr(c_new, torch.float64, "c_new"),
+                                    a, b, ctypes.c_void_p(in_bf16.data_ptr()),
+                                    _dev_ptr(target, torch.float32, "target")))
+
+
 MPM_NT_INPUT = 0
 MPM_NT_ACT = 1
 MPM_NT_ACT_GRAD = 2
@@ -611,16 +626,23 @@ class Solver:
     def ws_grid(self, problem=0):
         return mpm_ws_grid(self.ctx, problem)
 
-    def ws_pair(self, problem, c_old, c_new, in_scale, out_scale, in_bf16, target):
+    def ws_pair(self, problem, c_old, c_new, in_scale, out_scale, in_bf16, target, c_prev=None):
+        """Training pair (mpm_ws_pair); with c_prev, the pair of the extrapolated base start
+        (mpm_ws_pair_extrap)."""
         gx, gy, gz = self.ws_grid(problem)
         S = self.nspecies
         if in_bf16.numel() != gx * gy * gz * (5 * S + 1) or target.numel() != gx * gy * gz * S:
             raise ValueError(f"in_bf16 must hold {gx * gy * gz * (5 * S + 1)} values and target "
                              f"{gx * gy * gz * S} (grid {gx} x {gy} x {gz}, {S} species)")
-        for name, f in (("c_old", c_old), ("c_new", c_new)):
-            if f.dim() != 4 or f.shape[0] != S:
-                raise ValueError(f"{name} must be [S][z][y][x]")
-        mpm_ws_pair(self.ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target, self.nspecies)
+        fields = [("c_old", c_old), ("c_new", c_new)] + ([("c_prev", c_prev)] if c_prev is not None else [])
+        for name, f in fields:
+            if f.dim() != 4 or f.shape[0] != S or f.shape != c_old.shape:
+                raise ValueError(f"{name} must be [S][z][y][x] like c_old")
+        if c_prev is None:
+            mpm_ws_pair(self.ctx, problem, c_old, c_new, in_scale, out_scale, in_bf16, target, self.nspecies)
+        else:
+            mpm_ws_pair_extrap(self.ctx, problem, c_prev, c_old, c_new, in_scale, out_scale, in_bf16, target,
+                               self.nspecies)
 
     def ws_loss(self, problem, out, target, out_scale, grad_out):
         """Residual loss of a warm-start prediction and its gradient (see mpm_ws_loss)."""

@@ -25,12 +25,12 @@ def _bf16_values(bits):
     return (np.asarray(bits, np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def _ws_pair_case(p, S, box=None):
+def _ws_pair_case(p, S, box=None, extrap=False):
     """Network input and training target built by the library, against their
     definition: each channel (c^n, k, D, s per species, then the mask) times its scale,
     rounded to BF16 on the box grid (zero past the box), the Jacobi-scaled residual of
-    c^n per species; target (c^{n+1} - c^n) / out_scale on domain voxels, zero
-    elsewhere."""
+    the base start x_b per species; target (c^{n+1} - x_b) / out_scale on domain voxels,
+    zero elsewhere.  x_b = c^n, or with extrap the extrapolation 2 c^n - c^{n-1}."""
     torch = require_gpu()
     import paper_2505_03067_amd as m
     from oracle.fv import assemble, box_slice
@@ -40,10 +40,12 @@ def _ws_pair_case(p, S, box=None):
     in_scale = input_scales(S, out_scale)
     d = to_dev(p)
     f = torch.from_numpy(p.c0).cuda()
-    with m.Solver(S, 1, warm_start=m.MPM_WS_NET) as s:
+    with m.Solver(S, 1, warm_start=m.MPM_WS_NET_EXTRAP if extrap else m.MPM_WS_NET) as s:
         s.setup(0, box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
         for _ in range(2):          # a c^n away from the uniform initial state
             s.step([f], 1e-10)
+        prev = f.clone()
+        s.step([f], 1e-10)
         old = f.clone()
         s.step([f], 1e-10)
         gx, gy, gz = s.ws_grid(0)
@@ -51,11 +53,12 @@ def _ws_pair_case(p, S, box=None):
         assert (gx, gy, gz) == tuple((e + 7) // 8 * 8 for e in ext)
         inp = torch.empty((gz, gy, gx, 5 * S + 1), dtype=torch.int16, device="cuda")
         tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
-        s.ws_pair(0, old, f, in_scale, out_scale, inp, tgt)
+        s.ws_pair(0, old, f, in_scale, out_scale, inp, tgt, c_prev=prev if extrap else None)
     got_in = inp.cpu().numpy().view(np.uint16)
     got_t = tgt.cpu().numpy()
     c0 = old.cpu().numpy()
     c1 = f.cpu().numpy()
+    xb_all = 2.0 * c0 - prev.cpu().numpy() if extrap else c0
     sl = box_slice(box)
     chans = [c0[s] for s in range(S)] + [p.k[s] for s in range(S)] + [p.D[s] for s in range(S)] + \
             [p.src[s] for s in range(S)] + [p.mask.astype(np.float64)]
@@ -66,27 +69,29 @@ def _ws_pair_case(p, S, box=None):
         assert np.array_equal(got_in[..., ch], want), ch
     dom = np.zeros((gz, gy, gx), bool)
     dom[:ez, :ey, :ex] = p.mask[sl] != 0
-    # residual channels: d = (b - A c_old) / A_PP on the domain voxels, zero elsewhere,
-    # from the oracle's assembly.  The GPU forms S (S r) with S r stored in the Krylov
-    # type, so its BF16 value may differ by one unit in the last place, and r carries
-    # the cancellation error of b - A x (about 1e-15 of |b| + |A||x|) on both sides
+    # residual channels: d = (b - A x_b) / A_PP on the domain voxels, zero elsewhere,
+    # with b = c_old + q from the oracle's assembly.  The GPU forms S (S r) with S r
+    # stored in the Krylov type, so its BF16 value may differ by one unit in the last
+    # place, and r carries the cancellation error of b - A x (about 1e-15 of
+    # |b| + |A||x|) on both sides
     mb = p.mask[sl].astype(bool)
     for s in range(S):
         A, q = assemble(mb, p.D[s][sl], p.k[s][sl], p.src[s][sl], float(p.c_b[s]), p.dt, p.h)
         x = c0[s][sl][mb]
-        dvals = (x + q - A @ x) / A.diagonal()
+        xb = xb_all[s][sl][mb]
+        dvals = (x + q - A @ xb) / A.diagonal()
         scale = np.float32(in_scale[4 * S + 1 + s])
         want = np.zeros((gz, gy, gx))
         want[:ez, :ey, :ex][mb] = unet.bf16(dvals.astype(np.float32) * scale)
         got = _bf16_values(got_in[..., 4 * S + 1 + s])
         assert np.all(got[~dom] == 0.0)
-        atol = float(scale) * 1e-13 * (1.0 + np.abs(x).max() + np.abs(q).max())
+        atol = float(scale) * 1e-13 * (1.0 + np.abs(x).max() + np.abs(xb).max() + np.abs(q).max())
         assert np.all(np.abs(got - want) <= np.abs(want) * 2.0 ** -7 + atol), s
         big = np.abs(want) > 1e3 * atol     # values far above the cancellation error
         assert big.sum() > 1000 and np.mean(got[big] != want[big]) < 0.01, s
     for s in range(S):
         want = np.zeros((gz, gy, gx), np.float32)
-        full = ((c1[s] - c0[s]) / np.float64(np.float32(out_scale[s])))[sl].astype(np.float32)
+        full = ((c1[s] - xb_all[s]) / np.float64(np.float32(out_scale[s])))[sl].astype(np.float32)
         want[:ez, :ey, :ex] = full
         want[~dom] = 0.0
         assert np.array_equal(got_t[..., s], want), s
@@ -94,6 +99,12 @@ def _ws_pair_case(p, S, box=None):
 
 def test_ws_pair_matches_definition():
     _ws_pair_case(config4_patch(3, n=32), 3)
+
+
+def test_ws_pair_extrap_matches_definition():
+    """The pair of the network's correction of the extrapolated start (mpm_ws_pair_extrap):
+    the residual channels and the target are taken at 2 c^n - c^{n-1}."""
+    _ws_pair_case(config4_patch(5, n=32), 3, extrap=True)
 
 
 def test_ws_pair_matches_definition_four_species():
@@ -210,6 +221,98 @@ def test_extrapolated_start_parity():
     assert stats[3][0]["warm_start_used"] + stats[3][0]["fallback"] == 1
     # the extrapolation of a smoothly decaying field is a better start than c^n
     assert stats[3][0]["rel_res_warm"] < stats[3][0]["rel_res_initial"]
+
+
+def test_network_corrected_extrapolation_parity():
+    """MPM_WS_NET_EXTRAP with a zero correction (out_scale 0) is the extrapolated start:
+    the same fields bit for bit and the same statistics as MPM_WS_EXTRAP, no warm start
+    in the first step (no c^{n-1}), and the solve within 1e-8 of the oracle."""
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    p = config1()
+    d = to_dev(p)
+    res = {}
+    for mode in (m.MPM_WS_EXTRAP, m.MPM_WS_NET_EXTRAP):
+        f = torch.from_numpy(p.c0).cuda()
+        net = m.Net(5 * p.nspecies + 1, p.nspecies, [16, 32], seed=6) if mode == m.MPM_WS_NET_EXTRAP else None
+        with m.Solver(p.nspecies, 1, warm_start=mode) as s:
+            s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+            if net is not None:
+                s.attach(net, [1.0] * (5 * p.nspecies + 1), [0.0] * p.nspecies)
+            st = []
+            for _ in range(4):
+                s.step([f], 1e-12)
+                st.append([s.stats(0, sp) for sp in range(p.nspecies)])
+        if net is not None:
+            net.close()
+        res[mode] = (f.cpu().numpy(), st)
+    (fe, se), (fn, sn) = res[m.MPM_WS_EXTRAP], res[m.MPM_WS_NET_EXTRAP]
+    assert np.array_equal(fe, fn)
+    for a, b in zip(se, sn):
+        for x, y in zip(a, b):
+            for k in ("iterations", "warm_start_used", "fallback", "rel_res_warm", "rel_res_initial"):
+                assert x[k] == y[k], k
+    assert sn[0][0]["warm_start_used"] == 0 and sn[0][0]["fallback"] == 0
+    assert sn[3][0]["warm_start_used"] == 1
+    _check_oracle(p, 4, fn, tol=1e-12)
+
+
+def test_learned_correction_of_extrapolation():
+    """Train the network on the correction of the extrapolated start (residual loss,
+    pairs from mpm_ws_pair_extrap) and evaluate on an unseen patch: the start must be
+    accepted, leave a smaller residual than the extrapolation alone, and the solve to
+    1e-12 must match the oracle within 1e-8."""
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    from paper_2505_03067_amd import train as tr
+    train_probs = [config4_patch(200 + i, n=32) for i in range(3)]
+    raw = []
+    solvers = []
+    for pr in train_probs:
+        s, pairs = tr.solver_pairs(pr, 12, range(1, 12), [1.0, 1.0, 1.0], extrap=True)
+        raw += pairs
+        s.close()
+    out_scale = tr.target_rms(raw, 3)
+    del raw
+    items = []
+    for pr in train_probs:
+        s, pairs = tr.solver_pairs(pr, 12, range(1, 12), out_scale, extrap=True)
+        solvers.append(s)
+        items += [(s, inp, tgt) for inp, tgt in pairs]
+    net = m.Net(16, 3, [16, 32, 64, 64], seed=8)
+    rng = np.random.default_rng(1)
+    losses = []
+    for it in range(1, 301):
+        net.zero_grad()
+        losses.append(tr.residual_step(net, [items[int(rng.integers(len(items)))]], out_scale))
+        net.adam(1e-3 * 0.5 * (1 + np.cos(np.pi * it / 300)), it)
+    for s in solvers:
+        s.close()
+    print(f"{len(items)} pairs, residual loss {np.mean(losses[:10]):.3e} -> {np.mean(losses[-10:]):.3e}", flush=True)
+    p = config4_patch(10_010, n=32)
+    d = to_dev(p)
+    ratios = {}
+    fields = {}
+    for mode in (m.MPM_WS_EXTRAP, m.MPM_WS_NET_EXTRAP):
+        f = torch.from_numpy(p.c0).cuda()
+        r = []
+        with m.Solver(3, 1, warm_start=mode) as s:
+            s.setup(0, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+            if mode == m.MPM_WS_NET_EXTRAP:
+                s.attach(net, tr.input_scales(3, out_scale), out_scale)
+            for _ in range(5):
+                s.step([f], 1e-12)
+                r += [s.stats(0, sp)["rel_res_warm"] / s.stats(0, sp)["rel_res_initial"]
+                      for sp in range(3) if s.stats(0, sp)["warm_start_used"]]
+        ratios[mode] = r
+        fields[mode] = f.cpu().numpy()
+    net.close()
+    re, rn = np.mean(ratios[m.MPM_WS_EXTRAP]), np.mean(ratios[m.MPM_WS_NET_EXTRAP])
+    print(f"residual ratio: extrapolated {re:.3e}, corrected {rn:.3e} ({len(ratios[m.MPM_WS_NET_EXTRAP])} accepted)",
+          flush=True)
+    assert len(ratios[m.MPM_WS_NET_EXTRAP]) >= 6
+    assert rn < re
+    _check_oracle(p, 5, fields[m.MPM_WS_NET_EXTRAP], tol=1e-12)
 
 
 def test_learned_warm_start_gains_over_plain():
