@@ -53,6 +53,9 @@ def parse():
                     help="config4: geometries whose pairs are generated and trained on together")
     ap.add_argument("--c4-lr", type=float, default=1e-3, help="config4: Adam learning rate")
     ap.add_argument("--c4-save", default=None, help="config4: save the trained parameters and scales here")
+    ap.add_argument("--c4-base", default="cn", choices=["cn", "extrap"],
+                    help="config4: the network predicts the change from c^n (cn) or corrects the "
+                         "extrapolated start 2 c^n - c^{n-1} (extrap, MPM_WS_NET_EXTRAP)")
     ap.add_argument("--c4-loss", default="residual", choices=["residual", "mse"],
                     help="config4: train on the Jacobi-scaled residual each prediction leaves (mpm_ws_loss), "
                          "or on the mean squared error of the predicted change")
@@ -615,6 +618,7 @@ def config4_run(args, m, torch):
     from paper_2505_03067_amd import train as tr
     from synth import config4_patch
     S = 3
+    extrap = args.c4_base == "extrap"
     t0 = time.perf_counter()
     net = m.Net(5 * S + 1, S, [16, 32, 64, 64], seed=7)
     rng = np.random.default_rng(0)
@@ -624,6 +628,16 @@ def config4_run(args, m, torch):
         net.set_params(saved["params"].cuda())
         out_scale = list(saved["out_scale"])
         args.c4_epochs = 0
+    elif extrap:
+        # target scale: per-species RMS of the correction the extrapolated start needs, on
+        # four training geometries
+        raw = []
+        for seed in range(4):
+            sv, items = tr.solver_pairs(config4_patch(seed, 64), 10, range(1, 10), [1.0] * S, tol=1e-10, extrap=True)
+            raw += items
+            sv.close()
+        out_scale = tr.target_rms(raw, S)
+        del raw
     else:
         # target scale: per-species RMS of the one-step change on four training geometries
         out_scale = tr.estimate_out_scale([config4_patch(seed, 64) for seed in range(4)], 10)
@@ -639,8 +653,9 @@ def config4_run(args, m, torch):
             for seed in order[c0:c0 + args.c4_chunk]:
                 seed = int(seed)
                 pick = set(np.random.default_rng(seed).choice(50, size=args.c4_pairs, replace=False).tolist())
-                if args.c4_loss == "residual":
-                    sv, items = tr.solver_pairs(config4_patch(seed, 64), 50, pick, out_scale, tol=1e-10)
+                if args.c4_loss == "residual" or extrap:
+                    sv, items = tr.solver_pairs(config4_patch(seed, 64), 50, pick, out_scale, tol=1e-10,
+                                                extrap=extrap)
                     solvers.append(sv)
                     pairs += [(sv, inp, tgt) for inp, tgt in items]
                 else:
@@ -681,14 +696,14 @@ def config4_run(args, m, torch):
     pairs = None
     if args.c4_save:
         torch.save({"params": net.params().cpu(), "out_scale": list(out_scale), "widths": [16, 32, 64, 64],
-                    "in_ch": 5 * S + 1, "out_ch": S}, args.c4_save)
+                    "in_ch": 5 * S + 1, "out_ch": S, "base": args.c4_base}, args.c4_save)
     del pairs
     evalp = [config4_patch(10 ** 6 + i, 128) for i in range(args.c4_eval)]
     tol = args.tol if args.tol is not None else 1e-8
     res = {}
     for name, warm, prec in (("plain", m.MPM_WS_NONE, m.MPM_FP32_IR), ("plain_fp64", m.MPM_WS_NONE, m.MPM_FP64),
                              ("extrapolated", m.MPM_WS_EXTRAP, m.MPM_FP32_IR),
-                             ("learned", m.MPM_WS_NET, m.MPM_FP32_IR)):
+                             ("learned", m.MPM_WS_NET_EXTRAP if extrap else m.MPM_WS_NET, m.MPM_FP32_IR)):
         ratios = []
         its, sps, _, acc = tr.evaluate(evalp, 20, tol, net=net, out_scale=out_scale, warm=warm, precision=prec,
                                        ratios=ratios)
@@ -711,7 +726,8 @@ def config4_run(args, m, torch):
         "dtype": "f32+f64, bf16 network",
         "data": "synthetic",
         "config": {
-            "workload": f"config4: learned warm start, trained on {args.c4_geometries} x {args.c4_pairs} pairs of "
+            "workload": f"config4: learned warm start ({'correction of the extrapolation' if extrap else 'from c^n'}), "
+                        f"trained on {args.c4_geometries} x {args.c4_pairs} pairs of "
                         f"64^3 tumour patches ({args.c4_epochs} epochs), evaluated on {args.c4_eval} unseen 128^3 "
                         f"boxes x 20 steps at tol {tol:g}; value = steps/s with the learned start",
         },
@@ -722,6 +738,8 @@ def config4_run(args, m, torch):
             "extrapolated_over_plain": round(res["extrapolated"]["steps_per_s"] / res["plain"]["steps_per_s"], 3),
             "training": {"pairs_per_epoch": npairs, "epochs": args.c4_epochs, "batch": 4, "lr": args.c4_lr,
                          "loss": args.c4_loss,
+                         "base": ("the network corrects the extrapolated start 2 c^n - c^{n-1} (MPM_WS_NET_EXTRAP)"
+                                  if extrap else "the network predicts the change from c^n (MPM_WS_NET)"),
                          "streamed": f"pairs of {args.c4_chunk} geometries at a time, regenerated on the GPU "
                                      f"from their seeds every epoch",
                          "generation_s": round(gen_s, 1), "training_s": round(train_s, 1),
