@@ -310,7 +310,7 @@ __device__ inline void conv_fetch(const ConvArgs& a, const ConvTile& t, int cb, 
         for (int i = 0; i < kXM; ++i) {
             const int p = conv_halo_word(i);
             if (p < 0) continue;
-            const int hx = p & 31, hy = (p >> 5) & 7, hz = (p >> 8) & 7, gi = p >> 11;
+            const int hx = p & 31, hy = (p >> 5) & 7, hz = (p >> 8) & 7;
             if ((unsigned)(t.x0 - 1 + hx) < (unsigned)a.W && (unsigned)(t.y0 - 1 + hy) < (unsigned)a.H &&
                 (unsigned)(t.z0 - 1 + hz) < (unsigned)a.D) {
                 const unsigned o = XCAT && up ? ln.offh[XCAT ? i : 0] : ln.off[i];
