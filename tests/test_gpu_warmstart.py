@@ -257,6 +257,37 @@ def test_network_corrected_extrapolation_parity():
     _check_oracle(p, 4, fn, tol=1e-12)
 
 
+def test_network_corrected_extrapolation_two_problems_four_species():
+    """Two problems of four species in one context: with a zero correction the network's
+    mode reproduces the extrapolated start bit for bit for both, and both match the
+    oracle."""
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    probs = [random_problem(94, (22, 20, 18), S=4, fill=0.7), random_problem(95, (18, 24, 20), S=4, fill=0.6)]
+    res = {}
+    for mode in (m.MPM_WS_EXTRAP, m.MPM_WS_NET_EXTRAP):
+        fs = [torch.from_numpy(p.c0).cuda() for p in probs]
+        net = m.Net(21, 4, [16, 32], seed=9) if mode == m.MPM_WS_NET_EXTRAP else None
+        with m.Solver(4, 2, warm_start=mode) as s:
+            for i, p in enumerate(probs):
+                d = to_dev(p)
+                s.setup(i, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+            if net is not None:
+                s.attach(net, [1.0] * 21, [0.0] * 4)
+            used = 0
+            for _ in range(3):
+                s.step(fs, 1e-12)
+                used += sum(s.stats(i, sp)["warm_start_used"] for i in range(2) for sp in range(4))
+        if net is not None:
+            net.close()
+        res[mode] = ([f.cpu().numpy() for f in fs], used)
+    for a, b in zip(res[m.MPM_WS_EXTRAP][0], res[m.MPM_WS_NET_EXTRAP][0]):
+        assert np.array_equal(a, b)
+    assert res[m.MPM_WS_EXTRAP][1] == res[m.MPM_WS_NET_EXTRAP][1]
+    for p, f in zip(probs, res[m.MPM_WS_NET_EXTRAP][0]):
+        _check_oracle(p, 3, f, tol=1e-12)
+
+
 def test_learned_correction_of_extrapolation():
     """Train the network on the correction of the extrapolated start (residual loss,
     pairs from mpm_ws_pair_extrap) and evaluate on an unseen patch: the start must be
