@@ -350,9 +350,13 @@ extern "C" int32_t mpm_tile(mpm_ctx ctx, int32_t* out) {
 
 static int set_scales(Ctx* c, const float* in_scale, const float* out_scale) {
     const int cin = ws_channels(c->S);
-    for (int i = 0; i < kScaleCount; ++i) c->h_scales[i] = 0.f;
-    for (int i = 0; i < cin; ++i) c->h_scales[i] = in_scale[i];
-    for (int s = 0; s < c->S; ++s) c->h_scales[kScaleOut + s] = out_scale[s];
+    float h[kScaleCount] = {};
+    for (int i = 0; i < cin; ++i) h[i] = in_scale[i];
+    for (int s = 0; s < c->S; ++s) h[kScaleOut + s] = out_scale[s];
+    // new values: the network input buffers are built again in full at the next warm start
+    if (!c->have_scales || std::memcmp(h, c->h_scales, sizeof(h)) != 0)
+        for (auto& ph : c->probs) ph.ws_ready = false;
+    std::memcpy(c->h_scales, h, sizeof(h));
     MPM_HIP(hipMemcpy(c->d_scales, c->h_scales, kScaleCount * sizeof(float), hipMemcpyHostToDevice));
     c->have_scales = true;
     return MPM_OK;

@@ -1377,26 +1377,41 @@ __device__ inline uint16_t to_bf16(float f) {
 // Network input on the box grid of problem p: channels [c (S), k (S), D (S), s (S), mask,
 // d (S)], each multiplied by its scale, BF16; zero on grid voxels beyond the box.  c is
 // read from the lattice field; k, D, s and the mask come from the static channels; the
-// channels d (the Jacobi-scaled residual of c^n) are written as zero here and filled on
-// the domain voxels by k_ws_resid.
-__global__ void k_ws_input(ProbDev pd, int S, int bx, int by, int bz, const double* field, const float* stat,
-                           const float* scales, uint16_t* in) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long G = (long long)pd.gd[0] * pd.gd[1] * pd.gd[2];
-    if (i >= G) return;
+// channels d (the Jacobi-scaled residual of the base start) are written as zero here and
+// filled on the domain voxels by k_ws_resid.  With full = 0 only the c channels of the
+// box's voxels are written: every other value of the buffer is already this input's
+// (a full build on the same grid, domain and scales, after which k_ws_resid writes d
+// on the domain voxels only).  Threads (64, 4) over (x, y) of one z plane per block
+// row; the launch covers the grid (full) or the box.
+__global__ __launch_bounds__(256) void k_ws_input(ProbDev pd, int S, int bx, int by, int bz, const double* field,
+                                                  const float* stat, const float* scales, uint16_t* in, int full) {
     const int gx = pd.gd[0], gy = pd.gd[1];
-    const int x = (int)(i % gx);
-    const int y = (int)((i / gx) % gy);
-    const int z = (int)(i / ((long long)gx * gy));
-    const int C = ws_channels(S);
+    const int x = (int)blockIdx.x * 64 + (int)threadIdx.x;
+    const int y = (int)blockIdx.y * 4 + (int)threadIdx.y;
+    const int z = (int)blockIdx.z;
+    if (x >= gx || y >= gy) return;
     const bool inbox = x < bx && y < by && z < bz;
-    const float* st = stat + i * ws_static_channels(S);
+    if (!full && !inbox) return;
+    const long long i = ((long long)z * gy + y) * gx + x;
+    const int C = ws_channels(S);
     const long long v = ((long long)(pd.lo[2] + z) * pd.ny + (pd.lo[1] + y)) * pd.nx + (pd.lo[0] + x);
     uint16_t val[ws_channels(MPM_MAX_SPECIES)];
     for (int s = 0; s < S; ++s) {
         const float cv = inbox ? (float)field[s * pd.nvox + v] : 0.f;
         val[s] = to_bf16(cv * scales[s]);
     }
+    if (!full) {
+        uint16_t* o = in + i * C;
+        if (C % 2 == 0) {   // even channel count: 4-byte aligned voxel records
+            int s = 0;
+            for (; s + 1 < S; s += 2) *reinterpret_cast<uint32_t*>(o + s) = val[s] | ((uint32_t)val[s + 1] << 16);
+            if (s < S) o[s] = val[s];
+        } else {
+            for (int s = 0; s < S; ++s) o[s] = val[s];
+        }
+        return;
+    }
+    const float* st = stat + i * ws_static_channels(S);
     for (int c = 0; c < ws_static_channels(S); ++c) val[S + c] = to_bf16(st[c] * scales[S + c]);
     for (int c = 4 * S + 1; c < C; ++c) val[c] = 0;
     if (C % 8 == 0 && ((uintptr_t)in & 15) == 0) {   // three species: 16 channels, two 16-byte stores
@@ -1409,6 +1424,15 @@ __global__ void k_ws_input(ProbDev pd, int S, int bx, int by, int bz, const doub
     } else {
         for (int c = 0; c < C; ++c) in[i * C + c] = val[c];
     }
+}
+
+// Launch k_ws_input for problem p over its grid (full) or its box.
+static void launch_ws_input(const ProbHost& ph, const ProbDev& pd, int S, const double* field, const float* scales,
+                            uint16_t* in, bool full, hipStream_t st) {
+    const int bx = ph.hi[0] - ph.lo[0], by = ph.hi[1] - ph.lo[1], bz = ph.hi[2] - ph.lo[2];
+    const int ex = full ? ph.gd[0] : bx, ey = full ? ph.gd[1] : by, ez = full ? ph.gd[2] : bz;
+    const dim3 grid((unsigned)((ex + 63) / 64), (unsigned)((ey + 3) / 4), (unsigned)ez);
+    k_ws_input<<<grid, dim3(64, 4), 0, st>>>(pd, S, bx, by, bz, field, ph.stat, scales, in, full ? 1 : 0);
 }
 
 // Grid index of compact voxel l of a problem.
@@ -1433,14 +1457,23 @@ __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, con
     const ProbDev pd = a.probs[blk.sys / a.S];
     const Where wh = where_of(a, blk, pd);
     const float os = scales[kScaleOut + wh.s];
-    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
-        const int l = (int)(u - wh.base);
-        if (l >= pd.N) continue;
-        if (mode == MPM_WS_NET) {
-            a.x[u] += (double)(pd.wsout[grid_index(pd, l) * a.S + wh.s] * os);
-        } else {
-            a.x[u] = 2.0 * a.x[u] - pd.prev[u];
+    // four unknowns per thread, every load issued before the first use
+    constexpr int n = 4;
+    for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
+        const int l0 = (int)(u0 - wh.base);
+        double xv[n], w[n];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            const bool in = l0 + e < pd.N;
+            xv[e] = in ? a.x[u0 + e] : 0.0;
+            if (mode == MPM_WS_NET)
+                w[e] = in ? (double)(pd.wsout[grid_index(pd, l0 + e) * a.S + wh.s] * os) : 0.0;
+            else
+                w[e] = in ? pd.prev[u0 + e] : 0.0;
         }
+#pragma unroll
+        for (int e = 0; e < n; ++e)
+            if (l0 + e < pd.N) a.x[u0 + e] = mode == MPM_WS_NET ? xv[e] + w[e] : 2.0 * xv[e] - w[e];
     }
 }
 
@@ -1457,11 +1490,23 @@ __global__ __launch_bounds__(kThreads) void k_ws_resid(KArgs<T> a, int p, const 
     const int C = ws_channels(a.S);
     const int ch = 4 * a.S + 1 + wh.s;
     const float scale = scales[ch];
-    for (long long u = blk.start + threadIdx.x; u < blk.end; u += kThreads) {
-        const int l = (int)(u - wh.base);
-        if (l >= pd.N) continue;
-        const double d = pd.sc64[wh.locbase + l] * (double)a.V[u];
-        dst[grid_index(pd, l) * C + ch] = to_bf16((float)d * scale);
+    constexpr int n = 4;
+    for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
+        const int l0 = (int)(u0 - wh.base);
+        double sv[n];
+        T vv[n];
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            const bool in = l0 + e < pd.N;
+            sv[e] = in ? pd.sc64[wh.locbase + l0 + e] : 0.0;
+            vv[e] = in ? a.V[u0 + e] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < n; ++e) {
+            if (l0 + e >= pd.N) continue;
+            const double d = sv[e] * (double)vv[e];
+            dst[grid_index(pd, l0 + e) * C + ch] = to_bf16((float)d * scale);
+        }
     }
 }
 
@@ -2375,7 +2420,7 @@ static int warm_start(Ctx* c, hipStream_t st) {
         hipStream_t saved = c->net->stream;
         c->net->stream = st;
         for (int p = 0; p < c->P; ++p) {
-            const ProbHost& ph = c->probs[p];
+            ProbHost& ph = c->probs[p];
             const ProbDev& pd = c->h_probs[p];
             const long long G = (long long)ph.gd[0] * ph.gd[1] * ph.gd[2];
             if (G <= 0 || (size_t)G > ph.cap_grid || !ph.wsin || !ph.wsout || !ph.stat) {
@@ -2383,9 +2428,15 @@ static int warm_start(Ctx* c, hipStream_t st) {
                 set_error("warm start: the network buffers of a problem do not cover its grid");
                 return MPM_ESTATE;
             }
-            k_ws_input<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, ph.hi[0] - ph.lo[0], ph.hi[1] - ph.lo[1],
-                                                                  ph.hi[2] - ph.lo[2], c->h_fields[p], ph.stat,
-                                                                  c->d_scales, ph.wsin);
+            // the first build on this grid, domain and scales writes every channel, later
+            // ones only c (the buffer keeps the rest)
+            launch_ws_input(ph, pd, c->S, c->h_fields[p], c->d_scales, ph.wsin, !ph.ws_ready, st);
+            const hipError_t le = hipGetLastError();
+            if (le != hipSuccess) {
+                c->net->stream = saved;
+                return hip_fail(le, "warm start (network input)");
+            }
+            ph.ws_ready = true;
             k_ws_resid<T><<<nb, kThreads, 0, st>>>(a, p, c->d_scales, ph.wsin);
             int rc = net_forward(c->net, ph.wsin, 1, ph.gd[2], ph.gd[1], ph.gd[0], ph.wsout);
             if (rc != MPM_OK) {
@@ -2726,8 +2777,7 @@ int ws_pair(Ctx* c, int p, const double* c_prev, const double* c_old, const doub
     c->up_valid = false;
     rc = ksize(c) == 8 ? ws_first_residual<double>(c, p, c_prev, c_old) : ws_first_residual<float>(c, p, c_prev, c_old);
     if (rc == MPM_OK) {
-        k_ws_input<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_old, ph.stat, c->d_scales,
-                                                              in_bf16);
+        launch_ws_input(ph, pd, c->S, c_old, c->d_scales, in_bf16, true, st);
         const unsigned nb = (unsigned)c->blocks.size();
         if (ksize(c) == 8) k_ws_resid<double><<<nb, kThreads, 0, st>>>(make_args<double>(c, c->d_blocks), p, c->d_scales, in_bf16);
         else k_ws_resid<float><<<nb, kThreads, 0, st>>>(make_args<float>(c, c->d_blocks), p, c->d_scales, in_bf16);

@@ -494,6 +494,7 @@ static int discretise(Ctx* c, ProbHost& ph, const BoxGeo& g, const uint8_t* mask
         ph.gd[0] = gx;
         ph.gd[1] = gy;
         ph.gd[2] = gz;
+        ph.ws_ready = false;
         k_ws_static<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(mask, D, k, src, g, gx, gy, gz, c->S, ca.nvox,
                                                               ph.stat);
     }

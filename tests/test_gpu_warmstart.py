@@ -115,6 +115,57 @@ def test_ws_pair_matches_definition_four_species():
     _ws_pair_case(p, 4, box=((2, 3, 1), (27, 26, 18)))
 
 
+@pytest.mark.parametrize("S,extrap", [(3, False), (3, True), (4, False)])
+def test_in_step_input_matches_ws_pair(S, extrap):
+    """The network input a warm-start step builds equals, bit for bit, the one
+    mpm_ws_pair builds from the same state (itself pinned to the definition above): the
+    first warm start on a grid writes every channel, later ones only the c channels of
+    the box, and new scales or new coefficients must bring back a full build.  A ragged
+    box whose grid is padded past it on every axis; 16 (read in place) and 21 channels."""
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    from paper_2505_03067_amd import mpm as mpm_mod
+    from paper_2505_03067_amd.train import input_scales
+    p = random_problem(97 + S, (30, 27, 21), S=S, fill=0.7)
+    box = ((2, 3, 1), (27, 26, 18))
+    d = to_dev(p)
+    out_scale = [0.5, 0.25, 2e-3, 3e-3][:S]
+    scales = [input_scales(S, out_scale), [v * 1.5 for v in input_scales(S, out_scale)]]
+    C = 5 * S + 1
+    net = m.Net(C, S, [16, 32], seed=11)
+    f = torch.from_numpy(p.c0).cuda()
+    checked = 0
+    with m.Solver(S, 1, warm_start=m.MPM_WS_NET_EXTRAP if extrap else m.MPM_WS_NET) as s:
+        s.setup(0, box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+        gx, gy, gz = s.ws_grid(0)
+        cur = scales[0]
+        s.attach(net, cur, out_scale)
+        prev = None
+        for n in range(7):
+            if n == 3:                      # new input scales
+                cur = scales[1]
+                s.attach(net, cur, out_scale)
+            if n == 5:                      # new coefficients on the same box
+                s.update(0, d["mask"], d["D"], d["k"] * 1.25, d["src"], p.c_b, p.dt, p.h)
+            old = f.clone()
+            s.step([f], 1e-10)
+            if extrap and prev is None:     # no c^{n-1} yet: no warm start this step
+                prev = old
+                continue
+            got = net.debug_tensor(mpm_mod.MPM_NT_INPUT).cpu().numpy().view(np.uint16)
+            got = got.reshape(gz, gy, gx, -1)[..., :C]
+            inp = torch.empty((gz, gy, gx, C), dtype=torch.int16, device="cuda")
+            tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
+            s.ws_pair(0, old, f, cur, out_scale, inp, tgt, c_prev=prev if extrap else None)
+            want = inp.cpu().numpy().view(np.uint16)
+            for ch in range(C):
+                assert np.array_equal(got[..., ch], want[..., ch]), (n, ch)
+            checked += 1
+            prev = old
+    net.close()
+    assert checked == (6 if extrap else 7)
+
+
 def test_four_species_network_attaches_and_falls_back():
     """A 21-channel network on a four-species context: the zero prediction is rejected
     for every system and the solve matches the oracle."""
