@@ -270,6 +270,12 @@ int32_t mpm_net_write(mpm_net net, int32_t what, const float* src);
  * a multiple of 16 the input is read in place, so it must stay unchanged until the
  * backward pass; otherwise it is copied into a padded buffer. */
 int32_t mpm_net_forward(mpm_net net, const uint16_t* in, int32_t n, int32_t d, int32_t h, int32_t w, float* out);
+/* The same forward pass for inference (what the warm start runs): out is bit for bit
+ * that of mpm_net_forward, but when the last 3x3x3 layer maps 16 channels to 16 the
+ * head runs in its epilogue and that layer's output is not stored, so no
+ * mpm_net_backward may follow (MPM_ESTATE) until the next mpm_net_forward.  Arguments
+ * and errors as mpm_net_forward. */
+int32_t mpm_net_infer(mpm_net net, const uint16_t* in, int32_t n, int32_t d, int32_t h, int32_t w, float* out);
 /* Accumulate parameter gradients for dL/d(out) = grad_out (device FP32, shape of out). */
 int32_t mpm_net_backward(mpm_net net, const float* grad_out);
 int32_t mpm_net_zero_grad(mpm_net net);
@@ -342,10 +348,11 @@ int32_t mpm_net_debug_op(mpm_net net, int32_t op, int32_t n, int32_t d, int32_t 
 /* Use 'net' (in_ch = 5 S + 1, out_ch = S) as the warm start of a context created with
  * warm_start = MPM_WS_NET or MPM_WS_NET_EXTRAP; net = NULL detaches.  Network input on
  * the box grid (box sizes rounded up to multiples of 8, zero beyond the box), each
- * channel times in_scale[ch] (host, exactly 5 S + 1 floats are read): c^n (S), k (S),
- * D (S), s (S), the mask, and the Jacobi-scaled residual d = (b - A x_b) / A_PP of the
- * base start x_b (S; zero off the domain), the first Jacobi correction of x_b, computed
- * with the step's own residual kernel.  The base start is c^n (MPM_WS_NET) or the
+ * channel times in_scale[ch] (host, exactly 5 S + 1 floats are read): c^n (S; zero off
+ * the domain, which the solve never reads), k (S), D (S), s (S), the mask, and the
+ * Jacobi-scaled residual d = (b - A x_b) / A_PP of the base start x_b (S; zero off the
+ * domain), the first Jacobi correction of x_b, computed with the step's own residual
+ * kernel.  The base start is c^n (MPM_WS_NET) or the
  * extrapolation 2 c^n - c^{n-1} (MPM_WS_NET_EXTRAP, from the second step of the context
  * on).  The prediction of species s is output * out_scale[s] (host, S floats read)
  * added to x_b.  Each step keeps the prediction of a system only if its true residual

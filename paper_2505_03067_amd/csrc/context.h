@@ -47,8 +47,9 @@ struct ProbHost {
     uint16_t* wsin = nullptr;  // BF16 network input [G][ws_channels(S)]
     float* wsout = nullptr;    // network output [G][S]
     size_t cap_grid = 0;       // grid voxels the three buffers above hold
-    bool ws_ready = false;     // wsin holds every channel but c for the current grid,
-                               // domain and scales (cleared by a set-up and new scales)
+    bool ws_ready = false;     // wsin holds the static channels (and zero c and d off the
+                               // domain) of the current grid, domain and scales (cleared
+                               // by a set-up and by new scales)
 };
 
 // What a tuning result is kept for: species, basis word size, orthogonalisation,

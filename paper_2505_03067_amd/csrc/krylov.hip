@@ -1375,43 +1375,23 @@ __device__ inline uint16_t to_bf16(float f) {
 }
 
 // Network input on the box grid of problem p: channels [c (S), k (S), D (S), s (S), mask,
-// d (S)], each multiplied by its scale, BF16; zero on grid voxels beyond the box.  c is
-// read from the lattice field; k, D, s and the mask come from the static channels; the
-// channels d (the Jacobi-scaled residual of the base start) are written as zero here and
-// filled on the domain voxels by k_ws_resid.  With full = 0 only the c channels of the
-// box's voxels are written: every other value of the buffer is already this input's
-// (a full build on the same grid, domain and scales, after which k_ws_resid writes d
-// on the domain voxels only).  Threads (64, 4) over (x, y) of one z plane per block
-// row; the launch covers the grid (full) or the box.
-__global__ __launch_bounds__(256) void k_ws_input(ProbDev pd, int S, int bx, int by, int bz, const double* field,
-                                                  const float* stat, const float* scales, uint16_t* in, int full) {
+// d (S)], each multiplied by its scale, BF16.  This kernel writes the static channels
+// (k, D, s and the mask, zero beyond the box) and zero c and d channels; k_ws_resid
+// writes c and d on the domain voxels, so that only it runs again while the grid,
+// domain and scales stay the same.  Threads (64, 4) over (x, y) of one z plane per
+// block row.
+__global__ __launch_bounds__(256) void k_ws_input(ProbDev pd, int S, const float* stat, const float* scales,
+                                                  uint16_t* in) {
     const int gx = pd.gd[0], gy = pd.gd[1];
     const int x = (int)blockIdx.x * 64 + (int)threadIdx.x;
     const int y = (int)blockIdx.y * 4 + (int)threadIdx.y;
     const int z = (int)blockIdx.z;
     if (x >= gx || y >= gy) return;
-    const bool inbox = x < bx && y < by && z < bz;
-    if (!full && !inbox) return;
     const long long i = ((long long)z * gy + y) * gx + x;
     const int C = ws_channels(S);
-    const long long v = ((long long)(pd.lo[2] + z) * pd.ny + (pd.lo[1] + y)) * pd.nx + (pd.lo[0] + x);
     uint16_t val[ws_channels(MPM_MAX_SPECIES)];
-    for (int s = 0; s < S; ++s) {
-        const float cv = inbox ? (float)field[s * pd.nvox + v] : 0.f;
-        val[s] = to_bf16(cv * scales[s]);
-    }
-    if (!full) {
-        uint16_t* o = in + i * C;
-        if (C % 2 == 0) {   // even channel count: 4-byte aligned voxel records
-            int s = 0;
-            for (; s + 1 < S; s += 2) *reinterpret_cast<uint32_t*>(o + s) = val[s] | ((uint32_t)val[s + 1] << 16);
-            if (s < S) o[s] = val[s];
-        } else {
-            for (int s = 0; s < S; ++s) o[s] = val[s];
-        }
-        return;
-    }
-    const float* st = stat + i * ws_static_channels(S);
+    for (int s = 0; s < S; ++s) val[s] = 0;
+    const float* st = stat + i * ws_static_channels(S);   // zero beyond the box
     for (int c = 0; c < ws_static_channels(S); ++c) val[S + c] = to_bf16(st[c] * scales[S + c]);
     for (int c = 4 * S + 1; c < C; ++c) val[c] = 0;
     if (C % 8 == 0 && ((uintptr_t)in & 15) == 0) {   // three species: 16 channels, two 16-byte stores
@@ -1426,18 +1406,15 @@ __global__ __launch_bounds__(256) void k_ws_input(ProbDev pd, int S, int bx, int
     }
 }
 
-// Launch k_ws_input for problem p over its grid (full) or its box.
-static void launch_ws_input(const ProbHost& ph, const ProbDev& pd, int S, const double* field, const float* scales,
-                            uint16_t* in, bool full, hipStream_t st) {
-    const int bx = ph.hi[0] - ph.lo[0], by = ph.hi[1] - ph.lo[1], bz = ph.hi[2] - ph.lo[2];
-    const int ex = full ? ph.gd[0] : bx, ey = full ? ph.gd[1] : by, ez = full ? ph.gd[2] : bz;
-    const dim3 grid((unsigned)((ex + 63) / 64), (unsigned)((ey + 3) / 4), (unsigned)ez);
-    k_ws_input<<<grid, dim3(64, 4), 0, st>>>(pd, S, bx, by, bz, field, ph.stat, scales, in, full ? 1 : 0);
+// Launch k_ws_input over the grid of problem p.
+static void launch_ws_input(const ProbHost& ph, const ProbDev& pd, int S, const float* scales, uint16_t* in,
+                            hipStream_t st) {
+    const dim3 grid((unsigned)((ph.gd[0] + 63) / 64), (unsigned)((ph.gd[1] + 3) / 4), (unsigned)ph.gd[2]);
+    k_ws_input<<<grid, dim3(64, 4), 0, st>>>(pd, S, ph.stat, scales, in);
 }
 
-// Grid index of compact voxel l of a problem.
-__device__ inline long long grid_index(const ProbDev& pd, int l) {
-    const int v = pd.vox[l];
+// Grid index of lattice voxel v of a problem's box.
+__device__ inline long long grid_of_voxel(const ProbDev& pd, int v) {
     const int plane = pd.nx * pd.ny;
     const int z = v / plane;
     const int rem = v - z * plane;
@@ -1445,6 +1422,9 @@ __device__ inline long long grid_index(const ProbDev& pd, int l) {
     const int x = rem - y * pd.nx;
     return ((long long)(z - pd.lo[2]) * pd.gd[1] + (y - pd.lo[1])) * pd.gd[0] + (x - pd.lo[0]);
 }
+
+// Grid index of compact voxel l of a problem.
+__device__ inline long long grid_index(const ProbDev& pd, int l) { return grid_of_voxel(pd, pd.vox[l]); }
 
 // For the systems not already converged at c^n: x += out * out_scale (network; x holds
 // the base start) or x = 2 x - c^{n-1} (extrapolation; x holds c^n).
@@ -1477,35 +1457,45 @@ __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, con
     }
 }
 
-// Jacobi-scaled residual of the base start, d = r / A_PP = S (S r), on the domain voxels
-// of problem p into channel 4 S + 1 + s of the network input dst (times its scale,
-// BF16).  V holds S r from the residual of the base start (c^n: the step's first
-// residual; the extrapolation: its own), before any Arnoldi step overwrites it.
+// The per-step channels of the network input on the domain voxels of problem p, each
+// times its scale, BF16: c^n (channel s, from the lattice field) and the Jacobi-scaled
+// residual of the base start, d = r / A_PP = S (S r) (channel 4 S + 1 + s).  V holds
+// S r from the residual of the base start (c^n: the step's first residual; the
+// extrapolation: its own), before any Arnoldi step overwrites it.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_ws_resid(KArgs<T> a, int p, const float* scales, uint16_t* dst) {
+__global__ __launch_bounds__(kThreads) void k_ws_resid(KArgs<T> a, int p, const double* field, const float* scales,
+                                                       uint16_t* dst) {
     const Block blk = a.blocks[blockIdx.x];
     if (blk.sys < 0 || blk.p != p) return;
     const ProbDev pd = a.probs[p];
     const Where wh = where_of(a, blk, pd);
     const int C = ws_channels(a.S);
     const int ch = 4 * a.S + 1 + wh.s;
-    const float scale = scales[ch];
+    const float scale = scales[ch], cscale = scales[wh.s];
+    const double* f = field + (long long)wh.s * pd.nvox;
+    // four unknowns per thread, every load issued before the first use
     constexpr int n = 4;
     for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
         const int l0 = (int)(u0 - wh.base);
-        double sv[n];
+        int vx[n];
+        double sv[n], cv[n];
         T vv[n];
 #pragma unroll
         for (int e = 0; e < n; ++e) {
             const bool in = l0 + e < pd.N;
+            vx[e] = in ? pd.vox[l0 + e] : 0;
             sv[e] = in ? pd.sc64[wh.locbase + l0 + e] : 0.0;
             vv[e] = in ? a.V[u0 + e] : T(0);
         }
 #pragma unroll
+        for (int e = 0; e < n; ++e) cv[e] = l0 + e < pd.N ? f[vx[e]] : 0.0;
+#pragma unroll
         for (int e = 0; e < n; ++e) {
             if (l0 + e >= pd.N) continue;
             const double d = sv[e] * (double)vv[e];
-            dst[grid_index(pd, l0 + e) * C + ch] = to_bf16((float)d * scale);
+            uint16_t* o = dst + grid_of_voxel(pd, vx[e]) * C;
+            o[ch] = to_bf16((float)d * scale);
+            o[wh.s] = to_bf16((float)cv[e] * cscale);
         }
     }
 }
@@ -2428,17 +2418,18 @@ static int warm_start(Ctx* c, hipStream_t st) {
                 set_error("warm start: the network buffers of a problem do not cover its grid");
                 return MPM_ESTATE;
             }
-            // the first build on this grid, domain and scales writes every channel, later
-            // ones only c (the buffer keeps the rest)
-            launch_ws_input(ph, pd, c->S, c->h_fields[p], c->d_scales, ph.wsin, !ph.ws_ready, st);
-            const hipError_t le = hipGetLastError();
-            if (le != hipSuccess) {
-                c->net->stream = saved;
-                return hip_fail(le, "warm start (network input)");
+            // the static channels once per grid, domain and scales; c and d every step
+            if (!ph.ws_ready) {
+                launch_ws_input(ph, pd, c->S, c->d_scales, ph.wsin, st);
+                const hipError_t le = hipGetLastError();
+                if (le != hipSuccess) {
+                    c->net->stream = saved;
+                    return hip_fail(le, "warm start (network input)");
+                }
+                ph.ws_ready = true;
             }
-            ph.ws_ready = true;
-            k_ws_resid<T><<<nb, kThreads, 0, st>>>(a, p, c->d_scales, ph.wsin);
-            int rc = net_forward(c->net, ph.wsin, 1, ph.gd[2], ph.gd[1], ph.gd[0], ph.wsout);
+            k_ws_resid<T><<<nb, kThreads, 0, st>>>(a, p, c->h_fields[p], c->d_scales, ph.wsin);
+            int rc = net_forward(c->net, ph.wsin, 1, ph.gd[2], ph.gd[1], ph.gd[0], ph.wsout, true);
             if (rc != MPM_OK) {
                 c->net->stream = saved;
                 return rc;
@@ -2777,10 +2768,14 @@ int ws_pair(Ctx* c, int p, const double* c_prev, const double* c_old, const doub
     c->up_valid = false;
     rc = ksize(c) == 8 ? ws_first_residual<double>(c, p, c_prev, c_old) : ws_first_residual<float>(c, p, c_prev, c_old);
     if (rc == MPM_OK) {
-        launch_ws_input(ph, pd, c->S, c_old, c->d_scales, in_bf16, true, st);
+        launch_ws_input(ph, pd, c->S, c->d_scales, in_bf16, st);
         const unsigned nb = (unsigned)c->blocks.size();
-        if (ksize(c) == 8) k_ws_resid<double><<<nb, kThreads, 0, st>>>(make_args<double>(c, c->d_blocks), p, c->d_scales, in_bf16);
-        else k_ws_resid<float><<<nb, kThreads, 0, st>>>(make_args<float>(c, c->d_blocks), p, c->d_scales, in_bf16);
+        if (ksize(c) == 8)
+            k_ws_resid<double><<<nb, kThreads, 0, st>>>(make_args<double>(c, c->d_blocks), p, c_old, c->d_scales,
+                                                        in_bf16);
+        else
+            k_ws_resid<float><<<nb, kThreads, 0, st>>>(make_args<float>(c, c->d_blocks), p, c_old, c->d_scales,
+                                                       in_bf16);
         k_ws_target<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(pd, c->S, bx, by, bz, c_prev, c_old, c_new,
                                                                ph.stat, c->d_scales, target);
     }

@@ -41,6 +41,7 @@ struct Net {
     size_t dpart_cap = 0;
     float* outbuf = nullptr;
     bool have_fwd = false;
+    bool fwd_infer = false;            // the last forward pass was an inference pass
     // warm-start use
     double* mse_part = nullptr;        // pinned host copy of the MSE partial sums
     double* mse_dev = nullptr;         // device partial sums of the MSE
@@ -49,7 +50,9 @@ struct Net {
 int net_build(Net* n, int in_ch, int out_ch, int levels, const int* widths, uint64_t seed);
 int net_pack(Net* n);
 void net_free(Net* n);
-int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out);
+// infer: an inference pass (the head fused into the last convolution where the widths
+// allow; no backward pass may follow)
+int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out, bool infer);
 int net_backward(Net* n, const float* dout);
 
 }  // namespace mpm

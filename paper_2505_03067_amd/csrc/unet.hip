@@ -178,9 +178,9 @@ static int ensure_acts(Net* n, int nb, int D, int H, int W) {
 // a multiple of the group count).
 // Resident blocks of k_conv<NTB, WL, GATED> on the device (registers and LDS
 // permitting), found once; the first call also grants the kernel its LDS.
-template <int NTB, bool WL, bool GATED>
+template <int NTB, bool WL, bool GATED, bool HEAD = false>
 static hipError_t conv_slots(int* out) {
-    constexpr int lds = conv_lds_bytes(NTB, WL);
+    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD);
     static int slots = 0;
     static const hipError_t granted = [] {
         int dev = 0, cap = 0, cus = 0, per_cu = 0;
@@ -189,10 +189,10 @@ static hipError_t conv_slots(int* out) {
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess && cap < lds) e = hipErrorInvalidValue;
         if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, WL, GATED>),
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, WL, GATED, HEAD>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv<NTB, WL, GATED>, 256, lds);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv<NTB, WL, GATED, HEAD>, 256, lds);
         slots = std::max(1, cus) * std::max(1, per_cu);
         return e;
     }();
@@ -200,30 +200,31 @@ static hipError_t conv_slots(int* out) {
     return granted;
 }
 
-template <int NTB, bool WL, bool GATED>
+template <int NTB, bool WL, bool GATED, bool HEAD = false>
 static int launch_conv(const ConvArgs& a, hipStream_t st) {
-    constexpr int lds = conv_lds_bytes(NTB, WL);
+    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD);
     int slots = 0;
-    const hipError_t granted = conv_slots<NTB, WL, GATED>(&slots);
+    const hipError_t granted = conv_slots<NTB, WL, GATED, HEAD>(&slots);
     if (granted != hipSuccess) return hip_fail(granted, "U-Net convolution LDS");
     const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
     const int nsplit = a.nt / NTB;
     const long long items = tiles * nsplit;
     long long grid = std::min<long long>(items, slots);
     grid = std::max<long long>(nsplit, grid / nsplit * nsplit);
-    k_conv<NTB, WL, GATED><<<(unsigned)grid, 256, lds, st>>>(a);
+    k_conv<NTB, WL, GATED, HEAD><<<(unsigned)grid, 256, lds, st>>>(a);
     return MPM_OK;
 }
 
 // k_conv_staged<1> (16 input channels, one output tile, no gate; static LDS): one block
 // per resident slot, as launch_conv.
+template <bool HEAD = false>
 static hipError_t staged_slots(int* out) {
     static int slots = 0;
     static const hipError_t granted = [] {
         int dev = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_staged<1>, 256, 0);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_staged<1, HEAD>, 256, 0);
         slots = std::max(1, cus) * std::max(1, per_cu);
         return e;
     }();
@@ -241,6 +242,11 @@ static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
         set_error("unsupported channel count in the U-Net");
         return MPM_EINVAL;
     }
+    // the fused head needs one 16-channel output tile, the variants below that take it
+    if (a.hout && (nt != 1 || a.cin_p != 16 || a.gate || a.x2 || a.y || a.hcout < 1 || a.hcout > 4)) {
+        set_error("the fused head needs a 16 -> 16 convolution and at most 4 outputs");
+        return MPM_EINVAL;
+    }
     a.nt = nt;
     const bool one = a.cin_p == 16;
     if (a.gate) {
@@ -251,13 +257,16 @@ static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
     if (one && nt % 2) {
         // asynchronous staging pays once every block has two or more tiles (16 -> 16 on
         // 128^3: 50.5 -> 42.6 us; on small grids its longer start costs more than it saves)
+        const bool head = a.hout != nullptr;
         int slots = 0;
-        const hipError_t e = staged_slots(&slots);
+        const hipError_t e = head ? staged_slots<true>(&slots) : staged_slots<false>(&slots);
         if (e != hipSuccess) return hip_fail(e, "U-Net convolution occupancy");
-        if (tiles * nt < 2LL * slots) return launch_conv<1, false, false>(a, st);
+        if (tiles * nt < 2LL * slots)
+            return head ? launch_conv<1, false, false, true>(a, st) : launch_conv<1, false, false>(a, st);
         long long grid = std::min<long long>(tiles * nt, slots);
         grid = std::max<long long>(nt, grid / nt * nt);
-        k_conv_staged<1><<<(unsigned)grid, 256, 0, st>>>(a);
+        if (head) k_conv_staged<1, true><<<(unsigned)grid, 256, 0, st>>>(a);
+        else k_conv_staged<1><<<(unsigned)grid, 256, 0, st>>>(a);
         return MPM_OK;
     }
     if (one) return launch_conv<2, false, false>(a, st);
@@ -281,7 +290,7 @@ static ConvArgs conv_args(const Net* n, int lvl) {
 
 static unsigned blocks_for(long long count) { return (unsigned)((count + 255) / 256); }
 
-int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out) {
+int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out, bool infer) {
     const int L = n->L;
     const int div = 1 << (L - 1);
     if (nb < 1 || D < div || H < div || W < div || D % div || H % div || W % div) {
@@ -328,6 +337,12 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
             hch = c.cout;
         }
     }
+    const ConvL& hd = n->layers.back();
+    // inference: the head runs in the last convolution's epilogue, whose output is then
+    // not stored (only a 16 -> 16 last layer with its 16-channel head qualifies)
+    const int last = (int)n->layers.size() - 2;
+    const bool fuse = infer && n->layers[last].cin_p == 16 && n->layers[last].cout == 16 && hd.cin == 16 &&
+                      hd.cout <= 4;
     for (int lvl = L - 2; lvl >= 0; --lvl) {
         const int cu = n->widths[lvl + 1], cs = n->widths[lvl];
         for (int r = 0; r < 2; ++r, ++li) {
@@ -348,16 +363,24 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
             a.ldy = c.cout;
             a.cout = c.cout;
             a.relu = 1;
+            if (fuse && li == last) {
+                a.y = nullptr;
+                a.hw = n->theta + hd.woff;
+                a.hb = n->theta + hd.boff;
+                a.hout = out;
+                a.hcout = hd.cout;
+            }
             if ((rc = conv_dispatch(a, c.cout_p / 16, st))) return rc;
             h = n->act[li];
             hch = c.cout;
         }
     }
-    const ConvL& hd = n->layers[li];
-    n->head_in = h;
-    k_head<<<blocks_for(P0), 256, 0, st>>>(h, hch, n->theta + hd.woff, n->theta + hd.boff, hd.cout, P0, out);
+    if (!fuse)
+        k_head<<<blocks_for(P0), 256, 0, st>>>(h, hch, n->theta + hd.woff, n->theta + hd.boff, hd.cout, P0, out);
     MPM_HIP(hipGetLastError());
+    n->head_in = fuse ? nullptr : h;
     n->have_fwd = true;
+    n->fwd_infer = infer;
     return MPM_OK;
 }
 
@@ -436,8 +459,8 @@ static int conv_input_grad(Net* n, int li, int lvl, const uint16_t* g, const uin
 }
 
 int net_backward(Net* n, const float* dout) {
-    if (!n->have_fwd) {
-        set_error("mpm_net_backward needs a preceding mpm_net_forward");
+    if (!n->have_fwd || n->fwd_infer) {
+        set_error("mpm_net_backward needs a preceding mpm_net_forward (not an inference pass)");
         return MPM_ESTATE;
     }
     hipStream_t st = n->stream;
@@ -602,7 +625,17 @@ extern "C" int32_t mpm_net_forward(mpm_net net, const uint16_t* in, int32_t nb, 
         set_error("mpm_net_forward: null pointer");
         return MPM_EINVAL;
     }
-    return net_forward(n, in, nb, d, h, w, out);
+    return net_forward(n, in, nb, d, h, w, out, false);
+}
+
+extern "C" int32_t mpm_net_infer(mpm_net net, const uint16_t* in, int32_t nb, int32_t d, int32_t h, int32_t w,
+                                 float* out) {
+    Net* n = (Net*)net;
+    if (!n || !in || !out) {
+        set_error("mpm_net_infer: null pointer");
+        return MPM_EINVAL;
+    }
+    return net_forward(n, in, nb, d, h, w, out, true);
 }
 
 extern "C" int32_t mpm_net_backward(mpm_net net, const float* grad_out) {
@@ -765,6 +798,10 @@ extern "C" int32_t mpm_net_debug_tensor(mpm_net net, int32_t kind, int32_t index
         case MPM_NT_ACT:
         case MPM_NT_ACT_GRAD:
             if (index < 0 || index >= nl - 1) break;
+            if (kind == MPM_NT_ACT && index == nl - 2 && n->fwd_infer && !n->head_in) {
+                set_error("mpm_net_debug_tensor: an inference pass does not store the last layer's output");
+                return MPM_ESTATE;
+            }
             src = kind == MPM_NT_ACT ? n->act[index] : n->gin[index];
             elems = vox(n->lvl_of[index]) * n->layers[index].cout;
             break;

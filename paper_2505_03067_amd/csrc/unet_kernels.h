@@ -45,7 +45,17 @@ struct ConvArgs {
     int ldx2, c1;
     int ldy, yoff, cout, relu;
     int n, D, H, W;
+    // optional 1x1x1 head fused into the epilogue (one 16-channel output tile): per voxel
+    // hout[p][o] = hb[o] + sum_c bf16(y[p][c]) hw[c hcout + o], o < hcout <= 4, in the
+    // order of k_head; y itself is stored only when set
+    const float* hw;
+    const float* hb;
+    float* hout;
+    int hcout;
 };
+
+// LDS floats of the fused head's weights (16 x up to 4) and biases
+constexpr int kHeadLds = 16 * 4 + 4;
 
 // Keep each BF16 half of x only where the gate half is > 0 (ReLU backward).
 __device__ inline uint4 apply_gate(uint4 t, const uint4 g) {
@@ -129,8 +139,33 @@ __host__ __device__ constexpr int conv_x_bytes() { return kHV * kCS * 2; }
 // the block's weights (one chunk's) staged in LDS after the halo tile, except with one
 // chunk and one output tile (then they live in registers); then the block's bias values
 __host__ __device__ constexpr int conv_w_bytes(int ntb, bool wl) { return wl || ntb > 1 ? kSteps * ntb * 1024 : 0; }
-__host__ __device__ constexpr int conv_lds_bytes(int ntb, bool wl) {
-    return conv_x_bytes() + conv_w_bytes(ntb, wl) + 64 * ntb;   // + the block's bias values
+__host__ __device__ constexpr int conv_lds_bytes(int ntb, bool wl, bool head = false) {
+    // + the block's bias values and the fused head's parameters
+    return conv_x_bytes() + conv_w_bytes(ntb, wl) + 64 * ntb + (head ? 4 * kHeadLds : 0);
+}
+
+// Stage the fused head's parameters (a.hout set) in LDS: weights [16][4] at 0 (zero past
+// hcout outputs), biases at 64.  Read after the block's first barrier.
+__device__ inline void conv_stage_head(const ConvArgs& a, float* head_l) {
+    if (!a.hout) return;
+    if (threadIdx.x < 64) {
+        const int c = threadIdx.x >> 2, o = threadIdx.x & 3;
+        head_l[threadIdx.x] = o < a.hcout ? a.hw[c * a.hcout + o] : 0.f;
+    }
+    if (threadIdx.x < 4) head_l[64 + threadIdx.x] = threadIdx.x < a.hcout ? a.hb[threadIdx.x] : 0.f;
+}
+
+// Sum of x over lane l and lane l ^ 16 (v_permlane16_swap trades the odd 16-lane rows of
+// its first operand for the even rows of its second), and over l and l ^ 32
+// (v_permlane32_swap trades the upper half of the first for the lower half of the
+// second).  Both add the two values in the same order in every lane.
+__device__ inline float sum_xor16(float x) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+__device__ inline float sum_xor32(float x) {
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
 }
 
 // Origin of a voxel tile (tile index: x fastest, then y, z, sample), and whether its
@@ -397,10 +432,14 @@ __device__ inline void conv_chunk(const char* xs, uint32_t lb, const uint4 (&bre
 // Bias, ReLU and store of an item's output tiles (acc is cleared).  The MFMAs take the
 // weights as their A operand, so lane l holds output channels 4 (l / 16) .. + 3 of
 // voxel x0 + l mod 16 in row (y0 + mt, z0 + wave): one 8-byte BF16 word per M tile
-// when the output's stride and offset allow (vec), else single values.
-template <int NTB>
+// when the output's stride and offset allow (vec), else single values.  With the fused
+// head (NTB = 1, head_l its parameters in LDS), lane group g = l / 16 forms the partial
+// sums of its four channels, the groups' sums are added pairwise across lanes (g with
+// g ^ 1, then with g ^ 2), and group g stores output g (FP32).
+template <int NTB, bool HEAD = false>
 __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int tb, const float* bias_l, bool vec,
-                                     f32x4 (&acc)[4][NTB]) {
+                                     f32x4 (&acc)[4][NTB], const float* head_l = nullptr) {
+    static_assert(!HEAD || NTB == 1, "the fused head takes one output tile");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15;
     const long long ob = t.sbase + ((long long)t.z0 * a.H + t.y0) * a.W + t.x0;   // the tile's origin
@@ -420,6 +459,23 @@ __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int t
                 if (a.relu) v[i] = fmaxf(v[i], 0.f);
             }
             acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (HEAD) {   // every lane takes part in the exchanges; y is not stored
+                const int g = lane >> 4;
+                float r[4], tot[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) r[i] = (float)(__bf16)v[i];
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    float ps = 0.f;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) ps = __builtin_fmaf(r[i], head_l[(4 * g + i) * 4 + o], ps);
+                    tot[o] = sum_xor32(sum_xor16(ps));
+                }
+                // lane group g stores output g of its voxel: one store covers the M tile
+                const float tv = g == 0 ? tot[0] : g == 1 ? tot[1] : g == 2 ? tot[2] : tot[3];
+                if (g < a.hcout && inb) a.hout[(ob + pv) * a.hcout + g] = head_l[64 + g] + tv;
+                continue;
+            }
             if (!inb) continue;
             if (vec && co + 4 <= a.cout) {
                 const bf16x2 lo = {(__bf16)v[0], (__bf16)v[1]}, hi = {(__bf16)v[2], (__bf16)v[3]};
@@ -448,7 +504,7 @@ __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int t
 // next item's prefetched input does not also wait for the stores of this one.  Three
 // blocks per CU for the chunk-staged weights (WL); two for the others, whose registers
 // (the weights held in registers, or the ReLU gates) would not fit three.
-template <int NTB, bool WL, bool GATED>
+template <int NTB, bool WL, bool GATED, bool HEAD = false>
 __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_conv(ConvArgs a) {
     extern __shared__ uint4 xs_dyn[];
     char* xs = reinterpret_cast<char*>(xs_dyn);
@@ -469,6 +525,8 @@ __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_con
         const int co = tb * 16 + threadIdx.x;
         bias_l[threadIdx.x] = a.bias && co < a.cout ? a.bias[co] : 0.f;
     }
+    float* head_l = bias_l + 16 * NTB;   // (one output tile only)
+    if (HEAD) conv_stage_head(a, head_l);
     // BF16 output as one 8-byte word of four channels per lane and M tile
     const bool vec = a.y && a.ldy % 4 == 0 && a.yoff % 4 == 0 && ((uintptr_t)a.y & 7) == 0;
     // the lane's voxel x = lane % 16 in halo row 0 of plane 'wave' (M tile mt adds mt rows)
@@ -516,7 +574,7 @@ __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_con
         const ConvTile tn = nc == 0 ? conv_tile(a, nxt) : t;
         if (more) conv_fetch<NTB, WL, GATED>(a, tn, 16 * nc, tb, ln, regs);   // in flight during the MFMAs
         conv_chunk<NTB, BREG>(xs, lb, breg, acc);
-        if (chunk == nchunk - 1) conv_epilogue<NTB>(a, t, tb, bias_l, vec, acc);
+        if (chunk == nchunk - 1) conv_epilogue<NTB, HEAD>(a, t, tb, bias_l, vec, acc, head_l);
         if (!more) break;
         t = tn;
         cur = nxt;
@@ -552,13 +610,14 @@ __device__ inline void conv_stage(const ConvArgs& a, const ConvTile& t, const Co
 // item j, so its global loads overlap the MFMAs of item j + 1 and nothing passes through
 // registers (16 -> 16 channels on 128^3: 49 -> 42 us).  Same work split, results and
 // epilogue as k_conv.
-template <int NTB>
+template <int NTB, bool HEAD = false>
 __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs a) {
     constexpr int HB = kHV * kCS * 2;
     __shared__ __attribute__((aligned(16))) char h0[HB];
     __shared__ __attribute__((aligned(16))) char h1[HB];
     __shared__ __attribute__((aligned(16))) char wl[NTB > 1 ? kSteps * NTB * 1024 : 16];
     __shared__ __attribute__((aligned(16))) float bias_l[16 * NTB];
+    __shared__ __attribute__((aligned(16))) float head_l[HEAD ? kHeadLds : 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nsplit = a.nt / NTB;
@@ -570,6 +629,7 @@ __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs 
         const int co = tb * 16 + threadIdx.x;
         bias_l[threadIdx.x] = a.bias && co < a.cout ? a.bias[co] : 0.f;
     }
+    if (HEAD) conv_stage_head(a, head_l);
     const bool vec = a.y && a.ldy % 4 == 0 && a.yoff % 4 == 0 && ((uintptr_t)a.y & 7) == 0;
     const uint32_t lb = (uint32_t)(((wave * kHY) * kHX + (lane & 15)) * kCS * 2 + 16 * ((lane >> 4) & 1));
     f32x4 acc[4][NTB];
@@ -614,7 +674,7 @@ __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs 
         if (scur.n < a.n) conv_stage(a, st, ln, hn);
         conv_advance(a, scur);
         st = conv_tile(a, scur);
-        conv_epilogue<NTB>(a, t, tb, bias_l, vec, acc);
+        conv_epilogue<NTB, HEAD>(a, t, tb, bias_l, vec, acc, head_l);
         conv_advance(a, cur);
         if (cur.n >= a.n) return false;
         t = conv_tile(a, cur);
@@ -950,11 +1010,17 @@ __global__ void k_head(const uint16_t* h, int c, const float* W, const float* b,
     unpack8(*reinterpret_cast<const uint4*>(h + p * 16), *reinterpret_cast<float(*)[8]>(hv));
     unpack8(*reinterpret_cast<const uint4*>(h + p * 16 + 8), *reinterpret_cast<float(*)[8]>(hv + 8));
     (void)c;
+    // the order of the head fused into the convolution epilogue: the sums of channels
+    // 4 g .. 4 g + 3, added pairwise, then the bias
     for (int o = 0; o < cout; ++o) {
-        float s = b[o];
+        float ps[4];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) s += hv[k] * W[k * cout + o];
-        out[p * cout + o] = s;
+        for (int g = 0; g < 4; ++g) {
+            ps[g] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ps[g] = __builtin_fmaf(hv[4 * g + i], W[(4 * g + i) * cout + o], ps[g]);
+        }
+        out[p * cout + o] = b[o] + ((ps[0] + ps[1]) + (ps[2] + ps[3]));
     }
 }
 

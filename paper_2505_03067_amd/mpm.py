@@ -105,6 +105,8 @@ def lib() -> ctypes.CDLL:
             "mpm_net_write": [_vp, ctypes.c_int32, _vp],
             "mpm_net_forward": [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_int32, _vp],
+            "mpm_net_infer": [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_int32, _vp],
             "mpm_net_backward": [_vp, _vp],
             "mpm_net_zero_grad": [_vp],
             "mpm_net_mse": [_vp, _vp, _vp, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_double)],
@@ -372,16 +374,21 @@ def mpm_net_write(net, what: int, src) -> None:
     _check(lib().mpm_net_write(net, int(what), _dev_ptr(src, torch.float32, "src")))
 
 
-def mpm_net_forward(net, x, out) -> None:
-    """x: BF16 data as int16/uint16 tensor [n][d][h][w][c]; out: FP32 [n][d][h][w][out_ch]."""
+def mpm_net_forward(net, x, out, infer=False) -> None:
+    """x: BF16 data as int16/uint16 tensor [n][d][h][w][c]; out: FP32 [n][d][h][w][out_ch].
+    With infer, mpm_net_infer (no backward pass may follow)."""
     import torch
     if x.dtype not in (torch.int16, torch.uint16, torch.bfloat16):
         raise TypeError("x must hold BF16 bit patterns (int16/uint16/bfloat16)")
     if x.dim() != 5 or not x.is_contiguous() or x.device.type != "cuda":
         raise ValueError("x must be a contiguous 5-D GPU tensor")
     nb, d, h, w, _ = x.shape
-    _check(lib().mpm_net_forward(net, ctypes.c_void_p(x.data_ptr()), nb, d, h, w,
-                                 _dev_ptr(out, torch.float32, "out")))
+    fn = lib().mpm_net_infer if infer else lib().mpm_net_forward
+    _check(fn(net, ctypes.c_void_p(x.data_ptr()), nb, d, h, w, _dev_ptr(out, torch.float32, "out")))
+
+
+def mpm_net_infer(net, x, out) -> None:
+    mpm_net_forward(net, x, out, infer=True)
 
 
 def mpm_net_backward(net, grad_out) -> None:
@@ -535,12 +542,14 @@ class Net:
     def set_grads(self, t):
         mpm_net_write(self.handle, 1, t.contiguous())
 
-    def forward(self, x, out):
+    def forward(self, x, out, infer=False):
+        """Forward pass (mpm_net_forward); with infer the inference pass (mpm_net_infer),
+        after which backward raises until the next plain forward pass."""
         if x.dim() != 5 or x.shape[-1] != self.in_ch:
             raise ValueError(f"x must be [n][d][h][w][{self.in_ch}]")
         if tuple(out.shape) != tuple(x.shape[:4]) + (self.out_ch,):
             raise ValueError(f"out must be [n][d][h][w][{self.out_ch}] matching x")
-        mpm_net_forward(self.handle, x, out)
+        mpm_net_forward(self.handle, x, out, infer=infer)
         self._out_numel = out.numel()
 
     def backward(self, grad_out):

@@ -177,6 +177,34 @@ def test_forward_backward_match_oracle(widths, shape, monkeypatch):
     assert _rel(outg, plain) <= 3e-2
 
 
+@pytest.mark.parametrize("widths,shape", [([16, 32], (2, 8, 8, 16)), ([16, 32, 64, 64], (1, 64, 64, 128))])
+def test_inference_pass_matches_forward(widths, shape):
+    """mpm_net_infer (the head fused into the last convolution's epilogue, whose output is
+    then not stored) gives the forward pass's output bit for bit, on a grid small enough
+    for the register-staged kernel and on one large enough for the asynchronously staged
+    one; no backward pass may follow it until the next plain forward pass."""
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    import paper_2505_03067_amd.mpm as b
+    net = m.Net(16, 3, widths, seed=21)
+    g = torch.Generator().manual_seed(5)
+    x = torch.randn(tuple(shape) + (16,), generator=g).to(torch.bfloat16).view(torch.int16).cuda()
+    out_f = torch.empty(tuple(shape) + (3,), dtype=torch.float32, device="cuda")
+    out_i = torch.full_like(out_f, float("nan"))
+    net.forward(x, out_f)
+    net.forward(x, out_i, infer=True)
+    assert float(out_f.abs().sum()) > 0.0
+    assert torch.equal(out_f.view(torch.int32), out_i.view(torch.int32))
+    with pytest.raises(b.MpmError):
+        net.backward(torch.zeros_like(out_f))
+    with pytest.raises(b.MpmError):
+        net.debug_tensor(b.MPM_NT_ACT, 4 * len(widths) - 3)   # the last 3x3x3 layer's output
+    net.forward(x, out_f)
+    net.zero_grad()
+    net.backward(torch.zeros_like(out_f))
+    net.close()
+
+
 def _tensor(net, kind, index, shape, ch):
     t = net.debug_tensor(kind, index).cpu().numpy().view(np.uint16).astype(np.uint32) << 16
     return t.view(np.float32).astype(np.float64).reshape(tuple(shape) + (ch,))

@@ -27,10 +27,11 @@ def _bf16_values(bits):
 
 def _ws_pair_case(p, S, box=None, extrap=False):
     """Network input and training target built by the library, against their
-    definition: each channel (c^n, k, D, s per species, then the mask) times its scale,
-    rounded to BF16 on the box grid (zero past the box), the Jacobi-scaled residual of
-    the base start x_b per species; target (c^{n+1} - x_b) / out_scale on domain voxels,
-    zero elsewhere.  x_b = c^n, or with extrap the extrapolation 2 c^n - c^{n-1}."""
+    definition: each channel (c^n on the domain voxels and zero off them, k, D, s per
+    species, then the mask) times its scale, rounded to BF16 on the box grid (zero past
+    the box), the Jacobi-scaled residual of the base start x_b per species; target
+    (c^{n+1} - x_b) / out_scale on domain voxels, zero elsewhere.  x_b = c^n, or with
+    extrap the extrapolation 2 c^n - c^{n-1}."""
     torch = require_gpu()
     import paper_2505_03067_amd as m
     from oracle.fv import assemble, box_slice
@@ -60,8 +61,8 @@ def _ws_pair_case(p, S, box=None, extrap=False):
     c1 = f.cpu().numpy()
     xb_all = 2.0 * c0 - prev.cpu().numpy() if extrap else c0
     sl = box_slice(box)
-    chans = [c0[s] for s in range(S)] + [p.k[s] for s in range(S)] + [p.D[s] for s in range(S)] + \
-            [p.src[s] for s in range(S)] + [p.mask.astype(np.float64)]
+    chans = [c0[s] * (p.mask != 0) for s in range(S)] + [p.k[s] for s in range(S)] + \
+            [p.D[s] for s in range(S)] + [p.src[s] for s in range(S)] + [p.mask.astype(np.float64)]
     ex, ey, ez = ext
     for ch, a in enumerate(chans):
         want = np.zeros((gz, gy, gx), np.uint16)
