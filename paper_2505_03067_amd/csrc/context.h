@@ -47,6 +47,16 @@ struct ProbHost {
     uint16_t* wsin = nullptr;  // BF16 network input [G][ws_channels(S)]
     float* wsout = nullptr;    // network output [G][S]
     size_t cap_grid = 0;       // grid voxels the three buffers above hold
+    // tiles of the network's last level the warm start computes (16 x 4 x 4 voxels of the
+    // grid, entries tx | ty << 10 | tz << 20): [0, tl_n[0]) those within one voxel of a
+    // tile holding domain voxels (its first convolution), then the tl_n[1] tiles holding
+    // domain voxels (its second convolution and the head); tl_n[0] < 0: no lists
+    int* tl_dev = nullptr;
+    int* tl_host = nullptr;    // pinned
+    uint8_t* tf_dev = nullptr; // per-tile flags [2][tiles]
+    uint8_t* tf_host = nullptr;  // pinned
+    size_t cap_tiles = 0;
+    int tl_n[2] = {-1, 0};
     bool ws_ready = false;     // wsin holds the static channels (and zero c and d off the
                                // domain) of the current grid, domain and scales (cleared
                                // by a set-up and by new scales)

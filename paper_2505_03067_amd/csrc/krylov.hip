@@ -2429,7 +2429,10 @@ static int warm_start(Ctx* c, hipStream_t st) {
                 ph.ws_ready = true;
             }
             k_ws_resid<T><<<nb, kThreads, 0, st>>>(a, p, c->h_fields[p], c->d_scales, ph.wsin);
-            int rc = net_forward(c->net, ph.wsin, 1, ph.gd[2], ph.gd[1], ph.gd[0], ph.wsout, true);
+            // the last level computes only the tiles the domain voxels' outputs read
+            const TileLists tl{ph.tl_dev, ph.tl_n[0], ph.tl_dev + std::max(ph.tl_n[0], 0), ph.tl_n[1]};
+            int rc = net_forward(c->net, ph.wsin, 1, ph.gd[2], ph.gd[1], ph.gd[0], ph.wsout, true,
+                                 ph.tl_n[0] >= 0 ? &tl : nullptr);
             if (rc != MPM_OK) {
                 c->net->stream = saved;
                 return rc;

@@ -16,6 +16,7 @@
 //    and the Jacobi scaling S = diag(A)^(-1/2) with the scaled couplings
 //    S_P A_PQ S_Q in FP64 and FP32.
 #include <algorithm>
+#include <cstring>
 
 #include "context.h"
 
@@ -318,6 +319,42 @@ __global__ void k_ws_static(const uint8_t* mask, const double* D, const double* 
     o[3 * S] = mask[v] ? 1.f : 0.f;
 }
 
+// The network's voxel tiles on the warm-start grid (16 x 4 x 4, as its convolutions
+// tile it): per tile, flag[ntiles + t] = 1 when a domain voxel (mask channel of the
+// static input) lies in it; then flag[t] = 1 when one of its 27 neighbouring tiles (itself
+// included) is flagged so, i.e. when a 3x3x3 convolution over the flagged tiles reads it.
+constexpr int kWsTX = 16, kWsTY = 4, kWsTZ = 4;
+__global__ void k_ws_tile_domain(const float* stat, int S, int gx, int gy, int gz, uint8_t* flag) {
+    const int ntx = (gx + kWsTX - 1) / kWsTX, nty = gy / kWsTY, ntz = gz / kWsTZ;
+    const int nt = ntx * nty * ntz;
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= nt) return;
+    const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+    const int C = ws_static_channels(S);
+    uint8_t any = 0;
+    for (int v = 0; v < kWsTX * kWsTY * kWsTZ && !any; ++v) {
+        const int x = tx * kWsTX + v % kWsTX, y = ty * kWsTY + (v / kWsTX) % kWsTY, z = tz * kWsTZ + v / (kWsTX * kWsTY);
+        if (x < gx && stat[(((long long)z * gy + y) * gx + x) * C + 3 * S] > 0.f) any = 1;
+    }
+    flag[nt + t] = any;
+}
+__global__ void k_ws_tile_near(int gx, int gy, int gz, uint8_t* flag) {
+    const int ntx = (gx + kWsTX - 1) / kWsTX, nty = gy / kWsTY, ntz = gz / kWsTZ;
+    const int nt = ntx * nty * ntz;
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= nt) return;
+    const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+    uint8_t any = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = tx + dx, y = ty + dy, z = tz + dz;
+                if (x >= 0 && x < ntx && y >= 0 && y < nty && z >= 0 && z < ntz)
+                    any |= flag[nt + (z * nty + y) * ntx + x];
+            }
+    flag[t] = any;
+}
+
 // Grow a scratch buffer to hold n elements (with room for later growth).
 template <typename T>
 static hipError_t reserve(T** p, size_t* cap, size_t n) {
@@ -389,6 +426,17 @@ void free_problem(ProbHost& ph) {
     ph.wsin = nullptr;
     ph.wsout = nullptr;
     ph.cap_grid = 0;
+    (void)hipFree(ph.tl_dev);
+    (void)hipFree(ph.tf_dev);
+    if (ph.tl_host) (void)hipHostFree(ph.tl_host);
+    if (ph.tf_host) (void)hipHostFree(ph.tf_host);
+    ph.tl_dev = nullptr;
+    ph.tf_dev = nullptr;
+    ph.tl_host = nullptr;
+    ph.tf_host = nullptr;
+    ph.cap_tiles = 0;
+    ph.tl_n[0] = -1;
+    ph.tl_n[1] = 0;
 }
 
 // Zero elements [from, to) of a padded array (its trailing padding included).
@@ -497,6 +545,41 @@ static int discretise(Ctx* c, ProbHost& ph, const BoxGeo& g, const uint8_t* mask
         ph.ws_ready = false;
         k_ws_static<<<(unsigned)((G + 255) / 256), 256, 0, st>>>(mask, D, k, src, g, gx, gy, gz, c->S, ca.nvox,
                                                               ph.stat);
+        // the tiles of the network's last level that the domain needs (lists built below,
+        // once the flags are on the host); entries pack the tile digits in 10, 10 and 11 bits
+        const int ntx = (gx + kWsTX - 1) / kWsTX, nty = gy / kWsTY, ntz = gz / kWsTZ;
+        const size_t nt = (size_t)ntx * nty * ntz;
+        ph.tl_n[0] = -1;
+        ph.tl_n[1] = 0;
+        if (ntx < 1024 && nty < 1024 && ntz < 2048) {
+            if (nt > ph.cap_tiles) {
+                (void)hipFree(ph.tl_dev);
+                (void)hipFree(ph.tf_dev);
+                if (ph.tl_host) (void)hipHostFree(ph.tl_host);
+                if (ph.tf_host) (void)hipHostFree(ph.tf_host);
+                ph.tl_dev = nullptr;
+                ph.tf_dev = nullptr;
+                ph.tl_host = nullptr;
+                ph.tf_host = nullptr;
+                ph.cap_tiles = 0;
+                if (hipMalloc(&ph.tl_dev, 2 * nt * sizeof(int)) != hipSuccess ||
+                    hipMalloc(&ph.tf_dev, 2 * nt) != hipSuccess ||
+                    hipHostMalloc((void**)&ph.tl_host, 2 * nt * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+                    hipHostMalloc((void**)&ph.tf_host, 2 * nt, hipHostMallocDefault) != hipSuccess) {
+                    (void)hipGetLastError();
+                    set_error("mpm_fv_setup: device allocation of the warm-start tile lists failed");
+                    return MPM_ENOMEM;
+                }
+                ph.cap_tiles = nt;
+            }
+            const unsigned tb = (unsigned)((nt + 255) / 256);
+            k_ws_tile_domain<<<tb, 256, 0, st>>>(ph.stat, c->S, gx, gy, gz, ph.tf_dev);
+            k_ws_tile_near<<<tb, 256, 0, st>>>(gx, gy, gz, ph.tf_dev);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipMemcpyAsync(ph.tf_host, ph.tf_dev, 2 * nt, hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (tile flags)");
+            ph.tl_n[0] = 0;
+        }
     }
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_small + 1, flag, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -505,6 +588,24 @@ static int discretise(Ctx* c, ProbHost& ph, const BoxGeo& g, const uint8_t* mask
     if (c->h_small[1]) {
         set_error("mpm_fv_setup: negative or non-finite D, k or s on a domain voxel");
         return MPM_EINVAL;
+    }
+    if (net_warm_start(c) && ph.tl_n[0] == 0) {
+        const int ntx = (ph.gd[0] + kWsTX - 1) / kWsTX, nty = ph.gd[1] / kWsTY, ntz = ph.gd[2] / kWsTZ;
+        const int nt = ntx * nty * ntz;
+        int na = 0, nb = 0;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int t = 0; t < nt; ++t) {
+                if (!ph.tf_host[pass * nt + t]) continue;
+                const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+                const int entry = tx | ty << 10 | tz << 20;
+                if (pass == 0) ph.tl_host[na++] = entry;
+                else ph.tl_host[nt + nb++] = entry;   // moved behind the first list below
+            }
+        std::memmove(ph.tl_host + na, ph.tl_host + nt, (size_t)nb * sizeof(int));
+        e = hipMemcpyAsync(ph.tl_dev, ph.tl_host, (size_t)(na + nb) * sizeof(int), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (tile lists)");
+        ph.tl_n[0] = na;
+        ph.tl_n[1] = nb;
     }
     return MPM_OK;
 }

@@ -42,6 +42,7 @@ struct Net {
     float* outbuf = nullptr;
     bool have_fwd = false;
     bool fwd_infer = false;            // the last forward pass was an inference pass
+    bool fwd_listed = false;           // ... that computed listed tiles of the last level only
     // warm-start use
     double* mse_part = nullptr;        // pinned host copy of the MSE partial sums
     double* mse_dev = nullptr;         // device partial sums of the MSE
@@ -50,9 +51,20 @@ struct Net {
 int net_build(Net* n, int in_ch, int out_ch, int levels, const int* widths, uint64_t seed);
 int net_pack(Net* n);
 void net_free(Net* n);
+// Tiles of the last level an inference pass computes (device lists of tile entries, see
+// ConvArgs::tlist): those of its first convolution (near) and of its second one and
+// the head (domain).
+struct TileLists {
+    const int* near;
+    int n_near;
+    const int* domain;
+    int n_domain;
+};
 // infer: an inference pass (the head fused into the last convolution where the widths
-// allow; no backward pass may follow)
-int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out, bool infer);
+// allow; no backward pass may follow); with tiles (one sample, fused head), the last
+// level computes only the listed tiles, so the output is valid on the domain tiles only.
+int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out, bool infer,
+                const TileLists* tiles = nullptr);
 int net_backward(Net* n, const float* dout);
 
 }  // namespace mpm

@@ -178,9 +178,9 @@ static int ensure_acts(Net* n, int nb, int D, int H, int W) {
 // a multiple of the group count).
 // Resident blocks of k_conv<NTB, WL, GATED> on the device (registers and LDS
 // permitting), found once; the first call also grants the kernel its LDS.
-template <int NTB, bool WL, bool GATED, bool HEAD = false>
+template <int NTB, bool WL, bool GATED, bool HEAD = false, bool LIST = false>
 static hipError_t conv_slots(int* out) {
-    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD);
+    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD, LIST);
     static int slots = 0;
     static const hipError_t granted = [] {
         int dev = 0, cap = 0, cus = 0, per_cu = 0;
@@ -189,10 +189,10 @@ static hipError_t conv_slots(int* out) {
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess && cap < lds) e = hipErrorInvalidValue;
         if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, WL, GATED, HEAD>),
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, WL, GATED, HEAD, LIST>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv<NTB, WL, GATED, HEAD>, 256, lds);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv<NTB, WL, GATED, HEAD, LIST>, 256, lds);
         slots = std::max(1, cus) * std::max(1, per_cu);
         return e;
     }();
@@ -200,31 +200,40 @@ static hipError_t conv_slots(int* out) {
     return granted;
 }
 
-template <int NTB, bool WL, bool GATED, bool HEAD = false>
-static int launch_conv(const ConvArgs& a, hipStream_t st) {
-    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD);
-    int slots = 0;
-    const hipError_t granted = conv_slots<NTB, WL, GATED, HEAD>(&slots);
-    if (granted != hipSuccess) return hip_fail(granted, "U-Net convolution LDS");
-    const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
-    const int nsplit = a.nt / NTB;
-    const long long items = tiles * nsplit;
-    long long grid = std::min<long long>(items, slots);
+// Blocks of a persistent launch: one per resident slot, capped at the items (voxel tiles,
+// or listed tiles, times the output-tile groups) and rounded down to a multiple of the
+// group count; with a tile list, enough that no block takes more than kListMax entries.
+static long long conv_grid(const ConvArgs& a, int nsplit, int slots) {
+    const long long tiles = a.tlist ? (long long)a.tcount
+                                    : (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) *
+                                          ((a.W + kTX - 1) / kTX);
+    long long grid = std::min<long long>(tiles * nsplit, slots);
     grid = std::max<long long>(nsplit, grid / nsplit * nsplit);
-    k_conv<NTB, WL, GATED, HEAD><<<(unsigned)grid, 256, lds, st>>>(a);
+    if (a.tlist) grid = std::max<long long>(grid, (tiles + kListMax - 1) / kListMax * nsplit);
+    return grid;
+}
+
+template <int NTB, bool WL, bool GATED, bool HEAD = false, bool LIST = false>
+static int launch_conv(const ConvArgs& a, hipStream_t st) {
+    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD, LIST);
+    int slots = 0;
+    const hipError_t granted = conv_slots<NTB, WL, GATED, HEAD, LIST>(&slots);
+    if (granted != hipSuccess) return hip_fail(granted, "U-Net convolution LDS");
+    const long long grid = conv_grid(a, a.nt / NTB, slots);
+    k_conv<NTB, WL, GATED, HEAD, LIST><<<(unsigned)grid, 256, lds, st>>>(a);
     return MPM_OK;
 }
 
 // k_conv_staged<1> (16 input channels, one output tile, no gate; static LDS): one block
 // per resident slot, as launch_conv.
-template <bool HEAD = false>
+template <bool HEAD = false, bool LIST = false>
 static hipError_t staged_slots(int* out) {
     static int slots = 0;
     static const hipError_t granted = [] {
         int dev = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_staged<1, HEAD>, 256, 0);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_staged<1, HEAD, LIST>, 256, 0);
         slots = std::max(1, cus) * std::max(1, per_cu);
         return e;
     }();
@@ -247,25 +256,36 @@ static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
         set_error("the fused head needs a 16 -> 16 convolution and at most 4 outputs");
         return MPM_EINVAL;
     }
+    if (a.tlist && (a.n != 1 || a.gate || nt != 1 || a.tcount < 0 || (a.cin_p == 16 && !a.hout))) {
+        set_error("a tile list needs one sample and one output tile (with the fused head for 16 inputs)");
+        return MPM_EINVAL;
+    }
     a.nt = nt;
     const bool one = a.cin_p == 16;
+    if (a.tlist && a.tcount == 0) return MPM_OK;   // nothing listed
+    if (a.tlist && !one) return launch_conv<1, true, false, false, true>(a, st);
     if (a.gate) {
         if (one) return nt % 2 ? launch_conv<1, false, true>(a, st) : launch_conv<2, false, true>(a, st);
         return launch_conv<1, true, true>(a, st);
     }
-    const long long tiles = (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) * ((a.W + kTX - 1) / kTX);
+    const long long tiles = a.tlist ? (long long)a.tcount
+                                    : (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) *
+                                          ((a.W + kTX - 1) / kTX);
     if (one && nt % 2) {
         // asynchronous staging pays once every block has two or more tiles (16 -> 16 on
         // 128^3: 50.5 -> 42.6 us; on small grids its longer start costs more than it saves)
-        const bool head = a.hout != nullptr;
+        const bool head = a.hout != nullptr, list = a.tlist != nullptr;
         int slots = 0;
-        const hipError_t e = head ? staged_slots<true>(&slots) : staged_slots<false>(&slots);
+        const hipError_t e = list ? staged_slots<true, true>(&slots)
+                             : head ? staged_slots<true>(&slots) : staged_slots<false>(&slots);
         if (e != hipSuccess) return hip_fail(e, "U-Net convolution occupancy");
         if (tiles * nt < 2LL * slots)
-            return head ? launch_conv<1, false, false, true>(a, st) : launch_conv<1, false, false>(a, st);
-        long long grid = std::min<long long>(tiles * nt, slots);
-        grid = std::max<long long>(nt, grid / nt * nt);
-        if (head) k_conv_staged<1, true><<<(unsigned)grid, 256, 0, st>>>(a);
+            return list   ? launch_conv<1, false, false, true, true>(a, st)
+                   : head ? launch_conv<1, false, false, true>(a, st)
+                          : launch_conv<1, false, false>(a, st);
+        const long long grid = conv_grid(a, nt, slots);
+        if (list) k_conv_staged<1, true, true><<<(unsigned)grid, 256, 0, st>>>(a);
+        else if (head) k_conv_staged<1, true><<<(unsigned)grid, 256, 0, st>>>(a);
         else k_conv_staged<1><<<(unsigned)grid, 256, 0, st>>>(a);
         return MPM_OK;
     }
@@ -290,7 +310,8 @@ static ConvArgs conv_args(const Net* n, int lvl) {
 
 static unsigned blocks_for(long long count) { return (unsigned)((count + 255) / 256); }
 
-int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out, bool infer) {
+int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* out, bool infer,
+                const TileLists* tiles) {
     const int L = n->L;
     const int div = 1 << (L - 1);
     if (nb < 1 || D < div || H < div || W < div || D % div || H % div || W % div) {
@@ -343,6 +364,7 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
     const int last = (int)n->layers.size() - 2;
     const bool fuse = infer && n->layers[last].cin_p == 16 && n->layers[last].cout == 16 && hd.cin == 16 &&
                       hd.cout <= 4;
+    const bool listed = fuse && tiles && nb == 1;
     for (int lvl = L - 2; lvl >= 0; --lvl) {
         const int cu = n->widths[lvl + 1], cs = n->widths[lvl];
         for (int r = 0; r < 2; ++r, ++li) {
@@ -370,6 +392,10 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
                 a.hout = out;
                 a.hcout = hd.cout;
             }
+            if (listed && li >= last - 1) {
+                a.tlist = li == last ? tiles->domain : tiles->near;
+                a.tcount = li == last ? tiles->n_domain : tiles->n_near;
+            }
             if ((rc = conv_dispatch(a, c.cout_p / 16, st))) return rc;
             h = n->act[li];
             hch = c.cout;
@@ -381,6 +407,7 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
     n->head_in = fuse ? nullptr : h;
     n->have_fwd = true;
     n->fwd_infer = infer;
+    n->fwd_listed = listed;
     return MPM_OK;
 }
 
@@ -798,8 +825,9 @@ extern "C" int32_t mpm_net_debug_tensor(mpm_net net, int32_t kind, int32_t index
         case MPM_NT_ACT:
         case MPM_NT_ACT_GRAD:
             if (index < 0 || index >= nl - 1) break;
-            if (kind == MPM_NT_ACT && index == nl - 2 && n->fwd_infer && !n->head_in) {
-                set_error("mpm_net_debug_tensor: an inference pass does not store the last layer's output");
+            if (kind == MPM_NT_ACT && ((index == nl - 2 && n->fwd_infer && !n->head_in) ||
+                                       (index == nl - 3 && n->fwd_listed))) {
+                set_error("mpm_net_debug_tensor: the last inference pass did not store this output in full");
                 return MPM_ESTATE;
             }
             src = kind == MPM_NT_ACT ? n->act[index] : n->gin[index];

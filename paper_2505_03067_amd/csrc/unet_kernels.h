@@ -52,10 +52,16 @@ struct ConvArgs {
     const float* hb;
     float* hout;
     int hcout;
+    // optional list of the tiles to compute (sample 0 only, n = 1): entry tx | ty << 10 |
+    // tz << 20; the other tiles' outputs are left as they are
+    const int* tlist;
+    int tcount;
 };
 
 // LDS floats of the fused head's weights (16 x up to 4) and biases
 constexpr int kHeadLds = 16 * 4 + 4;
+// tile-list entries a block stages (see conv_start)
+constexpr int kListMax = 64;
 
 // Keep each BF16 half of x only where the gate half is > 0 (ReLU backward).
 __device__ inline uint4 apply_gate(uint4 t, const uint4 g) {
@@ -139,9 +145,9 @@ __host__ __device__ constexpr int conv_x_bytes() { return kHV * kCS * 2; }
 // the block's weights (one chunk's) staged in LDS after the halo tile, except with one
 // chunk and one output tile (then they live in registers); then the block's bias values
 __host__ __device__ constexpr int conv_w_bytes(int ntb, bool wl) { return wl || ntb > 1 ? kSteps * ntb * 1024 : 0; }
-__host__ __device__ constexpr int conv_lds_bytes(int ntb, bool wl, bool head = false) {
-    // + the block's bias values and the fused head's parameters
-    return conv_x_bytes() + conv_w_bytes(ntb, wl) + 64 * ntb + (head ? 4 * kHeadLds : 0);
+__host__ __device__ constexpr int conv_lds_bytes(int ntb, bool wl, bool head = false, bool list = false) {
+    // + the block's bias values, the fused head's parameters and the block's tile list
+    return conv_x_bytes() + conv_w_bytes(ntb, wl) + 64 * ntb + (head ? 4 * kHeadLds : 0) + (list ? 4 * kListMax : 0);
 }
 
 // Stage the fused head's parameters (a.hout set) in LDS: weights [16][4] at 0 (zero past
@@ -180,6 +186,7 @@ struct ConvTile {
 struct ConvCursor {
     int tx, ty, tz, n;
     int sx, sy, sz, sn;
+    int k;   // with a tile list: the block's entry
 };
 __device__ inline void conv_digits(const ConvArgs& a, unsigned t, int& x, int& y, int& z, int& n) {
     const unsigned ntx = (a.W + kTX - 1) / kTX, nty = (a.H + kTY - 1) / kTY, ntz = (a.D + kTZ - 1) / kTZ;
@@ -219,6 +226,47 @@ __device__ inline void conv_advance(const ConvArgs& a, ConvCursor& c) {
     c.tz -= k ? ntz : 0;
     c.n += c.sn + k;
 }
+// With a tile list, block b of an output-tile group takes list entries b', b' + s,
+// b' + 2 s, ... (b' its index among the group's blocks, s their count), at most
+// kListMax of them, staged in LDS at its start; past them the cursor reads n = a.n.
+__device__ inline void conv_list_tile(const ConvArgs& a, const int* tl, ConvCursor& c) {
+    const int e = c.k < kListMax ? tl[c.k] : -1;
+    if (e < 0) {
+        c.n = a.n;
+        return;
+    }
+    c.tx = e & 1023;
+    c.ty = (e >> 10) & 1023;
+    c.tz = e >> 20;
+    c.n = 0;
+}
+template <bool LIST>
+__device__ inline ConvCursor conv_start(const ConvArgs& a, unsigned first, unsigned stride, int* tl) {
+    if constexpr (!LIST) {
+        (void)tl;
+        return conv_cursor(a, first, stride);
+    } else {
+        for (int i = threadIdx.x; i < kListMax; i += blockDim.x) {
+            const long long li = (long long)first + (long long)i * stride;
+            tl[i] = li < a.tcount ? a.tlist[li] : -1;
+        }
+        __syncthreads();
+        ConvCursor c{};
+        conv_list_tile(a, tl, c);
+        return c;
+    }
+}
+template <bool LIST>
+__device__ inline void conv_next(const ConvArgs& a, ConvCursor& c, const int* tl) {
+    if constexpr (LIST) {
+        ++c.k;
+        conv_list_tile(a, tl, c);
+    } else {
+        (void)tl;
+        conv_advance(a, c);
+    }
+}
+
 __device__ inline ConvTile conv_tile(const ConvArgs& a, const ConvCursor& c) {
     ConvTile t;
     t.x0 = c.tx * kTX;
@@ -504,7 +552,7 @@ __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int t
 // next item's prefetched input does not also wait for the stores of this one.  Three
 // blocks per CU for the chunk-staged weights (WL); two for the others, whose registers
 // (the weights held in registers, or the ReLU gates) would not fit three.
-template <int NTB, bool WL, bool GATED, bool HEAD = false>
+template <int NTB, bool WL, bool GATED, bool HEAD = false, bool LIST = false>
 __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_conv(ConvArgs a) {
     extern __shared__ uint4 xs_dyn[];
     char* xs = reinterpret_cast<char*>(xs_dyn);
@@ -514,18 +562,19 @@ __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_con
     const int nchunk = WL ? a.cin_p / 16 : 1;
     const unsigned bid = blockIdx.x;
     const int tb = (int)(bid % nsplit) * NTB;   // the block's first output tile
-    // the block's tiles: bid / nsplit, then every gridDim.x / nsplit-th
-    ConvCursor cur = conv_cursor(a, bid / nsplit, gridDim.x / nsplit);
-    if (cur.n >= a.n) return;
-    // the MFMAs take the weights as their A operand, so the accumulator of M tile mt holds
-    // output channels 4 (lane / 16) .. + 3 of voxel lane % 16: the lane's bias values
-    // the block's bias values sit in LDS after the halo tile and the weights
+    // the block's bias values sit in LDS after the halo tile and the weights, then the
+    // fused head's parameters and the tile list
     float* bias_l = reinterpret_cast<float*>(xs + conv_x_bytes() + conv_w_bytes(NTB, WL));
+    float* head_l = bias_l + 16 * NTB;   // (one output tile only)
+    int* tl = reinterpret_cast<int*>(head_l + (HEAD ? kHeadLds : 0));
+    // the block's tiles: bid / nsplit, then every gridDim.x / nsplit-th (of the grid, or
+    // of the tile list)
+    ConvCursor cur = conv_start<LIST>(a, bid / nsplit, gridDim.x / nsplit, tl);
+    if (cur.n >= a.n) return;
     if (threadIdx.x < 16 * NTB) {
         const int co = tb * 16 + threadIdx.x;
         bias_l[threadIdx.x] = a.bias && co < a.cout ? a.bias[co] : 0.f;
     }
-    float* head_l = bias_l + 16 * NTB;   // (one output tile only)
     if (HEAD) conv_stage_head(a, head_l);
     // BF16 output as one 8-byte word of four channels per lane and M tile
     const bool vec = a.y && a.ldy % 4 == 0 && a.yoff % 4 == 0 && ((uintptr_t)a.y & 7) == 0;
@@ -568,7 +617,7 @@ __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_con
         int nc = chunk + 1;
         if (nc == nchunk) {
             nc = 0;
-            conv_advance(a, nxt);
+            conv_next<LIST>(a, nxt, tl);
         }
         const bool more = nxt.n < a.n;
         const ConvTile tn = nc == 0 ? conv_tile(a, nxt) : t;
@@ -610,7 +659,7 @@ __device__ inline void conv_stage(const ConvArgs& a, const ConvTile& t, const Co
 // item j, so its global loads overlap the MFMAs of item j + 1 and nothing passes through
 // registers (16 -> 16 channels on 128^3: 49 -> 42 us).  Same work split, results and
 // epilogue as k_conv.
-template <int NTB, bool HEAD = false>
+template <int NTB, bool HEAD = false, bool LIST = false>
 __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs a) {
     constexpr int HB = kHV * kCS * 2;
     __shared__ __attribute__((aligned(16))) char h0[HB];
@@ -618,12 +667,13 @@ __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs 
     __shared__ __attribute__((aligned(16))) char wl[NTB > 1 ? kSteps * NTB * 1024 : 16];
     __shared__ __attribute__((aligned(16))) float bias_l[16 * NTB];
     __shared__ __attribute__((aligned(16))) float head_l[HEAD ? kHeadLds : 1];
+    __shared__ int tl[LIST ? kListMax : 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nsplit = a.nt / NTB;
     const unsigned bid = blockIdx.x;
     const int tb = (int)(bid % nsplit) * NTB;
-    ConvCursor cur = conv_cursor(a, bid / nsplit, gridDim.x / nsplit);
+    ConvCursor cur = conv_start<LIST>(a, bid / nsplit, gridDim.x / nsplit, tl);
     if (cur.n >= a.n) return;
     if (threadIdx.x < 16 * NTB) {
         const int co = tb * 16 + threadIdx.x;
@@ -658,11 +708,11 @@ __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs 
     ConvCursor scur = cur;
     ConvTile st = t;
     conv_stage(a, st, ln, h0);
-    conv_advance(a, scur);
+    conv_next<LIST>(a, scur, tl);
     st = conv_tile(a, scur);
     __syncthreads();
     if (scur.n < a.n) conv_stage(a, st, ln, h1);
-    conv_advance(a, scur);
+    conv_next<LIST>(a, scur, tl);
     st = conv_tile(a, scur);
     conv_chunk<NTB, BREG>(h0, lb, breg, acc, wl);
     // One step: wait until every wave has read hn (the item just computed) and the
@@ -672,10 +722,10 @@ __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs 
     auto step = [&](char* __restrict__ hn, const char* __restrict__ hc) -> bool {
         __syncthreads();
         if (scur.n < a.n) conv_stage(a, st, ln, hn);
-        conv_advance(a, scur);
+        conv_next<LIST>(a, scur, tl);
         st = conv_tile(a, scur);
         conv_epilogue<NTB, HEAD>(a, t, tb, bias_l, vec, acc, head_l);
-        conv_advance(a, cur);
+        conv_next<LIST>(a, cur, tl);
         if (cur.n >= a.n) return false;
         t = conv_tile(a, cur);
         conv_chunk<NTB, BREG>(hc, lb, breg, acc, wl);
