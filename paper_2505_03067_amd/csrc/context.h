@@ -43,7 +43,7 @@ struct ProbHost {
     size_t cap_rows = 0, cap_boxvox = 0, cap_svox = 0;
     // warm start: static network input channels on the box grid (k, D, s, mask)
     int gd[3] = {0, 0, 0};
-    float* stat = nullptr;
+    float* stat = nullptr;     // [3 S + 1][G] FP32, channel-major
     uint16_t* wsin = nullptr;  // BF16 network input [G][ws_channels(S)]
     float* wsout = nullptr;    // network output [G][S]
     size_t cap_grid = 0;       // grid voxels the three buffers above hold

@@ -1391,8 +1391,13 @@ __global__ __launch_bounds__(256) void k_ws_input(ProbDev pd, int S, const float
     const int C = ws_channels(S);
     uint16_t val[ws_channels(MPM_MAX_SPECIES)];
     for (int s = 0; s < S; ++s) val[s] = 0;
-    const float* st = stat + i * ws_static_channels(S);   // zero beyond the box
-    for (int c = 0; c < ws_static_channels(S); ++c) val[S + c] = to_bf16(st[c] * scales[S + c]);
+    const long long G = (long long)gx * gy * pd.gd[2];
+    float sc[ws_static_channels(MPM_MAX_SPECIES)], sv[ws_static_channels(MPM_MAX_SPECIES)];
+    for (int c = 0; c < ws_static_channels(S); ++c) {
+        sc[c] = scales[S + c];
+        sv[c] = stat[c * G + i];   // channel-major, zero beyond the box
+    }
+    for (int c = 0; c < ws_static_channels(S); ++c) val[S + c] = to_bf16(sv[c] * sc[c]);
     for (int c = 4 * S + 1; c < C; ++c) val[c] = 0;
     if (C % 8 == 0 && ((uintptr_t)in & 15) == 0) {   // three species: 16 channels, two 16-byte stores
         uint4* o = reinterpret_cast<uint4*>(in + i * C);
@@ -1547,7 +1552,7 @@ __global__ void k_ws_target(ProbDev pd, int S, int bx, int by, int bz, const dou
     const int x = (int)(i % gx);
     const int y = (int)((i / gx) % gy);
     const int z = (int)(i / ((long long)gx * gy));
-    const bool dom = x < bx && y < by && z < bz && stat[i * ws_static_channels(S) + 3 * S] > 0.f;
+    const bool dom = x < bx && y < by && z < bz && stat[3 * S * G + i] > 0.f;   // the mask channel
     const long long v = ((long long)(pd.lo[2] + z) * pd.ny + (pd.lo[1] + y)) * pd.nx + (pd.lo[0] + x);
     for (int s = 0; s < S; ++s) {
         float t = 0.f;

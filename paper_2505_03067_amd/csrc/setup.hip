@@ -294,8 +294,8 @@ static void free_padded(T*& p) {
 }
 
 // Static input channels of the warm-start network on the box grid (box sizes rounded
-// up to multiples of 8): per grid voxel k[0..S), D[0..S), s[0..S), mask; zero outside
-// the box.
+// up to multiples of 8), channel-major (stat[c G + i] for grid voxel i of G): k[0..S),
+// D[0..S), s[0..S), mask; zero outside the box.
 __global__ void k_ws_static(const uint8_t* mask, const double* D, const double* k, const double* src, BoxGeo g,
                             int gx, int gy, int gz, int S, long long nvox, float* stat) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -305,18 +305,17 @@ __global__ void k_ws_static(const uint8_t* mask, const double* D, const double* 
     const int y = (int)((i / gx) % gy);
     const int z = (int)(i / ((long long)gx * gy));
     const int C = ws_static_channels(S);
-    float* o = stat + i * C;
     if (x >= g.bx || y >= g.by || z >= g.bz) {
-        for (int c = 0; c < C; ++c) o[c] = 0.f;
+        for (int c = 0; c < C; ++c) stat[c * G + i] = 0.f;
         return;
     }
     const long long v = ((long long)(g.z0 + z) * g.ny + (g.y0 + y)) * g.nx + (g.x0 + x);
     for (int s = 0; s < S; ++s) {
-        o[s] = (float)k[s * nvox + v];
-        o[S + s] = (float)D[s * nvox + v];
-        o[2 * S + s] = (float)src[s * nvox + v];
+        stat[s * G + i] = (float)k[s * nvox + v];
+        stat[(S + s) * G + i] = (float)D[s * nvox + v];
+        stat[(2 * S + s) * G + i] = (float)src[s * nvox + v];
     }
-    o[3 * S] = mask[v] ? 1.f : 0.f;
+    stat[3 * S * G + i] = mask[v] ? 1.f : 0.f;
 }
 
 // The network's voxel tiles on the warm-start grid (16 x 4 x 4, as its convolutions
@@ -327,16 +326,18 @@ constexpr int kWsTX = 16, kWsTY = 4, kWsTZ = 4;
 __global__ void k_ws_tile_domain(const float* stat, int S, int gx, int gy, int gz, uint8_t* flag) {
     const int ntx = (gx + kWsTX - 1) / kWsTX, nty = gy / kWsTY, ntz = gz / kWsTZ;
     const int nt = ntx * nty * ntz;
-    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int t = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);   // one wave per tile
     if (t >= nt) return;
+    const int lane = threadIdx.x & 63;
     const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-    const int C = ws_static_channels(S);
-    uint8_t any = 0;
-    for (int v = 0; v < kWsTX * kWsTY * kWsTZ && !any; ++v) {
+    const float* m = stat + (long long)3 * S * gx * gy * gz;   // the mask channel
+    bool hit = false;
+    for (int v = lane; v < kWsTX * kWsTY * kWsTZ; v += 64) {
         const int x = tx * kWsTX + v % kWsTX, y = ty * kWsTY + (v / kWsTX) % kWsTY, z = tz * kWsTZ + v / (kWsTX * kWsTY);
-        if (x < gx && stat[(((long long)z * gy + y) * gx + x) * C + 3 * S] > 0.f) any = 1;
+        if (x < gx && m[((long long)z * gy + y) * gx + x] > 0.f) hit = true;
     }
-    flag[nt + t] = any;
+    const bool any = __ballot(hit) != 0;
+    if (lane == 0) flag[nt + t] = any ? 1 : 0;
 }
 __global__ void k_ws_tile_near(int gx, int gy, int gz, uint8_t* flag) {
     const int ntx = (gx + kWsTX - 1) / kWsTX, nty = gy / kWsTY, ntz = gz / kWsTZ;
@@ -572,9 +573,8 @@ static int discretise(Ctx* c, ProbHost& ph, const BoxGeo& g, const uint8_t* mask
                 }
                 ph.cap_tiles = nt;
             }
-            const unsigned tb = (unsigned)((nt + 255) / 256);
-            k_ws_tile_domain<<<tb, 256, 0, st>>>(ph.stat, c->S, gx, gy, gz, ph.tf_dev);
-            k_ws_tile_near<<<tb, 256, 0, st>>>(gx, gy, gz, ph.tf_dev);
+            k_ws_tile_domain<<<(unsigned)((nt + 3) / 4), 256, 0, st>>>(ph.stat, c->S, gx, gy, gz, ph.tf_dev);
+            k_ws_tile_near<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(gx, gy, gz, ph.tf_dev);
             e = hipGetLastError();
             if (e == hipSuccess) e = hipMemcpyAsync(ph.tf_host, ph.tf_dev, 2 * nt, hipMemcpyDeviceToHost, st);
             if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (tile flags)");
