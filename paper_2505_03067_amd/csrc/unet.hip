@@ -178,9 +178,9 @@ static int ensure_acts(Net* n, int nb, int D, int H, int W) {
 // a multiple of the group count).
 // Resident blocks of k_conv<NTB, WL, GATED> on the device (registers and LDS
 // permitting), found once; the first call also grants the kernel its LDS.
-template <int NTB, bool WL, bool GATED, bool HEAD = false, bool LIST = false>
+template <int NTB, bool WL, bool GATED, bool HEAD = false, bool LIST = false, bool POOL = false>
 static hipError_t conv_slots(int* out) {
-    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD, LIST);
+    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD, LIST, POOL);
     static int slots = 0;
     static const hipError_t granted = [] {
         int dev = 0, cap = 0, cus = 0, per_cu = 0;
@@ -189,10 +189,11 @@ static hipError_t conv_slots(int* out) {
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess && cap < lds) e = hipErrorInvalidValue;
         if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, WL, GATED, HEAD, LIST>),
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv<NTB, WL, GATED, HEAD, LIST, POOL>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv<NTB, WL, GATED, HEAD, LIST>, 256, lds);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv<NTB, WL, GATED, HEAD, LIST, POOL>, 256,
+                                                             lds);
         slots = std::max(1, cus) * std::max(1, per_cu);
         return e;
     }();
@@ -213,27 +214,27 @@ static long long conv_grid(const ConvArgs& a, int nsplit, int slots) {
     return grid;
 }
 
-template <int NTB, bool WL, bool GATED, bool HEAD = false, bool LIST = false>
+template <int NTB, bool WL, bool GATED, bool HEAD = false, bool LIST = false, bool POOL = false>
 static int launch_conv(const ConvArgs& a, hipStream_t st) {
-    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD, LIST);
+    constexpr int lds = conv_lds_bytes(NTB, WL, HEAD, LIST, POOL);
     int slots = 0;
-    const hipError_t granted = conv_slots<NTB, WL, GATED, HEAD, LIST>(&slots);
+    const hipError_t granted = conv_slots<NTB, WL, GATED, HEAD, LIST, POOL>(&slots);
     if (granted != hipSuccess) return hip_fail(granted, "U-Net convolution LDS");
     const long long grid = conv_grid(a, a.nt / NTB, slots);
-    k_conv<NTB, WL, GATED, HEAD, LIST><<<(unsigned)grid, 256, lds, st>>>(a);
+    k_conv<NTB, WL, GATED, HEAD, LIST, POOL><<<(unsigned)grid, 256, lds, st>>>(a);
     return MPM_OK;
 }
 
 // k_conv_staged<1> (16 input channels, one output tile, no gate; static LDS): one block
 // per resident slot, as launch_conv.
-template <bool HEAD = false, bool LIST = false>
+template <bool HEAD = false, bool LIST = false, bool POOL = false>
 static hipError_t staged_slots(int* out) {
     static int slots = 0;
     static const hipError_t granted = [] {
         int dev = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_staged<1, HEAD, LIST>, 256, 0);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_staged<1, HEAD, LIST, POOL>, 256, 0);
         slots = std::max(1, cus) * std::max(1, per_cu);
         return e;
     }();
@@ -241,17 +242,30 @@ static hipError_t staged_slots(int* out) {
     return granted;
 }
 
+// 16-channel input and one output tile: k_conv_staged once every block has two or more
+// tiles (16 -> 16 on 128^3: 50.5 -> 42.6 us; on small grids its longer start costs more
+// than it saves), else k_conv.
+template <bool HEAD, bool LIST, bool POOL>
+static int launch_one_tile(const ConvArgs& a, long long tiles, hipStream_t st) {
+    int slots = 0;
+    const hipError_t e = staged_slots<HEAD, LIST, POOL>(&slots);
+    if (e != hipSuccess) return hip_fail(e, "U-Net convolution occupancy");
+    if (tiles * a.nt < 2LL * slots) return launch_conv<1, false, false, HEAD, LIST, POOL>(a, st);
+    k_conv_staged<1, HEAD, LIST, POOL><<<(unsigned)conv_grid(a, a.nt, slots), 256, 0, st>>>(a);
+    return MPM_OK;
+}
+
 // Output tiles per block: two for a 16-channel input with an even tile count (each A
 // fragment read from LDS then feeds two MFMAs); for wider inputs two when the grid has
 // tiles for at least two rounds of the resident blocks (64^3 layers with 32 outputs:
 // 29.3 -> 26.4 us), else one (three blocks per CU instead of two, which the smaller
-// grids need to fill the device).
+// grids need to fill the device).  The fused head and tile lists go with one output
+// tile, the fused pooling with every variant but the gated ones.
 static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
     if (nt < 1 || nt > 8 || a.cin_p % 16 || a.cin_p < 16 || (a.x2 && (a.gate || a.c1 % 16))) {
         set_error("unsupported channel count in the U-Net");
         return MPM_EINVAL;
     }
-    // the fused head needs one 16-channel output tile, the variants below that take it
     if (a.hout && (nt != 1 || a.cin_p != 16 || a.gate || a.x2 || a.y || a.hcout < 1 || a.hcout > 4)) {
         set_error("the fused head needs a 16 -> 16 convolution and at most 4 outputs");
         return MPM_EINVAL;
@@ -260,8 +274,12 @@ static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
         set_error("a tile list needs one sample and one output tile (with the fused head for 16 inputs)");
         return MPM_EINVAL;
     }
+    if (a.yp && (a.gate || a.hout || a.tlist || a.x2 || !a.y || (a.D | a.H | a.W) & 1)) {
+        set_error("the fused pooling needs even grid sizes and a plain convolution");
+        return MPM_EINVAL;
+    }
     a.nt = nt;
-    const bool one = a.cin_p == 16;
+    const bool one = a.cin_p == 16, pool = a.yp != nullptr;
     if (a.tlist && a.tcount == 0) return MPM_OK;   // nothing listed
     if (a.tlist && !one) return launch_conv<1, true, false, false, true>(a, st);
     if (a.gate) {
@@ -272,31 +290,21 @@ static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
                                     : (long long)a.n * ((a.D + kTZ - 1) / kTZ) * ((a.H + kTY - 1) / kTY) *
                                           ((a.W + kTX - 1) / kTX);
     if (one && nt % 2) {
-        // asynchronous staging pays once every block has two or more tiles (16 -> 16 on
-        // 128^3: 50.5 -> 42.6 us; on small grids its longer start costs more than it saves)
-        const bool head = a.hout != nullptr, list = a.tlist != nullptr;
-        int slots = 0;
-        const hipError_t e = list ? staged_slots<true, true>(&slots)
-                             : head ? staged_slots<true>(&slots) : staged_slots<false>(&slots);
-        if (e != hipSuccess) return hip_fail(e, "U-Net convolution occupancy");
-        if (tiles * nt < 2LL * slots)
-            return list   ? launch_conv<1, false, false, true, true>(a, st)
-                   : head ? launch_conv<1, false, false, true>(a, st)
-                          : launch_conv<1, false, false>(a, st);
-        const long long grid = conv_grid(a, nt, slots);
-        if (list) k_conv_staged<1, true, true><<<(unsigned)grid, 256, 0, st>>>(a);
-        else if (head) k_conv_staged<1, true><<<(unsigned)grid, 256, 0, st>>>(a);
-        else k_conv_staged<1><<<(unsigned)grid, 256, 0, st>>>(a);
-        return MPM_OK;
+        if (a.tlist) return launch_one_tile<true, true, false>(a, tiles, st);
+        if (a.hout) return launch_one_tile<true, false, false>(a, tiles, st);
+        if (pool) return launch_one_tile<false, false, true>(a, tiles, st);
+        return launch_one_tile<false, false, false>(a, tiles, st);
     }
-    if (one) return launch_conv<2, false, false>(a, st);
+    if (one) return pool ? launch_conv<2, false, false, false, false, true>(a, st) : launch_conv<2, false, false>(a, st);
     if (nt % 2 == 0) {
         int slots = 0;
-        const hipError_t e = conv_slots<2, true, false>(&slots);
+        const hipError_t e = pool ? conv_slots<2, true, false, false, false, true>(&slots)
+                                  : conv_slots<2, true, false>(&slots);
         if (e != hipSuccess) return hip_fail(e, "U-Net convolution LDS");
-        if (tiles * (nt / 2) >= 2LL * slots) return launch_conv<2, true, false>(a, st);
+        if (tiles * (nt / 2) >= 2LL * slots)
+            return pool ? launch_conv<2, true, false, false, false, true>(a, st) : launch_conv<2, true, false>(a, st);
     }
-    return launch_conv<1, true, false>(a, st);
+    return pool ? launch_conv<1, true, false, false, false, true>(a, st) : launch_conv<1, true, false>(a, st);
 }
 
 static ConvArgs conv_args(const Net* n, int lvl) {
@@ -335,12 +343,7 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
     int hch = l0.cin_p;
     int li = 0;
     for (int lvl = 0; lvl < L; ++lvl) {
-        if (lvl > 0) {
-            const long long Pl = P0 >> (3 * lvl);
-            k_pool2<<<blocks_for(Pl * hch / 8), 256, 0, st>>>(h, hch, hch, nb, D >> (lvl - 1), H >> (lvl - 1),
-                                                         W >> (lvl - 1), n->pooled[lvl]);
-            h = n->pooled[lvl];
-        }
+        if (lvl > 0) h = n->pooled[lvl];   // pooled by the previous level's second convolution
         for (int r = 0; r < 2; ++r, ++li) {
             const ConvL& c = n->layers[li];
             ConvArgs a = conv_args(n, lvl);
@@ -353,6 +356,7 @@ int net_forward(Net* n, const uint16_t* in, int nb, int D, int H, int W, float* 
             a.ldy = c.cout;
             a.cout = c.cout;
             a.relu = 1;
+            if (r == 1 && lvl + 1 < L) a.yp = n->pooled[lvl + 1];   // the next level's input
             if ((rc = conv_dispatch(a, c.cout_p / 16, st))) return rc;
             h = n->act[li];
             hch = c.cout;

@@ -56,6 +56,9 @@ struct ConvArgs {
     // tz << 20; the other tiles' outputs are left as they are
     const int* tlist;
     int tcount;
+    // optional 2x2x2 average pooling of the BF16 output fused into the epilogue: yp
+    // [n][D/2][H/2][W/2][cout] (D, H, W even), in the order of k_pool2
+    uint16_t* yp;
 };
 
 // LDS floats of the fused head's weights (16 x up to 4) and biases
@@ -145,9 +148,15 @@ __host__ __device__ constexpr int conv_x_bytes() { return kHV * kCS * 2; }
 // the block's weights (one chunk's) staged in LDS after the halo tile, except with one
 // chunk and one output tile (then they live in registers); then the block's bias values
 __host__ __device__ constexpr int conv_w_bytes(int ntb, bool wl) { return wl || ntb > 1 ? kSteps * ntb * 1024 : 0; }
-__host__ __device__ constexpr int conv_lds_bytes(int ntb, bool wl, bool head = false, bool list = false) {
-    // + the block's bias values, the fused head's parameters and the block's tile list
-    return conv_x_bytes() + conv_w_bytes(ntb, wl) + 64 * ntb + (head ? 4 * kHeadLds : 0) + (list ? 4 * kListMax : 0);
+// LDS bytes of the fused pooling's exchange between the waves of a plane pair: per pair
+// and lane, two pooled rows of four channels per output tile
+__host__ __device__ constexpr int conv_pool_bytes(int ntb) { return 2 * 64 * 8 * ntb * 4; }
+__host__ __device__ constexpr int conv_lds_bytes(int ntb, bool wl, bool head = false, bool list = false,
+                                                 bool pool = false) {
+    // + the block's bias values, the fused head's parameters, the block's tile list and
+    // the pooling exchange
+    return conv_x_bytes() + conv_w_bytes(ntb, wl) + 64 * ntb + (head ? 4 * kHeadLds : 0) + (list ? 4 * kListMax : 0) +
+           (pool ? conv_pool_bytes(ntb) : 0);
 }
 
 // Stage the fused head's parameters (a.hout set) in LDS: weights [16][4] at 0 (zero past
@@ -484,13 +493,17 @@ __device__ inline void conv_chunk(const char* xs, uint32_t lb, const uint4 (&bre
 // head (NTB = 1, head_l its parameters in LDS), lane group g = l / 16 forms the partial
 // sums of its four channels, the groups' sums are added pairwise across lanes (g with
 // g ^ 1, then with g ^ 2), and group g stores output g (FP32).
-template <int NTB, bool HEAD = false>
+template <int NTB, bool HEAD = false, bool POOL = false>
 __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int tb, const float* bias_l, bool vec,
-                                     f32x4 (&acc)[4][NTB], const float* head_l = nullptr) {
+                                     f32x4 (&acc)[4][NTB], const float* head_l = nullptr, float* pool_l = nullptr) {
     static_assert(!HEAD || NTB == 1, "the fused head takes one output tile");
+    static_assert(!(HEAD && POOL), "the head and the pooling are not fused together");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15;
     const long long ob = t.sbase + ((long long)t.z0 * a.H + t.y0) * a.W + t.x0;   // the tile's origin
+    // pooling: sums over the voxel pair x, x + 1 (lanes m, m ^ 1), then over the row pair
+    // (M tiles 2 r, 2 r + 1), per pooled row r and output tile
+    float ps[POOL ? 2 : 1][NTB][4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         const bool inb = t.out || (t.x0 + m < a.W && t.y0 + mt < a.H && t.z0 + wave < a.D);
@@ -507,6 +520,16 @@ __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int t
                 if (a.relu) v[i] = fmaxf(v[i], 0.f);
             }
             acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (POOL) {   // every lane takes part in the exchange
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float rb = (float)(__bf16)v[i];   // the stored value
+                    // quad_perm [1, 0, 3, 2]: the value of lane l ^ 1
+                    const float px = rb + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(rb), 0xB1, 0xF, 0xF, false));
+                    if (mt % 2 == 0) ps[mt / 2][nt][i] = px;
+                    else ps[mt / 2][nt][i] += px;
+                }
+            }
             if constexpr (HEAD) {   // every lane takes part in the exchanges; y is not stored
                 const int g = lane >> 4;
                 float r[4], tot[4];
@@ -543,6 +566,49 @@ __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int t
             }
         }
     }
+    if constexpr (POOL) {
+        // plane pairs: waves 2 q and 2 q + 1 hold planes z0 + 2 q and z0 + 2 q + 1; the odd
+        // wave hands its sums over LDS, the even one adds them and stores the pooled voxel
+        // (lanes with even m)
+        float* xl = pool_l + ((wave >> 1) * 64 + lane) * (8 * NTB);
+        if (wave & 1) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int nt = 0; nt < NTB; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) xl[(r * NTB + nt) * 4 + i] = ps[r][nt][i];
+        }
+        __syncthreads();
+        if (!(wave & 1)) {
+            const int PD = a.D >> 1, PH = a.H >> 1, PW = a.W >> 1;
+            const int px = (t.x0 >> 1) + (m >> 1), pz = (t.z0 >> 1) + (wave >> 1);
+            const bool xok = (m & 1) == 0 && px < PW && pz < PD;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int py = (t.y0 >> 1) + r;
+                const bool ok = xok && py < PH;
+                const long long q = (t.sbase >> 3) + ((long long)pz * PH + py) * PW + px;
+#pragma unroll
+                for (int nt = 0; nt < NTB; ++nt) {
+                    const int co = (tb + nt) * 16 + 4 * (lane >> 4);
+                    float sv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) sv[i] = (ps[r][nt][i] + xl[(r * NTB + nt) * 4 + i]) * 0.125f;
+                    if (!ok) continue;
+                    if (a.cout % 4 == 0 && co + 4 <= a.cout) {   // one 8-byte word (8-byte aligned)
+                        const bf16x2 lo = {(__bf16)sv[0], (__bf16)sv[1]}, hi = {(__bf16)sv[2], (__bf16)sv[3]};
+                        *reinterpret_cast<uint2*>(a.yp + q * a.cout + co) =
+                            make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (co + i < a.cout) a.yp[q * a.cout + co + i] = __builtin_bit_cast(uint16_t, (__bf16)sv[i]);
+                    }
+                }
+            }
+        }
+    }
 }
 
 // WL: the weights change with the chunk (more than 16 input channels); GATED: the input
@@ -552,7 +618,7 @@ __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int t
 // next item's prefetched input does not also wait for the stores of this one.  Three
 // blocks per CU for the chunk-staged weights (WL); two for the others, whose registers
 // (the weights held in registers, or the ReLU gates) would not fit three.
-template <int NTB, bool WL, bool GATED, bool HEAD = false, bool LIST = false>
+template <int NTB, bool WL, bool GATED, bool HEAD = false, bool LIST = false, bool POOL = false>
 __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_conv(ConvArgs a) {
     extern __shared__ uint4 xs_dyn[];
     char* xs = reinterpret_cast<char*>(xs_dyn);
@@ -567,6 +633,7 @@ __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_con
     float* bias_l = reinterpret_cast<float*>(xs + conv_x_bytes() + conv_w_bytes(NTB, WL));
     float* head_l = bias_l + 16 * NTB;   // (one output tile only)
     int* tl = reinterpret_cast<int*>(head_l + (HEAD ? kHeadLds : 0));
+    float* pool_l = reinterpret_cast<float*>(tl + (LIST ? kListMax : 0));
     // the block's tiles: bid / nsplit, then every gridDim.x / nsplit-th (of the grid, or
     // of the tile list)
     ConvCursor cur = conv_start<LIST>(a, bid / nsplit, gridDim.x / nsplit, tl);
@@ -623,7 +690,7 @@ __global__ __launch_bounds__(256, (NTB == 1 && WL && !GATED) ? 3 : 2) void k_con
         const ConvTile tn = nc == 0 ? conv_tile(a, nxt) : t;
         if (more) conv_fetch<NTB, WL, GATED>(a, tn, 16 * nc, tb, ln, regs);   // in flight during the MFMAs
         conv_chunk<NTB, BREG>(xs, lb, breg, acc);
-        if (chunk == nchunk - 1) conv_epilogue<NTB, HEAD>(a, t, tb, bias_l, vec, acc, head_l);
+        if (chunk == nchunk - 1) conv_epilogue<NTB, HEAD, POOL>(a, t, tb, bias_l, vec, acc, head_l, pool_l);
         if (!more) break;
         t = tn;
         cur = nxt;
@@ -659,7 +726,7 @@ __device__ inline void conv_stage(const ConvArgs& a, const ConvTile& t, const Co
 // item j, so its global loads overlap the MFMAs of item j + 1 and nothing passes through
 // registers (16 -> 16 channels on 128^3: 49 -> 42 us).  Same work split, results and
 // epilogue as k_conv.
-template <int NTB, bool HEAD = false, bool LIST = false>
+template <int NTB, bool HEAD = false, bool LIST = false, bool POOL = false>
 __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs a) {
     constexpr int HB = kHV * kCS * 2;
     __shared__ __attribute__((aligned(16))) char h0[HB];
@@ -668,6 +735,7 @@ __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs 
     __shared__ __attribute__((aligned(16))) float bias_l[16 * NTB];
     __shared__ __attribute__((aligned(16))) float head_l[HEAD ? kHeadLds : 1];
     __shared__ int tl[LIST ? kListMax : 1];
+    __shared__ float pool_l[POOL ? conv_pool_bytes(NTB) / 4 : 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nsplit = a.nt / NTB;
@@ -724,7 +792,7 @@ __global__ __launch_bounds__(256, NTB == 1 ? 3 : 2) void k_conv_staged(ConvArgs 
         if (scur.n < a.n) conv_stage(a, st, ln, hn);
         conv_next<LIST>(a, scur, tl);
         st = conv_tile(a, scur);
-        conv_epilogue<NTB, HEAD>(a, t, tb, bias_l, vec, acc, head_l);
+        conv_epilogue<NTB, HEAD, POOL>(a, t, tb, bias_l, vec, acc, head_l, pool_l);
         conv_next<LIST>(a, cur, tl);
         if (cur.n >= a.n) return false;
         t = conv_tile(a, cur);
@@ -967,17 +1035,18 @@ __global__ void k_pool2(const uint16_t* x, int ldx, int c, int n, int D, int H, 
     const int g = (int)(i % G);
     const long long po = i / G;
     const Vox v = decode(po, d, h, w);
-    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // children k = (z, y, x) bits, summed pairwise: x pairs, then y, then z (the order of
+    // the pooling fused into the convolution epilogue)
+    float f[8][8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const long long q = (((long long)v.b * D + 2 * v.z + (k >> 2)) * H + 2 * v.y + ((k >> 1) & 1)) * W + 2 * v.x + (k & 1);
-        float f[8];
-        unpack8(*reinterpret_cast<const uint4*>(x + q * ldx + 8 * g), f);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) s[e] += f[e];
+        unpack8(*reinterpret_cast<const uint4*>(x + q * ldx + 8 * g), f[k]);
     }
+    float s[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) s[e] *= 0.125f;
+    for (int e = 0; e < 8; ++e)
+        s[e] = (((f[0][e] + f[1][e]) + (f[2][e] + f[3][e])) + ((f[4][e] + f[5][e]) + (f[6][e] + f[7][e]))) * 0.125f;
     *reinterpret_cast<uint4*>(y + po * c + 8 * g) = pack8(s);
 }
 

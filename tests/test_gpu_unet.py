@@ -205,6 +205,35 @@ def test_inference_pass_matches_forward(widths, shape):
     net.close()
 
 
+@pytest.mark.parametrize("widths,shape", [([16, 32, 64, 64], (2, 8, 16, 24)), ([16, 32, 64, 64], (1, 128, 128, 128)),
+                                          ([16, 32, 48], (1, 8, 12, 20))])
+def test_fused_pooling_matches_pool_kernel(widths, shape):
+    """The pooling each encoder level's second convolution does in its epilogue equals
+    k_pool2 (MPM_OP_POOL) on the stored BF16 output bit for bit: grids that leave
+    partial voxel tiles, the 128^3 grid (the asynchronously staged kernel at the first
+    level, the chunk-staged kernel with two output tiles at the second), and a
+    three-level net."""
+    torch = require_gpu()
+    import paper_2505_03067_amd as m
+    import paper_2505_03067_amd.mpm as b
+    net = m.Net(16, 3, widths, seed=23)
+    g = torch.Generator().manual_seed(9)
+    x = torch.randn(tuple(shape) + (16,), generator=g).to(torch.bfloat16).view(torch.int16).cuda()
+    out = torch.empty(tuple(shape) + (3,), dtype=torch.float32, device="cuda")
+    net.forward(x, out)
+    n, d, h, w = shape
+    for lvl in range(1, len(widths)):
+        fine = (n, d >> (lvl - 1), h >> (lvl - 1), w >> (lvl - 1))
+        c = widths[lvl - 1]
+        act = net.debug_tensor(b.MPM_NT_ACT, 2 * (lvl - 1) + 1)
+        got = net.debug_tensor(b.MPM_NT_POOLED, lvl)
+        want = torch.empty_like(got)
+        net.debug_op(b.MPM_OP_POOL, fine, c, 0, act, None, want)
+        assert got.abs().sum() > 0
+        assert torch.equal(got, want), lvl
+    net.close()
+
+
 def _tensor(net, kind, index, shape, ch):
     t = net.debug_tensor(kind, index).cpu().numpy().view(np.uint16).astype(np.uint32) << 16
     return t.view(np.float32).astype(np.float64).reshape(tuple(shape) + (ch,))
