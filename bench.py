@@ -406,8 +406,8 @@ def cpu_baseline(prob, box, c_start, gpu_after, tol, budget_s, threads=1):
             c, _ = implicit_step(c, prob.mask, prob.D, prob.k, prob.src, prob.c_b, box,
                                  prob.dt, prob.h, solver="gmres", tol=tol, restart=30)
             done += 1
-            g = gpu_after[done - 1]
-            errs.append([float(np.linalg.norm(g[s][sl][mb] - c[s][sl][mb]) /
+            g = gpu_after[done - 1]   # the GPU's fields on the box
+            errs.append([float(np.linalg.norm(g[s][mb] - c[s][sl][mb]) /
                                np.linalg.norm(c[s][sl][mb])) for s in range(prob.nspecies)])
             if time.perf_counter() - t0 >= budget_s:
                 break
@@ -986,12 +986,16 @@ def main():
 
     if args.cpu_seconds > 0:
         # replay the first steps of the timed run on the GPU (deterministic) to compare
+        # (the fields on the box only, as many steps as about 2 GB of host memory holds, at
+        # most 32: the sample ends at the time budget or there)
         s3 = gpu_solver(m, prob, t, box, precision, args.graph, not args.unbatched, args.tile, ortho)
         f3 = c_start.clone()
         after = []
-        for _ in range(min(args.steps, 8)):
+        (x0, y0, z0), (x1, y1, z1) = box
+        box_bytes = prob.nspecies * (x1 - x0) * (y1 - y0) * (z1 - z0) * 8
+        for _ in range(max(2, min(args.steps, 32, int(2e9 // box_bytes)))):
             s3.step([f3], tol)
-            after.append(f3.cpu().numpy())
+            after.append(f3[:, z0:z1, y0:y1, x0:x1].cpu().numpy())
         s3.close()
         done, cpu_s, errs = cpu_baseline(prob, box, c_start.cpu().numpy(), after, tol,
                                          args.cpu_seconds)
