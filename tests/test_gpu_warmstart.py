@@ -167,59 +167,73 @@ def test_in_step_input_matches_ws_pair(S, extrap):
     assert checked == (6 if extrap else 7)
 
 
-@pytest.mark.parametrize("extrap", [False, True])
-def test_in_step_warm_start_matches_definition(extrap):
+def _masked_problem(seed, dims, S, cut):
+    """A random problem whose domain leaves many of the network's 16 x 4 x 4 tiles empty:
+    no domain at x < cut[0] or z < cut[1]."""
+    p = random_problem(seed, dims, S=S, fill=0.7)
+    p.mask[:, :, :cut[0]] = 0
+    p.mask[:cut[1]] = 0
+    return p
+
+
+@pytest.mark.parametrize("S,P,extrap", [(3, 1, False), (3, 1, True), (4, 2, False)])
+def test_in_step_warm_start_matches_definition(S, P, extrap):
     """The whole warm start of a step against its definition: the network's full forward
     pass on the input mpm_ws_pair builds, x0 = x_b + out * out_scale on the domain voxels,
     and the true residual of x0 relative to that of c^n from the oracle's assembly,
     against the step's rel_res_warm / rel_res_initial.  The step's inference pass computes
-    only the tiles of the last level that the domain's outputs read; the mask here leaves
-    many of the grid's 16 x 4 x 4 tiles without a domain voxel, so a tile it skipped
-    wrongly would leave a stale output on the domain."""
+    only the tiles of the last level that the domain's outputs read, from each problem's
+    own lists; the masks leave many of the grid's 16 x 4 x 4 tiles without a domain voxel,
+    so a tile skipped wrongly would leave a stale output on the domain.  Four species:
+    the head with four outputs in the last convolution's epilogue, two problems in one
+    context."""
     torch = require_gpu()
     import paper_2505_03067_amd as m
     from paper_2505_03067_amd.train import input_scales
-    p = random_problem(123, (48, 40, 36), S=3, fill=0.7)
-    p.mask[:, :, :26] = 0     # no domain at x < 26 or z < 14
-    p.mask[:14] = 0
-    box = ((0, 0, 0), (48, 40, 36))
-    sl = box_slice(box)
-    mb = p.mask[sl].astype(bool)
-    ex, ey, ez = 48, 40, 36
-    d = to_dev(p)
-    out_scale = [0.05, 0.05, 1e-3]
-    scales = input_scales(3, out_scale)
-    net = m.Net(16, 3, [16, 32, 64, 64], seed=31)
-    f = torch.from_numpy(p.c0).cuda()
+    probs = [_masked_problem(123, (48, 40, 36), S, (26, 14)),
+             _masked_problem(124, (40, 44, 28), S, (9, 19))][:P]
+    boxes = [((0, 0, 0), p.dims) for p in probs]
+    out_scale = [0.05, 0.05, 1e-3, 2e-3][:S]
+    scales = input_scales(S, out_scale)
+    C = 5 * S + 1
+    net = m.Net(C, S, [16, 32, 64, 64], seed=31)
+    fs = [torch.from_numpy(p.c0).cuda() for p in probs]
     checked = 0
-    with m.Solver(3, 1, warm_start=m.MPM_WS_NET_EXTRAP if extrap else m.MPM_WS_NET) as s:
-        s.setup(0, box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
+    with m.Solver(S, P, warm_start=m.MPM_WS_NET_EXTRAP if extrap else m.MPM_WS_NET) as s:
+        for i, (p, box) in enumerate(zip(probs, boxes)):
+            d = to_dev(p)
+            s.setup(i, box, d["mask"], d["D"], d["k"], d["src"], p.c_b, p.dt, p.h)
         s.attach(net, scales, out_scale)
-        gx, gy, gz = s.ws_grid(0)
-        prev = None
+        prev = [None] * P
         for n in range(4):
-            old = f.clone()
-            s.step([f], 1e-10)
-            st = [s.stats(0, sp) for sp in range(3)]
-            if extrap and prev is None:
+            old = [f.clone() for f in fs]
+            s.step(fs, 1e-10)
+            st = [[s.stats(i, sp) for sp in range(S)] for i in range(P)]
+            if extrap and prev[0] is None:
                 prev = old
                 continue
-            inp = torch.empty((1, gz, gy, gx, 16), dtype=torch.int16, device="cuda")
-            tgt = torch.empty((gz, gy, gx, 3), dtype=torch.float32, device="cuda")
-            s.ws_pair(0, old, f, scales, out_scale, inp[0], tgt, c_prev=prev if extrap else None)
-            out = torch.empty((1, gz, gy, gx, 3), dtype=torch.float32, device="cuda")
-            net.forward(inp, out)
-            o = out[0].cpu().numpy()[:ez, :ey, :ex]
-            c = old.cpu().numpy()
-            xb = 2.0 * c - prev.cpu().numpy() if extrap else c
-            for sp in range(3):
-                A, q = assemble(mb, p.D[sp][sl], p.k[sp][sl], p.src[sp][sl], float(p.c_b[sp]), p.dt, p.h)
-                cn = c[sp][sl][mb]
-                b = cn + q
-                x0 = xb[sp][sl][mb] + (o[..., sp][mb].astype(np.float32) * np.float32(out_scale[sp])).astype(np.float64)
-                want = np.linalg.norm(b - A @ x0) / np.linalg.norm(b - A @ cn)
-                got = st[sp]["rel_res_warm"] / st[sp]["rel_res_initial"]
-                assert abs(got - want) <= 1e-9 * want, (n, sp, got, want)
+            for i, (p, box) in enumerate(zip(probs, boxes)):
+                gx, gy, gz = s.ws_grid(i)
+                ex, ey, ez = p.dims
+                sl = box_slice(box)
+                mb = p.mask[sl].astype(bool)
+                inp = torch.empty((1, gz, gy, gx, C), dtype=torch.int16, device="cuda")
+                tgt = torch.empty((gz, gy, gx, S), dtype=torch.float32, device="cuda")
+                s.ws_pair(i, old[i], fs[i], scales, out_scale, inp[0], tgt, c_prev=prev[i] if extrap else None)
+                out = torch.empty((1, gz, gy, gx, S), dtype=torch.float32, device="cuda")
+                net.forward(inp, out)
+                o = out[0].cpu().numpy()[:ez, :ey, :ex]
+                c = old[i].cpu().numpy()
+                xb = 2.0 * c - prev[i].cpu().numpy() if extrap else c
+                for sp in range(S):
+                    A, q = assemble(mb, p.D[sp][sl], p.k[sp][sl], p.src[sp][sl], float(p.c_b[sp]), p.dt, p.h)
+                    cn = c[sp][sl][mb]
+                    b = cn + q
+                    x0 = xb[sp][sl][mb] + (o[..., sp][mb].astype(np.float32) *
+                                           np.float32(out_scale[sp])).astype(np.float64)
+                    want = np.linalg.norm(b - A @ x0) / np.linalg.norm(b - A @ cn)
+                    got = st[i][sp]["rel_res_warm"] / st[i][sp]["rel_res_initial"]
+                    assert abs(got - want) <= 1e-9 * want, (n, i, sp, got, want)
             checked += 1
             prev = old
     net.close()
