@@ -333,7 +333,8 @@ __global__ void k_ws_tile_domain(const float* stat, int S, int gx, int gy, int g
     const float* m = stat + (long long)3 * S * gx * gy * gz;   // the mask channel
     bool hit = false;
     for (int v = lane; v < kWsTX * kWsTY * kWsTZ; v += 64) {
-        const int x = tx * kWsTX + v % kWsTX, y = ty * kWsTY + (v / kWsTX) % kWsTY, z = tz * kWsTZ + v / (kWsTX * kWsTY);
+        const int x = tx * kWsTX + v % kWsTX, y = ty * kWsTY + (v / kWsTX) % kWsTY;
+        const int z = tz * kWsTZ + v / (kWsTX * kWsTY);
         if (x < gx && m[((long long)z * gy + y) * gx + x] > 0.f) hit = true;
     }
     const bool any = __ballot(hit) != 0;

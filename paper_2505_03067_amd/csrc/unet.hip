@@ -234,7 +234,8 @@ static hipError_t staged_slots(int* out) {
         int dev = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_staged<1, HEAD, LIST, POOL>, 256, 0);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_staged<1, HEAD, LIST, POOL>, 256, 0);
         slots = std::max(1, cus) * std::max(1, per_cu);
         return e;
     }();
@@ -295,7 +296,8 @@ static int conv_dispatch(ConvArgs a, int nt, hipStream_t st) {
         if (pool) return launch_one_tile<false, false, true>(a, tiles, st);
         return launch_one_tile<false, false, false>(a, tiles, st);
     }
-    if (one) return pool ? launch_conv<2, false, false, false, false, true>(a, st) : launch_conv<2, false, false>(a, st);
+    if (one)
+        return pool ? launch_conv<2, false, false, false, false, true>(a, st) : launch_conv<2, false, false>(a, st);
     if (nt % 2 == 0) {
         int slots = 0;
         const hipError_t e = pool ? conv_slots<2, true, false, false, false, true>(&slots)
