@@ -570,14 +570,15 @@ __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int t
         // plane pairs: waves 2 q and 2 q + 1 hold planes z0 + 2 q and z0 + 2 q + 1; the odd
         // wave hands its sums over LDS, the even one adds them and stores the pooled voxel
         // (lanes with even m)
-        float* xl = pool_l + ((wave >> 1) * 64 + lane) * (8 * NTB);
+        // value k of the pair's lane at xl[128 k]: consecutive lanes, consecutive banks
+        float* xl = pool_l + (wave >> 1) * 64 + lane;
         if (wave & 1) {
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
                 for (int nt = 0; nt < NTB; ++nt)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) xl[(r * NTB + nt) * 4 + i] = ps[r][nt][i];
+                    for (int i = 0; i < 4; ++i) xl[128 * ((r * NTB + nt) * 4 + i)] = ps[r][nt][i];
         }
         __syncthreads();
         if (!(wave & 1)) {
@@ -594,7 +595,7 @@ __device__ inline void conv_epilogue(const ConvArgs& a, const ConvTile& t, int t
                     const int co = (tb + nt) * 16 + 4 * (lane >> 4);
                     float sv[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) sv[i] = (ps[r][nt][i] + xl[(r * NTB + nt) * 4 + i]) * 0.125f;
+                    for (int i = 0; i < 4; ++i) sv[i] = (ps[r][nt][i] + xl[128 * ((r * NTB + nt) * 4 + i)]) * 0.125f;
                     if (!ok) continue;
                     if (a.cout % 4 == 0 && co + 4 <= a.cout) {   // one 8-byte word (8-byte aligned)
                         const bf16x2 lo = {(__bf16)sv[0], (__bf16)sv[1]}, hi = {(__bf16)sv[2], (__bf16)sv[3]};
