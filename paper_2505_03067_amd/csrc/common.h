@@ -53,7 +53,6 @@ struct ProbDev {
     int lo[3];
     int gd[3];
     const float* wsout;    // network output on the grid [G][S] (or null)
-    const double* prev;    // c^{n-1} on the global unknowns (or null)
 };
 
 // One block of work: a contiguous range of one system's unknowns (global indices),
@@ -139,6 +138,8 @@ struct KArgs {
     double* b;             // FP64 right-hand side
     double* const* fields; // [P] lattice fields (device pointers)
     SysK* hsk;             // host-visible mirror of the status heads (pinned host memory)
+    double* pcur;          // where the gather also writes c^n for the next extrapolation (or null)
+    const double* pold;    // c^{n-1} on the global unknowns (extrapolated starts)
     long long ldv;
     int nslots;
     int S;

@@ -145,9 +145,11 @@ struct Ctx {
     double* d_lossp = nullptr;         // per-block partial sums of the warm-start loss
     double* h_lossp = nullptr;         // their pinned host copy
     size_t cap_lossp = 0;
-    double* prev = nullptr;            // c^n of the previous step on the global unknowns
+    double* prev = nullptr;            // two halves on the global unknowns: c^{n-1} and
+                                       // this step's c^n, which trade places every step
     size_t cap_prev = 0;
     size_t prev_n = 0;                 // elements in each half of prev
+    int prev_half = 0;                 // the half that holds c^{n-1}
     bool have_prev = false;
 
     // kernel timing hook

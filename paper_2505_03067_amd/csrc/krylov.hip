@@ -334,6 +334,10 @@ __global__ __launch_bounds__(kThreads) void k_gather(KArgs<T> a) {
             a.b[u0 + e] = bb[e];
             acc[0] += bb[e] * bb[e];
         }
+        if (a.pcur) {
+#pragma unroll
+            for (int e = 0; e < n; ++e) a.pcur[u0 + e] = cn[e];
+        }
     }
     block_partials<1>(acc, a.part + (long long)kRowB * a.nslots, a.nslots, blk.slot);
 }
@@ -1454,7 +1458,7 @@ __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, con
             if (mode == MPM_WS_NET)
                 w[e] = in ? (double)(pd.wsout[grid_index(pd, l0 + e) * a.S + wh.s] * os) : 0.0;
             else
-                w[e] = in ? pd.prev[u0 + e] : 0.0;
+                w[e] = in ? a.pold[u0 + e] : 0.0;
         }
 #pragma unroll
         for (int e = 0; e < n; ++e)
@@ -1519,11 +1523,6 @@ __global__ __launch_bounds__(kThreads) void k_ws_revert(KArgs<T> a) {
         const int l = (int)(u - wh.base);
         if (l < pd.N) a.x[u] = f[pd.vox[l]];
     }
-}
-
-__global__ void k_copy64(const double* src, double* dst, long long n) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
 }
 
 // x = 2 x - c_prev on the domain unknowns of the blocks' systems (x holds c_old gathered
@@ -2099,12 +2098,11 @@ int ensure_layout(Ctx* c) {
             pd[p].gd[d] = ph.gd[d];
         }
         pd[p].wsout = ph.wsout;
-        pd[p].prev = nullptr;
     }
     // previous-step values for the extrapolated start live on the global unknowns
     c->have_prev = false;
     if (extrap_warm_start(c)) {
-        // [0, need): c^{n-1}; [need, 2 need): this step's c^n
+        // two halves of need unknowns: c^{n-1} and this step's c^n (see prev_half)
         if (2 * need > c->cap_prev) {
             (void)hipFree(c->prev);
             c->prev = nullptr;
@@ -2117,7 +2115,6 @@ int ensure_layout(Ctx* c) {
             c->cap_prev = 2 * need;
         }
         c->prev_n = need;
-        for (int p = 0; p < c->P; ++p) pd[p].prev = c->prev;
     }
     c->h_probs = pd;
     MPM_HIP(hipMemcpyAsync(c->d_probs, pd.data(), c->P * sizeof(ProbDev), hipMemcpyHostToDevice, st));
@@ -2188,6 +2185,8 @@ static KArgs<T> make_args(Ctx* c, const Block* blocks) {
     a.b = c->b;
     a.fields = c->d_fields;
     a.hsk = c->hsk_dev;
+    a.pcur = nullptr;
+    a.pold = c->prev ? c->prev + (size_t)c->prev_half * c->prev_n : nullptr;
     a.ldv = c->ldv;
     a.nslots = c->nslots;
     a.S = c->S;
@@ -2461,10 +2460,11 @@ static int run_step_t(Ctx* c, double tol) {
     const int nsys = c->S * c->P;
     KArgs<T> a = make_args<T>(c, c->d_blocks);
     const unsigned nb = (unsigned)c->blocks.size();
-    k_gather<T><<<nb, kThreads, 0, st>>>(a);
+    // with the extrapolated starts the gather also keeps c^n in the free half of prev
     const bool extrap = extrap_warm_start(c);
-    const long long nall = (long long)c->prev_n;
-    if (extrap) k_copy64<<<(unsigned)((nall + 255) / 256), 256, 0, st>>>(c->x, c->prev + nall, nall);
+    KArgs<T> ag = a;
+    if (extrap) ag.pcur = c->prev + (size_t)(1 - c->prev_half) * c->prev_n;
+    k_gather<T><<<nb, kThreads, 0, st>>>(ag);
     k_residual<T><<<nb, kThreads, 0, st>>>(a, kResFirst);
     k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResFirst);
     const int wsm = c->opt.warm_start;
@@ -2551,7 +2551,7 @@ static int run_step_t(Ctx* c, double tol) {
     if (any_active()) k_scatter<T><<<nb, kThreads, 0, st>>>(a, 0);
     if (extrap) {
         // this step's c^n becomes the previous step of the next extrapolation
-        k_copy64<<<(unsigned)((nall + 255) / 256), 256, 0, st>>>(c->prev + nall, c->prev, nall);
+        c->prev_half ^= 1;
         c->have_prev = true;
     }
     MPM_HIP(hipGetLastError());
