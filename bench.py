@@ -101,6 +101,8 @@ def parse():
     ap.add_argument("--train-pairs", type=int, default=16,
                     help="solver steps that produce training pairs for the warm-start network")
     ap.add_argument("--train-iters", type=int, default=600, help="Adam iterations of the network")
+    ap.add_argument("--widths", default="16,32,64,64",
+                    help="U-Net channels per level (16, 32, 48 or 64 each, the first 16)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device once (calibrates HBM counters)")
     return ap.parse_args()
@@ -254,8 +256,8 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     """Warm starts by networks trained on pairs this workload's own solver generates.
 
     From the state f0: ``train_pairs`` steps solved to 1e-10 give training pairs on the
-    box grid, for two networks (16-32-64-64 U-Net, the library's kernels, the residual
-    loss): one predicting the change from c^n (``MPM_WS_NET``), one correcting the
+    box grid, for two networks (U-Net with ``--widths`` channels per level, 16-32-64-64
+    by default, the library's kernels, the residual loss): one predicting the change from c^n (``MPM_WS_NET``), one correcting the
     extrapolated start 2 c^n - c^{n-1} (``MPM_WS_NET_EXTRAP``), each target scaled by its
     per-species RMS.  Then the same ``learned_steps`` steps are run from the state after
     the pair steps with each start: plain (c^n), extrapolated, learned and learned
@@ -266,6 +268,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     from paper_2505_03067_amd import train as tr
     from paper_2505_03067_amd.train import input_scales
     S = prob.nspecies
+    widths = [int(v) for v in args.widths.split(",")]
 
     def make_pairs(out_scale, extrap, keep=False):
         g = f0.clone()
@@ -294,7 +297,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
         out_scale = tr.target_rms([(inp, tgt) for _, inp, tgt in raw], S)
         del raw
         pairs, g_after, pair_solver = make_pairs(out_scale, extrap, keep=True)
-        net = m.Net(5 * S + 1, S, [16, 32, 64, 64], seed=7)
+        net = m.Net(5 * S + 1, S, widths, seed=7)
         rng = np.random.default_rng(0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -334,7 +337,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     torch.cuda.synchronize()
     inf_ms = e0.elapsed_time(e1) / 5
     grid = int(x0.shape[1] * x0.shape[2] * x0.shape[3])
-    fwd_flop = 2.0 * unet_macs_per_voxel(5 * S + 1, S, [16, 32, 64, 64]) * grid
+    fwd_flop = 2.0 * unet_macs_per_voxel(5 * S + 1, S, widths) * grid
     del x0, y0
     res = {}
     for name, warm in (("plain", m.MPM_WS_NONE), ("extrapolated", m.MPM_WS_EXTRAP), ("learned", m.MPM_WS_NET),
@@ -374,7 +377,8 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
                               "inference_ms": round(inf_ms, 3)}
     res["training"] = {"learned": info_cn, "learned_correction_of_extrapolated": info_x,
                        "loss": "Jacobi-scaled residual left by the prediction (mpm_ws_loss)",
-                       "network": "U-Net 16-32-64-64, BF16 MFMA kernels, FP32 Adam, on the box grid"}
+                       "network": "U-Net " + "-".join(map(str, widths)) +
+                                  ", BF16 MFMA kernels, FP32 Adam, on the box grid"}
     res["learned_over_plain"] = round(res["learned"]["steps_per_s"] / res["plain"]["steps_per_s"], 3)
     res["learned_correction_over_plain"] = round(
         res["learned_correction_of_extrapolated"]["steps_per_s"] / res["plain"]["steps_per_s"], 3)
@@ -641,11 +645,14 @@ def config4_run(args, m, torch):
     S = 3
     extrap = args.c4_base == "extrap"
     t0 = time.perf_counter()
-    net = m.Net(5 * S + 1, S, [16, 32, 64, 64], seed=7)
+    widths = [int(v) for v in args.widths.split(",")]
+    saved = torch.load(args.c4_load, weights_only=True) if args.c4_load else None
+    if saved is not None:
+        widths = [int(v) for v in saved["widths"]]
+    net = m.Net(5 * S + 1, S, widths, seed=7)
     rng = np.random.default_rng(0)
     losses, gen_s, train_s, npairs, t = [], 0.0, 0.0, 0, 0
-    if args.c4_load:
-        saved = torch.load(args.c4_load, weights_only=True)
+    if saved is not None:
         net.set_params(saved["params"].cuda())
         out_scale = list(saved["out_scale"])
         args.c4_epochs = 0
@@ -716,7 +723,7 @@ def config4_run(args, m, torch):
         losses.append(tot / max(nb, 1))
     pairs = None
     if args.c4_save:
-        torch.save({"params": net.params().cpu(), "out_scale": list(out_scale), "widths": [16, 32, 64, 64],
+        torch.save({"params": net.params().cpu(), "out_scale": list(out_scale), "widths": widths,
                     "in_ch": 5 * S + 1, "out_ch": S, "base": args.c4_base}, args.c4_save)
     del pairs
     evalp = [config4_patch(10 ** 6 + i, 128) for i in range(args.c4_eval)]
@@ -758,7 +765,7 @@ def config4_run(args, m, torch):
             "learned_over_plain_fp64": round(res["learned"]["steps_per_s"] / res["plain_fp64"]["steps_per_s"], 3),
             "extrapolated_over_plain": round(res["extrapolated"]["steps_per_s"] / res["plain"]["steps_per_s"], 3),
             "training": {"pairs_per_epoch": npairs, "epochs": args.c4_epochs, "batch": 4, "lr": args.c4_lr,
-                         "loss": args.c4_loss,
+                         "loss": args.c4_loss, "network": "U-Net " + "-".join(map(str, widths)),
                          "base": ("the network corrects the extrapolated start 2 c^n - c^{n-1} (MPM_WS_NET_EXTRAP)"
                                   if extrap else "the network predicts the change from c^n (MPM_WS_NET)"),
                          "streamed": f"pairs of {args.c4_chunk} geometries at a time, regenerated on the GPU "

@@ -131,7 +131,8 @@ def _per_layer(widths, a, b):
 # the first decoder convolution of each level reads the upsampled deeper output and the
 # skip directly (for [16, 48] the upsampled input is three 16-channel chunks)
 @pytest.mark.parametrize("widths,shape", [([16, 32], (2, 8, 8, 16)), ([16, 32, 64, 64], (1, 16, 16, 16)),
-                                          ([16, 32, 64, 64], (2, 8, 16, 24)), ([16, 48], (1, 6, 8, 18))])
+                                          ([16, 32, 64, 64], (2, 8, 16, 24)), ([16, 48], (1, 6, 8, 18)),
+                                          ([16, 16, 32, 32], (1, 16, 16, 16))])
 def test_forward_backward_match_oracle(widths, shape, monkeypatch):
     """The whole network against the BF16-storage oracle.  Both round to BF16 at the
     same points, so they differ only where an FP32 sum and an FP64 sum round to
@@ -177,7 +178,8 @@ def test_forward_backward_match_oracle(widths, shape, monkeypatch):
     assert _rel(outg, plain) <= 3e-2
 
 
-@pytest.mark.parametrize("widths,shape", [([16, 32], (2, 8, 8, 16)), ([16, 32, 64, 64], (1, 64, 64, 128))])
+@pytest.mark.parametrize("widths,shape", [([16, 32], (2, 8, 8, 16)), ([16, 32, 64, 64], (1, 64, 64, 128)),
+                                          ([16, 16, 32, 32], (1, 32, 48, 64))])
 def test_inference_pass_matches_forward(widths, shape):
     """mpm_net_infer (the head fused into the last convolution's epilogue, whose output is
     then not stored) gives the forward pass's output bit for bit, on a grid small enough
@@ -206,7 +208,7 @@ def test_inference_pass_matches_forward(widths, shape):
 
 
 @pytest.mark.parametrize("widths,shape", [([16, 32, 64, 64], (2, 8, 16, 24)), ([16, 32, 64, 64], (1, 128, 128, 128)),
-                                          ([16, 32, 48], (1, 8, 12, 20))])
+                                          ([16, 32, 48], (1, 8, 12, 20)), ([16, 16, 32, 32], (1, 32, 48, 64))])
 def test_fused_pooling_matches_pool_kernel(widths, shape):
     """The pooling each encoder level's second convolution does in its epilogue equals
     k_pool2 (MPM_OP_POOL) on the stored BF16 output bit for bit: grids that leave
