@@ -101,8 +101,10 @@ def parse():
     ap.add_argument("--train-pairs", type=int, default=16,
                     help="solver steps that produce training pairs for the warm-start network")
     ap.add_argument("--train-iters", type=int, default=600, help="Adam iterations of the network")
-    ap.add_argument("--widths", default="16,32,64,64",
-                    help="U-Net channels per level (16, 32, 48 or 64 each, the first 16)")
+    ap.add_argument("--widths", default=None,
+                    help="U-Net channels per level (16, 32, 48 or 64 each, the first 16); default "
+                         "16,16,16 for the learned starts on the box workloads (trained on a few "
+                         "pairs of the box itself), 16,32,64,64 for config4 (trained on many geometries)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device once (calibrates HBM counters)")
     return ap.parse_args()
@@ -256,8 +258,8 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     """Warm starts by networks trained on pairs this workload's own solver generates.
 
     From the state f0: ``train_pairs`` steps solved to 1e-10 give training pairs on the
-    box grid, for two networks (U-Net with ``--widths`` channels per level, 16-32-64-64
-    by default, the library's kernels, the residual loss): one predicting the change from c^n (``MPM_WS_NET``), one correcting the
+    box grid, for two networks (U-Net with ``--widths`` channels per level, 16-16-16 by
+    default, the library's kernels, the residual loss): one predicting the change from c^n (``MPM_WS_NET``), one correcting the
     extrapolated start 2 c^n - c^{n-1} (``MPM_WS_NET_EXTRAP``), each target scaled by its
     per-species RMS.  Then the same ``learned_steps`` steps are run from the state after
     the pair steps with each start: plain (c^n), extrapolated, learned and learned
@@ -268,7 +270,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     from paper_2505_03067_amd import train as tr
     from paper_2505_03067_amd.train import input_scales
     S = prob.nspecies
-    widths = [int(v) for v in args.widths.split(",")]
+    widths = [int(v) for v in (args.widths or "16,16,16").split(",")]
 
     def make_pairs(out_scale, extrap, keep=False):
         g = f0.clone()
@@ -645,7 +647,7 @@ def config4_run(args, m, torch):
     S = 3
     extrap = args.c4_base == "extrap"
     t0 = time.perf_counter()
-    widths = [int(v) for v in args.widths.split(",")]
+    widths = [int(v) for v in (args.widths or "16,32,64,64").split(",")]
     saved = torch.load(args.c4_load, weights_only=True) if args.c4_load else None
     if saved is not None:
         widths = [int(v) for v in saved["widths"]]

@@ -358,8 +358,11 @@ __device__ inline bool res_skip(const SysK* sk, int mode) {
 
 // r = b - A x (FP64); V_0 = S r; partials of ||r||^2 and ||S r||^2.  Two unknowns per
 // thread; the neighbour indices are requested first, the direct operands next, and the
-// neighbour values once the indices are in.
-template <typename T>
+// neighbour values once the indices are in.  PAIR (first residual of a step whose start
+// is the network's correction of the extrapolation): the same pass also forms the base
+// start x_b = 2 x - c^{n-1} (a.pold) at the seven stencil points and stores V_0 =
+// S (b - A x_b) for the network's input instead of S r; the partials stay those of r.
+template <typename T, bool PAIR = false>
 __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
     constexpr int n = 2;
     const int lane = threadIdx.x & 63;
@@ -391,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
             nb[e] = make_int4(t.x, t.y, t.z, t.w);
         }
         __builtin_amdgcn_sched_barrier(0);
-        double xv[n], bv[n], dv[n], ax[n], ay[n], az[n], sv[n];
+        double xv[n], bv[n], dv[n], ax[n], ay[n], az[n], sv[n], ov[n];
         ld16(a.x + u0, xv);
         ld16(a.b + u0, bv);
         ldg16(d + loc0, dv);
@@ -399,10 +402,12 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
         ldg16(A + tot + loc0, ay);
         ldg16(A + 2 * tot + loc0, az);
         ldg16(sc + loc0, sv);
+        if constexpr (PAIR) ld16(a.pold + u0, ov);
         const double xm = a.x[u0 - 1], xp = a.x[u0 + n];
+        const double om = PAIR ? a.pold[u0 - 1] : 0.0, op = PAIR ? a.pold[u0 + n] : 0.0;
         const double axm = A[loc0 - 1];
         __builtin_amdgcn_sched_barrier(0);
-        double gyp[n], gym[n], aym[n], gzp[n], gzm[n], azm[n];
+        double gyp[n], gym[n], aym[n], gzp[n], gzm[n], azm[n], hyp[n], hym[n], hzp[n], hzm[n];
 #pragma unroll
         for (int e = 0; e < n; ++e) {
             gyp[e] = a.x[blk.base + nb[e].y];
@@ -411,12 +416,18 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
             gzp[e] = a.x[blk.base + nb[e].w];
             gzm[e] = a.x[blk.base + nb[e].z];
             azm[e] = A[2 * tot + blk.locbase + nb[e].z];
+            if constexpr (PAIR) {
+                hyp[e] = a.pold[blk.base + nb[e].y];
+                hym[e] = a.pold[blk.base + nb[e].x];
+                hzp[e] = a.pold[blk.base + nb[e].w];
+                hzm[e] = a.pold[blk.base + nb[e].z];
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
         T v0[n];
 #pragma unroll
         for (int e = 0; e < n; ++e) {
-            double r = 0.0, sr = 0.0;
+            double r = 0.0, sr = 0.0, srb = 0.0;
             if (l0 + e < blk.N) {
                 const double left = e == 0 ? xm : xv[e - 1];
                 const double right = e == n - 1 ? xp : xv[e + 1];
@@ -430,8 +441,22 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
                 Ax += azm[e] * gzm[e];
                 r = bv[e] - Ax;
                 sr = sv[e] * r;
+                if constexpr (PAIR) {
+                    // x_b at each stencil point as the extrapolation stores it, summed in
+                    // the same order as above
+                    const double oleft = e == 0 ? om : ov[e - 1];
+                    const double oright = e == n - 1 ? op : ov[e + 1];
+                    double Axb = dv[e] * (2.0 * xv[e] - ov[e]);
+                    Axb += ax[e] * (2.0 * right - oright);
+                    Axb += leftc * (2.0 * left - oleft);
+                    Axb += ay[e] * (2.0 * gyp[e] - hyp[e]);
+                    Axb += aym[e] * (2.0 * gym[e] - hym[e]);
+                    Axb += az[e] * (2.0 * gzp[e] - hzp[e]);
+                    Axb += azm[e] * (2.0 * gzm[e] - hzm[e]);
+                    srb = sv[e] * (bv[e] - Axb);
+                }
             }
-            v0[e] = (T)sr;
+            v0[e] = (T)(PAIR ? srb : sr);
             acc[0] += r * r;
             acc[1] += sr * sr;
         }
@@ -1435,8 +1460,9 @@ __device__ inline long long grid_of_voxel(const ProbDev& pd, int v) {
 // Grid index of compact voxel l of a problem.
 __device__ inline long long grid_index(const ProbDev& pd, int l) { return grid_of_voxel(pd, pd.vox[l]); }
 
-// For the systems not already converged at c^n: x += out * out_scale (network; x holds
-// the base start) or x = 2 x - c^{n-1} (extrapolation; x holds c^n).
+// For the systems not already converged at c^n (x holds c^n): x += out * out_scale
+// (MPM_WS_NET), x = 2 x - c^{n-1} (MPM_WS_EXTRAP) or x = (2 x - c^{n-1}) + out * out_scale
+// (MPM_WS_NET_EXTRAP: the network's correction of the extrapolated start).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, const float* scales) {
     const Block blk = a.blocks[blockIdx.x];
@@ -1450,27 +1476,29 @@ __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, con
     constexpr int n = 4;
     for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
         const int l0 = (int)(u0 - wh.base);
-        double xv[n], w[n];
+        double xv[n], w[n], o[n];
 #pragma unroll
         for (int e = 0; e < n; ++e) {
             const bool in = l0 + e < pd.N;
             xv[e] = in ? a.x[u0 + e] : 0.0;
-            if (mode == MPM_WS_NET)
-                w[e] = in ? (double)(pd.wsout[grid_index(pd, l0 + e) * a.S + wh.s] * os) : 0.0;
-            else
-                w[e] = in ? a.pold[u0 + e] : 0.0;
+            w[e] = in && mode != MPM_WS_EXTRAP ? (double)(pd.wsout[grid_index(pd, l0 + e) * a.S + wh.s] * os) : 0.0;
+            o[e] = in && mode != MPM_WS_NET ? a.pold[u0 + e] : 0.0;
         }
 #pragma unroll
-        for (int e = 0; e < n; ++e)
-            if (l0 + e < pd.N) a.x[u0 + e] = mode == MPM_WS_NET ? xv[e] + w[e] : 2.0 * xv[e] - w[e];
+        for (int e = 0; e < n; ++e) {
+            if (l0 + e >= pd.N) continue;
+            const double xb = mode == MPM_WS_NET ? xv[e] : 2.0 * xv[e] - o[e];
+            a.x[u0 + e] = mode == MPM_WS_EXTRAP ? xb : xb + w[e];
+        }
     }
 }
 
 // The per-step channels of the network input on the domain voxels of problem p, each
 // times its scale, BF16: c^n (channel s, from the lattice field) and the Jacobi-scaled
 // residual of the base start, d = r / A_PP = S (S r) (channel 4 S + 1 + s).  V holds
-// S r from the residual of the base start (c^n: the step's first residual; the
-// extrapolation: its own), before any Arnoldi step overwrites it.
+// S r of the base start from the step's first residual pass (which, for the correction
+// of the extrapolation, forms it for x_b = 2 c^n - c^{n-1}), before any Arnoldi step
+// overwrites it.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_ws_resid(KArgs<T> a, int p, const double* field, const float* scales,
                                                        uint16_t* dst) {
@@ -2113,6 +2141,9 @@ int ensure_layout(Ctx* c) {
                 return MPM_ENOMEM;
             }
             c->cap_prev = 2 * need;
+            // entries no block covers (the lead, the gaps) stay zero: the residual pass of the
+            // corrected extrapolation reads them as stencil neighbours, as it reads those of x
+            MPM_HIP(hipMemsetAsync(c->prev, 0, 2 * need * 8, st));
         }
         c->prev_n = need;
     }
@@ -2400,12 +2431,9 @@ static int warm_start(Ctx* c, hipStream_t st) {
     KArgs<T> a = make_args<T>(c, c->d_blocks);
     const unsigned nb = (unsigned)c->blocks.size();
     const int mode = c->opt.warm_start;
-    if (mode == MPM_WS_NET_EXTRAP) {
-        // base start x_b = 2 c^n - c^{n-1}; V = S (b - A x_b) for the network's input (the
-        // residual's partial sums are scratch: the acceptance test recomputes them)
-        k_ws_apply<T><<<nb, kThreads, 0, st>>>(a, MPM_WS_EXTRAP, c->d_scales);
-        k_residual<T><<<nb, kThreads, 0, st>>>(a, kResWarm);
-    }
+    // the network's input reads V = S (b - A x_b) of the base start x_b: the step's first
+    // residual leaves it there (for MPM_WS_NET_EXTRAP that pass also forms x_b = 2 c^n -
+    // c^{n-1}), and k_ws_apply forms the start from c^n, c^{n-1} and the output
     if (net_warm_start(c)) {
         if (!c->have_scales) {
             set_error("warm start: no network scales (mpm_attach_net)");
@@ -2444,7 +2472,7 @@ static int warm_start(Ctx* c, hipStream_t st) {
         }
         c->net->stream = saved;
     }
-    k_ws_apply<T><<<nb, kThreads, 0, st>>>(a, mode == MPM_WS_NET_EXTRAP ? MPM_WS_NET : mode, c->d_scales);
+    k_ws_apply<T><<<nb, kThreads, 0, st>>>(a, mode, c->d_scales);
     k_residual<T><<<nb, kThreads, 0, st>>>(a, kResWarm);
     k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResWarm);
     k_ws_revert<T><<<nb, kThreads, 0, st>>>(a);
@@ -2465,11 +2493,14 @@ static int run_step_t(Ctx* c, double tol) {
     KArgs<T> ag = a;
     if (extrap) ag.pcur = c->prev + (size_t)(1 - c->prev_half) * c->prev_n;
     k_gather<T><<<nb, kThreads, 0, st>>>(ag);
-    k_residual<T><<<nb, kThreads, 0, st>>>(a, kResFirst);
-    k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResFirst);
     const int wsm = c->opt.warm_start;
-    if ((wsm == MPM_WS_NET && c->net) || (wsm == MPM_WS_EXTRAP && c->have_prev) ||
-        (wsm == MPM_WS_NET_EXTRAP && c->net && c->have_prev)) {
+    const bool net_extrap = wsm == MPM_WS_NET_EXTRAP && c->net && c->have_prev;
+    if (net_extrap)
+        k_residual<T, true><<<nb, kThreads, 0, st>>>(a, kResFirst);
+    else
+        k_residual<T><<<nb, kThreads, 0, st>>>(a, kResFirst);
+    k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResFirst);
+    if ((wsm == MPM_WS_NET && c->net) || (wsm == MPM_WS_EXTRAP && c->have_prev) || net_extrap) {
         int wrc = warm_start<T>(c, st);
         if (wrc != MPM_OK) return wrc;
     }
