@@ -53,6 +53,7 @@ struct ProbDev {
     int lo[3];
     int gd[3];
     const float* wsout;    // network output on the grid [G][S] (or null)
+    uint16_t* wsin;        // network input on the grid [G][5 S + 1], BF16 (or null)
 };
 
 // One block of work: a contiguous range of one system's unknowns (global indices),

@@ -342,6 +342,24 @@ __global__ __launch_bounds__(kThreads) void k_gather(KArgs<T> a) {
     block_partials<1>(acc, a.part + (long long)kRowB * a.nslots, a.nslots, blk.slot);
 }
 
+// BF16 of the network input: round to nearest, ties to even; NaN -> quiet NaN 0x7fc0
+__device__ inline uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Grid index of lattice voxel v of a problem's box.
+__device__ inline long long grid_of_voxel(const ProbDev& pd, int v) {
+    const int plane = pd.nx * pd.ny;
+    const int z = v / plane;
+    const int rem = v - z * plane;
+    const int y = rem / pd.nx;
+    const int x = rem - y * pd.nx;
+    return ((long long)(z - pd.lo[2]) * pd.gd[1] + (y - pd.lo[1])) * pd.gd[0] + (x - pd.lo[0]);
+}
+
 // Which systems a residual evaluation covers: the first one of a step covers all;
 // the one after a cycle the not yet converged; the warm-start one the systems not
 // converged at c^n; the revert one the systems whose warm start was rejected.
@@ -362,8 +380,11 @@ __device__ inline bool res_skip(const SysK* sk, int mode) {
 // is the network's correction of the extrapolation): the same pass also forms the base
 // start x_b = 2 x - c^{n-1} (a.pold) at the seven stencil points and stores V_0 =
 // S (b - A x_b) for the network's input instead of S r; the partials stay those of r.
-template <typename T, bool PAIR = false>
-__global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
+// WSIN (first residual of a step with a network start): the pass also writes the
+// network input's per-step channels of its domain voxels, each times its scale, BF16:
+// c^n (channel s; x holds c^n) and d = S V_0 (channel 4 S + 1 + s), as k_ws_resid does.
+template <typename T, bool PAIR = false, bool WSIN = false>
+__global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode, const float* scales = nullptr) {
     constexpr int n = 2;
     const int lane = threadIdx.x & 63;
     const int cv = lane < a.nsys ? a.sk[lane].converged : 0;
@@ -384,10 +405,22 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
     const long long tot = blk.tot;
     T* V0 = a.V;
     double acc[2] = {0.0, 0.0};
+    ProbDev pd{};
+    float cscale = 0.f, dscale = 0.f;
+    if constexpr (WSIN) {
+        pd = a.probs[blk.p];
+        cscale = scales[blk.s];
+        dscale = scales[4 * a.S + 1 + blk.s];
+    }
     for (long long u0 = blk.start + threadIdx.x * n; u0 < blk.end; u0 += kThreads * n) {
         const int l0 = (int)(u0 - blk.base);
         const long long loc0 = blk.locbase + l0;
         int4 nb[n];
+        int vx[n];
+        if constexpr (WSIN) {
+#pragma unroll
+            for (int e = 0; e < n; ++e) vx[e] = blk.vox[l0 + e];
+        }
 #pragma unroll
         for (int e = 0; e < n; ++e) {
             const i32x4 t = nbr[l0 + e];
@@ -459,6 +492,14 @@ __global__ __launch_bounds__(kThreads) void k_residual(KArgs<T> a, int mode) {
             v0[e] = (T)(PAIR ? srb : sr);
             acc[0] += r * r;
             acc[1] += sr * sr;
+            if constexpr (WSIN) {
+                if (l0 + e < blk.N) {
+                    const double dd = sv[e] * (double)v0[e];
+                    uint16_t* o = pd.wsin + grid_of_voxel(pd, vx[e]) * ws_channels(a.S);
+                    o[4 * a.S + 1 + blk.s] = to_bf16((float)dd * dscale);
+                    o[blk.s] = to_bf16((float)xv[e] * cscale);
+                }
+            }
         }
 #pragma unroll
         for (int e = 0; e < n; ++e) V0[u0 + e] = v0[e];
@@ -1395,18 +1436,11 @@ __global__ __launch_bounds__(kThreads) void k_dc_finish(KArgs<T> a, int sys0) {
 }
 
 // ------------------------------------------------------------------ warm start
-// BF16 of the network input: round to nearest, ties to even; NaN -> quiet NaN 0x7fc0
-__device__ inline uint16_t to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
 // Network input on the box grid of problem p: channels [c (S), k (S), D (S), s (S), mask,
 // d (S)], each multiplied by its scale, BF16.  This kernel writes the static channels
-// (k, D, s and the mask, zero beyond the box) and zero c and d channels; k_ws_resid
-// writes c and d on the domain voxels, so that only it runs again while the grid,
+// (k, D, s and the mask, zero beyond the box) and zero c and d channels; c and d of the
+// domain voxels are written by the step's first residual pass (k_residual with WSIN) or,
+// for training pairs, by k_ws_resid, so that only those run again while the grid,
 // domain and scales stay the same.  Threads (64, 4) over (x, y) of one z plane per
 // block row.
 __global__ __launch_bounds__(256) void k_ws_input(ProbDev pd, int S, const float* stat, const float* scales,
@@ -1447,16 +1481,6 @@ static void launch_ws_input(const ProbHost& ph, const ProbDev& pd, int S, const 
     k_ws_input<<<grid, dim3(64, 4), 0, st>>>(pd, S, ph.stat, scales, in);
 }
 
-// Grid index of lattice voxel v of a problem's box.
-__device__ inline long long grid_of_voxel(const ProbDev& pd, int v) {
-    const int plane = pd.nx * pd.ny;
-    const int z = v / plane;
-    const int rem = v - z * plane;
-    const int y = rem / pd.nx;
-    const int x = rem - y * pd.nx;
-    return ((long long)(z - pd.lo[2]) * pd.gd[1] + (y - pd.lo[1])) * pd.gd[0] + (x - pd.lo[0]);
-}
-
 // Grid index of compact voxel l of a problem.
 __device__ inline long long grid_index(const ProbDev& pd, int l) { return grid_of_voxel(pd, pd.vox[l]); }
 
@@ -1493,8 +1517,9 @@ __global__ __launch_bounds__(kThreads) void k_ws_apply(KArgs<T> a, int mode, con
     }
 }
 
-// The per-step channels of the network input on the domain voxels of problem p, each
-// times its scale, BF16: c^n (channel s, from the lattice field) and the Jacobi-scaled
+// The per-step channels of the network input on the domain voxels of problem p (for
+// the training pairs; a step writes them in its first residual pass), each times its
+// scale, BF16: c^n (channel s, from the lattice field) and the Jacobi-scaled
 // residual of the base start, d = r / A_PP = S (S r) (channel 4 S + 1 + s).  V holds
 // S r of the base start from the step's first residual pass (which, for the correction
 // of the extrapolation, forms it for x_b = 2 c^n - c^{n-1}), before any Arnoldi step
@@ -2126,6 +2151,7 @@ int ensure_layout(Ctx* c) {
             pd[p].gd[d] = ph.gd[d];
         }
         pd[p].wsout = ph.wsout;
+        pd[p].wsin = ph.wsin;
     }
     // previous-step values for the extrapolated start live on the global unknowns
     c->have_prev = false;
@@ -2425,42 +2451,46 @@ static int fetch_status(Ctx* c, hipStream_t st) {
 // only if its true FP64 residual is smaller than that of c^n (else the system restarts
 // from c^n).  The outcome is recorded in the statistics (warm_start_used, fallback,
 // rel_res_warm).
+// Before the first residual pass of a step with a network start: the scales are set,
+// each problem's network buffers cover its grid, and the input's static channels (k, D,
+// s, the mask) are built, once per grid, domain and scales; that pass then writes the
+// per-step channels (c^n and d) of the domain voxels.
+static int ws_prepare_inputs(Ctx* c, hipStream_t st) {
+    if (!c->have_scales) {
+        set_error("warm start: no network scales (mpm_attach_net)");
+        return MPM_ESTATE;
+    }
+    for (int p = 0; p < c->P; ++p) {
+        ProbHost& ph = c->probs[p];
+        const long long G = (long long)ph.gd[0] * ph.gd[1] * ph.gd[2];
+        if (G <= 0 || (size_t)G > ph.cap_grid || !ph.wsin || !ph.wsout || !ph.stat) {
+            set_error("warm start: the network buffers of a problem do not cover its grid");
+            return MPM_ESTATE;
+        }
+        if (!ph.ws_ready) {
+            launch_ws_input(ph, c->h_probs[p], c->S, c->d_scales, ph.wsin, st);
+            const hipError_t le = hipGetLastError();
+            if (le != hipSuccess) return hip_fail(le, "warm start (network input)");
+            ph.ws_ready = true;
+        }
+    }
+    return MPM_OK;
+}
+
 template <typename T>
 static int warm_start(Ctx* c, hipStream_t st) {
     const int nsys = c->S * c->P;
     KArgs<T> a = make_args<T>(c, c->d_blocks);
     const unsigned nb = (unsigned)c->blocks.size();
     const int mode = c->opt.warm_start;
-    // the network's input reads V = S (b - A x_b) of the base start x_b: the step's first
-    // residual leaves it there (for MPM_WS_NET_EXTRAP that pass also forms x_b = 2 c^n -
+    // the step's first residual pass has written the network input's per-step channels
+    // (c^n and d of the base start x_b; for MPM_WS_NET_EXTRAP it also forms x_b = 2 c^n -
     // c^{n-1}), and k_ws_apply forms the start from c^n, c^{n-1} and the output
     if (net_warm_start(c)) {
-        if (!c->have_scales) {
-            set_error("warm start: no network scales (mpm_attach_net)");
-            return MPM_ESTATE;
-        }
         hipStream_t saved = c->net->stream;
         c->net->stream = st;
         for (int p = 0; p < c->P; ++p) {
             ProbHost& ph = c->probs[p];
-            const ProbDev& pd = c->h_probs[p];
-            const long long G = (long long)ph.gd[0] * ph.gd[1] * ph.gd[2];
-            if (G <= 0 || (size_t)G > ph.cap_grid || !ph.wsin || !ph.wsout || !ph.stat) {
-                c->net->stream = saved;
-                set_error("warm start: the network buffers of a problem do not cover its grid");
-                return MPM_ESTATE;
-            }
-            // the static channels once per grid, domain and scales; c and d every step
-            if (!ph.ws_ready) {
-                launch_ws_input(ph, pd, c->S, c->d_scales, ph.wsin, st);
-                const hipError_t le = hipGetLastError();
-                if (le != hipSuccess) {
-                    c->net->stream = saved;
-                    return hip_fail(le, "warm start (network input)");
-                }
-                ph.ws_ready = true;
-            }
-            k_ws_resid<T><<<nb, kThreads, 0, st>>>(a, p, c->h_fields[p], c->d_scales, ph.wsin);
             // the last level computes only the tiles the domain voxels' outputs read
             const TileLists tl{ph.tl_dev, ph.tl_n[0], ph.tl_dev + std::max(ph.tl_n[0], 0), ph.tl_n[1]};
             int rc = net_forward(c->net, ph.wsin, 1, ph.gd[2], ph.gd[1], ph.gd[0], ph.wsout, true,
@@ -2495,12 +2525,19 @@ static int run_step_t(Ctx* c, double tol) {
     k_gather<T><<<nb, kThreads, 0, st>>>(ag);
     const int wsm = c->opt.warm_start;
     const bool net_extrap = wsm == MPM_WS_NET_EXTRAP && c->net && c->have_prev;
+    const bool net_ws = (wsm == MPM_WS_NET && c->net) || net_extrap;
+    if (net_ws) {
+        const int prc = ws_prepare_inputs(c, st);
+        if (prc != MPM_OK) return prc;
+    }
     if (net_extrap)
-        k_residual<T, true><<<nb, kThreads, 0, st>>>(a, kResFirst);
+        k_residual<T, true, true><<<nb, kThreads, 0, st>>>(a, kResFirst, c->d_scales);
+    else if (net_ws)
+        k_residual<T, false, true><<<nb, kThreads, 0, st>>>(a, kResFirst, c->d_scales);
     else
         k_residual<T><<<nb, kThreads, 0, st>>>(a, kResFirst);
     k_res_final<T><<<nsys, kThreads, 0, st>>>(a, 0, kResFirst);
-    if ((wsm == MPM_WS_NET && c->net) || (wsm == MPM_WS_EXTRAP && c->have_prev) || net_extrap) {
+    if (net_ws || (wsm == MPM_WS_EXTRAP && c->have_prev)) {
         int wrc = warm_start<T>(c, st);
         if (wrc != MPM_OK) return wrc;
     }
