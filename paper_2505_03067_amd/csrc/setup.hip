@@ -320,8 +320,12 @@ __global__ void k_ws_static(const uint8_t* mask, const double* D, const double* 
 
 // The network's voxel tiles on the warm-start grid (16 x 4 x 4, as its convolutions
 // tile it): per tile, flag[ntiles + t] = 1 when a domain voxel (mask channel of the
-// static input) lies in it; then flag[t] = 1 when one of its 27 neighbouring tiles (itself
-// included) is flagged so, i.e. when a 3x3x3 convolution over the flagged tiles reads it.
+// static input) lies in it (the last convolution's tiles); flag[t] = 1 when a domain
+// voxel lies in the tile grown by one voxel on every side, i.e. when the tile holds a
+// value the last 3x3x3 convolution reads for a domain voxel's output (the tiles of the
+// convolution before it).  The last convolution's other outputs, of the voxels off the
+// domain, may then read values no launch wrote; nothing reads those outputs.  One wave
+// per tile.
 constexpr int kWsTX = 16, kWsTY = 4, kWsTZ = 4;
 __global__ void k_ws_tile_domain(const float* stat, int S, int gx, int gy, int gz, uint8_t* flag) {
     const int ntx = (gx + kWsTX - 1) / kWsTX, nty = gy / kWsTY, ntz = gz / kWsTZ;
@@ -340,21 +344,24 @@ __global__ void k_ws_tile_domain(const float* stat, int S, int gx, int gy, int g
     const bool any = __ballot(hit) != 0;
     if (lane == 0) flag[nt + t] = any ? 1 : 0;
 }
-__global__ void k_ws_tile_near(int gx, int gy, int gz, uint8_t* flag) {
+__global__ void k_ws_tile_near(const float* stat, int S, int gx, int gy, int gz, uint8_t* flag) {
     const int ntx = (gx + kWsTX - 1) / kWsTX, nty = gy / kWsTY, ntz = gz / kWsTZ;
     const int nt = ntx * nty * ntz;
-    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int t = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);   // one wave per tile
     if (t >= nt) return;
+    const int lane = threadIdx.x & 63;
     const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-    uint8_t any = 0;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int x = tx + dx, y = ty + dy, z = tz + dz;
-                if (x >= 0 && x < ntx && y >= 0 && y < nty && z >= 0 && z < ntz)
-                    any |= flag[nt + (z * nty + y) * ntx + x];
-            }
-    flag[t] = any;
+    const float* m = stat + (long long)3 * S * gx * gy * gz;   // the mask channel
+    constexpr int EX = kWsTX + 2, EY = kWsTY + 2, EZ = kWsTZ + 2;
+    bool hit = false;
+    for (int v = lane; v < EX * EY * EZ; v += 64) {
+        const int x = tx * kWsTX - 1 + v % EX, y = ty * kWsTY - 1 + (v / EX) % EY;
+        const int z = tz * kWsTZ - 1 + v / (EX * EY);
+        if (x >= 0 && x < gx && y >= 0 && y < gy && z >= 0 && z < gz && m[((long long)z * gy + y) * gx + x] > 0.f)
+            hit = true;
+    }
+    const bool any = __ballot(hit) != 0;
+    if (lane == 0) flag[t] = any ? 1 : 0;
 }
 
 // Grow a scratch buffer to hold n elements (with room for later growth).
@@ -575,7 +582,7 @@ static int discretise(Ctx* c, ProbHost& ph, const BoxGeo& g, const uint8_t* mask
                 ph.cap_tiles = nt;
             }
             k_ws_tile_domain<<<(unsigned)((nt + 3) / 4), 256, 0, st>>>(ph.stat, c->S, gx, gy, gz, ph.tf_dev);
-            k_ws_tile_near<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(gx, gy, gz, ph.tf_dev);
+            k_ws_tile_near<<<(unsigned)((nt + 3) / 4), 256, 0, st>>>(ph.stat, c->S, gx, gy, gz, ph.tf_dev);
             e = hipGetLastError();
             if (e == hipSuccess) e = hipMemcpyAsync(ph.tf_host, ph.tf_dev, 2 * nt, hipMemcpyDeviceToHost, st);
             if (e != hipSuccess) return hip_fail(e, "mpm_fv_setup (tile flags)");
