@@ -2446,11 +2446,6 @@ static int fetch_status(Ctx* c, hipStream_t st) {
     return MPM_OK;
 }
 
-// Warm start of every system not converged at c^n: network prediction, linear
-// extrapolation, or the network's correction of the extrapolation, accepted per system
-// only if its true FP64 residual is smaller than that of c^n (else the system restarts
-// from c^n).  The outcome is recorded in the statistics (warm_start_used, fallback,
-// rel_res_warm).
 // Before the first residual pass of a step with a network start: the scales are set,
 // each problem's network buffers cover its grid, and the input's static channels (k, D,
 // s, the mask) are built, once per grid, domain and scales; that pass then writes the
@@ -2477,6 +2472,11 @@ static int ws_prepare_inputs(Ctx* c, hipStream_t st) {
     return MPM_OK;
 }
 
+// Warm start of every system not converged at c^n: network prediction, linear
+// extrapolation, or the network's correction of the extrapolation, accepted per system
+// only if its true FP64 residual is smaller than that of c^n (else the system restarts
+// from c^n).  The outcome is recorded in the statistics (warm_start_used, fallback,
+// rel_res_warm).
 template <typename T>
 static int warm_start(Ctx* c, hipStream_t st) {
     const int nsys = c->S * c->P;
