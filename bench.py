@@ -249,7 +249,7 @@ def run_steps(s, f, n, tol, torch, grow=None):
         rc = s.step([f], tol)
         if rc != 0:
             raise RuntimeError(f"step did not converge (status {rc})")
-        its.append(sum(s.stats(0, sp)["iterations"] for sp in range(s.nspecies)))
+        its.append(s.iterations(0))
     torch.cuda.synchronize()
     return its
 

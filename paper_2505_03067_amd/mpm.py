@@ -620,6 +620,19 @@ class Solver:
     def stats(self, problem=0, species=0):
         return mpm_gmres_stats(self.ctx, problem, species)
 
+    def iterations(self, problem=0):
+        """GMRES iterations of the last step summed over the species of ``problem``
+        (mpm_gmres_stats into one reused record, for per-step bookkeeping)."""
+        st = getattr(self, "_st", None)
+        if st is None:
+            st = self._st = mpm_stats()
+        L = lib()
+        n = 0
+        for sp in range(self.nspecies):
+            _check(L.mpm_gmres_stats(self.ctx, int(problem), sp, ctypes.byref(st)))
+            n += st.iterations
+        return n
+
     def time_kernel(self, kind, j=0, repeat=1):
         return mpm_time_kernel(self.ctx, kind, j, repeat)
 

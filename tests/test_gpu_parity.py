@@ -253,6 +253,9 @@ def test_multi_problem_context():
             s.setup(i, p.box, d["mask"], d["D"], d["k"], d["src"], p.c_b, 1.0, 1.0)
         for _ in range(2):
             s.step(fields, 1e-12)
+        # the per-step bookkeeping call sums the same statistics per problem
+        for i in range(len(probs)):
+            assert s.iterations(i) == sum(s.stats(i, sp)["iterations"] for sp in range(3)) > 0
     for p, f in zip(probs, fields):
         want, _ = run(p, steps=2, solver="pcg", tol=1e-13)
         mb = p.mask[box_slice(p.box)].astype(bool)
