@@ -110,6 +110,18 @@ def parse():
     return ap.parse_args()
 
 
+def net_widths(arg, default):
+    """U-Net channels per level from ``--widths`` ("16,32,64,64"), or ``default``: 1 to 6
+    levels of 16, 32, 48 or 64 channels, 16 at the first (the library's network)."""
+    try:
+        w = [int(v) for v in (arg or default).split(",")]
+    except ValueError:
+        raise SystemExit(f"--widths: comma-separated channel counts expected, got {arg!r}")
+    if not 1 <= len(w) <= 6 or w[0] != 16 or any(v not in (16, 32, 48, 64) for v in w):
+        raise SystemExit(f"--widths: 1 to 6 levels of 16, 32, 48 or 64 channels, the first 16; got {arg!r}")
+    return w
+
+
 def unet_macs_per_voxel(cin, cout, widths):
     """Multiply-adds per input-grid voxel of the warm-start U-Net: per level l (1/8^l of
     the voxels) two 3x3x3 convolutions on the way down (the first from the level above,
@@ -272,7 +284,7 @@ def learned_vs_plain(m, prob, t, box, f0, tol, precision, ortho, args, torch):
     from paper_2505_03067_amd import train as tr
     from paper_2505_03067_amd.train import input_scales
     S = prob.nspecies
-    widths = [int(v) for v in (args.widths or "16,16,16").split(",")]
+    widths = net_widths(args.widths, "16,16,16")
 
     def make_pairs(out_scale, extrap, keep=False):
         g = f0.clone()
@@ -656,7 +668,7 @@ def config4_run(args, m, torch):
     S = 3
     extrap = args.c4_base == "extrap"
     t0 = time.perf_counter()
-    widths = [int(v) for v in (args.widths or "16,32,64,64").split(",")]
+    widths = net_widths(args.widths, "16,32,64,64")
     saved = torch.load(args.c4_load, weights_only=True) if args.c4_load else None
     if saved is not None:
         widths = [int(v) for v in saved["widths"]]

@@ -44,3 +44,14 @@ def test_unet_work_per_voxel():
     assert bench.unet_macs_per_voxel(13, 3, [16, 32, 64, 64]) == 40224 + 19008 + 7776 + 432
     # one level, no skips: two convolutions and the head
     assert bench.unet_macs_per_voxel(2, 1, [4]) == 2 * 4 * 27 + 4 * 4 * 27 + 4
+
+
+def test_network_widths_option():
+    import pytest
+
+    import bench
+    assert bench.net_widths(None, "16,16,16") == [16, 16, 16]
+    assert bench.net_widths("16,32,64,64", "16,16,16") == [16, 32, 64, 64]
+    for bad in ("32,32", "16,24", "16,16,16,16,16,16,16", "16,x", "16,,32"):
+        with pytest.raises(SystemExit):
+            bench.net_widths(bad, "16,16,16")
